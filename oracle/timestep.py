@@ -1,0 +1,189 @@
+"""Theta-method time stepping with exact sparse solves (oracle, FP64).
+
+Test infrastructure only (see the package header).
+
+Transformed (strong pseudo-periodic) form, Appendix A,
+eq. theta_discretization and eq. linear_billinear. With
+  L(F) = S + I_Gamma + R2 + (G F)^2 M_D + i G F (q . B)
+each step n = 1..N solves
+  (M/k + theta L(F^n)) u^n = (M/k - (1 - theta) L(F^{n-1})) u^{n-1}.
+
+U-form (Neumann walls), Appendix B, eq. matrix_form with eq. loadvec, with
+the T2 term on the mass matrix (the printed A multiplies 1/T2 by J, which
+conflicts with eq. loadvec where it multiplies the plain mass):
+  L_n = S + I_Gamma + R2 + i G f_n (q . J),
+  (M/k + theta L_n) U^n = (M/k - (1 - theta) L_n) U^{n-1},
+where f_n is the value of f on (t^{n-1}, t^n) (pulse edges lie on the grid).
+
+Signal (Sec. 2, eq. signal): S = int U(T) = sum_i w_i u_i^N, because
+F(T) = 0 at T = Delta + delta makes u(T) = U(T).
+
+Each step is solved exactly with SuperLU (scipy.sparse.linalg.splu, minimum
+degree ordering on A + A^T). The left operator depends on the step only
+through F^n (or f_n), so factorizations are cached by that value. For meshes
+where sparse LU fill makes that impractical (tens of thousands of 3-D DOFs),
+solver="krylov" solves each step with SciPy's conjugate gradient (Hermitian
+transformed operator) or GMRES (complex-symmetric U-form) to a relative
+residual of 1e-13, i.e. exact up to rounding; tests pin it to SuperLU.
+
+Pins (tests/test_oracle_*.py): free diffusion closed-form recurrence and the
+Stejskal-Tanner limit exp(-D b) with second-order time convergence; mass
+conservation at b = 0; kappa -> 0 decoupling and kappa -> inf
+single-compartment limit; S(-q) = conj S(q); 1-D slab matrix formalism for
+both forms; the two forms agree on a non-symmetric case; dense solves equal
+SuperLU.
+"""
+
+from __future__ import annotations
+
+from collections import OrderedDict
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import sequence as seqmod
+from .fem import Assembly, assemble
+
+
+class _LUCache:
+    def __init__(self, size: int):
+        self.size = int(size)
+        self.d: "OrderedDict[float, object]" = OrderedDict()
+
+    def get(self, key, build):
+        if key in self.d:
+            self.d.move_to_end(key)
+            return self.d[key]
+        lu = build()
+        if self.size > 0:
+            self.d[key] = lu
+            while len(self.d) > self.size:
+                self.d.popitem(last=False)
+        return lu
+
+
+def _qB(asm: Assembly, q):
+    return q[0] * asm.B[0] + q[1] * asm.B[1] + q[2] * asm.B[2]
+
+
+def _qJ(asm: Assembly, q):
+    return q[0] * asm.J[0] + q[1] * asm.J[1] + q[2] * asm.J[2]
+
+
+KRYLOV_RTOL = 1e-13
+
+
+def _splu(A):
+    return spla.splu(A.tocsc().astype(np.complex128), permc_spec="MMD_AT_PLUS_A")
+
+
+def _krylov(A, rhs, x0, hermitian):
+    A = A.tocsr().astype(np.complex128)
+    dinv = 1.0 / A.diagonal()
+    P = spla.LinearOperator(A.shape, matvec=lambda v: dinv * v, dtype=np.complex128)
+    if hermitian:
+        x, info = spla.cg(A, rhs, x0=x0, rtol=KRYLOV_RTOL, atol=0.0, maxiter=20000, M=P)
+    else:
+        x, info = spla.gmres(A, rhs, x0=x0, rtol=KRYLOV_RTOL, atol=0.0, restart=60,
+                             maxiter=2000, M=P)
+    if info != 0:
+        raise RuntimeError("oracle Krylov solve did not reach rtol=%g (info=%d)"
+                           % (KRYLOV_RTOL, info))
+    return x
+
+
+def _unit(q):
+    q = np.asarray(q, dtype=np.float64)
+    nq = np.linalg.norm(q)
+    return q / nq if nq > 0 else np.array([1.0, 0.0, 0.0])
+
+
+def solve_transformed(asm: Assembly, seq, b: float, q, n_steps: Optional[int] = None,
+                      cache_size: int = 256, return_u: bool = False, solver: str = "splu"):
+    """Signal of one (b, q) system with the transformed operator.
+
+    n_steps limits the run to the first n steps (for timing samples and
+    intermediate checks); the signal is then sum w u^n at that step, which is
+    the physical signal only when F(t^n) = 0.
+    """
+    k = float(seq.dt)
+    th = float(seq.theta)
+    t = seqmod.time_grid(seq.delta, seq.Delta, seq.dt)
+    F = seqmod.pgse_F(t, seq.delta, seq.Delta)
+    G = float(seqmod.b_to_G(b, seq.delta, seq.Delta))
+    qn = _unit(q)
+    N = len(t) - 1 if n_steps is None else int(n_steps)
+
+    base = (asm.S + asm.IG + asm.R2).tocsr()
+    Mk = (asm.M / k).tocsr()
+    qB = _qB(asm, qn).tocsr()
+
+    def L(Fv):
+        return base + (G * Fv) ** 2 * asm.MD + 1j * (G * Fv) * qB
+
+    def L_apply(Fv, v):
+        return base @ v + (G * Fv) ** 2 * (asm.MD @ v) + 1j * (G * Fv) * (qB @ v)
+
+    cache = _LUCache(cache_size)
+    u = asm.u0.astype(np.complex128)
+    for n in range(1, N + 1):
+        rhs = Mk @ u - (1.0 - th) * L_apply(F[n - 1], u)
+        Fn = float(F[n])
+        if solver == "dense":
+            A = (Mk + th * L(Fn)).toarray()
+            u = np.linalg.solve(A, rhs)
+        elif solver == "krylov":
+            u = _krylov(Mk + th * L(Fn), rhs, u, hermitian=True)
+        else:
+            lu = cache.get(Fn, lambda: _splu(Mk + th * L(Fn)))
+            u = lu.solve(rhs)
+    s = complex(asm.w @ u)
+    return (s, u) if return_u else s
+
+
+def solve_uform(asm: Assembly, seq, b: float, q, n_steps: Optional[int] = None,
+                cache_size: int = 8, return_u: bool = False, solver: str = "splu"):
+    """Signal of one (b, q) system with the untransformed U-form (Neumann box)."""
+    k = float(seq.dt)
+    th = float(seq.theta)
+    fint = seqmod.interval_f(seq.delta, seq.Delta, seq.dt)
+    G = float(seqmod.b_to_G(b, seq.delta, seq.Delta))
+    qn = _unit(q)
+    N = len(fint) if n_steps is None else int(n_steps)
+
+    base = (asm.S + asm.IG + asm.R2).tocsr()
+    Mk = (asm.M / k).tocsr()
+    qJ = _qJ(asm, qn).tocsr()
+    cache = _LUCache(cache_size)
+    U = asm.u0.astype(np.complex128)
+    for n in range(1, N + 1):
+        fn = float(fint[n - 1])
+        rhs = Mk @ U - (1.0 - th) * (base @ U + 1j * (G * fn) * (qJ @ U))
+        if solver == "dense":
+            U = np.linalg.solve((Mk + th * (base + 1j * (G * fn) * qJ)).toarray(), rhs)
+        elif solver == "krylov":
+            U = _krylov(Mk + th * (base + 1j * (G * fn) * qJ), rhs, U, hermitian=False)
+        else:
+            lu = cache.get(fn, lambda: _splu(Mk + th * (base + 1j * (G * fn) * qJ)))
+            U = lu.solve(rhs)
+    s = complex(asm.w @ U)
+    return (s, U) if return_u else s
+
+
+def signals(prob, seq, b, q, form: str = "auto", asm: Optional[Assembly] = None, **kw):
+    """Signals of every (b_s, q_s) pair on one problem, in input order.
+
+    form: "transformed", "uform", or "auto" (U-form when the box has no
+    periodic axis, transformed otherwise).
+    """
+    if asm is None:
+        asm = assemble(prob)
+    if form == "auto":
+        form = "uform" if int(prob.periodic_mask) == 0 else "transformed"
+    fn = solve_transformed if form == "transformed" else solve_uform
+    b = np.atleast_1d(np.asarray(b, dtype=np.float64))
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
+    return np.array([fn(asm, seq, float(b[i]), q[i], **kw) for i in range(len(b))],
+                    dtype=np.complex128)

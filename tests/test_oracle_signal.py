@@ -1,0 +1,214 @@
+"""Pins of the oracle's time stepping and signal against closed forms.
+
+Each test ties the FP64 oracle to something other than itself:
+
+* free diffusion on a torus: a constant field stays constant, so the
+  theta-scheme collapses to a scalar recurrence written out here; its limit
+  is the Stejskal-Tanner attenuation exp(-D b) with O(dt^2) error
+  (Sec. 2 eq. b_value; Appendix A eq. theta_discretization);
+* mass conservation at b = 0 with permeable membranes (Sec. 2 eq. btpde_ic:
+  the flux is continuous, so no magnetization is lost);
+* kappa -> 0 decouples compartments (equals a run on the sub-mesh alone) and
+  kappa -> infinity merges them (equals the single-compartment run);
+* a gradient parallel to voxel-staircase prisms keeps each compartment
+  constant: per-compartment scalar recurrences;
+* a 1-D slab against the matrix formalism (the paper's reference method,
+  Sec. 4), for both the transformed (Appendix A) and the U-form
+  (Appendix B) discretizations, at second order in (h, dt);
+* the two forms agree on a non-symmetric case with a complex signal, which
+  fixes the sign of the first-order term;
+* S(-q) = conj S(q); dense, SuperLU and Krylov solves agree.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import dmri_inputs as di
+from oracle import fem, mf1d, sequence as sq, timestep
+
+PGSE = di.Sequence(10600.0, 13400.0, 100.0, 0.5)
+
+
+def recurrence(D, b, seq, T2=None, G=None):
+    """c^n = c^{n-1} (1/k - (1-th) a^{n-1}) / (1/k + th a^n), a = D (G F)^2 + 1/T2."""
+    T = seq.Delta + seq.delta
+    N = int(round(T / seq.dt))
+    if G is None:
+        G = math.sqrt(b / (seq.delta ** 2 * (seq.Delta - seq.delta / 3.0)))
+
+    def F(t):
+        return min(max(t, 0.0), seq.delta) - min(max(t - seq.Delta, 0.0), seq.delta)
+
+    r2 = 0.0 if T2 is None else 1.0 / T2
+    c = 1.0
+    for n in range(1, N + 1):
+        a0 = D * (G * F((n - 1) * seq.dt)) ** 2 + r2
+        a1 = D * (G * F(n * seq.dt)) ** 2 + r2
+        c *= (1.0 / seq.dt - (1.0 - seq.theta) * a0) / (1.0 / seq.dt + seq.theta * a1)
+    return c
+
+
+def test_config0_free_diffusion_closed_form():
+    prob, seq, sysl = di.config0()
+    s = timestep.signals(prob, seq, sysl.b, sysl.q)[0]
+    vol = 1000.0
+    c = recurrence(3e-3, 1000.0, seq)
+    assert s.real / vol == pytest.approx(c, rel=1e-12)
+    assert abs(s.imag) < 1e-12 * vol
+    # The value quoted for this workload (discrete CN, dt = 100 us).
+    assert s.real / vol == pytest.approx(0.049775509970, abs=5e-13)
+
+
+def test_stejskal_tanner_second_order():
+    prob = di.free_box(n=4, half=5.0)
+    asm = fem.assemble(prob)
+    D, b = 3e-3, 1000.0
+    st = math.exp(-D * b)
+    errs = []
+    for dt in (100.0, 50.0, 25.0):
+        seq = di.Sequence(10600.0, 13400.0, dt, 0.5)
+        s = timestep.signals(prob, seq, [b], [[1, 0, 0]], asm=asm, solver="krylov")[0]
+        errs.append(s.real / 1000.0 / st - 1.0)
+    assert errs[0] == pytest.approx(-2.32e-4, rel=5e-3)
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.9 < r1 < 4.1 and 3.9 < r2 < 4.1
+
+
+def test_free_diffusion_oblique_with_T2():
+    prob = di.free_box(n=5, half=5.0)
+    prob.T2 = np.array([4.0e4])
+    q = np.array([0.3, -0.5, 0.7])
+    s = timestep.signals(prob, PGSE, [2500.0], [q], solver="krylov")[0]
+    assert s.real / 1000.0 == pytest.approx(recurrence(3e-3, 2500.0, PGSE, T2=4.0e4), rel=1e-11)
+
+
+def test_mass_conservation_b0_permeable():
+    prob = di.cylinder_box(n=10, half=6.0, r=4.0, kappa=1e-2, D_in=1e-3, D_out=3e-3,
+                           u0=(0.3, 1.7))
+    asm = fem.assemble(prob)
+    s = timestep.signals(prob, PGSE, [0.0], [[1, 0, 0]], asm=asm, solver="krylov")[0]
+    expect = 0.3 * asm.comp_volume[0] + 1.7 * asm.comp_volume[1]
+    assert s.real == pytest.approx(expect, rel=1e-11)
+    assert abs(s.imag) < 1e-11 * expect
+
+
+def _submesh(prob, label):
+    keep = prob.tet_label == label
+    return di.Problem(prob.xyz, prob.tets[keep], np.zeros(keep.sum(), np.int32), 1,
+                      np.array([prob.D[label]]), None, None, 0.0, prob.box_lo, prob.box_hi,
+                      prob.periodic_mask)
+
+
+def test_kappa_zero_decouples():
+    prob = di.cylinder_box(n=10, half=6.0, r=4.0, kappa=0.0, D_in=1e-3, D_out=3e-3,
+                           u0=(0.0, 1.0))
+    q = np.array([1.0, 0.4, 0.2])
+    s2 = timestep.signals(prob, PGSE, [2000.0], [q], solver="krylov")[0]
+    s1 = timestep.signals(_submesh(prob, 1), PGSE, [2000.0], [q], solver="krylov")[0]
+    assert s2 == pytest.approx(s1, rel=1e-11, abs=1e-11)
+
+
+def test_kappa_infinity_merges():
+    base = di.cylinder_box(n=8, half=6.0, r=4.0, kappa=0.0)
+    single = di.Problem(base.xyz, base.tets, np.zeros(base.n_tets, np.int32), 1,
+                        np.array([3e-3]), None, None, 0.0, base.box_lo, base.box_hi, 7)
+    q = [[1.0, 0.0, 0.0]]
+    ref = timestep.signals(single, PGSE, [3000.0], q, solver="krylov")[0]
+    errs = []
+    for kappa in (0.1, 1.0, 10.0):
+        p = di.cylinder_box(n=8, half=6.0, r=4.0, kappa=kappa)
+        s = timestep.signals(p, PGSE, [3000.0], q, solver="krylov")[0]
+        errs.append(abs(s - ref) / abs(ref))
+    # O(1/kappa): each decade of kappa removes about a decade of error.
+    assert errs[0] > 5 * errs[1] > 25 * errs[2]
+    assert errs[2] < 3e-4
+
+
+def test_axial_gradient_staircase_prisms():
+    # Voxel labels make every membrane face vertical: with q along z and no
+    # exchange each compartment keeps a constant field.
+    D_in, D_out = 1e-3, 3e-3
+    prob = di.cylinder_box(n=9, half=6.0, r=4.0, kappa=0.0, D_in=D_in, D_out=D_out,
+                           mode="cube")
+    asm = fem.assemble(prob)
+    b = 2000.0
+    s = timestep.signals(prob, PGSE, [b], [[0, 0, 1]], asm=asm, solver="krylov")[0]
+    expect = (asm.comp_volume[0] * recurrence(D_out, b, PGSE)
+              + asm.comp_volume[1] * recurrence(D_in, b, PGSE))
+    assert s.real == pytest.approx(expect, rel=1e-11)
+    # Equal diffusivities: one recurrence even with exchange.
+    prob2 = di.cylinder_box(n=9, half=6.0, r=4.0, kappa=0.05, mode="cube")
+    s2 = timestep.signals(prob2, PGSE, [b], [[0, 0, 1]], solver="krylov")[0]
+    assert s2.real == pytest.approx(1728.0 * recurrence(3e-3, b, PGSE), rel=1e-11)
+
+
+@pytest.mark.parametrize("form,mask", [("uform", 0), ("transformed", 0), ("transformed", 6)])
+def test_slab_matches_matrix_formalism(form, mask):
+    L, D, b = 10.0, 3e-3, 3000.0
+    G = float(sq.b_to_G(b, PGSE.delta, PGSE.Delta))
+    ref = mf1d.slab_signal(L, D, G, PGSE.delta, PGSE.Delta, n_modes=96)
+    # The truncated expansion has converged.
+    assert abs(ref - mf1d.slab_signal(L, D, G, PGSE.delta, PGSE.Delta, n_modes=48)) < 1e-8
+    errs = []
+    for n, dt in ((10, 200.0), (20, 100.0), (40, 50.0)):
+        seq = di.Sequence(PGSE.delta, PGSE.Delta, dt, 0.5)
+        p = di.slab_box(n=n, half=L / 2, split=99.0, cross=(1.0, 1), periodic_mask=mask)
+        s = timestep.signals(p, seq, [b], [[1, 0, 0]], form=form, solver="krylov")[0]
+        errs.append(abs(s - ref) / abs(ref))
+    assert errs[2] < 5e-3
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+
+
+def test_forms_agree_on_complex_signal():
+    # Asymmetric two-compartment slab with exchange and unequal initial
+    # values: the signal has a large imaginary part, whose sign depends on
+    # the sign convention of the first-order term.
+    prev = None
+    vals = []
+    for n, dt in ((10, 200.0), (20, 100.0), (40, 50.0)):
+        seq = di.Sequence(PGSE.delta, PGSE.Delta, dt, 0.5)
+        p = di.slab_box(n=n, half=5.0, split=-1.0, D=(3e-3, 1e-3), kappa=1e-3, u0=(1.0, 0.2),
+                        cross=(1.0, 1), periodic_mask=0)
+        asm = fem.assemble(p)
+        su = timestep.signals(p, seq, [3000.0], [[1, 0, 0]], form="uform", asm=asm,
+                              solver="krylov")[0]
+        st = timestep.signals(p, seq, [3000.0], [[1, 0, 0]], form="transformed", asm=asm,
+                              solver="krylov")[0]
+        vals.append((su, st))
+        d = abs(su - st)
+        if prev is not None:
+            assert prev / d > 3.5
+        prev = d
+    su, st = vals[-1]
+    assert su.imag > 0.5 and st.imag > 0.5
+    assert abs(su - st) / abs(su) < 1e-2
+
+
+def test_conjugate_symmetry():
+    p = di.slab_box(n=12, half=5.0, split=-1.0, D=(3e-3, 1e-3), kappa=1e-3, u0=(1.0, 0.2),
+                    cross=(1.0, 1), periodic_mask=0b110)
+    asm = fem.assemble(p)
+    q = np.array([0.8, 0.36, 0.48])
+    sp_, sm = timestep.signals(p, PGSE, [1500.0, 1500.0], [q, -q], form="transformed",
+                               asm=asm, solver="krylov")
+    assert abs(sp_.imag) > 0.1
+    assert abs(sp_ - np.conj(sm)) < 1e-11 * abs(sp_)
+
+
+def test_dense_splu_krylov_agree():
+    prob = di.cylinder_box(n=4, half=6.0, r=4.0, kappa=1e-2, D_in=1e-3)
+    asm = fem.assemble(prob)
+    seq = di.Sequence(2000.0, 3000.0, 250.0, 0.5)
+    q = [[0.6, 0.0, 0.8]]
+    vals = [timestep.signals(prob, seq, [4000.0], q, asm=asm, solver=s)[0]
+            for s in ("dense", "splu", "krylov")]
+    assert abs(vals[0] - vals[1]) < 1e-12 * abs(vals[0])
+    assert abs(vals[0] - vals[2]) < 1e-11 * abs(vals[0])
+    p0 = di.slab_box(n=6, half=3.0, split=0.5, D=(3e-3, 2e-3), kappa=1e-3, periodic_mask=0)
+    a0 = fem.assemble(p0)
+    vu = [timestep.signals(p0, seq, [4000.0], [[1, 0, 0]], asm=a0, form="uform", solver=s)[0]
+          for s in ("dense", "splu", "krylov")]
+    assert abs(vu[0] - vu[1]) < 1e-12 * abs(vu[0])
+    assert abs(vu[0] - vu[2]) < 1e-11 * abs(vu[0])
