@@ -1,0 +1,211 @@
+/*
+ * dmri.h -- C ABI of libdmri: finite-element Bloch-Torrey simulation of the
+ * diffusion MRI signal on one AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for every (b-value, gradient direction) pair, the
+ * complex signal S = int_Omega U(x, T) dx at echo time T (Sec. 2, eq. signal)
+ * of the Bloch-Torrey equation (Sec. 2, eq. strong_BT) with permeable
+ * membranes between compartments (Sec. 2, eq. btpde_ic), discretized with P1
+ * tetrahedra, one field per compartment (Appendix A, eq. phase_func) and the
+ * theta-method in time (Appendix A, eq. theta_discretization; Appendix B,
+ * eq. matrix_form). Boxes that are periodic along every axis use the strong
+ * imposition of the pseudo-periodic conditions of Sec. 2 (eq. btpde_bc)
+ * through the transformation of Appendix A (eq. trBlo); boxes with walls use
+ * homogeneous Neumann conditions (Sec. 2) on the untransformed U-form of
+ * Appendix B (eq. loadvec). The gradient profile is the PGSE sequence of
+ * Sec. 2 (eq. pgse); b and the gradient strength are related by
+ * eq. b_value.
+ *
+ * Units: micrometres and microseconds throughout. D in um^2/us (== mm^2/s),
+ * b in us/um^2 (== s/mm^2), kappa in um/us (== m/s), T2 in us, signals in
+ * um^3 (volume-weighted magnetization).
+ *
+ * Conventions
+ *  - Every function returns a dmri_status; the library never aborts and no
+ *    C++ exception crosses this interface. dmri_last_error() gives the text
+ *    of the last failure on a handle.
+ *  - All input arrays are owned by the caller and are copied (or fully
+ *    consumed) before the call returns. Outputs go to caller-allocated
+ *    buffers. A handle owns every device allocation it makes until
+ *    dmri_destroy().
+ *  - One handle per host thread at a time; several handles may coexist.
+ *  - Sizes are int64_t, mesh indices int32_t (0-based), reals double.
+ */
+#ifndef DMRI_H
+#define DMRI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dmri_ctx* dmri_handle;
+
+typedef enum {
+    DMRI_OK = 0,
+    DMRI_NOT_CONVERGED = 1,   /* warning: results written, some systems hit max_iter */
+    DMRI_E_INVALID = -1,      /* bad argument (NaN/Inf, out of range, degenerate mesh...) */
+    DMRI_E_STATE = -2,        /* call out of order (no sequence, no device, bad id) */
+    DMRI_E_NOMEM = -3,        /* host or device allocation failed */
+    DMRI_E_DEVICE = -4,       /* HIP runtime error */
+    DMRI_E_UNSUPPORTED = -5   /* valid request this build does not implement */
+} dmri_status;
+
+/* Per-run statistics. Array members are caller-owned, length n_sys (the
+ * n_pairs of the run), and may be NULL. Scalars are always written. */
+typedef struct {
+    int64_t  n_sys;
+    int32_t* iters_total;     /* Krylov iterations summed over all time steps */
+    uint8_t* converged;       /* 1 if every step reached rtol */
+    double*  final_rel_res;   /* ||r|| / ||b|| of the last step */
+    int64_t  total_iterations;/* sum over systems and steps */
+    int64_t  spmv_rows;       /* matrix rows applied (all systems), work counter */
+    int64_t  n_steps;         /* time steps taken */
+    double   t_setup_s;       /* host+device set-up inside the run */
+    double   t_solve_s;       /* time loop */
+    double   t_signal_s;      /* signal quadrature and copy-out */
+} dmri_stats;
+
+/* Create a context on HIP device `device_ordinal`. device_ordinal = -1
+ * creates a host-only context: problems can be added and their assembled
+ * operators exported (dmri_export_operator), but dmri_run* return
+ * DMRI_E_STATE. On failure *out is NULL and dmri_last_error(NULL) has the
+ * reason. */
+dmri_status dmri_create(int device_ordinal, dmri_handle* out);
+
+/* Free every host and device resource of h. NULL-safe. */
+void dmri_destroy(dmri_handle h);
+
+/* Text of the last error on h (or of the last failed dmri_create for
+ * h == NULL). Valid until the next call on h. Never NULL. */
+const char* dmri_last_error(dmri_handle h);
+
+/* Add one mesh with its compartments (Sec. 2: compartments Omega_k with
+ * diffusivity D_k, relaxation T2_k, permeability kappa on the interfaces
+ * Gamma; Sec. 3 "Initial conditions" per compartment).
+ *   xyz        [n_nodes][3] node coordinates
+ *   tets       [n_tets][4] node indices (any orientation)
+ *   tet_label  [n_tets] compartment of each tetrahedron, in [0, n_comp)
+ *   D          [n_comp] > 0
+ *   T2         [n_comp] > 0, or NULL for no relaxation
+ *   u0         [n_comp] initial magnetization per compartment, or NULL (1)
+ *   kappa      >= 0, applied on every face between different labels
+ *   box_lo/hi  the box Omega = [lo, hi] (lo < hi on every axis)
+ *   periodic_mask  7 = periodic along x, y and z: pseudo-periodic
+ *              conditions imposed strongly (Appendix A); opposite faces must
+ *              match node for node. 0 = homogeneous Neumann walls (U-form,
+ *              Appendix B). Other values: DMRI_E_UNSUPPORTED.
+ * Interior interfaces are found from the labels: a face shared by two
+ * tetrahedra with different labels carries the kappa jump term.
+ * Validation (DMRI_E_INVALID): non-finite values, D <= 0, T2 <= 0,
+ * kappa < 0, a label or node index out of range, a degenerate tetrahedron
+ * (|volume| < 1e-12 h^3 with h the mean edge length), a periodic face that
+ * does not match its opposite face.
+ * On success *problem_id receives the new id (0, 1, ...). */
+dmri_status dmri_add_problem(dmri_handle h,
+                             int64_t n_nodes, const double* xyz,
+                             int64_t n_tets, const int32_t* tets,
+                             const int32_t* tet_label, int32_t n_comp,
+                             const double* D, const double* T2, const double* u0,
+                             double kappa,
+                             const double box_lo[3], const double box_hi[3],
+                             uint32_t periodic_mask,
+                             int32_t* problem_id);
+
+/* Number of DOFs (one per compartment touching a node, after periodic
+ * identification) and stored nonzeros of problem `problem_id`. */
+dmri_status dmri_problem_info(dmri_handle h, int32_t problem_id,
+                              int64_t* n_dof, int64_t* nnz);
+
+/* Copy the assembled real operators of a problem (host data, no device).
+ * Every output pointer may be NULL to skip it.
+ *   row_ptr [n_dof+1], col [nnz]: CSR pattern shared by every array
+ *   vals    [6][nnz]: M (mass), R (stiffness + interface + relaxation),
+ *           M_D (D-weighted mass), V_x, V_y, V_z, where V is the skew
+ *           first-order operator B of Appendix A (periodic boxes) or the
+ *           x-weighted mass J of Appendix B (Neumann boxes, x measured
+ *           from the box centre)
+ *   w       [n_dof] signal weights int phi_i over its compartment
+ *   u0      [n_dof] initial magnetization per DOF
+ *   dof_comp [n_dof] compartment, dof_node [n_dof] a mesh node of the DOF
+ *           (the lowest-index node among periodically identified copies). */
+dmri_status dmri_export_operator(dmri_handle h, int32_t problem_id,
+                                 int32_t* row_ptr, int32_t* col, double* vals,
+                                 double* w, double* u0,
+                                 int32_t* dof_comp, int32_t* dof_node);
+
+/* PGSE sequence (Sec. 2, eq. pgse) with pulse length delta and pulse
+ * spacing Delta (us), fixed time step dt (us) and theta in [1/2, 1]
+ * (theta = 1/2 is Crank-Nicolson). The echo time is T = Delta + delta.
+ * delta/dt and Delta/dt must be integers (within 1e-9) so pulse edges
+ * fall on the grid; 0 < delta <= Delta. */
+dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_us,
+                                   double dt_us, double theta);
+
+/* Solver options (all have defaults):
+ *  "precision"  0 = all FP64 (default), 1 = FP32 matrices and Krylov
+ *               vectors with FP64 reductions and FP64 residual refinement
+ *  "krylov"     0 = auto (CG on the Hermitian transformed operator, COCG on
+ *               the complex-symmetric U-form), 1 = CG, 2 = COCG
+ *  "rtol"       per-step relative residual ||b - A x|| <= rtol ||b||
+ *               (default 1e-10)
+ *  "inner_rtol" FP32 inner solve reduction in mixed precision (1e-4)
+ *  "max_iter"   Krylov iterations per step and system (default 2000)
+ *  "guess"      0 = previous step, 1 = linear extrapolation (default),
+ *               2 = learned correction (needs dmri_load_guess_model)
+ *  "sys_tile"   systems per lane group: 0 = auto, or 8, 16, 32, 64
+ *  "graph"      1 = replay chunks of Krylov iterations from a HIP graph
+ *  "autotune"   1 = time the tile candidates on the first step and keep the
+ *               fastest per problem size
+ *  "n_steps"    0 = full echo (default); n > 0 stops after n steps and
+ *               returns sum_i w_i u_i^n (a sampling aid, not a signal unless
+ *               F(t^n) = 0)
+ * Unknown keys or out-of-range values: DMRI_E_INVALID. */
+dmri_status dmri_set_option(dmri_handle h, const char* key, double value);
+dmri_status dmri_get_option(dmri_handle h, const char* key, double* value);
+
+/* Load the weights of the learned initial-guess network from a file written
+ * by the Python training driver (little-endian float32 blob with a header).
+ * Used when option "guess" = 2. */
+dmri_status dmri_load_guess_model(dmri_handle h, const char* path);
+
+/* Simulate n_pairs (problem, b, direction) systems and write their signals.
+ *   problem_id [n_pairs] ids from dmri_add_problem
+ *   b          [n_pairs] >= 0
+ *   q          [n_pairs][3] gradient direction, normalized inside; ignored
+ *              when b == 0; must be nonzero when b > 0
+ *   signal_out [n_pairs][2] Re, Im of S (um^3)
+ *   stats      may be NULL
+ * All pairs of all problems are solved as one batch on the device.
+ * Returns DMRI_NOT_CONVERGED (results still written) when any system hit
+ * max_iter in some step. */
+dmri_status dmri_run(dmri_handle h, int64_t n_pairs,
+                     const int32_t* problem_id, const double* b, const double* q,
+                     double* signal_out, dmri_stats* stats);
+
+/* Same as dmri_run with device-resident inputs and output (e.g. from
+ * PyTorch tensors): d_b [n_pairs], d_q [n_pairs][3], d_signal [n_pairs][2]
+ * are device pointers, all pairs on one problem (problem_id). Work is
+ * enqueued on hip_stream (NULL = the handle's own stream); the call
+ * synchronizes that stream to poll convergence and returns after the
+ * signals have been written. */
+dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
+                            int64_t n_pairs, const double* d_b, const double* d_q,
+                            double* d_signal, dmri_stats* stats);
+
+/* Apply one step operator of problem `problem_id` to host vectors
+ * (kernel check): y = (Base + c M_D + i (d . V)) x with Base = M/dt +
+ * theta R when which = 0 (left side) or M/dt - (1-theta) R when which = 1
+ * (right side, without the sign flip of the time-dependent parts: the
+ * coefficients are taken as given). x, y: [n_dof][n_sys][2] doubles;
+ * c [n_sys], d [n_sys][3]. Uses the precision of option "precision". */
+dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which,
+                                int64_t n_sys, const double* c, const double* d,
+                                const double* x, double* y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMRI_H */

@@ -1,0 +1,262 @@
+"""ctypes binding of libdmri (argument marshalling only).
+
+Every computation runs in the C/HIP library; this module converts NumPy
+arrays and PyTorch device tensors to pointers and status codes to
+exceptions. Function names follow the C ABI declared in include/dmri.h.
+If the shared library is missing the import fails loudly: there is no
+Python or CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdmri.so")
+
+DMRI_OK = 0
+DMRI_NOT_CONVERGED = 1
+STATUS_NAMES = {
+    0: "DMRI_OK", 1: "DMRI_NOT_CONVERGED", -1: "DMRI_E_INVALID", -2: "DMRI_E_STATE",
+    -3: "DMRI_E_NOMEM", -4: "DMRI_E_DEVICE", -5: "DMRI_E_UNSUPPORTED",
+}
+
+# Symbols declared in include/dmri.h (checked by the CPU test suite).
+EXPORTED = [
+    "dmri_create", "dmri_destroy", "dmri_last_error", "dmri_add_problem", "dmri_problem_info",
+    "dmri_export_operator", "dmri_set_sequence_pgse", "dmri_set_option", "dmri_get_option",
+    "dmri_load_guess_model", "dmri_run", "dmri_run_device", "dmri_apply_operator",
+]
+
+
+class DmriError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("n_sys", C.c_int64),
+        ("iters_total", C.POINTER(C.c_int32)),
+        ("converged", C.POINTER(C.c_uint8)),
+        ("final_rel_res", C.POINTER(C.c_double)),
+        ("total_iterations", C.c_int64),
+        ("spmv_rows", C.c_int64),
+        ("n_steps", C.c_int64),
+        ("t_setup_s", C.c_double),
+        ("t_solve_s", C.c_double),
+        ("t_signal_s", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load libdmri.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError("libdmri.so not found at %s: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`" % p)
+    lib = C.CDLL(p)
+    P = C.POINTER
+    dbl, i32, i64 = C.c_double, C.c_int32, C.c_int64
+    vp = C.c_void_p
+    lib.dmri_create.argtypes = [C.c_int, P(vp)]
+    lib.dmri_destroy.argtypes = [vp]
+    lib.dmri_destroy.restype = None
+    lib.dmri_last_error.argtypes = [vp]
+    lib.dmri_last_error.restype = C.c_char_p
+    lib.dmri_add_problem.argtypes = [vp, i64, vp, i64, vp, vp, i32, vp, vp, vp, dbl, vp, vp,
+                                     C.c_uint32, P(i32)]
+    lib.dmri_problem_info.argtypes = [vp, i32, P(i64), P(i64)]
+    lib.dmri_export_operator.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.dmri_set_sequence_pgse.argtypes = [vp, dbl, dbl, dbl, dbl]
+    lib.dmri_set_option.argtypes = [vp, C.c_char_p, dbl]
+    lib.dmri_get_option.argtypes = [vp, C.c_char_p, P(dbl)]
+    lib.dmri_load_guess_model.argtypes = [vp, C.c_char_p]
+    lib.dmri_run.argtypes = [vp, i64, vp, vp, vp, vp, P(Stats)]
+    lib.dmri_run_device.argtypes = [vp, vp, i32, i64, vp, vp, vp, P(Stats)]
+    lib.dmri_apply_operator.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
+    for name in EXPORTED:
+        f = getattr(lib, name)
+        if name not in ("dmri_destroy", "dmri_last_error"):
+            f.restype = C.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+class Simulator:
+    """Owns one dmri_handle. device=-1 gives a host-only context."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = C.c_void_p()
+        st = self.lib.dmri_create(int(device), C.byref(h))
+        if st != DMRI_OK:
+            raise DmriError(st, self.lib.dmri_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    # -- errors -------------------------------------------------------------
+    def _check(self, st: int, allow_nc: bool = False) -> int:
+        if st == DMRI_OK or (allow_nc and st == DMRI_NOT_CONVERGED):
+            return st
+        raise DmriError(st, self.lib.dmri_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dmri_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- problems -----------------------------------------------------------
+    def dmri_add_problem(self, xyz, tets, tet_label, n_comp, D, T2=None, u0=None, kappa=0.0,
+                         box_lo=(0, 0, 0), box_hi=(1, 1, 1), periodic_mask=7) -> int:
+        xyz = _c(xyz, np.float64).reshape(-1, 3)
+        tets = _c(tets, np.int32).reshape(-1, 4)
+        lab = _c(tet_label, np.int32).reshape(-1)
+        D = _c(D, np.float64)
+        T2 = _c(T2, np.float64)
+        u0 = _c(u0, np.float64)
+        lo = _c(box_lo, np.float64)
+        hi = _c(box_hi, np.float64)
+        pid = C.c_int32(-1)
+        self._check(self.lib.dmri_add_problem(
+            self.h, xyz.shape[0], _ptr(xyz), tets.shape[0], _ptr(tets), _ptr(lab), int(n_comp),
+            _ptr(D), _ptr(T2), _ptr(u0), float(kappa), _ptr(lo), _ptr(hi),
+            int(periodic_mask), C.byref(pid)))
+        return pid.value
+
+    def add_problem(self, prob) -> int:
+        """Add a dmri_inputs.Problem-like object (fields as in include/dmri.h)."""
+        return self.dmri_add_problem(prob.xyz, prob.tets, prob.tet_label, prob.n_comp, prob.D,
+                                     prob.T2, prob.u0, prob.kappa, prob.box_lo, prob.box_hi,
+                                     prob.periodic_mask)
+
+    def dmri_problem_info(self, pid: int):
+        n, z = C.c_int64(), C.c_int64()
+        self._check(self.lib.dmri_problem_info(self.h, int(pid), C.byref(n), C.byref(z)))
+        return n.value, z.value
+
+    def dmri_export_operator(self, pid: int) -> dict:
+        n, nnz = self.dmri_problem_info(pid)
+        out = {
+            "row_ptr": np.empty(n + 1, np.int32), "col": np.empty(nnz, np.int32),
+            "vals": np.empty((6, nnz), np.float64), "w": np.empty(n, np.float64),
+            "u0": np.empty(n, np.float64), "dof_comp": np.empty(n, np.int32),
+            "dof_node": np.empty(n, np.int32),
+        }
+        self._check(self.lib.dmri_export_operator(
+            self.h, int(pid), _ptr(out["row_ptr"]), _ptr(out["col"]), _ptr(out["vals"]),
+            _ptr(out["w"]), _ptr(out["u0"]), _ptr(out["dof_comp"]), _ptr(out["dof_node"])))
+        return out
+
+    # -- sequence and options -----------------------------------------------
+    def dmri_set_sequence_pgse(self, delta, Delta, dt, theta=0.5):
+        self._check(self.lib.dmri_set_sequence_pgse(self.h, float(delta), float(Delta),
+                                                    float(dt), float(theta)))
+
+    def set_sequence(self, seq):
+        self.dmri_set_sequence_pgse(seq.delta, seq.Delta, seq.dt, seq.theta)
+
+    def dmri_set_option(self, key: str, value: float):
+        self._check(self.lib.dmri_set_option(self.h, key.encode(), float(value)))
+
+    def dmri_get_option(self, key: str) -> float:
+        v = C.c_double()
+        self._check(self.lib.dmri_get_option(self.h, key.encode(), C.byref(v)))
+        return v.value
+
+    def set_options(self, **kw):
+        for k, v in kw.items():
+            self.dmri_set_option(k, v)
+
+    def dmri_load_guess_model(self, path: str):
+        self._check(self.lib.dmri_load_guess_model(self.h, os.fsencode(path)))
+
+    # -- runs ---------------------------------------------------------------
+    def dmri_run(self, problem_id: Sequence[int], b, q, want_stats: bool = True):
+        """Signals (complex128 [n]) and a stats dict."""
+        b = _c(np.atleast_1d(b), np.float64)
+        n = b.shape[0]
+        pid = _c(np.broadcast_to(np.asarray(problem_id, dtype=np.int32), (n,)), np.int32)
+        q = _c(q, np.float64).reshape(n, 3)
+        sig = np.empty((n, 2), np.float64)
+        iters = np.zeros(n, np.int32)
+        conv = np.zeros(n, np.uint8)
+        rres = np.zeros(n, np.float64)
+        st = Stats()
+        st.iters_total = iters.ctypes.data_as(C.POINTER(C.c_int32))
+        st.converged = conv.ctypes.data_as(C.POINTER(C.c_uint8))
+        st.final_rel_res = rres.ctypes.data_as(C.POINTER(C.c_double))
+        status = self._check(self.lib.dmri_run(self.h, n, _ptr(pid), _ptr(b), _ptr(q),
+                                               _ptr(sig), C.byref(st)), allow_nc=True)
+        stats = _stats_dict(st, iters, conv, rres, status)
+        return sig[:, 0] + 1j * sig[:, 1], stats
+
+    def dmri_run_device(self, problem_id: int, b_dev, q_dev, sig_dev, stream_ptr=None):
+        """Device-resident run. b_dev/q_dev/sig_dev are torch float64 CUDA tensors
+        ([n], [n,3], [n,2]); stream_ptr is a raw HIP stream handle or None."""
+        n = int(b_dev.shape[0])
+        for t in (b_dev, q_dev, sig_dev):
+            if not t.is_contiguous():
+                raise ValueError("tensors must be contiguous")
+        st = Stats()
+        status = self._check(self.lib.dmri_run_device(
+            self.h, None if stream_ptr is None else C.c_void_p(stream_ptr), int(problem_id), n,
+            C.c_void_p(b_dev.data_ptr()), C.c_void_p(q_dev.data_ptr()),
+            C.c_void_p(sig_dev.data_ptr()), C.byref(st)), allow_nc=True)
+        return _stats_dict(st, None, None, None, status)
+
+    def dmri_apply_operator(self, pid: int, which: int, c, d, x):
+        c = _c(c, np.float64).reshape(-1)
+        ns = c.shape[0]
+        d = _c(d, np.float64).reshape(ns, 3)
+        x = np.asarray(x)
+        n = x.shape[0]
+        xr = np.empty((n, ns, 2), np.float64)
+        xr[..., 0] = x.real
+        xr[..., 1] = x.imag
+        y = np.empty_like(xr)
+        self._check(self.lib.dmri_apply_operator(self.h, int(pid), int(which), ns, _ptr(c),
+                                                 _ptr(d), _ptr(xr), _ptr(y)))
+        return y[..., 0] + 1j * y[..., 1]
+
+
+def _stats_dict(st, iters, conv, rres, status):
+    return {
+        "status": STATUS_NAMES.get(status, status),
+        "iters_total": iters, "converged": conv, "final_rel_res": rres,
+        "total_iterations": st.total_iterations, "spmv_rows": st.spmv_rows,
+        "n_steps": st.n_steps, "t_setup_s": st.t_setup_s, "t_solve_s": st.t_solve_s,
+        "t_signal_s": st.t_signal_s,
+    }

@@ -1,0 +1,73 @@
+// Host-side mesh processing and operator assembly for libdmri.
+//
+// Builds, once per mesh, the time-independent real sparse operators of the
+// P1 / PUFEM discretization (Appendix A, eq. theta_discretization and
+// eq. phase_func; Appendix B, eq. loadvec):
+//   M   = sum_k int_{Omega_k} phi_i phi_j
+//   R   = sum_k D_k int grad phi_i . grad phi_j              (stiffness)
+//         + kappa int_Gamma [[phi_i]] [[phi_j]]              (membranes)
+//         + sum_k (1/T2_k) int_{Omega_k} phi_i phi_j          (relaxation)
+//   M_D = sum_k D_k int_{Omega_k} phi_i phi_j
+//   V_a = B_a = sum_k D_k int (phi_i d_a phi_j - phi_j d_a phi_i)   (periodic box)
+//   V_a = J_a = sum_k int (x_a - c_a) phi_i phi_j                   (Neumann box)
+// on the DOF set "one P1 field per compartment": DOF (k, node) exists iff the
+// node touches a tetrahedron of compartment k. Periodic boxes identify the
+// nodes of opposite faces (strong pseudo-periodic imposition, Appendix A).
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dmri.h"
+
+namespace dmri {
+
+struct Error : std::runtime_error {
+    dmri_status code;
+    Error(dmri_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+enum Form : int32_t { FORM_TRANSFORMED = 1, FORM_UFORM = 2 };
+
+struct MeshInput {
+    int64_t n_nodes = 0;
+    const double* xyz = nullptr;
+    int64_t n_tets = 0;
+    const int32_t* tets = nullptr;
+    const int32_t* label = nullptr;
+    int32_t n_comp = 0;
+    const double* D = nullptr;
+    const double* T2 = nullptr;   // may be null
+    const double* u0 = nullptr;   // may be null
+    double kappa = 0.0;
+    double lo[3] = {0, 0, 0};
+    double hi[3] = {0, 0, 0};
+    uint32_t periodic_mask = 0;
+};
+
+// Assembled operators in the library's DOF order (spatially sorted).
+struct HostOperator {
+    int32_t form = FORM_TRANSFORMED;
+    int64_t n_dof = 0;
+    int64_t nnz = 0;
+    int32_t n_comp = 0;
+    std::vector<int32_t> row_ptr, col, diag_pos;
+    std::vector<double> M, R, MD, V[3];
+    std::vector<double> w, u0;
+    std::vector<int32_t> dof_comp, dof_node;
+    std::vector<double> comp_volume;
+    double volume = 0.0;
+    double interface_area = 0.0;
+    int64_t n_torus_nodes = 0;
+    int64_t n_interface_faces = 0;
+    // Extra per-DOF geometry used by the learned guess features.
+    std::vector<float> dof_xyz;      // [n_dof][3] position relative to box centre
+    std::vector<float> dof_membrane; // [n_dof] 1 if the node also belongs to another compartment
+};
+
+// Validate the input and assemble. Throws dmri::Error.
+HostOperator assemble(const MeshInput& in);
+
+}  // namespace dmri

@@ -1,0 +1,128 @@
+// Device kernels of libdmri (gfx950 / CDNA4) and their host launchers.
+//
+// Data layout in HBM (one problem = one mesh):
+//   CSR pattern      row_ptr[n+1], col[nnz]                        int32
+//   matrix values    K0[nnz], Kr[nnz]                               T
+//                    aux[nnz] = {M_D, V_x, V_y, V_z}                T4 (16/32 B)
+//                    dK0[n], daux[n] (the diagonal, for Jacobi)
+//   vectors          [n_rows][ld] complex (T2), systems fastest;
+//                    ld = number of systems rounded up to the tile width
+//   per system       gq[ld] = {G, q_x, q_y, q_z} (double4)
+// K0 = M/dt + theta R is the constant part of the left operator,
+// Kr = M/dt - (1-theta) R the constant part of the right operator
+// (Appendix A, eq. linear_billinear). The time-dependent parts are built on
+// the fly per system: c = cm (G F)^2 on M_D and i d . V with d = cd G F q.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dmri {
+
+template <typename T> struct Vec2Of;
+template <> struct Vec2Of<double> { using type = double2; };
+template <> struct Vec2Of<float> { using type = float2; };
+template <typename T> struct Vec4Of;
+template <> struct Vec4Of<double> { using type = double4; };
+template <> struct Vec4Of<float> { using type = float4; };
+
+template <typename T>
+struct MatView {
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const T* K0;
+    const T* Kr;
+    const typename Vec4Of<T>::type* aux;
+    const T* dK0;
+    const typename Vec4Of<T>::type* daux;
+    int32_t n_rows;
+};
+
+// Coefficients of one operator application: F value of the step and the
+// multipliers of (G F)^2 (on M_D) and G F q (on V).
+struct Coef {
+    double F;
+    double cm;
+    double cd;
+};
+
+// Per-system Krylov state, all FP64.
+struct SolverState {
+    double2* rho;
+    double2* alpha;
+    double2* beta;
+    double* bb;         // ||b||^2
+    double* rr;         // ||r||^2
+    int32_t* active;    // 1 while iterating
+    int32_t* iters;     // iterations this step
+    int32_t* iters_total;
+    int32_t* flags;     // bit 0: hit max_iter, bit 1: non-finite residual
+    int32_t* n_active;  // systems still iterating (single counter)
+    int32_t n_sys;
+    int32_t max_iter;
+    double rtol2;
+};
+
+// Launch geometry shared by every kernel of a problem.
+struct Geom {
+    int32_t n_rows;
+    int32_t ld;          // leading dimension (systems, padded)
+    int32_t S;           // systems per lane group (tile width)
+    int32_t n_tiles;     // ld / S
+    int32_t n_chunks;    // row chunks per tile
+    int32_t chunk_rows;  // rows per chunk (multiple of 4 * 64 / S)
+};
+
+struct Scratch {
+    double* partial;     // [n_chunks][ld][4]
+    int32_t* counters;   // [n_tiles], zero between launches
+};
+
+Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t target_blocks);
+
+// guess_mode: 0 x0 = u_prev, 1 x0 = 2 u_prev - u_prev2, 2 x0 given in x.
+template <typename T>
+void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
+                 Coef lhs, Coef rhs, bool herm, int guess_mode,
+                 const typename Vec2Of<T>::type* u_prev, const typename Vec2Of<T>::type* u_prev2,
+                 typename Vec2Of<T>::type* x, typename Vec2Of<T>::type* r,
+                 typename Vec2Of<T>::type* p, SolverState s, Scratch sc);
+
+template <typename T>
+void launch_spmv_dot(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
+                     Coef lhs, bool herm, const typename Vec2Of<T>::type* p,
+                     typename Vec2Of<T>::type* q, SolverState s, Scratch sc);
+
+template <typename T>
+void launch_update(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
+                   Coef lhs, bool herm, typename Vec2Of<T>::type* x,
+                   typename Vec2Of<T>::type* r, const typename Vec2Of<T>::type* p,
+                   const typename Vec2Of<T>::type* q, SolverState s, Scratch sc);
+
+template <typename T>
+void launch_pupdate(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
+                    Coef lhs, const typename Vec2Of<T>::type* r, typename Vec2Of<T>::type* p,
+                    SolverState s);
+
+template <typename T>
+void launch_signal(hipStream_t st, const Geom& g, const double* w,
+                   const typename Vec2Of<T>::type* x, double2* out, int32_t n_sys, Scratch sc);
+
+// y = (Base + c M_D + i d.V) x for explicit per-system c and d (kernel check).
+template <typename T>
+void launch_apply(hipStream_t st, const Geom& g, const MatView<T>& A, int which,
+                  const double* c, const double3* d, const typename Vec2Of<T>::type* x,
+                  typename Vec2Of<T>::type* y);
+
+// Fill: x = u0 per DOF for every system < n_sys, 0 for padding.
+template <typename T>
+void launch_set_initial(hipStream_t st, const Geom& g, const double* u0, int32_t n_sys,
+                        typename Vec2Of<T>::type* x);
+
+// Per-system parameters from b and q on the device: G = sqrt(b / intF2),
+// q normalised; padding systems get G = 0.
+void launch_sys_params(hipStream_t st, int32_t n_sys, int32_t ld, const double* b,
+                       const double* q, double int_F2, double4* gq, int32_t* bad);
+
+}  // namespace dmri

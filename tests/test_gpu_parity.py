@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances: the all-FP64 GPU path within 1e-9 of the oracle's exact-solve
+signal (relative error with the floor max(|S_ref|, 1e-8 S(b=0))); the FP32
+operator within 1e-6 of FP64 CSR products.
+"""
+
+import numpy as np
+import pytest
+
+import dmri_inputs as di
+from oracle import fem, timestep
+
+pytestmark = pytest.mark.gpu
+
+SHORT = di.Sequence(2000.0, 4000.0, 200.0, 0.5)
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_01719_amd import Simulator
+    return Simulator
+
+
+def rel_err(s, ref, s0):
+    floor = np.maximum(np.abs(ref), 1e-8 * abs(s0))
+    return np.abs(s - ref) / floor
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_apply_operator_matches_csr(Sim):
+    prob = di.cylinder_box(n=10, half=6.0, r=4.0, kappa=1e-2, D_in=1e-3)
+    rng = np.random.default_rng(0)
+    with Sim(0) as sim:
+        sim.set_sequence(di.PGSE_SHORT)
+        pid = sim.add_problem(prob)
+        exp = sim.dmri_export_operator(pid)
+        n = exp["w"].shape[0]
+        rows = np.repeat(np.arange(n), np.diff(exp["row_ptr"]))
+        import scipy.sparse as sp
+        mk = lambda v: sp.csr_matrix((v, (rows, exp["col"])), shape=(n, n))  # noqa: E731
+        M, R, MD = mk(exp["vals"][0]), mk(exp["vals"][1]), mk(exp["vals"][2])
+        V = [mk(exp["vals"][3 + a]) for a in range(3)]
+        k, th = di.PGSE_SHORT.dt, di.PGSE_SHORT.theta
+        for n_sys in (1, 13, 64, 70):
+            c = rng.uniform(0, 2e-3, n_sys)
+            d = rng.normal(size=(n_sys, 3)) * 0.01
+            x = rng.normal(size=(n, n_sys)) + 1j * rng.normal(size=(n, n_sys))
+            for which, base in ((0, M / k + th * R), (1, M / k - (1 - th) * R)):
+                ref = np.empty_like(x)
+                for s in range(n_sys):
+                    A = base + c[s] * MD + 1j * (d[s, 0] * V[0] + d[s, 1] * V[1] + d[s, 2] * V[2])
+                    ref[:, s] = A @ x[:, s]
+                for prec, tol in ((0, 1e-13), (2, 2e-6)):
+                    sim.dmri_set_option("precision", prec)
+                    y = sim.dmri_apply_operator(pid, which, c, d, x)
+                    err = np.abs(y - ref).max() / np.abs(ref).max()
+                    _say("apply n_sys=%d which=%d prec=%d err=%.2e" % (n_sys, which, prec, err))
+                    assert err < tol
+        sim.dmri_set_option("precision", 0)
+
+
+def test_config0_closed_form(Sim):
+    prob, seq, sysl = di.config0()
+    with Sim(0) as sim:
+        sim.set_sequence(seq)
+        sim.set_options(rtol=1e-12)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid], sysl.b, sysl.q)
+    assert st["status"] == "DMRI_OK"
+    assert sig[0].real / 1000.0 == pytest.approx(0.049775509970, abs=1e-11)
+    assert abs(sig[0].imag) < 1e-10
+
+
+def _cyl_case():
+    prob = di.cylinder_box(n=11, half=6.0, r=4.3, kappa=5e-3, D_in=1.5e-3, T2=(6e4, 4e4),
+                           u0=(1.0, 0.7))
+    b = np.array([0.0, 500.0, 1500.0, 3000.0, 5000.0, 2500.0, 4000.0, 1000.0, 3500.0, 200.0,
+                  4500.0, 800.0, 2000.0])
+    q = di.fibonacci_directions(13)
+    return prob, b, q
+
+
+@pytest.mark.parametrize("tile", [0, 8, 16, 64])
+@pytest.mark.parametrize("guess", [0, 1])
+def test_fp64_transformed_matches_oracle(Sim, tile, guess):
+    prob, b, q = _cyl_case()
+    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12, sys_tile=tile, guess=guess)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+    err = rel_err(sig, ref, ref[0])
+    _say("tile=%d guess=%d max err %.2e iters %s" % (tile, guess, err.max(),
+                                                    st["iters_total"].tolist()))
+    assert st["status"] == "DMRI_OK"
+    assert err.max() < 1e-9
+
+
+def test_fp64_full_pgse_config1_geometry_coarse(Sim):
+    # The config-1 geometry (cylinder r=5 in a 12 um box) at n=12 with the
+    # full PGSE timing of the workload.
+    prob = di.cylinder_box(n=12)
+    seq = di.PGSE_SHORT
+    b = np.linspace(0.0, 3000.0, 8)
+    q = np.tile([[1.0, 0.0, 0.0]], (8, 1))
+    ref = timestep.signals(prob, seq, b, q, solver="krylov")
+    with Sim(0) as sim:
+        sim.set_sequence(seq)
+        sim.set_options(rtol=1e-12)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * 8, b, q)
+    err = rel_err(sig, ref, ref[0])
+    _say("config1-coarse max err %.2e" % err.max())
+    assert err.max() < 1e-9
+    assert sig[0].real == pytest.approx(1728.0, rel=1e-12)
+
+
+def test_uform_cocg_matches_oracle(Sim):
+    prob = di.slab_box(n=10, half=5.0, split=-1.0, D=(3e-3, 1e-3), kappa=1e-3, u0=(1.0, 0.2),
+                       periodic_mask=0)
+    b = np.array([0.0, 1000.0, 3000.0])
+    q = np.array([[1.0, 0.0, 0.0], [0.8, 0.6, 0.0], [0.0, 0.3, 0.95]])
+    ref = timestep.signals(prob, SHORT, b, q, form="uform", solver="splu")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * 3, b, q)
+    err = rel_err(sig, ref, ref[0])
+    _say("uform max err %.2e" % err.max())
+    assert err.max() < 1e-9
+    assert abs(ref[1].imag) > 1e-3  # a genuinely complex signal
+
+
+def test_batched_equals_single(Sim):
+    prob, b, q = _cyl_case()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12)
+        pid = sim.add_problem(prob)
+        allsig, _ = sim.dmri_run([pid] * len(b), b, q)
+        for i in (3, 7, 12):
+            one, _ = sim.dmri_run([pid], b[i:i + 1], q[i:i + 1])
+            assert abs(one[0] - allsig[i]) <= 1e-11 * abs(allsig[0])
+
+
+def test_two_problems_one_run(Sim):
+    p1 = di.cylinder_box(n=9, half=6.0, r=4.0, kappa=1e-2)
+    p2 = di.free_box(n=7, half=3.5)
+    b = np.array([1000.0, 2000.0, 1000.0, 3000.0])
+    q = np.array([[1.0, 0, 0], [0, 1.0, 0], [0.6, 0.8, 0], [0, 0, 1.0]])
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12)
+        i1 = sim.add_problem(p1)
+        i2 = sim.add_problem(p2)
+        sig, _ = sim.dmri_run([i1, i2, i2, i1], b, q)
+    r1 = timestep.signals(p1, SHORT, b[[0, 3]], q[[0, 3]], solver="splu")
+    r2 = timestep.signals(p2, SHORT, b[[1, 2]], q[[1, 2]], solver="splu")
+    assert np.abs(sig[[0, 3]] - r1).max() < 1e-9 * abs(r1).max()
+    assert np.abs(sig[[1, 2]] - r2).max() < 1e-9 * abs(r2).max()
+
+
+def test_sampled_first_steps(Sim):
+    # n_steps limits the run; compare sum w u^n after 3 steps with the oracle.
+    prob, b, q = _cyl_case()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-13, n_steps=3)
+        pid = sim.add_problem(prob)
+        sig, _ = sim.dmri_run([pid] * 4, b[:4], q[:4])
+    ref = timestep.signals(prob, SHORT, b[:4], q[:4], solver="splu", n_steps=3)
+    assert np.abs(sig - ref).max() < 1e-10 * abs(ref).max()
+
+
+def test_not_converged_and_invalid(Sim):
+    from paper_1908_01719_amd import DmriError
+    prob, b, q = _cyl_case()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.set_options(max_iter=1, rtol=1e-12)
+        sig, st = sim.dmri_run([pid] * 3, b[1:4], q[1:4])
+        assert st["status"] == "DMRI_NOT_CONVERGED"
+        assert not st["converged"].any()
+        assert np.all(np.isfinite(sig))
+        sim.set_options(max_iter=2000)
+        with pytest.raises(DmriError) as ei:
+            sim.dmri_run([pid], [-1.0], [[1, 0, 0]])
+        assert "DMRI_E_INVALID" in str(ei.value)
+        with pytest.raises(DmriError):
+            sim.dmri_run([pid], [1000.0], [[0, 0, 0]])
+        with pytest.raises(DmriError):
+            sim.dmri_run([5], [1000.0], [[1, 0, 0]])
+
+
+def test_run_device_torch(Sim):
+    import torch
+    prob, b, q = _cyl_case()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12)
+        pid = sim.add_problem(prob)
+        host, _ = sim.dmri_run([pid] * len(b), b, q)
+        db = torch.tensor(b, dtype=torch.float64, device="cuda")
+        dq = torch.tensor(q, dtype=torch.float64, device="cuda")
+        ds = torch.zeros((len(b), 2), dtype=torch.float64, device="cuda")
+        stream = torch.cuda.current_stream()
+        st = sim.dmri_run_device(pid, db, dq, ds, stream_ptr=stream.cuda_stream)
+        torch.cuda.synchronize()
+        dev = ds.cpu().numpy()
+    assert st["status"] == "DMRI_OK"
+    np.testing.assert_allclose(dev[:, 0] + 1j * dev[:, 1], host, rtol=0, atol=1e-12 * abs(host[0]))
+
+
+def test_fp32_path_close(Sim):
+    prob, b, q = _cyl_case()
+    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(precision=2, rtol=1e-6)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+    err = rel_err(sig, ref, ref[0])
+    _say("fp32 max err %.2e" % err.max())
+    assert err.max() < 1e-4

@@ -1,0 +1,142 @@
+"""Host logic of libdmri on the CPU (host-only context, no device calls).
+
+* the shared library loads and exports every function include/dmri.h declares;
+* the C++ assembly (periodic identification, PUFEM DOFs, CSR, element and
+  membrane integrals) equals the oracle's operators entry by entry after
+  matching DOFs by (compartment, mesh node);
+* input validation returns DMRI_E_INVALID / DMRI_E_UNSUPPORTED.
+"""
+
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import dmri_inputs as di
+from oracle import fem
+from paper_1908_01719_amd import binding
+from paper_1908_01719_amd.binding import DmriError, Simulator
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    header = open(os.path.join(ROOT, "include", "dmri.h")).read()
+    declared = sorted(set(re.findall(r"\b(dmri_[a-z_]+)\s*\(", header)))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(binding.EXPORTED) == declared
+
+
+def _lib_to_oracle_perm(prob, exp, asm):
+    tn, _ = fem.torus_nodes(prob.xyz, prob.box_lo, prob.box_hi, prob.periodic_mask)
+    key = {(int(c), int(n)): i for i, (c, n) in enumerate(zip(asm.dof_comp, asm.dof_node))}
+    return np.array([key[(int(c), int(tn[n]))] for c, n in zip(exp["dof_comp"], exp["dof_node"])])
+
+
+CASES = {
+    "free_periodic": lambda: di.free_box(n=5, half=2.5),
+    "cyl_centroid": lambda: di.cylinder_box(n=9, half=6.0, r=4.0, kappa=2e-3, D_in=1e-3,
+                                            T2=(5e4, 3e4), u0=(0.5, 1.5)),
+    "cyl_cube": lambda: di.cylinder_box(n=8, half=6.0, r=4.0, kappa=0.1, mode="cube"),
+    "slab_neumann": lambda: di.slab_box(n=6, half=3.0, split=0.4, D=(3e-3, 1e-3), kappa=1e-2,
+                                        periodic_mask=0),
+    "seeded_cells": lambda: di.config3(3, n_fixed=10)[0],
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_operators_match_oracle(name):
+    prob = CASES[name]()
+    with Simulator(-1) as s:
+        pid = s.add_problem(prob)
+        exp = s.dmri_export_operator(pid)
+    asm = fem.assemble(prob)
+    n = asm.n_dof
+    assert exp["w"].shape[0] == n
+    perm = _lib_to_oracle_perm(prob, exp, asm)
+    assert sorted(perm) == list(range(n))
+    nnz = exp["col"].shape[0]
+    rows = np.repeat(np.arange(n), np.diff(exp["row_ptr"]))
+    P = sp.csr_matrix((np.ones(n), (np.arange(n), perm)), shape=(n, n))
+    V = asm.B if prob.periodic_mask else asm.J
+    refs = [asm.M, asm.S + asm.IG + asm.R2, asm.MD, V[0], V[1], V[2]]
+    names = ["M", "R", "MD", "Vx", "Vy", "Vz"]
+    for a in range(6):
+        mine = sp.csr_matrix((exp["vals"][a], (rows, exp["col"])), shape=(n, n))
+        ref = (P @ refs[a] @ P.T).tocsr()
+        scale = abs(ref).max()
+        diff = abs(mine - ref).max()
+        assert diff <= 1e-12 * scale, (names[a], diff, scale)
+    np.testing.assert_allclose(exp["w"], asm.w[perm], rtol=1e-13)
+    np.testing.assert_allclose(exp["u0"], asm.u0[perm], rtol=0)
+    # Every stored row holds its diagonal and the pattern is symmetric.
+    pat = sp.csr_matrix((np.ones(nnz), (rows, exp["col"])), shape=(n, n))
+    assert (pat != pat.T).nnz == 0
+    assert np.all(pat.diagonal() == 1)
+
+
+def _prob_args(prob):
+    return dict(xyz=prob.xyz.copy(), tets=prob.tets.copy(), tet_label=prob.tet_label.copy(),
+                n_comp=prob.n_comp, D=np.array(prob.D, float), T2=None, u0=None,
+                kappa=prob.kappa, box_lo=prob.box_lo, box_hi=prob.box_hi,
+                periodic_mask=prob.periodic_mask)
+
+
+def _expect(status_name, **over):
+    prob = di.cylinder_box(n=4, half=6.0, r=4.0, kappa=1e-3)
+    args = _prob_args(prob)
+    args.update(over)
+    with Simulator(-1) as s:
+        with pytest.raises(DmriError) as ei:
+            s.dmri_add_problem(**args)
+    assert ei.value.args[0].startswith(status_name)
+
+
+def test_validation_errors():
+    prob = di.cylinder_box(n=4, half=6.0, r=4.0, kappa=1e-3)
+    xyz = prob.xyz.copy()
+    xyz[5, 1] = np.nan
+    _expect("DMRI_E_INVALID", xyz=xyz)
+    _expect("DMRI_E_INVALID", D=np.array([3e-3, 0.0]))
+    _expect("DMRI_E_INVALID", D=np.array([3e-3, -1.0]))
+    _expect("DMRI_E_INVALID", kappa=-1.0)
+    _expect("DMRI_E_INVALID", T2=np.array([1e4, 0.0]))
+    lab = prob.tet_label.copy()
+    lab[3] = 2
+    _expect("DMRI_E_INVALID", tet_label=lab)
+    tets = prob.tets.copy()
+    tets[7, 2] = prob.n_nodes
+    _expect("DMRI_E_INVALID", tets=tets)
+    tets = prob.tets.copy()
+    tets[0, 1] = tets[0, 0]
+    _expect("DMRI_E_INVALID", tets=tets)          # degenerate tetrahedron
+    _expect("DMRI_E_UNSUPPORTED", periodic_mask=3)
+    # A node of the upper x face moved off the face: opposite faces differ.
+    xyz = prob.xyz.copy()
+    on_hi = np.nonzero(np.isclose(xyz[:, 0], 6.0))[0]
+    xyz[on_hi[4], 1] += 0.25
+    _expect("DMRI_E_INVALID", xyz=xyz)
+    _expect("DMRI_E_INVALID", box_lo=np.array([0.0, -6, -6]), box_hi=np.array([0.0, 6, 6]))
+
+
+def test_sequence_and_option_validation():
+    with Simulator(-1) as s:
+        s.dmri_set_sequence_pgse(10600, 13400, 100, 0.5)
+        for bad in [(10600, 13400, 300, 0.5), (10600, 13400, 100, 0.4), (10600, 13400, 0, 0.5),
+                    (13400, 10600, 100, 0.5), (float("nan"), 13400, 100, 0.5)]:
+            with pytest.raises(DmriError):
+                s.dmri_set_sequence_pgse(*bad)
+        s.dmri_set_option("rtol", 1e-8)
+        assert s.dmri_get_option("rtol") == 1e-8
+        for k, v in [("rtol", 0.0), ("precision", 5), ("sys_tile", 12), ("nope", 1),
+                     ("max_iter", 0)]:
+            with pytest.raises(DmriError):
+                s.dmri_set_option(k, v)
+        with pytest.raises(DmriError) as ei:
+            s.dmri_run([0], [1000.0], [[1, 0, 0]])
+        assert "DMRI_E_STATE" in str(ei.value)
