@@ -65,6 +65,8 @@ typedef struct {
     double   t_setup_s;       /* host+device set-up inside the run */
     double   t_solve_s;       /* time loop */
     double   t_signal_s;      /* signal quadrature and copy-out */
+    int64_t  n_kernel_launches; /* launches of the kernel chosen by option "time_kernel" */
+    double   t_kernel_s;      /* their summed durations (HIP events on the run's stream) */
 } dmri_stats;
 
 /* Create a context on HIP device `device_ordinal`. device_ordinal = -1
@@ -161,6 +163,12 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *  "n_steps"    0 = full echo (default); n > 0 stops after n steps and
  *               returns sum_i w_i u_i^n (a sampling aid, not a signal unless
  *               F(t^n) = 0)
+ *  "time_kernel" 0 = off, 1 = SpMV+dot, 2 = CG update, 3 = direction
+ *               update, 4 = step start: bracket every launch of that kernel
+ *               with HIP events and report the summed time in dmri_stats
+ *  "blocks_per_xcd" workgroups per XCD sweeping the rows (default 256)
+ *  "chunk_passes" rows per workgroup chunk, in wavefront passes (default 1)
+ *  "progress"   k > 0 prints one line to stderr every k time steps
  * Unknown keys or out-of-range values: DMRI_E_INVALID. */
 dmri_status dmri_set_option(dmri_handle h, const char* key, double value);
 dmri_status dmri_get_option(dmri_handle h, const char* key, double* value);

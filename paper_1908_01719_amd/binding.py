@@ -51,6 +51,8 @@ class Stats(C.Structure):
         ("t_setup_s", C.c_double),
         ("t_solve_s", C.c_double),
         ("t_signal_s", C.c_double),
+        ("n_kernel_launches", C.c_int64),
+        ("t_kernel_s", C.c_double),
     ]
 
 
@@ -258,5 +260,6 @@ def _stats_dict(st, iters, conv, rres, status):
         "iters_total": iters, "converged": conv, "final_rel_res": rres,
         "total_iterations": st.total_iterations, "spmv_rows": st.spmv_rows,
         "n_steps": st.n_steps, "t_setup_s": st.t_setup_s, "t_solve_s": st.t_solve_s,
-        "t_signal_s": st.t_signal_s,
+        "t_signal_s": st.t_signal_s, "n_kernel_launches": st.n_kernel_launches,
+        "t_kernel_s": st.t_kernel_s,
     }

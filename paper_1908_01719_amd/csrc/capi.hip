@@ -98,7 +98,10 @@ struct Options {
     int graph = 0;
     int autotune = 0;
     int n_steps = 0;
-    int target_blocks = 2048;
+    int blocks_per_xcd = 256;
+    int chunk_passes = 1;
+    int time_kernel = 0;
+    int progress = 0;
 };
 
 // Per-batch device workspace (grow-only, reused across runs).
@@ -108,7 +111,7 @@ struct Workspace {
     DevBuf<double4> gq;
     DevBuf<double2> rho, alpha, beta, sig;
     DevBuf<double> bb, rr, partial, b_in, q_in;
-    DevBuf<int32_t> active, iters, iters_total, flags, n_active, counters, bad;
+    DevBuf<int32_t> active, iters, iters_total, flags, n_active, bad;
     int32_t* h_active[2] = {nullptr, nullptr};  // pinned
     size_t h_active_n = 0;
     ~Workspace() {
@@ -141,6 +144,7 @@ struct dmri_ctx {
     dmri::Options opt;
     dmri::Workspace ws;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> tpool;  // timing events, reused across runs
 };
 
 namespace dmri {
@@ -253,6 +257,45 @@ struct BatchResult {
     int64_t spmv_rows = 0;
     int steps = 0;
     double t_solve = 0, t_signal = 0;
+    int64_t n_timed = 0;
+    double t_timed = 0;
+};
+
+// Brackets launches of one kernel with timing events from the context's pool.
+struct KernelTimer {
+    dmri_ctx* h;
+    hipStream_t st;
+    int which;
+    size_t used = 0;
+    KernelTimer(dmri_ctx* hh, hipStream_t s, int w) : h(hh), st(s), which(w) {}
+    template <typename L>
+    void run(int kind, L&& launch) {
+        if (kind != which) {
+            launch();
+            return;
+        }
+        while (h->tpool.size() < used + 2) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            h->tpool.push_back(e);
+        }
+        HIPCHK(hipEventRecord(h->tpool[used], st));
+        launch();
+        HIPCHK(hipEventRecord(h->tpool[used + 1], st));
+        used += 2;
+    }
+    void collect(BatchResult& res) {
+        HIPCHK(hipStreamSynchronize(st));
+        double tot = 0.0;
+        for (size_t i = 0; i + 1 < used; i += 2) {
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, h->tpool[i], h->tpool[i + 1]));
+            tot += ms;
+        }
+        res.n_timed += static_cast<int64_t>(used / 2);
+        res.t_timed += tot * 1e-3;
+        used = 0;
+    }
 };
 
 // Solve one batch of systems on one problem in precision T (FP64 or FP32
@@ -269,7 +312,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
         throw Error(DMRI_E_INVALID, "CG needs the Hermitian (periodic-box) operator; use COCG");
     const int S = h->opt.sys_tile ? h->opt.sys_tile : auto_tile(n_sys);
     const Geom g = make_geom(static_cast<int32_t>(P.op.n_dof), static_cast<int32_t>(n_sys), S,
-                             h->opt.target_blocks);
+                             h->opt.blocks_per_xcd, h->opt.chunk_passes);
     const size_t nv = static_cast<size_t>(g.n_rows) * g.ld;
     DevBuf<T>* vecs;
     if constexpr (sizeof(T) == 8) vecs = W.vec64; else vecs = W.vec32;
@@ -291,11 +334,9 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     W.iters_total.alloc(ld);
     W.flags.alloc(ld);
     W.n_active.alloc(static_cast<size_t>(g.n_tiles));
-    W.counters.alloc(static_cast<size_t>(g.n_tiles));
-    W.partial.alloc(static_cast<size_t>(g.n_chunks) * ld * 4);
+    W.partial.alloc(static_cast<size_t>(g.n_items) * g.B * S * 4);
     W.bad.alloc(1);
     W.pinned(static_cast<size_t>(g.n_tiles));
-    HIPCHK(hipMemsetAsync(W.counters.p, 0, sizeof(int32_t) * g.n_tiles, st));
     HIPCHK(hipMemsetAsync(W.iters_total.p, 0, sizeof(int32_t) * ld, st));
     HIPCHK(hipMemsetAsync(W.flags.p, 0, sizeof(int32_t) * ld, st));
     HIPCHK(hipMemsetAsync(W.active.p, 0, sizeof(int32_t) * ld, st));
@@ -328,7 +369,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     s.n_sys = static_cast<int32_t>(n_sys);
     s.max_iter = h->opt.max_iter;
     s.rtol2 = h->opt.rtol * h->opt.rtol;
-    Scratch sc{W.partial.p, W.counters.p};
+    Scratch sc{W.partial.p};
     const MatView<T> Av = view<T>(P, A);
 
     launch_set_initial<T>(st, g, P.u0.p, s.n_sys, bufs[0]);
@@ -338,6 +379,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     const double th = h->theta;
     const int N = h->opt.n_steps > 0 ? std::min(h->opt.n_steps, h->n_steps) : h->n_steps;
 
+    KernelTimer timer(h, st, h->opt.time_kernel);
     double t0 = now_s();
     int cur = 0, prev2 = 1, nxt = 2;  // indices into bufs: u_prev, u_prev2, x
     int last_iters = 8;
@@ -351,8 +393,10 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
             rhs = Coef{f[n], 0.0, -(1.0 - th)};
         }
         const int gm = (h->opt.guess == 1 && n >= 2) ? 1 : 0;
-        launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, herm, gm, bufs[cur], bufs[prev2], bufs[nxt], r,
-                       p, s, sc);
+        timer.run(4, [&] {
+            launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, herm, gm, bufs[cur], bufs[prev2],
+                           bufs[nxt], r, p, s, sc);
+        });
         // Pipelined chunks: enqueue chunk k+1 before checking chunk k.
         int done = 0, slot = 0;
         bool pending = false;
@@ -360,9 +404,11 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
         int chunk = first;
         for (;;) {
             for (int i = 0; i < chunk; ++i) {
-                launch_spmv_dot<T>(st, g, Av, W.gq.p, lhs, herm, p, q, s, sc);
-                launch_update<T>(st, g, Av, W.gq.p, lhs, herm, bufs[nxt], r, p, q, s, sc);
-                launch_pupdate<T>(st, g, Av, W.gq.p, lhs, r, p, s);
+                timer.run(1, [&] { launch_spmv_dot<T>(st, g, Av, W.gq.p, lhs, herm, p, q, s, sc); });
+                timer.run(2, [&] {
+                    launch_update<T>(st, g, Av, W.gq.p, lhs, herm, bufs[nxt], r, p, q, s, sc);
+                });
+                timer.run(3, [&] { launch_pupdate<T>(st, g, Av, W.gq.p, lhs, r, p, s); });
             }
             done += chunk;
             HIPCHK(hipMemcpyAsync(W.h_active[slot], W.n_active.p, sizeof(int32_t) * g.n_tiles,
@@ -386,6 +432,11 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
             }
         }
         last_iters = done;
+        if (h->opt.progress > 0 && (n % h->opt.progress == 0 || n == N)) {
+            std::fprintf(stderr, "[dmri] step %d/%d: %d iterations, %.2fs\n", n, N, done,
+                         now_s() - t0);
+            std::fflush(stderr);
+        }
         res.spmv_rows += static_cast<int64_t>(done) * g.n_rows * n_sys;
         const int old_prev2 = prev2;
         prev2 = cur;
@@ -395,8 +446,8 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     HIPCHK(hipStreamSynchronize(st));
     res.t_solve = now_s() - t0;
     res.steps = N;
+    timer.collect(res);
     t0 = now_s();
-    HIPCHK(hipMemsetAsync(W.counters.p, 0, sizeof(int32_t) * g.n_tiles, st));
     launch_signal<T>(st, g, P.w.p, bufs[cur], d_sig, s.n_sys, sc);
     res.iters.resize(n_sys);
     res.flags.resize(n_sys);
@@ -429,6 +480,8 @@ void fill_stats(dmri_stats* stats, const std::vector<int64_t>& owner_idx, const 
     stats->n_steps = R.steps;
     stats->t_solve_s += R.t_solve;
     stats->t_signal_s += R.t_signal;
+    stats->n_kernel_launches += R.n_timed;
+    stats->t_kernel_s += R.t_timed;
 }
 
 void run_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, const double* d_q,
@@ -516,6 +569,7 @@ void dmri_destroy(dmri_handle h) {
         if (!h->host_only) {
             for (auto& e : h->ev)
                 if (e) (void)hipEventDestroy(e);
+            for (auto& e : h->tpool) (void)hipEventDestroy(e);
             (void)hipStreamDestroy(h->stream);
         }
     } catch (...) {
@@ -647,7 +701,10 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         } else if (k == "graph") o.graph = as_int(0, 1);
         else if (k == "autotune") o.autotune = as_int(0, 1);
         else if (k == "n_steps") o.n_steps = as_int(0, 10000000);
-        else if (k == "target_blocks") o.target_blocks = as_int(1, 1 << 20);
+        else if (k == "blocks_per_xcd") o.blocks_per_xcd = as_int(1, 4096);
+        else if (k == "chunk_passes") o.chunk_passes = as_int(1, 64);
+        else if (k == "time_kernel") o.time_kernel = as_int(0, 4);
+        else if (k == "progress") o.progress = as_int(0, 1000000);
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -669,7 +726,10 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "graph") *value = o.graph;
         else if (k == "autotune") *value = o.autotune;
         else if (k == "n_steps") *value = o.n_steps;
-        else if (k == "target_blocks") *value = o.target_blocks;
+        else if (k == "blocks_per_xcd") *value = o.blocks_per_xcd;
+        else if (k == "chunk_passes") *value = o.chunk_passes;
+        else if (k == "time_kernel") *value = o.time_kernel;
+        else if (k == "progress") *value = o.progress;
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -706,6 +766,8 @@ dmri_status dmri_run(dmri_handle h, int64_t n_pairs, const int32_t* problem_id, 
             stats->spmv_rows = 0;
             stats->n_steps = 0;
             stats->t_setup_s = stats->t_solve_s = stats->t_signal_s = 0.0;
+            stats->n_kernel_launches = 0;
+            stats->t_kernel_s = 0.0;
         }
         bool any_nc = false;
         hipStream_t st = h->stream;
@@ -772,6 +834,8 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
             stats->n_steps = 0;
             stats->t_setup_s = now_s() - ts;
             stats->t_solve_s = stats->t_signal_s = 0.0;
+            stats->n_kernel_launches = 0;
+            stats->t_kernel_s = 0.0;
         }
         BatchResult R;
         run_batch(h, P, n_pairs, d_b, d_q, reinterpret_cast<double2*>(d_signal), R);
@@ -798,7 +862,7 @@ dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which
         hipStream_t st = h->stream;
         const int S = h->opt.sys_tile ? h->opt.sys_tile : auto_tile(n_sys);
         const Geom g = make_geom(static_cast<int32_t>(P.op.n_dof), static_cast<int32_t>(n_sys), S,
-                                 h->opt.target_blocks);
+                                 h->opt.blocks_per_xcd, h->opt.chunk_passes);
         const size_t nrow = static_cast<size_t>(g.n_rows), ld = static_cast<size_t>(g.ld);
         std::vector<double> hc(ld, 0.0), hd(3 * ld, 0.0);
         for (int64_t s = 0; s < n_sys; ++s) {

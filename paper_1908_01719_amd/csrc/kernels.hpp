@@ -12,6 +12,16 @@
 // Kr = M/dt - (1-theta) R the constant part of the right operator
 // (Appendix A, eq. linear_billinear). The time-dependent parts are built on
 // the fly per system: c = cm (G F)^2 on M_D and i d . V with d = cd G F q.
+//
+// Work decomposition ("XCD sweep"). A tile is S consecutive systems. Work
+// items are (tile, row part) pairs, numbered so that their count is a
+// multiple of 8; XCD x (blocks with blockIdx % 8 == x, which the hardware
+// places on XCD x) owns items x, x+8, ... Inside an item the B blocks of the
+// XCD sweep the rows in chunks (block j takes chunks j, j+B, ...), so the
+// rows being gathered at any moment form one window of B*chunk rows that
+// stays in that XCD's L2. Every block keeps one FP64 partial per system for
+// each item; small finalize kernels add the partials in a fixed order
+// (deterministic) and update the per-system Krylov scalars.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -58,7 +68,7 @@ struct SolverState {
     int32_t* iters;     // iterations this step
     int32_t* iters_total;
     int32_t* flags;     // bit 0: hit max_iter, bit 1: non-finite residual
-    int32_t* n_active;  // systems still iterating (single counter)
+    int32_t* n_active;  // [n_tiles] systems still iterating per tile
     int32_t n_sys;
     int32_t max_iter;
     double rtol2;
@@ -70,16 +80,19 @@ struct Geom {
     int32_t ld;          // leading dimension (systems, padded)
     int32_t S;           // systems per lane group (tile width)
     int32_t n_tiles;     // ld / S
-    int32_t n_chunks;    // row chunks per tile
-    int32_t chunk_rows;  // rows per chunk (multiple of 4 * 64 / S)
+    int32_t n_parts;     // row parts per tile
+    int32_t n_items;     // n_tiles * n_parts (a multiple of 8)
+    int32_t part_rows;   // rows per part (multiple of chunk_rows)
+    int32_t chunk_rows;  // rows per block chunk (4 wavefronts x 64/S rows x passes)
+    int32_t B;           // blocks per XCD
 };
 
 struct Scratch {
-    double* partial;     // [n_chunks][ld][4]
-    int32_t* counters;   // [n_tiles], zero between launches
+    double* partial;     // [n_items][B][S][4]
 };
 
-Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t target_blocks);
+Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
+               int32_t chunk_passes);
 
 // guess_mode: 0 x0 = u_prev, 1 x0 = 2 u_prev - u_prev2, 2 x0 given in x.
 template <typename T>
@@ -124,5 +137,8 @@ void launch_set_initial(hipStream_t st, const Geom& g, const double* u0, int32_t
 // q normalised; padding systems get G = 0.
 void launch_sys_params(hipStream_t st, int32_t n_sys, int32_t ld, const double* b,
                        const double* q, double int_F2, double4* gq, int32_t* bad);
+
+// Zero n int32 values (a kernel, so it may be captured in a graph).
+void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n);
 
 }  // namespace dmri
