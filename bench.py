@@ -108,7 +108,6 @@ def main():
     ap.add_argument("--time-kernel", default="spmv", choices=sorted(KERNELS))
     ap.add_argument("--sys-tile", type=int, default=0)
     ap.add_argument("--blocks-per-xcd", type=int, default=0)
-    ap.add_argument("--chunk-passes", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--progress", type=int, default=40, help="library progress line every k steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -142,8 +141,6 @@ def main():
         opts["sys_tile"] = args.sys_tile
     if args.blocks_per_xcd:
         opts["blocks_per_xcd"] = args.blocks_per_xcd
-    if args.chunk_passes:
-        opts["chunk_passes"] = args.chunk_passes
     sim.set_options(**opts)
     pids = np.full(len(sysl), pid, np.int32)
 

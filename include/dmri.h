@@ -166,9 +166,20 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *  "time_kernel" 0 = off, 1 = SpMV+dot, 2 = CG update, 3 = direction
  *               update, 4 = step start: bracket every launch of that kernel
  *               with HIP events and report the summed time in dmri_stats
- *  "blocks_per_xcd" workgroups per XCD sweeping the rows (default 256)
- *  "chunk_passes" rows per workgroup chunk, in wavefront passes (default 1)
+ *  "blocks_per_xcd" workgroups per XCD sweeping the rows (default 512)
+ *  "max_outer"  FP64 refinement passes per step in mixed precision (8)
+ *  "queue"      1 = gather kernels take rows from a per-XCD queue,
+ *               0 = static chunks (default)
+ *  "grab"       rows per queue grab, in units of 2 wavefront passes (4)
+ *  "nt"         1 = SpMV results stored non-temporally (default)
+ *  "lds"        1 = SpMV stages matrix chunks in LDS for tiles of 32/64
+ *               systems (default 0)
  *  "progress"   k > 0 prints one line to stderr every k time steps
+ *  "ordering"   DOF order of problems added afterwards: 0 = Morton curve,
+ *               1 = pencils (default): columns of "pencil" x "pencil" cells
+ *               swept z-, y-, x-major, bounding the index distance between
+ *               mesh neighbours
+ *  "pencil"     pencil width in cells (default 16)
  * Unknown keys or out-of-range values: DMRI_E_INVALID. */
 dmri_status dmri_set_option(dmri_handle h, const char* key, double value);
 dmri_status dmri_get_option(dmri_handle h, const char* key, double* value);

@@ -160,15 +160,48 @@ HostOperator assemble(const MeshInput& in) {
     const int64_t nTor = static_cast<int64_t>(rep.size());
     op.n_torus_nodes = nTor;
 
-    // Spatial (Morton) order of torus nodes: consecutive DOFs are neighbours.
+    // Spatial order of torus nodes: consecutive DOFs are mesh neighbours.
     std::vector<int64_t> rank(nTor);
     {
         std::vector<std::pair<uint64_t, int64_t>> code(nTor);
-        for (int64_t t = 0; t < nTor; ++t) {
-            uint64_t c = spread3(static_cast<uint64_t>(tkey[t][0]) >> 11) |
-                         spread3(static_cast<uint64_t>(tkey[t][1]) >> 11) << 1 |
-                         spread3(static_cast<uint64_t>(tkey[t][2]) >> 11) << 2;
-            code[t] = {c, t};
+        if (in.ordering == 0) {
+            for (int64_t t = 0; t < nTor; ++t) {
+                uint64_t c = spread3(static_cast<uint64_t>(tkey[t][0]) >> 11) |
+                             spread3(static_cast<uint64_t>(tkey[t][1]) >> 11) << 1 |
+                             spread3(static_cast<uint64_t>(tkey[t][2]) >> 11) << 2;
+                code[t] = {c, t};
+            }
+        } else {
+            // Cell size estimate: mean edge length of (up to) 4096 tetrahedra.
+            double hsum = 0.0;
+            int64_t hn = 0;
+            const int64_t stride = std::max<int64_t>(1, nT / 4096);
+            for (int64_t e = 0; e < nT; e += stride) {
+                const int32_t* tv = in.tets + 4 * e;
+                for (int a = 0; a < 4; ++a)
+                    for (int b = a + 1; b < 4; ++b) {
+                        hsum += norm(sub(in.xyz + 3 * tv[a], in.xyz + 3 * tv[b]));
+                        ++hn;
+                    }
+            }
+            // A Kuhn cube of edge h splits into tetrahedra whose six edges are
+            // h, h, h, sqrt2 h, sqrt2 h, sqrt3 h (mean 1.26 h); for other meshes
+            // any estimate of the right order serves the ordering.
+            const double h = std::max(1e-300, hsum / std::max<int64_t>(1, hn) / 1.26008);
+            const int64_t w = std::max<int32_t>(1, in.pencil);
+            for (int64_t t = 0; t < nTor; ++t) {
+                uint64_t gxyz[3];
+                for (int a = 0; a < 3; ++a) {
+                    double gv = (tkey[t][a] / kQuant) * L[a] / h;
+                    int64_t gi = std::llround(gv);
+                    gi = std::min<int64_t>(std::max<int64_t>(gi, 0), (1 << 12) - 1);
+                    gxyz[a] = static_cast<uint64_t>(gi);
+                }
+                const uint64_t bx = gxyz[0] / w, by = gxyz[1] / w;
+                const uint64_t c = (by << 44) | (bx << 36) | (gxyz[2] << 24) | (gxyz[1] << 12) |
+                                   gxyz[0];
+                code[t] = {c, t};
+            }
         }
         std::sort(code.begin(), code.end());
         for (int64_t r = 0; r < nTor; ++r) rank[code[r].second] = r;

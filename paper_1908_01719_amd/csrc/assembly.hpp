@@ -45,6 +45,12 @@ struct MeshInput {
     double lo[3] = {0, 0, 0};
     double hi[3] = {0, 0, 0};
     uint32_t periodic_mask = 0;
+    // DOF ordering: 0 = Morton (Z-order) of node positions; 1 = pencils:
+    // columns of pencil x pencil cells in (x, y), each swept z-, y-, x-major,
+    // which bounds the index distance between mesh neighbours by about
+    // pencil^2 rows.
+    int32_t ordering = 1;
+    int32_t pencil = 16;
 };
 
 // Assembled operators in the library's DOF order (spatially sorted).

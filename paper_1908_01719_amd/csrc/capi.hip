@@ -85,7 +85,33 @@ struct ProblemRec {
     DevMatrix<float> A32;
     double dt_up = -1, theta_up = -1;  // sequence the K0/Kr on device were built for
     bool pattern_up = false;
+    // Device pattern: CSR rows padded to a multiple of kRowPad; pad_src maps
+    // a padded entry to its stored entry (-1 for padding).
+    std::vector<int32_t> pad_row_ptr, pad_col;
+    std::vector<int64_t> pad_src;
 };
+
+void build_padded(ProblemRec& P) {
+    const HostOperator& op = P.op;
+    const int64_t n = op.n_dof;
+    P.pad_row_ptr.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t len = op.row_ptr[i + 1] - op.row_ptr[i];
+        const int64_t padded = (len + kRowPad - 1) / kRowPad * kRowPad;
+        P.pad_row_ptr[i + 1] = static_cast<int32_t>(P.pad_row_ptr[i] + padded);
+    }
+    const int64_t total = P.pad_row_ptr[n];
+    P.pad_col.assign(total, 0);
+    P.pad_src.assign(total, -1);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t d = P.pad_row_ptr[i];
+        for (int64_t k = op.row_ptr[i]; k < op.row_ptr[i + 1]; ++k, ++d) {
+            P.pad_col[d] = op.col[k];
+            P.pad_src[d] = k;
+        }
+        for (; d < P.pad_row_ptr[i + 1]; ++d) P.pad_col[d] = static_cast<int32_t>(i);
+    }
+}
 
 struct Options {
     int precision = 0;
@@ -98,10 +124,63 @@ struct Options {
     int graph = 0;
     int autotune = 0;
     int n_steps = 0;
-    int blocks_per_xcd = 256;
-    int chunk_passes = 1;
+    int blocks_per_xcd = 512;
+    int max_outer = 8;
+    int queue = 0;
+    int grab = 4;
+    int nt = 1;
+    int lds = 0;
     int time_kernel = 0;
     int progress = 0;
+    int ordering = 1;
+    int pencil = 16;
+};
+
+// Per-system Krylov state arrays of one solver level.
+struct StateBufs {
+    DevBuf<double2> rho, alpha, beta;
+    DevBuf<double> bb, rr;
+    DevBuf<int32_t> active, iters, iters_total, flags, n_active;
+    void alloc(size_t ld, size_t n_tiles) {
+        rho.alloc(ld);
+        alpha.alloc(ld);
+        beta.alloc(ld);
+        bb.alloc(ld);
+        rr.alloc(ld);
+        active.alloc(ld);
+        iters.alloc(ld);
+        iters_total.alloc(ld);
+        flags.alloc(ld);
+        n_active.alloc(n_tiles);
+    }
+    void reset(size_t ld, hipStream_t st) {
+        HIPCHK(hipMemsetAsync(rho.p, 0, sizeof(double2) * ld, st));
+        HIPCHK(hipMemsetAsync(alpha.p, 0, sizeof(double2) * ld, st));
+        HIPCHK(hipMemsetAsync(beta.p, 0, sizeof(double2) * ld, st));
+        HIPCHK(hipMemsetAsync(bb.p, 0, sizeof(double) * ld, st));
+        HIPCHK(hipMemsetAsync(rr.p, 0, sizeof(double) * ld, st));
+        HIPCHK(hipMemsetAsync(active.p, 0, sizeof(int32_t) * ld, st));
+        HIPCHK(hipMemsetAsync(iters.p, 0, sizeof(int32_t) * ld, st));
+        HIPCHK(hipMemsetAsync(iters_total.p, 0, sizeof(int32_t) * ld, st));
+        HIPCHK(hipMemsetAsync(flags.p, 0, sizeof(int32_t) * ld, st));
+    }
+    SolverState view(int32_t n_sys, int32_t max_iter, double rtol2) {
+        SolverState s{};
+        s.rho = rho.p;
+        s.alpha = alpha.p;
+        s.beta = beta.p;
+        s.bb = bb.p;
+        s.rr = rr.p;
+        s.active = active.p;
+        s.iters = iters.p;
+        s.iters_total = iters_total.p;
+        s.flags = flags.p;
+        s.n_active = n_active.p;
+        s.n_sys = n_sys;
+        s.max_iter = max_iter;
+        s.rtol2 = rtol2;
+        return s;
+    }
 };
 
 // Per-batch device workspace (grow-only, reused across runs).
@@ -109,9 +188,10 @@ struct Workspace {
     DevBuf<double> vec64[6];
     DevBuf<float> vec32[6];
     DevBuf<double4> gq;
-    DevBuf<double2> rho, alpha, beta, sig;
-    DevBuf<double> bb, rr, partial, b_in, q_in;
-    DevBuf<int32_t> active, iters, iters_total, flags, n_active, bad;
+    DevBuf<double2> sig;
+    DevBuf<double> partial, b_in, q_in;
+    DevBuf<int32_t> ctr, bad;
+    StateBufs outer, inner;
     int32_t* h_active[2] = {nullptr, nullptr};  // pinned
     size_t h_active_n = 0;
     ~Workspace() {
@@ -158,28 +238,38 @@ void need_device(dmri_ctx* h) {
 // Build K0 = M/dt + theta R, Kr = M/dt - (1-theta) R, aux = {M_D, V} and the
 // diagonal, in precision T, and upload them.
 template <typename T>
-void upload_matrix(const HostOperator& op, double dt, double th, DevMatrix<T>& A,
-                   hipStream_t st) {
+void upload_matrix(const ProblemRec& P, double dt, double th, DevMatrix<T>& A, hipStream_t st) {
     using T4 = typename Vec4Of<T>::type;
-    const size_t nnz = static_cast<size_t>(op.nnz), n = static_cast<size_t>(op.n_dof);
-    std::vector<T> K0(nnz), Kr(nnz), dK0(n);
-    std::vector<T4> aux(nnz), daux(n);
-    for (size_t k = 0; k < nnz; ++k) {
-        K0[k] = static_cast<T>(op.M[k] / dt + th * op.R[k]);
-        Kr[k] = static_cast<T>(op.M[k] / dt - (1.0 - th) * op.R[k]);
-        aux[k].x = static_cast<T>(op.MD[k]);
-        aux[k].y = static_cast<T>(op.V[0][k]);
-        aux[k].z = static_cast<T>(op.V[1][k]);
-        aux[k].w = static_cast<T>(op.V[2][k]);
+    const HostOperator& op = P.op;
+    const size_t total = P.pad_col.size(), n = static_cast<size_t>(op.n_dof);
+    std::vector<T> K0(total, T(0)), Kr(total, T(0)), dK0(n);
+    std::vector<T4> aux(total), daux(n);
+    for (size_t d = 0; d < total; ++d) {
+        const int64_t k = P.pad_src[d];
+        T4 a;
+        a.x = a.y = a.z = a.w = T(0);
+        if (k >= 0) {
+            K0[d] = static_cast<T>(op.M[k] / dt + th * op.R[k]);
+            Kr[d] = static_cast<T>(op.M[k] / dt - (1.0 - th) * op.R[k]);
+            a.x = static_cast<T>(op.MD[k]);
+            a.y = static_cast<T>(op.V[0][k]);
+            a.z = static_cast<T>(op.V[1][k]);
+            a.w = static_cast<T>(op.V[2][k]);
+        }
+        aux[d] = a;
     }
     for (size_t i = 0; i < n; ++i) {
-        dK0[i] = K0[op.diag_pos[i]];
-        daux[i] = aux[op.diag_pos[i]];
+        const int64_t k = op.diag_pos[i];
+        dK0[i] = static_cast<T>(op.M[k] / dt + th * op.R[k]);
+        daux[i].x = static_cast<T>(op.MD[k]);
+        daux[i].y = static_cast<T>(op.V[0][k]);
+        daux[i].z = static_cast<T>(op.V[1][k]);
+        daux[i].w = static_cast<T>(op.V[2][k]);
     }
-    A.K0.upload(K0.data(), nnz, st);
-    A.Kr.upload(Kr.data(), nnz, st);
+    A.K0.upload(K0.data(), total, st);
+    A.Kr.upload(Kr.data(), total, st);
     A.dK0.upload(dK0.data(), n, st);
-    A.aux.upload(aux.data(), nnz, st);
+    A.aux.upload(aux.data(), total, st);
     A.daux.upload(daux.data(), n, st);
     HIPCHK(hipStreamSynchronize(st));  // host staging vectors go out of scope
     A.ready = true;
@@ -188,8 +278,9 @@ void upload_matrix(const HostOperator& op, double dt, double th, DevMatrix<T>& A
 void ensure_uploaded(dmri_ctx* h, ProblemRec& P, bool need32) {
     hipStream_t st = h->stream;
     if (!P.pattern_up) {
-        P.row_ptr.upload(P.op.row_ptr.data(), P.op.row_ptr.size(), st);
-        P.col.upload(P.op.col.data(), P.op.col.size(), st);
+        build_padded(P);
+        P.row_ptr.upload(P.pad_row_ptr.data(), P.pad_row_ptr.size(), st);
+        P.col.upload(P.pad_col.data(), P.pad_col.size(), st);
         P.w.upload(P.op.w.data(), P.op.w.size(), st);
         P.u0.upload(P.op.u0.data(), P.op.u0.size(), st);
         HIPCHK(hipStreamSynchronize(st));
@@ -201,8 +292,8 @@ void ensure_uploaded(dmri_ctx* h, ProblemRec& P, bool need32) {
         P.dt_up = h->dt;
         P.theta_up = h->theta;
     }
-    if (!P.A64.ready) upload_matrix<double>(P.op, h->dt, h->theta, P.A64, st);
-    if (need32 && !P.A32.ready) upload_matrix<float>(P.op, h->dt, h->theta, P.A32, st);
+    if (!P.A64.ready) upload_matrix<double>(P, h->dt, h->theta, P.A64, st);
+    if (need32 && !P.A32.ready) upload_matrix<float>(P, h->dt, h->theta, P.A32, st);
 }
 
 template <typename T>
@@ -298,22 +389,153 @@ struct KernelTimer {
     }
 };
 
-// Solve one batch of systems on one problem in precision T (FP64 or FP32
-// throughout). b/q are device pointers ([n_sys], [n_sys][3]); the signals
-// are written to d_sig ([n_sys] double2, device).
+// Common set-up of a batch: geometry, per-system parameters, scratch.
+struct BatchSetup {
+    Geom g;
+    bool herm;
+    Scratch sc;
+};
+
+BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
+                       const double* d_q) {
+    hipStream_t st = h->stream;
+    Workspace& W = h->ws;
+    BatchSetup bs{};
+    bs.herm = (P.op.form == FORM_TRANSFORMED) ? (h->opt.krylov != 2) : false;
+    if (P.op.form == FORM_UFORM && h->opt.krylov == 1)
+        throw Error(DMRI_E_INVALID, "CG needs the Hermitian (periodic-box) operator; use COCG");
+    const int S = h->opt.sys_tile ? h->opt.sys_tile : auto_tile(n_sys);
+    bs.g = make_geom(static_cast<int32_t>(P.op.n_dof), static_cast<int32_t>(n_sys), S,
+                     h->opt.blocks_per_xcd, h->opt.queue, h->opt.grab);
+    bs.g.nt = h->opt.nt;
+    bs.g.lds = h->opt.lds;
+    const Geom& g = bs.g;
+    const size_t ld = static_cast<size_t>(g.ld);
+    W.gq.alloc(ld);
+    W.partial.alloc(static_cast<size_t>(g.n_items) * g.B * S * 4);
+    W.ctr.alloc(2 * static_cast<size_t>(g.n_items));
+    W.bad.alloc(1);
+    W.pinned(static_cast<size_t>(g.n_tiles));
+    HIPCHK(hipMemsetAsync(W.ctr.p, 0, sizeof(int32_t) * 2 * g.n_items, st));
+    HIPCHK(hipMemsetAsync(W.bad.p, 0, sizeof(int32_t), st));
+    const double intF2 = h->delta * h->delta * (h->Delta - h->delta / 3.0);
+    launch_sys_params(st, static_cast<int32_t>(n_sys), g.ld, d_b, d_q, intF2, W.gq.p, W.bad.p);
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, W.bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad) throw Error(DMRI_E_INVALID, "b must be finite and >= 0, q finite and nonzero when b > 0");
+    bs.sc.partial = W.partial.p;
+    bs.sc.ctr_spmv = W.ctr.p;
+    bs.sc.ctr_init = W.ctr.p + g.n_items;
+    return bs;
+}
+
+// Sum of the per-tile active counts after the work enqueued so far.
+int poll_active(dmri_ctx* h, const Geom& g, const SolverState& s) {
+    HIPCHK(hipMemcpyAsync(h->ws.h_active[0], s.n_active, sizeof(int32_t) * g.n_tiles,
+                          hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    int tot = 0;
+    for (int t = 0; t < g.n_tiles; ++t) tot += h->ws.h_active[0][t];
+    return tot;
+}
+
+// Krylov iterations on the systems active in s until none is left.
+// Chunks of iterations are enqueued back to back; behind each chunk the
+// per-tile active counts are copied to pinned memory, and the host checks
+// chunk k's counts while chunk k+1 runs. Returns the iterations enqueued.
+template <typename T>
+int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const double4* gq,
+                Coef lhs, typename Vec2Of<T>::type* x, typename Vec2Of<T>::type* r,
+                typename Vec2Of<T>::type* p, typename Vec2Of<T>::type* q, SolverState s,
+                KernelTimer& timer, int first_chunk, int max_iter) {
+    hipStream_t st = h->stream;
+    const Geom& g = bs.g;
+    int done = 0, slot = 0;
+    bool pending = false;
+    int chunk = std::max(1, first_chunk);
+    for (;;) {
+        for (int i = 0; i < chunk; ++i) {
+            timer.run(1, [&] { launch_spmv_dot<T>(st, g, Av, gq, lhs, bs.herm, p, q, s, bs.sc); });
+            timer.run(2, [&] {
+                launch_update<T>(st, g, Av, gq, lhs, bs.herm, x, r, p, q, s, bs.sc);
+            });
+            timer.run(3, [&] { launch_pupdate<T>(st, g, Av, gq, lhs, r, p, s); });
+        }
+        done += chunk;
+        HIPCHK(hipMemcpyAsync(h->ws.h_active[slot], s.n_active, sizeof(int32_t) * g.n_tiles,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(h->ev[slot], st));
+        if (pending) {
+            HIPCHK(hipEventSynchronize(h->ev[slot ^ 1]));
+            int tot = 0;
+            for (int t = 0; t < g.n_tiles; ++t) tot += h->ws.h_active[slot ^ 1][t];
+            if (tot == 0) {
+                done -= chunk;  // the chunk just enqueued only early-exits
+                break;
+            }
+        }
+        pending = true;
+        slot ^= 1;
+        chunk = 2;
+        if (done > max_iter + 4) {
+            HIPCHK(hipStreamSynchronize(st));
+            break;
+        }
+    }
+    return done;
+}
+
+Coef lhs_coef(const dmri_ctx* h, bool tr, const std::vector<double>& F,
+              const std::vector<double>& f, int n) {
+    const double th = h->theta;
+    return tr ? Coef{F[n], th, th} : Coef{f[n], 0.0, th};
+}
+Coef rhs_coef(const dmri_ctx* h, bool tr, const std::vector<double>& F,
+              const std::vector<double>& f, int n) {
+    const double th = h->theta;
+    return tr ? Coef{F[n - 1], -(1.0 - th), -(1.0 - th)} : Coef{f[n], 0.0, -(1.0 - th)};
+}
+
+void progress_line(dmri_ctx* h, int n, int N, int iters, double t0) {
+    if (h->opt.progress > 0 && (n % h->opt.progress == 0 || n == N)) {
+        std::fprintf(stderr, "[dmri] step %d/%d: %d iterations, %.2fs\n", n, N, iters,
+                     now_s() - t0);
+        std::fflush(stderr);
+    }
+}
+
+template <typename T>
+void collect_result(dmri_ctx* h, const BatchSetup& bs, ProblemRec& P, StateBufs& sb,
+                    const typename Vec2Of<T>::type* u, double2* d_sig, int64_t n_sys,
+                    BatchResult& res) {
+    hipStream_t st = h->stream;
+    const double t0 = now_s();
+    launch_signal<T>(st, bs.g, P.w.p, u, d_sig, static_cast<int32_t>(n_sys), bs.sc);
+    res.iters.resize(n_sys);
+    res.flags.resize(n_sys);
+    res.rr.resize(n_sys);
+    res.bb.resize(n_sys);
+    HIPCHK(hipMemcpyAsync(res.flags.data(), sb.flags.p, sizeof(int32_t) * n_sys,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(res.rr.data(), sb.rr.p, sizeof(double) * n_sys, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(res.bb.data(), sb.bb.p, sizeof(double) * n_sys, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    res.t_signal = now_s() - t0;
+}
+
+// Solve one batch of systems on one problem in precision T throughout
+// (all-FP64, or all-FP32 for testing). b/q are device pointers ([n_sys],
+// [n_sys][3]); the signals go to d_sig ([n_sys] double2, device).
 template <typename T>
 void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, const double* d_b,
                  const double* d_q, double2* d_sig, BatchResult& res) {
     using V2 = typename Vec2Of<T>::type;
     hipStream_t st = h->stream;
     Workspace& W = h->ws;
-    const bool herm = (P.op.form == FORM_TRANSFORMED) ? (h->opt.krylov != 2) : false;
-    if (P.op.form == FORM_UFORM && h->opt.krylov == 1)
-        throw Error(DMRI_E_INVALID, "CG needs the Hermitian (periodic-box) operator; use COCG");
-    const int S = h->opt.sys_tile ? h->opt.sys_tile : auto_tile(n_sys);
-    const Geom g = make_geom(static_cast<int32_t>(P.op.n_dof), static_cast<int32_t>(n_sys), S,
-                             h->opt.blocks_per_xcd, h->opt.chunk_passes);
-    const size_t nv = static_cast<size_t>(g.n_rows) * g.ld;
+    const BatchSetup bs = setup_batch(h, P, n_sys, d_b, d_q);
+    const Geom& g = bs.g;
+    const size_t nv = static_cast<size_t>(g.n_rows) * g.ld, ld = static_cast<size_t>(g.ld);
     DevBuf<T>* vecs;
     if constexpr (sizeof(T) == 8) vecs = W.vec64; else vecs = W.vec32;
     for (int i = 0; i < 6; ++i) vecs[i].alloc(2 * nv);
@@ -322,121 +544,32 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     V2* r = reinterpret_cast<V2*>(vecs[3].p);
     V2* p = reinterpret_cast<V2*>(vecs[4].p);
     V2* q = reinterpret_cast<V2*>(vecs[5].p);
-    const size_t ld = static_cast<size_t>(g.ld);
-    W.gq.alloc(ld);
-    W.rho.alloc(ld);
-    W.alpha.alloc(ld);
-    W.beta.alloc(ld);
-    W.bb.alloc(ld);
-    W.rr.alloc(ld);
-    W.active.alloc(ld);
-    W.iters.alloc(ld);
-    W.iters_total.alloc(ld);
-    W.flags.alloc(ld);
-    W.n_active.alloc(static_cast<size_t>(g.n_tiles));
-    W.partial.alloc(static_cast<size_t>(g.n_items) * g.B * S * 4);
-    W.bad.alloc(1);
-    W.pinned(static_cast<size_t>(g.n_tiles));
-    HIPCHK(hipMemsetAsync(W.iters_total.p, 0, sizeof(int32_t) * ld, st));
-    HIPCHK(hipMemsetAsync(W.flags.p, 0, sizeof(int32_t) * ld, st));
-    HIPCHK(hipMemsetAsync(W.active.p, 0, sizeof(int32_t) * ld, st));
-    HIPCHK(hipMemsetAsync(W.iters.p, 0, sizeof(int32_t) * ld, st));
-    HIPCHK(hipMemsetAsync(W.bad.p, 0, sizeof(int32_t), st));
-    HIPCHK(hipMemsetAsync(W.rho.p, 0, sizeof(double2) * ld, st));
-    HIPCHK(hipMemsetAsync(W.alpha.p, 0, sizeof(double2) * ld, st));
-    HIPCHK(hipMemsetAsync(W.beta.p, 0, sizeof(double2) * ld, st));
-    HIPCHK(hipMemsetAsync(W.bb.p, 0, sizeof(double) * ld, st));
-    HIPCHK(hipMemsetAsync(W.rr.p, 0, sizeof(double) * ld, st));
-
-    const double intF2 = h->delta * h->delta * (h->Delta - h->delta / 3.0);
-    launch_sys_params(st, static_cast<int32_t>(n_sys), g.ld, d_b, d_q, intF2, W.gq.p, W.bad.p);
-    int32_t bad = 0;
-    HIPCHK(hipMemcpyAsync(&bad, W.bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (bad) throw Error(DMRI_E_INVALID, "b must be finite and >= 0, q finite and nonzero when b > 0");
-
-    SolverState s{};
-    s.rho = W.rho.p;
-    s.alpha = W.alpha.p;
-    s.beta = W.beta.p;
-    s.bb = W.bb.p;
-    s.rr = W.rr.p;
-    s.active = W.active.p;
-    s.iters = W.iters.p;
-    s.iters_total = W.iters_total.p;
-    s.flags = W.flags.p;
-    s.n_active = W.n_active.p;
-    s.n_sys = static_cast<int32_t>(n_sys);
-    s.max_iter = h->opt.max_iter;
-    s.rtol2 = h->opt.rtol * h->opt.rtol;
-    Scratch sc{W.partial.p};
+    W.outer.alloc(ld, g.n_tiles);
+    W.outer.reset(ld, st);
+    SolverState s = W.outer.view(static_cast<int32_t>(n_sys), h->opt.max_iter,
+                                 h->opt.rtol * h->opt.rtol);
     const MatView<T> Av = view<T>(P, A);
-
     launch_set_initial<T>(st, g, P.u0.p, s.n_sys, bufs[0]);
     std::vector<double> F, f;
     step_tables(h, F, f);
     const bool tr = P.op.form == FORM_TRANSFORMED;
-    const double th = h->theta;
     const int N = h->opt.n_steps > 0 ? std::min(h->opt.n_steps, h->n_steps) : h->n_steps;
 
     KernelTimer timer(h, st, h->opt.time_kernel);
-    double t0 = now_s();
+    const double t0 = now_s();
     int cur = 0, prev2 = 1, nxt = 2;  // indices into bufs: u_prev, u_prev2, x
     int last_iters = 8;
     for (int n = 1; n <= N; ++n) {
-        Coef lhs, rhs;
-        if (tr) {
-            lhs = Coef{F[n], th, th};
-            rhs = Coef{F[n - 1], -(1.0 - th), -(1.0 - th)};
-        } else {
-            lhs = Coef{f[n], 0.0, th};
-            rhs = Coef{f[n], 0.0, -(1.0 - th)};
-        }
+        const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
         const int gm = (h->opt.guess == 1 && n >= 2) ? 1 : 0;
         timer.run(4, [&] {
-            launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, herm, gm, bufs[cur], bufs[prev2],
-                           bufs[nxt], r, p, s, sc);
+            launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, bs.herm, gm, bufs[cur], bufs[prev2],
+                           bufs[nxt], r, p, nullptr, nullptr, s, bs.sc);
         });
-        // Pipelined chunks: enqueue chunk k+1 before checking chunk k.
-        int done = 0, slot = 0;
-        bool pending = false;
-        int first = std::max(1, last_iters - 2);
-        int chunk = first;
-        for (;;) {
-            for (int i = 0; i < chunk; ++i) {
-                timer.run(1, [&] { launch_spmv_dot<T>(st, g, Av, W.gq.p, lhs, herm, p, q, s, sc); });
-                timer.run(2, [&] {
-                    launch_update<T>(st, g, Av, W.gq.p, lhs, herm, bufs[nxt], r, p, q, s, sc);
-                });
-                timer.run(3, [&] { launch_pupdate<T>(st, g, Av, W.gq.p, lhs, r, p, s); });
-            }
-            done += chunk;
-            HIPCHK(hipMemcpyAsync(W.h_active[slot], W.n_active.p, sizeof(int32_t) * g.n_tiles,
-                                  hipMemcpyDeviceToHost, st));
-            HIPCHK(hipEventRecord(h->ev[slot], st));
-            if (pending) {
-                HIPCHK(hipEventSynchronize(h->ev[slot ^ 1]));
-                int tot = 0;
-                for (int t = 0; t < g.n_tiles; ++t) tot += W.h_active[slot ^ 1][t];
-                if (tot == 0) {
-                    done -= chunk;  // the chunk just enqueued only early-exits
-                    break;
-                }
-            }
-            pending = true;
-            slot ^= 1;
-            chunk = 2;
-            if (done > h->opt.max_iter + 4) {
-                HIPCHK(hipStreamSynchronize(st));
-                break;
-            }
-        }
+        const int done = krylov_loop<T>(h, bs, Av, W.gq.p, lhs, bufs[nxt], r, p, q, s, timer,
+                                        last_iters - 2, h->opt.max_iter);
         last_iters = done;
-        if (h->opt.progress > 0 && (n % h->opt.progress == 0 || n == N)) {
-            std::fprintf(stderr, "[dmri] step %d/%d: %d iterations, %.2fs\n", n, N, done,
-                         now_s() - t0);
-            std::fflush(stderr);
-        }
+        progress_line(h, n, N, done, t0);
         res.spmv_rows += static_cast<int64_t>(done) * g.n_rows * n_sys;
         const int old_prev2 = prev2;
         prev2 = cur;
@@ -447,21 +580,112 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     res.t_solve = now_s() - t0;
     res.steps = N;
     timer.collect(res);
-    t0 = now_s();
-    launch_signal<T>(st, g, P.w.p, bufs[cur], d_sig, s.n_sys, sc);
-    res.iters.resize(n_sys);
-    res.flags.resize(n_sys);
-    res.rr.resize(n_sys);
-    res.bb.resize(n_sys);
-    HIPCHK(hipMemcpyAsync(res.iters.data(), W.iters_total.p, sizeof(int32_t) * n_sys,
+    collect_result<T>(h, bs, P, W.outer, bufs[cur], d_sig, n_sys, res);
+    HIPCHK(hipMemcpyAsync(res.iters.data(), W.outer.iters_total.p, sizeof(int32_t) * n_sys,
                           hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(res.flags.data(), W.flags.p, sizeof(int32_t) * n_sys,
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(res.rr.data(), W.rr.p, sizeof(double) * n_sys, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(res.bb.data(), W.bb.p, sizeof(double) * n_sys, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    res.t_signal = now_s() - t0;
     for (int64_t i = 0; i < n_sys; ++i) res.total_iters += res.iters[i];
+}
+
+// Mixed precision: FP64 time stepping (right-hand side, residual, solution,
+// signal) around FP32 Krylov solves of the correction equation
+//   A dx = r64,  x64 += dx,  r64 = b - A x64  (FP64 operator)
+// repeated until ||r64|| <= rtol ||b|| (iterative refinement). The inner
+// solves reduce the residual by inner_rtol and use FP32 matrices and vectors
+// with FP64 dot products.
+void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
+                       const double* d_q, double2* d_sig, BatchResult& res) {
+    hipStream_t st = h->stream;
+    Workspace& W = h->ws;
+    const BatchSetup bs = setup_batch(h, P, n_sys, d_b, d_q);
+    const Geom& g = bs.g;
+    const size_t nv = static_cast<size_t>(g.n_rows) * g.ld, ld = static_cast<size_t>(g.ld);
+    for (int i = 0; i < 6; ++i) W.vec64[i].alloc(2 * nv);
+    for (int i = 0; i < 4; ++i) W.vec32[i].alloc(2 * nv);
+    double2* U[4];  // u_prev, u_prev2, x, x_alt
+    for (int i = 0; i < 4; ++i) U[i] = reinterpret_cast<double2*>(W.vec64[i].p);
+    double2* r64 = reinterpret_cast<double2*>(W.vec64[4].p);
+    double2* p64 = reinterpret_cast<double2*>(W.vec64[5].p);
+    float2* r32 = reinterpret_cast<float2*>(W.vec32[0].p);
+    float2* dx = reinterpret_cast<float2*>(W.vec32[1].p);
+    float2* p32 = reinterpret_cast<float2*>(W.vec32[2].p);
+    float2* q32 = reinterpret_cast<float2*>(W.vec32[3].p);
+    W.outer.alloc(ld, g.n_tiles);
+    W.inner.alloc(ld, g.n_tiles);
+    W.outer.reset(ld, st);
+    W.inner.reset(ld, st);
+    SolverState so = W.outer.view(static_cast<int32_t>(n_sys), h->opt.max_outer,
+                                  h->opt.rtol * h->opt.rtol);
+    SolverState si = W.inner.view(static_cast<int32_t>(n_sys), h->opt.max_iter,
+                                  h->opt.inner_rtol * h->opt.inner_rtol);
+    const MatView<double> A64 = view<double>(P, P.A64);
+    const MatView<float> A32 = view<float>(P, P.A32);
+    launch_set_initial<double>(st, g, P.u0.p, so.n_sys, U[0]);
+    std::vector<double> F, f;
+    step_tables(h, F, f);
+    const bool tr = P.op.form == FORM_TRANSFORMED;
+    const int N = h->opt.n_steps > 0 ? std::min(h->opt.n_steps, h->n_steps) : h->n_steps;
+    std::vector<int32_t> flag_or(n_sys, 0);
+
+    KernelTimer timer(h, st, h->opt.time_kernel);
+    const double t0 = now_s();
+    int cur = 0, prev2 = 1, xi = 2, yi = 3;
+    int last_first_pass = 8;
+    for (int n = 1; n <= N; ++n) {
+        const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
+        const int gm = (h->opt.guess == 1 && n >= 2) ? 1 : 0;
+        timer.run(4, [&] {
+            launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, gm, U[cur], U[prev2], U[xi],
+                                r64, p64, nullptr, nullptr, so, bs.sc);
+        });
+        int step_iters = 0;
+        for (int pass = 0; pass < h->opt.max_outer; ++pass) {
+            if (poll_active(h, g, so) == 0) break;
+            launch_inner_start(st, g, A32, W.gq.p, lhs, bs.herm, r64, W.outer.active.p, r32, dx,
+                               p32, si, bs.sc);
+            const int it = krylov_loop<float>(h, bs, A32, W.gq.p, lhs, dx, r32, p32, q32, si,
+                                              timer, pass == 0 ? last_first_pass - 2 : 2,
+                                              h->opt.max_iter);
+            if (pass == 0) last_first_pass = it;
+            step_iters += it;
+            res.spmv_rows += static_cast<int64_t>(it) * g.n_rows * n_sys;
+            timer.run(4, [&] {
+                launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, 3, U[cur], U[prev2],
+                                    U[xi], r64, p64, dx, U[yi], so, bs.sc);
+            });
+            std::swap(xi, yi);
+        }
+        if (poll_active(h, g, so) != 0) {
+            // Outer refinement did not reach rtol within max_outer passes.
+            std::vector<int32_t> act(n_sys);
+            HIPCHK(hipMemcpy(act.data(), W.outer.active.p, sizeof(int32_t) * n_sys,
+                             hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n_sys; ++i)
+                if (act[i]) flag_or[i] |= 1;
+        }
+        progress_line(h, n, N, step_iters, t0);
+        const int old_prev2 = prev2;
+        prev2 = cur;
+        cur = xi;
+        xi = old_prev2;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    res.t_solve = now_s() - t0;
+    res.steps = N;
+    timer.collect(res);
+    collect_result<double>(h, bs, P, W.outer, U[cur], d_sig, n_sys, res);
+    std::vector<int32_t> inner_flags(n_sys);
+    HIPCHK(hipMemcpyAsync(res.iters.data(), W.inner.iters_total.p, sizeof(int32_t) * n_sys,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(inner_flags.data(), W.inner.flags.p, sizeof(int32_t) * n_sys,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n_sys; ++i) {
+        res.total_iters += res.iters[i];
+        // Inner max_iter hits are recovered by the next outer pass; only
+        // non-finite inner residuals and outer failures are reported.
+        res.flags[i] |= flag_or[i] | (inner_flags[i] & 2);
+    }
 }
 
 void fill_stats(dmri_stats* stats, const std::vector<int64_t>& owner_idx, const BatchResult& R,
@@ -491,7 +715,7 @@ void run_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, con
     } else if (h->opt.precision == 2) {
         solve_batch<float>(h, P, P.A32, n_sys, d_b, d_q, d_sig, R);
     } else {
-        throw Error(DMRI_E_UNSUPPORTED, "mixed precision with FP64 refinement is not built yet");
+        solve_batch_mixed(h, P, n_sys, d_b, d_q, d_sig, R);
     }
 }
 
@@ -605,6 +829,8 @@ dmri_status dmri_add_problem(dmri_handle h, int64_t n_nodes, const double* xyz, 
             in.hi[a] = box_hi[a];
         }
         in.periodic_mask = periodic_mask;
+        in.ordering = h->opt.ordering;
+        in.pencil = h->opt.pencil;
         auto rec = std::make_unique<ProblemRec>();
         rec->op = assemble(in);
         h->problems.push_back(std::move(rec));
@@ -702,9 +928,15 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "autotune") o.autotune = as_int(0, 1);
         else if (k == "n_steps") o.n_steps = as_int(0, 10000000);
         else if (k == "blocks_per_xcd") o.blocks_per_xcd = as_int(1, 4096);
-        else if (k == "chunk_passes") o.chunk_passes = as_int(1, 64);
+        else if (k == "max_outer") o.max_outer = as_int(1, 1000);
+        else if (k == "queue") o.queue = as_int(0, 1);
+        else if (k == "grab") o.grab = as_int(1, 1024);
+        else if (k == "nt") o.nt = as_int(0, 1);
+        else if (k == "lds") o.lds = as_int(0, 1);
         else if (k == "time_kernel") o.time_kernel = as_int(0, 4);
         else if (k == "progress") o.progress = as_int(0, 1000000);
+        else if (k == "ordering") o.ordering = as_int(0, 1);
+        else if (k == "pencil") o.pencil = as_int(1, 4096);
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -727,9 +959,15 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "autotune") *value = o.autotune;
         else if (k == "n_steps") *value = o.n_steps;
         else if (k == "blocks_per_xcd") *value = o.blocks_per_xcd;
-        else if (k == "chunk_passes") *value = o.chunk_passes;
+        else if (k == "max_outer") *value = o.max_outer;
+        else if (k == "queue") *value = o.queue;
+        else if (k == "grab") *value = o.grab;
+        else if (k == "nt") *value = o.nt;
+        else if (k == "lds") *value = o.lds;
         else if (k == "time_kernel") *value = o.time_kernel;
         else if (k == "progress") *value = o.progress;
+        else if (k == "ordering") *value = o.ordering;
+        else if (k == "pencil") *value = o.pencil;
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -862,7 +1100,7 @@ dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which
         hipStream_t st = h->stream;
         const int S = h->opt.sys_tile ? h->opt.sys_tile : auto_tile(n_sys);
         const Geom g = make_geom(static_cast<int32_t>(P.op.n_dof), static_cast<int32_t>(n_sys), S,
-                                 h->opt.blocks_per_xcd, h->opt.chunk_passes);
+                                 h->opt.blocks_per_xcd, h->opt.queue, h->opt.grab);
         const size_t nrow = static_cast<size_t>(g.n_rows), ld = static_cast<size_t>(g.ld);
         std::vector<double> hc(ld, 0.0), hd(3 * ld, 0.0);
         for (int64_t s = 0; s < n_sys; ++s) {
@@ -872,11 +1110,16 @@ dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which
         DevBuf<double> dc, dd;
         dc.upload(hc.data(), ld, st);
         dd.upload(hd.data(), 3 * ld, st);
+        // Device vectors are tile-major: element (row, s) at
+        // ((s / S) * n_rows + row) * S + s % S.
+        auto didx = [&](size_t row, int64_t sy) -> size_t {
+            return (static_cast<size_t>(sy / S) * nrow + row) * S + static_cast<size_t>(sy % S);
+        };
         if (!f32) {
             std::vector<double> hx(2 * nrow * ld, 0.0), hy(2 * nrow * ld);
             for (size_t i = 0; i < nrow; ++i)
-                for (int64_t s = 0; s < n_sys; ++s)
-                    for (int k = 0; k < 2; ++k) hx[2 * (i * ld + s) + k] = x[2 * (i * n_sys + s) + k];
+                for (int64_t sy = 0; sy < n_sys; ++sy)
+                    for (int k = 0; k < 2; ++k) hx[2 * didx(i, sy) + k] = x[2 * (i * n_sys + sy) + k];
             DevBuf<double> dx, dy;
             dx.upload(hx.data(), hx.size(), st);
             dy.alloc(hy.size());
@@ -887,14 +1130,14 @@ dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which
             HIPCHK(hipMemcpyAsync(hy.data(), dy.p, hy.size() * sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             for (size_t i = 0; i < nrow; ++i)
-                for (int64_t s = 0; s < n_sys; ++s)
-                    for (int k = 0; k < 2; ++k) y[2 * (i * n_sys + s) + k] = hy[2 * (i * ld + s) + k];
+                for (int64_t sy = 0; sy < n_sys; ++sy)
+                    for (int k = 0; k < 2; ++k) y[2 * (i * n_sys + sy) + k] = hy[2 * didx(i, sy) + k];
         } else {
             std::vector<float> hx(2 * nrow * ld, 0.0f), hy(2 * nrow * ld);
             for (size_t i = 0; i < nrow; ++i)
-                for (int64_t s = 0; s < n_sys; ++s)
+                for (int64_t sy = 0; sy < n_sys; ++sy)
                     for (int k = 0; k < 2; ++k)
-                        hx[2 * (i * ld + s) + k] = static_cast<float>(x[2 * (i * n_sys + s) + k]);
+                        hx[2 * didx(i, sy) + k] = static_cast<float>(x[2 * (i * n_sys + sy) + k]);
             DevBuf<float> dx, dy;
             dx.upload(hx.data(), hx.size(), st);
             dy.alloc(hy.size());
@@ -905,8 +1148,8 @@ dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which
             HIPCHK(hipMemcpyAsync(hy.data(), dy.p, hy.size() * sizeof(float), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             for (size_t i = 0; i < nrow; ++i)
-                for (int64_t s = 0; s < n_sys; ++s)
-                    for (int k = 0; k < 2; ++k) y[2 * (i * n_sys + s) + k] = hy[2 * (i * ld + s) + k];
+                for (int64_t sy = 0; sy < n_sys; ++sy)
+                    for (int k = 0; k < 2; ++k) y[2 * (i * n_sys + sy) + k] = hy[2 * didx(i, sy) + k];
         }
         return DMRI_OK;
     });

@@ -3,14 +3,18 @@
 //
 // Inside a wavefront, lane l works on system (tile*S + l % S) and on row
 // sub-slot l / S, so one pass of a wavefront covers 64/S rows x S systems:
-// for S = 64 every lane reads the same matrix row (uniform loads) and the
-// vector gathers are 64 consecutive complex values (1 KiB in FP64); for
+// for S = 64 every lane reads the same matrix row (uniform scalar loads) and
+// the vector accesses are 64 consecutive complex values (1 KiB in FP64); for
 // small batches S = 8 keeps all lanes busy with 8 rows at a time.
+//
+// Streaming kernels (vector updates) handle kUs row slots per wavefront per
+// chunk; out-of-range slots are clamped to a valid row and masked, so every
+// load of a chunk is issued before the first use (memory-level parallelism).
 //
 // Reductions (per-system dot products) are FP64 in every precision: lanes
 // accumulate their rows, wavefront shuffles and LDS combine a block, each
 // block stores one partial per system and item, and a finalize kernel adds
-// them in a fixed order. The hot kernels contain no fences and no atomics.
+// them in a fixed order. The hot kernels contain no fences.
 #include "kernels.hpp"
 
 #include <algorithm>
@@ -24,6 +28,10 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kUs = 4;  // row slots per wavefront per chunk (streaming kernels)
+constexpr int kUg = 2;  // row slots per wavefront per queue grab (gather kernels)
+constexpr int kLdsRowCap = 32;  // LDS staging: padded entries per row budgeted
+constexpr int kSpmvRows = 2;    // rows per lane processed together in the LDS SpMV
 
 template <typename T> using V2 = typename Vec2Of<T>::type;
 template <typename T> using V4 = typename Vec4Of<T>::type;
@@ -48,6 +56,19 @@ struct LaneCoef {
         d2 = static_cast<T>(s * gg.w);
     }
 };
+
+// Store that bypasses cache allocation (the value is not re-read soon), so
+// streamed outputs do not evict the gather working set from L2.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_nt(double2* p, double2 v) {
+    nt_d2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_d2*>(p));
+}
+__device__ __forceinline__ void store_nt(float2* p, float2 v) {
+    nt_f2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_f2*>(p));
+}
 
 template <typename T>
 __device__ __forceinline__ V2<T> mk2(T a, T b) {
@@ -84,19 +105,82 @@ __device__ __forceinline__ void diag_at(const T* __restrict__ dK0, const V4<T>* 
     di = lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w;
 }
 
-// Visit this block's rows of one item: block j takes chunks j, j+B, ...
+// Vectors are stored tile-major: [n_tiles][n_rows][S] complex, so the rows of
+// one tile are contiguous (S complex values per row) and spread evenly over
+// the L2 channels. Element (row, sys) of the tile is at vbase + row * S.
+__device__ __forceinline__ size_t vbase(const Geom& g, int tile, int S, int sys) {
+    return static_cast<size_t>(tile) * g.n_rows * S + (sys - tile * S);
+}
+
+__device__ __forceinline__ int wave_id_uniform() {
+    return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+}
+
+// Static sweep of a streaming kernel: block j takes chunks j, j+B, ...;
+// body(first_slot_row, r1) handles the kUs row slots first + u*kWaves*R.
 template <int S, typename Body>
-__device__ __forceinline__ void sweep_rows(const Geom& g, int part, int j, Body body) {
+__device__ __forceinline__ void sweep_static(const Geom& g, int part, int j, Body body) {
     constexpr int R = 64 / S;
     const int r0 = part * g.part_rows;
     const int r1 = min(g.n_rows, r0 + g.part_rows);
-    int wave = threadIdx.x >> 6;
-    if (S == 64) wave = __builtin_amdgcn_readfirstlane(wave);
-    const int off = wave * R + (threadIdx.x & 63) / S;
+    const int off = wave_id_uniform() * R + (threadIdx.x & 63) / S;
     const int step = g.B * g.chunk_rows;
-    for (int c0 = r0 + j * g.chunk_rows; c0 < r1; c0 += step) {
-        const int c1 = min(r1, c0 + g.chunk_rows);
-        for (int row = c0 + off; row < c1; row += kWaves * R) body(row);
+    for (int c0 = r0 + j * g.chunk_rows; c0 < r1; c0 += step) body(c0 + off, r1);
+}
+
+// Row of slot u of a static chunk, clamped into [.., r1).
+template <int S>
+__device__ __forceinline__ int slot_row(int first, int u, int r1, bool& ok) {
+    constexpr int R = 64 / S;
+    const int row = first + u * kWaves * R;
+    ok = row < r1;
+    return ok ? row : r1 - 1;
+}
+
+// Next queue position for this wavefront (one atomic per wavefront).
+__device__ __forceinline__ int grab(int32_t* ctr) {
+    int v = 0;
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(ctr, 1);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Sweep of a gather kernel, body(row) per valid row. Queue mode: each
+// wavefront takes grab*kUg*R consecutive rows at a time from the item's
+// queue (one atomic per grab). Static mode: block j takes chunks j, j+B, ...
+template <int S, typename Body>
+__device__ __forceinline__ void sweep_gather(const Geom& g, int part, int j, int32_t* ctr,
+                                             Body body) {
+    constexpr int R = 64 / S;
+    const int r0 = part * g.part_rows;
+    const int r1 = min(g.n_rows, r0 + g.part_rows);
+    if (r1 <= r0) return;
+    const int rs = (threadIdx.x & 63) / S;
+    if (g.queue) {
+        const int per = g.grab * kUg * R;
+        const int n = (r1 - r0 + per - 1) / per;
+        int c = grab(ctr);
+        while (c < n) {
+            const int cn = grab(ctr);
+            const int base = r0 + c * per + rs;
+            for (int m = 0; m < g.grab; ++m) {
+#pragma unroll
+                for (int u = 0; u < kUg; ++u) {
+                    const int row = base + (m * kUg + u) * R;
+                    if (row < r1) body(row);
+                }
+            }
+            c = cn;
+        }
+    } else {
+        const int off = wave_id_uniform() * R + rs;
+        const int step = g.B * g.chunk_rows;
+        for (int c0 = r0 + j * g.chunk_rows; c0 < r1; c0 += step) {
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                const int row = c0 + off + u * kWaves * R;
+                if (row < r1) body(row);
+            }
+        }
     }
 }
 
@@ -142,28 +226,163 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(
     for (int item = xcd; item < g.n_items; item += 8) {
         const int tile = item / g.n_parts, part = item - tile * g.n_parts;
         const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && s.active[sys];
         if (!__syncthreads_or(act)) continue;
         const LaneCoef<T> lc(gq[sys], lhs);
         double acc[2] = {0.0, 0.0};
-        if (act) {
-            sweep_rows<S>(g, part, j, [&](int row) {
-                const int kb = row_ptr[row], ke = row_ptr[row + 1];
-                T yr = 0, yi = 0;
-#pragma unroll 4
-                for (int k = kb; k < ke; ++k) {
-                    const int jj = col[k];
-                    const V4<T> a = aux[k];
-                    const T ar = K0[k] + lc.c * a.x;
+        sweep_gather<S>(g, part, j, sc.ctr_spmv + item, [&](int row) {
+            if (!act) return;
+            const int kb = row_ptr[row], ke = row_ptr[row + 1];
+            T yr = 0, yi = 0;
+            for (int k0 = kb; k0 < ke; k0 += kRowPad) {
+                int jj[kRowPad];
+                V2<T> xv[kRowPad];
+#pragma unroll
+                for (int u = 0; u < kRowPad; ++u) jj[u] = col[k0 + u];
+#pragma unroll
+                for (int u = 0; u < kRowPad; ++u) xv[u] = p[tb + static_cast<size_t>(jj[u]) * S];
+#pragma unroll
+                for (int u = 0; u < kRowPad; ++u) {
+                    const V4<T> a = aux[k0 + u];
+                    const T ar = K0[k0 + u] + lc.c * a.x;
                     const T ai = lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w;
-                    const V2<T> xv = p[static_cast<size_t>(jj) * g.ld + sys];
-                    yr += ar * xv.x - ai * xv.y;
-                    yi += ar * xv.y + ai * xv.x;
+                    yr += ar * xv[u].x - ai * xv[u].y;
+                    yi += ar * xv[u].y + ai * xv[u].x;
                 }
-                const size_t idx = static_cast<size_t>(row) * g.ld + sys;
-                q[idx] = mk2<T>(yr, yi);
-                dot_acc<HERM, T>(acc[0], acc[1], p[idx], mk2<T>(yr, yi));
-            });
+            }
+            const size_t idx = tb + static_cast<size_t>(row) * S;
+            if (g.nt) store_nt(q + idx, mk2<T>(yr, yi));
+            else q[idx] = mk2<T>(yr, yi);
+            dot_acc<HERM, T>(acc[0], acc[1], p[idx], mk2<T>(yr, yi));
+        });
+        reduce_store<S, 2>(g, sc, item, j, acc, lds);
+    }
+}
+
+// LDS-staged SpMV for wide tiles (S >= 32). Per chunk of rows the block
+// copies the chunk's matrix entries (column, K0, {M_D, V}) into LDS with one
+// coalesced burst, then every wavefront works on G of its rows at once:
+// column indices and values come from LDS (broadcast reads) and the G*kRowPad
+// gathers of a batch are issued back to back. Rows with fewer batches than
+// the longest row of the group repeat their last batch with a zero mask
+// (branch-free). Chunks with more entries than fit fall back to reading the
+// matrix from global memory row by row.
+template <typename T, int S, bool HERM>
+__global__ __launch_bounds__(kBlock) void k_spmv_lds(
+    Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const T* __restrict__ K0, const V4<T>* __restrict__ aux, const double4* __restrict__ gq,
+    Coef lhs, const V2<T>* __restrict__ p, V2<T>* __restrict__ q, SolverState s, Scratch sc) {
+    constexpr int R = 64 / S;
+    constexpr int CH = kUs * kWaves * R;
+    constexpr int MAXE = CH * kLdsRowCap;
+    constexpr int G = kSpmvRows;
+    __shared__ int32_t s_col[MAXE];
+    __shared__ T s_k0[MAXE];
+    __shared__ V4<T> s_aux[MAXE];
+    __shared__ int32_t s_rp[CH + 1];
+    __shared__ double lds[kWaves * S * 2];
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int item = xcd; item < g.n_items; item += 8) {
+        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+        const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
+        const bool act = sys < s.n_sys && s.active[sys];
+        if (!__syncthreads_or(act)) continue;
+        const LaneCoef<T> lc(gq[sys], lhs);
+        double acc[2] = {0.0, 0.0};
+        const int r0 = part * g.part_rows;
+        const int r1 = min(g.n_rows, r0 + g.part_rows);
+        const int lane_off = wave_id_uniform() * R + (threadIdx.x & 63) / S;
+        for (int c0 = r0 + j * CH; c0 < r1; c0 += g.B * CH) {
+            const int c1 = min(r1, c0 + CH);
+            const int e0 = row_ptr[c0];
+            const int ne = row_ptr[c1] - e0;
+            const bool staged = ne <= MAXE;
+            if (staged) {
+                for (int e = threadIdx.x; e < ne; e += kBlock) {
+                    s_col[e] = col[e0 + e];
+                    s_k0[e] = K0[e0 + e];
+                    s_aux[e] = aux[e0 + e];
+                }
+                for (int i = threadIdx.x; i <= c1 - c0; i += kBlock) s_rp[i] = row_ptr[c0 + i] - e0;
+            }
+            __syncthreads();
+            if (act && staged) {
+#pragma unroll
+                for (int m = 0; m < kUs / G; ++m) {
+                    int rw[G], kb[G], nb[G];
+                    bool ok[G];
+                    int nbmax = 1;
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) {
+                        const int row = c0 + lane_off + (m * G + gg) * kWaves * R;
+                        ok[gg] = row < c1;
+                        rw[gg] = ok[gg] ? row : c1 - 1;
+                        kb[gg] = s_rp[rw[gg] - c0];
+                        nb[gg] = (s_rp[rw[gg] - c0 + 1] - kb[gg]) / kRowPad;
+                        nbmax = max(nbmax, nb[gg]);
+                    }
+                    T yr[G], yi[G];
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) yr[gg] = yi[gg] = T(0);
+                    for (int b = 0; b < nbmax; ++b) {
+                        int jj[G][kRowPad];
+                        V2<T> xv[G][kRowPad];
+#pragma unroll
+                        for (int gg = 0; gg < G; ++gg) {
+                            const int base = kb[gg] + kRowPad * min(b, nb[gg] - 1);
+#pragma unroll
+                            for (int u = 0; u < kRowPad; ++u) jj[gg][u] = s_col[base + u];
+                        }
+#pragma unroll
+                        for (int gg = 0; gg < G; ++gg) {
+#pragma unroll
+                            for (int u = 0; u < kRowPad; ++u)
+                                xv[gg][u] = p[tb + static_cast<size_t>(jj[gg][u]) * S];
+                        }
+#pragma unroll
+                        for (int gg = 0; gg < G; ++gg) {
+                            const int base = kb[gg] + kRowPad * min(b, nb[gg] - 1);
+                            const T mk = b < nb[gg] ? T(1) : T(0);
+#pragma unroll
+                            for (int u = 0; u < kRowPad; ++u) {
+                                const V4<T> a = s_aux[base + u];
+                                const T ar = mk * (s_k0[base + u] + lc.c * a.x);
+                                const T ai = mk * (lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w);
+                                yr[gg] += ar * xv[gg][u].x - ai * xv[gg][u].y;
+                                yi[gg] += ar * xv[gg][u].y + ai * xv[gg][u].x;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) {
+                        if (!ok[gg]) continue;
+                        const size_t idx = tb + static_cast<size_t>(rw[gg]) * S;
+                        if (g.nt) store_nt(q + idx, mk2<T>(yr[gg], yi[gg]));
+                        else q[idx] = mk2<T>(yr[gg], yi[gg]);
+                        dot_acc<HERM, T>(acc[0], acc[1], p[idx], mk2<T>(yr[gg], yi[gg]));
+                    }
+                }
+            } else if (act) {
+                for (int u = 0; u < kUs; ++u) {
+                    const int row = c0 + lane_off + u * kWaves * R;
+                    if (row >= c1) continue;
+                    T yr = 0, yi = 0;
+                    for (int k = row_ptr[row]; k < row_ptr[row + 1]; ++k) {
+                        const V4<T> a = aux[k];
+                        const T ar = K0[k] + lc.c * a.x;
+                        const T ai = lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w;
+                        const V2<T> xv = p[tb + static_cast<size_t>(col[k]) * S];
+                        yr += ar * xv.x - ai * xv.y;
+                        yi += ar * xv.y + ai * xv.x;
+                    }
+                    const size_t idx = tb + static_cast<size_t>(row) * S;
+                    q[idx] = mk2<T>(yr, yi);
+                    dot_acc<HERM, T>(acc[0], acc[1], p[idx], mk2<T>(yr, yi));
+                }
+            }
+            __syncthreads();
         }
         reduce_store<S, 2>(g, sc, item, j, acc, lds);
     }
@@ -180,6 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
     for (int item = xcd; item < g.n_items; item += 8) {
         const int tile = item / g.n_parts, part = item - tile * g.n_parts;
         const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && s.active[sys];
         if (!__syncthreads_or(act)) continue;
         const LaneCoef<T> lc(gq[sys], lhs);
@@ -187,20 +407,34 @@ __global__ __launch_bounds__(kBlock) void k_update(
         const T ar = static_cast<T>(al.x), ai = static_cast<T>(al.y);
         double acc[3] = {0.0, 0.0, 0.0};
         if (act) {
-            sweep_rows<S>(g, part, j, [&](int row) {
-                const size_t idx = static_cast<size_t>(row) * g.ld + sys;
-                const V2<T> pv = p[idx], qv = q[idx];
-                V2<T> xv = x[idx], rv = r[idx];
-                xv.x += ar * pv.x - ai * pv.y;
-                xv.y += ar * pv.y + ai * pv.x;
-                rv.x -= ar * qv.x - ai * qv.y;
-                rv.y -= ar * qv.y + ai * qv.x;
-                x[idx] = xv;
-                r[idx] = rv;
-                T dr, di;
-                diag_at(dK0, daux, row, lc, dr, di);
-                dot_acc<HERM, T>(acc[0], acc[1], rv, cdivT<T>(rv, dr, di));
-                acc[2] += double(rv.x) * rv.x + double(rv.y) * rv.y;
+            sweep_static<S>(g, part, j, [&](int first, int r1) {
+                int row[kUs];
+                bool ok[kUs];
+                V2<T> pv[kUs], qv[kUs], xv[kUs], rv[kUs];
+#pragma unroll
+                for (int u = 0; u < kUs; ++u) {
+                    row[u] = slot_row<S>(first, u, r1, ok[u]);
+                    const size_t idx = tb + static_cast<size_t>(row[u]) * S;
+                    pv[u] = p[idx];
+                    qv[u] = q[idx];
+                    xv[u] = x[idx];
+                    rv[u] = r[idx];
+                }
+#pragma unroll
+                for (int u = 0; u < kUs; ++u) {
+                    if (!ok[u]) continue;
+                    const size_t idx = tb + static_cast<size_t>(row[u]) * S;
+                    xv[u].x += ar * pv[u].x - ai * pv[u].y;
+                    xv[u].y += ar * pv[u].y + ai * pv[u].x;
+                    rv[u].x -= ar * qv[u].x - ai * qv[u].y;
+                    rv[u].y -= ar * qv[u].y + ai * qv[u].x;
+                    x[idx] = xv[u];
+                    r[idx] = rv[u];
+                    T dr, di;
+                    diag_at(dK0, daux, row[u], lc, dr, di);
+                    dot_acc<HERM, T>(acc[0], acc[1], rv[u], cdivT<T>(rv[u], dr, di));
+                    acc[2] += double(rv[u].x) * rv[u].x + double(rv[u].y) * rv[u].y;
+                }
             });
         }
         reduce_store<S, 3>(g, sc, item, j, acc, lds);
@@ -218,83 +452,162 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(Geom g, const T* __restrict_
     for (int item = xcd; item < g.n_items; item += 8) {
         const int tile = item / g.n_parts, part = item - tile * g.n_parts;
         const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
         if (!(sys < s.n_sys && s.active[sys])) continue;
         const LaneCoef<T> lc(gq[sys], lhs);
         const double2 be = s.beta[sys];
         const T br = static_cast<T>(be.x), bi = static_cast<T>(be.y);
-        sweep_rows<S>(g, part, j, [&](int row) {
-            const size_t idx = static_cast<size_t>(row) * g.ld + sys;
-            T dr, di;
-            diag_at(dK0, daux, row, lc, dr, di);
-            const V2<T> z = cdivT<T>(r[idx], dr, di);
-            const V2<T> pv = p[idx];
-            p[idx] = mk2<T>(z.x + br * pv.x - bi * pv.y, z.y + br * pv.y + bi * pv.x);
+        sweep_static<S>(g, part, j, [&](int first, int r1) {
+            int row[kUs];
+            bool ok[kUs];
+            V2<T> rv[kUs], pv[kUs];
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                row[u] = slot_row<S>(first, u, r1, ok[u]);
+                const size_t idx = tb + static_cast<size_t>(row[u]) * S;
+                rv[u] = r[idx];
+                pv[u] = p[idx];
+            }
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                if (!ok[u]) continue;
+                T dr, di;
+                diag_at(dK0, daux, row[u], lc, dr, di);
+                const V2<T> z = cdivT<T>(rv[u], dr, di);
+                p[tb + static_cast<size_t>(row[u]) * S] =
+                    mk2<T>(z.x + br * pv[u].x - bi * pv[u].y, z.y + br * pv[u].y + bi * pv[u].x);
+            }
         });
     }
 }
 
-// Start of a time step: b = Right(u_prev), x0 = guess, r = b - A x0,
-// p = z = D^-1 r; partials rho, ||r||^2, ||b||^2.
+// Start of a time step (or of an outer refinement pass): b = Right(u_prev),
+// x0 = guess, r = b - A x0, p = z = D^-1 r; partials rho, ||r||^2, ||b||^2.
 template <typename T, int S, bool HERM, int GM>
 __global__ __launch_bounds__(kBlock) void k_init(
     Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const T* __restrict__ K0, const T* __restrict__ Kr, const V4<T>* __restrict__ aux,
     const T* __restrict__ dK0, const V4<T>* __restrict__ daux, const double4* __restrict__ gq,
     Coef lhs, Coef rhs, const V2<T>* __restrict__ u_prev, const V2<T>* __restrict__ u_prev2,
-    V2<T>* __restrict__ x, V2<T>* __restrict__ r, V2<T>* __restrict__ p, SolverState s,
-    Scratch sc) {
+    V2<T>* __restrict__ x, V2<T>* __restrict__ r, V2<T>* __restrict__ p,
+    const float2* __restrict__ dx, V2<T>* __restrict__ x_out, SolverState s, Scratch sc) {
     __shared__ double lds[kWaves * S * 4];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     for (int item = xcd; item < g.n_items; item += 8) {
         const int tile = item / g.n_parts, part = item - tile * g.n_parts;
         const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys;
         const double4 gg = gq[sys];
         const LaneCoef<T> ll(gg, lhs), lr(gg, rhs);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        if (act) {
-            sweep_rows<S>(g, part, j, [&](int row) {
-                const int kb = row_ptr[row], ke = row_ptr[row + 1];
-                T br = 0, bi = 0, axr = 0, axi = 0;
-                V2<T> x0_own = mk2<T>(0, 0);
-#pragma unroll 2
-                for (int k = kb; k < ke; ++k) {
-                    const int jj = col[k];
+        sweep_gather<S>(g, part, j, sc.ctr_init + item, [&](int row) {
+            if (!act) return;
+            const int kb = row_ptr[row], ke = row_ptr[row + 1];
+            T br = 0, bi = 0, axr = 0, axi = 0;
+            V2<T> x0_own = mk2<T>(0, 0);
+            constexpr int kB = kRowPad / 2;
+            for (int k0 = kb; k0 < ke; k0 += kB) {
+                int jj[kB];
+                V2<T> uj[kB], xj[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) jj[u] = col[k0 + u];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const size_t jdx = tb + static_cast<size_t>(jj[u]) * S;
+                    uj[u] = u_prev[jdx];
+                    if (GM == 1) {
+                        const V2<T> u2 = u_prev2[jdx];
+                        xj[u] = mk2<T>(u2.x, u2.y);
+                    } else if (GM == 2) {
+                        xj[u] = x[jdx];
+                    } else if (GM == 3) {
+                        const V2<T> xo = x[jdx];
+                        const float2 d = dx[jdx];
+                        xj[u] = mk2<T>(xo.x + static_cast<T>(d.x), xo.y + static_cast<T>(d.y));
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const int k = k0 + u;
+                    if (GM == 0) xj[u] = uj[u];
+                    if (GM == 1) xj[u] = mk2<T>(T(2) * uj[u].x - xj[u].x, T(2) * uj[u].y - xj[u].y);
                     const V4<T> a = aux[k];
                     const T vl = ll.d0 * a.y + ll.d1 * a.z + ll.d2 * a.w;
                     const T vr = lr.d0 * a.y + lr.d1 * a.z + lr.d2 * a.w;
                     const T al = K0[k] + ll.c * a.x;
                     const T arr = Kr[k] + lr.c * a.x;
-                    const size_t jdx = static_cast<size_t>(jj) * g.ld + sys;
-                    const V2<T> uj = u_prev[jdx];
-                    V2<T> xj;
-                    if (GM == 0) {
-                        xj = uj;
-                    } else if (GM == 1) {
-                        const V2<T> u2 = u_prev2[jdx];
-                        xj = mk2<T>(T(2) * uj.x - u2.x, T(2) * uj.y - u2.y);
-                    } else {
-                        xj = x[jdx];
-                    }
-                    if (jj == row) x0_own = xj;
-                    br += arr * uj.x - vr * uj.y;
-                    bi += arr * uj.y + vr * uj.x;
-                    axr += al * xj.x - vl * xj.y;
-                    axi += al * xj.y + vl * xj.x;
+                    if (jj[u] == row) x0_own = xj[u];
+                    br += arr * uj[u].x - vr * uj[u].y;
+                    bi += arr * uj[u].y + vr * uj[u].x;
+                    axr += al * xj[u].x - vl * xj[u].y;
+                    axi += al * xj[u].y + vl * xj[u].x;
                 }
-                const size_t idx = static_cast<size_t>(row) * g.ld + sys;
-                const V2<T> rv = mk2<T>(br - axr, bi - axi);
-                if (GM != 2) x[idx] = x0_own;
+            }
+            const size_t idx = tb + static_cast<size_t>(row) * S;
+            const V2<T> rv = mk2<T>(br - axr, bi - axi);
+            r[idx] = rv;
+            T dr, di;
+            diag_at(dK0, daux, row, ll, dr, di);
+            const V2<T> z = cdivT<T>(rv, dr, di);
+            if (GM != 3) p[idx] = z;
+            dot_acc<HERM, T>(acc[0], acc[1], rv, z);
+            acc[2] += double(rv.x) * rv.x + double(rv.y) * rv.y;
+            acc[3] += double(br) * br + double(bi) * bi;
+            // The guess of this row is stored where no other row reads it
+            // during this launch: x itself when the gathers read u_prev
+            // (GM 0/1), a second buffer when they read x (GM 3).
+            if (GM == 0 || GM == 1) x[idx] = x0_own;
+            if (GM == 3) x_out[idx] = x0_own;
+        });
+        reduce_store<S, 4>(g, sc, item, j, acc, lds);
+    }
+}
+
+// Start of the FP32 inner solve: r = (float) r64 for outer-active systems,
+// dx = 0 everywhere, p = z = D^-1 r; partials rho, ||r||^2, ||r64||^2.
+template <int S, bool HERM>
+__global__ __launch_bounds__(kBlock) void k_inner_start(
+    Geom g, const float* __restrict__ dK0, const float4* __restrict__ daux,
+    const double4* __restrict__ gq, Coef lhs, const double2* __restrict__ r64,
+    const int32_t* __restrict__ outer_active, float2* __restrict__ r, float2* __restrict__ dx,
+    float2* __restrict__ p, SolverState s, Scratch sc) {
+    __shared__ double lds[kWaves * S * 4];
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int item = xcd; item < g.n_items; item += 8) {
+        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+        const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
+        const bool act = sys < s.n_sys && outer_active[sys];
+        const LaneCoef<float> lc(gq[sys], lhs);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        sweep_static<S>(g, part, j, [&](int first, int r1) {
+            int row[kUs];
+            bool ok[kUs];
+            double2 rv64[kUs];
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                row[u] = slot_row<S>(first, u, r1, ok[u]);
+                rv64[u] = act ? r64[tb + static_cast<size_t>(row[u]) * S]
+                              : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                if (!ok[u]) continue;
+                const size_t idx = tb + static_cast<size_t>(row[u]) * S;
+                dx[idx] = make_float2(0.0f, 0.0f);
+                const float2 rv = make_float2(static_cast<float>(rv64[u].x),
+                                              static_cast<float>(rv64[u].y));
+                float dr, di;
+                diag_at(dK0, daux, row[u], lc, dr, di);
+                const float2 z = cdivT<float>(rv, dr, di);
                 r[idx] = rv;
-                T dr, di;
-                diag_at(dK0, daux, row, ll, dr, di);
-                const V2<T> z = cdivT<T>(rv, dr, di);
                 p[idx] = z;
-                dot_acc<HERM, T>(acc[0], acc[1], rv, z);
+                dot_acc<HERM, float>(acc[0], acc[1], rv, z);
                 acc[2] += double(rv.x) * rv.x + double(rv.y) * rv.y;
-                acc[3] += double(br) * br + double(bi) * bi;
-            });
-        }
+                acc[3] += rv64[u].x * rv64[u].x + rv64[u].y * rv64[u].y;
+            }
+        });
         reduce_store<S, 4>(g, sc, item, j, acc, lds);
     }
 }
@@ -309,12 +622,19 @@ __global__ __launch_bounds__(kBlock) void k_signal(Geom g, const double* __restr
     for (int item = xcd; item < g.n_items; item += 8) {
         const int tile = item / g.n_parts, part = item - tile * g.n_parts;
         const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
         double acc[2] = {0.0, 0.0};
         if (sys < n_sys) {
-            sweep_rows<S>(g, part, j, [&](int row) {
-                const V2<T> xv = x[static_cast<size_t>(row) * g.ld + sys];
-                acc[0] += w[row] * double(xv.x);
-                acc[1] += w[row] * double(xv.y);
+            sweep_static<S>(g, part, j, [&](int first, int r1) {
+#pragma unroll
+                for (int u = 0; u < kUs; ++u) {
+                    bool ok;
+                    const int row = slot_row<S>(first, u, r1, ok);
+                    const V2<T> xv = x[tb + static_cast<size_t>(row) * S];
+                    const double wv = ok ? w[row] : 0.0;
+                    acc[0] += wv * double(xv.x);
+                    acc[1] += wv * double(xv.y);
+                }
             });
         }
         reduce_store<S, 2>(g, sc, item, j, acc, lds);
@@ -323,16 +643,19 @@ __global__ __launch_bounds__(kBlock) void k_signal(Geom g, const double* __restr
 
 // Add a tile's partials in a fixed order and update the per-system scalars.
 // One block per tile; thread (grp, s) sums partials grp, grp+G, ... of
-// system s, then the groups are combined in order.
+// system s, then the groups are combined in order. Resets the tile's queue
+// counters in `zero_ctr` (items tile*n_parts .. +n_parts-1).
 template <int S, int K, int MODE>
 __global__ __launch_bounds__(kBlock) void k_finalize(Geom g, SolverState s, Scratch sc,
-                                                     double2* __restrict__ out, int32_t n_sig) {
+                                                     double2* __restrict__ out, int32_t n_sig,
+                                                     int32_t* __restrict__ zero_ctr) {
     constexpr int G = kBlock / S;
     __shared__ double lds[kBlock * K];
     __shared__ int cnt;
     const int tile = blockIdx.x;
     const int grp = threadIdx.x / S, sl = threadIdx.x % S;
     const int sys = tile * S + sl;
+    if (zero_ctr && threadIdx.x < g.n_parts) zero_ctr[tile * g.n_parts + threadIdx.x] = 0;
     if (MODE == FIN_ALPHA || MODE == FIN_BETA) {
         const bool act = sys < s.n_sys && s.active[sys];
         if (!__syncthreads_or(act)) return;
@@ -425,32 +748,41 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, MatView<T> A, int whic
     for (int item = xcd; item < g.n_items; item += 8) {
         const int tile = item / g.n_parts, part = item - tile * g.n_parts;
         const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
         const T c = static_cast<T>(cc[sys]);
         const double3 d3 = dd[sys];
         const T d0 = static_cast<T>(d3.x), d1 = static_cast<T>(d3.y), d2 = static_cast<T>(d3.z);
-        sweep_rows<S>(g, part, j, [&](int row) {
-            T yr = 0, yi = 0;
-            for (int k = A.row_ptr[row]; k < A.row_ptr[row + 1]; ++k) {
-                const V4<T> a = A.aux[k];
-                const T ar = base[k] + c * a.x;
-                const T ai = d0 * a.y + d1 * a.z + d2 * a.w;
-                const V2<T> xv = x[static_cast<size_t>(A.col[k]) * g.ld + sys];
-                yr += ar * xv.x - ai * xv.y;
-                yi += ar * xv.y + ai * xv.x;
+        sweep_static<S>(g, part, j, [&](int first, int r1) {
+            for (int u = 0; u < kUs; ++u) {
+                bool ok;
+                const int row = slot_row<S>(first, u, r1, ok);
+                if (!ok) continue;
+                T yr = 0, yi = 0;
+                for (int k = A.row_ptr[row]; k < A.row_ptr[row + 1]; ++k) {
+                    const V4<T> a = A.aux[k];
+                    const T ar = base[k] + c * a.x;
+                    const T ai = d0 * a.y + d1 * a.z + d2 * a.w;
+                    const V2<T> xv = x[tb + static_cast<size_t>(A.col[k]) * S];
+                    yr += ar * xv.x - ai * xv.y;
+                    yi += ar * xv.y + ai * xv.x;
+                }
+                y[tb + static_cast<size_t>(row) * S] = mk2<T>(yr, yi);
             }
-            y[static_cast<size_t>(row) * g.ld + sys] = mk2<T>(yr, yi);
         });
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_set_initial(int64_t n, int32_t ld, int32_t n_sys,
+__global__ __launch_bounds__(kBlock) void k_set_initial(int64_t n, int32_t n_rows, int32_t S,
+                                                        int32_t n_sys,
                                                         const double* __restrict__ u0,
                                                         V2<T>* __restrict__ x) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    const int64_t row = i / ld;
-    const int sys = static_cast<int>(i - row * ld);
+    const int64_t slab = i / S;  // tile * n_rows + row
+    const int64_t tile = slab / n_rows;
+    const int64_t row = slab - tile * n_rows;
+    const int64_t sys = tile * S + (i - slab * S);
     x[i] = mk2<T>(sys < n_sys ? static_cast<T>(u0[row]) : T(0), T(0));
 }
 
@@ -496,13 +828,13 @@ inline dim3 grid_of(const Geom& g) { return dim3(8u * static_cast<unsigned>(g.B)
 
 template <int MODE, int K>
 void launch_fin(hipStream_t st, const Geom& g, SolverState s, Scratch sc, double2* out,
-                int32_t n_sig) {
+                int32_t n_sig, int32_t* zero_ctr) {
     const dim3 grid(static_cast<unsigned>(g.n_tiles)), block(kBlock);
     switch (g.S) {
-        case 8: k_finalize<8, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig); break;
-        case 16: k_finalize<16, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig); break;
-        case 32: k_finalize<32, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig); break;
-        case 64: k_finalize<64, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig); break;
+        case 8: k_finalize<8, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
+        case 16: k_finalize<16, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
+        case 32: k_finalize<32, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
+        case 64: k_finalize<64, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
         default: throw std::runtime_error("unsupported tile width");
     }
     check_launch("finalize");
@@ -512,16 +844,18 @@ void launch_fin(hipStream_t st, const Geom& g, SolverState s, Scratch sc, double
 
 // ------------------------------------------------------------- launchers
 
-Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
-               int32_t chunk_passes) {
+Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd, int32_t queue,
+               int32_t grab) {
     Geom g{};
+    g.queue = queue;
+    g.grab = std::max(1, grab);
     g.n_rows = n_rows;
     g.S = S;
     g.n_tiles = std::max(1, (n_sys + S - 1) / S);
     g.ld = g.n_tiles * S;
     g.n_parts = 8 / std::gcd(g.n_tiles, 8);
     g.n_items = g.n_tiles * g.n_parts;
-    g.chunk_rows = kWaves * (64 / S) * std::max(1, chunk_passes);
+    g.chunk_rows = kUs * kWaves * (64 / S);
     int32_t pr = (n_rows + g.n_parts - 1) / g.n_parts;
     pr = ((pr + g.chunk_rows - 1) / g.chunk_rows) * g.chunk_rows;
     g.part_rows = std::max(pr, g.chunk_rows);
@@ -542,26 +876,47 @@ Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
 template <typename T>
 void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq, Coef lhs,
                  Coef rhs, bool herm, int guess_mode, const V2<T>* u_prev, const V2<T>* u_prev2,
-                 V2<T>* x, V2<T>* r, V2<T>* p, SolverState s, Scratch sc) {
+                 V2<T>* x, V2<T>* r, V2<T>* p, const float2* dx, V2<T>* x_out, SolverState s,
+                 Scratch sc) {
     const dim3 grid = grid_of(g), block(kBlock);
 #define DMRI_INIT(H, GMV)                                                                     \
     k_init<T, S, H, GMV><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.Kr, A.aux, A.dK0, \
                                                  A.daux, gq, lhs, rhs, u_prev, u_prev2, x, r, p, \
-                                                 s, sc)
+                                                 dx, x_out, s, sc)
+#define DMRI_INIT_GM(H)                      \
+    switch (guess_mode) {                    \
+        case 0: DMRI_INIT(H, 0); break;      \
+        case 1: DMRI_INIT(H, 1); break;      \
+        case 2: DMRI_INIT(H, 2); break;      \
+        default: DMRI_INIT(H, 3); break;     \
+    }
     DMRI_DISPATCH_S(g.S, {
         if (herm) {
-            if (guess_mode == 0) DMRI_INIT(true, 0);
-            else if (guess_mode == 1) DMRI_INIT(true, 1);
-            else DMRI_INIT(true, 2);
+            DMRI_INIT_GM(true)
         } else {
-            if (guess_mode == 0) DMRI_INIT(false, 0);
-            else if (guess_mode == 1) DMRI_INIT(false, 1);
-            else DMRI_INIT(false, 2);
+            DMRI_INIT_GM(false)
         }
     });
+#undef DMRI_INIT_GM
 #undef DMRI_INIT
     check_launch("init");
-    launch_fin<FIN_INIT, 4>(st, g, s, sc, nullptr, 0);
+    launch_fin<FIN_INIT, 4>(st, g, s, sc, nullptr, 0, sc.ctr_init);
+}
+
+void launch_inner_start(hipStream_t st, const Geom& g, const MatView<float>& A, const double4* gq,
+                        Coef lhs, bool herm, const double2* r64, const int32_t* outer_active,
+                        float2* r, float2* dx, float2* p, SolverState s, Scratch sc) {
+    const dim3 grid = grid_of(g), block(kBlock);
+    DMRI_DISPATCH_S(g.S, {
+        if (herm)
+            k_inner_start<S, true><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r64,
+                                                           outer_active, r, dx, p, s, sc);
+        else
+            k_inner_start<S, false><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r64,
+                                                            outer_active, r, dx, p, s, sc);
+    });
+    check_launch("inner_start");
+    launch_fin<FIN_INIT, 4>(st, g, s, sc, nullptr, 0, nullptr);
 }
 
 template <typename T>
@@ -569,15 +924,29 @@ void launch_spmv_dot(hipStream_t st, const Geom& g, const MatView<T>& A, const d
                      Coef lhs, bool herm, const V2<T>* p, V2<T>* q, SolverState s, Scratch sc) {
     const dim3 grid = grid_of(g), block(kBlock);
     DMRI_DISPATCH_S(g.S, {
-        if (herm)
-            k_spmv_dot<T, S, true><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.aux, gq,
-                                                           lhs, p, q, s, sc);
-        else
-            k_spmv_dot<T, S, false><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.aux, gq,
-                                                            lhs, p, q, s, sc);
+        bool done = false;
+        if constexpr (S >= 32) {
+            if (g.lds) {
+                done = true;
+                if (herm)
+                    k_spmv_lds<T, S, true><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.aux,
+                                                               gq, lhs, p, q, s, sc);
+                else
+                    k_spmv_lds<T, S, false><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0,
+                                                                    A.aux, gq, lhs, p, q, s, sc);
+            }
+        }
+        if (!done) {
+            if (herm)
+                k_spmv_dot<T, S, true><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.aux,
+                                                               gq, lhs, p, q, s, sc);
+            else
+                k_spmv_dot<T, S, false><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.aux,
+                                                                gq, lhs, p, q, s, sc);
+        }
     });
     check_launch("spmv_dot");
-    launch_fin<FIN_ALPHA, 2>(st, g, s, sc, nullptr, 0);
+    launch_fin<FIN_ALPHA, 2>(st, g, s, sc, nullptr, 0, sc.ctr_spmv);
 }
 
 template <typename T>
@@ -594,7 +963,7 @@ void launch_update(hipStream_t st, const Geom& g, const MatView<T>& A, const dou
                                                           s, sc);
     });
     check_launch("update");
-    launch_fin<FIN_BETA, 3>(st, g, s, sc, nullptr, 0);
+    launch_fin<FIN_BETA, 3>(st, g, s, sc, nullptr, 0, nullptr);
 }
 
 template <typename T>
@@ -613,7 +982,7 @@ void launch_signal(hipStream_t st, const Geom& g, const double* w, const V2<T>* 
     const dim3 grid = grid_of(g), block(kBlock);
     DMRI_DISPATCH_S(g.S, { k_signal<T, S><<<grid, block, 0, st>>>(g, w, x, n_sys, sc); });
     check_launch("signal");
-    launch_fin<FIN_SIGNAL, 2>(st, g, SolverState{}, sc, out, n_sys);
+    launch_fin<FIN_SIGNAL, 2>(st, g, SolverState{}, sc, out, n_sys, nullptr);
 }
 
 template <typename T>
@@ -629,7 +998,7 @@ void launch_set_initial(hipStream_t st, const Geom& g, const double* u0, int32_t
                         V2<T>* x) {
     const int64_t n = static_cast<int64_t>(g.n_rows) * g.ld;
     const unsigned blocks = static_cast<unsigned>((n + kBlock - 1) / kBlock);
-    k_set_initial<T><<<blocks, kBlock, 0, st>>>(n, g.ld, n_sys, u0, x);
+    k_set_initial<T><<<blocks, kBlock, 0, st>>>(n, g.n_rows, g.S, n_sys, u0, x);
     check_launch("set_initial");
 }
 
@@ -650,7 +1019,7 @@ void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
 #define DMRI_INST(T)                                                                          \
     template void launch_init<T>(hipStream_t, const Geom&, const MatView<T>&, const double4*,  \
                                  Coef, Coef, bool, int, const V2<T>*, const V2<T>*, V2<T>*,    \
-                                 V2<T>*, V2<T>*, SolverState, Scratch);                        \
+                                 V2<T>*, V2<T>*, const float2*, V2<T>*, SolverState, Scratch); \
     template void launch_spmv_dot<T>(hipStream_t, const Geom&, const MatView<T>&,              \
                                      const double4*, Coef, bool, const V2<T>*, V2<T>*,         \
                                      SolverState, Scratch);                                    \

@@ -2,11 +2,16 @@
 //
 // Data layout in HBM (one problem = one mesh):
 //   CSR pattern      row_ptr[n+1], col[nnz]                        int32
+//                    every row padded to a multiple of kRowPad entries
+//                    (padding: column = the row itself, all values 0), so
+//                    the gather kernels fetch kRowPad column indices with one
+//                    scalar load and issue kRowPad gathers back to back
 //   matrix values    K0[nnz], Kr[nnz]                               T
 //                    aux[nnz] = {M_D, V_x, V_y, V_z}                T4 (16/32 B)
 //                    dK0[n], daux[n] (the diagonal, for Jacobi)
-//   vectors          [n_rows][ld] complex (T2), systems fastest;
-//                    ld = number of systems rounded up to the tile width
+//   vectors          [n_tiles][n_rows][S] complex (T2): tile-major, systems
+//                    fastest inside a tile, so a tile's rows are contiguous
+//                    (S complex values per row); ld = n_tiles * S
 //   per system       gq[ld] = {G, q_x, q_y, q_z} (double4)
 // K0 = M/dt + theta R is the constant part of the left operator,
 // Kr = M/dt - (1-theta) R the constant part of the right operator
@@ -16,12 +21,14 @@
 // Work decomposition ("XCD sweep"). A tile is S consecutive systems. Work
 // items are (tile, row part) pairs, numbered so that their count is a
 // multiple of 8; XCD x (blocks with blockIdx % 8 == x, which the hardware
-// places on XCD x) owns items x, x+8, ... Inside an item the B blocks of the
-// XCD sweep the rows in chunks (block j takes chunks j, j+B, ...), so the
-// rows being gathered at any moment form one window of B*chunk rows that
-// stays in that XCD's L2. Every block keeps one FP64 partial per system for
-// each item; small finalize kernels add the partials in a fixed order
-// (deterministic) and update the per-system Krylov scalars.
+// places on XCD x) owns items x, x+8, ... Inside an item the wavefronts of
+// the XCD sweep the rows: the kernels that gather neighbour values (SpMV,
+// step start) take the next few rows from a per-item queue (one atomic per
+// wavefront grab), so the rows in flight form one compact window that stays
+// in that XCD's L2; the streaming kernels give block j the chunks j, j+B, ...
+// Every block keeps one FP64 partial per system for each item; small
+// finalize kernels add the partials in a fixed order (deterministic), update
+// the per-system Krylov scalars and reset the queues.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,6 +36,8 @@
 #include <cstdint>
 
 namespace dmri {
+
+constexpr int kRowPad = 8;
 
 template <typename T> struct Vec2Of;
 template <> struct Vec2Of<double> { using type = double2; };
@@ -83,24 +92,40 @@ struct Geom {
     int32_t n_parts;     // row parts per tile
     int32_t n_items;     // n_tiles * n_parts (a multiple of 8)
     int32_t part_rows;   // rows per part (multiple of chunk_rows)
-    int32_t chunk_rows;  // rows per block chunk (4 wavefronts x 64/S rows x passes)
+    int32_t chunk_rows;  // rows per block chunk of the streaming kernels
     int32_t B;           // blocks per XCD
+    int32_t queue;       // gather kernels: 1 = per-item row queue, 0 = static chunks
+    int32_t grab;        // queue grabs per wavefront take grab * 2 * 64/S rows
+    int32_t nt;          // 1 = SpMV output stored non-temporally
+    int32_t lds;         // 1 = LDS-staged SpMV for tiles of 32 or 64 systems
 };
 
 struct Scratch {
     double* partial;     // [n_items][B][S][4]
+    int32_t* ctr_spmv;   // [n_items] chunk queues of the gather kernels,
+    int32_t* ctr_init;   // [n_items] zero between launches
 };
 
-Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
-               int32_t chunk_passes);
+Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd, int32_t queue,
+               int32_t grab);
 
-// guess_mode: 0 x0 = u_prev, 1 x0 = 2 u_prev - u_prev2, 2 x0 given in x.
+// guess_mode: 0 x0 = u_prev, 1 x0 = 2 u_prev - u_prev2 (x0 written to x),
+// 2 x0 given in x, 3 x0 = x + dx (mixed-precision correction, written to
+// x_out, which must not alias x). p is written except in mode 3.
 template <typename T>
 void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
                  Coef lhs, Coef rhs, bool herm, int guess_mode,
                  const typename Vec2Of<T>::type* u_prev, const typename Vec2Of<T>::type* u_prev2,
                  typename Vec2Of<T>::type* x, typename Vec2Of<T>::type* r,
-                 typename Vec2Of<T>::type* p, SolverState s, Scratch sc);
+                 typename Vec2Of<T>::type* p, const float2* dx, typename Vec2Of<T>::type* x_out,
+                 SolverState s, Scratch sc);
+
+// Start of an FP32 inner solve on the FP64 residual r64 of the systems still
+// active in `outer`: r = (float) r64, dx = 0, p = D^-1 r (FP32 operator).
+void launch_inner_start(hipStream_t st, const Geom& g, const MatView<float>& A,
+                        const double4* gq, Coef lhs, bool herm, const double2* r64,
+                        const int32_t* outer_active, float2* r, float2* dx, float2* p,
+                        SolverState s, Scratch sc);
 
 template <typename T>
 void launch_spmv_dot(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,

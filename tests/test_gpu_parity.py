@@ -232,3 +232,39 @@ def test_fp32_path_close(Sim):
     err = rel_err(sig, ref, ref[0])
     _say("fp32 max err %.2e" % err.max())
     assert err.max() < 1e-4
+
+
+@pytest.mark.parametrize("case", ["periodic", "neumann"])
+def test_mixed_precision_refinement_matches_oracle(Sim, case):
+    if case == "periodic":
+        prob, b, q = _cyl_case()
+        form = "transformed"
+    else:
+        prob = di.slab_box(n=10, half=5.0, split=-1.0, D=(3e-3, 1e-3), kappa=1e-3,
+                           u0=(1.0, 0.2), periodic_mask=0)
+        b = np.array([0.0, 1000.0, 3000.0])
+        q = np.array([[1.0, 0.0, 0.0], [0.8, 0.6, 0.0], [0.0, 0.3, 0.95]])
+        form = "uform"
+    ref = timestep.signals(prob, SHORT, b, q, form=form, solver="splu")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(precision=1, rtol=1e-12, inner_rtol=1e-4)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+    err = rel_err(sig, ref, ref[0])
+    _say("mixed %s max err %.2e status %s iters %s" % (case, err.max(), st["status"],
+                                                      st["iters_total"].tolist()))
+    assert st["status"] == "DMRI_OK"
+    assert err.max() < 1e-9
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_orderings_agree(Sim, ordering):
+    prob, b, q = _cyl_case()
+    ref = timestep.signals(prob, SHORT, b[:5], q[:5], solver="splu")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12, ordering=ordering, pencil=4)
+        pid = sim.add_problem(prob)
+        sig, _ = sim.dmri_run([pid] * 5, b[:5], q[:5])
+    assert rel_err(sig, ref, ref[0]).max() < 1e-9
