@@ -174,6 +174,9 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *  "nt"         1 = SpMV results stored non-temporally (default)
  *  "lds"        1 = SpMV stages matrix chunks in LDS for tiles of 32/64
  *               systems (default 0)
+ *  "persistent" Krylov iterations of a step in one persistent launch with
+ *               grid barriers: 0 = off, 1 = on (batches of <= 64 systems),
+ *               2 = auto (default: on when rows x systems <= 131072)
  *  "progress"   k > 0 prints one line to stderr every k time steps
  *  "ordering"   DOF order of problems added afterwards: 0 = Morton curve,
  *               1 = pencils (default): columns of "pencil" x "pencil" cells

@@ -130,6 +130,7 @@ struct Options {
     int grab = 4;
     int nt = 1;
     int lds = 0;
+    int persistent = 2;
     int time_kernel = 0;
     int progress = 0;
     int ordering = 1;
@@ -191,6 +192,7 @@ struct Workspace {
     DevBuf<double2> sig;
     DevBuf<double> partial, b_in, q_in;
     DevBuf<int32_t> ctr, bad;
+    DevBuf<uint32_t> barrier;  // count, generation, error flag of the persistent solver
     StateBufs outer, inner;
     int32_t* h_active[2] = {nullptr, nullptr};  // pinned
     size_t h_active_n = 0;
@@ -392,8 +394,11 @@ struct KernelTimer {
 // Common set-up of a batch: geometry, per-system parameters, scratch.
 struct BatchSetup {
     Geom g;
+    Geom gp;        // geometry of the persistent solver (one block per CU)
+    bool persist;   // Krylov loop in one persistent launch per solve
     bool herm;
     Scratch sc;
+    GridBarrier bar;
 };
 
 BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
@@ -411,8 +416,25 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     bs.g.lds = h->opt.lds;
     const Geom& g = bs.g;
     const size_t ld = static_cast<size_t>(g.ld);
+    int n_cu = 0;
+    HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
+    bs.gp = make_geom(g.n_rows, static_cast<int32_t>(n_sys), S, std::max(1, n_cu / 8), 0, 1);
+    bs.gp.nt = g.nt;
+    bs.gp.lds = 0;
+    // Auto: the persistent solver wins where launch latency dominates (small
+    // batches on small meshes); chunked launches win once a phase has enough
+    // work to hide the per-launch cost.
+    const bool small = static_cast<int64_t>(g.n_rows) * g.ld <= 131072;
+    bs.persist = (h->opt.persistent == 1 || (h->opt.persistent == 2 && small)) && g.ld <= 64;
     W.gq.alloc(ld);
-    W.partial.alloc(static_cast<size_t>(g.n_items) * g.B * S * 4);
+    const size_t part_n = std::max<size_t>(static_cast<size_t>(g.n_items) * g.B * S * 4,
+                                           2 * static_cast<size_t>(bs.gp.n_items) * bs.gp.B * S * 4);
+    W.partial.alloc(part_n);
+    W.barrier.alloc(32 * 11);
+    HIPCHK(hipMemsetAsync(W.barrier.p, 0, sizeof(uint32_t) * 32 * 11, st));
+    bs.bar.count = W.barrier.p;
+    bs.bar.gen = W.barrier.p + 32 * 9;
+    bs.bar.err = reinterpret_cast<int32_t*>(W.barrier.p + 32 * 10);
     W.ctr.alloc(2 * static_cast<size_t>(g.n_items));
     W.bad.alloc(1);
     W.pinned(static_cast<size_t>(g.n_tiles));
@@ -451,6 +473,13 @@ int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const d
                 KernelTimer& timer, int first_chunk, int max_iter) {
     hipStream_t st = h->stream;
     const Geom& g = bs.g;
+    if (bs.persist) {
+        timer.run(1, [&] {
+            launch_krylov_persistent<T>(st, bs.gp, Av, gq, lhs, bs.herm, x, r, p, q, s, bs.sc,
+                                        bs.bar);
+        });
+        return 0;
+    }
     int done = 0, slot = 0;
     bool pending = false;
     int chunk = std::max(1, first_chunk);
@@ -520,7 +549,12 @@ void collect_result(dmri_ctx* h, const BatchSetup& bs, ProblemRec& P, StateBufs&
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(res.rr.data(), sb.rr.p, sizeof(double) * n_sys, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(res.bb.data(), sb.bb.p, sizeof(double) * n_sys, hipMemcpyDeviceToHost, st));
+    int32_t bar_err = 0;
+    HIPCHK(hipMemcpyAsync(&bar_err, h->ws.barrier.p + 32 * 10, sizeof(int32_t),
+                          hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (bar_err != 0)
+        throw Error(DMRI_E_DEVICE, "persistent solver: a grid barrier wait timed out");
     res.t_signal = now_s() - t0;
 }
 
@@ -570,7 +604,6 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
                                         last_iters - 2, h->opt.max_iter);
         last_iters = done;
         progress_line(h, n, N, done, t0);
-        res.spmv_rows += static_cast<int64_t>(done) * g.n_rows * n_sys;
         const int old_prev2 = prev2;
         prev2 = cur;
         cur = nxt;
@@ -585,6 +618,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int64_t i = 0; i < n_sys; ++i) res.total_iters += res.iters[i];
+    res.spmv_rows = res.total_iters * g.n_rows;
 }
 
 // Mixed precision: FP64 time stepping (right-hand side, residual, solution,
@@ -648,7 +682,6 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                                               h->opt.max_iter);
             if (pass == 0) last_first_pass = it;
             step_iters += it;
-            res.spmv_rows += static_cast<int64_t>(it) * g.n_rows * n_sys;
             timer.run(4, [&] {
                 launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, 3, U[cur], U[prev2],
                                     U[xi], r64, p64, dx, U[yi], so, bs.sc);
@@ -686,6 +719,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
         // non-finite inner residuals and outer failures are reported.
         res.flags[i] |= flag_or[i] | (inner_flags[i] & 2);
     }
+    res.spmv_rows = res.total_iters * g.n_rows;
 }
 
 void fill_stats(dmri_stats* stats, const std::vector<int64_t>& owner_idx, const BatchResult& R,
@@ -933,6 +967,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "grab") o.grab = as_int(1, 1024);
         else if (k == "nt") o.nt = as_int(0, 1);
         else if (k == "lds") o.lds = as_int(0, 1);
+        else if (k == "persistent") o.persistent = as_int(0, 2);
         else if (k == "time_kernel") o.time_kernel = as_int(0, 4);
         else if (k == "progress") o.progress = as_int(0, 1000000);
         else if (k == "ordering") o.ordering = as_int(0, 1);
@@ -964,6 +999,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "grab") *value = o.grab;
         else if (k == "nt") *value = o.nt;
         else if (k == "lds") *value = o.lds;
+        else if (k == "persistent") *value = o.persistent;
         else if (k == "time_kernel") *value = o.time_kernel;
         else if (k == "progress") *value = o.progress;
         else if (k == "ordering") *value = o.ordering;

@@ -215,6 +215,42 @@ __device__ __forceinline__ void reduce_store(const Geom& g, Scratch sc, int item
 
 // --------------------------------------------------------------- kernels
 
+// One item of q = A p with sigma partial sums (p^H q or p^T q) per lane.
+template <typename T, int S, bool HERM>
+__device__ __forceinline__ void spmv_item(const Geom& g, int part, int j, int32_t* ctr, bool act,
+                                          size_t tb, const LaneCoef<T>& lc,
+                                          const int32_t* __restrict__ row_ptr,
+                                          const int32_t* __restrict__ col,
+                                          const T* __restrict__ K0, const V4<T>* __restrict__ aux,
+                                          const V2<T>* __restrict__ p, V2<T>* __restrict__ q,
+                                          double (&acc)[2]) {
+    sweep_gather<S>(g, part, j, ctr, [&](int row) {
+        if (!act) return;
+        const int kb = row_ptr[row], ke = row_ptr[row + 1];
+        T yr = 0, yi = 0;
+        for (int k0 = kb; k0 < ke; k0 += kRowPad) {
+            int jj[kRowPad];
+            V2<T> xv[kRowPad];
+#pragma unroll
+            for (int u = 0; u < kRowPad; ++u) jj[u] = col[k0 + u];
+#pragma unroll
+            for (int u = 0; u < kRowPad; ++u) xv[u] = p[tb + static_cast<size_t>(jj[u]) * S];
+#pragma unroll
+            for (int u = 0; u < kRowPad; ++u) {
+                const V4<T> a = aux[k0 + u];
+                const T ar = K0[k0 + u] + lc.c * a.x;
+                const T ai = lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w;
+                yr += ar * xv[u].x - ai * xv[u].y;
+                yi += ar * xv[u].y + ai * xv[u].x;
+            }
+        }
+        const size_t idx = tb + static_cast<size_t>(row) * S;
+        if (g.nt) store_nt(q + idx, mk2<T>(yr, yi));
+        else q[idx] = mk2<T>(yr, yi);
+        dot_acc<HERM, T>(acc[0], acc[1], p[idx], mk2<T>(yr, yi));
+    });
+}
+
 // q = A p and sigma = p^H q (or p^T q) per system.
 template <typename T, int S, bool HERM>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot(
@@ -231,31 +267,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(
         if (!__syncthreads_or(act)) continue;
         const LaneCoef<T> lc(gq[sys], lhs);
         double acc[2] = {0.0, 0.0};
-        sweep_gather<S>(g, part, j, sc.ctr_spmv + item, [&](int row) {
-            if (!act) return;
-            const int kb = row_ptr[row], ke = row_ptr[row + 1];
-            T yr = 0, yi = 0;
-            for (int k0 = kb; k0 < ke; k0 += kRowPad) {
-                int jj[kRowPad];
-                V2<T> xv[kRowPad];
-#pragma unroll
-                for (int u = 0; u < kRowPad; ++u) jj[u] = col[k0 + u];
-#pragma unroll
-                for (int u = 0; u < kRowPad; ++u) xv[u] = p[tb + static_cast<size_t>(jj[u]) * S];
-#pragma unroll
-                for (int u = 0; u < kRowPad; ++u) {
-                    const V4<T> a = aux[k0 + u];
-                    const T ar = K0[k0 + u] + lc.c * a.x;
-                    const T ai = lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w;
-                    yr += ar * xv[u].x - ai * xv[u].y;
-                    yi += ar * xv[u].y + ai * xv[u].x;
-                }
-            }
-            const size_t idx = tb + static_cast<size_t>(row) * S;
-            if (g.nt) store_nt(q + idx, mk2<T>(yr, yi));
-            else q[idx] = mk2<T>(yr, yi);
-            dot_acc<HERM, T>(acc[0], acc[1], p[idx], mk2<T>(yr, yi));
-        });
+        spmv_item<T, S, HERM>(g, part, j, sc.ctr_spmv + item, act, tb, lc, row_ptr, col, K0, aux,
+                              p, q, acc);
         reduce_store<S, 2>(g, sc, item, j, acc, lds);
     }
 }
@@ -388,6 +401,46 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lds(
     }
 }
 
+// One item of x += alpha p, r -= alpha q, z = D^-1 r with partial sums
+// rho' = r^H z (or r^T z) and ||r||^2.
+template <typename T, int S, bool HERM>
+__device__ __forceinline__ void update_item(const Geom& g, int part, int j, size_t tb,
+                                            const LaneCoef<T>& lc, T ar, T ai,
+                                            const T* __restrict__ dK0,
+                                            const V4<T>* __restrict__ daux, V2<T>* __restrict__ x,
+                                            V2<T>* __restrict__ r, const V2<T>* __restrict__ p,
+                                            const V2<T>* __restrict__ q, double (&acc)[3]) {
+    sweep_static<S>(g, part, j, [&](int first, int r1) {
+        int row[kUs];
+        bool ok[kUs];
+        V2<T> pv[kUs], qv[kUs], xv[kUs], rv[kUs];
+#pragma unroll
+        for (int u = 0; u < kUs; ++u) {
+            row[u] = slot_row<S>(first, u, r1, ok[u]);
+            const size_t idx = tb + static_cast<size_t>(row[u]) * S;
+            pv[u] = p[idx];
+            qv[u] = q[idx];
+            xv[u] = x[idx];
+            rv[u] = r[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < kUs; ++u) {
+            if (!ok[u]) continue;
+            const size_t idx = tb + static_cast<size_t>(row[u]) * S;
+            xv[u].x += ar * pv[u].x - ai * pv[u].y;
+            xv[u].y += ar * pv[u].y + ai * pv[u].x;
+            rv[u].x -= ar * qv[u].x - ai * qv[u].y;
+            rv[u].y -= ar * qv[u].y + ai * qv[u].x;
+            x[idx] = xv[u];
+            r[idx] = rv[u];
+            T dr, di;
+            diag_at(dK0, daux, row[u], lc, dr, di);
+            dot_acc<HERM, T>(acc[0], acc[1], rv[u], cdivT<T>(rv[u], dr, di));
+            acc[2] += double(rv[u].x) * rv[u].x + double(rv[u].y) * rv[u].y;
+        }
+    });
+}
+
 // x += alpha p, r -= alpha q, z = D^-1 r; rho' = r^H z (or r^T z), ||r||^2.
 template <typename T, int S, bool HERM>
 __global__ __launch_bounds__(kBlock) void k_update(
@@ -404,41 +457,42 @@ __global__ __launch_bounds__(kBlock) void k_update(
         if (!__syncthreads_or(act)) continue;
         const LaneCoef<T> lc(gq[sys], lhs);
         const double2 al = act ? s.alpha[sys] : make_double2(0.0, 0.0);
-        const T ar = static_cast<T>(al.x), ai = static_cast<T>(al.y);
         double acc[3] = {0.0, 0.0, 0.0};
-        if (act) {
-            sweep_static<S>(g, part, j, [&](int first, int r1) {
-                int row[kUs];
-                bool ok[kUs];
-                V2<T> pv[kUs], qv[kUs], xv[kUs], rv[kUs];
-#pragma unroll
-                for (int u = 0; u < kUs; ++u) {
-                    row[u] = slot_row<S>(first, u, r1, ok[u]);
-                    const size_t idx = tb + static_cast<size_t>(row[u]) * S;
-                    pv[u] = p[idx];
-                    qv[u] = q[idx];
-                    xv[u] = x[idx];
-                    rv[u] = r[idx];
-                }
-#pragma unroll
-                for (int u = 0; u < kUs; ++u) {
-                    if (!ok[u]) continue;
-                    const size_t idx = tb + static_cast<size_t>(row[u]) * S;
-                    xv[u].x += ar * pv[u].x - ai * pv[u].y;
-                    xv[u].y += ar * pv[u].y + ai * pv[u].x;
-                    rv[u].x -= ar * qv[u].x - ai * qv[u].y;
-                    rv[u].y -= ar * qv[u].y + ai * qv[u].x;
-                    x[idx] = xv[u];
-                    r[idx] = rv[u];
-                    T dr, di;
-                    diag_at(dK0, daux, row[u], lc, dr, di);
-                    dot_acc<HERM, T>(acc[0], acc[1], rv[u], cdivT<T>(rv[u], dr, di));
-                    acc[2] += double(rv[u].x) * rv[u].x + double(rv[u].y) * rv[u].y;
-                }
-            });
-        }
+        if (act)
+            update_item<T, S, HERM>(g, part, j, tb, lc, static_cast<T>(al.x),
+                                    static_cast<T>(al.y), dK0, daux, x, r, p, q, acc);
         reduce_store<S, 3>(g, sc, item, j, acc, lds);
     }
+}
+
+// One item of p = D^-1 r + beta p.
+template <typename T, int S>
+__device__ __forceinline__ void pupdate_item(const Geom& g, int part, int j, size_t tb,
+                                             const LaneCoef<T>& lc, T br, T bi,
+                                             const T* __restrict__ dK0,
+                                             const V4<T>* __restrict__ daux,
+                                             const V2<T>* __restrict__ r, V2<T>* __restrict__ p) {
+    sweep_static<S>(g, part, j, [&](int first, int r1) {
+        int row[kUs];
+        bool ok[kUs];
+        V2<T> rv[kUs], pv[kUs];
+#pragma unroll
+        for (int u = 0; u < kUs; ++u) {
+            row[u] = slot_row<S>(first, u, r1, ok[u]);
+            const size_t idx = tb + static_cast<size_t>(row[u]) * S;
+            rv[u] = r[idx];
+            pv[u] = p[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < kUs; ++u) {
+            if (!ok[u]) continue;
+            T dr, di;
+            diag_at(dK0, daux, row[u], lc, dr, di);
+            const V2<T> z = cdivT<T>(rv[u], dr, di);
+            p[tb + static_cast<size_t>(row[u]) * S] =
+                mk2<T>(z.x + br * pv[u].x - bi * pv[u].y, z.y + br * pv[u].y + bi * pv[u].x);
+        }
+    });
 }
 
 // p = D^-1 r + beta p.
@@ -456,28 +510,231 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(Geom g, const T* __restrict_
         if (!(sys < s.n_sys && s.active[sys])) continue;
         const LaneCoef<T> lc(gq[sys], lhs);
         const double2 be = s.beta[sys];
-        const T br = static_cast<T>(be.x), bi = static_cast<T>(be.y);
-        sweep_static<S>(g, part, j, [&](int first, int r1) {
-            int row[kUs];
-            bool ok[kUs];
-            V2<T> rv[kUs], pv[kUs];
-#pragma unroll
-            for (int u = 0; u < kUs; ++u) {
-                row[u] = slot_row<S>(first, u, r1, ok[u]);
-                const size_t idx = tb + static_cast<size_t>(row[u]) * S;
-                rv[u] = r[idx];
-                pv[u] = p[idx];
+        pupdate_item<T, S>(g, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y), dK0,
+                           daux, r, p);
+    }
+}
+
+// ------------------------------------------------------ persistent solver
+
+constexpr int kMaxPersistSys = 64;
+constexpr long kBarrierSpinLimit = 1L << 21;
+
+// Two-level barrier: the blocks of XCD group x (blockIdx % 8 == x) count on
+// their own counter (count[32 * (x + 1)], one cache line each), the last of
+// each group counts on the global counter count[0], and the last group
+// releases everyone by advancing the generation. Every wait is bounded: a
+// wait that times out sets *err, and every block that sees *err set returns
+// false, so the kernel always terminates.
+__device__ __forceinline__ bool grid_sync(GridBarrier b) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 1;
+        if (__hip_atomic_load(b.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            ok = 0;
+        } else {
+            const uint32_t my =
+                __hip_atomic_load(b.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            const uint32_t grp = blockIdx.x & 7;
+            const uint32_t in_grp = (gridDim.x - grp + 7) / 8;
+            uint32_t* gc = b.count + 32 * (grp + 1);
+            bool released = false;
+            if (atomicAdd(gc, 1u) == in_grp - 1) {
+                __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t groups = gridDim.x < 8 ? gridDim.x : 8;
+                if (atomicAdd(b.count, 1u) == groups - 1) {
+                    __hip_atomic_store(b.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __threadfence();
+                    atomicAdd(b.gen, 1u);
+                    released = true;
+                }
             }
-#pragma unroll
-            for (int u = 0; u < kUs; ++u) {
-                if (!ok[u]) continue;
-                T dr, di;
-                diag_at(dK0, daux, row[u], lc, dr, di);
-                const V2<T> z = cdivT<T>(rv[u], dr, di);
-                p[tb + static_cast<size_t>(row[u]) * S] =
-                    mk2<T>(z.x + br * pv[u].x - bi * pv[u].y, z.y + br * pv[u].y + bi * pv[u].x);
+            if (!released) {
+                long spins = 0;
+                while (__hip_atomic_load(b.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == my) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > kBarrierSpinLimit) {
+                        atomicOr(b.err, 1);
+                        ok = 0;
+                        break;
+                    }
+                    if ((spins & 1023) == 0 &&
+                        __hip_atomic_load(b.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        ok = 0;
+                        break;
+                    }
+                }
             }
-        });
+            __threadfence();
+        }
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// Sum the partials of every system (ld <= 64) in a fixed order; thread t < ld
+// receives the totals of system t. Every block computes the same values.
+template <int S, int K>
+__device__ __forceinline__ void sum_partials(const Geom& g, Scratch sc, double* red,
+                                             double (&tot)[K]) {
+    const int ld = g.ld;
+    const int G = kBlock / ld;
+    const int grp = threadIdx.x / ld, sy = threadIdx.x - grp * ld;
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    if (grp < G) {
+        const int tile = sy / S, sl = sy - tile * S;
+        const int nb = g.n_parts * g.B;
+        const double* base = sc.partial + static_cast<size_t>(tile) * nb * S * 4;
+        for (int i = grp; i < nb; i += G) {
+            const double* pp = base + (static_cast<size_t>(i) * S + sl) * 4;
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] += pp[k];
+        }
+        if (grp < G) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) red[(grp * ld + sy) * K + k] = acc[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < ld) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double t = 0.0;
+            for (int gg = 0; gg < G; ++gg) t += red[(gg * ld + threadIdx.x) * K + k];
+            tot[k] = t;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int S, bool HERM>
+__global__ __launch_bounds__(kBlock) void k_krylov_persistent(
+    Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const T* __restrict__ K0, const V4<T>* __restrict__ aux, const T* __restrict__ dK0,
+    const V4<T>* __restrict__ daux, const double4* __restrict__ gq, Coef lhs,
+    V2<T>* __restrict__ x, V2<T>* __restrict__ r, V2<T>* __restrict__ p, V2<T>* __restrict__ q,
+    SolverState s, Scratch sc, GridBarrier bar) {
+    __shared__ double2 sh_rho[kMaxPersistSys], sh_alpha[kMaxPersistSys], sh_beta[kMaxPersistSys];
+    __shared__ double sh_bb[kMaxPersistSys], sh_rr[kMaxPersistSys];
+    __shared__ int sh_act[kMaxPersistSys], sh_it[kMaxPersistSys], sh_flag[kMaxPersistSys];
+    __shared__ int sh_any;
+    __shared__ double lds[kWaves * S * 3];
+    __shared__ double red[kBlock * 3];
+    const int ld = g.ld;
+    // Separate partial buffers for the two reductions of an iteration: a block
+    // may start writing phase-B partials while another still reads phase A's.
+    Scratch scA = sc, scB = sc;
+    scB.partial = sc.partial + static_cast<size_t>(g.n_items) * g.B * S * 4;
+    for (int t = threadIdx.x; t < ld; t += kBlock) {
+        const bool real = t < s.n_sys;
+        sh_rho[t] = real ? s.rho[t] : make_double2(0.0, 0.0);
+        sh_bb[t] = real ? s.bb[t] : 0.0;
+        sh_rr[t] = real ? s.rr[t] : 0.0;
+        sh_act[t] = real ? s.active[t] : 0;
+        sh_it[t] = 0;
+        sh_flag[t] = 0;
+        sh_alpha[t] = make_double2(0.0, 0.0);
+        sh_beta[t] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int it = 0; it <= s.max_iter; ++it) {
+        // Phase A: q = A p, sigma partials.
+        for (int item = xcd; item < g.n_items; item += 8) {
+            const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+            const int sys = tile * S + (threadIdx.x & 63) % S;
+            const size_t tb = vbase(g, tile, S, sys);
+            const bool act = sh_act[sys] != 0;
+            if (!__syncthreads_or(act)) continue;
+            const LaneCoef<T> lc(gq[sys], lhs);
+            double acc[2] = {0.0, 0.0};
+            spmv_item<T, S, HERM>(g, part, j, nullptr, act, tb, lc, row_ptr, col, K0, aux, p, q,
+                                  acc);
+            reduce_store<S, 2>(g, scA, item, j, acc, lds);
+        }
+        if (!grid_sync(bar)) break;
+        {
+            double tot[2];
+            sum_partials<S, 2>(g, scA, red, tot);
+            if (threadIdx.x < ld && sh_act[threadIdx.x])
+                sh_alpha[threadIdx.x] = cdiv(sh_rho[threadIdx.x], make_double2(tot[0], tot[1]));
+            __syncthreads();
+        }
+        // Phase B: x, r update; rho', ||r||^2 partials.
+        for (int item = xcd; item < g.n_items; item += 8) {
+            const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+            const int sys = tile * S + (threadIdx.x & 63) % S;
+            const size_t tb = vbase(g, tile, S, sys);
+            const bool act = sh_act[sys] != 0;
+            if (!__syncthreads_or(act)) continue;
+            const LaneCoef<T> lc(gq[sys], lhs);
+            const double2 al = sh_alpha[sys];
+            double acc[3] = {0.0, 0.0, 0.0};
+            if (act)
+                update_item<T, S, HERM>(g, part, j, tb, lc, static_cast<T>(al.x),
+                                        static_cast<T>(al.y), dK0, daux, x, r, p, q, acc);
+            reduce_store<S, 3>(g, scB, item, j, acc, lds);
+        }
+        if (!grid_sync(bar)) break;
+        {
+            double tot[3];
+            sum_partials<S, 3>(g, scB, red, tot);
+            if (threadIdx.x == 0) sh_any = 0;
+            __syncthreads();
+            if (threadIdx.x < ld && sh_act[threadIdx.x]) {
+                const int sy = threadIdx.x;
+                const double2 rho_new = make_double2(tot[0], tot[1]);
+                const double rr = tot[2];
+                sh_rr[sy] = rr;
+                sh_it[sy] += 1;
+                bool stop = false;
+                if (!isfinite(rr) || !isfinite(rho_new.x) || !isfinite(rho_new.y)) {
+                    sh_flag[sy] |= 2;
+                    stop = true;
+                } else if (rr <= s.rtol2 * sh_bb[sy]) {
+                    stop = true;
+                } else if (sh_it[sy] >= s.max_iter) {
+                    sh_flag[sy] |= 1;
+                    stop = true;
+                }
+                if (stop) {
+                    sh_act[sy] = 0;
+                } else {
+                    sh_beta[sy] = cdiv(rho_new, sh_rho[sy]);
+                    sh_rho[sy] = rho_new;
+                    sh_any = 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (!sh_any) break;
+        // Phase C: p = z + beta p.
+        for (int item = xcd; item < g.n_items; item += 8) {
+            const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+            const int sys = tile * S + (threadIdx.x & 63) % S;
+            const size_t tb = vbase(g, tile, S, sys);
+            if (!sh_act[sys]) continue;
+            const LaneCoef<T> lc(gq[sys], lhs);
+            const double2 be = sh_beta[sys];
+            pupdate_item<T, S>(g, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y),
+                               dK0, daux, r, p);
+        }
+        if (!grid_sync(bar)) break;
+    }
+    if (blockIdx.x == 0) {
+        for (int t = threadIdx.x; t < s.n_sys; t += kBlock) {
+            s.rho[t] = sh_rho[t];
+            s.rr[t] = sh_rr[t];
+            s.active[t] = 0;
+            s.iters[t] = sh_it[t];
+            s.iters_total[t] += sh_it[t];
+            s.flags[t] |= sh_flag[t];
+        }
+        for (int t = threadIdx.x; t < g.n_tiles; t += kBlock) s.n_active[t] = 0;
     }
 }
 
@@ -967,6 +1224,24 @@ void launch_update(hipStream_t st, const Geom& g, const MatView<T>& A, const dou
 }
 
 template <typename T>
+void launch_krylov_persistent(hipStream_t st, const Geom& g, const MatView<T>& A,
+                              const double4* gq, Coef lhs, bool herm, V2<T>* x, V2<T>* r,
+                              V2<T>* p, V2<T>* q, SolverState s, Scratch sc, GridBarrier bar) {
+    if (g.ld > kMaxPersistSys || g.queue)
+        throw std::runtime_error("persistent solver needs <= 64 systems and static chunks");
+    const dim3 grid = grid_of(g), block(kBlock);
+    DMRI_DISPATCH_S(g.S, {
+        if (herm)
+            k_krylov_persistent<T, S, true><<<grid, block, 0, st>>>(
+                g, A.row_ptr, A.col, A.K0, A.aux, A.dK0, A.daux, gq, lhs, x, r, p, q, s, sc, bar);
+        else
+            k_krylov_persistent<T, S, false><<<grid, block, 0, st>>>(
+                g, A.row_ptr, A.col, A.K0, A.aux, A.dK0, A.daux, gq, lhs, x, r, p, q, s, sc, bar);
+    });
+    check_launch("krylov_persistent");
+}
+
+template <typename T>
 void launch_pupdate(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
                     Coef lhs, const V2<T>* r, V2<T>* p, SolverState s) {
     const dim3 grid = grid_of(g), block(kBlock);
@@ -1033,7 +1308,11 @@ void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
     template void launch_apply<T>(hipStream_t, const Geom&, const MatView<T>&, int,            \
                                   const double*, const double3*, const V2<T>*, V2<T>*);        \
     template void launch_set_initial<T>(hipStream_t, const Geom&, const double*, int32_t,      \
-                                        V2<T>*);
+                                        V2<T>*);                                               \
+    template void launch_krylov_persistent<T>(hipStream_t, const Geom&, const MatView<T>&,     \
+                                              const double4*, Coef, bool, V2<T>*, V2<T>*,      \
+                                              V2<T>*, V2<T>*, SolverState, Scratch,            \
+                                              GridBarrier);
 
 DMRI_INST(double)
 DMRI_INST(float)

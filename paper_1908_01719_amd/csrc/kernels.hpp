@@ -163,6 +163,26 @@ void launch_set_initial(hipStream_t st, const Geom& g, const double* u0, int32_t
 void launch_sys_params(hipStream_t st, int32_t n_sys, int32_t ld, const double* b,
                        const double* q, double int_F2, double4* gq, int32_t* bad);
 
+// Grid-wide barrier state for the persistent solver (zero-initialised once).
+struct GridBarrier {
+    uint32_t* count;  // [32 * 9]: global counter at 0, XCD-group counters at 32*(x+1)
+    uint32_t* gen;
+    int32_t* err;     // set to 1 if a barrier wait timed out
+};
+
+// Krylov iterations of one step in a single launch of 8 * g.B blocks, all of
+// which must be co-resident (the host sizes g.B from the CU count). The
+// per-system scalars are recomputed redundantly in every block from the
+// partials after each grid barrier, so a batch may hold at most 64 systems
+// (g.ld <= 64). Requires g.queue == 0 and a partial buffer of twice the
+// usual size (2 * n_items * B * S * 4 doubles).
+template <typename T>
+void launch_krylov_persistent(hipStream_t st, const Geom& g, const MatView<T>& A,
+                              const double4* gq, Coef lhs, bool herm,
+                              typename Vec2Of<T>::type* x, typename Vec2Of<T>::type* r,
+                              typename Vec2Of<T>::type* p, typename Vec2Of<T>::type* q,
+                              SolverState s, Scratch sc, GridBarrier bar);
+
 // Zero n int32 values (a kernel, so it may be captured in a graph).
 void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n);
 

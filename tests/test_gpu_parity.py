@@ -268,3 +268,24 @@ def test_orderings_agree(Sim, ordering):
         pid = sim.add_problem(prob)
         sig, _ = sim.dmri_run([pid] * 5, b[:5], q[:5])
     assert rel_err(sig, ref, ref[0]).max() < 1e-9
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_solver_matches_oracle(Sim, precision):
+    # One launch per Krylov solve with grid barriers; the same signals as the
+    # oracle and as the chunked multi-launch loop.
+    prob, b, q = _cyl_case()
+    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    out = {}
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        for persist in (0, 1):
+            sim.set_options(rtol=1e-12, precision=precision, persistent=persist)
+            out[persist], st = sim.dmri_run([pid] * len(b), b, q)
+            assert st["status"] == "DMRI_OK"
+    for persist in (0, 1):
+        err = rel_err(out[persist], ref, ref[0])
+        _say("persistent=%d precision=%d max err %.2e" % (persist, precision, err.max()))
+        assert err.max() < 1e-9
+    assert np.abs(out[0] - out[1]).max() < 1e-10 * abs(ref[0])
