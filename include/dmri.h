@@ -155,7 +155,8 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *  "inner_rtol" FP32 inner solve reduction in mixed precision (1e-4)
  *  "max_iter"   Krylov iterations per step and system (default 2000)
  *  "guess"      0 = previous step, 1 = linear extrapolation (default),
- *               2 = learned correction (needs dmri_load_guess_model)
+ *               2 = learned correction of the extrapolation (needs
+ *               network parameters; precision 0 or 1)
  *  "sys_tile"   systems per lane group: 0 = auto, or 8, 16, 32, 64
  *  "graph"      1 = replay chunks of Krylov iterations from a HIP graph
  *  "autotune"   1 = time the tile candidates on the first step and keep the
@@ -187,10 +188,60 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
 dmri_status dmri_set_option(dmri_handle h, const char* key, double value);
 dmri_status dmri_get_option(dmri_handle h, const char* key, double* value);
 
-/* Load the weights of the learned initial-guess network from a file written
- * by the Python training driver (little-endian float32 blob with a header).
- * Used when option "guess" = 2. */
+/* ---- Learned initial guess (option "guess" = 2) ----------------------
+ * A per-element network corrects the linear extrapolation of the next time
+ * step's solution (the theta-scheme of Appendix A marches u^{n-1} -> u^n;
+ * the network only moves the Krylov starting point, the solve and its
+ * stopping test are unchanged). For element (DOF i, system s) the inputs are
+ * 16 features: relative first difference (u^{n-1} - u^{n-2}) / |u^{n-1}| and
+ * phase u^{n-1} / |u^{n-1}| (Re, Im), the changes of G F(t) over the last two
+ * steps (x10), G F(t^n), dt D (G F)^2 at t^n and t^{n-1}, (q . x) / 10 with x
+ * from the box centre in um, compartment index, membrane flag, zeros. The
+ * network 16 -> 64 -> 64 -> 2 (ReLU) predicts 100 (u^n - (2u^{n-1} - u^{n-2}))
+ * / |u^{n-1}| (Re, Im; recorded targets clipped to [-100, 100]). Layers run as BF16 matrix-core products with FP32
+ * accumulation; the parameters are FP32, packed W1[16][64], b1[64],
+ * W2[64][64], b2[64], W3[64][2], b3[2] (row-major, x W + b). Non-finite
+ * predictions fall back to u^{n-1} element by element. */
+#define DMRI_GUESS_N_FEATURES 16
+#define DMRI_GUESS_N_PARAMS 5378
+
+/* Set the network parameters from host memory (n_params must equal
+ * DMRI_GUESS_N_PARAMS); restarts the Adam moments. */
+dmri_status dmri_guess_set_params(dmri_handle h, const float* params, int64_t n_params);
+/* Copy the current parameters to host memory. DMRI_E_STATE if none set. */
+dmri_status dmri_guess_get_params(dmri_handle h, float* params, int64_t n_params);
+/* Load / save parameters as a file: 8 bytes "DMRIMLP1", int32 16, 64, 2,
+ * then DMRI_GUESS_N_PARAMS little-endian float32. A wrong header gives
+ * DMRI_E_INVALID. */
 dmri_status dmri_load_guess_model(dmri_handle h, const char* path);
+dmri_status dmri_save_guess_model(dmri_handle h, const char* path);
+
+/* Record training samples during later dmri_run / dmri_run_device calls:
+ * at every step n >= 2, every stride-th element of the batch (a different
+ * offset each step) appends its features to d_features ([capacity][16]
+ * float32, device) and its target to d_targets ([capacity][2] float32,
+ * device) until capacity samples are held; capacity = 0 stops recording.
+ * The buffers are the caller's and must stay valid while recording is on.
+ * Resets the sample count. Recording needs precision 0 or 1. */
+dmri_status dmri_guess_record(dmri_handle h, float* d_features, float* d_targets,
+                              int64_t capacity, int64_t stride);
+/* Samples recorded so far (<= capacity). */
+dmri_status dmri_guess_record_count(dmri_handle h, int64_t* count);
+
+/* Evaluate the network on n samples (device buffers): outputs d_out[n][2]
+ * (may be NULL), the gradient of the mean squared error
+ * L = sum((y - t)^2) / n with respect to the packed parameters into
+ * d_grad[DMRI_GUESS_N_PARAMS] (may be NULL) and L into *loss (may be NULL).
+ * Gradient and loss need d_targets. Returns after the results are written. */
+dmri_status dmri_guess_eval(dmri_handle h, int64_t n, const float* d_features,
+                            const float* d_targets, float* d_out, float* d_grad, double* loss);
+/* n_iters full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, step
+ * size lr) on the mean squared error over n device samples. *loss_first is
+ * L before the first step, *loss_last L before the last step (either may be
+ * NULL). */
+dmri_status dmri_guess_train(dmri_handle h, int64_t n, const float* d_features,
+                             const float* d_targets, int32_t n_iters, double lr,
+                             double* loss_first, double* loss_last);
 
 /* Simulate n_pairs (problem, b, direction) systems and write their signals.
  *   problem_id [n_pairs] ids from dmri_add_problem

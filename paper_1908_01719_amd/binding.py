@@ -29,8 +29,14 @@ STATUS_NAMES = {
 EXPORTED = [
     "dmri_create", "dmri_destroy", "dmri_last_error", "dmri_add_problem", "dmri_problem_info",
     "dmri_export_operator", "dmri_set_sequence_pgse", "dmri_set_option", "dmri_get_option",
-    "dmri_load_guess_model", "dmri_run", "dmri_run_device", "dmri_apply_operator",
+    "dmri_run", "dmri_run_device", "dmri_apply_operator",
+    "dmri_guess_set_params", "dmri_guess_get_params", "dmri_load_guess_model",
+    "dmri_save_guess_model", "dmri_guess_record", "dmri_guess_record_count", "dmri_guess_eval",
+    "dmri_guess_train",
 ]
+
+GUESS_N_FEATURES = 16
+GUESS_N_PARAMS = 5378
 
 
 class DmriError(RuntimeError):
@@ -84,7 +90,14 @@ def load(path: Optional[str] = None):
     lib.dmri_set_sequence_pgse.argtypes = [vp, dbl, dbl, dbl, dbl]
     lib.dmri_set_option.argtypes = [vp, C.c_char_p, dbl]
     lib.dmri_get_option.argtypes = [vp, C.c_char_p, P(dbl)]
+    lib.dmri_guess_set_params.argtypes = [vp, vp, i64]
+    lib.dmri_guess_get_params.argtypes = [vp, vp, i64]
     lib.dmri_load_guess_model.argtypes = [vp, C.c_char_p]
+    lib.dmri_save_guess_model.argtypes = [vp, C.c_char_p]
+    lib.dmri_guess_record.argtypes = [vp, vp, vp, i64, i64]
+    lib.dmri_guess_record_count.argtypes = [vp, P(i64)]
+    lib.dmri_guess_eval.argtypes = [vp, i64, vp, vp, vp, vp, P(dbl)]
+    lib.dmri_guess_train.argtypes = [vp, i64, vp, vp, i32, dbl, P(dbl), P(dbl)]
     lib.dmri_run.argtypes = [vp, i64, vp, vp, vp, vp, P(Stats)]
     lib.dmri_run_device.argtypes = [vp, vp, i32, i64, vp, vp, vp, P(Stats)]
     lib.dmri_apply_operator.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
@@ -202,8 +215,67 @@ class Simulator:
         for k, v in kw.items():
             self.dmri_set_option(k, v)
 
+    # -- learned initial guess -----------------------------------------------
+    def dmri_guess_set_params(self, params):
+        p = _c(params, np.float32).reshape(-1)
+        self._check(self.lib.dmri_guess_set_params(self.h, _ptr(p), p.shape[0]))
+
+    def dmri_guess_get_params(self) -> np.ndarray:
+        p = np.empty(GUESS_N_PARAMS, np.float32)
+        self._check(self.lib.dmri_guess_get_params(self.h, _ptr(p), p.shape[0]))
+        return p
+
     def dmri_load_guess_model(self, path: str):
         self._check(self.lib.dmri_load_guess_model(self.h, os.fsencode(path)))
+
+    def dmri_save_guess_model(self, path: str):
+        self._check(self.lib.dmri_save_guess_model(self.h, os.fsencode(path)))
+
+    def dmri_guess_record(self, features_dev, targets_dev, capacity: int, stride: int):
+        """Record samples into torch float32 CUDA tensors [capacity, 16] and
+        [capacity, 2] during later runs (capacity 0 stops recording)."""
+        if capacity > 0:
+            _dev_f32(features_dev, (capacity, GUESS_N_FEATURES))
+            _dev_f32(targets_dev, (capacity, 2))
+        self._check(self.lib.dmri_guess_record(
+            self.h, _dptr(features_dev) if capacity > 0 else None,
+            _dptr(targets_dev) if capacity > 0 else None, int(capacity), int(stride)))
+
+    def dmri_guess_record_count(self) -> int:
+        n = C.c_int64()
+        self._check(self.lib.dmri_guess_record_count(self.h, C.byref(n)))
+        return n.value
+
+    def dmri_guess_eval(self, features_dev, targets_dev=None, out_dev=None, grad_dev=None,
+                        want_loss: bool = True):
+        """Network outputs / loss gradient / loss on n device samples."""
+        n = int(features_dev.shape[0])
+        _dev_f32(features_dev, (n, GUESS_N_FEATURES))
+        if targets_dev is not None:
+            _dev_f32(targets_dev, (n, 2))
+        if out_dev is not None:
+            _dev_f32(out_dev, (n, 2))
+        if grad_dev is not None:
+            _dev_f32(grad_dev, (GUESS_N_PARAMS,))
+        loss = C.c_double(float("nan"))
+        _sync(features_dev)
+        self._check(self.lib.dmri_guess_eval(
+            self.h, n, _dptr(features_dev), _dptr(targets_dev), _dptr(out_dev), _dptr(grad_dev),
+            C.byref(loss) if want_loss and targets_dev is not None else None))
+        return loss.value
+
+    def dmri_guess_train(self, features_dev, targets_dev, n_iters: int, lr: float, n=None):
+        """Full-batch Adam steps; returns (loss before the first, before the last step)."""
+        n = int(features_dev.shape[0]) if n is None else int(n)
+        _dev_f32(features_dev, None)
+        _dev_f32(targets_dev, None)
+        if n > features_dev.shape[0] or n > targets_dev.shape[0]:
+            raise ValueError("n exceeds the sample buffers")
+        l0, l1 = C.c_double(), C.c_double()
+        _sync(features_dev)
+        self._check(self.lib.dmri_guess_train(self.h, n, _dptr(features_dev), _dptr(targets_dev),
+                                              int(n_iters), float(lr), C.byref(l0), C.byref(l1)))
+        return l0.value, l1.value
 
     # -- runs ---------------------------------------------------------------
     def dmri_run(self, problem_id: Sequence[int], b, q, want_stats: bool = True):
@@ -252,6 +324,25 @@ class Simulator:
         self._check(self.lib.dmri_apply_operator(self.h, int(pid), int(which), ns, _ptr(c),
                                                  _ptr(d), _ptr(xr), _ptr(y)))
         return y[..., 0] + 1j * y[..., 1]
+
+
+def _dptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_f32(t, shape):
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (shape, tuple(t.shape)))
+
+
+def _sync(t):
+    """Finish torch's pending work on the tensor's device: the library runs on
+    its own stream."""
+    import torch
+    torch.cuda.current_stream(t.device).synchronize()
 
 
 def _stats_dict(st, iters, conv, rres, status):

@@ -445,7 +445,11 @@ HostOperator assemble(const MeshInput& in) {
     }
     op.interface_area = area_total;
     op.u0.resize(nD);
-    for (int64_t dd = 0; dd < nD; ++dd) op.u0[dd] = in.u0 ? in.u0[op.dof_comp[dd]] : 1.0;
+    op.dof_D.resize(nD);
+    for (int64_t dd = 0; dd < nD; ++dd) {
+        op.u0[dd] = in.u0 ? in.u0[op.dof_comp[dd]] : 1.0;
+        op.dof_D[dd] = static_cast<float>(in.D[op.dof_comp[dd]]);
+    }
     op.volume = 0.0;
     for (double v : op.comp_volume) op.volume += v;
     return op;

@@ -71,6 +71,7 @@ struct HostOperator {
     // Extra per-DOF geometry used by the learned guess features.
     std::vector<float> dof_xyz;      // [n_dof][3] position relative to box centre
     std::vector<float> dof_membrane; // [n_dof] 1 if the node also belongs to another compartment
+    std::vector<float> dof_D;        // [n_dof] diffusivity of the DOF's compartment
 };
 
 // Validate the input and assemble. Throws dmri::Error.

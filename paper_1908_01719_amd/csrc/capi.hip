@@ -27,6 +27,7 @@
 #include "../../include/dmri.h"
 #include "assembly.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 
 namespace dmri {
 namespace {
@@ -89,6 +90,10 @@ struct ProblemRec {
     // a padded entry to its stored entry (-1 for padding).
     std::vector<int32_t> pad_row_ptr, pad_col;
     std::vector<int64_t> pad_src;
+    // Per-DOF inputs of the learned-guess features (uploaded on first use).
+    DevBuf<float4> feat_geo;
+    DevBuf<float2> feat_flags;
+    bool feat_up = false;
 };
 
 void build_padded(ProblemRec& P) {
@@ -211,6 +216,18 @@ struct Workspace {
     }
 };
 
+// Learned-guess network: FP32 parameters, Adam moments, gradient scratch,
+// and the sample recorder registered by dmri_guess_record.
+struct GuessModel {
+    DevBuf<float> theta, adam_m, adam_v, grad, partial, loss_hist;
+    int adam_t = 0;
+    bool set = false;
+    float* rec_X = nullptr;
+    float* rec_T = nullptr;
+    int64_t rec_cap = 0, rec_count = 0;
+    int64_t rec_stride = 1;
+};
+
 }  // namespace
 }  // namespace dmri
 
@@ -225,6 +242,7 @@ struct dmri_ctx {
     int n_steps = 0;
     dmri::Options opt;
     dmri::Workspace ws;
+    dmri::GuessModel model;
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> tpool;  // timing events, reused across runs
 };
@@ -340,6 +358,75 @@ void step_tables(const dmri_ctx* h, std::vector<double>& F, std::vector<double>&
             f[n] = (tm <= h->delta) ? 1.0 : ((tm > h->Delta && tm <= h->Delta + h->delta) ? -1.0 : 0.0);
         }
     }
+}
+
+// Learned-guess inputs of step n (n >= 2): F (or f) at the last three
+// levels and the step length.
+MlpStep mlp_step(const dmri_ctx* h, bool tr, const std::vector<double>& F,
+                 const std::vector<double>& f, int n) {
+    const std::vector<double>& v = tr ? F : f;
+    return MlpStep{v[n], v[n - 1], v[n - 2], h->dt};
+}
+
+MlpDofs ensure_features(dmri_ctx* h, ProblemRec& P) {
+    if (!P.feat_up) {
+        const HostOperator& op = P.op;
+        const size_t n = static_cast<size_t>(op.n_dof);
+        std::vector<float4> geo(n);
+        std::vector<float2> fl(n);
+        for (size_t i = 0; i < n; ++i) {
+            geo[i] = make_float4(op.dof_xyz[3 * i], op.dof_xyz[3 * i + 1], op.dof_xyz[3 * i + 2],
+                                 op.dof_D[i]);
+            fl[i] = make_float2(static_cast<float>(op.dof_comp[i]), op.dof_membrane[i]);
+        }
+        P.feat_geo.upload(geo.data(), n, h->stream);
+        P.feat_flags.upload(fl.data(), n, h->stream);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        P.feat_up = true;
+    }
+    return MlpDofs{P.feat_geo.p, P.feat_flags.p};
+}
+
+// Guess mode of step n; for the learned guess the network's prediction is
+// written to x first and k_init then starts from x (mode 2).
+int prepare_guess(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
+                  const std::vector<double>& F, const std::vector<double>& f, int n,
+                  int64_t n_sys, const double2* u1, const double2* u2, double2* x) {
+    if (n < 2 || h->opt.guess == 0) return 0;
+    if (h->opt.guess == 1) return 1;
+    launch_mlp_guess(h->stream, g, h->model.theta.p, dofs, h->ws.gq.p, mlp_step(h, tr, F, f, n),
+                     static_cast<int32_t>(n_sys), u1, u2, x);
+    return 2;
+}
+
+// Append training samples of step n (u1 = u^{n-1}, u2 = u^{n-2}, un = u^n)
+// while the registered recorder has room.
+void record_samples(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
+                    const std::vector<double>& F, const std::vector<double>& f, int n,
+                    int64_t n_sys, const double2* u1, const double2* u2, const double2* un) {
+    GuessModel& M = h->model;
+    if (n < 2 || M.rec_cap <= 0 || M.rec_count >= M.rec_cap) return;
+    const int64_t nv = static_cast<int64_t>(g.n_rows) * g.ld;
+    const int64_t offset = static_cast<int64_t>((static_cast<uint64_t>(n) * 2654435761u) %
+                                                static_cast<uint64_t>(M.rec_stride));
+    if (offset >= nv) return;
+    const int64_t cnt = (nv - offset + M.rec_stride - 1) / M.rec_stride;
+    launch_mlp_record(h->stream, g, dofs, h->ws.gq.p, mlp_step(h, tr, F, f, n),
+                      static_cast<int32_t>(n_sys), u1, u2, un, M.rec_stride, offset, M.rec_count,
+                      M.rec_cap, M.rec_X, M.rec_T);
+    M.rec_count = std::min(M.rec_cap, M.rec_count + cnt);
+}
+
+void check_guess_setup(dmri_ctx* h, bool fp64_vectors) {
+    const bool rec = h->model.rec_cap > 0;
+    if (h->opt.guess == 2 && !h->model.set)
+        throw Error(DMRI_E_STATE,
+                    "guess = 2 needs network parameters (dmri_guess_set_params or "
+                    "dmri_load_guess_model)");
+    if ((h->opt.guess == 2 || rec) && !fp64_vectors)
+        throw Error(DMRI_E_UNSUPPORTED,
+                    "the learned guess and sample recording need FP64 solution vectors "
+                    "(precision 0 or 1)");
 }
 
 struct BatchResult {
@@ -589,13 +676,21 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     const bool tr = P.op.form == FORM_TRANSFORMED;
     const int N = h->opt.n_steps > 0 ? std::min(h->opt.n_steps, h->n_steps) : h->n_steps;
 
+    constexpr bool kF64 = sizeof(T) == 8;
+    check_guess_setup(h, kF64);
+    const bool learn = h->opt.guess == 2 || h->model.rec_cap > 0;
+    const MlpDofs dofs = learn ? ensure_features(h, P) : MlpDofs{nullptr, nullptr};
+
     KernelTimer timer(h, st, h->opt.time_kernel);
     const double t0 = now_s();
     int cur = 0, prev2 = 1, nxt = 2;  // indices into bufs: u_prev, u_prev2, x
     int last_iters = 8;
     for (int n = 1; n <= N; ++n) {
         const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
-        const int gm = (h->opt.guess == 1 && n >= 2) ? 1 : 0;
+        int gm = (h->opt.guess == 1 && n >= 2) ? 1 : 0;
+        if constexpr (kF64) {
+            gm = prepare_guess(h, g, dofs, tr, F, f, n, n_sys, bufs[cur], bufs[prev2], bufs[nxt]);
+        }
         timer.run(4, [&] {
             launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, bs.herm, gm, bufs[cur], bufs[prev2],
                            bufs[nxt], r, p, nullptr, nullptr, s, bs.sc);
@@ -603,6 +698,9 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
         const int done = krylov_loop<T>(h, bs, Av, W.gq.p, lhs, bufs[nxt], r, p, q, s, timer,
                                         last_iters - 2, h->opt.max_iter);
         last_iters = done;
+        if constexpr (kF64) {
+            record_samples(h, g, dofs, tr, F, f, n, n_sys, bufs[cur], bufs[prev2], bufs[nxt]);
+        }
         progress_line(h, n, N, done, t0);
         const int old_prev2 = prev2;
         prev2 = cur;
@@ -660,6 +758,9 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     const bool tr = P.op.form == FORM_TRANSFORMED;
     const int N = h->opt.n_steps > 0 ? std::min(h->opt.n_steps, h->n_steps) : h->n_steps;
     std::vector<int32_t> flag_or(n_sys, 0);
+    check_guess_setup(h, true);
+    const bool learn = h->opt.guess == 2 || h->model.rec_cap > 0;
+    const MlpDofs dofs = learn ? ensure_features(h, P) : MlpDofs{nullptr, nullptr};
 
     KernelTimer timer(h, st, h->opt.time_kernel);
     const double t0 = now_s();
@@ -667,7 +768,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     int last_first_pass = 8;
     for (int n = 1; n <= N; ++n) {
         const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
-        const int gm = (h->opt.guess == 1 && n >= 2) ? 1 : 0;
+        const int gm = prepare_guess(h, g, dofs, tr, F, f, n, n_sys, U[cur], U[prev2], U[xi]);
         timer.run(4, [&] {
             launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, gm, U[cur], U[prev2], U[xi],
                                 r64, p64, nullptr, nullptr, so, bs.sc);
@@ -696,6 +797,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
             for (int64_t i = 0; i < n_sys; ++i)
                 if (act[i]) flag_or[i] |= 1;
         }
+        record_samples(h, g, dofs, tr, F, f, n, n_sys, U[cur], U[prev2], U[xi]);
         progress_line(h, n, N, step_iters, t0);
         const int old_prev2 = prev2;
         prev2 = cur;
@@ -782,6 +884,35 @@ ProblemRec& get_problem(dmri_ctx* h, int32_t id) {
 
 void need_sequence(dmri_ctx* h) {
     if (!h->seq_set) throw Error(DMRI_E_STATE, "no sequence: call dmri_set_sequence_pgse first");
+}
+
+constexpr char kModelMagic[8] = {'D', 'M', 'R', 'I', 'M', 'L', 'P', '1'};
+
+// New parameters; the Adam moments restart from zero.
+void set_guess_params(dmri_ctx* h, const float* host_theta) {
+    GuessModel& M = h->model;
+    hipStream_t st = h->stream;
+    M.theta.alloc(kMlpParams);
+    M.adam_m.alloc(kMlpParams);
+    M.adam_v.alloc(kMlpParams);
+    M.grad.alloc(kMlpParams + 1);
+    HIPCHK(hipMemcpyAsync(M.theta.p, host_theta, sizeof(float) * kMlpParams,
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(M.adam_m.p, 0, sizeof(float) * kMlpParams, st));
+    HIPCHK(hipMemsetAsync(M.adam_v.p, 0, sizeof(float) * kMlpParams, st));
+    HIPCHK(hipStreamSynchronize(st));
+    M.adam_t = 0;
+    M.set = true;
+}
+
+// Gradient and loss of the current parameters over n samples into M.grad.
+void grad_pass(dmri_ctx* h, int64_t n, const float* X, const float* T) {
+    GuessModel& M = h->model;
+    int n_cu = 0;
+    HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
+    const int waves = std::max(4, 4 * n_cu);  // one block of four waves per CU
+    M.partial.alloc(static_cast<size_t>(waves) * (kMlpParams + 1));
+    launch_mlp_grad(h->stream, n, X, T, M.theta.p, M.partial.p, waves, M.grad.p);
 }
 
 }  // namespace
@@ -1009,11 +1140,163 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
     });
 }
 
+dmri_status dmri_guess_set_params(dmri_handle h, const float* params, int64_t n_params) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        if (!params || n_params != kMlpParams)
+            throw Error(DMRI_E_INVALID, "params must hold DMRI_GUESS_N_PARAMS floats");
+        set_guess_params(h, params);
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_guess_get_params(dmri_handle h, float* params, int64_t n_params) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        if (!params || n_params != kMlpParams)
+            throw Error(DMRI_E_INVALID, "params must hold DMRI_GUESS_N_PARAMS floats");
+        if (!h->model.set) throw Error(DMRI_E_STATE, "no guess network parameters set");
+        HIPCHK(hipMemcpyAsync(params, h->model.theta.p, sizeof(float) * kMlpParams,
+                              hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return DMRI_OK;
+    });
+}
+
 dmri_status dmri_load_guess_model(dmri_handle h, const char* path) {
     if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
     return guarded(h, [&]() -> dmri_status {
-        (void)path;
-        throw Error(DMRI_E_UNSUPPORTED, "learned guess model not built yet");
+        need_device(h);
+        if (!path) throw Error(DMRI_E_INVALID, "NULL path");
+        std::FILE* fp = std::fopen(path, "rb");
+        if (!fp) throw Error(DMRI_E_INVALID, std::string("cannot open ") + path);
+        char magic[8];
+        int32_t dims[3];
+        std::vector<float> theta(kMlpParams);
+        const bool ok = std::fread(magic, 1, 8, fp) == 8 && std::fread(dims, 4, 3, fp) == 3 &&
+                        std::fread(theta.data(), 4, kMlpParams, fp) ==
+                            static_cast<size_t>(kMlpParams);
+        std::fclose(fp);
+        if (!ok || std::memcmp(magic, kModelMagic, 8) != 0 || dims[0] != kMlpIn ||
+            dims[1] != kMlpHid || dims[2] != kMlpOut)
+            throw Error(DMRI_E_INVALID, std::string("not a guess-network file: ") + path);
+        set_guess_params(h, theta.data());
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_save_guess_model(dmri_handle h, const char* path) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        if (!path) throw Error(DMRI_E_INVALID, "NULL path");
+        if (!h->model.set) throw Error(DMRI_E_STATE, "no guess network parameters set");
+        std::vector<float> theta(kMlpParams);
+        HIPCHK(hipMemcpyAsync(theta.data(), h->model.theta.p, sizeof(float) * kMlpParams,
+                              hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        std::FILE* fp = std::fopen(path, "wb");
+        if (!fp) throw Error(DMRI_E_INVALID, std::string("cannot create ") + path);
+        const int32_t dims[3] = {kMlpIn, kMlpHid, kMlpOut};
+        const bool ok = std::fwrite(kModelMagic, 1, 8, fp) == 8 && std::fwrite(dims, 4, 3, fp) == 3 &&
+                        std::fwrite(theta.data(), 4, kMlpParams, fp) ==
+                            static_cast<size_t>(kMlpParams);
+        const bool closed = std::fclose(fp) == 0;
+        if (!ok || !closed) throw Error(DMRI_E_INVALID, std::string("write failed: ") + path);
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_guess_record(dmri_handle h, float* d_features, float* d_targets,
+                              int64_t capacity, int64_t stride) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        if (capacity < 0 || stride < 1) throw Error(DMRI_E_INVALID, "need capacity >= 0, stride >= 1");
+        if (capacity > 0 && (!d_features || !d_targets))
+            throw Error(DMRI_E_INVALID, "NULL sample buffer");
+        GuessModel& M = h->model;
+        M.rec_X = capacity > 0 ? d_features : nullptr;
+        M.rec_T = capacity > 0 ? d_targets : nullptr;
+        M.rec_cap = capacity;
+        M.rec_stride = stride;
+        M.rec_count = 0;
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_guess_record_count(dmri_handle h, int64_t* count) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        if (!count) throw Error(DMRI_E_INVALID, "NULL argument");
+        *count = h->model.rec_count;
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_guess_eval(dmri_handle h, int64_t n, const float* d_features,
+                            const float* d_targets, float* d_out, float* d_grad, double* loss) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        if (!h->model.set) throw Error(DMRI_E_STATE, "no guess network parameters set");
+        if (n < 1 || !d_features) throw Error(DMRI_E_INVALID, "need n >= 1 and features");
+        if ((d_grad || loss) && !d_targets)
+            throw Error(DMRI_E_INVALID, "gradient and loss need targets");
+        hipStream_t st = h->stream;
+        GuessModel& M = h->model;
+        if (d_out) launch_mlp_forward(st, n, d_features, M.theta.p, d_out);
+        if (d_grad || loss) {
+            grad_pass(h, n, d_features, d_targets);
+            if (d_grad)
+                HIPCHK(hipMemcpyAsync(d_grad, M.grad.p, sizeof(float) * kMlpParams,
+                                      hipMemcpyDeviceToDevice, st));
+            if (loss) {
+                float l = 0.0f;
+                HIPCHK(hipMemcpyAsync(&l, M.grad.p + kMlpParams, sizeof(float),
+                                      hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                *loss = l;
+            }
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_guess_train(dmri_handle h, int64_t n, const float* d_features,
+                             const float* d_targets, int32_t n_iters, double lr,
+                             double* loss_first, double* loss_last) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        if (!h->model.set) throw Error(DMRI_E_STATE, "no guess network parameters set");
+        if (n < 1 || !d_features || !d_targets || n_iters < 1)
+            throw Error(DMRI_E_INVALID, "need n >= 1, n_iters >= 1 and sample buffers");
+        if (!(lr > 0.0) || !std::isfinite(lr)) throw Error(DMRI_E_INVALID, "lr must be > 0");
+        hipStream_t st = h->stream;
+        GuessModel& M = h->model;
+        M.loss_hist.alloc(2);
+        for (int32_t it = 0; it < n_iters; ++it) {
+            grad_pass(h, n, d_features, d_targets);
+            if (it == 0)
+                HIPCHK(hipMemcpyAsync(M.loss_hist.p, M.grad.p + kMlpParams, sizeof(float),
+                                      hipMemcpyDeviceToDevice, st));
+            if (it == n_iters - 1)
+                HIPCHK(hipMemcpyAsync(M.loss_hist.p + 1, M.grad.p + kMlpParams, sizeof(float),
+                                      hipMemcpyDeviceToDevice, st));
+            ++M.adam_t;
+            launch_adam(st, M.theta.p, M.adam_m.p, M.adam_v.p, M.grad.p, static_cast<float>(lr),
+                        0.9f, 0.999f, 1e-8f, M.adam_t);
+        }
+        float lh[2] = {0.0f, 0.0f};
+        HIPCHK(hipMemcpyAsync(lh, M.loss_hist.p, sizeof(lh), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (loss_first) *loss_first = lh[0];
+        if (loss_last) *loss_last = lh[1];
+        return DMRI_OK;
     });
 }
 
