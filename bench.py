@@ -8,12 +8,17 @@ The default workload is the batched two-compartment case: a z-cylinder of
 radius 5 um in a 12 um periodic box on a 57^3-cube Kuhn mesh (195,112 nodes,
 196,593 DOFs), 64 Fibonacci directions x 16 b-values in [0, 5000] s/mm^2 =
 1024 systems solved in one batch, PGSE delta = 10.6 ms, Delta = 13.4 ms,
-dt = 100 us (240 steps).
+dt = 100 us (240 steps). The default solver is the mixed-precision form
+(FP32 matrices and Krylov vectors, FP64 dots, FP64 residual refinement and
+signal) at a per-step relative residual of 1e-6, which keeps every signal
+within 1e-5 of the all-FP64 solution (the accuracy target is 1e-4).
 
 Prints one JSON line:
   value      DOF-steps/s = n_dof x n_systems x n_steps / seconds per step
   roofline   the dominant kernel's algorithmic HBM bytes per launch over its
              mean launch time (HIP events on the library's stream), vs 8 TB/s
+  plain_fp64 the plain FP64 GPU solve (one system at a time, previous-step
+             guess, all FP64, same tolerance) on a sample of the systems
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
 """
 
@@ -26,7 +31,12 @@ import os
 import sys
 import time
 
-import numpy as np
+# The CPU oracle baseline runs one single-threaded process per core; BLAS
+# thread pools must be sized before numpy is imported.
+for _k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_k] = "1"
+
+import numpy as np  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -34,6 +44,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 KERNELS = {"spmv": 1, "update": 2, "pupdate": 3, "init": 4}
+KERNEL_NAMES = {"spmv": "k_spmv_dot", "update": "k_update", "pupdate": "k_pupdate",
+                "init": "k_init"}
 
 
 def workload(name):
@@ -76,23 +88,88 @@ def kernel_bytes(kind, n_dof, nnz, total_iters, tile, prec_bytes, n_steps, n_sys
     raise ValueError(kind)
 
 
-def cpu_baseline(prob, seq, sysl, n_steps_sample):
-    """FP64 oracle (assembly + Krylov-to-rounding solves) on a bounded sample."""
-    from oracle import fem, timestep
+def profiled_traffic(kernel, workload, precision, rtol):
+    """Measured HBM bytes per launch of `kernel` from the committed rocprofv3
+    counter summary, or None when none matches or the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_counters_%s_%s_%s.md" % (kernel, workload, precision))
+    src = os.path.join(ROOT, "paper_1908_01719_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m_h = re.search(r"kernels_hip_sha256:\s*([0-9a-f]+)", text)
+    m_w = re.search(r"workload: \S+ precision=\S+ rtol=(\S+)", text)
+    if not (m_t and m_h and m_w) or float(m_w.group(1)) != rtol:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_h.group(1):
+        return None
+    return float(m_t.group(1))
+
+
+_CPU = {}
+
+
+def _cpu_worker(args):
+    """One single-threaded oracle solve of the first n steps of one system."""
+    i, n_steps = args
+    from oracle import timestep
+    asm, seq, sysl = _CPU["asm"], _CPU["seq"], _CPU["sysl"]
+    t0 = time.perf_counter()
+    timestep.solve_transformed(asm, seq, float(sysl.b[i]), sysl.q[i], n_steps=n_steps,
+                               solver="krylov")
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(prob, seq, sysl, n_steps_sample, n_proc):
+    """FP64 oracle (assembly + Krylov-to-rounding solves) on a bounded sample:
+    n_proc single-threaded processes, each stepping a different system."""
+    import multiprocessing as mp
+    from oracle import fem
     t0 = time.perf_counter()
     asm = fem.assemble(prob)
     t_asm = time.perf_counter() - t0
-    i = int(np.argmax(sysl.b))
+    _CPU.update(asm=asm, seq=seq, sysl=sysl)
+    order = np.argsort(-np.asarray(sysl.b), kind="stable")
+    idx = [int(order[k % len(order)]) for k in range(n_proc)]
+    ctx = mp.get_context("fork")
     t0 = time.perf_counter()
-    timestep.solve_transformed(asm, seq, float(sysl.b[i]), sysl.q[i], n_steps=n_steps_sample,
-                               solver="krylov")
-    t_run = time.perf_counter() - t0
-    rate = asm.n_dof * n_steps_sample / t_run
+    with ctx.Pool(n_proc) as pool:
+        per = pool.map(_cpu_worker, [(i, n_steps_sample) for i in idx])
+    wall = time.perf_counter() - t0
+    rate = asm.n_dof * n_steps_sample * n_proc / wall
     return {
-        "value": rate, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
-        "sample": ("1 system (b=%g) x first %d of %d steps, single-threaded SciPy CG to 1e-13; "
-                   "assembly %.1fs excluded" % (sysl.b[i], n_steps_sample, seq.n_steps, t_asm)),
+        "value": rate, "unit": "DOF-steps/s", "cores": n_proc, "kind": "oracle",
+        "sample": ("%d systems (largest b first) x first %d of %d steps, one single-threaded "
+                   "process each (SciPy CG to 1e-13, Jacobi); wall %.1fs; per-process %.1f-%.1fs; "
+                   "assembly %.1fs excluded" % (n_proc, n_steps_sample, seq.n_steps, wall,
+                                                min(per), max(per), t_asm)),
         "host_cpus": os.cpu_count(),
+    }
+
+
+def plain_fp64(sim, pid, sysl, rtol, n_sample, batched_sig):
+    """Plain FP64 GPU solve, one system at a time, previous-step guess."""
+    order = np.argsort(-np.asarray(sysl.b), kind="stable")
+    pick = [int(order[k * len(order) // n_sample]) for k in range(n_sample)]
+    saved = {k: sim.dmri_get_option(k) for k in ("precision", "rtol", "guess", "time_kernel",
+                                                  "progress")}
+    sim.set_options(precision=0, rtol=rtol, guess=0, time_kernel=0, progress=0)
+    t = []
+    diff = []
+    for i in pick:
+        t0 = time.perf_counter()
+        sig, _ = sim.dmri_run([pid], sysl.b[i:i + 1], sysl.q[i:i + 1])
+        t.append(time.perf_counter() - t0)
+        diff.append(abs(sig[0] - batched_sig[i]) / abs(sig[0]))
+    sim.set_options(**saved)
+    return {
+        "time_to_signal_s_per_pair": float(np.mean(t)),
+        "sample": "%d systems, indices %s (b = %s), rtol %g" % (
+            n_sample, pick, [float(sysl.b[i]) for i in pick], rtol),
+        "max_rel_diff_vs_batched": float(max(diff)),
     }
 
 
@@ -102,13 +179,17 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="config2", choices=["config0", "config1", "config2"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--guess", type=int, default=1)
     ap.add_argument("--time-kernel", default="spmv", choices=sorted(KERNELS))
     ap.add_argument("--sys-tile", type=int, default=0)
     ap.add_argument("--blocks-per-xcd", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle processes for the CPU baseline (0 = min(16, host CPUs))")
+    ap.add_argument("--plain-sample", type=int, default=4,
+                    help="systems timed one at a time in plain FP64 (0 = skip)")
     ap.add_argument("--progress", type=int, default=40, help="library progress line every k steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -125,9 +206,18 @@ def main():
 
     prob, seq, sysl, desc = workload(args.workload)
     prec = {"fp64": 0, "mixed": 1, "fp32": 2}[args.precision]
-    rtol = args.rtol if args.rtol is not None else {0: 1e-10, 1: 1e-10, 2: 1e-6}[prec]
+    rtol = args.rtol if args.rtol is not None else 1e-6
     print("bench: workload %s (%s), %d systems, precision %s" % (
         args.workload, desc, len(sysl), args.precision), file=sys.stderr, flush=True)
+
+    # The oracle's worker processes are forked before this process touches the GPU.
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_proc = args.cpu_procs or min(16, os.cpu_count() or 1)
+        print("bench: timing the CPU oracle on a bounded sample (%d processes)" % n_proc,
+              file=sys.stderr, flush=True)
+        cpu = cpu_baseline(prob, seq, sysl, args.cpu_steps, n_proc)
+        print("bench: CPU oracle %.3g DOF-steps/s" % cpu["value"], file=sys.stderr, flush=True)
 
     sim = Simulator(0)
     sim.set_sequence(seq)
@@ -149,7 +239,7 @@ def main():
         bcopy = torch.empty_like(a)
         a.fill_(1.0)
         for _ in range(3):
-            bcopy.copy_(a)
+            torch.mul(a, 2.0, out=bcopy)  # one elementwise kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         del a, bcopy
 
@@ -182,12 +272,14 @@ def main():
                       len(sysl))
     achieved = kb / t_kernel / 1e9 if t_kernel > 0 else None
     roofline = {
-        "kernel": {"spmv": "k_spmv_dot", "update": "k_update", "pupdate": "k_pupdate",
-                   "init": "k_init"}[args.time_kernel],
+        "kernel": KERNEL_NAMES[args.time_kernel],
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+        "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+        "traffic": profiled_traffic(KERNEL_NAMES[args.time_kernel], args.workload,
+                                    args.precision, rtol),
         "launches": n_launch, "mean_launch_us": 1e6 * t_kernel / max(1, n_launch),
         "bytes_per_launch": kb / max(1, n_launch),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
     }
     out = {
         "metric": "DOF-steps/s", "value": value, "unit": "DOF-steps/s", "n_gpus": 1,
@@ -202,12 +294,17 @@ def main():
         "krylov_iterations_per_system_step": tot_iters / (len(sysl) * n_steps * args.steps),
         "host_assembly_s": t_asm,
         "roofline": roofline,
+        "plain_fp64": None,
         "cpu_baseline": None,
     }
-    if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, seq, sysl, args.cpu_steps)
+    if args.plain_sample > 0:
+        print("bench: timing the plain FP64 solve on %d systems" % args.plain_sample,
+              file=sys.stderr, flush=True)
+        pf = plain_fp64(sim, pid, sysl, rtol, args.plain_sample, sig)
+        pf["speedup"] = pf["time_to_signal_s_per_pair"] / out["time_to_signal_s_per_pair"]
+        out["plain_fp64"] = pf
     sim.close()
+    out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -165,7 +165,8 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *               returns sum_i w_i u_i^n (a sampling aid, not a signal unless
  *               F(t^n) = 0)
  *  "time_kernel" 0 = off, 1 = SpMV+dot, 2 = CG update, 3 = direction
- *               update, 4 = step start: bracket every launch of that kernel
+ *               update, 4 = step start, 5 = learned-guess network: bracket
+ *               every launch of that kernel
  *               with HIP events and report the summed time in dmri_stats
  *  "blocks_per_xcd" workgroups per XCD sweeping the rows (default 512)
  *  "max_outer"  FP64 refinement passes per step in mixed precision (8)
