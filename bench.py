@@ -288,7 +288,8 @@ def main():
         "dtype": {0: "f64", 1: "f32+f64", 2: "f32"}[prec], "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n_dof": n_dof, "nnz": nnz,
                    "n_systems": len(sysl), "time_steps": n_steps, "dt_us": seq.dt,
-                   "rtol": rtol, "guess": args.guess, "sys_tile": tile,
+                   "rtol": rtol, "guess": args.guess,
+                   "extrap_order": int(sim.dmri_get_option("extrap_order")), "sys_tile": tile,
                    "parallelism": "single GPU, systems batched"},
         "time_to_signal_s_per_pair": elapsed / args.steps / len(sysl),
         "krylov_iterations_per_system_step": tot_iters / (len(sysl) * n_steps * args.steps),

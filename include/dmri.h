@@ -154,9 +154,14 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *               (default 1e-10)
  *  "inner_rtol" FP32 inner solve reduction in mixed precision (1e-4)
  *  "max_iter"   Krylov iterations per step and system (default 2000)
- *  "guess"      0 = previous step, 1 = linear extrapolation (default),
- *               2 = learned correction of the extrapolation (needs
- *               network parameters; precision 0 or 1)
+ *  "guess"      0 = previous step, 1 = polynomial extrapolation of the
+ *               past solutions (default), 2 = learned correction of the
+ *               linear extrapolation (needs network parameters; precision
+ *               0 or 1)
+ *  "extrap_order" order p of the extrapolation (1..4, default 3): the
+ *               polynomial through u^{n-1}, ..., u^{n-1-p} at t^n, i.e.
+ *               x0 = sum_k (-1)^k C(p+1, k+1) u^{n-1-k}; early steps use the
+ *               history available
  *  "sys_tile"   systems per lane group: 0 = auto, or 8, 16, 32, 64
  *  "graph"      1 = replay chunks of Krylov iterations from a HIP graph
  *  "autotune"   1 = time the tile candidates on the first step and keep the
@@ -165,8 +170,8 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *               returns sum_i w_i u_i^n (a sampling aid, not a signal unless
  *               F(t^n) = 0)
  *  "time_kernel" 0 = off, 1 = SpMV+dot, 2 = CG update, 3 = direction
- *               update, 4 = step start, 5 = learned-guess network: bracket
- *               every launch of that kernel
+ *               update, 4 = step start, 5 = learned-guess network, 6 =
+ *               extrapolation: bracket every launch of that kernel
  *               with HIP events and report the summed time in dmri_stats
  *  "blocks_per_xcd" workgroups per XCD sweeping the rows (default 512)
  *  "max_outer"  FP64 refinement passes per step in mixed precision (8)

@@ -125,6 +125,7 @@ struct Options {
     double inner_rtol = 1e-4;
     int max_iter = 2000;
     int guess = 1;
+    int extrap_order = 3;
     int sys_tile = 0;
     int graph = 0;
     int autotune = 0;
@@ -185,14 +186,16 @@ struct StateBufs {
         s.n_sys = n_sys;
         s.max_iter = max_iter;
         s.rtol2 = rtol2;
+        s.floor_bb = nullptr;
+        s.floor_scale = 0.0;
         return s;
     }
 };
 
 // Per-batch device workspace (grow-only, reused across runs).
 struct Workspace {
-    DevBuf<double> vec64[6];
-    DevBuf<float> vec32[6];
+    DevBuf<double> vec64[kMaxHist + 5];
+    DevBuf<float> vec32[kMaxHist + 5];
     DevBuf<double4> gq;
     DevBuf<double2> sig;
     DevBuf<double> partial, b_in, q_in;
@@ -387,15 +390,71 @@ MlpDofs ensure_features(dmri_ctx* h, ProblemRec& P) {
     return MlpDofs{P.feat_geo.p, P.feat_flags.p};
 }
 
-// Guess mode of step n: 0 = u^{n-1}, 1 = extrapolation, 2 = learned (the
-// network's prediction is written to x first and k_init starts from x).
-int guess_mode(const dmri_ctx* h, int n) { return n < 2 ? 0 : h->opt.guess; }
+// Solution history of the initial guess. ring[0..nh-1] hold u^{n-1},
+// u^{n-2}, ... (newest first; `avail` of them are filled) and ring[nh] is the
+// next solution x. After a step x becomes u^{n-1} and the oldest slot is
+// reused for the next x.
+template <typename V2>
+struct History {
+    std::vector<V2*> ring;
+    int nh = 2, avail = 1;
+    V2* u(int k) const { return ring[k]; }
+    V2* x() const { return ring[nh]; }
+    void advance() {
+        V2* oldest = ring[nh - 1];
+        for (int k = nh - 1; k >= 1; --k) ring[k] = ring[k - 1];
+        ring[0] = ring[nh];
+        ring[nh] = oldest;
+        avail = std::min(avail + 1, nh);
+    }
+};
 
-void launch_learned_guess(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
-                          const std::vector<double>& F, const std::vector<double>& f, int n,
-                          int64_t n_sys, const double2* u1, const double2* u2, double2* x) {
-    launch_mlp_guess(h->stream, g, h->model.theta.p, dofs, h->ws.gq.p, mlp_step(h, tr, F, f, n),
-                     static_cast<int32_t>(n_sys), u1, u2, x);
+// History length needed by the guess options: polynomial extrapolation of
+// order p uses p + 1 past solutions; the learned guess uses two.
+int history_len(const dmri_ctx* h) {
+    return h->opt.guess == 1 ? std::max(2, h->opt.extrap_order + 1) : 2;
+}
+
+// Weights of the order-p polynomial through u^{n-1}, ..., u^{n-1-p} on equal
+// steps, evaluated one step ahead: c_k = (-1)^k C(p+1, k+1).
+void extrap_weights(int p, double* c) {
+    for (int k = 0; k <= p; ++k) {
+        double bin = 1.0;  // C(p+1, k+1)
+        for (int i = 1; i <= k + 1; ++i) bin = bin * (p + 2 - i) / i;
+        c[k] = (k & 1) ? -bin : bin;
+    }
+}
+
+// Start of step n: writes the guess into hist.x() when it is not formed
+// inside k_init, and returns k_init's guess mode (0 = u^{n-1}, 1 = linear
+// extrapolation inside k_init, 2 = x already holds the guess).
+template <typename T, typename Timer>
+int prepare_guess(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
+                  const std::vector<double>& F, const std::vector<double>& f, int n,
+                  int64_t n_sys, const History<typename Vec2Of<T>::type>& hs, Timer& timer) {
+    const int og = h->opt.guess;
+    if (og == 1) {
+        const int m = std::min(h->opt.extrap_order, hs.avail - 1);
+        if (m <= 0) return 0;
+        if (m == 1) return 1;
+        ExtrapTerms<T> t{};
+        t.m = m + 1;
+        extrap_weights(m, t.c);
+        for (int k = 0; k <= m; ++k) t.u[k] = hs.u(k);
+        timer.run(6, [&] { launch_combine<T>(h->stream, g, t, hs.x()); });
+        return 2;
+    }
+    if (og == 2 && hs.avail >= 2) {
+        if constexpr (sizeof(T) == 8) {
+            timer.run(5, [&] {
+                launch_mlp_guess(h->stream, g, h->model.theta.p, dofs, h->ws.gq.p,
+                                 mlp_step(h, tr, F, f, n), static_cast<int32_t>(n_sys), hs.u(0),
+                                 hs.u(1), hs.x());
+            });
+            return 2;
+        }
+    }
+    return 0;
 }
 
 // Append training samples of step n (u1 = u^{n-1}, u2 = u^{n-2}, un = u^n)
@@ -658,18 +717,19 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     const size_t nv = static_cast<size_t>(g.n_rows) * g.ld, ld = static_cast<size_t>(g.ld);
     DevBuf<T>* vecs;
     if constexpr (sizeof(T) == 8) vecs = W.vec64; else vecs = W.vec32;
-    for (int i = 0; i < 6; ++i) vecs[i].alloc(2 * nv);
-    V2* bufs[3] = {reinterpret_cast<V2*>(vecs[0].p), reinterpret_cast<V2*>(vecs[1].p),
-                   reinterpret_cast<V2*>(vecs[2].p)};
-    V2* r = reinterpret_cast<V2*>(vecs[3].p);
-    V2* p = reinterpret_cast<V2*>(vecs[4].p);
-    V2* q = reinterpret_cast<V2*>(vecs[5].p);
+    History<V2> hs;
+    hs.nh = history_len(h);
+    for (int i = 0; i < hs.nh + 4; ++i) vecs[i].alloc(2 * nv);
+    for (int i = 0; i <= hs.nh; ++i) hs.ring.push_back(reinterpret_cast<V2*>(vecs[i].p));
+    V2* r = reinterpret_cast<V2*>(vecs[hs.nh + 1].p);
+    V2* p = reinterpret_cast<V2*>(vecs[hs.nh + 2].p);
+    V2* q = reinterpret_cast<V2*>(vecs[hs.nh + 3].p);
     W.outer.alloc(ld, g.n_tiles);
     W.outer.reset(ld, st);
     SolverState s = W.outer.view(static_cast<int32_t>(n_sys), h->opt.max_iter,
                                  h->opt.rtol * h->opt.rtol);
     const MatView<T> Av = view<T>(P, A);
-    launch_set_initial<T>(st, g, P.u0.p, s.n_sys, bufs[0]);
+    launch_set_initial<T>(st, g, P.u0.p, s.n_sys, hs.u(0));
     std::vector<double> F, f;
     step_tables(h, F, f);
     const bool tr = P.op.form == FORM_TRANSFORMED;
@@ -682,39 +742,29 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
 
     KernelTimer timer(h, st, h->opt.time_kernel);
     const double t0 = now_s();
-    int cur = 0, prev2 = 1, nxt = 2;  // indices into bufs: u_prev, u_prev2, x
     int last_iters = 8;
     for (int n = 1; n <= N; ++n) {
         const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
-        const int gm = guess_mode(h, n);
-        if constexpr (kF64) {
-            if (gm == 2)
-                timer.run(5, [&] {
-                    launch_learned_guess(h, g, dofs, tr, F, f, n, n_sys, bufs[cur], bufs[prev2],
-                                         bufs[nxt]);
-                });
-        }
+        const int gm = prepare_guess<T>(h, g, dofs, tr, F, f, n, n_sys, hs, timer);
         timer.run(4, [&] {
-            launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, bs.herm, gm, bufs[cur], bufs[prev2],
-                           bufs[nxt], r, p, nullptr, nullptr, s, bs.sc);
+            launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, bs.herm, gm, hs.u(0), hs.u(1), hs.x(), r,
+                           p, nullptr, nullptr, s, bs.sc);
         });
-        const int done = krylov_loop<T>(h, bs, Av, W.gq.p, lhs, bufs[nxt], r, p, q, s, timer,
+        const int done = krylov_loop<T>(h, bs, Av, W.gq.p, lhs, hs.x(), r, p, q, s, timer,
                                         last_iters - 2, h->opt.max_iter);
         last_iters = done;
         if constexpr (kF64) {
-            record_samples(h, g, dofs, tr, F, f, n, n_sys, bufs[cur], bufs[prev2], bufs[nxt]);
+            if (hs.avail >= 2)
+                record_samples(h, g, dofs, tr, F, f, n, n_sys, hs.u(0), hs.u(1), hs.x());
         }
         progress_line(h, n, N, done, t0);
-        const int old_prev2 = prev2;
-        prev2 = cur;
-        cur = nxt;
-        nxt = old_prev2;
+        hs.advance();
     }
     HIPCHK(hipStreamSynchronize(st));
     res.t_solve = now_s() - t0;
     res.steps = N;
     timer.collect(res);
-    collect_result<T>(h, bs, P, W.outer, bufs[cur], d_sig, n_sys, res);
+    collect_result<T>(h, bs, P, W.outer, hs.u(0), d_sig, n_sys, res);
     HIPCHK(hipMemcpyAsync(res.iters.data(), W.outer.iters_total.p, sizeof(int32_t) * n_sys,
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -735,12 +785,15 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     const BatchSetup bs = setup_batch(h, P, n_sys, d_b, d_q);
     const Geom& g = bs.g;
     const size_t nv = static_cast<size_t>(g.n_rows) * g.ld, ld = static_cast<size_t>(g.ld);
-    for (int i = 0; i < 6; ++i) W.vec64[i].alloc(2 * nv);
+    History<double2> hs;
+    hs.nh = history_len(h);
+    for (int i = 0; i < hs.nh + 4; ++i) W.vec64[i].alloc(2 * nv);
     for (int i = 0; i < 4; ++i) W.vec32[i].alloc(2 * nv);
-    double2* U[4];  // u_prev, u_prev2, x, x_alt
-    for (int i = 0; i < 4; ++i) U[i] = reinterpret_cast<double2*>(W.vec64[i].p);
-    double2* r64 = reinterpret_cast<double2*>(W.vec64[4].p);
-    double2* p64 = reinterpret_cast<double2*>(W.vec64[5].p);
+    for (int i = 0; i <= hs.nh; ++i) hs.ring.push_back(reinterpret_cast<double2*>(W.vec64[i].p));
+    // The refinement passes alternate x between hs.x() and x_alt.
+    double2* x_alt = reinterpret_cast<double2*>(W.vec64[hs.nh + 1].p);
+    double2* r64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 2].p);
+    double2* p64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 3].p);
     float2* r32 = reinterpret_cast<float2*>(W.vec32[0].p);
     float2* dx = reinterpret_cast<float2*>(W.vec32[1].p);
     float2* p32 = reinterpret_cast<float2*>(W.vec32[2].p);
@@ -753,9 +806,16 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                                   h->opt.rtol * h->opt.rtol);
     SolverState si = W.inner.view(static_cast<int32_t>(n_sys), h->opt.max_iter,
                                   h->opt.inner_rtol * h->opt.inner_rtol);
+    // An inner solve need not reduce its residual below a quarter of the
+    // outer target: ||r|| <= max(inner_rtol ||r64||, rtol ||b|| / 4).
+    si.floor_bb = W.outer.bb.p;
+    {
+        const double k = 0.25 * h->opt.rtol / h->opt.inner_rtol;
+        si.floor_scale = k * k;
+    }
     const MatView<double> A64 = view<double>(P, P.A64);
     const MatView<float> A32 = view<float>(P, P.A32);
-    launch_set_initial<double>(st, g, P.u0.p, so.n_sys, U[0]);
+    launch_set_initial<double>(st, g, P.u0.p, so.n_sys, hs.u(0));
     std::vector<double> F, f;
     step_tables(h, F, f);
     const bool tr = P.op.form == FORM_TRANSFORMED;
@@ -767,18 +827,13 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
 
     KernelTimer timer(h, st, h->opt.time_kernel);
     const double t0 = now_s();
-    int cur = 0, prev2 = 1, xi = 2, yi = 3;
     int last_first_pass = 8;
     for (int n = 1; n <= N; ++n) {
         const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
-        const int gm = guess_mode(h, n);
-        if (gm == 2)
-            timer.run(5, [&] {
-                launch_learned_guess(h, g, dofs, tr, F, f, n, n_sys, U[cur], U[prev2], U[xi]);
-            });
+        const int gm = prepare_guess<double>(h, g, dofs, tr, F, f, n, n_sys, hs, timer);
         timer.run(4, [&] {
-            launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, gm, U[cur], U[prev2], U[xi],
-                                r64, p64, nullptr, nullptr, so, bs.sc);
+            launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, gm, hs.u(0), hs.u(1),
+                                hs.x(), r64, p64, nullptr, nullptr, so, bs.sc);
         });
         int step_iters = 0;
         for (int pass = 0; pass < h->opt.max_outer; ++pass) {
@@ -791,10 +846,10 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
             if (pass == 0) last_first_pass = it;
             step_iters += it;
             timer.run(4, [&] {
-                launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, 3, U[cur], U[prev2],
-                                    U[xi], r64, p64, dx, U[yi], so, bs.sc);
+                launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, 3, hs.u(0), hs.u(1),
+                                    hs.x(), r64, p64, dx, x_alt, so, bs.sc);
             });
-            std::swap(xi, yi);
+            std::swap(hs.ring[hs.nh], x_alt);
         }
         if (poll_active(h, g, so) != 0) {
             // Outer refinement did not reach rtol within max_outer passes.
@@ -804,18 +859,15 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
             for (int64_t i = 0; i < n_sys; ++i)
                 if (act[i]) flag_or[i] |= 1;
         }
-        record_samples(h, g, dofs, tr, F, f, n, n_sys, U[cur], U[prev2], U[xi]);
+        if (hs.avail >= 2) record_samples(h, g, dofs, tr, F, f, n, n_sys, hs.u(0), hs.u(1), hs.x());
         progress_line(h, n, N, step_iters, t0);
-        const int old_prev2 = prev2;
-        prev2 = cur;
-        cur = xi;
-        xi = old_prev2;
+        hs.advance();
     }
     HIPCHK(hipStreamSynchronize(st));
     res.t_solve = now_s() - t0;
     res.steps = N;
     timer.collect(res);
-    collect_result<double>(h, bs, P, W.outer, U[cur], d_sig, n_sys, res);
+    collect_result<double>(h, bs, P, W.outer, hs.u(0), d_sig, n_sys, res);
     std::vector<int32_t> inner_flags(n_sys);
     HIPCHK(hipMemcpyAsync(res.iters.data(), W.inner.iters_total.p, sizeof(int32_t) * n_sys,
                           hipMemcpyDeviceToHost, st));
@@ -1091,6 +1143,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
             o.inner_rtol = v;
         } else if (k == "max_iter") o.max_iter = as_int(1, 1000000);
         else if (k == "guess") o.guess = as_int(0, 2);
+        else if (k == "extrap_order") o.extrap_order = as_int(1, kMaxHist - 1);
         else if (k == "sys_tile") {
             int t = as_int(0, 64);
             if (t != 0 && t != 8 && t != 16 && t != 32 && t != 64)
@@ -1106,7 +1159,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "nt") o.nt = as_int(0, 1);
         else if (k == "lds") o.lds = as_int(0, 1);
         else if (k == "persistent") o.persistent = as_int(0, 2);
-        else if (k == "time_kernel") o.time_kernel = as_int(0, 5);
+        else if (k == "time_kernel") o.time_kernel = as_int(0, 6);
         else if (k == "progress") o.progress = as_int(0, 1000000);
         else if (k == "ordering") o.ordering = as_int(0, 1);
         else if (k == "pencil") o.pencil = as_int(1, 4096);
@@ -1127,6 +1180,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "inner_rtol") *value = o.inner_rtol;
         else if (k == "max_iter") *value = o.max_iter;
         else if (k == "guess") *value = o.guess;
+        else if (k == "extrap_order") *value = o.extrap_order;
         else if (k == "sys_tile") *value = o.sys_tile;
         else if (k == "graph") *value = o.graph;
         else if (k == "autotune") *value = o.autotune;

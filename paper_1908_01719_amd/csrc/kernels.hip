@@ -251,6 +251,158 @@ __device__ __forceinline__ void spmv_item(const Geom& g, int part, int j, int32_
     });
 }
 
+// Accumulate y += (ar + i ai) x with explicit fused multiply-adds.
+template <typename T>
+__device__ __forceinline__ void cmac(T& yr, T& yi, T ar, T ai, V2<T> x) {
+    yr = fma(ar, x.x, yr);
+    yr = fma(-ai, x.y, yr);
+    yi = fma(ar, x.y, yi);
+    yi = fma(ai, x.x, yi);
+}
+
+// Gathers from one 64-wide tile go through a buffer resource covering the
+// tile: the row offset j * 64 * sizeof(V2) is wavefront-uniform (a scalar
+// register) and the lane offset is the same vector register for every
+// gather, so a gather costs no vector address arithmetic. Offsets outside
+// the resource read as zero.
+constexpr int kBufWord3 = 0x00020000;  // raw 32-bit data format (gfx9 family)
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const V2<T>* pt, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<V2<T>*>(pt), 0, static_cast<int>(bytes),
+                                             kBufWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ V2<T> tile_row(__amdgpu_buffer_rsrc_t rs, int j, uint32_t lane_bytes) {
+    const uint32_t off = static_cast<uint32_t>(j) * static_cast<uint32_t>(64 * sizeof(V2<T>));
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(V2<T>, __builtin_amdgcn_raw_buffer_load_b64(rs, lane_bytes, off, 0));
+    } else {
+        return __builtin_bit_cast(V2<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, lane_bytes, off, 0));
+    }
+}
+
+// Rows whose padded length is 16 entries (every interior row of a Kuhn
+// mesh): G rows of one wavefront at once, all 16 * G gathers issued before
+// the first use. Returns the rows' results in yr/yi.
+template <typename T, int G>
+__device__ __forceinline__ void spmv16_rows(const int32_t* __restrict__ col,
+                                            const T* __restrict__ K0,
+                                            const V4<T>* __restrict__ aux,
+                                            __amdgpu_buffer_rsrc_t pt, uint32_t lane_bytes,
+                                            const int (&kb)[G], const LaneCoef<T>& lc,
+                                            T (&yr)[G], T (&yi)[G]) {
+    V2<T> xv[G][16];
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+        int jj[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) jj[u] = col[kb[gi] + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) xv[gi][u] = tile_row<T>(pt, jj[u], lane_bytes);
+    }
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+        T r = 0, i = 0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const V4<T> a = aux[kb[gi] + u];
+            const T ar = fma(lc.c, a.x, K0[kb[gi] + u]);
+            const T ai = fma(lc.d2, a.w, fma(lc.d1, a.z, lc.d0 * a.y));
+            cmac<T>(r, i, ar, ai, xv[gi][u]);
+        }
+        yr[gi] = r;
+        yi[gi] = i;
+    }
+}
+
+// One row of any padded length, 8 entries at a time.
+template <typename T>
+__device__ __forceinline__ void spmv8_row(const int32_t* __restrict__ col,
+                                          const T* __restrict__ K0,
+                                          const V4<T>* __restrict__ aux,
+                                          __amdgpu_buffer_rsrc_t pt, uint32_t lane_bytes,
+                                          int kb, int ke, const LaneCoef<T>& lc, T& yr, T& yi) {
+    yr = 0;
+    yi = 0;
+    for (int k0 = kb; k0 < ke; k0 += kRowPad) {
+        int jj[kRowPad];
+        V2<T> xv[kRowPad];
+#pragma unroll
+        for (int u = 0; u < kRowPad; ++u) jj[u] = col[k0 + u];
+#pragma unroll
+        for (int u = 0; u < kRowPad; ++u) xv[u] = tile_row<T>(pt, jj[u], lane_bytes);
+#pragma unroll
+        for (int u = 0; u < kRowPad; ++u) {
+            const V4<T> a = aux[k0 + u];
+            const T ar = fma(lc.c, a.x, K0[k0 + u]);
+            const T ai = fma(lc.d2, a.w, fma(lc.d1, a.z, lc.d0 * a.y));
+            cmac<T>(yr, yi, ar, ai, xv[u]);
+        }
+    }
+}
+
+// SpMV item for 64-system tiles with static chunks: the kUs row slots of a
+// wavefront are taken G at a time (G = 2 in FP32, 1 in FP64 for registers).
+template <typename T, bool HERM>
+__device__ __forceinline__ void spmv_item64(const Geom& g, int part, int j, int tile,
+                                            const LaneCoef<T>& lc,
+                                            const int32_t* __restrict__ row_ptr,
+                                            const int32_t* __restrict__ col,
+                                            const T* __restrict__ K0,
+                                            const V4<T>* __restrict__ aux,
+                                            const V2<T>* __restrict__ p, V2<T>* __restrict__ q,
+                                            double (&acc)[2]) {
+    constexpr int G = sizeof(T) == 4 ? 2 : 1;
+    const int r0 = part * g.part_rows;
+    const int r1 = min(g.n_rows, r0 + g.part_rows);
+    const int lane = threadIdx.x & 63;
+    const uint32_t lane_bytes = static_cast<uint32_t>(lane) * sizeof(V2<T>);
+    const size_t tbase = static_cast<size_t>(tile) * g.n_rows * 64;
+    const V2<T>* pt = p + tbase;
+    V2<T>* qt = q + tbase;
+    const __amdgpu_buffer_rsrc_t rs =
+        tile_rsrc<T>(pt, static_cast<uint32_t>(g.n_rows) * 64u * sizeof(V2<T>));
+    const int off = wave_id_uniform();
+    const int step = g.B * g.chunk_rows;
+    for (int c0 = r0 + j * g.chunk_rows; c0 < r1; c0 += step) {
+#pragma unroll
+        for (int u0 = 0; u0 < kUs; u0 += G) {
+            int row[G], kb[G], ke[G];
+            bool all16 = true, any = false;
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) {
+                row[gi] = c0 + off + (u0 + gi) * kWaves;
+                const bool ok = row[gi] < r1;
+                any |= ok;
+                if (!ok) row[gi] = r1 - 1;  // clamped duplicate, result not stored
+                kb[gi] = row_ptr[row[gi]];
+                ke[gi] = row_ptr[row[gi] + 1];
+                all16 &= (ke[gi] - kb[gi] == 16);
+            }
+            if (!any) break;
+            T yr[G], yi[G];
+            if (all16) {
+                spmv16_rows<T, G>(col, K0, aux, rs, lane_bytes, kb, lc, yr, yi);
+            } else {
+#pragma unroll
+                for (int gi = 0; gi < G; ++gi)
+                    spmv8_row<T>(col, K0, aux, rs, lane_bytes, kb[gi], ke[gi], lc, yr[gi], yi[gi]);
+            }
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) {
+                if (c0 + off + (u0 + gi) * kWaves >= r1) continue;
+                const size_t o = static_cast<size_t>(row[gi]) * 64 + lane;
+                const V2<T> y = mk2<T>(yr[gi], yi[gi]);
+                if (g.nt) store_nt(qt + o, y);
+                else qt[o] = y;
+                dot_acc<HERM, T>(acc[0], acc[1], pt[o], y);
+            }
+        }
+    }
+}
+
 // q = A p and sigma = p^H q (or p^T q) per system.
 template <typename T, int S, bool HERM>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot(
@@ -267,8 +419,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(
         if (!__syncthreads_or(act)) continue;
         const LaneCoef<T> lc(gq[sys], lhs);
         double acc[2] = {0.0, 0.0};
-        spmv_item<T, S, HERM>(g, part, j, sc.ctr_spmv + item, act, tb, lc, row_ptr, col, K0, aux,
-                              p, q, acc);
+        if constexpr (S == 64) {
+            if (!g.queue && g.tile_bytes_ok) {
+                if (act)
+                    spmv_item64<T, HERM>(g, part, j, tile, lc, row_ptr, col, K0, aux, p, q, acc);
+            } else {
+                spmv_item<T, S, HERM>(g, part, j, sc.ctr_spmv + item, act, tb, lc, row_ptr, col,
+                                      K0, aux, p, q, acc);
+            }
+        } else {
+            spmv_item<T, S, HERM>(g, part, j, sc.ctr_spmv + item, act, tb, lc, row_ptr, col, K0,
+                                  aux, p, q, acc);
+        }
         reduce_store<S, 2>(g, sc, item, j, acc, lds);
     }
 }
@@ -972,7 +1134,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Geom g, SolverState s, Scra
             }
         } else {  // FIN_INIT
             if (sys < s.n_sys) {
-                const double rr = tot[2], bb = tot[3];
+                const double rr = tot[2];
+                const double bb =
+                    s.floor_bb ? fmax(tot[3], s.floor_scale * s.floor_bb[sys]) : tot[3];
                 s.rho[sys] = make_double2(tot[0], tot[1]);
                 s.rr[sys] = rr;
                 s.bb[sys] = bb;
@@ -1041,6 +1205,29 @@ __global__ __launch_bounds__(kBlock) void k_set_initial(int64_t n, int32_t n_row
     const int64_t row = slab - tile * n_rows;
     const int64_t sys = tile * S + (i - slab * S);
     x[i] = mk2<T>(sys < n_sys ? static_cast<T>(u0[row]) : T(0), T(0));
+}
+
+// x = sum_k c[k] u_k over all elements (polynomial extrapolation of the
+// solution history, or any fixed linear combination of up to kMaxHist
+// vectors). Four elements per thread per pass, all loads issued first.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_combine(int64_t n, ExtrapTerms<T> t,
+                                                   V2<T>* __restrict__ x) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        V2<T> v[kMaxHist];
+#pragma unroll
+        for (int k = 0; k < kMaxHist; ++k)
+            if (k < t.m) v[k] = t.u[k][i];
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMaxHist; ++k)
+            if (k < t.m) {
+                re = fma(t.c[k], static_cast<double>(v[k].x), re);
+                im = fma(t.c[k], static_cast<double>(v[k].y), im);
+            }
+        x[i] = mk2<T>(static_cast<T>(re), static_cast<T>(im));
+    }
 }
 
 __global__ void k_zero_i32(int32_t* __restrict__ p, int64_t n) {
@@ -1118,6 +1305,8 @@ Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
     g.part_rows = std::max(pr, g.chunk_rows);
     const int32_t chunks = (g.part_rows + g.chunk_rows - 1) / g.chunk_rows;
     g.B = std::max(1, std::min(blocks_per_xcd, chunks));
+    // Buffer-resource gathers need a tile (FP64, 64 systems) below 2^31 bytes.
+    g.tile_bytes_ok = static_cast<int64_t>(n_rows) * 64 * 16 < (int64_t(1) << 31) ? 1 : 0;
     return g;
 }
 
@@ -1283,6 +1472,18 @@ void launch_sys_params(hipStream_t st, int32_t n_sys, int32_t ld, const double* 
     k_sys_params<<<blocks, 256, 0, st>>>(n_sys, ld, b, q, int_F2, gq, bad);
     check_launch("sys_params");
 }
+
+template <typename T>
+void launch_combine(hipStream_t st, const Geom& g, const ExtrapTerms<T>& t, V2<T>* x) {
+    if (t.m < 1 || t.m > kMaxHist) throw std::runtime_error("combine: 1..kMaxHist terms");
+    const int64_t n = static_cast<int64_t>(g.n_rows) * g.ld;
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(8192, (n + kBlock - 1) / kBlock));
+    k_combine<T><<<blocks, kBlock, 0, st>>>(n, t, x);
+    check_launch("combine");
+}
+template void launch_combine<double>(hipStream_t, const Geom&, const ExtrapTerms<double>&,
+                                     double2*);
+template void launch_combine<float>(hipStream_t, const Geom&, const ExtrapTerms<float>&, float2*);
 
 void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
     if (n <= 0) return;

@@ -81,6 +81,11 @@ struct SolverState {
     int32_t n_sys;
     int32_t max_iter;
     double rtol2;
+    // Optional floor of the reference norm: a solve starts with
+    // bb = max(||b||^2, floor_scale * floor_bb[sys]) (the FP32 inner solves
+    // of mixed precision stop once they reach the outer tolerance).
+    const double* floor_bb;
+    double floor_scale;
 };
 
 // Launch geometry shared by every kernel of a problem.
@@ -96,6 +101,7 @@ struct Geom {
     int32_t B;           // blocks per XCD
     int32_t queue;       // gather kernels: 1 = per-item row queue, 0 = static chunks
     int32_t grab;        // queue grabs per wavefront take grab * 2 * 64/S rows
+    int32_t tile_bytes_ok;  // a 64-system FP64 tile is below 2^31 bytes (buffer gathers)
     int32_t nt;          // 1 = SpMV output stored non-temporally
     int32_t lds;         // 1 = LDS-staged SpMV for tiles of 32 or 64 systems
 };
@@ -185,5 +191,19 @@ void launch_krylov_persistent(hipStream_t st, const Geom& g, const MatView<T>& A
 
 // Zero n int32 values (a kernel, so it may be captured in a graph).
 void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n);
+
+// Up to kMaxHist vectors and FP64 weights of a linear combination.
+constexpr int kMaxHist = 5;
+template <typename T>
+struct ExtrapTerms {
+    const typename Vec2Of<T>::type* u[kMaxHist];
+    double c[kMaxHist];
+    int32_t m;
+};
+
+// x = sum_k c[k] u[k] over all n_rows * ld elements of the batch.
+template <typename T>
+void launch_combine(hipStream_t st, const Geom& g, const ExtrapTerms<T>& t,
+                    typename Vec2Of<T>::type* x);
 
 }  // namespace dmri

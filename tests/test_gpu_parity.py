@@ -289,3 +289,58 @@ def test_persistent_solver_matches_oracle(Sim, precision):
         _say("persistent=%d precision=%d max err %.2e" % (persist, precision, err.max()))
         assert err.max() < 1e-9
     assert np.abs(out[0] - out[1]).max() < 1e-10 * abs(ref[0])
+
+
+_WIDE = {}
+
+
+def _wide_case():
+    # 67 systems: a full 64-system tile and a ragged one of 3
+    if not _WIDE:
+        prob, _, _ = _cyl_case()
+        rng = np.random.default_rng(4)
+        b = rng.uniform(0.0, 5000.0, 67)
+        b[0] = 0.0
+        q = di.fibonacci_directions(67)
+        _WIDE["case"] = (prob, b, q, timestep.signals(prob, SHORT, b, q, solver="splu"))
+    return _WIDE["case"]
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_wide_tiles_chunked_match_oracle(Sim, precision):
+    # 64-wide tiles through the chunked multi-launch loop: the
+    # wavefront-uniform SpMV path (two rows per wavefront in FP32, 16-entry
+    # rows and the general fallback).
+    prob, b, q, ref = _wide_case()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12 if precision != 2 else 1e-6, precision=precision,
+                        sys_tile=64, persistent=0)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+    assert st["status"] == "DMRI_OK"
+    err = rel_err(sig, ref, ref[0])
+    _say("wide tiles precision=%d max err %.2e" % (precision, err.max()))
+    assert err.max() < (1e-9 if precision != 2 else 1e-4)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_extrapolation_orders_match_oracle(Sim, order, precision):
+    # The polynomial-extrapolation guess only moves the Krylov starting
+    # point: every order gives the oracle's signals (the iteration counts are
+    # reported; on this coarse time grid at rtol 1e-12 they barely differ).
+    prob, b, q = _cyl_case()
+    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.set_options(rtol=1e-12, precision=precision, guess=0)
+        _, st0 = sim.dmri_run([pid] * len(b), b, q)
+        sim.set_options(guess=1, extrap_order=order)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+    assert st["status"] == "DMRI_OK"
+    err = rel_err(sig, ref, ref[0])
+    _say("order %d precision %d: max err %.2e, iterations %d (previous-step guess %d)"
+         % (order, precision, err.max(), st["total_iterations"], st0["total_iterations"]))
+    assert err.max() < 1e-9
