@@ -163,9 +163,12 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *               x0 = sum_k (-1)^k C(p+1, k+1) u^{n-1-k}; early steps use the
  *               history available
  *  "sys_tile"   systems per lane group: 0 = auto, or 8, 16, 32, 64
- *  "graph"      1 = replay chunks of Krylov iterations from a HIP graph
- *  "autotune"   1 = time the tile candidates on the first step and keep the
- *               fastest per problem size
+ *  "graph"      1 = when the Krylov solves run in the persistent kernel
+ *               (no host decisions inside the time loop), capture the whole
+ *               time loop in a HIP graph and replay it; the graph is kept in
+ *               the handle and replayed while the batch, buffers and options
+ *               are unchanged (default 0; not with time_kernel or sample
+ *               recording)
  *  "n_steps"    0 = full echo (default); n > 0 stops after n steps and
  *               returns sum_i w_i u_i^n (a sampling aid, not a signal unless
  *               F(t^n) = 0)
@@ -184,12 +187,25 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *  "persistent" Krylov iterations of a step in one persistent launch with
  *               grid barriers: 0 = off, 1 = on (batches of <= 64 systems),
  *               2 = auto (default: on when rows x systems <= 131072)
+ *  "autotune"   1 = before the first run of a kind of batch (problem,
+ *               number of systems, precision, solver), time its first steps
+ *               under each candidate launch configuration (tile width,
+ *               blocks per XCD, persistent kernel, LDS SpMV) and use the
+ *               fastest; the choice is cached in the handle (default 0)
+ *  "tuned_sys_tile", "tuned_blocks_per_xcd", "tuned_persistent",
+ *  "tuned_lds", "tuned_trials"  read-only (dmri_get_option): the
+ *               configuration the autotuner applied last (-1 before any)
  *  "progress"   k > 0 prints one line to stderr every k time steps
  *  "ordering"   DOF order of problems added afterwards: 0 = Morton curve,
  *               1 = pencils (default): columns of "pencil" x "pencil" cells
  *               swept z-, y-, x-major, bounding the index distance between
  *               mesh neighbours
  *  "pencil"     pencil width in cells (default 16)
+ *  "concurrency" k > 1: a dmri_run over several problems runs up to k of
+ *               them at once, each on its own stream and workspace driven by
+ *               its own host thread (meshes of uneven size share the GPU);
+ *               1 = one after another (default). Runs with autotune, graph
+ *               or sample recording use one lane
  * Unknown keys or out-of-range values: DMRI_E_INVALID. */
 dmri_status dmri_set_option(dmri_handle h, const char* key, double value);
 dmri_status dmri_get_option(dmri_handle h, const char* key, double* value);

@@ -19,8 +19,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
+#include <exception>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -141,6 +146,7 @@ struct Options {
     int progress = 0;
     int ordering = 1;
     int pencil = 16;
+    int concurrency = 1;
 };
 
 // Per-system Krylov state arrays of one solver level.
@@ -219,6 +225,54 @@ struct Workspace {
     }
 };
 
+// Captured time loop of the persistent path, replayed while its key (every
+// pointer and scalar baked into the launches) is unchanged.
+struct GraphCache {
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* final_u = nullptr;  // u^N after the loop
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        key.clear();
+        final_u = nullptr;
+    }
+    ~GraphCache() { reset(); }
+};
+
+// One execution lane: a stream with its own workspace, polling events,
+// timing-event pool and captured graph.
+struct Lane {
+    hipStream_t stream = nullptr;
+    Workspace ws;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> tpool;  // timing events, reused across runs
+    GraphCache graph;
+    void create() {
+        HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    }
+    ~Lane() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        graph.reset();
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto& e : tpool) (void)hipEventDestroy(e);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+// Launch configuration picked by the autotuner for one kind of batch.
+struct TuneChoice {
+    int sys_tile = -1, blocks_per_xcd = -1, persistent = -1, lds = -1;
+    double seconds = 0.0;  // trial time of the chosen configuration
+    int trials = 0;
+};
+
 // Learned-guess network: FP32 parameters, Adam moments, gradient scratch,
 // and the sample recorder registered by dmri_guess_record.
 struct GuessModel {
@@ -237,18 +291,30 @@ struct GuessModel {
 struct dmri_ctx {
     int device = -1;
     bool host_only = true;
-    hipStream_t stream = nullptr;
     std::string last_error = "no error";
     std::vector<std::unique_ptr<dmri::ProblemRec>> problems;
     bool seq_set = false;
     double delta = 0, Delta = 0, dt = 0, theta = 0.5;
     int n_steps = 0;
     dmri::Options opt;
-    dmri::Workspace ws;
     dmri::GuessModel model;
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    std::vector<hipEvent_t> tpool;  // timing events, reused across runs
+    std::map<std::string, dmri::TuneChoice> tuned;  // autotuner cache
+    dmri::TuneChoice last_tune;
+    // Execution lanes: lane 0 serves the calling thread; runs over several
+    // problems may use more lanes, one host thread each.
+    std::vector<std::unique_ptr<dmri::Lane>> lanes;
 };
+
+namespace dmri {
+namespace {
+
+// The lane of the calling thread (set by the multi-problem scheduler).
+thread_local Lane* tl_lane = nullptr;
+
+Lane& lane(dmri_ctx* h) { return tl_lane ? *tl_lane : *h->lanes[0]; }
+
+}  // namespace
+}  // namespace dmri
 
 namespace dmri {
 namespace {
@@ -299,7 +365,7 @@ void upload_matrix(const ProblemRec& P, double dt, double th, DevMatrix<T>& A, h
 }
 
 void ensure_uploaded(dmri_ctx* h, ProblemRec& P, bool need32) {
-    hipStream_t st = h->stream;
+    hipStream_t st = lane(h).stream;
     if (!P.pattern_up) {
         build_padded(P);
         P.row_ptr.upload(P.pad_row_ptr.data(), P.pad_row_ptr.size(), st);
@@ -382,9 +448,9 @@ MlpDofs ensure_features(dmri_ctx* h, ProblemRec& P) {
                                  op.dof_D[i]);
             fl[i] = make_float2(static_cast<float>(op.dof_comp[i]), op.dof_membrane[i]);
         }
-        P.feat_geo.upload(geo.data(), n, h->stream);
-        P.feat_flags.upload(fl.data(), n, h->stream);
-        HIPCHK(hipStreamSynchronize(h->stream));
+        P.feat_geo.upload(geo.data(), n, lane(h).stream);
+        P.feat_flags.upload(fl.data(), n, lane(h).stream);
+        HIPCHK(hipStreamSynchronize(lane(h).stream));
         P.feat_up = true;
     }
     return MlpDofs{P.feat_geo.p, P.feat_flags.p};
@@ -441,13 +507,13 @@ int prepare_guess(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
         t.m = m + 1;
         extrap_weights(m, t.c);
         for (int k = 0; k <= m; ++k) t.u[k] = hs.u(k);
-        timer.run(6, [&] { launch_combine<T>(h->stream, g, t, hs.x()); });
+        timer.run(6, [&] { launch_combine<T>(lane(h).stream, g, t, hs.x()); });
         return 2;
     }
     if (og == 2 && hs.avail >= 2) {
         if constexpr (sizeof(T) == 8) {
             timer.run(5, [&] {
-                launch_mlp_guess(h->stream, g, h->model.theta.p, dofs, h->ws.gq.p,
+                launch_mlp_guess(lane(h).stream, g, h->model.theta.p, dofs, lane(h).ws.gq.p,
                                  mlp_step(h, tr, F, f, n), static_cast<int32_t>(n_sys), hs.u(0),
                                  hs.u(1), hs.x());
             });
@@ -469,7 +535,7 @@ void record_samples(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
                                                 static_cast<uint64_t>(M.rec_stride));
     if (offset >= nv) return;
     const int64_t cnt = (nv - offset + M.rec_stride - 1) / M.rec_stride;
-    launch_mlp_record(h->stream, g, dofs, h->ws.gq.p, mlp_step(h, tr, F, f, n),
+    launch_mlp_record(lane(h).stream, g, dofs, lane(h).ws.gq.p, mlp_step(h, tr, F, f, n),
                       static_cast<int32_t>(n_sys), u1, u2, un, M.rec_stride, offset, M.rec_count,
                       M.rec_cap, M.rec_X, M.rec_T);
     M.rec_count = std::min(M.rec_cap, M.rec_count + cnt);
@@ -512,14 +578,14 @@ struct KernelTimer {
             launch();
             return;
         }
-        while (h->tpool.size() < used + 2) {
+        while (lane(h).tpool.size() < used + 2) {
             hipEvent_t e;
             HIPCHK(hipEventCreate(&e));
-            h->tpool.push_back(e);
+            lane(h).tpool.push_back(e);
         }
-        HIPCHK(hipEventRecord(h->tpool[used], st));
+        HIPCHK(hipEventRecord(lane(h).tpool[used], st));
         launch();
-        HIPCHK(hipEventRecord(h->tpool[used + 1], st));
+        HIPCHK(hipEventRecord(lane(h).tpool[used + 1], st));
         used += 2;
     }
     void collect(BatchResult& res) {
@@ -527,7 +593,7 @@ struct KernelTimer {
         double tot = 0.0;
         for (size_t i = 0; i + 1 < used; i += 2) {
             float ms = 0.0f;
-            HIPCHK(hipEventElapsedTime(&ms, h->tpool[i], h->tpool[i + 1]));
+            HIPCHK(hipEventElapsedTime(&ms, lane(h).tpool[i], lane(h).tpool[i + 1]));
             tot += ms;
         }
         res.n_timed += static_cast<int64_t>(used / 2);
@@ -548,8 +614,8 @@ struct BatchSetup {
 
 BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
                        const double* d_q) {
-    hipStream_t st = h->stream;
-    Workspace& W = h->ws;
+    hipStream_t st = lane(h).stream;
+    Workspace& W = lane(h).ws;
     BatchSetup bs{};
     bs.herm = (P.op.form == FORM_TRANSFORMED) ? (h->opt.krylov != 2) : false;
     if (P.op.form == FORM_UFORM && h->opt.krylov == 1)
@@ -599,11 +665,11 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
 
 // Sum of the per-tile active counts after the work enqueued so far.
 int poll_active(dmri_ctx* h, const Geom& g, const SolverState& s) {
-    HIPCHK(hipMemcpyAsync(h->ws.h_active[0], s.n_active, sizeof(int32_t) * g.n_tiles,
-                          hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpyAsync(lane(h).ws.h_active[0], s.n_active, sizeof(int32_t) * g.n_tiles,
+                          hipMemcpyDeviceToHost, lane(h).stream));
+    HIPCHK(hipStreamSynchronize(lane(h).stream));
     int tot = 0;
-    for (int t = 0; t < g.n_tiles; ++t) tot += h->ws.h_active[0][t];
+    for (int t = 0; t < g.n_tiles; ++t) tot += lane(h).ws.h_active[0][t];
     return tot;
 }
 
@@ -616,7 +682,7 @@ int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const d
                 Coef lhs, typename Vec2Of<T>::type* x, typename Vec2Of<T>::type* r,
                 typename Vec2Of<T>::type* p, typename Vec2Of<T>::type* q, SolverState s,
                 KernelTimer& timer, int first_chunk, int max_iter) {
-    hipStream_t st = h->stream;
+    hipStream_t st = lane(h).stream;
     const Geom& g = bs.g;
     if (bs.persist) {
         timer.run(1, [&] {
@@ -630,20 +696,21 @@ int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const d
     int chunk = std::max(1, first_chunk);
     for (;;) {
         for (int i = 0; i < chunk; ++i) {
+            const int32_t k_iter = done + i + 1;
             timer.run(1, [&] { launch_spmv_dot<T>(st, g, Av, gq, lhs, bs.herm, p, q, s, bs.sc); });
             timer.run(2, [&] {
                 launch_update<T>(st, g, Av, gq, lhs, bs.herm, x, r, p, q, s, bs.sc);
             });
-            timer.run(3, [&] { launch_pupdate<T>(st, g, Av, gq, lhs, r, p, s); });
+            timer.run(3, [&] { launch_pupdate<T>(st, g, Av, gq, lhs, r, p, x, k_iter, s); });
         }
         done += chunk;
-        HIPCHK(hipMemcpyAsync(h->ws.h_active[slot], s.n_active, sizeof(int32_t) * g.n_tiles,
+        HIPCHK(hipMemcpyAsync(lane(h).ws.h_active[slot], s.n_active, sizeof(int32_t) * g.n_tiles,
                               hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(h->ev[slot], st));
+        HIPCHK(hipEventRecord(lane(h).ev[slot], st));
         if (pending) {
-            HIPCHK(hipEventSynchronize(h->ev[slot ^ 1]));
+            HIPCHK(hipEventSynchronize(lane(h).ev[slot ^ 1]));
             int tot = 0;
-            for (int t = 0; t < g.n_tiles; ++t) tot += h->ws.h_active[slot ^ 1][t];
+            for (int t = 0; t < g.n_tiles; ++t) tot += lane(h).ws.h_active[slot ^ 1][t];
             if (tot == 0) {
                 done -= chunk;  // the chunk just enqueued only early-exits
                 break;
@@ -683,7 +750,7 @@ template <typename T>
 void collect_result(dmri_ctx* h, const BatchSetup& bs, ProblemRec& P, StateBufs& sb,
                     const typename Vec2Of<T>::type* u, double2* d_sig, int64_t n_sys,
                     BatchResult& res) {
-    hipStream_t st = h->stream;
+    hipStream_t st = lane(h).stream;
     const double t0 = now_s();
     launch_signal<T>(st, bs.g, P.w.p, u, d_sig, static_cast<int32_t>(n_sys), bs.sc);
     res.iters.resize(n_sys);
@@ -695,7 +762,7 @@ void collect_result(dmri_ctx* h, const BatchSetup& bs, ProblemRec& P, StateBufs&
     HIPCHK(hipMemcpyAsync(res.rr.data(), sb.rr.p, sizeof(double) * n_sys, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(res.bb.data(), sb.bb.p, sizeof(double) * n_sys, hipMemcpyDeviceToHost, st));
     int32_t bar_err = 0;
-    HIPCHK(hipMemcpyAsync(&bar_err, h->ws.barrier.p + 32 * 10, sizeof(int32_t),
+    HIPCHK(hipMemcpyAsync(&bar_err, lane(h).ws.barrier.p + 32 * 10, sizeof(int32_t),
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (bar_err != 0)
@@ -710,8 +777,8 @@ template <typename T>
 void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, const double* d_b,
                  const double* d_q, double2* d_sig, BatchResult& res) {
     using V2 = typename Vec2Of<T>::type;
-    hipStream_t st = h->stream;
-    Workspace& W = h->ws;
+    hipStream_t st = lane(h).stream;
+    Workspace& W = lane(h).ws;
     const BatchSetup bs = setup_batch(h, P, n_sys, d_b, d_q);
     const Geom& g = bs.g;
     const size_t nv = static_cast<size_t>(g.n_rows) * g.ld, ld = static_cast<size_t>(g.ld);
@@ -743,12 +810,12 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     KernelTimer timer(h, st, h->opt.time_kernel);
     const double t0 = now_s();
     int last_iters = 8;
-    for (int n = 1; n <= N; ++n) {
+    auto step = [&](int n) {
         const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
         const int gm = prepare_guess<T>(h, g, dofs, tr, F, f, n, n_sys, hs, timer);
         timer.run(4, [&] {
             launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, bs.herm, gm, hs.u(0), hs.u(1), hs.x(), r,
-                           p, nullptr, nullptr, s, bs.sc);
+                           p, nullptr, nullptr, nullptr, s, bs.sc);
         });
         const int done = krylov_loop<T>(h, bs, Av, W.gq.p, lhs, hs.x(), r, p, q, s, timer,
                                         last_iters - 2, h->opt.max_iter);
@@ -759,12 +826,68 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
         }
         progress_line(h, n, N, done, t0);
         hs.advance();
+    };
+    // With the persistent solver no host decision is needed inside the time
+    // loop, so the whole loop can be captured once and replayed.
+    const bool use_graph = h->opt.graph && bs.persist && h->opt.time_kernel == 0 &&
+                           h->model.rec_cap == 0 && h->opt.progress == 0;
+    V2* u_final = nullptr;
+    if (use_graph) {
+        std::vector<uint64_t> key;
+        auto kp = [&](const void* ptr) { key.push_back(reinterpret_cast<uintptr_t>(ptr)); };
+        auto kd = [&](double v) {
+            uint64_t bits;
+            std::memcpy(&bits, &v, sizeof bits);
+            key.push_back(bits);
+        };
+        kp(&P);
+        kp(Av.K0);
+        kp(Av.aux);
+        kp(W.gq.p);
+        kp(bs.sc.partial);
+        kp(bs.bar.count);
+        kp(s.rho);
+        kp(h->model.theta.p);
+        for (V2* v : hs.ring) kp(v);
+        kp(r);
+        kp(p);
+        kp(q);
+        for (double v : {double(n_sys), double(N), double(sizeof(T)), double(bs.herm),
+                         double(g.S), double(bs.gp.B), h->opt.rtol, double(h->opt.max_iter),
+                         double(h->opt.guess), double(h->opt.extrap_order), h->dt, h->theta,
+                         h->delta, h->Delta})
+            kd(v);
+        GraphCache& gc = lane(h).graph;
+        if (gc.exec && gc.key == key) {
+            HIPCHK(hipGraphLaunch(gc.exec, st));
+            u_final = static_cast<V2*>(gc.final_u);
+        } else {
+            gc.reset();
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int n = 1; n <= N; ++n) step(n);
+            } catch (...) {
+                hipGraph_t broken = nullptr;
+                (void)hipStreamEndCapture(st, &broken);
+                if (broken) (void)hipGraphDestroy(broken);
+                throw;
+            }
+            HIPCHK(hipStreamEndCapture(st, &gc.graph));
+            HIPCHK(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
+            gc.key = key;
+            gc.final_u = hs.u(0);
+            HIPCHK(hipGraphLaunch(gc.exec, st));
+            u_final = hs.u(0);
+        }
+    } else {
+        for (int n = 1; n <= N; ++n) step(n);
+        u_final = hs.u(0);
     }
     HIPCHK(hipStreamSynchronize(st));
     res.t_solve = now_s() - t0;
     res.steps = N;
     timer.collect(res);
-    collect_result<T>(h, bs, P, W.outer, hs.u(0), d_sig, n_sys, res);
+    collect_result<T>(h, bs, P, W.outer, u_final, d_sig, n_sys, res);
     HIPCHK(hipMemcpyAsync(res.iters.data(), W.outer.iters_total.p, sizeof(int32_t) * n_sys,
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -780,20 +903,21 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
 // with FP64 dot products.
 void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
                        const double* d_q, double2* d_sig, BatchResult& res) {
-    hipStream_t st = h->stream;
-    Workspace& W = h->ws;
+    hipStream_t st = lane(h).stream;
+    Workspace& W = lane(h).ws;
     const BatchSetup bs = setup_batch(h, P, n_sys, d_b, d_q);
     const Geom& g = bs.g;
     const size_t nv = static_cast<size_t>(g.n_rows) * g.ld, ld = static_cast<size_t>(g.ld);
     History<double2> hs;
     hs.nh = history_len(h);
-    for (int i = 0; i < hs.nh + 4; ++i) W.vec64[i].alloc(2 * nv);
+    for (int i = 0; i < hs.nh + 5; ++i) W.vec64[i].alloc(2 * nv);
     for (int i = 0; i < 4; ++i) W.vec32[i].alloc(2 * nv);
     for (int i = 0; i <= hs.nh; ++i) hs.ring.push_back(reinterpret_cast<double2*>(W.vec64[i].p));
     // The refinement passes alternate x between hs.x() and x_alt.
     double2* x_alt = reinterpret_cast<double2*>(W.vec64[hs.nh + 1].p);
     double2* r64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 2].p);
     double2* p64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 3].p);
+    double2* b64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 4].p);  // right-hand side of the step
     float2* r32 = reinterpret_cast<float2*>(W.vec32[0].p);
     float2* dx = reinterpret_cast<float2*>(W.vec32[1].p);
     float2* p32 = reinterpret_cast<float2*>(W.vec32[2].p);
@@ -833,7 +957,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
         const int gm = prepare_guess<double>(h, g, dofs, tr, F, f, n, n_sys, hs, timer);
         timer.run(4, [&] {
             launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, gm, hs.u(0), hs.u(1),
-                                hs.x(), r64, p64, nullptr, nullptr, so, bs.sc);
+                                hs.x(), r64, p64, nullptr, nullptr, b64, so, bs.sc);
         });
         int step_iters = 0;
         for (int pass = 0; pass < h->opt.max_outer; ++pass) {
@@ -847,7 +971,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
             step_iters += it;
             timer.run(4, [&] {
                 launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, 3, hs.u(0), hs.u(1),
-                                    hs.x(), r64, p64, dx, x_alt, so, bs.sc);
+                                    hs.x(), r64, p64, dx, x_alt, b64, so, bs.sc);
             });
             std::swap(hs.ring[hs.nh], x_alt);
         }
@@ -903,8 +1027,8 @@ void fill_stats(dmri_stats* stats, const std::vector<int64_t>& owner_idx, const 
     stats->t_kernel_s += R.t_timed;
 }
 
-void run_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, const double* d_q,
-               double2* d_sig, BatchResult& R) {
+void run_batch_with(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
+                    const double* d_q, double2* d_sig, BatchResult& R) {
     if (h->opt.precision == 0) {
         solve_batch<double>(h, P, P.A64, n_sys, d_b, d_q, d_sig, R);
     } else if (h->opt.precision == 2) {
@@ -912,6 +1036,113 @@ void run_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, con
     } else {
         solve_batch_mixed(h, P, n_sys, d_b, d_q, d_sig, R);
     }
+}
+
+// Restores the context's options (and the sample recorder) on scope exit.
+struct OptionGuard {
+    dmri_ctx* h;
+    Options saved;
+    int64_t rec_cap;
+    explicit OptionGuard(dmri_ctx* hh) : h(hh), saved(hh->opt), rec_cap(hh->model.rec_cap) {}
+    ~OptionGuard() {
+        h->opt = saved;
+        h->model.rec_cap = rec_cap;
+    }
+};
+
+// Autotuner: times the first few steps of the batch under each candidate
+// launch configuration (tile width, blocks per XCD, persistent Krylov
+// kernel, LDS-staged SpMV) and keeps the fastest. Trials write their
+// signals to scratch and record no training samples.
+TuneChoice autotune(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
+                    const double* d_q) {
+    OptionGuard guard(h);
+    h->model.rec_cap = 0;
+    const int total = h->opt.n_steps > 0 ? std::min(h->opt.n_steps, h->n_steps) : h->n_steps;
+    h->opt.n_steps = std::max(1, std::min(4, total));
+    h->opt.progress = 0;
+    h->opt.time_kernel = 0;
+    DevBuf<double2> sig;
+    sig.alloc(static_cast<size_t>(n_sys));
+    const int s0 = guard.saved.sys_tile ? guard.saved.sys_tile : auto_tile(n_sys);
+    std::vector<TuneChoice> cands;
+    for (int S : {s0, s0 / 2}) {
+        if (S < 8) continue;
+        for (int bpx : {256, 512, 1024}) {
+            TuneChoice c;
+            c.sys_tile = S;
+            c.blocks_per_xcd = bpx;
+            c.persistent = 0;
+            c.lds = 0;
+            cands.push_back(c);
+        }
+        if (S >= 32) {
+            TuneChoice c;
+            c.sys_tile = S;
+            c.blocks_per_xcd = 512;
+            c.persistent = 0;
+            c.lds = 1;
+            cands.push_back(c);
+        }
+        if ((n_sys + S - 1) / S * S <= 64) {
+            TuneChoice c;
+            c.sys_tile = S;
+            c.blocks_per_xcd = 512;
+            c.persistent = 1;
+            c.lds = 0;
+            cands.push_back(c);
+        }
+    }
+    auto apply = [&](const TuneChoice& c) {
+        h->opt.sys_tile = c.sys_tile;
+        h->opt.blocks_per_xcd = c.blocks_per_xcd;
+        h->opt.persistent = c.persistent;
+        h->opt.lds = c.lds;
+    };
+    TuneChoice best;
+    best.seconds = 1e300;
+    {  // warm-up: allocations and first-touch costs stay out of the trials
+        apply(cands.front());
+        BatchResult R;
+        run_batch_with(h, P, n_sys, d_b, d_q, sig.p, R);
+    }
+    int trials = 0;
+    for (const TuneChoice& c : cands) {
+        apply(c);
+        BatchResult R;
+        const double t0 = now_s();
+        run_batch_with(h, P, n_sys, d_b, d_q, sig.p, R);
+        HIPCHK(hipStreamSynchronize(lane(h).stream));
+        const double t = now_s() - t0;
+        ++trials;
+        if (t < best.seconds) {
+            best = c;
+            best.seconds = t;
+        }
+    }
+    best.trials = trials;
+    return best;
+}
+
+void run_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, const double* d_q,
+               double2* d_sig, BatchResult& R) {
+    if (!h->opt.autotune) {
+        run_batch_with(h, P, n_sys, d_b, d_q, d_sig, R);
+        return;
+    }
+    const std::string key = std::to_string(reinterpret_cast<uintptr_t>(&P)) + "/" +
+                            std::to_string(n_sys) + "/" + std::to_string(h->opt.precision) + "/" +
+                            std::to_string(h->opt.krylov) + "/" + std::to_string(h->opt.sys_tile);
+    auto it = h->tuned.find(key);
+    if (it == h->tuned.end()) it = h->tuned.emplace(key, autotune(h, P, n_sys, d_b, d_q)).first;
+    const TuneChoice c = it->second;
+    h->last_tune = c;
+    OptionGuard guard(h);
+    h->opt.sys_tile = c.sys_tile;
+    h->opt.blocks_per_xcd = c.blocks_per_xcd;
+    h->opt.persistent = c.persistent;
+    h->opt.lds = c.lds;
+    run_batch_with(h, P, n_sys, d_b, d_q, d_sig, R);
 }
 
 dmri_status set_err(dmri_ctx* h, dmri_status c, const std::string& m) {
@@ -950,7 +1181,7 @@ constexpr char kModelMagic[8] = {'D', 'M', 'R', 'I', 'M', 'L', 'P', '1'};
 // New parameters; the Adam moments restart from zero.
 void set_guess_params(dmri_ctx* h, const float* host_theta) {
     GuessModel& M = h->model;
-    hipStream_t st = h->stream;
+    hipStream_t st = lane(h).stream;
     M.theta.alloc(kMlpParams);
     M.adam_m.alloc(kMlpParams);
     M.adam_v.alloc(kMlpParams);
@@ -971,7 +1202,7 @@ void grad_pass(dmri_ctx* h, int64_t n, const float* X, const float* T) {
     HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
     const int waves = std::max(4, 4 * n_cu);  // one block of four waves per CU
     M.partial.alloc(static_cast<size_t>(waves) * (kMlpParams + 1));
-    launch_mlp_grad(h->stream, n, X, T, M.theta.p, M.partial.p, waves, M.grad.p);
+    launch_mlp_grad(lane(h).stream, n, X, T, M.theta.p, M.partial.p, waves, M.grad.p);
 }
 
 }  // namespace
@@ -993,9 +1224,8 @@ dmri_status dmri_create(int device_ordinal, dmri_handle* out) {
             HIPCHK(hipSetDevice(device_ordinal));
             h->device = device_ordinal;
             h->host_only = false;
-            HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
+            h->lanes.push_back(std::make_unique<Lane>());
+            h->lanes.back()->create();
         } else if (device_ordinal != -1) {
             throw Error(DMRI_E_INVALID, "device_ordinal must be >= 0 or -1 (host only)");
         }
@@ -1007,19 +1237,9 @@ dmri_status dmri_create(int device_ordinal, dmri_handle* out) {
 void dmri_destroy(dmri_handle h) {
     if (!h) return;
     try {
-        if (!h->host_only) {
-            (void)hipSetDevice(h->device);
-            (void)hipStreamSynchronize(h->stream);
-        }
+        if (!h->host_only) (void)hipSetDevice(h->device);
+        h->lanes.clear();  // synchronizes and frees each lane's stream and workspace
         h->problems.clear();
-        h->ws.~Workspace();
-        new (&h->ws) Workspace();
-        if (!h->host_only) {
-            for (auto& e : h->ev)
-                if (e) (void)hipEventDestroy(e);
-            for (auto& e : h->tpool) (void)hipEventDestroy(e);
-            (void)hipStreamDestroy(h->stream);
-        }
     } catch (...) {
     }
     delete h;
@@ -1163,6 +1383,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "progress") o.progress = as_int(0, 1000000);
         else if (k == "ordering") o.ordering = as_int(0, 1);
         else if (k == "pencil") o.pencil = as_int(1, 4096);
+        else if (k == "concurrency") o.concurrency = as_int(1, 16);
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -1196,6 +1417,12 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "progress") *value = o.progress;
         else if (k == "ordering") *value = o.ordering;
         else if (k == "pencil") *value = o.pencil;
+        else if (k == "concurrency") *value = o.concurrency;
+        else if (k == "tuned_sys_tile") *value = h->last_tune.sys_tile;
+        else if (k == "tuned_blocks_per_xcd") *value = h->last_tune.blocks_per_xcd;
+        else if (k == "tuned_persistent") *value = h->last_tune.persistent;
+        else if (k == "tuned_lds") *value = h->last_tune.lds;
+        else if (k == "tuned_trials") *value = h->last_tune.trials;
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -1220,8 +1447,8 @@ dmri_status dmri_guess_get_params(dmri_handle h, float* params, int64_t n_params
             throw Error(DMRI_E_INVALID, "params must hold DMRI_GUESS_N_PARAMS floats");
         if (!h->model.set) throw Error(DMRI_E_STATE, "no guess network parameters set");
         HIPCHK(hipMemcpyAsync(params, h->model.theta.p, sizeof(float) * kMlpParams,
-                              hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
+                              hipMemcpyDeviceToHost, lane(h).stream));
+        HIPCHK(hipStreamSynchronize(lane(h).stream));
         return DMRI_OK;
     });
 }
@@ -1256,8 +1483,8 @@ dmri_status dmri_save_guess_model(dmri_handle h, const char* path) {
         if (!h->model.set) throw Error(DMRI_E_STATE, "no guess network parameters set");
         std::vector<float> theta(kMlpParams);
         HIPCHK(hipMemcpyAsync(theta.data(), h->model.theta.p, sizeof(float) * kMlpParams,
-                              hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
+                              hipMemcpyDeviceToHost, lane(h).stream));
+        HIPCHK(hipStreamSynchronize(lane(h).stream));
         std::FILE* fp = std::fopen(path, "wb");
         if (!fp) throw Error(DMRI_E_INVALID, std::string("cannot create ") + path);
         const int32_t dims[3] = {kMlpIn, kMlpHid, kMlpOut};
@@ -1306,7 +1533,7 @@ dmri_status dmri_guess_eval(dmri_handle h, int64_t n, const float* d_features,
         if (n < 1 || !d_features) throw Error(DMRI_E_INVALID, "need n >= 1 and features");
         if ((d_grad || loss) && !d_targets)
             throw Error(DMRI_E_INVALID, "gradient and loss need targets");
-        hipStream_t st = h->stream;
+        hipStream_t st = lane(h).stream;
         GuessModel& M = h->model;
         if (d_out) launch_mlp_forward(st, n, d_features, M.theta.p, d_out);
         if (d_grad || loss) {
@@ -1337,7 +1564,7 @@ dmri_status dmri_guess_train(dmri_handle h, int64_t n, const float* d_features,
         if (n < 1 || !d_features || !d_targets || n_iters < 1)
             throw Error(DMRI_E_INVALID, "need n >= 1, n_iters >= 1 and sample buffers");
         if (!(lr > 0.0) || !std::isfinite(lr)) throw Error(DMRI_E_INVALID, "lr must be > 0");
-        hipStream_t st = h->stream;
+        hipStream_t st = lane(h).stream;
         GuessModel& M = h->model;
         M.loss_hist.alloc(2);
         for (int32_t it = 0; it < n_iters; ++it) {
@@ -1387,14 +1614,18 @@ dmri_status dmri_run(dmri_handle h, int64_t n_pairs, const int32_t* problem_id, 
             stats->n_kernel_launches = 0;
             stats->t_kernel_s = 0.0;
         }
-        bool any_nc = false;
-        hipStream_t st = h->stream;
         // Group pairs by problem, keeping input order inside each group.
+        std::vector<std::pair<int32_t, std::vector<int64_t>>> groups;
         for (int32_t pid = 0; pid < static_cast<int32_t>(h->problems.size()); ++pid) {
             std::vector<int64_t> idx;
             for (int64_t i = 0; i < n_pairs; ++i)
                 if (problem_id[i] == pid) idx.push_back(i);
-            if (idx.empty()) continue;
+            if (!idx.empty()) groups.emplace_back(pid, std::move(idx));
+        }
+        std::atomic<bool> any_nc{false};
+        std::mutex mu;
+        auto run_group = [&](int32_t pid, const std::vector<int64_t>& idx) {
+            hipStream_t st = lane(h).stream;
             ProblemRec& P = get_problem(h, pid);
             const double ts = now_s();
             ensure_uploaded(h, P, h->opt.precision != 0);
@@ -1404,25 +1635,60 @@ dmri_status dmri_run(dmri_handle h, int64_t n_pairs, const int32_t* problem_id, 
                 hb[i] = b[idx[i]];
                 for (int a = 0; a < 3; ++a) hq[3 * i + a] = q[3 * idx[i] + a];
             }
-            h->ws.b_in.upload(hb.data(), ns, st);
-            h->ws.q_in.upload(hq.data(), 3 * ns, st);
-            h->ws.sig.alloc(ns);
-            if (stats) stats->t_setup_s += now_s() - ts;
+            Workspace& W = lane(h).ws;
+            W.b_in.upload(hb.data(), ns, st);
+            W.q_in.upload(hq.data(), 3 * ns, st);
+            W.sig.alloc(ns);
+            const double t_up = now_s() - ts;
             BatchResult R;
-            run_batch(h, P, ns, h->ws.b_in.p, h->ws.q_in.p, h->ws.sig.p, R);
+            run_batch(h, P, ns, W.b_in.p, W.q_in.p, W.sig.p, R);
             std::vector<double> hs(2 * ns);
-            HIPCHK(hipMemcpyAsync(hs.data(), h->ws.sig.p, sizeof(double2) * ns,
-                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(hs.data(), W.sig.p, sizeof(double2) * ns, hipMemcpyDeviceToHost,
+                                  st));
             HIPCHK(hipStreamSynchronize(st));
+            std::lock_guard<std::mutex> lock(mu);
             for (int64_t i = 0; i < ns; ++i) {
                 signal_out[2 * idx[i]] = hs[2 * i];
                 signal_out[2 * idx[i] + 1] = hs[2 * i + 1];
                 if (R.flags[i]) any_nc = true;
             }
+            if (stats) stats->t_setup_s += t_up;
             fill_stats(stats, idx, R, n_pairs);
+        };
+        // Several problems run concurrently, one lane (stream, workspace,
+        // host thread) each, unless a feature shares state across batches.
+        int n_lanes = std::min<int>(h->opt.concurrency, static_cast<int>(groups.size()));
+        if (h->opt.autotune || h->model.rec_cap > 0 || h->opt.graph) n_lanes = 1;
+        if (n_lanes <= 1) {
+            for (const auto& gr : groups) run_group(gr.first, gr.second);
+        } else {
+            while (static_cast<int>(h->lanes.size()) < n_lanes) {
+                h->lanes.push_back(std::make_unique<Lane>());
+                h->lanes.back()->create();
+            }
+            std::atomic<int> next{0};
+            std::exception_ptr first_error;
+            std::vector<std::thread> pool;
+            for (int t = 0; t < n_lanes; ++t) {
+                pool.emplace_back([&, t] {
+                    tl_lane = h->lanes[t].get();
+                    try {
+                        HIPCHK(hipSetDevice(h->device));
+                        for (int gi = next++; gi < static_cast<int>(groups.size()); gi = next++)
+                            run_group(groups[gi].first, groups[gi].second);
+                    } catch (...) {
+                        std::lock_guard<std::mutex> lock(mu);
+                        if (!first_error) first_error = std::current_exception();
+                        next = static_cast<int>(groups.size());
+                    }
+                    tl_lane = nullptr;
+                });
+            }
+            for (auto& th : pool) th.join();
+            if (first_error) std::rethrow_exception(first_error);
         }
         (void)t_start;
-        return any_nc ? DMRI_NOT_CONVERGED : DMRI_OK;
+        return any_nc.load() ? DMRI_NOT_CONVERGED : DMRI_OK;
     });
 }
 
@@ -1436,12 +1702,12 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
         if (n_pairs <= 0) return n_pairs == 0 ? DMRI_OK : set_err(h, DMRI_E_INVALID, "n_pairs < 0");
         if (!d_b || !d_q || !d_signal) throw Error(DMRI_E_INVALID, "NULL argument");
         ProblemRec& P = get_problem(h, problem_id);
-        hipStream_t saved = h->stream;
-        if (hip_stream) h->stream = static_cast<hipStream_t>(hip_stream);
+        hipStream_t saved = lane(h).stream;
+        if (hip_stream) lane(h).stream = static_cast<hipStream_t>(hip_stream);
         struct Restore {
             dmri_ctx* h;
             hipStream_t s;
-            ~Restore() { h->stream = s; }
+            ~Restore() { lane(h).stream = s; }
         } restore{h, saved};
         const double ts = now_s();
         ensure_uploaded(h, P, h->opt.precision != 0);
@@ -1477,7 +1743,7 @@ dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which
         ProblemRec& P = get_problem(h, problem_id);
         const bool f32 = h->opt.precision != 0;
         ensure_uploaded(h, P, f32);
-        hipStream_t st = h->stream;
+        hipStream_t st = lane(h).stream;
         const int S = h->opt.sys_tile ? h->opt.sys_tile : auto_tile(n_sys);
         const Geom g = make_geom(static_cast<int32_t>(P.op.n_dof), static_cast<int32_t>(n_sys), S,
                                  h->opt.blocks_per_xcd, h->opt.queue, h->opt.grab);

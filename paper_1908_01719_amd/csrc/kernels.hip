@@ -92,8 +92,8 @@ __device__ __forceinline__ void dot_acc(double& re, double& im, V2<T> a, V2<T> b
 
 template <typename T>
 __device__ __forceinline__ V2<T> cdivT(V2<T> a, T dr, T di) {
-    const T den = dr * dr + di * di;
-    return mk2<T>((a.x * dr + a.y * di) / den, (a.y * dr - a.x * di) / den);
+    const T inv = T(1) / (dr * dr + di * di);
+    return mk2<T>((a.x * dr + a.y * di) * inv, (a.y * dr - a.x * di) * inv);
 }
 
 // Jacobi diagonal of A_s at a row: dK0 + c dM_D + i d . dV.
@@ -563,9 +563,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lds(
     }
 }
 
-// One item of x += alpha p, r -= alpha q, z = D^-1 r with partial sums
-// rho' = r^H z (or r^T z) and ||r||^2.
-template <typename T, int S, bool HERM>
+// One item of x += alpha p (WITH_X), r -= alpha q, z = D^-1 r with partial
+// sums rho' = r^H z (or r^T z) and ||r||^2.
+template <typename T, int S, bool HERM, bool WITH_X = true>
 __device__ __forceinline__ void update_item(const Geom& g, int part, int j, size_t tb,
                                             const LaneCoef<T>& lc, T ar, T ai,
                                             const T* __restrict__ dK0,
@@ -580,20 +580,24 @@ __device__ __forceinline__ void update_item(const Geom& g, int part, int j, size
         for (int u = 0; u < kUs; ++u) {
             row[u] = slot_row<S>(first, u, r1, ok[u]);
             const size_t idx = tb + static_cast<size_t>(row[u]) * S;
-            pv[u] = p[idx];
+            if (WITH_X) {
+                pv[u] = p[idx];
+                xv[u] = x[idx];
+            }
             qv[u] = q[idx];
-            xv[u] = x[idx];
             rv[u] = r[idx];
         }
 #pragma unroll
         for (int u = 0; u < kUs; ++u) {
             if (!ok[u]) continue;
             const size_t idx = tb + static_cast<size_t>(row[u]) * S;
-            xv[u].x += ar * pv[u].x - ai * pv[u].y;
-            xv[u].y += ar * pv[u].y + ai * pv[u].x;
+            if (WITH_X) {
+                xv[u].x += ar * pv[u].x - ai * pv[u].y;
+                xv[u].y += ar * pv[u].y + ai * pv[u].x;
+                x[idx] = xv[u];
+            }
             rv[u].x -= ar * qv[u].x - ai * qv[u].y;
             rv[u].y -= ar * qv[u].y + ai * qv[u].x;
-            x[idx] = xv[u];
             r[idx] = rv[u];
             T dr, di;
             diag_at(dK0, daux, row[u], lc, dr, di);
@@ -603,7 +607,9 @@ __device__ __forceinline__ void update_item(const Geom& g, int part, int j, size
     });
 }
 
-// x += alpha p, r -= alpha q, z = D^-1 r; rho' = r^H z (or r^T z), ||r||^2.
+// r -= alpha q, z = D^-1 r; rho' = r^H z (or r^T z), ||r||^2. (The matching
+// x += alpha p is done by the direction update of the same iteration, which
+// reads p anyway.)
 template <typename T, int S, bool HERM>
 __global__ __launch_bounds__(kBlock) void k_update(
     Geom g, const T* __restrict__ dK0, const V4<T>* __restrict__ daux,
@@ -621,59 +627,75 @@ __global__ __launch_bounds__(kBlock) void k_update(
         const double2 al = act ? s.alpha[sys] : make_double2(0.0, 0.0);
         double acc[3] = {0.0, 0.0, 0.0};
         if (act)
-            update_item<T, S, HERM>(g, part, j, tb, lc, static_cast<T>(al.x),
-                                    static_cast<T>(al.y), dK0, daux, x, r, p, q, acc);
+            update_item<T, S, HERM, false>(g, part, j, tb, lc, static_cast<T>(al.x),
+                                           static_cast<T>(al.y), dK0, daux, x, r, p, q, acc);
         reduce_store<S, 3>(g, sc, item, j, acc, lds);
     }
 }
 
-// One item of p = D^-1 r + beta p.
+// One item of x += alpha p (do_x) and p = D^-1 r + beta p (do_p), per lane.
 template <typename T, int S>
 __device__ __forceinline__ void pupdate_item(const Geom& g, int part, int j, size_t tb,
-                                             const LaneCoef<T>& lc, T br, T bi,
+                                             const LaneCoef<T>& lc, T br, T bi, bool do_p,
+                                             T ar, T ai, bool do_x,
                                              const T* __restrict__ dK0,
                                              const V4<T>* __restrict__ daux,
-                                             const V2<T>* __restrict__ r, V2<T>* __restrict__ p) {
+                                             const V2<T>* __restrict__ r, V2<T>* __restrict__ p,
+                                             V2<T>* __restrict__ x) {
     sweep_static<S>(g, part, j, [&](int first, int r1) {
         int row[kUs];
         bool ok[kUs];
-        V2<T> rv[kUs], pv[kUs];
+        V2<T> rv[kUs], pv[kUs], xv[kUs];
 #pragma unroll
         for (int u = 0; u < kUs; ++u) {
             row[u] = slot_row<S>(first, u, r1, ok[u]);
             const size_t idx = tb + static_cast<size_t>(row[u]) * S;
-            rv[u] = r[idx];
             pv[u] = p[idx];
+            if (do_p) rv[u] = r[idx];
+            if (do_x) xv[u] = x[idx];
         }
 #pragma unroll
         for (int u = 0; u < kUs; ++u) {
             if (!ok[u]) continue;
-            T dr, di;
-            diag_at(dK0, daux, row[u], lc, dr, di);
-            const V2<T> z = cdivT<T>(rv[u], dr, di);
-            p[tb + static_cast<size_t>(row[u]) * S] =
-                mk2<T>(z.x + br * pv[u].x - bi * pv[u].y, z.y + br * pv[u].y + bi * pv[u].x);
+            const size_t idx = tb + static_cast<size_t>(row[u]) * S;
+            if (do_x)
+                x[idx] = mk2<T>(xv[u].x + ar * pv[u].x - ai * pv[u].y,
+                                xv[u].y + ar * pv[u].y + ai * pv[u].x);
+            if (do_p) {
+                T dr, di;
+                diag_at(dK0, daux, row[u], lc, dr, di);
+                const V2<T> z = cdivT<T>(rv[u], dr, di);
+                p[idx] = mk2<T>(z.x + br * pv[u].x - bi * pv[u].y,
+                                z.y + br * pv[u].y + bi * pv[u].x);
+            }
         }
     });
 }
 
-// p = D^-1 r + beta p.
+// End of Krylov iteration k: x += alpha p for every system that took part in
+// iteration k (its count equals k, including systems that stopped in it),
+// then p = D^-1 r + beta p for the systems still active.
 template <typename T, int S>
 __global__ __launch_bounds__(kBlock) void k_pupdate(Geom g, const T* __restrict__ dK0,
                                                     const V4<T>* __restrict__ daux,
                                                     const double4* __restrict__ gq, Coef lhs,
                                                     const V2<T>* __restrict__ r,
-                                                    V2<T>* __restrict__ p, SolverState s) {
+                                                    V2<T>* __restrict__ p, V2<T>* __restrict__ x,
+                                                    int32_t k_iter, SolverState s) {
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     for (int item = xcd; item < g.n_items; item += 8) {
         const int tile = item / g.n_parts, part = item - tile * g.n_parts;
         const int sys = tile * S + (threadIdx.x & 63) % S;
         const size_t tb = vbase(g, tile, S, sys);
-        if (!(sys < s.n_sys && s.active[sys])) continue;
+        const bool real = sys < s.n_sys;
+        const bool do_p = real && s.active[sys];
+        const bool do_x = real && s.iters[sys] == k_iter;
+        if (!(do_p || do_x)) continue;
         const LaneCoef<T> lc(gq[sys], lhs);
-        const double2 be = s.beta[sys];
-        pupdate_item<T, S>(g, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y), dK0,
-                           daux, r, p);
+        const double2 be = do_p ? s.beta[sys] : make_double2(0.0, 0.0);
+        const double2 al = s.alpha[sys];
+        pupdate_item<T, S>(g, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y), do_p,
+                           static_cast<T>(al.x), static_cast<T>(al.y), do_x, dK0, daux, r, p, x);
     }
 }
 
@@ -883,7 +905,7 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
             const LaneCoef<T> lc(gq[sys], lhs);
             const double2 be = sh_beta[sys];
             pupdate_item<T, S>(g, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y),
-                               dK0, daux, r, p);
+                               true, T(0), T(0), false, dK0, daux, r, p, x);
         }
         if (!grid_sync(bar)) break;
     }
@@ -902,6 +924,8 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
 
 // Start of a time step (or of an outer refinement pass): b = Right(u_prev),
 // x0 = guess, r = b - A x0, p = z = D^-1 r; partials rho, ||r||^2, ||b||^2.
+// At a step start (GM 0/1/2) b is also stored to bvec when it is given; a
+// refinement pass (GM 3) reads b from bvec instead of recomputing it.
 template <typename T, int S, bool HERM, int GM>
 __global__ __launch_bounds__(kBlock) void k_init(
     Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
@@ -909,7 +933,9 @@ __global__ __launch_bounds__(kBlock) void k_init(
     const T* __restrict__ dK0, const V4<T>* __restrict__ daux, const double4* __restrict__ gq,
     Coef lhs, Coef rhs, const V2<T>* __restrict__ u_prev, const V2<T>* __restrict__ u_prev2,
     V2<T>* __restrict__ x, V2<T>* __restrict__ r, V2<T>* __restrict__ p,
-    const float2* __restrict__ dx, V2<T>* __restrict__ x_out, SolverState s, Scratch sc) {
+    const float2* __restrict__ dx, V2<T>* __restrict__ x_out, V2<T>* __restrict__ bvec,
+    SolverState s, Scratch sc) {
+    constexpr bool kRhs = GM != 3;  // b formed from u_prev in this launch
     __shared__ double lds[kWaves * S * 4];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     for (int item = xcd; item < g.n_items; item += 8) {
@@ -934,7 +960,7 @@ __global__ __launch_bounds__(kBlock) void k_init(
 #pragma unroll
                 for (int u = 0; u < kB; ++u) {
                     const size_t jdx = tb + static_cast<size_t>(jj[u]) * S;
-                    uj[u] = u_prev[jdx];
+                    if (kRhs) uj[u] = u_prev[jdx];
                     if (GM == 1) {
                         const V2<T> u2 = u_prev2[jdx];
                         xj[u] = mk2<T>(u2.x, u2.y);
@@ -953,17 +979,26 @@ __global__ __launch_bounds__(kBlock) void k_init(
                     if (GM == 1) xj[u] = mk2<T>(T(2) * uj[u].x - xj[u].x, T(2) * uj[u].y - xj[u].y);
                     const V4<T> a = aux[k];
                     const T vl = ll.d0 * a.y + ll.d1 * a.z + ll.d2 * a.w;
-                    const T vr = lr.d0 * a.y + lr.d1 * a.z + lr.d2 * a.w;
                     const T al = K0[k] + ll.c * a.x;
-                    const T arr = Kr[k] + lr.c * a.x;
                     if (jj[u] == row) x0_own = xj[u];
-                    br += arr * uj[u].x - vr * uj[u].y;
-                    bi += arr * uj[u].y + vr * uj[u].x;
+                    if (kRhs) {
+                        const T vr = lr.d0 * a.y + lr.d1 * a.z + lr.d2 * a.w;
+                        const T arr = Kr[k] + lr.c * a.x;
+                        br += arr * uj[u].x - vr * uj[u].y;
+                        bi += arr * uj[u].y + vr * uj[u].x;
+                    }
                     axr += al * xj[u].x - vl * xj[u].y;
                     axi += al * xj[u].y + vl * xj[u].x;
                 }
             }
             const size_t idx = tb + static_cast<size_t>(row) * S;
+            if (!kRhs) {
+                const V2<T> bv = bvec[idx];
+                br = bv.x;
+                bi = bv.y;
+            } else if (bvec) {
+                bvec[idx] = mk2<T>(br, bi);
+            }
             const V2<T> rv = mk2<T>(br - axr, bi - axi);
             r[idx] = rv;
             T dr, di;
@@ -1322,13 +1357,14 @@ Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
 template <typename T>
 void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq, Coef lhs,
                  Coef rhs, bool herm, int guess_mode, const V2<T>* u_prev, const V2<T>* u_prev2,
-                 V2<T>* x, V2<T>* r, V2<T>* p, const float2* dx, V2<T>* x_out, SolverState s,
-                 Scratch sc) {
+                 V2<T>* x, V2<T>* r, V2<T>* p, const float2* dx, V2<T>* x_out, V2<T>* bvec,
+                 SolverState s, Scratch sc) {
+    if (guess_mode == 3 && !bvec) throw std::runtime_error("init: refinement needs the stored b");
     const dim3 grid = grid_of(g), block(kBlock);
 #define DMRI_INIT(H, GMV)                                                                     \
     k_init<T, S, H, GMV><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.Kr, A.aux, A.dK0, \
                                                  A.daux, gq, lhs, rhs, u_prev, u_prev2, x, r, p, \
-                                                 dx, x_out, s, sc)
+                                                 dx, x_out, bvec, s, sc)
 #define DMRI_INIT_GM(H)                      \
     switch (guess_mode) {                    \
         case 0: DMRI_INIT(H, 0); break;      \
@@ -1432,10 +1468,10 @@ void launch_krylov_persistent(hipStream_t st, const Geom& g, const MatView<T>& A
 
 template <typename T>
 void launch_pupdate(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
-                    Coef lhs, const V2<T>* r, V2<T>* p, SolverState s) {
+                    Coef lhs, const V2<T>* r, V2<T>* p, V2<T>* x, int32_t k_iter, SolverState s) {
     const dim3 grid = grid_of(g), block(kBlock);
     DMRI_DISPATCH_S(g.S, {
-        k_pupdate<T, S><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r, p, s);
+        k_pupdate<T, S><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r, p, x, k_iter, s);
     });
     check_launch("pupdate");
 }
@@ -1495,7 +1531,8 @@ void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
 #define DMRI_INST(T)                                                                          \
     template void launch_init<T>(hipStream_t, const Geom&, const MatView<T>&, const double4*,  \
                                  Coef, Coef, bool, int, const V2<T>*, const V2<T>*, V2<T>*,    \
-                                 V2<T>*, V2<T>*, const float2*, V2<T>*, SolverState, Scratch); \
+                                 V2<T>*, V2<T>*, const float2*, V2<T>*, V2<T>*, SolverState, \
+                                 Scratch);                                                     \
     template void launch_spmv_dot<T>(hipStream_t, const Geom&, const MatView<T>&,              \
                                      const double4*, Coef, bool, const V2<T>*, V2<T>*,         \
                                      SolverState, Scratch);                                    \
@@ -1503,7 +1540,8 @@ void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
                                    const double4*, Coef, bool, V2<T>*, V2<T>*, const V2<T>*,   \
                                    const V2<T>*, SolverState, Scratch);                        \
     template void launch_pupdate<T>(hipStream_t, const Geom&, const MatView<T>&,               \
-                                    const double4*, Coef, const V2<T>*, V2<T>*, SolverState);  \
+                                    const double4*, Coef, const V2<T>*, V2<T>*, V2<T>*,        \
+                                    int32_t, SolverState);                                     \
     template void launch_signal<T>(hipStream_t, const Geom&, const double*, const V2<T>*,      \
                                    double2*, int32_t, Scratch);                                \
     template void launch_apply<T>(hipStream_t, const Geom&, const MatView<T>&, int,            \

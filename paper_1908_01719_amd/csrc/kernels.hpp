@@ -124,7 +124,7 @@ void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const doubl
                  const typename Vec2Of<T>::type* u_prev, const typename Vec2Of<T>::type* u_prev2,
                  typename Vec2Of<T>::type* x, typename Vec2Of<T>::type* r,
                  typename Vec2Of<T>::type* p, const float2* dx, typename Vec2Of<T>::type* x_out,
-                 SolverState s, Scratch sc);
+                 typename Vec2Of<T>::type* bvec, SolverState s, Scratch sc);
 
 // Start of an FP32 inner solve on the FP64 residual r64 of the systems still
 // active in `outer`: r = (float) r64, dx = 0, p = D^-1 r (FP32 operator).
@@ -145,9 +145,12 @@ void launch_update(hipStream_t st, const Geom& g, const MatView<T>& A, const dou
                    const typename Vec2Of<T>::type* q, SolverState s, Scratch sc);
 
 template <typename T>
+// End of Krylov iteration k_iter (1-based within the solve): x += alpha p
+// for the systems that took part in it, p = D^-1 r + beta p for the systems
+// still active.
 void launch_pupdate(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
                     Coef lhs, const typename Vec2Of<T>::type* r, typename Vec2Of<T>::type* p,
-                    SolverState s);
+                    typename Vec2Of<T>::type* x, int32_t k_iter, SolverState s);
 
 template <typename T>
 void launch_signal(hipStream_t st, const Geom& g, const double* w,

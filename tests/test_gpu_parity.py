@@ -344,3 +344,77 @@ def test_extrapolation_orders_match_oracle(Sim, order, precision):
     _say("order %d precision %d: max err %.2e, iterations %d (previous-step guess %d)"
          % (order, precision, err.max(), st["total_iterations"], st0["total_iterations"]))
     assert err.max() < 1e-9
+
+
+def test_graph_replay_matches_eager(Sim):
+    # The persistent path's time loop captured in a HIP graph: the first run
+    # captures, later runs replay, with eager runs in between; every replay
+    # gives the eager signals bit for bit and the oracle's within 1e-9.
+    prob, b, q = _cyl_case()
+    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.set_options(rtol=1e-12, persistent=1, graph=0)
+        eager, _ = sim.dmri_run([pid] * len(b), b, q)
+        runs = []
+        for k in range(3):
+            sim.set_options(graph=1)
+            sig, st = sim.dmri_run([pid] * len(b), b, q)
+            assert st["status"] == "DMRI_OK"
+            runs.append(sig)
+            sim.set_options(graph=0)
+            again, _ = sim.dmri_run([pid] * len(b), b, q)
+            assert np.array_equal(again, eager)
+    for sig in runs:
+        assert np.array_equal(sig, eager)
+    assert rel_err(eager, ref, ref[0]).max() < 1e-9
+
+
+def test_autotune_matches_oracle(Sim):
+    prob, b, q = _cyl_case()
+    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        assert sim.dmri_get_option("tuned_sys_tile") == -1
+        sim.set_options(rtol=1e-12, autotune=1)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+        choice = [sim.dmri_get_option(k) for k in ("tuned_sys_tile", "tuned_blocks_per_xcd",
+                                                     "tuned_persistent", "tuned_lds")]
+        trials = sim.dmri_get_option("tuned_trials")
+        sig2, _ = sim.dmri_run([pid] * len(b), b, q)  # cached choice, no new trials
+        assert sim.dmri_get_option("tuned_trials") == trials
+        # the user's own options are restored after the tuned run
+        assert sim.dmri_get_option("sys_tile") == 0
+    _say("autotune choice %s after %d trials" % (choice, trials))
+    assert choice[0] in (8, 16) and trials >= 2
+    for s_ in (sig, sig2):
+        assert rel_err(s_, ref, ref[0]).max() < 1e-9
+
+
+def test_concurrent_problems_match_sequential(Sim):
+    # Meshes of uneven size in one run: with concurrency each problem runs on
+    # its own lane (stream, workspace, host thread); the signals are the same
+    # bit for bit as one after another, and match the oracle.
+    probs = [di.cylinder_box(n=n, half=6.0, r=r, kappa=5e-3, D_in=1.5e-3)
+             for n, r in ((8, 4.0), (11, 4.3), (6, 3.5))]
+    b = np.array([0.0, 800.0, 2500.0, 4000.0])
+    q = di.fibonacci_directions(4)
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pids = [sim.add_problem(p) for p in probs]
+        sim.set_options(rtol=1e-12)
+        pid_arr = np.repeat(pids, len(b))
+        bb = np.tile(b, len(pids))
+        qq = np.tile(q, (len(pids), 1))
+        out = {}
+        for c in (1, 3):
+            sim.set_options(concurrency=c)
+            out[c], st = sim.dmri_run(pid_arr, bb, qq)
+            assert st["status"] == "DMRI_OK"
+    assert np.array_equal(out[1], out[3])
+    for k, prob in enumerate(probs):
+        ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+        sig = out[3][k * len(b):(k + 1) * len(b)]
+        assert rel_err(sig, ref, ref[0]).max() < 1e-9
