@@ -162,6 +162,11 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *               polynomial through u^{n-1}, ..., u^{n-1-p} at t^n, i.e.
  *               x0 = sum_k (-1)^k C(p+1, k+1) u^{n-1-k}; early steps use the
  *               history available
+ *  "extrap_damp" 1 = use p + 2 past solutions with weights that reproduce
+ *               polynomials of degree <= p and cancel a sign-alternating
+ *               sequence (the components the theta = 1/2 scheme barely
+ *               damps, which plain extrapolation amplifies by 2^(p+1))
+ *               (default); 0 = plain polynomial extrapolation
  *  "sys_tile"   systems per lane group: 0 = auto, or 8, 16, 32, 64
  *  "graph"      1 = when the Krylov solves run in the persistent kernel
  *               (no host decisions inside the time loop), capture the whole
@@ -201,6 +206,16 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *               swept z-, y-, x-major, bounding the index distance between
  *               mesh neighbours
  *  "pencil"     pencil width in cells (default 16)
+ *  "sort_systems" 1 = order the systems of a batch before tiling, so tiles
+ *               of similar systems converge and leave the Krylov loop
+ *               together (default): by the iterations each (problem, b, q)
+ *               needed in its last run in this handle when all are known,
+ *               else by b; 0 = input order. Results are returned in input
+ *               order and do not depend on the setting
+ *  "xcd_split"  1 = every tile of systems is split into 8 row parts, one
+ *               per XCD, so the tiles still iterating keep the whole chip
+ *               busy; 0 = tiles split only as far as needed for a multiple
+ *               of 8 work items (default)
  *  "concurrency" k > 1: a dmri_run over several problems runs up to k of
  *               them at once, each on its own stream and workspace driven by
  *               its own host thread (meshes of uneven size share the GPU);

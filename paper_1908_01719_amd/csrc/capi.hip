@@ -131,6 +131,7 @@ struct Options {
     int max_iter = 2000;
     int guess = 1;
     int extrap_order = 3;
+    int extrap_damp = 1;
     int sys_tile = 0;
     int graph = 0;
     int autotune = 0;
@@ -147,6 +148,8 @@ struct Options {
     int ordering = 1;
     int pencil = 16;
     int concurrency = 1;
+    int sort_systems = 1;
+    int xcd_split = 0;
 };
 
 // Per-system Krylov state arrays of one solver level.
@@ -300,6 +303,10 @@ struct dmri_ctx {
     dmri::GuessModel model;
     std::map<std::string, dmri::TuneChoice> tuned;  // autotuner cache
     dmri::TuneChoice last_tune;
+    // Krylov iterations each (problem, b, q) system needed in its last run:
+    // the order in which later batches tile their systems.
+    std::map<std::string, int64_t> sys_cost;
+    std::mutex sys_cost_mu;
     // Execution lanes: lane 0 serves the calling thread; runs over several
     // problems may use more lanes, one host thread each.
     std::vector<std::unique_ptr<dmri::Lane>> lanes;
@@ -312,6 +319,51 @@ namespace {
 thread_local Lane* tl_lane = nullptr;
 
 Lane& lane(dmri_ctx* h) { return tl_lane ? *tl_lane : *h->lanes[0]; }
+
+std::string sys_key(int32_t pid, double b, const double* q) {
+    std::string k(reinterpret_cast<const char*>(&pid), sizeof pid);
+    k.append(reinterpret_cast<const char*>(&b), sizeof b);
+    k.append(reinterpret_cast<const char*>(q), 3 * sizeof(double));
+    return k;
+}
+
+// Order of the systems of a batch for tiling: by the iterations each needed
+// in its last run when every system has one, otherwise by b (larger b needs
+// more iterations). Stable, so ties keep the input order.
+void order_systems(dmri_ctx* h, int32_t pid, const double* b, const double* q,
+                   std::vector<int64_t>& idx) {
+    std::vector<int64_t> cost(idx.size(), -1);
+    bool all = true;
+    {
+        std::lock_guard<std::mutex> lock(h->sys_cost_mu);
+        for (size_t i = 0; i < idx.size(); ++i) {
+            auto it = h->sys_cost.find(sys_key(pid, b[idx[i]], q + 3 * idx[i]));
+            if (it == h->sys_cost.end()) {
+                all = false;
+                break;
+            }
+            cost[i] = it->second;
+        }
+    }
+    std::vector<size_t> perm(idx.size());
+    for (size_t i = 0; i < perm.size(); ++i) perm[i] = i;
+    if (all)
+        std::stable_sort(perm.begin(), perm.end(),
+                         [&](size_t a, size_t c) { return cost[a] < cost[c]; });
+    else
+        std::stable_sort(perm.begin(), perm.end(),
+                         [&](size_t a, size_t c) { return b[idx[a]] < b[idx[c]]; });
+    std::vector<int64_t> out(idx.size());
+    for (size_t i = 0; i < perm.size(); ++i) out[i] = idx[perm[i]];
+    idx.swap(out);
+}
+
+void remember_costs(dmri_ctx* h, int32_t pid, const double* b, const double* q,
+                    const std::vector<int64_t>& idx, const std::vector<int32_t>& iters) {
+    std::lock_guard<std::mutex> lock(h->sys_cost_mu);
+    for (size_t i = 0; i < idx.size() && i < iters.size(); ++i)
+        h->sys_cost[sys_key(pid, b[idx[i]], q + 3 * idx[i])] = iters[i];
+}
 
 }  // namespace
 }  // namespace dmri
@@ -478,7 +530,8 @@ struct History {
 // History length needed by the guess options: polynomial extrapolation of
 // order p uses p + 1 past solutions; the learned guess uses two.
 int history_len(const dmri_ctx* h) {
-    return h->opt.guess == 1 ? std::max(2, h->opt.extrap_order + 1) : 2;
+    if (h->opt.guess != 1) return 2;
+    return std::min(kMaxHist, std::max(2, h->opt.extrap_order + 1 + (h->opt.extrap_damp ? 1 : 0)));
 }
 
 // Weights of the order-p polynomial through u^{n-1}, ..., u^{n-1-p} on equal
@@ -491,6 +544,35 @@ void extrap_weights(int p, double* c) {
     }
 }
 
+// Damped extrapolation over p + 2 past solutions: the weights c_0..c_{p+1}
+// reproduce every polynomial of degree <= p one step ahead and give zero
+// response to a sequence alternating in sign from step to step (the
+// components the theta = 1/2 scheme barely damps, which the plain
+// extrapolation amplifies by 2^(p+1)). Solves the (p+2) x (p+2) system
+//   sum_k c_k k^j = (-1)^j (j = 0..p),  sum_k c_k (-1)^k = 0.
+void extrap_weights_damped(int p, double* c) {
+    const int n = p + 2;
+    double A[kMaxHist][kMaxHist + 1];
+    for (int j = 0; j <= p; ++j) {
+        for (int k = 0; k < n; ++k) A[j][k] = std::pow(static_cast<double>(k), j);
+        A[j][n] = (j & 1) ? -1.0 : 1.0;
+    }
+    for (int k = 0; k < n; ++k) A[p + 1][k] = (k & 1) ? -1.0 : 1.0;
+    A[p + 1][n] = 0.0;
+    for (int col = 0; col < n; ++col) {  // Gaussian elimination, partial pivoting
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+        for (int k = 0; k <= n; ++k) std::swap(A[col][k], A[piv][k]);
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const double f = A[r][col] / A[col][col];
+            for (int k = col; k <= n; ++k) A[r][k] -= f * A[col][k];
+        }
+    }
+    for (int k = 0; k < n; ++k) c[k] = A[k][n] / A[k][k];
+}
+
 // Start of step n: writes the guess into hist.x() when it is not formed
 // inside k_init, and returns k_init's guess mode (0 = u^{n-1}, 1 = linear
 // extrapolation inside k_init, 2 = x already holds the guess).
@@ -500,13 +582,19 @@ int prepare_guess(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
                   int64_t n_sys, const History<typename Vec2Of<T>::type>& hs, Timer& timer) {
     const int og = h->opt.guess;
     if (og == 1) {
-        const int m = std::min(h->opt.extrap_order, hs.avail - 1);
-        if (m <= 0) return 0;
-        if (m == 1) return 1;
+        const int p = h->opt.extrap_order;
         ExtrapTerms<T> t{};
-        t.m = m + 1;
-        extrap_weights(m, t.c);
-        for (int k = 0; k <= m; ++k) t.u[k] = hs.u(k);
+        if (h->opt.extrap_damp && hs.avail >= p + 2 && p + 2 <= kMaxHist) {
+            t.m = p + 2;
+            extrap_weights_damped(p, t.c);
+        } else {
+            const int m = std::min(p, hs.avail - 1);
+            if (m <= 0) return 0;
+            if (m == 1) return 1;
+            t.m = m + 1;
+            extrap_weights(m, t.c);
+        }
+        for (int k = 0; k < t.m; ++k) t.u[k] = hs.u(k);
         timer.run(6, [&] { launch_combine<T>(lane(h).stream, g, t, hs.x()); });
         return 2;
     }
@@ -622,7 +710,7 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
         throw Error(DMRI_E_INVALID, "CG needs the Hermitian (periodic-box) operator; use COCG");
     const int S = h->opt.sys_tile ? h->opt.sys_tile : auto_tile(n_sys);
     bs.g = make_geom(static_cast<int32_t>(P.op.n_dof), static_cast<int32_t>(n_sys), S,
-                     h->opt.blocks_per_xcd, h->opt.queue, h->opt.grab);
+                     h->opt.blocks_per_xcd, h->opt.queue, h->opt.grab, h->opt.xcd_split != 0);
     bs.g.nt = h->opt.nt;
     bs.g.lds = h->opt.lds;
     const Geom& g = bs.g;
@@ -961,7 +1049,13 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
         });
         int step_iters = 0;
         for (int pass = 0; pass < h->opt.max_outer; ++pass) {
-            if (poll_active(h, g, so) == 0) break;
+            const int still = poll_active(h, g, so);
+            if (h->opt.progress > 0 && n % h->opt.progress == 0) {
+                std::fprintf(stderr, "[dmri] step %d refinement pass %d: %d systems above rtol\n",
+                             n, pass, still);
+                std::fflush(stderr);
+            }
+            if (still == 0) break;
             launch_inner_start(st, g, A32, W.gq.p, lhs, bs.herm, r64, W.outer.active.p, r32, dx,
                                p32, si, bs.sc);
             const int it = krylov_loop<float>(h, bs, A32, W.gq.p, lhs, dx, r32, p32, q32, si,
@@ -1364,6 +1458,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         } else if (k == "max_iter") o.max_iter = as_int(1, 1000000);
         else if (k == "guess") o.guess = as_int(0, 2);
         else if (k == "extrap_order") o.extrap_order = as_int(1, kMaxHist - 1);
+        else if (k == "extrap_damp") o.extrap_damp = as_int(0, 1);
         else if (k == "sys_tile") {
             int t = as_int(0, 64);
             if (t != 0 && t != 8 && t != 16 && t != 32 && t != 64)
@@ -1384,6 +1479,8 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "ordering") o.ordering = as_int(0, 1);
         else if (k == "pencil") o.pencil = as_int(1, 4096);
         else if (k == "concurrency") o.concurrency = as_int(1, 16);
+        else if (k == "sort_systems") o.sort_systems = as_int(0, 1);
+        else if (k == "xcd_split") o.xcd_split = as_int(0, 1);
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -1402,6 +1499,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "max_iter") *value = o.max_iter;
         else if (k == "guess") *value = o.guess;
         else if (k == "extrap_order") *value = o.extrap_order;
+        else if (k == "extrap_damp") *value = o.extrap_damp;
         else if (k == "sys_tile") *value = o.sys_tile;
         else if (k == "graph") *value = o.graph;
         else if (k == "autotune") *value = o.autotune;
@@ -1418,6 +1516,8 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "ordering") *value = o.ordering;
         else if (k == "pencil") *value = o.pencil;
         else if (k == "concurrency") *value = o.concurrency;
+        else if (k == "sort_systems") *value = o.sort_systems;
+        else if (k == "xcd_split") *value = o.xcd_split;
         else if (k == "tuned_sys_tile") *value = h->last_tune.sys_tile;
         else if (k == "tuned_blocks_per_xcd") *value = h->last_tune.blocks_per_xcd;
         else if (k == "tuned_persistent") *value = h->last_tune.persistent;
@@ -1624,7 +1724,11 @@ dmri_status dmri_run(dmri_handle h, int64_t n_pairs, const int32_t* problem_id, 
         }
         std::atomic<bool> any_nc{false};
         std::mutex mu;
-        auto run_group = [&](int32_t pid, const std::vector<int64_t>& idx) {
+        auto run_group = [&](int32_t pid, std::vector<int64_t> idx) {
+            // Tiles of systems with similar b converge together, so whole tiles
+            // drop out of the Krylov loop early (results do not depend on the
+            // position of a system in the batch).
+            if (h->opt.sort_systems) order_systems(h, pid, b, q, idx);
             hipStream_t st = lane(h).stream;
             ProblemRec& P = get_problem(h, pid);
             const double ts = now_s();
@@ -1654,6 +1758,7 @@ dmri_status dmri_run(dmri_handle h, int64_t n_pairs, const int32_t* problem_id, 
             }
             if (stats) stats->t_setup_s += t_up;
             fill_stats(stats, idx, R, n_pairs);
+            remember_costs(h, pid, b, q, idx, R.iters);
         };
         // Several problems run concurrently, one lane (stream, workspace,
         // host thread) each, unless a feature shares state across batches.
@@ -1722,10 +1827,49 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
             stats->t_kernel_s = 0.0;
         }
         BatchResult R;
-        run_batch(h, P, n_pairs, d_b, d_q, reinterpret_cast<double2*>(d_signal), R);
         std::vector<int64_t> idx(n_pairs);
         for (int64_t i = 0; i < n_pairs; ++i) idx[i] = i;
+        std::vector<double> hb(n_pairs), hq(3 * n_pairs);
+        if (h->opt.sort_systems) {
+            HIPCHK(hipMemcpyAsync(hb.data(), d_b, sizeof(double) * n_pairs, hipMemcpyDeviceToHost,
+                                  lane(h).stream));
+            HIPCHK(hipMemcpyAsync(hq.data(), d_q, sizeof(double) * 3 * n_pairs,
+                                  hipMemcpyDeviceToHost, lane(h).stream));
+            HIPCHK(hipStreamSynchronize(lane(h).stream));
+            order_systems(h, problem_id, hb.data(), hq.data(), idx);
+        }
+        bool identity = true;
+        for (int64_t i = 0; i < n_pairs; ++i) identity &= idx[i] == i;
+        if (identity) {
+            run_batch(h, P, n_pairs, d_b, d_q, reinterpret_cast<double2*>(d_signal), R);
+        } else {
+            // Sorted copies of b and q in the lane's workspace; signals are
+            // scattered back to the caller's order.
+            hipStream_t st = lane(h).stream;
+            std::vector<double> sb(n_pairs), sq(3 * n_pairs);
+            for (int64_t i = 0; i < n_pairs; ++i) {
+                sb[i] = hb[idx[i]];
+                for (int a = 0; a < 3; ++a) sq[3 * i + a] = hq[3 * idx[i] + a];
+            }
+            Workspace& W = lane(h).ws;
+            W.b_in.upload(sb.data(), n_pairs, st);
+            W.q_in.upload(sq.data(), 3 * n_pairs, st);
+            W.sig.alloc(n_pairs);
+            run_batch(h, P, n_pairs, W.b_in.p, W.q_in.p, W.sig.p, R);
+            std::vector<double> ss(2 * n_pairs), out(2 * n_pairs);
+            HIPCHK(hipMemcpyAsync(ss.data(), W.sig.p, sizeof(double2) * n_pairs,
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t i = 0; i < n_pairs; ++i) {
+                out[2 * idx[i]] = ss[2 * i];
+                out[2 * idx[i] + 1] = ss[2 * i + 1];
+            }
+            HIPCHK(hipMemcpyAsync(d_signal, out.data(), sizeof(double2) * n_pairs,
+                                  hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
         fill_stats(stats, idx, R, n_pairs);
+        if (h->opt.sort_systems) remember_costs(h, problem_id, hb.data(), hq.data(), idx, R.iters);
         for (int32_t fl : R.flags)
             if (fl) return DMRI_NOT_CONVERGED;
         return DMRI_OK;

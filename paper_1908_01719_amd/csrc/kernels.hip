@@ -1324,7 +1324,7 @@ void launch_fin(hipStream_t st, const Geom& g, SolverState s, Scratch sc, double
 // ------------------------------------------------------------- launchers
 
 Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd, int32_t queue,
-               int32_t grab) {
+               int32_t grab, bool xcd_split) {
     Geom g{};
     g.queue = queue;
     g.grab = std::max(1, grab);
@@ -1332,7 +1332,10 @@ Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
     g.S = S;
     g.n_tiles = std::max(1, (n_sys + S - 1) / S);
     g.ld = g.n_tiles * S;
-    g.n_parts = 8 / std::gcd(g.n_tiles, 8);
+    // Every tile split into 8 row parts (one per XCD) keeps all XCDs busy
+    // when tiles leave the Krylov loop at different times; otherwise tiles
+    // are only split as far as needed for a multiple of 8 items.
+    g.n_parts = xcd_split ? 8 : 8 / std::gcd(g.n_tiles, 8);
     g.n_items = g.n_tiles * g.n_parts;
     g.chunk_rows = kUs * kWaves * (64 / S);
     int32_t pr = (n_rows + g.n_parts - 1) / g.n_parts;

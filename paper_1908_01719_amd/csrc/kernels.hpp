@@ -113,7 +113,7 @@ struct Scratch {
 };
 
 Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd, int32_t queue,
-               int32_t grab);
+               int32_t grab, bool xcd_split = false);
 
 // guess_mode: 0 x0 = u_prev, 1 x0 = 2 u_prev - u_prev2 (x0 written to x),
 // 2 x0 given in x, 3 x0 = x + dx (mixed-precision correction, written to
