@@ -1064,7 +1064,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
             if (pass == 0) last_first_pass = it;
             step_iters += it;
             timer.run(4, [&] {
-                launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, 3, hs.u(0), hs.u(1),
+                launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, 4, hs.u(0), hs.u(1),
                                     hs.x(), r64, p64, dx, x_alt, b64, so, bs.sc);
             });
             std::swap(hs.ring[hs.nh], x_alt);

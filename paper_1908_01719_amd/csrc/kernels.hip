@@ -925,7 +925,9 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
 // Start of a time step (or of an outer refinement pass): b = Right(u_prev),
 // x0 = guess, r = b - A x0, p = z = D^-1 r; partials rho, ||r||^2, ||b||^2.
 // At a step start (GM 0/1/2) b is also stored to bvec when it is given; a
-// refinement pass (GM 3) reads b from bvec instead of recomputing it.
+// refinement pass (GM 3) reads b from bvec instead of recomputing it. GM 4
+// is the cheaper refinement pass: r -= A dx (FP64 operator, only the FP32
+// correction dx is gathered) and x_out = x + dx.
 template <typename T, int S, bool HERM, int GM>
 __global__ __launch_bounds__(kBlock) void k_init(
     Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
@@ -935,7 +937,7 @@ __global__ __launch_bounds__(kBlock) void k_init(
     V2<T>* __restrict__ x, V2<T>* __restrict__ r, V2<T>* __restrict__ p,
     const float2* __restrict__ dx, V2<T>* __restrict__ x_out, V2<T>* __restrict__ bvec,
     SolverState s, Scratch sc) {
-    constexpr bool kRhs = GM != 3;  // b formed from u_prev in this launch
+    constexpr bool kRhs = GM < 3;  // b formed from u_prev in this launch
     __shared__ double lds[kWaves * S * 4];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     for (int item = xcd; item < g.n_items; item += 8) {
@@ -970,6 +972,9 @@ __global__ __launch_bounds__(kBlock) void k_init(
                         const V2<T> xo = x[jdx];
                         const float2 d = dx[jdx];
                         xj[u] = mk2<T>(xo.x + static_cast<T>(d.x), xo.y + static_cast<T>(d.y));
+                    } else if (GM == 4) {
+                        const float2 d = dx[jdx];
+                        xj[u] = mk2<T>(static_cast<T>(d.x), static_cast<T>(d.y));
                     }
                 }
 #pragma unroll
@@ -999,12 +1004,18 @@ __global__ __launch_bounds__(kBlock) void k_init(
             } else if (bvec) {
                 bvec[idx] = mk2<T>(br, bi);
             }
-            const V2<T> rv = mk2<T>(br - axr, bi - axi);
+            V2<T> rv;
+            if (GM == 4) {
+                const V2<T> r_old = r[idx];
+                rv = mk2<T>(r_old.x - axr, r_old.y - axi);
+            } else {
+                rv = mk2<T>(br - axr, bi - axi);
+            }
             r[idx] = rv;
             T dr, di;
             diag_at(dK0, daux, row, ll, dr, di);
             const V2<T> z = cdivT<T>(rv, dr, di);
-            if (GM != 3) p[idx] = z;
+            if (GM < 3) p[idx] = z;
             dot_acc<HERM, T>(acc[0], acc[1], rv, z);
             acc[2] += double(rv.x) * rv.x + double(rv.y) * rv.y;
             acc[3] += double(br) * br + double(bi) * bi;
@@ -1013,6 +1024,10 @@ __global__ __launch_bounds__(kBlock) void k_init(
             // (GM 0/1), a second buffer when they read x (GM 3).
             if (GM == 0 || GM == 1) x[idx] = x0_own;
             if (GM == 3) x_out[idx] = x0_own;
+            if (GM == 4) {
+                const V2<T> xo = x[idx];
+                x_out[idx] = mk2<T>(xo.x + x0_own.x, xo.y + x0_own.y);
+            }
         });
         reduce_store<S, 4>(g, sc, item, j, acc, lds);
     }
@@ -1362,7 +1377,7 @@ void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const doubl
                  Coef rhs, bool herm, int guess_mode, const V2<T>* u_prev, const V2<T>* u_prev2,
                  V2<T>* x, V2<T>* r, V2<T>* p, const float2* dx, V2<T>* x_out, V2<T>* bvec,
                  SolverState s, Scratch sc) {
-    if (guess_mode == 3 && !bvec) throw std::runtime_error("init: refinement needs the stored b");
+    if (guess_mode >= 3 && !bvec) throw std::runtime_error("init: refinement needs the stored b");
     const dim3 grid = grid_of(g), block(kBlock);
 #define DMRI_INIT(H, GMV)                                                                     \
     k_init<T, S, H, GMV><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.Kr, A.aux, A.dK0, \
@@ -1373,7 +1388,8 @@ void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const doubl
         case 0: DMRI_INIT(H, 0); break;      \
         case 1: DMRI_INIT(H, 1); break;      \
         case 2: DMRI_INIT(H, 2); break;      \
-        default: DMRI_INIT(H, 3); break;     \
+        case 3: DMRI_INIT(H, 3); break;      \
+        default: DMRI_INIT(H, 4); break;     \
     }
     DMRI_DISPATCH_S(g.S, {
         if (herm) {

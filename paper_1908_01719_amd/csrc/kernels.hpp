@@ -196,7 +196,7 @@ void launch_krylov_persistent(hipStream_t st, const Geom& g, const MatView<T>& A
 void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n);
 
 // Up to kMaxHist vectors and FP64 weights of a linear combination.
-constexpr int kMaxHist = 5;
+constexpr int kMaxHist = 7;
 template <typename T>
 struct ExtrapTerms {
     const typename Vec2Of<T>::type* u[kMaxHist];
