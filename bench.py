@@ -78,10 +78,10 @@ def kernel_bytes(kind, n_dof, nnz, total_iters, tile, prec_bytes, n_steps, n_sys
     tile_iters = total_iters / tile
     if kind == "spmv":
         return 2 * c * n_dof * total_iters + mat * tile_iters
-    if kind == "update":
-        return 6 * c * n_dof * total_iters + diag * tile_iters
-    if kind == "pupdate":
+    if kind == "update":  # r, q read, r written
         return 3 * c * n_dof * total_iters + diag * tile_iters
+    if kind == "pupdate":  # r, p, x read, p, x written
+        return 5 * c * n_dof * total_iters + diag * tile_iters
     if kind == "init":
         # gathers u_prev (and u_prev2), writes x, r, p, reads both base arrays
         return (5 * c * n_dof * n_sys + (mat + nnz * prec_bytes) * n_sys / tile) * n_steps
