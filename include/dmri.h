@@ -216,6 +216,10 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *               per XCD, so the tiles still iterating keep the whole chip
  *               busy; 0 = tiles split only as far as needed for a multiple
  *               of 8 work items (default)
+ *  "pair_lanes" 1 = the FP32 inner solves of mixed precision on batches of
+ *               more than 64 systems use tiles of 128 systems with two
+ *               systems per lane (16-byte vector accesses, half the memory
+ *               instructions per system) (default); 0 = 64-system tiles
  *  "concurrency" k > 1: a dmri_run over several problems runs up to k of
  *               them at once, each on its own stream and workspace driven by
  *               its own host thread (meshes of uneven size share the GPU);

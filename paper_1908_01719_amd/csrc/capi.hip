@@ -150,6 +150,7 @@ struct Options {
     int concurrency = 1;
     int sort_systems = 1;
     int xcd_split = 0;
+    int pair_lanes = 1;
 };
 
 // Per-system Krylov state arrays of one solver level.
@@ -693,6 +694,8 @@ struct KernelTimer {
 // Common set-up of a batch: geometry, per-system parameters, scratch.
 struct BatchSetup {
     Geom g;
+    Geom gi;        // geometry of the FP32 inner solves (g, or 128-system paired tiles)
+    bool pair;      // inner solves use the paired-lane layout
     Geom gp;        // geometry of the persistent solver (one block per CU)
     bool persist;   // Krylov loop in one persistent launch per solve
     bool herm;
@@ -701,7 +704,7 @@ struct BatchSetup {
 };
 
 BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
-                       const double* d_q) {
+                       const double* d_q, bool want_pair = false) {
     hipStream_t st = lane(h).stream;
     Workspace& W = lane(h).ws;
     BatchSetup bs{};
@@ -725,29 +728,45 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     // work to hide the per-launch cost.
     const bool small = static_cast<int64_t>(g.n_rows) * g.ld <= 131072;
     bs.persist = (h->opt.persistent == 1 || (h->opt.persistent == 2 && small)) && g.ld <= 64;
-    W.gq.alloc(ld);
-    const size_t part_n = std::max<size_t>(static_cast<size_t>(g.n_items) * g.B * S * 4,
-                                           2 * static_cast<size_t>(bs.gp.n_items) * bs.gp.B * S * 4);
+    // FP32 inner solves of wide batches: 128-system tiles, two systems per lane.
+    bs.pair = want_pair && !bs.persist && S == 64 && n_sys > 64 && !g.queue &&
+              static_cast<int64_t>(g.n_rows) * 1024 < (int64_t(1) << 31);
+    bs.gi = g;
+    if (bs.pair) {
+        bs.gi = make_geom(g.n_rows, static_cast<int32_t>(n_sys), 128, h->opt.blocks_per_xcd, 0, 1,
+                          h->opt.xcd_split != 0);
+        bs.gi.nt = g.nt;
+        bs.gi.lds = 0;
+    }
+    const Geom& gi = bs.gi;
+    const size_t ld_max = std::max<size_t>(ld, static_cast<size_t>(gi.ld));
+    const int32_t items_max = std::max(g.n_items, gi.n_items);
+    W.gq.alloc(ld_max);
+    const size_t part_n = std::max<size_t>(
+        std::max<size_t>(static_cast<size_t>(g.n_items) * g.B * S * 4,
+                         static_cast<size_t>(gi.n_items) * gi.B * gi.S * 4),
+        2 * static_cast<size_t>(bs.gp.n_items) * bs.gp.B * S * 4);
     W.partial.alloc(part_n);
     W.barrier.alloc(32 * 11);
     HIPCHK(hipMemsetAsync(W.barrier.p, 0, sizeof(uint32_t) * 32 * 11, st));
     bs.bar.count = W.barrier.p;
     bs.bar.gen = W.barrier.p + 32 * 9;
     bs.bar.err = reinterpret_cast<int32_t*>(W.barrier.p + 32 * 10);
-    W.ctr.alloc(2 * static_cast<size_t>(g.n_items));
+    W.ctr.alloc(2 * static_cast<size_t>(items_max));
     W.bad.alloc(1);
-    W.pinned(static_cast<size_t>(g.n_tiles));
-    HIPCHK(hipMemsetAsync(W.ctr.p, 0, sizeof(int32_t) * 2 * g.n_items, st));
+    W.pinned(static_cast<size_t>(std::max(g.n_tiles, gi.n_tiles)));
+    HIPCHK(hipMemsetAsync(W.ctr.p, 0, sizeof(int32_t) * 2 * items_max, st));
     HIPCHK(hipMemsetAsync(W.bad.p, 0, sizeof(int32_t), st));
     const double intF2 = h->delta * h->delta * (h->Delta - h->delta / 3.0);
-    launch_sys_params(st, static_cast<int32_t>(n_sys), g.ld, d_b, d_q, intF2, W.gq.p, W.bad.p);
+    launch_sys_params(st, static_cast<int32_t>(n_sys), static_cast<int32_t>(ld_max), d_b, d_q,
+                      intF2, W.gq.p, W.bad.p);
     int32_t bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, W.bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (bad) throw Error(DMRI_E_INVALID, "b must be finite and >= 0, q finite and nonzero when b > 0");
     bs.sc.partial = W.partial.p;
     bs.sc.ctr_spmv = W.ctr.p;
-    bs.sc.ctr_init = W.ctr.p + g.n_items;
+    bs.sc.ctr_init = W.ctr.p + items_max;
     return bs;
 }
 
@@ -993,13 +1012,20 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                        const double* d_q, double2* d_sig, BatchResult& res) {
     hipStream_t st = lane(h).stream;
     Workspace& W = lane(h).ws;
-    const BatchSetup bs = setup_batch(h, P, n_sys, d_b, d_q);
+    const BatchSetup bs = setup_batch(h, P, n_sys, d_b, d_q, h->opt.pair_lanes != 0);
     const Geom& g = bs.g;
+    // Inner (FP32) solves run on bsi: the same geometry, or paired tiles.
+    BatchSetup bsi = bs;
+    bsi.g = bs.gi;
+    Geom gr = g;  // refinement residual: dx in the inner layout
+    gr.dx_pair = bs.pair ? 1 : 0;
     const size_t nv = static_cast<size_t>(g.n_rows) * g.ld, ld = static_cast<size_t>(g.ld);
+    const size_t ldi = std::max(ld, static_cast<size_t>(bs.gi.ld));
+    const size_t nvi = static_cast<size_t>(g.n_rows) * ldi;
     History<double2> hs;
     hs.nh = history_len(h);
     for (int i = 0; i < hs.nh + 5; ++i) W.vec64[i].alloc(2 * nv);
-    for (int i = 0; i < 4; ++i) W.vec32[i].alloc(2 * nv);
+    for (int i = 0; i < 4; ++i) W.vec32[i].alloc(2 * nvi);
     for (int i = 0; i <= hs.nh; ++i) hs.ring.push_back(reinterpret_cast<double2*>(W.vec64[i].p));
     // The refinement passes alternate x between hs.x() and x_alt.
     double2* x_alt = reinterpret_cast<double2*>(W.vec64[hs.nh + 1].p);
@@ -1011,9 +1037,9 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     float2* p32 = reinterpret_cast<float2*>(W.vec32[2].p);
     float2* q32 = reinterpret_cast<float2*>(W.vec32[3].p);
     W.outer.alloc(ld, g.n_tiles);
-    W.inner.alloc(ld, g.n_tiles);
+    W.inner.alloc(ldi, std::max(g.n_tiles, bs.gi.n_tiles));
     W.outer.reset(ld, st);
-    W.inner.reset(ld, st);
+    W.inner.reset(ldi, st);
     SolverState so = W.outer.view(static_cast<int32_t>(n_sys), h->opt.max_outer,
                                   h->opt.rtol * h->opt.rtol);
     SolverState si = W.inner.view(static_cast<int32_t>(n_sys), h->opt.max_iter,
@@ -1056,15 +1082,15 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                 std::fflush(stderr);
             }
             if (still == 0) break;
-            launch_inner_start(st, g, A32, W.gq.p, lhs, bs.herm, r64, W.outer.active.p, r32, dx,
+            launch_inner_start(st, bsi.g, A32, W.gq.p, lhs, bs.herm, r64, W.outer.active.p, r32, dx,
                                p32, si, bs.sc);
-            const int it = krylov_loop<float>(h, bs, A32, W.gq.p, lhs, dx, r32, p32, q32, si,
+            const int it = krylov_loop<float>(h, bsi, A32, W.gq.p, lhs, dx, r32, p32, q32, si,
                                               timer, pass == 0 ? last_first_pass - 2 : 2,
                                               h->opt.max_iter);
             if (pass == 0) last_first_pass = it;
             step_iters += it;
             timer.run(4, [&] {
-                launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, 4, hs.u(0), hs.u(1),
+                launch_init<double>(st, gr, A64, W.gq.p, lhs, rhs, bs.herm, 4, hs.u(0), hs.u(1),
                                     hs.x(), r64, p64, dx, x_alt, b64, so, bs.sc);
             });
             std::swap(hs.ring[hs.nh], x_alt);
@@ -1481,6 +1507,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "concurrency") o.concurrency = as_int(1, 16);
         else if (k == "sort_systems") o.sort_systems = as_int(0, 1);
         else if (k == "xcd_split") o.xcd_split = as_int(0, 1);
+        else if (k == "pair_lanes") o.pair_lanes = as_int(0, 1);
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -1518,6 +1545,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "concurrency") *value = o.concurrency;
         else if (k == "sort_systems") *value = o.sort_systems;
         else if (k == "xcd_split") *value = o.xcd_split;
+        else if (k == "pair_lanes") *value = o.pair_lanes;
         else if (k == "tuned_sys_tile") *value = h->last_tune.sys_tile;
         else if (k == "tuned_blocks_per_xcd") *value = h->last_tune.blocks_per_xcd;
         else if (k == "tuned_persistent") *value = h->last_tune.persistent;

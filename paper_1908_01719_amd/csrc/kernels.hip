@@ -28,9 +28,13 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kUs = 4;  // row slots per wavefront per chunk (streaming kernels)
+#ifndef DMRI_ROW_SLOTS
+#define DMRI_ROW_SLOTS 4
+#endif
+constexpr int kUs = DMRI_ROW_SLOTS;  // row slots per wavefront per chunk
 constexpr int kUg = 2;  // row slots per wavefront per queue grab (gather kernels)
 constexpr int kLdsRowCap = 32;  // LDS staging: padded entries per row budgeted
+constexpr int kPairS = 128;     // systems per tile of the paired-lane FP32 kernels
 constexpr int kSpmvRows = 2;    // rows per lane processed together in the LDS SpMV
 
 template <typename T> using V2 = typename Vec2Of<T>::type;
@@ -68,6 +72,11 @@ __device__ __forceinline__ void store_nt(double2* p, double2 v) {
 __device__ __forceinline__ void store_nt(float2* p, float2 v) {
     nt_f2 t = {v.x, v.y};
     __builtin_nontemporal_store(t, reinterpret_cast<nt_f2*>(p));
+}
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_nt(float4* p, float4 v) {
+    nt_f4 t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_f4*>(p));
 }
 
 template <typename T>
@@ -699,6 +708,336 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(Geom g, const T* __restrict_
     }
 }
 
+// ------------------------------------------- paired lanes (FP32, 128 systems)
+//
+// The FP32 inner solves of wide batches use tiles of 128 systems with two
+// systems per lane: systems 2l and 2l + 1 of a tile are the two complex
+// halves of the float4 that lane l loads, so a row of a tile is one 1 KiB
+// wavefront access of 16-byte lanes. This halves the vector-memory
+// instructions per system of the 64-wide layout; those instructions, not
+// HBM bandwidth, bound the SpMV gathers. Vector element (row, system s) of
+// the paired layout is at ((s / 128) * n_rows + row) * 128 + s % 128
+// (complex units); the matrix stays wavefront-uniform.
+
+__device__ __forceinline__ size_t pair_tile(const Geom& g, int tile) {
+    return static_cast<size_t>(tile) * g.n_rows * 64;  // float4 units
+}
+
+template <int K>
+__device__ __forceinline__ void reduce_store_pair(const Geom& g, Scratch sc, int item, int j,
+                                                  double (&v)[2][K], double* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[(wave * kPairS + 2 * lane + q) * K + k] = v[q][k];
+    __syncthreads();
+    if (threadIdx.x < kPairS) {
+        double* dst =
+            sc.partial + ((static_cast<size_t>(item) * g.B + j) * kPairS + threadIdx.x) * 4;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) t += lds[(w * kPairS + threadIdx.x) * K + k];
+            dst[k] = t;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ float2 lo2(float4 v) { return make_float2(v.x, v.y); }
+__device__ __forceinline__ float2 hi2(float4 v) { return make_float2(v.z, v.w); }
+__device__ __forceinline__ float4 cat4(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
+
+// NB entries of a row from k0 for both systems of the lane.
+template <int NB>
+__device__ __forceinline__ void pair_block(const int32_t* __restrict__ col,
+                                           const float* __restrict__ K0,
+                                           const float4* __restrict__ aux,
+                                           __amdgpu_buffer_rsrc_t rs, uint32_t lane_bytes, int k0,
+                                           const LaneCoef<float>& c0, const LaneCoef<float>& c1,
+                                           float& yr0, float& yi0, float& yr1, float& yi1) {
+    float4 xv[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const uint32_t off = static_cast<uint32_t>(col[k0 + u]) * (kPairS * 8u);
+        xv[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, lane_bytes, off, 0));
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const float4 a = aux[k0 + u];
+        const float k = K0[k0 + u];
+        const float ar0 = fma(c0.c, a.x, k), ai0 = fma(c0.d2, a.w, fma(c0.d1, a.z, c0.d0 * a.y));
+        const float ar1 = fma(c1.c, a.x, k), ai1 = fma(c1.d2, a.w, fma(c1.d1, a.z, c1.d0 * a.y));
+        cmac<float>(yr0, yi0, ar0, ai0, lo2(xv[u]));
+        cmac<float>(yr1, yi1, ar1, ai1, hi2(xv[u]));
+    }
+}
+
+// q = A p and sigma = p^H q (or p^T q) for the paired layout.
+template <bool HERM>
+__global__ __launch_bounds__(kBlock) void k_spmv_pair(
+    Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const float* __restrict__ K0, const float4* __restrict__ aux, const double4* __restrict__ gq,
+    Coef lhs, const float4* __restrict__ p, float4* __restrict__ q, SolverState s, Scratch sc) {
+    __shared__ double lds[kWaves * kPairS * 2];
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int lane = threadIdx.x & 63;
+    const uint32_t lane_bytes = static_cast<uint32_t>(lane) * 16u;
+    const int off = wave_id_uniform();
+    for (int item = xcd; item < g.n_items; item += 8) {
+        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+        const int s0 = tile * kPairS + 2 * lane;
+        const bool a0 = s0 < s.n_sys && s.active[s0];
+        const bool a1 = s0 + 1 < s.n_sys && s.active[s0 + 1];
+        if (!__syncthreads_or(a0 || a1)) continue;
+        const LaneCoef<float> c0(gq[s0], lhs), c1(gq[s0 + 1], lhs);
+        double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        const float4* pt = p + pair_tile(g, tile);
+        float4* qt = q + pair_tile(g, tile);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float4*>(pt), 0, static_cast<int>(static_cast<uint32_t>(g.n_rows) * 1024u),
+            kBufWord3);
+        const int r0 = part * g.part_rows;
+        const int r1 = min(g.n_rows, r0 + g.part_rows);
+        const int step = g.B * g.chunk_rows;
+        for (int c0r = r0 + j * g.chunk_rows; c0r < r1; c0r += step) {
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                const int row = c0r + off + u * kWaves;
+                if (row >= r1) break;
+                const int kb = row_ptr[row], ke = row_ptr[row + 1];
+                float yr0 = 0.f, yi0 = 0.f, yr1 = 0.f, yi1 = 0.f;
+                if (ke - kb == 16) {
+                    pair_block<16>(col, K0, aux, rs, lane_bytes, kb, c0, c1, yr0, yi0, yr1, yi1);
+                } else {
+                    for (int k0 = kb; k0 < ke; k0 += kRowPad)
+                        pair_block<kRowPad>(col, K0, aux, rs, lane_bytes, k0, c0, c1, yr0, yi0,
+                                            yr1, yi1);
+                }
+                const size_t o = static_cast<size_t>(row) * 64 + lane;
+                const float4 y = make_float4(yr0, yi0, yr1, yi1);
+                if (g.nt) store_nt(qt + o, y);
+                else qt[o] = y;
+                const float4 pv = pt[o];
+                dot_acc<HERM, float>(acc[0][0], acc[0][1], lo2(pv), lo2(y));
+                dot_acc<HERM, float>(acc[1][0], acc[1][1], hi2(pv), hi2(y));
+            }
+        }
+        reduce_store_pair<2>(g, sc, item, j, acc, lds);
+    }
+}
+
+// r -= alpha q, z = D^-1 r; rho' and ||r||^2 partials (paired layout). A
+// system that is not active keeps its r (alpha taken as 0).
+template <bool HERM>
+__global__ __launch_bounds__(kBlock) void k_update_pair(
+    Geom g, const float* __restrict__ dK0, const float4* __restrict__ daux,
+    const double4* __restrict__ gq, Coef lhs, float4* __restrict__ r,
+    const float4* __restrict__ q, SolverState s, Scratch sc) {
+    __shared__ double lds[kWaves * kPairS * 3];
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int lane = threadIdx.x & 63;
+    const int off = wave_id_uniform();
+    for (int item = xcd; item < g.n_items; item += 8) {
+        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+        const int s0 = tile * kPairS + 2 * lane;
+        const bool a0 = s0 < s.n_sys && s.active[s0];
+        const bool a1 = s0 + 1 < s.n_sys && s.active[s0 + 1];
+        if (!__syncthreads_or(a0 || a1)) continue;
+        const LaneCoef<float> c0(gq[s0], lhs), c1(gq[s0 + 1], lhs);
+        const double2 al0 = a0 ? s.alpha[s0] : make_double2(0.0, 0.0);
+        const double2 al1 = a1 ? s.alpha[s0 + 1] : make_double2(0.0, 0.0);
+        const float ar0 = static_cast<float>(al0.x), ai0 = static_cast<float>(al0.y);
+        const float ar1 = static_cast<float>(al1.x), ai1 = static_cast<float>(al1.y);
+        double acc[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        float4* rt = r + pair_tile(g, tile);
+        const float4* qt = q + pair_tile(g, tile);
+        const int r0 = part * g.part_rows;
+        const int r1 = min(g.n_rows, r0 + g.part_rows);
+        const int step = g.B * g.chunk_rows;
+        if (a0 || a1) {
+            for (int c0r = r0 + j * g.chunk_rows; c0r < r1; c0r += step) {
+                int row[kUs];
+                bool ok[kUs];
+                float4 rv[kUs], qv[kUs];
+#pragma unroll
+                for (int u = 0; u < kUs; ++u) {
+                    const int rr = c0r + off + u * kWaves;
+                    ok[u] = rr < r1;
+                    row[u] = ok[u] ? rr : r1 - 1;
+                    const size_t o = static_cast<size_t>(row[u]) * 64 + lane;
+                    rv[u] = rt[o];
+                    qv[u] = qt[o];
+                }
+#pragma unroll
+                for (int u = 0; u < kUs; ++u) {
+                    if (!ok[u]) continue;
+                    float2 x0 = lo2(rv[u]), x1 = hi2(rv[u]);
+                    const float2 q0 = lo2(qv[u]), q1 = hi2(qv[u]);
+                    x0 = make_float2(x0.x - (ar0 * q0.x - ai0 * q0.y), x0.y - (ar0 * q0.y + ai0 * q0.x));
+                    x1 = make_float2(x1.x - (ar1 * q1.x - ai1 * q1.y), x1.y - (ar1 * q1.y + ai1 * q1.x));
+                    rt[static_cast<size_t>(row[u]) * 64 + lane] = cat4(x0, x1);
+                    float dr, di;
+                    diag_at(dK0, daux, row[u], c0, dr, di);
+                    dot_acc<HERM, float>(acc[0][0], acc[0][1], x0, cdivT<float>(x0, dr, di));
+                    acc[0][2] += double(x0.x) * x0.x + double(x0.y) * x0.y;
+                    diag_at(dK0, daux, row[u], c1, dr, di);
+                    dot_acc<HERM, float>(acc[1][0], acc[1][1], x1, cdivT<float>(x1, dr, di));
+                    acc[1][2] += double(x1.x) * x1.x + double(x1.y) * x1.y;
+                }
+            }
+        }
+        reduce_store_pair<3>(g, sc, item, j, acc, lds);
+    }
+}
+
+// End of Krylov iteration k_iter in the paired layout: x += alpha p for the
+// systems that took part in it, p = D^-1 r + beta p for those still active.
+__global__ __launch_bounds__(kBlock) void k_pupdate_pair(
+    Geom g, const float* __restrict__ dK0, const float4* __restrict__ daux,
+    const double4* __restrict__ gq, Coef lhs, const float4* __restrict__ r,
+    float4* __restrict__ p, float4* __restrict__ x, int32_t k_iter, SolverState s) {
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int lane = threadIdx.x & 63;
+    const int off = wave_id_uniform();
+    for (int item = xcd; item < g.n_items; item += 8) {
+        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+        const int s0 = tile * kPairS + 2 * lane;
+        const bool re0 = s0 < s.n_sys, re1 = s0 + 1 < s.n_sys;
+        const bool dp0 = re0 && s.active[s0], dp1 = re1 && s.active[s0 + 1];
+        const bool dx0 = re0 && s.iters[s0] == k_iter, dx1 = re1 && s.iters[s0 + 1] == k_iter;
+        const bool do_p = dp0 || dp1, do_x = dx0 || dx1;
+        if (!(do_p || do_x)) continue;
+        const LaneCoef<float> c0(gq[s0], lhs), c1(gq[s0 + 1], lhs);
+        const double2 b0 = dp0 ? s.beta[s0] : make_double2(0.0, 0.0);
+        const double2 b1 = dp1 ? s.beta[s0 + 1] : make_double2(0.0, 0.0);
+        const double2 al0 = dx0 ? s.alpha[s0] : make_double2(0.0, 0.0);
+        const double2 al1 = dx1 ? s.alpha[s0 + 1] : make_double2(0.0, 0.0);
+        const float br0 = static_cast<float>(b0.x), bi0 = static_cast<float>(b0.y);
+        const float br1 = static_cast<float>(b1.x), bi1 = static_cast<float>(b1.y);
+        const float xr0 = static_cast<float>(al0.x), xi0 = static_cast<float>(al0.y);
+        const float xr1 = static_cast<float>(al1.x), xi1 = static_cast<float>(al1.y);
+        const float4* rt = r + pair_tile(g, tile);
+        float4* pt = p + pair_tile(g, tile);
+        float4* xt = x + pair_tile(g, tile);
+        const int r0 = part * g.part_rows;
+        const int r1 = min(g.n_rows, r0 + g.part_rows);
+        const int step = g.B * g.chunk_rows;
+        for (int c0r = r0 + j * g.chunk_rows; c0r < r1; c0r += step) {
+            int row[kUs];
+            bool ok[kUs];
+            float4 pv[kUs], rv[kUs], xv[kUs];
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                const int rr = c0r + off + u * kWaves;
+                ok[u] = rr < r1;
+                row[u] = ok[u] ? rr : r1 - 1;
+                const size_t o = static_cast<size_t>(row[u]) * 64 + lane;
+                pv[u] = pt[o];
+                if (do_p) rv[u] = rt[o];
+                if (do_x) xv[u] = xt[o];
+            }
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                if (!ok[u]) continue;
+                const size_t o = static_cast<size_t>(row[u]) * 64 + lane;
+                const float2 p0 = lo2(pv[u]), p1 = hi2(pv[u]);
+                if (do_x) {
+                    const float2 x0 = lo2(xv[u]), x1 = hi2(xv[u]);
+                    xt[o] = cat4(make_float2(x0.x + xr0 * p0.x - xi0 * p0.y,
+                                             x0.y + xr0 * p0.y + xi0 * p0.x),
+                                 make_float2(x1.x + xr1 * p1.x - xi1 * p1.y,
+                                             x1.y + xr1 * p1.y + xi1 * p1.x));
+                }
+                if (do_p) {
+                    float dr, di;
+                    float2 n0 = p0, n1 = p1;
+                    if (dp0) {
+                        diag_at(dK0, daux, row[u], c0, dr, di);
+                        const float2 z = cdivT<float>(lo2(rv[u]), dr, di);
+                        n0 = make_float2(z.x + br0 * p0.x - bi0 * p0.y, z.y + br0 * p0.y + bi0 * p0.x);
+                    }
+                    if (dp1) {
+                        diag_at(dK0, daux, row[u], c1, dr, di);
+                        const float2 z = cdivT<float>(hi2(rv[u]), dr, di);
+                        n1 = make_float2(z.x + br1 * p1.x - bi1 * p1.y, z.y + br1 * p1.y + bi1 * p1.x);
+                    }
+                    pt[o] = cat4(n0, n1);
+                }
+            }
+        }
+    }
+}
+
+// Start of an FP32 inner solve in the paired layout: r = (float) r64 for
+// outer-active systems (0 otherwise), dx = 0, p = z = D^-1 r; partials rho,
+// ||r||^2, ||r64||^2. r64 is in the 64-wide FP64 layout (n64 rows per tile).
+template <bool HERM>
+__global__ __launch_bounds__(kBlock) void k_inner_start_pair(
+    Geom g, const float* __restrict__ dK0, const float4* __restrict__ daux,
+    const double4* __restrict__ gq, Coef lhs, const double2* __restrict__ r64,
+    const int32_t* __restrict__ outer_active, float4* __restrict__ r, float4* __restrict__ dx,
+    float4* __restrict__ p, SolverState s, Scratch sc) {
+    __shared__ double lds[kWaves * kPairS * 4];
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int lane = threadIdx.x & 63;
+    const int off = wave_id_uniform();
+    for (int item = xcd; item < g.n_items; item += 8) {
+        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+        const int s0 = tile * kPairS + 2 * lane;
+        const bool a0 = s0 < s.n_sys && outer_active[s0];
+        const bool a1 = s0 + 1 < s.n_sys && outer_active[s0 + 1];
+        const LaneCoef<float> c0(gq[s0], lhs), c1(gq[s0 + 1], lhs);
+        // both systems of the lane sit next to each other in the 64-wide tile
+        const size_t b64 = static_cast<size_t>(s0 / 64) * g.n_rows * 64 + (s0 % 64);
+        double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+        float4* rt = r + pair_tile(g, tile);
+        float4* xt = dx + pair_tile(g, tile);
+        float4* pt = p + pair_tile(g, tile);
+        const int r0 = part * g.part_rows;
+        const int r1 = min(g.n_rows, r0 + g.part_rows);
+        const int step = g.B * g.chunk_rows;
+        for (int c0r = r0 + j * g.chunk_rows; c0r < r1; c0r += step) {
+            int row[kUs];
+            bool ok[kUs];
+            double2 v0[kUs], v1[kUs];
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                const int rr = c0r + off + u * kWaves;
+                ok[u] = rr < r1;
+                row[u] = ok[u] ? rr : r1 - 1;
+                const size_t o = b64 + static_cast<size_t>(row[u]) * 64;
+                v0[u] = a0 ? r64[o] : make_double2(0.0, 0.0);
+                v1[u] = a1 ? r64[o + 1] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                if (!ok[u]) continue;
+                const size_t o = static_cast<size_t>(row[u]) * 64 + lane;
+                const float2 x0 = make_float2(static_cast<float>(v0[u].x), static_cast<float>(v0[u].y));
+                const float2 x1 = make_float2(static_cast<float>(v1[u].x), static_cast<float>(v1[u].y));
+                float dr, di;
+                diag_at(dK0, daux, row[u], c0, dr, di);
+                const float2 z0 = cdivT<float>(x0, dr, di);
+                diag_at(dK0, daux, row[u], c1, dr, di);
+                const float2 z1 = cdivT<float>(x1, dr, di);
+                rt[o] = cat4(x0, x1);
+                pt[o] = cat4(z0, z1);
+                xt[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+                dot_acc<HERM, float>(acc[0][0], acc[0][1], x0, z0);
+                dot_acc<HERM, float>(acc[1][0], acc[1][1], x1, z1);
+                acc[0][2] += double(x0.x) * x0.x + double(x0.y) * x0.y;
+                acc[1][2] += double(x1.x) * x1.x + double(x1.y) * x1.y;
+                acc[0][3] += v0[u].x * v0[u].x + v0[u].y * v0[u].y;
+                acc[1][3] += v1[u].x * v1[u].x + v1[u].y * v1[u].y;
+            }
+        }
+        reduce_store_pair<4>(g, sc, item, j, acc, lds);
+    }
+}
+
 // ------------------------------------------------------ persistent solver
 
 constexpr int kMaxPersistSys = 64;
@@ -947,6 +1286,11 @@ __global__ __launch_bounds__(kBlock) void k_init(
         const bool act = sys < s.n_sys;
         const double4 gg = gq[sys];
         const LaneCoef<T> ll(gg, lhs), lr(gg, rhs);
+        // dx of the refinement passes may be stored in the paired layout.
+        const size_t tbx = g.dx_pair ? static_cast<size_t>(sys / kPairS) * g.n_rows * kPairS +
+                                           static_cast<size_t>(sys % kPairS)
+                                     : tb;
+        const size_t sx = g.dx_pair ? kPairS : S;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         sweep_gather<S>(g, part, j, sc.ctr_init + item, [&](int row) {
             if (!act) return;
@@ -970,10 +1314,10 @@ __global__ __launch_bounds__(kBlock) void k_init(
                         xj[u] = x[jdx];
                     } else if (GM == 3) {
                         const V2<T> xo = x[jdx];
-                        const float2 d = dx[jdx];
+                        const float2 d = dx[tbx + static_cast<size_t>(jj[u]) * sx];
                         xj[u] = mk2<T>(xo.x + static_cast<T>(d.x), xo.y + static_cast<T>(d.y));
                     } else if (GM == 4) {
-                        const float2 d = dx[jdx];
+                        const float2 d = dx[tbx + static_cast<size_t>(jj[u]) * sx];
                         xj[u] = mk2<T>(static_cast<T>(d.x), static_cast<T>(d.y));
                     }
                 }
@@ -1329,6 +1673,7 @@ void launch_fin(hipStream_t st, const Geom& g, SolverState s, Scratch sc, double
         case 16: k_finalize<16, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
         case 32: k_finalize<32, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
         case 64: k_finalize<64, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
+        case kPairS: k_finalize<kPairS, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
         default: throw std::runtime_error("unsupported tile width");
     }
     check_launch("finalize");
@@ -1352,7 +1697,7 @@ Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
     // are only split as far as needed for a multiple of 8 items.
     g.n_parts = xcd_split ? 8 : 8 / std::gcd(g.n_tiles, 8);
     g.n_items = g.n_tiles * g.n_parts;
-    g.chunk_rows = kUs * kWaves * (64 / S);
+    g.chunk_rows = kUs * kWaves * std::max(1, 64 / S);
     int32_t pr = (n_rows + g.n_parts - 1) / g.n_parts;
     pr = ((pr + g.chunk_rows - 1) / g.chunk_rows) * g.chunk_rows;
     g.part_rows = std::max(pr, g.chunk_rows);
@@ -1408,6 +1753,20 @@ void launch_inner_start(hipStream_t st, const Geom& g, const MatView<float>& A, 
                         Coef lhs, bool herm, const double2* r64, const int32_t* outer_active,
                         float2* r, float2* dx, float2* p, SolverState s, Scratch sc) {
     const dim3 grid = grid_of(g), block(kBlock);
+    if (g.S == kPairS) {
+        auto* r4 = reinterpret_cast<float4*>(r);
+        auto* x4 = reinterpret_cast<float4*>(dx);
+        auto* p4 = reinterpret_cast<float4*>(p);
+        if (herm)
+            k_inner_start_pair<true><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r64,
+                                                             outer_active, r4, x4, p4, s, sc);
+        else
+            k_inner_start_pair<false><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r64,
+                                                              outer_active, r4, x4, p4, s, sc);
+        check_launch("inner_start");
+        launch_fin<FIN_INIT, 4>(st, g, s, sc, nullptr, 0, nullptr);
+        return;
+    }
     DMRI_DISPATCH_S(g.S, {
         if (herm)
             k_inner_start<S, true><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r64,
@@ -1424,6 +1783,23 @@ template <typename T>
 void launch_spmv_dot(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
                      Coef lhs, bool herm, const V2<T>* p, V2<T>* q, SolverState s, Scratch sc) {
     const dim3 grid = grid_of(g), block(kBlock);
+    if (g.S == kPairS) {
+        if constexpr (sizeof(T) == 4) {
+            const auto* p4 = reinterpret_cast<const float4*>(p);
+            auto* q4 = reinterpret_cast<float4*>(q);
+            if (herm)
+                k_spmv_pair<true><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.aux, gq,
+                                                          lhs, p4, q4, s, sc);
+            else
+                k_spmv_pair<false><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.aux, gq,
+                                                           lhs, p4, q4, s, sc);
+            check_launch("spmv_pair");
+            launch_fin<FIN_ALPHA, 2>(st, g, s, sc, nullptr, 0, sc.ctr_spmv);
+            return;
+        } else {
+            throw std::runtime_error("paired layout is FP32 only");
+        }
+    }
     DMRI_DISPATCH_S(g.S, {
         bool done = false;
         if constexpr (S >= 32) {
@@ -1455,6 +1831,22 @@ void launch_update(hipStream_t st, const Geom& g, const MatView<T>& A, const dou
                    Coef lhs, bool herm, V2<T>* x, V2<T>* r, const V2<T>* p, const V2<T>* q,
                    SolverState s, Scratch sc) {
     const dim3 grid = grid_of(g), block(kBlock);
+    if (g.S == kPairS) {
+        if constexpr (sizeof(T) == 4) {
+            auto* r4 = reinterpret_cast<float4*>(r);
+            const auto* q4 = reinterpret_cast<const float4*>(q);
+            if (herm)
+                k_update_pair<true><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r4, q4, s, sc);
+            else
+                k_update_pair<false><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r4, q4, s,
+                                                             sc);
+            check_launch("update_pair");
+            launch_fin<FIN_BETA, 3>(st, g, s, sc, nullptr, 0, nullptr);
+            return;
+        } else {
+            throw std::runtime_error("paired layout is FP32 only");
+        }
+    }
     DMRI_DISPATCH_S(g.S, {
         if (herm)
             k_update<T, S, true><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, x, r, p, q, s,
@@ -1489,6 +1881,18 @@ template <typename T>
 void launch_pupdate(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
                     Coef lhs, const V2<T>* r, V2<T>* p, V2<T>* x, int32_t k_iter, SolverState s) {
     const dim3 grid = grid_of(g), block(kBlock);
+    if (g.S == kPairS) {
+        if constexpr (sizeof(T) == 4) {
+            k_pupdate_pair<<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs,
+                                                   reinterpret_cast<const float4*>(r),
+                                                   reinterpret_cast<float4*>(p),
+                                                   reinterpret_cast<float4*>(x), k_iter, s);
+            check_launch("pupdate_pair");
+            return;
+        } else {
+            throw std::runtime_error("paired layout is FP32 only");
+        }
+    }
     DMRI_DISPATCH_S(g.S, {
         k_pupdate<T, S><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r, p, x, k_iter, s);
     });

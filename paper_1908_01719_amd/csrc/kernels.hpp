@@ -102,6 +102,7 @@ struct Geom {
     int32_t queue;       // gather kernels: 1 = per-item row queue, 0 = static chunks
     int32_t grab;        // queue grabs per wavefront take grab * 2 * 64/S rows
     int32_t tile_bytes_ok;  // a 64-system FP64 tile is below 2^31 bytes (buffer gathers)
+    int32_t dx_pair;        // refinement: dx is stored in the 128-system paired layout
     int32_t nt;          // 1 = SpMV output stored non-temporally
     int32_t lds;         // 1 = LDS-staged SpMV for tiles of 32 or 64 systems
 };

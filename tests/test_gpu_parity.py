@@ -443,3 +443,21 @@ def test_sorted_batches_give_identical_signals(Sim, precision):
             dev = sd.cpu().numpy()
             assert np.array_equal(dev[:, 0] + 1j * dev[:, 1], out[srt])
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("pair", [0, 1])
+def test_paired_lanes_match_oracle(Sim, pair):
+    # Mixed precision on 67 systems: the FP32 inner solves in one ragged
+    # 128-system tile with two systems per lane (pair = 1) or in 64-system
+    # tiles (pair = 0); both refine to the oracle.
+    prob, b, q, ref = _wide_case()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12, precision=1, persistent=0, pair_lanes=pair)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+    assert st["status"] == "DMRI_OK"
+    err = rel_err(sig, ref, ref[0])
+    _say("paired lanes %d: max err %.2e, %d inner iterations" % (pair, err.max(),
+                                                                 st["total_iterations"]))
+    assert err.max() < 1e-9
