@@ -267,16 +267,24 @@ def main():
 
     tile = args.sys_tile or (64 if len(sysl) >= 64 else 32 if len(sysl) >= 32 else
                              16 if len(sysl) >= 16 else 8)
+    # Mixed precision on more than 64 systems runs its FP32 Krylov kernels on
+    # 128-system paired-lane tiles (the matrix is read once per such tile).
+    paired = (prec == 1 and tile == 64 and len(sysl) > 64
+              and sim.dmri_get_option("pair_lanes") == 1 and args.time_kernel != "init")
+    ktile = 128 if paired else tile
+    kname = KERNEL_NAMES[args.time_kernel]
+    if paired:
+        kname = kname.replace("k_spmv_dot", "k_spmv_pair").replace("k_update", "k_update_pair") \
+            .replace("k_pupdate", "k_pupdate_pair")
     pbytes = 8 if prec == 0 else 4
-    kb = kernel_bytes(args.time_kernel, n_dof, nnz, tot_iters, tile, pbytes, n_steps * args.steps,
-                      len(sysl))
+    kb = kernel_bytes(args.time_kernel, n_dof, nnz, tot_iters, ktile, pbytes,
+                      n_steps * args.steps, len(sysl))
     achieved = kb / t_kernel / 1e9 if t_kernel > 0 else None
     roofline = {
-        "kernel": KERNEL_NAMES[args.time_kernel],
+        "kernel": kname,
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-        "traffic": profiled_traffic(KERNEL_NAMES[args.time_kernel], args.workload,
-                                    args.precision, rtol),
+        "traffic": profiled_traffic(kname, args.workload, args.precision, rtol),
         "launches": n_launch, "mean_launch_us": 1e6 * t_kernel / max(1, n_launch),
         "bytes_per_launch": kb / max(1, n_launch),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",

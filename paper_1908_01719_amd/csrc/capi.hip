@@ -571,7 +571,14 @@ void extrap_weights_damped(int p, double* c) {
             for (int k = col; k <= n; ++k) A[r][k] -= f * A[col][k];
         }
     }
-    for (int k = 0; k < n; ++k) c[k] = A[k][n] / A[k][k];
+    // The exact weights are dyadic rationals with denominator 2^(p+1) (for
+    // p = 3: 49/16, -9/4, -13/8, 11/4, -15/16). Snapping the eliminated values
+    // to that grid makes them exact, so they sum to exactly 1: a constant
+    // history is then reproduced without a bias that a loose solve would keep.
+    for (int k = 0; k < n; ++k) {
+        const double v = A[k][n] / A[k][k];
+        c[k] = std::round(v * 1024.0) / 1024.0;
+    }
 }
 
 // Start of step n: writes the guess into hist.x() when it is not formed

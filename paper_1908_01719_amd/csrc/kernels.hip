@@ -292,6 +292,35 @@ __device__ __forceinline__ V2<T> tile_row(__amdgpu_buffer_rsrc_t rs, int j, uint
     }
 }
 
+// Rows of one 64-system tile of a vector read through a buffer resource:
+// row j of the tile starts at the wavefront-uniform offset j * stride and
+// the lane's element sits lane_bytes further.
+struct TileRows {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t lane_bytes;
+    uint32_t stride;
+};
+
+template <typename V>
+__device__ __forceinline__ TileRows tile_rows(const V* base, uint32_t n_rows, uint32_t stride,
+                                              uint32_t lane_bytes) {
+    TileRows t;
+    t.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<V*>(base), 0,
+                                             static_cast<int>(n_rows * stride), kBufWord3);
+    t.lane_bytes = lane_bytes;
+    t.stride = stride;
+    return t;
+}
+
+template <typename V>
+__device__ __forceinline__ V load_row(const TileRows& t, int j) {
+    const uint32_t off = static_cast<uint32_t>(j) * t.stride;
+    if constexpr (sizeof(V) == 16)
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(t.rs, t.lane_bytes, off, 0));
+    else
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(t.rs, t.lane_bytes, off, 0));
+}
+
 // Rows whose padded length is 16 entries (every interior row of a Kuhn
 // mesh): G rows of one wavefront at once, all 16 * G gathers issued before
 // the first use. Returns the rows' results in yr/yi.
@@ -1291,13 +1320,35 @@ __global__ __launch_bounds__(kBlock) void k_init(
                                            static_cast<size_t>(sys % kPairS)
                                      : tb;
         const size_t sx = g.dx_pair ? kPairS : S;
+        // 64-system tiles with static chunks: every row is wavefront-uniform,
+        // so the gathers go through buffer resources with uniform row offsets.
+        const bool fast = S == 64 && !g.queue && g.tile_bytes_ok;
+        TileRows tu{}, tu2{}, tx{}, tdx{};
+        if constexpr (S == 64) {
+            if (fast) {
+                const uint32_t lane = threadIdx.x & 63;
+                const uint32_t nr = static_cast<uint32_t>(g.n_rows);
+                const size_t off = static_cast<size_t>(tile) * g.n_rows * 64;
+                constexpr uint32_t kRow = 64 * sizeof(V2<T>);
+                tu = tile_rows(u_prev + off, nr, kRow, lane * sizeof(V2<T>));
+                if (GM == 1) tu2 = tile_rows(u_prev2 + off, nr, kRow, lane * sizeof(V2<T>));
+                if (GM == 2 || GM == 3) tx = tile_rows<V2<T>>(x + off, nr, kRow, lane * sizeof(V2<T>));
+                if (GM >= 3) {
+                    if (g.dx_pair)
+                        tdx = tile_rows(dx + static_cast<size_t>(tile / 2) * g.n_rows * kPairS, nr,
+                                        kPairS * 8u, ((tile & 1) * 64u + lane) * 8u);
+                    else
+                        tdx = tile_rows(dx + off, nr, 64u * 8u, lane * 8u);
+                }
+            }
+        }
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         sweep_gather<S>(g, part, j, sc.ctr_init + item, [&](int row) {
             if (!act) return;
             const int kb = row_ptr[row], ke = row_ptr[row + 1];
             T br = 0, bi = 0, axr = 0, axi = 0;
             V2<T> x0_own = mk2<T>(0, 0);
-            constexpr int kB = kRowPad / 2;
+            constexpr int kB = S == 64 ? kRowPad : kRowPad / 2;
             for (int k0 = kb; k0 < ke; k0 += kB) {
                 int jj[kB];
                 V2<T> uj[kB], xj[kB];
@@ -1305,6 +1356,22 @@ __global__ __launch_bounds__(kBlock) void k_init(
                 for (int u = 0; u < kB; ++u) jj[u] = col[k0 + u];
 #pragma unroll
                 for (int u = 0; u < kB; ++u) {
+                    if (fast) {
+                        if (kRhs) uj[u] = load_row<V2<T>>(tu, jj[u]);
+                        if (GM == 1) {
+                            xj[u] = load_row<V2<T>>(tu2, jj[u]);
+                        } else if (GM == 2) {
+                            xj[u] = load_row<V2<T>>(tx, jj[u]);
+                        } else if (GM == 3) {
+                            const V2<T> xo = load_row<V2<T>>(tx, jj[u]);
+                            const float2 d = load_row<float2>(tdx, jj[u]);
+                            xj[u] = mk2<T>(xo.x + static_cast<T>(d.x), xo.y + static_cast<T>(d.y));
+                        } else if (GM == 4) {
+                            const float2 d = load_row<float2>(tdx, jj[u]);
+                            xj[u] = mk2<T>(static_cast<T>(d.x), static_cast<T>(d.y));
+                        }
+                        continue;
+                    }
                     const size_t jdx = tb + static_cast<size_t>(jj[u]) * S;
                     if (kRhs) uj[u] = u_prev[jdx];
                     if (GM == 1) {
@@ -1458,12 +1525,16 @@ __global__ __launch_bounds__(kBlock) void k_signal(Geom g, const double* __restr
 // One block per tile; thread (grp, s) sums partials grp, grp+G, ... of
 // system s, then the groups are combined in order. Resets the tile's queue
 // counters in `zero_ctr` (items tile*n_parts .. +n_parts-1).
+// One wide block per tile: kFinBlock / S thread groups add interleaved block
+// partials, then the groups are combined in a fixed order.
+constexpr int kFinBlock = 1024;
+
 template <int S, int K, int MODE>
-__global__ __launch_bounds__(kBlock) void k_finalize(Geom g, SolverState s, Scratch sc,
-                                                     double2* __restrict__ out, int32_t n_sig,
-                                                     int32_t* __restrict__ zero_ctr) {
-    constexpr int G = kBlock / S;
-    __shared__ double lds[kBlock * K];
+__global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, Scratch sc,
+                                                        double2* __restrict__ out, int32_t n_sig,
+                                                        int32_t* __restrict__ zero_ctr) {
+    constexpr int G = kFinBlock / S;
+    __shared__ double lds[kFinBlock * K];
     __shared__ int cnt;
     const int tile = blockIdx.x;
     const int grp = threadIdx.x / S, sl = threadIdx.x % S;
@@ -1667,7 +1738,7 @@ inline dim3 grid_of(const Geom& g) { return dim3(8u * static_cast<unsigned>(g.B)
 template <int MODE, int K>
 void launch_fin(hipStream_t st, const Geom& g, SolverState s, Scratch sc, double2* out,
                 int32_t n_sig, int32_t* zero_ctr) {
-    const dim3 grid(static_cast<unsigned>(g.n_tiles)), block(kBlock);
+    const dim3 grid(static_cast<unsigned>(g.n_tiles)), block(kFinBlock);
     switch (g.S) {
         case 8: k_finalize<8, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
         case 16: k_finalize<16, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
