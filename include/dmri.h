@@ -216,6 +216,11 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *               per XCD, so the tiles still iterating keep the whole chip
  *               busy; 0 = tiles split only as far as needed for a multiple
  *               of 8 work items (default)
+ *  "tile_sched" 1 = each chunk of Krylov iterations is launched over the
+ *               tiles still active (as of the last counts the host read),
+ *               each split into enough row parts that all XCDs get the same
+ *               work (default); 0 = every launch covers every tile and
+ *               converged tiles only exit early. Results do not depend on it
  *  "pair_lanes" 1 = the FP32 inner solves of mixed precision on batches of
  *               more than 64 systems use tiles of 128 systems with two
  *               systems per lane (16-byte vector accesses, half the memory

@@ -150,6 +150,7 @@ struct Options {
     int concurrency = 1;
     int sort_systems = 1;
     int xcd_split = 0;
+    int tile_sched = 1;
     int pair_lanes = 1;
 };
 
@@ -747,11 +748,15 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     }
     const Geom& gi = bs.gi;
     const size_t ld_max = std::max<size_t>(ld, static_cast<size_t>(gi.ld));
-    const int32_t items_max = std::max(g.n_items, gi.n_items);
+    // Launches restricted to the active tiles split a tile into up to 8 parts
+    // (sched_geom); partials and counters are addressed by tile * n_parts + part.
+    const int32_t items_max =
+        std::max({g.n_items, gi.n_items, 8 * g.n_tiles, 8 * gi.n_tiles});
     W.gq.alloc(ld_max);
     const size_t part_n = std::max<size_t>(
-        std::max<size_t>(static_cast<size_t>(g.n_items) * g.B * S * 4,
-                         static_cast<size_t>(gi.n_items) * gi.B * gi.S * 4),
+        std::max<size_t>(static_cast<size_t>(std::max(g.n_items, 8 * g.n_tiles)) * g.B * S * 4,
+                         static_cast<size_t>(std::max(gi.n_items, 8 * gi.n_tiles)) * gi.B *
+                             gi.S * 4),
         2 * static_cast<size_t>(bs.gp.n_items) * bs.gp.B * S * 4);
     W.partial.alloc(part_n);
     W.barrier.alloc(32 * 11);
@@ -808,14 +813,16 @@ int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const d
     int done = 0, slot = 0;
     bool pending = false;
     int chunk = std::max(1, first_chunk);
+    Geom gk = g;  // geometry of the next chunk: every tile, or the tiles still active
+    std::vector<int32_t> live;
     for (;;) {
         for (int i = 0; i < chunk; ++i) {
             const int32_t k_iter = done + i + 1;
-            timer.run(1, [&] { launch_spmv_dot<T>(st, g, Av, gq, lhs, bs.herm, p, q, s, bs.sc); });
+            timer.run(1, [&] { launch_spmv_dot<T>(st, gk, Av, gq, lhs, bs.herm, p, q, s, bs.sc); });
             timer.run(2, [&] {
-                launch_update<T>(st, g, Av, gq, lhs, bs.herm, x, r, p, q, s, bs.sc);
+                launch_update<T>(st, gk, Av, gq, lhs, bs.herm, x, r, p, q, s, bs.sc);
             });
-            timer.run(3, [&] { launch_pupdate<T>(st, g, Av, gq, lhs, r, p, x, k_iter, s); });
+            timer.run(3, [&] { launch_pupdate<T>(st, gk, Av, gq, lhs, r, p, x, k_iter, s); });
         }
         done += chunk;
         HIPCHK(hipMemcpyAsync(lane(h).ws.h_active[slot], s.n_active, sizeof(int32_t) * g.n_tiles,
@@ -824,11 +831,20 @@ int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const d
         if (pending) {
             HIPCHK(hipEventSynchronize(lane(h).ev[slot ^ 1]));
             int tot = 0;
-            for (int t = 0; t < g.n_tiles; ++t) tot += lane(h).ws.h_active[slot ^ 1][t];
+            live.clear();
+            for (int t = 0; t < g.n_tiles; ++t) {
+                const int32_t a = lane(h).ws.h_active[slot ^ 1][t];
+                tot += a;
+                if (a > 0) live.push_back(t);
+            }
             if (tot == 0) {
                 done -= chunk;  // the chunk just enqueued only early-exits
                 break;
             }
+            // A tile that has left the loop never re-enters it, so the tiles
+            // active in these (older) counts cover the ones still active.
+            if (h->opt.tile_sched)
+                gk = sched_geom(g, live.data(), static_cast<int>(live.size()));
         }
         pending = true;
         slot ^= 1;
@@ -1514,6 +1530,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "concurrency") o.concurrency = as_int(1, 16);
         else if (k == "sort_systems") o.sort_systems = as_int(0, 1);
         else if (k == "xcd_split") o.xcd_split = as_int(0, 1);
+        else if (k == "tile_sched") o.tile_sched = as_int(0, 1);
         else if (k == "pair_lanes") o.pair_lanes = as_int(0, 1);
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
@@ -1552,6 +1569,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "concurrency") *value = o.concurrency;
         else if (k == "sort_systems") *value = o.sort_systems;
         else if (k == "xcd_split") *value = o.xcd_split;
+        else if (k == "tile_sched") *value = o.tile_sched;
         else if (k == "pair_lanes") *value = o.pair_lanes;
         else if (k == "tuned_sys_tile") *value = h->last_tune.sys_tile;
         else if (k == "tuned_blocks_per_xcd") *value = h->last_tune.blocks_per_xcd;

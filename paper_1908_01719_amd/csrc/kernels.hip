@@ -121,6 +121,25 @@ __device__ __forceinline__ size_t vbase(const Geom& g, int tile, int S, int sys)
     return static_cast<size_t>(tile) * g.n_rows * S + (sys - tile * S);
 }
 
+// Work item kk of a launch: its tile (through the schedule list when the
+// launch is restricted to some tiles), its row part, and the slot
+// tile * n_parts + part that addresses its partials and queue counter.
+struct ItemRef {
+    int tile, part, item;
+};
+__device__ __forceinline__ ItemRef item_ref(const Geom& g, int kk) {
+    const int t = kk / g.n_parts, part = kk - t * g.n_parts;
+    int tile = t;
+    if (g.n_sched) {
+        // Uniform select over the list (a dynamic index into the by-value
+        // kernel argument would copy it to scratch memory).
+#pragma unroll
+        for (int i = 0; i < kMaxSched; ++i)
+            if (i == t) tile = g.sched[i];
+    }
+    return {tile, part, tile * g.n_parts + part};
+}
+
 __device__ __forceinline__ int wave_id_uniform() {
     return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
 }
@@ -449,8 +468,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(
     Coef lhs, const V2<T>* __restrict__ p, V2<T>* __restrict__ q, SolverState s, Scratch sc) {
     __shared__ double lds[kWaves * S * 2];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int sys = tile * S + (threadIdx.x & 63) % S;
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && s.active[sys];
@@ -496,8 +516,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lds(
     __shared__ int32_t s_rp[CH + 1];
     __shared__ double lds[kWaves * S * 2];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int sys = tile * S + (threadIdx.x & 63) % S;
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && s.active[sys];
@@ -655,8 +676,9 @@ __global__ __launch_bounds__(kBlock) void k_update(
     const V2<T>* __restrict__ p, const V2<T>* __restrict__ q, SolverState s, Scratch sc) {
     __shared__ double lds[kWaves * S * 3];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int sys = tile * S + (threadIdx.x & 63) % S;
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && s.active[sys];
@@ -721,8 +743,9 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(Geom g, const T* __restrict_
                                                     V2<T>* __restrict__ p, V2<T>* __restrict__ x,
                                                     int32_t k_iter, SolverState s) {
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int sys = tile * S + (threadIdx.x & 63) % S;
         const size_t tb = vbase(g, tile, S, sys);
         const bool real = sys < s.n_sys;
@@ -815,8 +838,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(
     const int lane = threadIdx.x & 63;
     const uint32_t lane_bytes = static_cast<uint32_t>(lane) * 16u;
     const int off = wave_id_uniform();
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int s0 = tile * kPairS + 2 * lane;
         const bool a0 = s0 < s.n_sys && s.active[s0];
         const bool a1 = s0 + 1 < s.n_sys && s.active[s0 + 1];
@@ -869,8 +893,9 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const int lane = threadIdx.x & 63;
     const int off = wave_id_uniform();
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int s0 = tile * kPairS + 2 * lane;
         const bool a0 = s0 < s.n_sys && s.active[s0];
         const bool a1 = s0 + 1 < s.n_sys && s.active[s0 + 1];
@@ -931,8 +956,9 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_pair(
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const int lane = threadIdx.x & 63;
     const int off = wave_id_uniform();
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int s0 = tile * kPairS + 2 * lane;
         const bool re0 = s0 < s.n_sys, re1 = s0 + 1 < s.n_sys;
         const bool dp0 = re0 && s.active[s0], dp1 = re1 && s.active[s0 + 1];
@@ -1013,8 +1039,9 @@ __global__ __launch_bounds__(kBlock) void k_inner_start_pair(
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const int lane = threadIdx.x & 63;
     const int off = wave_id_uniform();
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int s0 = tile * kPairS + 2 * lane;
         const bool a0 = s0 < s.n_sys && outer_active[s0];
         const bool a1 = s0 + 1 < s.n_sys && outer_active[s0 + 1];
@@ -1196,8 +1223,9 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     for (int it = 0; it <= s.max_iter; ++it) {
         // Phase A: q = A p, sigma partials.
-        for (int item = xcd; item < g.n_items; item += 8) {
-            const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+        for (int kk = xcd; kk < g.n_items; kk += 8) {
+            const ItemRef ir = item_ref(g, kk);
+            const int tile = ir.tile, part = ir.part, item = ir.item;
             const int sys = tile * S + (threadIdx.x & 63) % S;
             const size_t tb = vbase(g, tile, S, sys);
             const bool act = sh_act[sys] != 0;
@@ -1217,8 +1245,9 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
             __syncthreads();
         }
         // Phase B: x, r update; rho', ||r||^2 partials.
-        for (int item = xcd; item < g.n_items; item += 8) {
-            const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+        for (int kk = xcd; kk < g.n_items; kk += 8) {
+            const ItemRef ir = item_ref(g, kk);
+            const int tile = ir.tile, part = ir.part, item = ir.item;
             const int sys = tile * S + (threadIdx.x & 63) % S;
             const size_t tb = vbase(g, tile, S, sys);
             const bool act = sh_act[sys] != 0;
@@ -1265,8 +1294,9 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
         }
         if (!sh_any) break;
         // Phase C: p = z + beta p.
-        for (int item = xcd; item < g.n_items; item += 8) {
-            const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+        for (int kk = xcd; kk < g.n_items; kk += 8) {
+            const ItemRef ir = item_ref(g, kk);
+            const int tile = ir.tile, part = ir.part, item = ir.item;
             const int sys = tile * S + (threadIdx.x & 63) % S;
             const size_t tb = vbase(g, tile, S, sys);
             if (!sh_act[sys]) continue;
@@ -1308,8 +1338,9 @@ __global__ __launch_bounds__(kBlock) void k_init(
     constexpr bool kRhs = GM < 3;  // b formed from u_prev in this launch
     __shared__ double lds[kWaves * S * 4];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int sys = tile * S + (threadIdx.x & 63) % S;
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys;
@@ -1454,8 +1485,9 @@ __global__ __launch_bounds__(kBlock) void k_inner_start(
     float2* __restrict__ p, SolverState s, Scratch sc) {
     __shared__ double lds[kWaves * S * 4];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int sys = tile * S + (threadIdx.x & 63) % S;
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && outer_active[sys];
@@ -1499,8 +1531,9 @@ __global__ __launch_bounds__(kBlock) void k_signal(Geom g, const double* __restr
                                                    Scratch sc) {
     __shared__ double lds[kWaves * S * 2];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int sys = tile * S + (threadIdx.x & 63) % S;
         const size_t tb = vbase(g, tile, S, sys);
         double acc[2] = {0.0, 0.0};
@@ -1536,7 +1569,13 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, S
     constexpr int G = kFinBlock / S;
     __shared__ double lds[kFinBlock * K];
     __shared__ int cnt;
-    const int tile = blockIdx.x;
+    int tile = static_cast<int>(blockIdx.x);
+    if (g.n_sched) {
+        const int t = tile;
+#pragma unroll
+        for (int i = 0; i < kMaxSched; ++i)
+            if (i == t) tile = g.sched[i];
+    }
     const int grp = threadIdx.x / S, sl = threadIdx.x % S;
     const int sys = tile * S + sl;
     if (zero_ctr && threadIdx.x < g.n_parts) zero_ctr[tile * g.n_parts + threadIdx.x] = 0;
@@ -1549,7 +1588,23 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, S
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
     const int nb = g.n_parts * g.B;
     const double* base = sc.partial + static_cast<size_t>(tile) * nb * S * 4;
-    for (int i = grp; i < nb; i += G) {
+    // Partials grp, grp + G, ... in that order; kU loads in flight per batch.
+    constexpr int kU = 8;
+    int i = grp;
+    for (; i + (kU - 1) * G < nb; i += kU * G) {
+        double v[kU][K];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const double* pp = base + (static_cast<size_t>(i + u * G) * S + sl) * 4;
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[u][k] = pp[k];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] += v[u][k];
+    }
+    for (; i < nb; i += G) {
         const double* pp = base + (static_cast<size_t>(i) * S + sl) * 4;
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[k] += pp[k];
@@ -1563,6 +1618,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, S
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double t = 0.0;
+#pragma unroll 4
             for (int gg = 0; gg < G; ++gg) t += lds[(gg * S + sl) * K + k];
             tot[k] = t;
         }
@@ -1631,8 +1687,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, MatView<T> A, int whic
                                                   V2<T>* __restrict__ y) {
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const T* base = which == 0 ? A.K0 : A.Kr;
-    for (int item = xcd; item < g.n_items; item += 8) {
-        const int tile = item / g.n_parts, part = item - tile * g.n_parts;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
         const int sys = tile * S + (threadIdx.x & 63) % S;
         const size_t tb = vbase(g, tile, S, sys);
         const T c = static_cast<T>(cc[sys]);
@@ -1738,7 +1795,7 @@ inline dim3 grid_of(const Geom& g) { return dim3(8u * static_cast<unsigned>(g.B)
 template <int MODE, int K>
 void launch_fin(hipStream_t st, const Geom& g, SolverState s, Scratch sc, double2* out,
                 int32_t n_sig, int32_t* zero_ctr) {
-    const dim3 grid(static_cast<unsigned>(g.n_tiles)), block(kFinBlock);
+    const dim3 grid(static_cast<unsigned>(g.n_sched ? g.n_sched : g.n_tiles)), block(kFinBlock);
     switch (g.S) {
         case 8: k_finalize<8, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
         case 16: k_finalize<16, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;
@@ -1773,10 +1830,29 @@ Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
     pr = ((pr + g.chunk_rows - 1) / g.chunk_rows) * g.chunk_rows;
     g.part_rows = std::max(pr, g.chunk_rows);
     const int32_t chunks = (g.part_rows + g.chunk_rows - 1) / g.chunk_rows;
-    g.B = std::max(1, std::min(blocks_per_xcd, chunks));
+    g.bpx = std::max(1, blocks_per_xcd);
+    g.B = std::max(1, std::min(g.bpx, chunks));
     // Buffer-resource gathers need a tile (FP64, 64 systems) below 2^31 bytes.
     g.tile_bytes_ok = static_cast<int64_t>(n_rows) * 64 * 16 < (int64_t(1) << 31) ? 1 : 0;
     return g;
+}
+
+Geom sched_geom(const Geom& g, const int32_t* tiles, int n) {
+    if (n <= 0 || n >= g.n_tiles || n > kMaxSched || g.queue) return g;
+    Geom s = g;
+    s.n_sched = n;
+    for (int i = 0; i < n; ++i) {
+        if (tiles[i] < 0 || tiles[i] >= g.n_tiles) throw std::runtime_error("schedule: bad tile");
+        s.sched[i] = tiles[i];
+    }
+    s.n_parts = std::max(g.n_parts, 8 / std::gcd(n, 8));
+    s.n_items = n * s.n_parts;
+    int32_t pr = (g.n_rows + s.n_parts - 1) / s.n_parts;
+    pr = ((pr + g.chunk_rows - 1) / g.chunk_rows) * g.chunk_rows;
+    s.part_rows = std::max(pr, g.chunk_rows);
+    const int32_t chunks = (s.part_rows + g.chunk_rows - 1) / g.chunk_rows;
+    s.B = std::max(1, std::min(g.bpx, chunks));
+    return s;
 }
 
 #define DMRI_DISPATCH_S(S_, ...)                                             \

@@ -38,6 +38,8 @@
 namespace dmri {
 
 constexpr int kRowPad = 8;
+// Most tiles a Krylov launch can be restricted to (the tiles still active).
+constexpr int kMaxSched = 32;
 
 template <typename T> struct Vec2Of;
 template <> struct Vec2Of<double> { using type = double2; };
@@ -105,16 +107,26 @@ struct Geom {
     int32_t dx_pair;        // refinement: dx is stored in the 128-system paired layout
     int32_t nt;          // 1 = SpMV output stored non-temporally
     int32_t lds;         // 1 = LDS-staged SpMV for tiles of 32 or 64 systems
+    int32_t bpx;         // blocks per XCD asked for (B = min(bpx, chunks of a part))
+    int32_t n_sched;     // 0: items cover tiles 0..n_tiles-1; else tiles sched[0..n_sched)
+    int32_t sched[kMaxSched];
 };
 
 struct Scratch {
-    double* partial;     // [n_items][B][S][4]
-    int32_t* ctr_spmv;   // [n_items] chunk queues of the gather kernels,
-    int32_t* ctr_init;   // [n_items] zero between launches
+    double* partial;     // [n_tiles * n_parts][B][S][4], item = tile * n_parts + part
+    int32_t* ctr_spmv;   // [n_tiles * n_parts] chunk queues of the gather kernels,
+    int32_t* ctr_init;   // [n_tiles * n_parts] zero between launches
 };
 
 Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd, int32_t queue,
                int32_t grab, bool xcd_split = false);
+// Geometry of g restricted to the n tiles listed (the tiles that may still
+// be active): each is split into enough row parts that every XCD gets the
+// same number of items. Returns g itself when the list is empty, covers
+// every tile, is longer than kMaxSched or g uses row queues. Partials and
+// queue counters of the restricted launches stay addressed by
+// (tile * n_parts + part), so buffers sized for n_tiles * 8 parts serve both.
+Geom sched_geom(const Geom& g, const int32_t* tiles, int n);
 
 // guess_mode: 0 x0 = u_prev, 1 x0 = 2 u_prev - u_prev2 (x0 written to x),
 // 2 x0 given in x, 3 x0 = x + dx (mixed-precision correction, written to

@@ -87,11 +87,24 @@ def _cyl_case():
     return prob, b, q
 
 
+_CYL_REF = {}
+
+
+def _cyl_ref():
+    # The oracle's exact-solve signals of _cyl_case under SHORT, computed once
+    # per session (each call builds the case afresh, so nothing is shared
+    # with the GPU side).
+    if "ref" not in _CYL_REF:
+        prob, b, q = _cyl_case()
+        _CYL_REF["ref"] = timestep.signals(prob, SHORT, b, q, solver="splu")
+    return _CYL_REF["ref"].copy()
+
+
 @pytest.mark.parametrize("tile", [0, 8, 16, 64])
 @pytest.mark.parametrize("guess", [0, 1])
 def test_fp64_transformed_matches_oracle(Sim, tile, guess):
     prob, b, q = _cyl_case()
-    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    ref = _cyl_ref()
     with Sim(0) as sim:
         sim.set_sequence(SHORT)
         sim.set_options(rtol=1e-12, sys_tile=tile, guess=guess)
@@ -223,7 +236,7 @@ def test_run_device_torch(Sim):
 
 def test_fp32_path_close(Sim):
     prob, b, q = _cyl_case()
-    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    ref = _cyl_ref()
     with Sim(0) as sim:
         sim.set_sequence(SHORT)
         sim.set_options(precision=2, rtol=1e-6)
@@ -275,7 +288,7 @@ def test_persistent_solver_matches_oracle(Sim, precision):
     # One launch per Krylov solve with grid barriers; the same signals as the
     # oracle and as the chunked multi-launch loop.
     prob, b, q = _cyl_case()
-    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    ref = _cyl_ref()
     out = {}
     with Sim(0) as sim:
         sim.set_sequence(SHORT)
@@ -331,7 +344,7 @@ def test_extrapolation_orders_match_oracle(Sim, order, precision):
     # point: every order gives the oracle's signals (the iteration counts are
     # reported; on this coarse time grid at rtol 1e-12 they barely differ).
     prob, b, q = _cyl_case()
-    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    ref = _cyl_ref()
     with Sim(0) as sim:
         sim.set_sequence(SHORT)
         pid = sim.add_problem(prob)
@@ -351,7 +364,7 @@ def test_graph_replay_matches_eager(Sim):
     # captures, later runs replay, with eager runs in between; every replay
     # gives the eager signals bit for bit and the oracle's within 1e-9.
     prob, b, q = _cyl_case()
-    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    ref = _cyl_ref()
     with Sim(0) as sim:
         sim.set_sequence(SHORT)
         pid = sim.add_problem(prob)
@@ -373,7 +386,7 @@ def test_graph_replay_matches_eager(Sim):
 
 def test_autotune_matches_oracle(Sim):
     prob, b, q = _cyl_case()
-    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    ref = _cyl_ref()
     with Sim(0) as sim:
         sim.set_sequence(SHORT)
         pid = sim.add_problem(prob)
@@ -460,4 +473,28 @@ def test_paired_lanes_match_oracle(Sim, pair):
     err = rel_err(sig, ref, ref[0])
     _say("paired lanes %d: max err %.2e, %d inner iterations" % (pair, err.max(),
                                                                  st["total_iterations"]))
+    assert err.max() < 1e-9
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tile_schedule_matches_oracle(Sim, precision):
+    # Two 8-system tiles sorted by b: the low-b tile leaves the Krylov loop
+    # first, after which each chunk of iterations is launched over the one
+    # tile still active, split over all XCDs (tile_sched = 1). Partials are
+    # then grouped differently, so the signals agree with the unrestricted
+    # launches to rounding and with the oracle to the solver tolerance.
+    prob, b, q = _cyl_case()
+    ref = _cyl_ref()
+    out = {}
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.set_options(rtol=1e-12, precision=precision, sys_tile=8, persistent=0)
+        for ts in (0, 1):
+            sim.set_options(tile_sched=ts)
+            out[ts], st = sim.dmri_run([pid] * len(b), b, q)
+            assert st["status"] == "DMRI_OK"
+    assert rel_err(out[1], out[0], ref[0]).max() < 1e-11
+    err = rel_err(out[1], ref, ref[0])
+    _say("tile schedule, precision %d: max err %.2e" % (precision, err.max()))
     assert err.max() < 1e-9
