@@ -844,7 +844,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(
         const int s0 = tile * kPairS + 2 * lane;
         const bool a0 = s0 < s.n_sys && s.active[s0];
         const bool a1 = s0 + 1 < s.n_sys && s.active[s0 + 1];
-        if (!__syncthreads_or(a0 || a1)) continue;
+        const bool la = a0 || a1;
+        if (!__syncthreads_or(la)) continue;
         const LaneCoef<float> c0(gq[s0], lhs), c1(gq[s0 + 1], lhs);
         double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
         const float4* pt = p + pair_tile(g, tile);
@@ -860,6 +861,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(
             for (int u = 0; u < kUs; ++u) {
                 const int row = c0r + off + u * kWaves;
                 if (row >= r1) break;
+                // Lanes whose two systems have both converged neither gather
+                // nor store: in a tile that is only partly active, the cache
+                // lines of its converged systems are not fetched.
+                if (!la) continue;
                 const int kb = row_ptr[row], ke = row_ptr[row + 1];
                 float yr0 = 0.f, yi0 = 0.f, yr1 = 0.f, yi1 = 0.f;
                 if (ke - kb == 16) {
