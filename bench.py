@@ -43,6 +43,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# L2-to-CU ceiling of 1 KB row gathers (64 lanes x 16 B) from an L2-resident
+# vector, measured on MI355X with gather_ceiling.hip: 19.3 cycles per
+# wavefront load per CU, i.e. 53 B per clock per CU at 2.4 GHz on 256 CUs.
+L2_GATHER_PEAK_GBS = 32600.0
 KERNELS = {"spmv": 1, "update": 2, "pupdate": 3, "init": 4}
 KERNEL_NAMES = {"spmv": "k_spmv_dot", "update": "k_update", "pupdate": "k_pupdate",
                 "init": "k_init"}
@@ -280,6 +284,16 @@ def main():
     kb = kernel_bytes(args.time_kernel, n_dof, nnz, tot_iters, ktile, pbytes,
                       n_steps * args.steps, len(sysl))
     achieved = kb / t_kernel / 1e9 if t_kernel > 0 else None
+    # Every stored matrix entry gathers one complex vector value per system
+    # (from L2 when the neighbour row is cached): the SpMV's second bound.
+    gather = None
+    if args.time_kernel == "spmv" and t_kernel > 0:
+        gb = nnz * 2 * pbytes * tot_iters
+        gather = {"achieved": gb / t_kernel / 1e9, "peak": L2_GATHER_PEAK_GBS, "unit": "GB/s",
+                  "frac": gb / t_kernel / 1e9 / L2_GATHER_PEAK_GBS,
+                  "bytes_per_launch": gb / max(1, n_launch),
+                  "peak_source": "gather_ceiling.hip: L2-resident 1 KB row gathers, 19.3 "
+                                 "cycles per wavefront load per CU"}
     roofline = {
         "kernel": kname,
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -288,6 +302,7 @@ def main():
         "launches": n_launch, "mean_launch_us": 1e6 * t_kernel / max(1, n_launch),
         "bytes_per_launch": kb / max(1, n_launch),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
+        "l2_gather": gather,
     }
     out = {
         "metric": "DOF-steps/s", "value": value, "unit": "DOF-steps/s", "n_gpus": 1,
