@@ -18,17 +18,17 @@
 // (Appendix A, eq. linear_billinear). The time-dependent parts are built on
 // the fly per system: c = cm (G F)^2 on M_D and i d . V with d = cd G F q.
 //
-// Work decomposition ("XCD sweep"). A tile is S consecutive systems. Work
-// items are (tile, row part) pairs, numbered so that their count is a
-// multiple of 8; XCD x (blocks with blockIdx % 8 == x, which the hardware
-// places on XCD x) owns items x, x+8, ... Inside an item the wavefronts of
-// the XCD sweep the rows: the kernels that gather neighbour values (SpMV,
-// step start) take the next few rows from a per-item queue (one atomic per
-// wavefront grab), so the rows in flight form one compact window that stays
-// in that XCD's L2; the streaming kernels give block j the chunks j, j+B, ...
-// Every block keeps one FP64 partial per system for each item; small
-// finalize kernels add the partials in a fixed order (deterministic), update
-// the per-system Krylov scalars and reset the queues.
+// Work decomposition ("XCD sweep"). A tile is S consecutive systems (S = 128
+// for the paired FP32 layout, two systems per lane). Work items are (tile,
+// row part) pairs, numbered so that their count is a multiple of 8; XCD x
+// (blocks with blockIdx % 8 == x, which the hardware places on XCD x) owns
+// items x, x+8, ... A Krylov launch may cover only the tiles still active
+// (Geom::sched), each split into enough parts that every XCD gets the same
+// number of items. Inside an item block j takes the row chunks j, j+B, ...;
+// the gather kernels can instead take rows from a per-item queue (one atomic
+// per wavefront grab, option). Every block keeps one FP64 partial per system
+// for each item; small finalize kernels add the partials in a fixed order
+// (deterministic), update the per-system Krylov scalars and reset the queues.
 #pragma once
 
 #include <hip/hip_runtime.h>
