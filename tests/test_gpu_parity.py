@@ -498,3 +498,26 @@ def test_tile_schedule_matches_oracle(Sim, precision):
     err = rel_err(out[1], ref, ref[0])
     _say("tile schedule, precision %d: max err %.2e" % (precision, err.max()))
     assert err.max() < 1e-9
+
+
+def test_tile_schedule_odd_tile_counts(Sim):
+    # 37 systems in five 8-system tiles (the last one ragged), b spread so the
+    # tiles leave the Krylov loop at different times: the restricted launches
+    # cover subsets of 1-4 tiles, each split into 8 row parts (five tiles
+    # already need 8 parts for a multiple of 8 items). The signals match the
+    # unrestricted launches (checked against the oracle above) to rounding.
+    prob, _, _ = _cyl_case()
+    b = np.linspace(0.0, 5000.0, 37)
+    q = di.fibonacci_directions(37)
+    out = {}
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.set_options(rtol=1e-12, sys_tile=8, persistent=0)
+        for ts in (0, 1):
+            sim.set_options(tile_sched=ts)
+            out[ts], st = sim.dmri_run([pid] * len(b), b, q)
+            assert st["status"] == "DMRI_OK"
+    err = rel_err(out[1], out[0], out[0][0])
+    _say("tile schedule, 5 tiles: max difference %.2e" % err.max())
+    assert err.max() < 1e-11
