@@ -94,23 +94,34 @@ def kernel_bytes(kind, n_dof, nnz, total_iters, tile, prec_bytes, n_steps, n_sys
 
 def profiled_traffic(kernel, workload, precision, rtol):
     """Measured HBM bytes per launch of `kernel` from the committed rocprofv3
-    counter summary, or None when none matches or the kernel source changed
+    counter summary, or None when none matches or the library sources changed
     since the counters were taken."""
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "hbm_counters_%s_%s_%s.md" % (kernel, workload, precision))
-    src = os.path.join(ROOT, "paper_1908_01719_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m_t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    m_h = re.search(r"kernels_hip_sha256:\s*([0-9a-f]+)", text)
+    m_h = re.search(r"csrc_sha256:\s*([0-9a-f]+)", text)
     m_w = re.search(r"workload: \S+ precision=\S+ rtol=(\S+)", text)
     if not (m_t and m_h and m_w) or float(m_w.group(1)) != rtol:
         return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_h.group(1):
+    if csrc_sha256() != m_h.group(1):
         return None
     return float(m_t.group(1))
+
+
+def csrc_sha256():
+    """SHA-256 over the library sources (kernels and the host code that shapes
+    the launches and the DOF order), in name order."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1908_01719_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(os.path.basename(f).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 _CPU = {}

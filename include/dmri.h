@@ -205,7 +205,7 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *               1 = pencils (default): columns of "pencil" x "pencil" cells
  *               swept z-, y-, x-major, bounding the index distance between
  *               mesh neighbours
- *  "pencil"     pencil width in cells (default 16)
+ *  "pencil"     pencil width in cells (default 12)
  *  "sort_systems" 1 = order the systems of a batch before tiling, so tiles
  *               of similar systems converge and leave the Krylov loop
  *               together (default): by the iterations each (problem, b, q)

@@ -50,7 +50,7 @@ struct MeshInput {
     // which bounds the index distance between mesh neighbours by about
     // pencil^2 rows.
     int32_t ordering = 1;
-    int32_t pencil = 16;
+    int32_t pencil = 12;
 };
 
 // Assembled operators in the library's DOF order (spatially sorted).

@@ -146,7 +146,7 @@ struct Options {
     int time_kernel = 0;
     int progress = 0;
     int ordering = 1;
-    int pencil = 16;
+    int pencil = 12;
     int concurrency = 1;
     int sort_systems = 1;
     int xcd_split = 0;
