@@ -36,6 +36,10 @@
 
 #include <stdint.h>
 
+/* Every entry point below is exported from libdmri.so; the library is built
+ * with hidden default visibility, so nothing else is. */
+#define DMRI_API __attribute__((visibility("default")))
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -74,14 +78,14 @@ typedef struct {
  * operators exported (dmri_export_operator), but dmri_run* return
  * DMRI_E_STATE. On failure *out is NULL and dmri_last_error(NULL) has the
  * reason. */
-dmri_status dmri_create(int device_ordinal, dmri_handle* out);
+DMRI_API dmri_status dmri_create(int device_ordinal, dmri_handle* out);
 
 /* Free every host and device resource of h. NULL-safe. */
-void dmri_destroy(dmri_handle h);
+DMRI_API void dmri_destroy(dmri_handle h);
 
 /* Text of the last error on h (or of the last failed dmri_create for
  * h == NULL). Valid until the next call on h. Never NULL. */
-const char* dmri_last_error(dmri_handle h);
+DMRI_API const char* dmri_last_error(dmri_handle h);
 
 /* Add one mesh with its compartments (Sec. 2: compartments Omega_k with
  * diffusivity D_k, relaxation T2_k, permeability kappa on the interfaces
@@ -105,7 +109,7 @@ const char* dmri_last_error(dmri_handle h);
  * (|volume| < 1e-12 h^3 with h the mean edge length), a periodic face that
  * does not match its opposite face.
  * On success *problem_id receives the new id (0, 1, ...). */
-dmri_status dmri_add_problem(dmri_handle h,
+DMRI_API dmri_status dmri_add_problem(dmri_handle h,
                              int64_t n_nodes, const double* xyz,
                              int64_t n_tets, const int32_t* tets,
                              const int32_t* tet_label, int32_t n_comp,
@@ -117,7 +121,7 @@ dmri_status dmri_add_problem(dmri_handle h,
 
 /* Number of DOFs (one per compartment touching a node, after periodic
  * identification) and stored nonzeros of problem `problem_id`. */
-dmri_status dmri_problem_info(dmri_handle h, int32_t problem_id,
+DMRI_API dmri_status dmri_problem_info(dmri_handle h, int32_t problem_id,
                               int64_t* n_dof, int64_t* nnz);
 
 /* Copy the assembled real operators of a problem (host data, no device).
@@ -132,7 +136,7 @@ dmri_status dmri_problem_info(dmri_handle h, int32_t problem_id,
  *   u0      [n_dof] initial magnetization per DOF
  *   dof_comp [n_dof] compartment, dof_node [n_dof] a mesh node of the DOF
  *           (the lowest-index node among periodically identified copies). */
-dmri_status dmri_export_operator(dmri_handle h, int32_t problem_id,
+DMRI_API dmri_status dmri_export_operator(dmri_handle h, int32_t problem_id,
                                  int32_t* row_ptr, int32_t* col, double* vals,
                                  double* w, double* u0,
                                  int32_t* dof_comp, int32_t* dof_node);
@@ -142,7 +146,7 @@ dmri_status dmri_export_operator(dmri_handle h, int32_t problem_id,
  * (theta = 1/2 is Crank-Nicolson). The echo time is T = Delta + delta.
  * delta/dt and Delta/dt must be integers (within 1e-9) so pulse edges
  * fall on the grid; 0 < delta <= Delta. */
-dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_us,
+DMRI_API dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_us,
                                    double dt_us, double theta);
 
 /* Solver options (all have defaults):
@@ -231,8 +235,8 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
  *               1 = one after another (default). Runs with autotune, graph
  *               or sample recording use one lane
  * Unknown keys or out-of-range values: DMRI_E_INVALID. */
-dmri_status dmri_set_option(dmri_handle h, const char* key, double value);
-dmri_status dmri_get_option(dmri_handle h, const char* key, double* value);
+DMRI_API dmri_status dmri_set_option(dmri_handle h, const char* key, double value);
+DMRI_API dmri_status dmri_get_option(dmri_handle h, const char* key, double* value);
 
 /* ---- Learned initial guess (option "guess" = 2) ----------------------
  * A per-element network corrects the linear extrapolation of the next time
@@ -253,14 +257,14 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value);
 
 /* Set the network parameters from host memory (n_params must equal
  * DMRI_GUESS_N_PARAMS); restarts the Adam moments. */
-dmri_status dmri_guess_set_params(dmri_handle h, const float* params, int64_t n_params);
+DMRI_API dmri_status dmri_guess_set_params(dmri_handle h, const float* params, int64_t n_params);
 /* Copy the current parameters to host memory. DMRI_E_STATE if none set. */
-dmri_status dmri_guess_get_params(dmri_handle h, float* params, int64_t n_params);
+DMRI_API dmri_status dmri_guess_get_params(dmri_handle h, float* params, int64_t n_params);
 /* Load / save parameters as a file: 8 bytes "DMRIMLP1", int32 16, 64, 2,
  * then DMRI_GUESS_N_PARAMS little-endian float32. A wrong header gives
  * DMRI_E_INVALID. */
-dmri_status dmri_load_guess_model(dmri_handle h, const char* path);
-dmri_status dmri_save_guess_model(dmri_handle h, const char* path);
+DMRI_API dmri_status dmri_load_guess_model(dmri_handle h, const char* path);
+DMRI_API dmri_status dmri_save_guess_model(dmri_handle h, const char* path);
 
 /* Record training samples during later dmri_run / dmri_run_device calls:
  * at every step n >= 2, every stride-th element of the batch (a different
@@ -269,23 +273,23 @@ dmri_status dmri_save_guess_model(dmri_handle h, const char* path);
  * device) until capacity samples are held; capacity = 0 stops recording.
  * The buffers are the caller's and must stay valid while recording is on.
  * Resets the sample count. Recording needs precision 0 or 1. */
-dmri_status dmri_guess_record(dmri_handle h, float* d_features, float* d_targets,
+DMRI_API dmri_status dmri_guess_record(dmri_handle h, float* d_features, float* d_targets,
                               int64_t capacity, int64_t stride);
 /* Samples recorded so far (<= capacity). */
-dmri_status dmri_guess_record_count(dmri_handle h, int64_t* count);
+DMRI_API dmri_status dmri_guess_record_count(dmri_handle h, int64_t* count);
 
 /* Evaluate the network on n samples (device buffers): outputs d_out[n][2]
  * (may be NULL), the gradient of the mean squared error
  * L = sum((y - t)^2) / n with respect to the packed parameters into
  * d_grad[DMRI_GUESS_N_PARAMS] (may be NULL) and L into *loss (may be NULL).
  * Gradient and loss need d_targets. Returns after the results are written. */
-dmri_status dmri_guess_eval(dmri_handle h, int64_t n, const float* d_features,
+DMRI_API dmri_status dmri_guess_eval(dmri_handle h, int64_t n, const float* d_features,
                             const float* d_targets, float* d_out, float* d_grad, double* loss);
 /* n_iters full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, step
  * size lr) on the mean squared error over n device samples. *loss_first is
  * L before the first step, *loss_last L before the last step (either may be
  * NULL). */
-dmri_status dmri_guess_train(dmri_handle h, int64_t n, const float* d_features,
+DMRI_API dmri_status dmri_guess_train(dmri_handle h, int64_t n, const float* d_features,
                              const float* d_targets, int32_t n_iters, double lr,
                              double* loss_first, double* loss_last);
 
@@ -297,9 +301,10 @@ dmri_status dmri_guess_train(dmri_handle h, int64_t n, const float* d_features,
  *   signal_out [n_pairs][2] Re, Im of S (um^3)
  *   stats      may be NULL
  * All pairs of all problems are solved as one batch on the device.
+ * n_pairs = 0 is an empty run: DMRI_OK, stats zeroed, nothing read or written.
  * Returns DMRI_NOT_CONVERGED (results still written) when any system hit
  * max_iter in some step. */
-dmri_status dmri_run(dmri_handle h, int64_t n_pairs,
+DMRI_API dmri_status dmri_run(dmri_handle h, int64_t n_pairs,
                      const int32_t* problem_id, const double* b, const double* q,
                      double* signal_out, dmri_stats* stats);
 
@@ -308,8 +313,8 @@ dmri_status dmri_run(dmri_handle h, int64_t n_pairs,
  * are device pointers, all pairs on one problem (problem_id). Work is
  * enqueued on hip_stream (NULL = the handle's own stream); the call
  * synchronizes that stream to poll convergence and returns after the
- * signals have been written. */
-dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
+ * signals have been written. n_pairs = 0: DMRI_OK, stats zeroed. */
+DMRI_API dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
                             int64_t n_pairs, const double* d_b, const double* d_q,
                             double* d_signal, dmri_stats* stats);
 
@@ -319,7 +324,7 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
  * (right side, without the sign flip of the time-dependent parts: the
  * coefficients are taken as given). x, y: [n_dof][n_sys][2] doubles;
  * c [n_sys], d [n_sys][3]. Uses the precision of option "precision". */
-dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which,
+DMRI_API dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which,
                                 int64_t n_sys, const double* c, const double* d,
                                 const double* x, double* y);
 

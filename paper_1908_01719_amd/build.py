@@ -23,6 +23,7 @@ SOURCES = ["assembly.cpp", "kernels.hip", "mlp.hip", "capi.hip"]
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-fvisibility=hidden",
     "-Wno-unused-command-line-argument",
 ]
 

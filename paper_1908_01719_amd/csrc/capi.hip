@@ -1741,6 +1741,19 @@ dmri_status dmri_guess_train(dmri_handle h, int64_t n, const float* d_features,
     });
 }
 
+// The scalar members of a run's statistics, zeroed for a run of n pairs; the
+// caller-owned array pointers are left as they are.
+static void reset_stats(dmri_stats* st, int64_t n) {
+    if (!st) return;
+    st->n_sys = n;
+    st->total_iterations = 0;
+    st->spmv_rows = 0;
+    st->n_steps = 0;
+    st->t_setup_s = st->t_solve_s = st->t_signal_s = 0.0;
+    st->n_kernel_launches = 0;
+    st->t_kernel_s = 0.0;
+}
+
 dmri_status dmri_run(dmri_handle h, int64_t n_pairs, const int32_t* problem_id, const double* b,
                      const double* q, double* signal_out, dmri_stats* stats) {
     if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
@@ -1748,8 +1761,8 @@ dmri_status dmri_run(dmri_handle h, int64_t n_pairs, const int32_t* problem_id, 
         need_device(h);
         need_sequence(h);
         if (n_pairs < 0) throw Error(DMRI_E_INVALID, "n_pairs must be >= 0");
-        if (n_pairs == 0) return DMRI_OK;
-        if (!problem_id || !b || !q || !signal_out) throw Error(DMRI_E_INVALID, "NULL argument");
+        if (n_pairs > 0 && (!problem_id || !b || !q || !signal_out))
+            throw Error(DMRI_E_INVALID, "NULL argument");
         for (int64_t i = 0; i < n_pairs; ++i) {
             get_problem(h, problem_id[i]);
             const double nq = std::sqrt(q[3 * i] * q[3 * i] + q[3 * i + 1] * q[3 * i + 1] +
@@ -1758,15 +1771,8 @@ dmri_status dmri_run(dmri_handle h, int64_t n_pairs, const int32_t* problem_id, 
                 throw Error(DMRI_E_INVALID, "b must be finite and >= 0, q finite and nonzero");
         }
         const double t_start = now_s();
-        if (stats) {
-            stats->n_sys = n_pairs;
-            stats->total_iterations = 0;
-            stats->spmv_rows = 0;
-            stats->n_steps = 0;
-            stats->t_setup_s = stats->t_solve_s = stats->t_signal_s = 0.0;
-            stats->n_kernel_launches = 0;
-            stats->t_kernel_s = 0.0;
-        }
+        reset_stats(stats, n_pairs);
+        if (n_pairs == 0) return DMRI_OK;
         // Group pairs by problem, keeping input order inside each group.
         std::vector<std::pair<int32_t, std::vector<int64_t>>> groups;
         for (int32_t pid = 0; pid < static_cast<int32_t>(h->problems.size()); ++pid) {
@@ -1857,7 +1863,11 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
     return guarded(h, [&]() -> dmri_status {
         need_device(h);
         need_sequence(h);
-        if (n_pairs <= 0) return n_pairs == 0 ? DMRI_OK : set_err(h, DMRI_E_INVALID, "n_pairs < 0");
+        if (n_pairs < 0) throw Error(DMRI_E_INVALID, "n_pairs must be >= 0");
+        if (n_pairs == 0) {
+            reset_stats(stats, 0);
+            return DMRI_OK;
+        }
         if (!d_b || !d_q || !d_signal) throw Error(DMRI_E_INVALID, "NULL argument");
         ProblemRec& P = get_problem(h, problem_id);
         hipStream_t saved = lane(h).stream;
@@ -1869,16 +1879,8 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
         } restore{h, saved};
         const double ts = now_s();
         ensure_uploaded(h, P, h->opt.precision != 0);
-        if (stats) {
-            stats->n_sys = n_pairs;
-            stats->total_iterations = 0;
-            stats->spmv_rows = 0;
-            stats->n_steps = 0;
-            stats->t_setup_s = now_s() - ts;
-            stats->t_solve_s = stats->t_signal_s = 0.0;
-            stats->n_kernel_launches = 0;
-            stats->t_kernel_s = 0.0;
-        }
+        reset_stats(stats, n_pairs);
+        if (stats) stats->t_setup_s = now_s() - ts;
         BatchResult R;
         std::vector<int64_t> idx(n_pairs);
         for (int64_t i = 0; i < n_pairs; ++i) idx[i] = i;

@@ -215,6 +215,22 @@ def test_not_converged_and_invalid(Sim):
             sim.dmri_run([5], [1000.0], [[1, 0, 0]])
 
 
+def test_empty_runs(Sim):
+    # n_pairs = 0 through both entry points: DMRI_OK, nothing written, the
+    # scalar statistics zeroed.
+    import torch
+    prob, b, q = _cyl_case()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid], np.zeros(0), np.zeros((0, 3)))
+        assert sig.shape == (0,) and st["status"] == "DMRI_OK"
+        assert st["total_iterations"] == 0 and st["n_steps"] == 0
+        e = torch.zeros(0, dtype=torch.float64, device="cuda")
+        sim.dmri_run_device(pid, e, torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
+                            torch.zeros((0, 2), dtype=torch.float64, device="cuda"))
+
+
 def test_run_device_torch(Sim):
     import torch
     prob, b, q = _cyl_case()
