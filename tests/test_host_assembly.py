@@ -32,6 +32,23 @@ def test_library_exports_every_declared_symbol():
     assert sorted(binding.EXPORTED) == declared
 
 
+def test_library_exports_nothing_else():
+    # The C entry points are the whole boundary: the library is built with
+    # hidden default visibility, so no C++ internals are exported.
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    header = open(os.path.join(ROOT, "include", "dmri.h")).read()
+    declared = set(re.findall(r"\b(dmri_[a-z_]+)\s*\(", header))
+    out = subprocess.run([nm, "-D", "--defined-only", binding.LIB_PATH], check=True,
+                         stdout=subprocess.PIPE, text=True).stdout
+    funcs = {ln.split()[-1] for ln in out.splitlines() if len(ln.split()) == 3
+             and ln.split()[1] == "T"}
+    assert funcs == declared, sorted(funcs ^ declared)
+
+
 def _lib_to_oracle_perm(prob, exp, asm):
     tn, _ = fem.torus_nodes(prob.xyz, prob.box_lo, prob.box_hi, prob.periodic_mask)
     key = {(int(c), int(n)): i for i, (c, n) in enumerate(zip(asm.dof_comp, asm.dof_node))}
