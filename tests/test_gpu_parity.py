@@ -537,3 +537,23 @@ def test_tile_schedule_odd_tile_counts(Sim):
     err = rel_err(out[1], out[0], out[0][0])
     _say("tile schedule, 5 tiles: max difference %.2e" % err.max())
     assert err.max() < 1e-11
+
+
+@pytest.mark.parametrize("queue,lds", [(1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_row_queue_and_lds_spmv_match_oracle(Sim, queue, lds, precision):
+    # The optional launch shapes of the gather kernels: rows taken from a
+    # per-item atomic queue instead of static chunks, and the SpMV that stages
+    # each chunk's matrix entries in LDS (64-system tile, 13 systems ragged).
+    prob, b, q = _cyl_case()
+    ref = _cyl_ref()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.set_options(rtol=1e-12, precision=precision, sys_tile=64, persistent=0, queue=queue,
+                        lds=lds)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+    assert st["status"] == "DMRI_OK"
+    err = rel_err(sig, ref, ref[0])
+    _say("queue=%d lds=%d precision=%d max err %.2e" % (queue, lds, precision, err.max()))
+    assert err.max() < 1e-9
