@@ -557,3 +557,28 @@ def test_row_queue_and_lds_spmv_match_oracle(Sim, queue, lds, precision):
     err = rel_err(sig, ref, ref[0])
     _say("queue=%d lds=%d precision=%d max err %.2e" % (queue, lds, precision, err.max()))
     assert err.max() < 1e-9
+
+
+@pytest.mark.parametrize("opts", [
+    dict(precision=1, xcd_split=1),
+    dict(precision=1, nt=0),
+    dict(precision=1, blocks_per_xcd=3),
+    dict(precision=0, blocks_per_xcd=3),
+    dict(precision=0, guess=1, extrap_damp=0, extrap_order=3),
+    dict(precision=1, pair_lanes=0, tile_sched=0),
+], ids=["xcd_split", "nt0", "bpx3_mixed", "bpx3_fp64", "undamped_cubic", "unpaired_unsched"])
+def test_launch_options_match_oracle(Sim, opts):
+    # Launch-shape and guess options on the two-tile 67-system batch: every
+    # tile split over all XCDs, plain stores for the SpMV output, three blocks
+    # per XCD (each block sweeps many chunks), the undamped cubic
+    # extrapolation, and the unpaired, unscheduled FP32 inner solves.
+    prob, b, q, ref = _wide_case()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.set_options(rtol=1e-12, persistent=0, **opts)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+    assert st["status"] == "DMRI_OK"
+    err = rel_err(sig, ref, ref[0])
+    _say("%s max err %.2e" % (opts, err.max()))
+    assert err.max() < 1e-9
