@@ -54,15 +54,15 @@ KERNEL_NAMES = {"spmv": "k_spmv_dot", "update": "k_update", "pupdate": "k_pupdat
 
 def workload(name):
     import dmri_inputs as di
-    if name == "config2":
-        prob, seq, sysl = di.config2()
+    if name == "cylinder_57_batched":
+        prob, seq, sysl = di.cylinder_57_batched()
         desc = ("cylinder r=5um in 12um periodic box, 57^3 Kuhn cubes, 2 compartments, "
                 "kappa=1e-5, 64 dirs x 16 b in [0,5000]")
-    elif name == "config1":
-        prob, seq, sysl = di.config1()
+    elif name == "cylinder_36":
+        prob, seq, sysl = di.cylinder_36()
         desc = "cylinder r=5um in 12um periodic box, 36^3 Kuhn cubes, 8 b in [0,3000] along x"
-    elif name == "config0":
-        prob, seq, sysl = di.config0()
+    elif name == "free_diffusion_10":
+        prob, seq, sysl = di.free_diffusion_10()
         desc = "free diffusion [-5,5]^3, 10^3 Kuhn cubes, b=1000 along x"
     else:
         raise SystemExit("unknown workload %s" % name)
@@ -193,7 +193,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="config2", choices=["config0", "config1", "config2"])
+    ap.add_argument("--workload", default="cylinder_57_batched",
+                    choices=["free_diffusion_10", "cylinder_36", "cylinder_57_batched"])
     ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--guess", type=int, default=1)

@@ -33,11 +33,11 @@ __all__ = [
     "kuhn_box_mesh",
     "label_tets",
     "fibonacci_directions",
-    "config0",
-    "config1",
-    "config2",
-    "config3",
-    "config4",
+    "free_diffusion_10",
+    "cylinder_36",
+    "cylinder_57_batched",
+    "seeded_cells",
+    "seeded_cells_78",
     "cylinder_box",
     "slab_box",
     "free_box",
@@ -275,14 +275,14 @@ def slab_box(n=16, half=5.0, split=0.0, D=(D_FREE, D_FREE), kappa=0.0, u0=None,
                    n_cells=n, meta={"name": "slab_box", "n": n, "split": split})
 
 
-def config0():
+def free_diffusion_10():
     """Free diffusion in [-5,5]^3, 10 cubes per side, b=1000 along x."""
     prob = free_box(n=10, half=5.0)
     sysl = Systems(np.array([1000.0]), np.array([[1.0, 0.0, 0.0]]))
     return prob, PGSE_SHORT, sysl
 
 
-def config1(n=36):
+def cylinder_36(n=36):
     """Cylinder r=5 in a 12 um box, kappa=1e-5, 8 b-values in [0,3000] along x."""
     prob = cylinder_box(n=n)
     b = np.linspace(0.0, 3000.0, 8)
@@ -290,8 +290,8 @@ def config1(n=36):
     return prob, PGSE_SHORT, Systems(b, q)
 
 
-def config2(n=57, n_dir=64, n_b=16):
-    """Config-1 geometry refined to n=57; 64 Fibonacci directions x 16 b in [0,5000]."""
+def cylinder_57_batched(n=57, n_dir=64, n_b=16):
+    """The cylinder_36 geometry refined to n=57; 64 Fibonacci directions x 16 b in [0,5000]."""
     prob = cylinder_box(n=n)
     dirs = fibonacci_directions(n_dir)
     bs = np.linspace(0.0, 5000.0, n_b)
@@ -344,7 +344,7 @@ def _random_geometry(seed: int, n_fixed: Optional[int] = None, box=30.0):
     return n, kappa, count, shapes, fails
 
 
-def config3(seed: int, n_fixed: Optional[int] = None):
+def seeded_cells(seed: int, n_fixed: Optional[int] = None):
     """One geometry of the uneven batch: seeded shapes in a 30 um box."""
     n, kappa, count, shapes, fails = _random_geometry(seed, n_fixed)
     xyz, tets, _ = kuhn_box_mesh([0.0] * 3, [30.0] * 3, n)
@@ -360,6 +360,6 @@ def config3(seed: int, n_fixed: Optional[int] = None):
     return prob, PGSE_SHORT, Systems(b, q)
 
 
-def config4(seed: int):
+def seeded_cells_78(seed: int):
     """Held-out geometry for the learned guess: same generator, n = 78."""
-    return config3(seed, n_fixed=78)
+    return seeded_cells(seed, n_fixed=78)

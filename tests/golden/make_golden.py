@@ -7,12 +7,13 @@ the workload, the solver the oracle used and the signals.
     python tests/golden/make_golden.py [name ...]      (default: all)
 
 Fixtures:
-  config1.json        the two-compartment cylinder box (36^3 cubes, 51,408
-                      DOFs), all 8 b-values, full PGSE echo (240 steps)
-  config2_first2.json the 57^3 batched workload (196,593 DOFs): 6 sampled
-                      (b, q) pairs after the first 2 steps (sum w u^2)
-  config3_seed3.json  the smallest seeded-cell geometry, 4 sampled pairs,
-                      full echo
+  cylinder_36.json         the two-compartment cylinder box (36^3 cubes,
+                           51,408 DOFs), all 8 b-values, full PGSE echo
+                           (240 steps)
+  cylinder_57_first2.json  the 57^3 batched workload (196,593 DOFs): 6 sampled
+                           (b, q) pairs after the first 2 steps (sum w u^2)
+  seeded_cells_seed3.json  the smallest seeded-cell geometry, 4 sampled pairs,
+                           full echo
 """
 
 from __future__ import annotations
@@ -22,6 +23,11 @@ import os
 import sys
 import time
 from concurrent.futures import ProcessPoolExecutor
+
+# One BLAS thread per worker process; set before numpy is imported (the
+# workers are forked from this process).
+for _k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_k] = "1"
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -34,7 +40,6 @@ import dmri_inputs as di  # noqa: E402
 
 def _solve(args):
     name, idx, n_steps = args
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle import fem, timestep
     prob, seq, sysl = _workload(name)
     asm = fem.assemble(prob)
@@ -45,20 +50,20 @@ def _solve(args):
 
 
 def _workload(name):
-    if name == "config1":
-        return di.config1()
-    if name == "config2_first2":
-        return di.config2()
-    if name == "config3_seed3":
-        return di.config3(3)
+    if name == "cylinder_36":
+        return di.cylinder_36()
+    if name == "cylinder_57_first2":
+        return di.cylinder_57_batched()
+    if name == "seeded_cells_seed3":
+        return di.seeded_cells(3)
     raise KeyError(name)
 
 
 SAMPLES = {
-    "config1": (list(range(8)), None),
+    "cylinder_36": (list(range(8)), None),
     # b in {5000, 2667, 333} x an axis-near, an oblique and an equatorial direction
-    "config2_first2": ([15, 8, 1, 16 * 20 + 15, 16 * 33 + 8, 16 * 63 + 1], 2),
-    "config3_seed3": ([0, 11, 22, 31], None),
+    "cylinder_57_first2": ([15, 8, 1, 16 * 20 + 15, 16 * 33 + 8, 16 * 63 + 1], 2),
+    "seeded_cells_seed3": ([0, 11, 22, 31], None),
 }
 
 

@@ -46,7 +46,7 @@ def test_spmv_bytes_formula():
 
 
 def _summary():
-    path = os.path.join(ROOT, "profiles", "hbm_counters_k_spmv_pair_config2_mixed.md")
+    path = os.path.join(ROOT, "profiles", "hbm_counters_k_spmv_pair_cylinder_57_batched_mixed.md")
     if not os.path.exists(path):
         pytest.skip("no committed counter summary")
     return open(path).read()
@@ -57,16 +57,16 @@ def test_counter_summary_is_tied_to_its_workload():
     m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     assert m
     recorded = re.search(r"csrc_sha256:\s*([0-9a-f]+)", text).group(1)
-    got = bench.profiled_traffic("k_spmv_pair", "config2", "mixed", 1e-6)
+    got = bench.profiled_traffic("k_spmv_pair", "cylinder_57_batched", "mixed", 1e-6)
     if recorded == bench.csrc_sha256():
         assert got == pytest.approx(float(m.group(1)))
     else:
         assert got is None
     # other tolerance, precision, workload or kernel: no figure
-    assert bench.profiled_traffic("k_spmv_pair", "config2", "mixed", 1e-8) is None
-    assert bench.profiled_traffic("k_spmv_pair", "config2", "fp64", 1e-6) is None
-    assert bench.profiled_traffic("k_spmv_pair", "config1", "mixed", 1e-6) is None
-    assert bench.profiled_traffic("k_spmv_dot", "config2", "mixed", 1e-6) is None
+    assert bench.profiled_traffic("k_spmv_pair", "cylinder_57_batched", "mixed", 1e-8) is None
+    assert bench.profiled_traffic("k_spmv_pair", "cylinder_57_batched", "fp64", 1e-6) is None
+    assert bench.profiled_traffic("k_spmv_pair", "cylinder_36", "mixed", 1e-6) is None
+    assert bench.profiled_traffic("k_spmv_dot", "cylinder_57_batched", "mixed", 1e-6) is None
 
 
 def test_source_hash_covers_the_library_sources(tmp_path, monkeypatch):

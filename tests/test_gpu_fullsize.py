@@ -59,8 +59,8 @@ def _err(sig, ref, s0):
 
 @pytest.mark.parametrize("precision,rtol,tol", [(0, 1e-12, 1e-9), (1, 1e-6, 1e-4)])
 def test_cylinder_36_full_echo(Sim, precision, rtol, tol):
-    d, ref = _golden("config1")
-    prob, seq, sysl = di.config1()
+    d, ref = _golden("cylinder_36")
+    prob, seq, sysl = di.cylinder_36()
     idx = np.array(d["index"])
     sig = _run(Sim, prob, seq, sysl.b[idx], sysl.q[idx], precision=precision, rtol=rtol)
     err = _err(sig, ref, ref[np.argmin(sysl.b[idx])])
@@ -69,8 +69,8 @@ def test_cylinder_36_full_echo(Sim, precision, rtol, tol):
 
 
 def test_benchmark_workload_first_steps(Sim):
-    d, ref = _golden("config2_first2")
-    prob, seq, sysl = di.config2()
+    d, ref = _golden("cylinder_57_first2")
+    prob, seq, sysl = di.cylinder_57_batched()
     idx = np.array(d["index"])
     sig = _run(Sim, prob, seq, sysl.b[idx], sysl.q[idx], precision=0, rtol=1e-12,
                n_steps=d["n_steps"])
@@ -85,7 +85,7 @@ def test_benchmark_workload_conservation(Sim):
     # discrete scheme (the oracle pins this); here every one of the 1024
     # systems runs with the default solver and the 64 b = 0 signals must
     # equal the box volume (u0 = 1) to the solver tolerance.
-    prob, seq, sysl = di.config2()
+    prob, seq, sysl = di.cylinder_57_batched()
     sig = _run(Sim, prob, seq, sysl.b, sysl.q)
     vol = float(np.prod(np.asarray(prob.box_hi) - np.asarray(prob.box_lo)))
     zero = sysl.b == 0
@@ -97,8 +97,8 @@ def test_benchmark_workload_conservation(Sim):
 
 
 def test_seeded_cells_full_echo(Sim):
-    d, ref = _golden("config3_seed3")
-    prob, seq, sysl = di.config3(3)
+    d, ref = _golden("seeded_cells_seed3")
+    prob, seq, sysl = di.seeded_cells(3)
     idx = np.array(d["index"])
     sig = _run(Sim, prob, seq, sysl.b[idx], sysl.q[idx], precision=0, rtol=1e-12)
     err = np.abs(sig - ref) / np.abs(ref)

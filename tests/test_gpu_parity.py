@@ -66,8 +66,8 @@ def test_apply_operator_matches_csr(Sim):
         sim.dmri_set_option("precision", 0)
 
 
-def test_config0_closed_form(Sim):
-    prob, seq, sysl = di.config0()
+def test_free_diffusion_closed_form(Sim):
+    prob, seq, sysl = di.free_diffusion_10()
     with Sim(0) as sim:
         sim.set_sequence(seq)
         sim.set_options(rtol=1e-12)
@@ -117,7 +117,7 @@ def test_fp64_transformed_matches_oracle(Sim, tile, guess):
     assert err.max() < 1e-9
 
 
-def test_fp64_full_pgse_config1_geometry_coarse(Sim):
+def test_fp64_full_pgse_cylinder_geometry_coarse(Sim):
     # The config-1 geometry (cylinder r=5 in a 12 um box) at n=12 with the
     # full PGSE timing of the workload.
     prob = di.cylinder_box(n=12)
@@ -131,7 +131,7 @@ def test_fp64_full_pgse_config1_geometry_coarse(Sim):
         pid = sim.add_problem(prob)
         sig, st = sim.dmri_run([pid] * 8, b, q)
     err = rel_err(sig, ref, ref[0])
-    _say("config1-coarse max err %.2e" % err.max())
+    _say("cylinder-coarse max err %.2e" % err.max())
     assert err.max() < 1e-9
     assert sig[0].real == pytest.approx(1728.0, rel=1e-12)
 

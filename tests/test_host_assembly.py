@@ -62,7 +62,7 @@ CASES = {
     "cyl_cube": lambda: di.cylinder_box(n=8, half=6.0, r=4.0, kappa=0.1, mode="cube"),
     "slab_neumann": lambda: di.slab_box(n=6, half=3.0, split=0.4, D=(3e-3, 1e-3), kappa=1e-2,
                                         periodic_mask=0),
-    "seeded_cells": lambda: di.config3(3, n_fixed=10)[0],
+    "seeded_cells": lambda: di.seeded_cells(3, n_fixed=10)[0],
 }
 
 

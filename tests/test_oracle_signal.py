@@ -50,8 +50,8 @@ def recurrence(D, b, seq, T2=None, G=None):
     return c
 
 
-def test_config0_free_diffusion_closed_form():
-    prob, seq, sysl = di.config0()
+def test_free_diffusion_box_closed_form():
+    prob, seq, sysl = di.free_diffusion_10()
     s = timestep.signals(prob, seq, sysl.b, sysl.q)[0]
     vol = 1000.0
     c = recurrence(3e-3, 1000.0, seq)
