@@ -984,7 +984,8 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
         kp(q);
         for (double v : {double(n_sys), double(N), double(sizeof(T)), double(bs.herm),
                          double(g.S), double(bs.gp.B), h->opt.rtol, double(h->opt.max_iter),
-                         double(h->opt.guess), double(h->opt.extrap_order), h->dt, h->theta,
+                         double(h->opt.guess), double(h->opt.extrap_order),
+                         double(h->opt.extrap_damp), h->dt, h->theta,
                          h->delta, h->Delta})
             kd(v);
         GraphCache& gc = lane(h).graph;

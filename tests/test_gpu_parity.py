@@ -395,9 +395,17 @@ def test_graph_replay_matches_eager(Sim):
             sim.set_options(graph=0)
             again, _ = sim.dmri_run([pid] * len(b), b, q)
             assert np.array_equal(again, eager)
+        # A changed guess option must not replay the graph captured with the
+        # old one: undamped extrapolation, graph vs eager, bit for bit.
+        sim.set_options(guess=1, extrap_damp=0, graph=0)
+        eager_u, _ = sim.dmri_run([pid] * len(b), b, q)
+        sim.set_options(graph=1)
+        graph_u, _ = sim.dmri_run([pid] * len(b), b, q)
+        assert np.array_equal(graph_u, eager_u)
     for sig in runs:
         assert np.array_equal(sig, eager)
     assert rel_err(eager, ref, ref[0]).max() < 1e-9
+    assert rel_err(eager_u, ref, ref[0]).max() < 1e-9
 
 
 def test_autotune_matches_oracle(Sim):
