@@ -72,9 +72,13 @@ def workload(name):
 def kernel_bytes(kind, n_dof, nnz, total_iters, tile, prec_bytes, n_steps, n_sys):
     """Algorithmic HBM bytes of one kernel summed over a run.
 
-    Vector traffic per DOF and system (complex of 2*prec_bytes) and matrix
-    traffic per matrix row per active system tile (every tile of S systems
-    re-reads the matrix): see the design doc for the derivation.
+    Vector traffic per DOF and system (complex of c = 2*prec_bytes bytes) plus
+    matrix traffic per active system tile, since every tile of S systems
+    re-reads the matrix: the SpMV reads p once and writes q (2c) and reads per
+    stored entry a column index (4 B) and five values (K0, M_D, V_x, V_y, V_z),
+    plus the row pointers; the CG update reads r, q and writes r (3c); the
+    direction update reads r, p, x and writes p, x (5c); both read the five
+    diagonal values per row and tile.
     """
     c = 2 * prec_bytes
     mat = nnz * (4 + 5 * prec_bytes) + 4 * n_dof       # col + K0 + {MD, Vx, Vy, Vz} + row_ptr
@@ -213,8 +217,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (got --gpus %d); the per-GPU "
-              "shard design is described in DESIGN.md" % args.gpus, file=sys.stderr)
+        print("bench.py: this build runs on exactly one GPU (got --gpus %d); systems and "
+              "meshes would shard across GPUs without communication, but only one GPU is "
+              "driven here" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
