@@ -32,6 +32,10 @@ conservation at b = 0; kappa -> 0 decoupling and kappa -> inf
 single-compartment limit; S(-q) = conj S(q); 1-D slab matrix formalism for
 both forms; the two forms agree on a non-symmetric case; dense solves equal
 SuperLU.
+
+Parity unpinned: signals of the staircase compartment geometries with the
+gradient across the membranes (e.g. q perpendicular to the cylinder) have no
+closed form; there the oracle rests on the invariants and limits above.
 """
 
 from __future__ import annotations
