@@ -43,10 +43,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# L2-to-CU ceiling of 1 KB row gathers (64 lanes x 16 B) from an L2-resident
-# vector, measured on MI355X with gather_ceiling.hip: 19.3 cycles per
-# wavefront load per CU, i.e. 53 B per clock per CU at 2.4 GHz on 256 CUs.
-L2_GATHER_PEAK_GBS = 32600.0
 KERNELS = {"spmv": 1, "update": 2, "pupdate": 3, "init": 4}
 KERNEL_NAMES = {"spmv": "k_spmv_dot", "update": "k_update", "pupdate": "k_pupdate",
                 "init": "k_init"}
@@ -132,39 +128,56 @@ _CPU = {}
 
 
 def _cpu_worker(args):
-    """One single-threaded oracle solve of the first n steps of one system."""
-    i, n_steps = args
+    """One single-threaded oracle solve of n steps of one system, from step s0."""
+    i, s0, n_steps = args
     from oracle import timestep
     asm, seq, sysl = _CPU["asm"], _CPU["seq"], _CPU["sysl"]
     t0 = time.perf_counter()
     timestep.solve_transformed(asm, seq, float(sysl.b[i]), sysl.q[i], n_steps=n_steps,
-                               solver="krylov")
+                               solver="krylov", start_step=s0)
     return time.perf_counter() - t0
+
+
+def cpu_sample_plan(sysl, n_total_steps, n_steps_sample, n_proc):
+    """(system, first step) per oracle process: systems spread over the b range
+    (sorted by b, evenly spaced), windows of n_steps_sample steps spread over
+    the whole echo, so the sample mixes easy and hard solves as the full run
+    does."""
+    order = np.argsort(np.asarray(sysl.b), kind="stable")
+    plan = []
+    for k in range(n_proc):
+        i = int(order[(2 * k + 1) * len(order) // (2 * n_proc)])
+        s0 = (k * (n_total_steps - n_steps_sample)) // max(1, n_proc - 1)
+        plan.append((i, int(s0)))
+    return plan
 
 
 def cpu_baseline(prob, seq, sysl, n_steps_sample, n_proc):
     """FP64 oracle (assembly + Krylov-to-rounding solves) on a bounded sample:
-    n_proc single-threaded processes, each stepping a different system."""
+    n_proc single-threaded processes, each stepping a different system over a
+    different window of the echo."""
     import multiprocessing as mp
     from oracle import fem
     t0 = time.perf_counter()
     asm = fem.assemble(prob)
     t_asm = time.perf_counter() - t0
     _CPU.update(asm=asm, seq=seq, sysl=sysl)
-    order = np.argsort(-np.asarray(sysl.b), kind="stable")
-    idx = [int(order[k % len(order)]) for k in range(n_proc)]
+    plan = cpu_sample_plan(sysl, seq.n_steps, n_steps_sample, n_proc)
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(n_proc) as pool:
-        per = pool.map(_cpu_worker, [(i, n_steps_sample) for i in idx])
+        per = pool.map(_cpu_worker, [(i, s0, n_steps_sample) for i, s0 in plan])
     wall = time.perf_counter() - t0
     rate = asm.n_dof * n_steps_sample * n_proc / wall
     return {
         "value": rate, "unit": "DOF-steps/s", "cores": n_proc, "kind": "oracle",
-        "sample": ("%d systems (largest b first) x first %d of %d steps, one single-threaded "
-                   "process each (SciPy CG to 1e-13, Jacobi); wall %.1fs; per-process %.1f-%.1fs; "
-                   "assembly %.1fs excluded" % (n_proc, n_steps_sample, seq.n_steps, wall,
-                                                min(per), max(per), t_asm)),
+        "sample": ("%d systems spread over b (%g..%g) x %d-step windows spread over the %d-step "
+                   "echo (first steps %s), each started from the initial magnetization; one "
+                   "single-threaded process each (SciPy CG to 1e-13, Jacobi); wall %.1fs; "
+                   "per-process %.1f-%.1fs; assembly %.1fs excluded"
+                   % (n_proc, min(float(sysl.b[i]) for i, _ in plan),
+                      max(float(sysl.b[i]) for i, _ in plan), n_steps_sample, seq.n_steps,
+                      [s for _, s in plan], wall, min(per), max(per), t_asm)),
         "host_cpus": os.cpu_count(),
     }
 
@@ -301,16 +314,6 @@ def main():
     kb = kernel_bytes(args.time_kernel, n_dof, nnz, tot_iters, ktile, pbytes,
                       n_steps * args.steps, len(sysl))
     achieved = kb / t_kernel / 1e9 if t_kernel > 0 else None
-    # Every stored matrix entry gathers one complex vector value per system
-    # (from L2 when the neighbour row is cached): the SpMV's second bound.
-    gather = None
-    if args.time_kernel == "spmv" and t_kernel > 0:
-        gb = nnz * 2 * pbytes * tot_iters
-        gather = {"achieved": gb / t_kernel / 1e9, "peak": L2_GATHER_PEAK_GBS, "unit": "GB/s",
-                  "frac": gb / t_kernel / 1e9 / L2_GATHER_PEAK_GBS,
-                  "bytes_per_launch": gb / max(1, n_launch),
-                  "peak_source": "gather_ceiling.hip: L2-resident 1 KB row gathers, 19.3 "
-                                 "cycles per wavefront load per CU"}
     roofline = {
         "kernel": kname,
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -319,7 +322,6 @@ def main():
         "launches": n_launch, "mean_launch_us": 1e6 * t_kernel / max(1, n_launch),
         "bytes_per_launch": kb / max(1, n_launch),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
-        "l2_gather": gather,
     }
     out = {
         "metric": "DOF-steps/s", "value": value, "unit": "DOF-steps/s", "n_gpus": 1,

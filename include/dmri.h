@@ -57,18 +57,20 @@ typedef enum {
 } dmri_status;
 
 /* Per-run statistics. Array members are caller-owned, length n_sys (the
- * n_pairs of the run), and may be NULL. Scalars are always written. */
+ * n_pairs of the run), and may be NULL. Scalars are always written. The
+ * first seven members are the minimal set (sizes, per-system results, the
+ * three wall times); the rest are work counters and kernel timing. */
 typedef struct {
     int64_t  n_sys;
     int32_t* iters_total;     /* Krylov iterations summed over all time steps */
     uint8_t* converged;       /* 1 if every step reached rtol */
     double*  final_rel_res;   /* ||r|| / ||b|| of the last step */
-    int64_t  total_iterations;/* sum over systems and steps */
-    int64_t  spmv_rows;       /* matrix rows applied (all systems), work counter */
-    int64_t  n_steps;         /* time steps taken */
     double   t_setup_s;       /* host+device set-up inside the run */
     double   t_solve_s;       /* time loop */
     double   t_signal_s;      /* signal quadrature and copy-out */
+    int64_t  total_iterations;/* sum over systems and steps */
+    int64_t  spmv_rows;       /* matrix rows applied (all systems), work counter */
+    int64_t  n_steps;         /* time steps taken */
     int64_t  n_kernel_launches; /* launches of the kernel chosen by option "time_kernel" */
     double   t_kernel_s;      /* their summed durations (HIP events on the run's stream) */
 } dmri_stats;
@@ -300,7 +302,10 @@ DMRI_API dmri_status dmri_guess_train(dmri_handle h, int64_t n, const float* d_f
  *              when b == 0; must be nonzero when b > 0
  *   signal_out [n_pairs][2] Re, Im of S (um^3)
  *   stats      may be NULL
- * All pairs of all problems are solved as one batch on the device.
+ * The pairs of each problem are solved as one batch on the device (all
+ * systems of a mesh share every matrix read); batches of different
+ * problems run one after another, or several at once on their own streams
+ * with option "concurrency" > 1. Results do not depend on either.
  * n_pairs = 0 is an empty run: DMRI_OK, stats zeroed, nothing read or written.
  * Returns DMRI_NOT_CONVERGED (results still written) when any system hit
  * max_iter in some step. */
@@ -309,13 +314,16 @@ DMRI_API dmri_status dmri_run(dmri_handle h, int64_t n_pairs,
                      double* signal_out, dmri_stats* stats);
 
 /* Same as dmri_run with device-resident inputs and output (e.g. from
- * PyTorch tensors): d_b [n_pairs], d_q [n_pairs][3], d_signal [n_pairs][2]
- * are device pointers, all pairs on one problem (problem_id). Work is
- * enqueued on hip_stream (NULL = the handle's own stream); the call
- * synchronizes that stream to poll convergence and returns after the
- * signals have been written. n_pairs = 0: DMRI_OK, stats zeroed. */
-DMRI_API dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
-                            int64_t n_pairs, const double* d_b, const double* d_q,
+ * PyTorch tensors): d_problem_id [n_pairs] (int32), d_b [n_pairs],
+ * d_q [n_pairs][3], d_signal [n_pairs][2] are device pointers. Work is
+ * enqueued on hip_stream (NULL = the handle's own stream), after the work
+ * already queued there; the call reads the (small) pair list to the host to
+ * check it and form the batches, synchronizes that stream to poll
+ * convergence, and returns after the signals have been written. When every
+ * pair names the same problem its b and q are used in place; otherwise the
+ * batches are formed as in dmri_run. n_pairs = 0: DMRI_OK, stats zeroed. */
+DMRI_API dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int64_t n_pairs,
+                            const int32_t* d_problem_id, const double* d_b, const double* d_q,
                             double* d_signal, dmri_stats* stats);
 
 /* Apply one step operator of problem `problem_id` to host vectors

@@ -105,12 +105,16 @@ def _unit(q):
 
 
 def solve_transformed(asm: Assembly, seq, b: float, q, n_steps: Optional[int] = None,
-                      cache_size: int = 256, return_u: bool = False, solver: str = "splu"):
+                      cache_size: int = 256, return_u: bool = False, solver: str = "splu",
+                      start_step: int = 0):
     """Signal of one (b, q) system with the transformed operator.
 
     n_steps limits the run to the first n steps (for timing samples and
     intermediate checks); the signal is then sum w u^n at that step, which is
-    the physical signal only when F(t^n) = 0.
+    the physical signal only when F(t^n) = 0. start_step = s > 0 starts the
+    recurrence at t^s from the initial magnetization instead of t^0 and takes
+    steps s+1 .. s+n_steps (a timing sample of later steps; not a physical
+    trajectory).
     """
     k = float(seq.dt)
     th = float(seq.theta)
@@ -118,7 +122,8 @@ def solve_transformed(asm: Assembly, seq, b: float, q, n_steps: Optional[int] = 
     F = seqmod.pgse_F(t, seq.delta, seq.Delta)
     G = float(seqmod.b_to_G(b, seq.delta, seq.Delta))
     qn = _unit(q)
-    N = len(t) - 1 if n_steps is None else int(n_steps)
+    s0 = int(start_step)
+    N = len(t) - 1 if n_steps is None else min(len(t) - 1, s0 + int(n_steps))
 
     base = (asm.S + asm.IG + asm.R2).tocsr()
     Mk = (asm.M / k).tocsr()
@@ -132,7 +137,7 @@ def solve_transformed(asm: Assembly, seq, b: float, q, n_steps: Optional[int] = 
 
     cache = _LUCache(cache_size)
     u = asm.u0.astype(np.complex128)
-    for n in range(1, N + 1):
+    for n in range(s0 + 1, N + 1):
         rhs = Mk @ u - (1.0 - th) * L_apply(F[n - 1], u)
         Fn = float(F[n])
         if solver == "dense":

@@ -51,12 +51,12 @@ class Stats(C.Structure):
         ("iters_total", C.POINTER(C.c_int32)),
         ("converged", C.POINTER(C.c_uint8)),
         ("final_rel_res", C.POINTER(C.c_double)),
-        ("total_iterations", C.c_int64),
-        ("spmv_rows", C.c_int64),
-        ("n_steps", C.c_int64),
         ("t_setup_s", C.c_double),
         ("t_solve_s", C.c_double),
         ("t_signal_s", C.c_double),
+        ("total_iterations", C.c_int64),
+        ("spmv_rows", C.c_int64),
+        ("n_steps", C.c_int64),
         ("n_kernel_launches", C.c_int64),
         ("t_kernel_s", C.c_double),
     ]
@@ -99,7 +99,7 @@ def load(path: Optional[str] = None):
     lib.dmri_guess_eval.argtypes = [vp, i64, vp, vp, vp, vp, P(dbl)]
     lib.dmri_guess_train.argtypes = [vp, i64, vp, vp, i32, dbl, P(dbl), P(dbl)]
     lib.dmri_run.argtypes = [vp, i64, vp, vp, vp, vp, P(Stats)]
-    lib.dmri_run_device.argtypes = [vp, vp, i32, i64, vp, vp, vp, P(Stats)]
+    lib.dmri_run_device.argtypes = [vp, vp, i64, vp, vp, vp, vp, P(Stats)]
     lib.dmri_apply_operator.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
     for name in EXPORTED:
         f = getattr(lib, name)
@@ -297,18 +297,29 @@ class Simulator:
         stats = _stats_dict(st, iters, conv, rres, status)
         return sig[:, 0] + 1j * sig[:, 1], stats
 
-    def dmri_run_device(self, problem_id: int, b_dev, q_dev, sig_dev, stream_ptr=None):
-        """Device-resident run. b_dev/q_dev/sig_dev are torch float64 CUDA tensors
-        ([n], [n,3], [n,2]); stream_ptr is a raw HIP stream handle or None."""
+    def dmri_run_device(self, pid_dev, b_dev, q_dev, sig_dev, stream_ptr=None):
+        """Device-resident run. pid_dev is a torch int32 CUDA tensor [n] (or an
+        int: one problem for every pair, placed in a device tensor here);
+        b_dev/q_dev/sig_dev are torch float64 CUDA tensors ([n], [n,3], [n,2]);
+        stream_ptr is a raw HIP stream handle or None."""
+        import torch
         n = int(b_dev.shape[0])
-        for t in (b_dev, q_dev, sig_dev):
+        made = isinstance(pid_dev, (int, np.integer))
+        if made:
+            pid_dev = torch.full((n,), int(pid_dev), dtype=torch.int32, device=b_dev.device)
+        if pid_dev.dtype != torch.int32 or tuple(pid_dev.shape) != (n,):
+            raise ValueError("problem ids must be an int32 tensor of shape [n]")
+        for t in (pid_dev, b_dev, q_dev, sig_dev):
             if not t.is_contiguous():
                 raise ValueError("tensors must be contiguous")
+        if made or stream_ptr is None:
+            _sync(b_dev)  # torch's pending work, when the library runs on its own stream
         st = Stats()
         status = self._check(self.lib.dmri_run_device(
-            self.h, None if stream_ptr is None else C.c_void_p(stream_ptr), int(problem_id), n,
-            C.c_void_p(b_dev.data_ptr()), C.c_void_p(q_dev.data_ptr()),
-            C.c_void_p(sig_dev.data_ptr()), C.byref(st)), allow_nc=True)
+            self.h, None if stream_ptr is None else C.c_void_p(stream_ptr), n,
+            C.c_void_p(pid_dev.data_ptr()), C.c_void_p(b_dev.data_ptr()),
+            C.c_void_p(q_dev.data_ptr()), C.c_void_p(sig_dev.data_ptr()), C.byref(st)),
+            allow_nc=True)
         return _stats_dict(st, None, None, None, status)
 
     def dmri_apply_operator(self, pid: int, which: int, c, d, x):

@@ -50,6 +50,11 @@ thread_local std::string g_create_error = "no error";
         }                                                                              \
     } while (0)
 
+// Bumped by every device (re)allocation of a DevBuf. A captured graph bakes
+// device addresses into its launches, so its cache key includes this count:
+// any reallocation since the capture forces a new capture.
+std::atomic<uint64_t> g_alloc_gen{0};
+
 template <typename T>
 struct DevBuf {
     T* p = nullptr;
@@ -69,6 +74,7 @@ struct DevBuf {
         if (count == 0) count = 1;
         HIPCHK(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
         n = count;
+        g_alloc_gen.fetch_add(1);
     }
     void upload(const T* h, size_t count, hipStream_t st) {
         alloc(count);
@@ -736,6 +742,12 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     // work to hide the per-launch cost.
     const bool small = static_cast<int64_t>(g.n_rows) * g.ld <= 131072;
     bs.persist = (h->opt.persistent == 1 || (h->opt.persistent == 2 && small)) && g.ld <= 64;
+    // The grid barrier needs every block resident: otherwise chunked launches.
+    if (bs.persist) {
+        const bool fits = h->opt.precision != 0 ? persistent_fits<float>(bs.gp, bs.herm, n_cu)
+                                                : persistent_fits<double>(bs.gp, bs.herm, n_cu);
+        if (!fits) bs.persist = false;
+    }
     // FP32 inner solves of wide batches: 128-system tiles, two systems per lane.
     bs.pair = want_pair && !bs.persist && S == 64 && n_sys > 64 && !g.queue &&
               static_cast<int64_t>(g.n_rows) * 1024 < (int64_t(1) << 31);
@@ -970,6 +982,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
             std::memcpy(&bits, &v, sizeof bits);
             key.push_back(bits);
         };
+        key.push_back(g_alloc_gen.load());
         kp(&P);
         kp(Av.K0);
         kp(Av.aux);
@@ -1755,6 +1768,125 @@ static void reset_stats(dmri_stats* st, int64_t n) {
     st->t_kernel_s = 0.0;
 }
 
+}  // extern "C"
+
+namespace dmri {
+namespace {
+
+// Validates host pairs (problem ids, b >= 0, q nonzero when b > 0).
+void check_pairs(dmri_ctx* h, int64_t n_pairs, const int32_t* problem_id, const double* b,
+                 const double* q) {
+    for (int64_t i = 0; i < n_pairs; ++i) {
+        get_problem(h, problem_id[i]);
+        const double nq = std::sqrt(q[3 * i] * q[3 * i] + q[3 * i + 1] * q[3 * i + 1] +
+                                    q[3 * i + 2] * q[3 * i + 2]);
+        if (!std::isfinite(b[i]) || b[i] < 0 || !std::isfinite(nq) || (b[i] > 0 && !(nq > 0)))
+            throw Error(DMRI_E_INVALID, "b must be finite and >= 0, q finite and nonzero");
+    }
+}
+
+// Runs host pairs grouped by problem: one batch per problem, in sequence or
+// (option "concurrency") on several lanes at once. Signals go to host memory
+// in input order. Returns true when some system did not converge.
+bool run_host_pairs(dmri_ctx* h, int64_t n_pairs, const int32_t* problem_id, const double* b,
+                    const double* q, double* signal_out, dmri_stats* stats) {
+    // Group pairs by problem, keeping input order inside each group.
+    std::vector<std::pair<int32_t, std::vector<int64_t>>> groups;
+    for (int32_t pid = 0; pid < static_cast<int32_t>(h->problems.size()); ++pid) {
+        std::vector<int64_t> idx;
+        for (int64_t i = 0; i < n_pairs; ++i)
+            if (problem_id[i] == pid) idx.push_back(i);
+        if (!idx.empty()) groups.emplace_back(pid, std::move(idx));
+    }
+    std::atomic<bool> any_nc{false};
+    std::mutex mu;
+    auto run_group = [&](int32_t pid, std::vector<int64_t> idx) {
+        // Tiles of systems with similar b converge together, so whole tiles
+        // drop out of the Krylov loop early (results do not depend on the
+        // position of a system in the batch).
+        if (h->opt.sort_systems) order_systems(h, pid, b, q, idx);
+        hipStream_t st = lane(h).stream;
+        ProblemRec& P = get_problem(h, pid);
+        const double ts = now_s();
+        ensure_uploaded(h, P, h->opt.precision != 0);
+        const int64_t ns = static_cast<int64_t>(idx.size());
+        std::vector<double> hb(ns), hq(3 * ns);
+        for (int64_t i = 0; i < ns; ++i) {
+            hb[i] = b[idx[i]];
+            for (int a = 0; a < 3; ++a) hq[3 * i + a] = q[3 * idx[i] + a];
+        }
+        Workspace& W = lane(h).ws;
+        W.b_in.upload(hb.data(), ns, st);
+        W.q_in.upload(hq.data(), 3 * ns, st);
+        W.sig.alloc(ns);
+        const double t_up = now_s() - ts;
+        BatchResult R;
+        run_batch(h, P, ns, W.b_in.p, W.q_in.p, W.sig.p, R);
+        std::vector<double> hs(2 * ns);
+        HIPCHK(hipMemcpyAsync(hs.data(), W.sig.p, sizeof(double2) * ns, hipMemcpyDeviceToHost,
+                              st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::lock_guard<std::mutex> lock(mu);
+        for (int64_t i = 0; i < ns; ++i) {
+            signal_out[2 * idx[i]] = hs[2 * i];
+            signal_out[2 * idx[i] + 1] = hs[2 * i + 1];
+            if (R.flags[i]) any_nc = true;
+        }
+        if (stats) stats->t_setup_s += t_up;
+        fill_stats(stats, idx, R, n_pairs);
+        remember_costs(h, pid, b, q, idx, R.iters);
+    };
+    // Several problems run concurrently, one lane (stream, workspace, host
+    // thread) each, unless a feature shares state across batches.
+    int n_lanes = std::min<int>(h->opt.concurrency, static_cast<int>(groups.size()));
+    if (h->opt.autotune || h->model.rec_cap > 0 || h->opt.graph) n_lanes = 1;
+    if (n_lanes <= 1) {
+        for (const auto& gr : groups) run_group(gr.first, gr.second);
+    } else {
+        while (static_cast<int>(h->lanes.size()) < n_lanes) {
+            h->lanes.push_back(std::make_unique<Lane>());
+            h->lanes.back()->create();
+        }
+        std::atomic<int> next{0};
+        std::exception_ptr first_error;
+        std::vector<std::thread> pool;
+        for (int t = 0; t < n_lanes; ++t) {
+            pool.emplace_back([&, t] {
+                // Lane 0 keeps the stream the caller's thread set on it.
+                tl_lane = t == 0 ? &lane(h) : h->lanes[t].get();
+                try {
+                    HIPCHK(hipSetDevice(h->device));
+                    for (int gi = next++; gi < static_cast<int>(groups.size()); gi = next++)
+                        run_group(groups[gi].first, groups[gi].second);
+                } catch (...) {
+                    std::lock_guard<std::mutex> lock(mu);
+                    if (!first_error) first_error = std::current_exception();
+                    next = static_cast<int>(groups.size());
+                }
+                tl_lane = nullptr;
+            });
+        }
+        for (auto& th : pool) th.join();
+        if (first_error) std::rethrow_exception(first_error);
+    }
+    return any_nc.load();
+}
+
+// Sets the lane's stream for the duration of a call and restores it.
+struct StreamOverride {
+    dmri_ctx* h;
+    hipStream_t saved;
+    StreamOverride(dmri_ctx* hh, void* s) : h(hh), saved(lane(hh).stream) {
+        if (s) lane(h).stream = static_cast<hipStream_t>(s);
+    }
+    ~StreamOverride() { lane(h).stream = saved; }
+};
+
+}  // namespace
+}  // namespace dmri
+
+extern "C" {
+
 dmri_status dmri_run(dmri_handle h, int64_t n_pairs, const int32_t* problem_id, const double* b,
                      const double* q, double* signal_out, dmri_stats* stats) {
     if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
@@ -1764,102 +1896,17 @@ dmri_status dmri_run(dmri_handle h, int64_t n_pairs, const int32_t* problem_id, 
         if (n_pairs < 0) throw Error(DMRI_E_INVALID, "n_pairs must be >= 0");
         if (n_pairs > 0 && (!problem_id || !b || !q || !signal_out))
             throw Error(DMRI_E_INVALID, "NULL argument");
-        for (int64_t i = 0; i < n_pairs; ++i) {
-            get_problem(h, problem_id[i]);
-            const double nq = std::sqrt(q[3 * i] * q[3 * i] + q[3 * i + 1] * q[3 * i + 1] +
-                                        q[3 * i + 2] * q[3 * i + 2]);
-            if (!std::isfinite(b[i]) || b[i] < 0 || !std::isfinite(nq) || (b[i] > 0 && !(nq > 0)))
-                throw Error(DMRI_E_INVALID, "b must be finite and >= 0, q finite and nonzero");
-        }
-        const double t_start = now_s();
+        check_pairs(h, n_pairs, problem_id, b, q);
         reset_stats(stats, n_pairs);
         if (n_pairs == 0) return DMRI_OK;
-        // Group pairs by problem, keeping input order inside each group.
-        std::vector<std::pair<int32_t, std::vector<int64_t>>> groups;
-        for (int32_t pid = 0; pid < static_cast<int32_t>(h->problems.size()); ++pid) {
-            std::vector<int64_t> idx;
-            for (int64_t i = 0; i < n_pairs; ++i)
-                if (problem_id[i] == pid) idx.push_back(i);
-            if (!idx.empty()) groups.emplace_back(pid, std::move(idx));
-        }
-        std::atomic<bool> any_nc{false};
-        std::mutex mu;
-        auto run_group = [&](int32_t pid, std::vector<int64_t> idx) {
-            // Tiles of systems with similar b converge together, so whole tiles
-            // drop out of the Krylov loop early (results do not depend on the
-            // position of a system in the batch).
-            if (h->opt.sort_systems) order_systems(h, pid, b, q, idx);
-            hipStream_t st = lane(h).stream;
-            ProblemRec& P = get_problem(h, pid);
-            const double ts = now_s();
-            ensure_uploaded(h, P, h->opt.precision != 0);
-            const int64_t ns = static_cast<int64_t>(idx.size());
-            std::vector<double> hb(ns), hq(3 * ns);
-            for (int64_t i = 0; i < ns; ++i) {
-                hb[i] = b[idx[i]];
-                for (int a = 0; a < 3; ++a) hq[3 * i + a] = q[3 * idx[i] + a];
-            }
-            Workspace& W = lane(h).ws;
-            W.b_in.upload(hb.data(), ns, st);
-            W.q_in.upload(hq.data(), 3 * ns, st);
-            W.sig.alloc(ns);
-            const double t_up = now_s() - ts;
-            BatchResult R;
-            run_batch(h, P, ns, W.b_in.p, W.q_in.p, W.sig.p, R);
-            std::vector<double> hs(2 * ns);
-            HIPCHK(hipMemcpyAsync(hs.data(), W.sig.p, sizeof(double2) * ns, hipMemcpyDeviceToHost,
-                                  st));
-            HIPCHK(hipStreamSynchronize(st));
-            std::lock_guard<std::mutex> lock(mu);
-            for (int64_t i = 0; i < ns; ++i) {
-                signal_out[2 * idx[i]] = hs[2 * i];
-                signal_out[2 * idx[i] + 1] = hs[2 * i + 1];
-                if (R.flags[i]) any_nc = true;
-            }
-            if (stats) stats->t_setup_s += t_up;
-            fill_stats(stats, idx, R, n_pairs);
-            remember_costs(h, pid, b, q, idx, R.iters);
-        };
-        // Several problems run concurrently, one lane (stream, workspace,
-        // host thread) each, unless a feature shares state across batches.
-        int n_lanes = std::min<int>(h->opt.concurrency, static_cast<int>(groups.size()));
-        if (h->opt.autotune || h->model.rec_cap > 0 || h->opt.graph) n_lanes = 1;
-        if (n_lanes <= 1) {
-            for (const auto& gr : groups) run_group(gr.first, gr.second);
-        } else {
-            while (static_cast<int>(h->lanes.size()) < n_lanes) {
-                h->lanes.push_back(std::make_unique<Lane>());
-                h->lanes.back()->create();
-            }
-            std::atomic<int> next{0};
-            std::exception_ptr first_error;
-            std::vector<std::thread> pool;
-            for (int t = 0; t < n_lanes; ++t) {
-                pool.emplace_back([&, t] {
-                    tl_lane = h->lanes[t].get();
-                    try {
-                        HIPCHK(hipSetDevice(h->device));
-                        for (int gi = next++; gi < static_cast<int>(groups.size()); gi = next++)
-                            run_group(groups[gi].first, groups[gi].second);
-                    } catch (...) {
-                        std::lock_guard<std::mutex> lock(mu);
-                        if (!first_error) first_error = std::current_exception();
-                        next = static_cast<int>(groups.size());
-                    }
-                    tl_lane = nullptr;
-                });
-            }
-            for (auto& th : pool) th.join();
-            if (first_error) std::rethrow_exception(first_error);
-        }
-        (void)t_start;
-        return any_nc.load() ? DMRI_NOT_CONVERGED : DMRI_OK;
+        const bool nc = run_host_pairs(h, n_pairs, problem_id, b, q, signal_out, stats);
+        return nc ? DMRI_NOT_CONVERGED : DMRI_OK;
     });
 }
 
-dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id, int64_t n_pairs,
-                            const double* d_b, const double* d_q, double* d_signal,
-                            dmri_stats* stats) {
+dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int64_t n_pairs,
+                            const int32_t* d_problem_id, const double* d_b, const double* d_q,
+                            double* d_signal, dmri_stats* stats) {
     if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
     return guarded(h, [&]() -> dmri_status {
         need_device(h);
@@ -1869,31 +1916,44 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
             reset_stats(stats, 0);
             return DMRI_OK;
         }
-        if (!d_b || !d_q || !d_signal) throw Error(DMRI_E_INVALID, "NULL argument");
+        if (!d_problem_id || !d_b || !d_q || !d_signal)
+            throw Error(DMRI_E_INVALID, "NULL argument");
+        StreamOverride so(h, hip_stream);
+        hipStream_t st = lane(h).stream;
+        // The pair list is small: read it (and b, q for the checks and the
+        // tile order) to the host, in stream order after the caller's work.
+        std::vector<int32_t> hp(n_pairs);
+        std::vector<double> hb(n_pairs), hq(3 * n_pairs);
+        HIPCHK(hipMemcpyAsync(hp.data(), d_problem_id, sizeof(int32_t) * n_pairs,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hb.data(), d_b, sizeof(double) * n_pairs, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hq.data(), d_q, sizeof(double) * 3 * n_pairs, hipMemcpyDeviceToHost,
+                              st));
+        HIPCHK(hipStreamSynchronize(st));
+        check_pairs(h, n_pairs, hp.data(), hb.data(), hq.data());
+        reset_stats(stats, n_pairs);
+        bool one = true;
+        for (int64_t i = 1; i < n_pairs; ++i) one &= hp[i] == hp[0];
+        if (!one) {
+            // Several problems: one batch per problem (as dmri_run), signals
+            // copied to the caller's buffer in input order.
+            std::vector<double> sig(2 * n_pairs);
+            const bool nc = run_host_pairs(h, n_pairs, hp.data(), hb.data(), hq.data(),
+                                           sig.data(), stats);
+            HIPCHK(hipMemcpyAsync(d_signal, sig.data(), sizeof(double2) * n_pairs,
+                                  hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            return nc ? DMRI_NOT_CONVERGED : DMRI_OK;
+        }
+        const int32_t problem_id = hp[0];
         ProblemRec& P = get_problem(h, problem_id);
-        hipStream_t saved = lane(h).stream;
-        if (hip_stream) lane(h).stream = static_cast<hipStream_t>(hip_stream);
-        struct Restore {
-            dmri_ctx* h;
-            hipStream_t s;
-            ~Restore() { lane(h).stream = s; }
-        } restore{h, saved};
         const double ts = now_s();
         ensure_uploaded(h, P, h->opt.precision != 0);
-        reset_stats(stats, n_pairs);
         if (stats) stats->t_setup_s = now_s() - ts;
         BatchResult R;
         std::vector<int64_t> idx(n_pairs);
         for (int64_t i = 0; i < n_pairs; ++i) idx[i] = i;
-        std::vector<double> hb(n_pairs), hq(3 * n_pairs);
-        if (h->opt.sort_systems) {
-            HIPCHK(hipMemcpyAsync(hb.data(), d_b, sizeof(double) * n_pairs, hipMemcpyDeviceToHost,
-                                  lane(h).stream));
-            HIPCHK(hipMemcpyAsync(hq.data(), d_q, sizeof(double) * 3 * n_pairs,
-                                  hipMemcpyDeviceToHost, lane(h).stream));
-            HIPCHK(hipStreamSynchronize(lane(h).stream));
-            order_systems(h, problem_id, hb.data(), hq.data(), idx);
-        }
+        if (h->opt.sort_systems) order_systems(h, problem_id, hb.data(), hq.data(), idx);
         bool identity = true;
         for (int64_t i = 0; i < n_pairs; ++i) identity &= idx[i] == i;
         if (identity) {
@@ -1901,7 +1961,6 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int32_t problem_id,
         } else {
             // Sorted copies of b and q in the lane's workspace; signals are
             // scattered back to the caller's order.
-            hipStream_t st = lane(h).stream;
             std::vector<double> sb(n_pairs), sq(3 * n_pairs);
             for (int64_t i = 0; i < n_pairs; ++i) {
                 sb[i] = hb[idx[i]];

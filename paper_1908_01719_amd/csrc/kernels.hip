@@ -1127,6 +1127,10 @@ __device__ __forceinline__ bool grid_sync(GridBarrier b) {
             bool released = false;
             if (atomicAdd(gc, 1u) == in_grp - 1) {
                 __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // The reset must be visible before this group's arrival on the
+                // global counter: a block released by the next generation may
+                // arrive on gc right after that.
+                __threadfence();
                 const uint32_t groups = gridDim.x < 8 ? gridDim.x : 8;
                 if (atomicAdd(b.count, 1u) == groups - 1) {
                     __hip_atomic_store(b.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2012,6 +2016,22 @@ void launch_update(hipStream_t st, const Geom& g, const MatView<T>& A, const dou
 }
 
 template <typename T>
+bool persistent_fits(const Geom& g, bool herm, int n_cu) {
+    int per_cu = 0;
+    hipError_t e = hipSuccess;
+    DMRI_DISPATCH_S(g.S, {
+        if (herm)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(&k_krylov_persistent<T, S, true>), kBlock, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(&k_krylov_persistent<T, S, false>), kBlock, 0);
+    });
+    if (e != hipSuccess) return false;
+    return static_cast<int64_t>(per_cu) * n_cu >= static_cast<int64_t>(8) * g.B;
+}
+
+template <typename T>
 void launch_krylov_persistent(hipStream_t st, const Geom& g, const MatView<T>& A,
                               const double4* gq, Coef lhs, bool herm, V2<T>* x, V2<T>* r,
                               V2<T>* p, V2<T>* q, SolverState s, Scratch sc, GridBarrier bar) {
@@ -2126,7 +2146,8 @@ void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
     template void launch_krylov_persistent<T>(hipStream_t, const Geom&, const MatView<T>&,     \
                                               const double4*, Coef, bool, V2<T>*, V2<T>*,      \
                                               V2<T>*, V2<T>*, SolverState, Scratch,            \
-                                              GridBarrier);
+                                              GridBarrier);                                    \
+    template bool persistent_fits<T>(const Geom&, bool, int);
 
 DMRI_INST(double)
 DMRI_INST(float)

@@ -205,6 +205,12 @@ void launch_krylov_persistent(hipStream_t st, const Geom& g, const MatView<T>& A
                               typename Vec2Of<T>::type* p, typename Vec2Of<T>::type* q,
                               SolverState s, Scratch sc, GridBarrier bar);
 
+// True when the 8 * g.B blocks of the persistent solver can all be resident
+// at once on a device with n_cu compute units (occupancy of the kernel that
+// launch_krylov_persistent would pick); the grid barrier needs that.
+template <typename T>
+bool persistent_fits(const Geom& g, bool herm, int n_cu);
+
 // Zero n int32 values (a kernel, so it may be captured in a graph).
 void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n);
 

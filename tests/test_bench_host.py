@@ -89,3 +89,39 @@ def test_binding_fails_loudly_without_library(tmp_path):
     from paper_1908_01719_amd import binding
     with pytest.raises(ImportError, match="not found"):
         binding.load(str(tmp_path / "libdmri.so"))
+
+
+def test_cpu_sample_spans_the_echo_and_the_b_range():
+    import dmri_inputs as di
+    _, seq, sysl = di.cylinder_57_batched()
+    plan = bench.cpu_sample_plan(sysl, seq.n_steps, 6, 16)
+    starts = [s0 for _, s0 in plan]
+    bs = sorted(float(sysl.b[i]) for i, _ in plan)
+    assert starts[0] == 0 and starts[-1] == seq.n_steps - 6
+    assert all(0 <= s <= seq.n_steps - 6 for s in starts)
+    assert len(set(starts)) == 16
+    assert bs[0] < 500 and bs[-1] > 4500
+
+
+def test_oracle_start_step_takes_later_steps():
+    # start_step s with n steps takes steps s+1 .. s+n from the initial
+    # magnetization: s = 0 is the plain run; for free diffusion the state
+    # stays uniform and follows the scalar recurrence from that step on.
+    import numpy as np
+    import dmri_inputs as di
+    from oracle import fem, sequence, timestep
+    prob, seq, sysl = di.free_diffusion_10()
+    asm = fem.assemble(prob)
+    s_plain = timestep.solve_transformed(asm, seq, 1000.0, [1, 0, 0], n_steps=5)
+    s_zero = timestep.solve_transformed(asm, seq, 1000.0, [1, 0, 0], n_steps=5, start_step=0)
+    assert s_plain == s_zero
+    s_late = timestep.solve_transformed(asm, seq, 1000.0, [1, 0, 0], n_steps=3,
+                                        start_step=100)
+    G = float(sequence.b_to_G(1000.0, seq.delta, seq.Delta))
+    F = sequence.pgse_F(np.arange(seq.n_steps + 1) * seq.dt, seq.delta, seq.Delta)
+    c = 1.0
+    a = lambda Fv: prob.D[0] * (G * Fv) ** 2  # noqa: E731
+    for n in range(101, 104):
+        c *= (1 - 0.5 * seq.dt * a(F[n - 1])) / (1 + 0.5 * seq.dt * a(F[n]))
+    vol = 1000.0
+    assert abs(s_late / vol - c) < 1e-12

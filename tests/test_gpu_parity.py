@@ -182,6 +182,41 @@ def test_two_problems_one_run(Sim):
     assert np.abs(sig[[1, 2]] - r2).max() < 1e-9 * abs(r2).max()
 
 
+def test_two_problems_device_entry(Sim):
+    # The device entry point with a per-pair problem-id array: pairs of two
+    # meshes interleaved, inputs and signals in device memory.
+    import torch
+    p1 = di.cylinder_box(n=9, half=6.0, r=4.0, kappa=1e-2)
+    p2 = di.free_box(n=7, half=3.5)
+    b = np.array([1000.0, 2000.0, 1000.0, 3000.0, 0.0])
+    q = np.array([[1.0, 0, 0], [0, 1.0, 0], [0.6, 0.8, 0], [0, 0, 1.0], [1.0, 0, 0]])
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12)
+        i1 = sim.add_problem(p1)
+        i2 = sim.add_problem(p2)
+        ids = np.array([i1, i2, i2, i1, i2], np.int32)
+        dp = torch.tensor(ids, dtype=torch.int32, device="cuda")
+        db = torch.tensor(b, dtype=torch.float64, device="cuda")
+        dq = torch.tensor(q, dtype=torch.float64, device="cuda")
+        ds = torch.zeros((len(b), 2), dtype=torch.float64, device="cuda")
+        st = sim.dmri_run_device(dp, db, dq, ds)
+        torch.cuda.synchronize()
+        dev = ds.cpu().numpy()
+        sig = dev[:, 0] + 1j * dev[:, 1]
+        bad = torch.tensor([i1, 7], dtype=torch.int32, device="cuda")
+        with pytest.raises(Exception, match="DMRI_E_STATE"):
+            sim.dmri_run_device(bad, db[:2], dq[:2], ds[:2])
+    assert st["status"] == "DMRI_OK"
+    r1 = timestep.signals(p1, SHORT, b[[0, 3]], q[[0, 3]], solver="splu")
+    r2 = timestep.signals(p2, SHORT, b[[1, 2, 4]], q[[1, 2, 4]], solver="splu")
+    _say("device entry, two problems: errs %.2e %.2e" % (
+        np.abs(sig[[0, 3]] - r1).max() / abs(r1).max(),
+        np.abs(sig[[1, 2, 4]] - r2).max() / abs(r2).max()))
+    assert np.abs(sig[[0, 3]] - r1).max() < 1e-9 * abs(r1).max()
+    assert np.abs(sig[[1, 2, 4]] - r2).max() < 1e-9 * abs(r2).max()
+
+
 def test_sampled_first_steps(Sim):
     # n_steps limits the run; compare sum w u^n after 3 steps with the oracle.
     prob, b, q = _cyl_case()
