@@ -326,6 +326,32 @@ DMRI_API dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int64_t n_
                             const int32_t* d_problem_id, const double* d_b, const double* d_q,
                             double* d_signal, dmri_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * run as dmri_run_device, with every buffer of the run (solution history,
+ * Krylov vectors, partial sums, counters, per-system scalars, grid barrier)
+ * taken from a fixed 64 MiB device array that the library holds on each
+ * device it runs on until the process ends. The call makes no hipMalloc,
+ * hipFree, pinned-host or other device allocation; state is cleared with
+ * fill kernels. The caller still passes the inputs and the output.
+ * Limits: 1..64 pairs, all on one problem; precision 0 (FP64) with the
+ * persistent Krylov kernel (one launch per step); guess 0 or 1; no sample
+ * recording. The problem's operators must already be on the device for the
+ * current sequence (any earlier dmri_run / dmri_run_device of the problem
+ * uploads them), else DMRI_E_STATE. A run that needs more scratch than the
+ * array holds (n_dof x padded systems x (history + 4) x 16 bytes plus
+ * partials) gives DMRI_E_INVALID with the size in the message; other
+ * violated limits DMRI_E_INVALID or DMRI_E_UNSUPPORTED. Systems are tiled in
+ * input order (option "sort_systems" is not applied). Every call on a device
+ * uses that device's one array and leaves its contents there: calls that
+ * overlap on one device (other threads, other handles, or work still queued
+ * on another stream) race and corrupt each other; serialize them. Same
+ * arguments, statistics and status as dmri_run_device; returns after the
+ * signals are written. */
+DMRI_API dmri_status dmri_run_device_noalloc(dmri_handle h, void* hip_stream, int64_t n_pairs,
+                                    const int32_t* d_problem_id, const double* d_b,
+                                    const double* d_q, double* d_signal, dmri_stats* stats);
+
 /* Apply one step operator of problem `problem_id` to host vectors
  * (kernel check): y = (Base + c M_D + i (d . V)) x with Base = M/dt +
  * theta R when which = 0 (left side) or M/dt - (1-theta) R when which = 1

@@ -29,7 +29,7 @@ STATUS_NAMES = {
 EXPORTED = [
     "dmri_create", "dmri_destroy", "dmri_last_error", "dmri_add_problem", "dmri_problem_info",
     "dmri_export_operator", "dmri_set_sequence_pgse", "dmri_set_option", "dmri_get_option",
-    "dmri_run", "dmri_run_device", "dmri_apply_operator",
+    "dmri_run", "dmri_run_device", "dmri_run_device_noalloc", "dmri_apply_operator",
     "dmri_guess_set_params", "dmri_guess_get_params", "dmri_load_guess_model",
     "dmri_save_guess_model", "dmri_guess_record", "dmri_guess_record_count", "dmri_guess_eval",
     "dmri_guess_train",
@@ -100,6 +100,7 @@ def load(path: Optional[str] = None):
     lib.dmri_guess_train.argtypes = [vp, i64, vp, vp, i32, dbl, P(dbl), P(dbl)]
     lib.dmri_run.argtypes = [vp, i64, vp, vp, vp, vp, P(Stats)]
     lib.dmri_run_device.argtypes = [vp, vp, i64, vp, vp, vp, vp, P(Stats)]
+    lib.dmri_run_device_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, P(Stats)]
     lib.dmri_apply_operator.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
     for name in EXPORTED:
         f = getattr(lib, name)
@@ -321,6 +322,32 @@ class Simulator:
             C.c_void_p(q_dev.data_ptr()), C.c_void_p(sig_dev.data_ptr()), C.byref(st)),
             allow_nc=True)
         return _stats_dict(st, None, None, None, status)
+
+    def dmri_run_device_noalloc(self, pid_dev, b_dev, q_dev, sig_dev, stream_ptr=None):
+        """As dmri_run_device, through the entry point that allocates no device
+        memory (pid_dev must be an int32 CUDA tensor [n], n <= 64)."""
+        import torch
+        n = int(b_dev.shape[0])
+        if pid_dev.dtype != torch.int32 or tuple(pid_dev.shape) != (n,):
+            raise ValueError("problem ids must be an int32 tensor of shape [n]")
+        for t in (pid_dev, b_dev, q_dev, sig_dev):
+            if not t.is_contiguous():
+                raise ValueError("tensors must be contiguous")
+        if stream_ptr is None:
+            _sync(b_dev)
+        iters = np.zeros(n, np.int32)
+        conv = np.zeros(n, np.uint8)
+        rres = np.zeros(n, np.float64)
+        st = Stats()
+        st.iters_total = iters.ctypes.data_as(C.POINTER(C.c_int32))
+        st.converged = conv.ctypes.data_as(C.POINTER(C.c_uint8))
+        st.final_rel_res = rres.ctypes.data_as(C.POINTER(C.c_double))
+        status = self._check(self.lib.dmri_run_device_noalloc(
+            self.h, None if stream_ptr is None else C.c_void_p(stream_ptr), n,
+            C.c_void_p(pid_dev.data_ptr()), C.c_void_p(b_dev.data_ptr()),
+            C.c_void_p(q_dev.data_ptr()), C.c_void_p(sig_dev.data_ptr()), C.byref(st)),
+            allow_nc=True)
+        return _stats_dict(st, iters, conv, rres, status)
 
     def dmri_apply_operator(self, pid: int, which: int, c, d, x):
         c = _c(c, np.float64).reshape(-1)

@@ -318,6 +318,9 @@ struct dmri_ctx {
     // Execution lanes: lane 0 serves the calling thread; runs over several
     // problems may use more lanes, one host thread each.
     std::vector<std::unique_ptr<dmri::Lane>> lanes;
+    // Device address of this device's copy of the file-scope scratch array
+    // (the buffers of dmri_run_device_noalloc), looked up at creation.
+    void* scratch_dev = nullptr;
 };
 
 namespace dmri {
@@ -1365,6 +1368,40 @@ void grad_pass(dmri_ctx* h, int64_t n, const float* X, const float* T) {
 }  // namespace
 }  // namespace dmri
 
+// Buffers of dmri_run_device_noalloc: every vector, partial sum, counter and
+// per-system scalar of that entry point lives in this array, of which each
+// device the library runs on holds one copy until the process ends. Host
+// code never uses the name itself as an address (it is a host-side stand-in):
+// it uses the device address looked up once per device with
+// hipGetSymbolAddress (scratch_address below).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;  // 64 MiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace dmri {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current. Looked up
+// on the first call for a device and kept.
+void* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices)
+        throw Error(DMRI_E_UNSUPPORTED, "device ordinal above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw Error(DMRI_E_DEVICE, "hipGetSymbolAddress gave a null address");
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+}  // namespace dmri
+
 using namespace dmri;
 
 extern "C" {
@@ -1381,6 +1418,7 @@ dmri_status dmri_create(int device_ordinal, dmri_handle* out) {
             HIPCHK(hipSetDevice(device_ordinal));
             h->device = device_ordinal;
             h->host_only = false;
+            h->scratch_dev = scratch_address(device_ordinal);
             h->lanes.push_back(std::make_unique<Lane>());
             h->lanes.back()->create();
         } else if (device_ordinal != -1) {
@@ -1882,6 +1920,194 @@ struct StreamOverride {
     ~StreamOverride() { lane(h).stream = saved; }
 };
 
+// Bump allocator over a fixed device region (256-byte aligned pieces). With
+// base == nullptr it only measures.
+struct Arena {
+    char* base;
+    size_t cap;
+    size_t used = 0;
+    template <typename T>
+    T* take(size_t count) {
+        const size_t off = (used + 255) & ~static_cast<size_t>(255);
+        used = off + std::max<size_t>(1, count) * sizeof(T);
+        if (base && used > cap) throw Error(DMRI_E_INVALID, "scratch region overflow");
+        return base ? reinterpret_cast<T*>(base + off) : nullptr;
+    }
+};
+
+// Device buffers of one no-allocation run.
+struct NoAllocBufs {
+    double2* vec[kMaxHist + 4];
+    double4* gq;
+    double* partial;
+    int32_t* ctr;
+    int32_t* bad;
+    uint32_t* barrier;
+    double2 *rho, *alpha, *beta;
+    double *bb, *rr;
+    int32_t *active, *iters, *iters_total, *flags, *n_active;
+    // zero-filled at the start of a run: [zero_from, zero_to) in int32 words
+    int32_t* zero_from;
+    int32_t* zero_to;
+    void carve(Arena& a, int n_vec, size_t nv, size_t ld, size_t n_tiles, size_t part_n,
+               size_t items_max) {
+        for (int i = 0; i < n_vec; ++i) vec[i] = a.take<double2>(nv);
+        gq = a.take<double4>(ld);
+        partial = a.take<double>(part_n);
+        // The state below is contiguous so one fill clears it.
+        rho = a.take<double2>(ld);
+        alpha = a.take<double2>(ld);
+        beta = a.take<double2>(ld);
+        bb = a.take<double>(ld);
+        rr = a.take<double>(ld);
+        active = a.take<int32_t>(ld);
+        iters = a.take<int32_t>(ld);
+        iters_total = a.take<int32_t>(ld);
+        flags = a.take<int32_t>(ld);
+        n_active = a.take<int32_t>(n_tiles);
+        ctr = a.take<int32_t>(2 * items_max);
+        bad = a.take<int32_t>(1);
+        barrier = a.take<uint32_t>(32 * 11);
+        zero_from = reinterpret_cast<int32_t*>(rho);
+        zero_to = reinterpret_cast<int32_t*>(barrier + 32 * 11);
+    }
+};
+
+// All-FP64 run of n_sys <= 64 systems of one problem with the persistent
+// Krylov kernel, every buffer taken from this device's scratch array. No
+// device or pinned memory is allocated: the problem's operators must already
+// be on the device (uploaded by an earlier run with the same sequence), and
+// state is cleared with fill kernels, not memset nodes.
+void run_noalloc(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, const double* d_q,
+                 double2* d_sig, dmri_stats* stats) {
+    const Options& o = h->opt;
+    hipStream_t st = lane(h).stream;
+    if (o.precision != 0)
+        throw Error(DMRI_E_UNSUPPORTED, "the no-allocation entry point runs precision 0 (FP64)");
+    if (o.guess == 2)
+        throw Error(DMRI_E_UNSUPPORTED, "the no-allocation entry point has no learned guess");
+    if (h->model.rec_cap > 0)
+        throw Error(DMRI_E_UNSUPPORTED, "sample recording allocates; not with this entry point");
+    if (!P.pattern_up || !P.A64.ready || P.dt_up != h->dt || P.theta_up != h->theta)
+        throw Error(DMRI_E_STATE,
+                    "the problem's operators are not on the device for this sequence: run it "
+                    "once through dmri_run or dmri_run_device first");
+    const bool herm = (P.op.form == FORM_TRANSFORMED) ? (o.krylov != 2) : false;
+    if (P.op.form == FORM_UFORM && o.krylov == 1)
+        throw Error(DMRI_E_INVALID, "CG needs the Hermitian (periodic-box) operator; use COCG");
+    const int S = o.sys_tile ? o.sys_tile : auto_tile(n_sys);
+    const int32_t n_rows = static_cast<int32_t>(P.op.n_dof);
+    Geom g = make_geom(n_rows, static_cast<int32_t>(n_sys), S, o.blocks_per_xcd, 0, o.grab,
+                       o.xcd_split != 0);
+    g.nt = o.nt;
+    g.lds = 0;
+    if (g.ld > 64)
+        throw Error(DMRI_E_INVALID, "the no-allocation entry point takes at most 64 systems");
+    int n_cu = 0;
+    HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
+    Geom gp = make_geom(n_rows, static_cast<int32_t>(n_sys), S, std::max(1, n_cu / 8), 0, 1);
+    gp.nt = g.nt;
+    gp.lds = 0;
+    if (!persistent_fits<double>(gp, herm, n_cu))
+        throw Error(DMRI_E_UNSUPPORTED, "the persistent Krylov grid does not fit on this device");
+    const size_t ld = static_cast<size_t>(g.ld), nv = static_cast<size_t>(n_rows) * ld;
+    const int32_t items_max = std::max(g.n_items, 8 * g.n_tiles);
+    const size_t part_n =
+        std::max(static_cast<size_t>(items_max) * g.B * S * 4,
+                 2 * static_cast<size_t>(gp.n_items) * gp.B * S * 4);
+    History<double2> hs;
+    hs.nh = history_len(h);
+    const int n_vec = hs.nh + 4;
+    Arena probe{nullptr, 0};
+    NoAllocBufs B{};
+    B.carve(probe, n_vec, nv, ld, static_cast<size_t>(g.n_tiles), part_n,
+            static_cast<size_t>(items_max));
+    if (probe.used > kNoAllocScratchBytes)
+        throw Error(DMRI_E_INVALID,
+                    "the run needs " + std::to_string(probe.used) + " bytes of scratch; the "
+                    "no-allocation entry point has " + std::to_string(kNoAllocScratchBytes) +
+                    " (fewer systems or a smaller mesh)");
+    Arena arena{static_cast<char*>(h->scratch_dev), kNoAllocScratchBytes};
+    B.carve(arena, n_vec, nv, ld, static_cast<size_t>(g.n_tiles), part_n,
+            static_cast<size_t>(items_max));
+    // The array keeps the previous call's contents: clear the state, the
+    // queue counters, the invalid-input flag and the grid barrier.
+    launch_zero_i32(st, B.zero_from, B.zero_to - B.zero_from);
+    const double intF2 = h->delta * h->delta * (h->Delta - h->delta / 3.0);
+    launch_sys_params(st, static_cast<int32_t>(n_sys), static_cast<int32_t>(ld), d_b, d_q, intF2,
+                      B.gq, B.bad);
+    SolverState s{};
+    s.rho = B.rho;
+    s.alpha = B.alpha;
+    s.beta = B.beta;
+    s.bb = B.bb;
+    s.rr = B.rr;
+    s.active = B.active;
+    s.iters = B.iters;
+    s.iters_total = B.iters_total;
+    s.flags = B.flags;
+    s.n_active = B.n_active;
+    s.n_sys = static_cast<int32_t>(n_sys);
+    s.max_iter = o.max_iter;
+    s.rtol2 = o.rtol * o.rtol;
+    s.floor_bb = nullptr;
+    s.floor_scale = 0.0;
+    Scratch sc{B.partial, B.ctr, B.ctr + items_max};
+    GridBarrier bar{B.barrier, B.barrier + 32 * 9, reinterpret_cast<int32_t*>(B.barrier + 32 * 10)};
+    for (int i = 0; i <= hs.nh; ++i) hs.ring.push_back(B.vec[i]);
+    double2* r = B.vec[hs.nh + 1];
+    double2* p = B.vec[hs.nh + 2];
+    double2* q = B.vec[hs.nh + 3];
+    const MatView<double> Av = view<double>(P, P.A64);
+    launch_set_initial<double>(st, g, P.u0.p, s.n_sys, hs.u(0));
+    std::vector<double> F, f;
+    step_tables(h, F, f);
+    const bool tr = P.op.form == FORM_TRANSFORMED;
+    const int N = o.n_steps > 0 ? std::min(o.n_steps, h->n_steps) : h->n_steps;
+    KernelTimer timer(h, st, 0);
+    const MlpDofs no_dofs{nullptr, nullptr};
+    const double t0 = now_s();
+    for (int n = 1; n <= N; ++n) {
+        const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
+        const int gm = prepare_guess<double>(h, g, no_dofs, tr, F, f, n, n_sys, hs, timer);
+        launch_init<double>(st, g, Av, B.gq, lhs, rhs, herm, gm, hs.u(0), hs.u(1), hs.x(), r, p,
+                            nullptr, nullptr, nullptr, s, sc);
+        launch_krylov_persistent<double>(st, gp, Av, B.gq, lhs, herm, hs.x(), r, p, q, s, sc, bar);
+        hs.advance();
+    }
+    launch_signal<double>(st, g, P.w.p, hs.u(0), d_sig, s.n_sys, sc);
+    // Results for the statistics and the status (n_sys <= 64: stack arrays).
+    int32_t bad = 0, bar_err = 0;
+    int32_t fl[64], it[64];
+    double rr[64], bb[64];
+    HIPCHK(hipMemcpyAsync(&bad, B.bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&bar_err, bar.err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(fl, B.flags, sizeof(int32_t) * n_sys, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(it, B.iters_total, sizeof(int32_t) * n_sys, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(rr, B.rr, sizeof(double) * n_sys, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(bb, B.bb, sizeof(double) * n_sys, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad) throw Error(DMRI_E_INVALID, "b must be finite and >= 0, q finite and nonzero when b > 0");
+    if (bar_err) throw Error(DMRI_E_DEVICE, "persistent solver: a grid barrier wait timed out");
+    bool nc = false;
+    int64_t tot = 0;
+    for (int64_t i = 0; i < n_sys; ++i) {
+        nc |= fl[i] != 0;
+        tot += it[i];
+        if (stats && stats->iters_total) stats->iters_total[i] = it[i];
+        if (stats && stats->converged) stats->converged[i] = fl[i] == 0 ? 1 : 0;
+        if (stats && stats->final_rel_res)
+            stats->final_rel_res[i] = bb[i] > 0 ? std::sqrt(rr[i] / bb[i]) : 0.0;
+    }
+    if (stats) {
+        stats->t_solve_s = now_s() - t0;
+        stats->total_iterations = tot;
+        stats->spmv_rows = tot * n_rows;
+        stats->n_steps = N;
+    }
+    if (nc) throw Error(DMRI_NOT_CONVERGED, "some systems hit max_iter");
+}
+
 }  // namespace
 }  // namespace dmri
 
@@ -1987,6 +2213,45 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int64_t n_pairs,
         if (h->opt.sort_systems) remember_costs(h, problem_id, hb.data(), hq.data(), idx, R.iters);
         for (int32_t fl : R.flags)
             if (fl) return DMRI_NOT_CONVERGED;
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_run_device_noalloc(dmri_handle h, void* hip_stream, int64_t n_pairs,
+                                    const int32_t* d_problem_id, const double* d_b,
+                                    const double* d_q, double* d_signal, dmri_stats* stats) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        need_sequence(h);
+        if (n_pairs < 0 || n_pairs > 64)
+            throw Error(DMRI_E_INVALID, "the no-allocation entry point takes 0..64 pairs");
+        reset_stats(stats, n_pairs);
+        if (n_pairs == 0) return DMRI_OK;
+        if (!d_problem_id || !d_b || !d_q || !d_signal)
+            throw Error(DMRI_E_INVALID, "NULL argument");
+        StreamOverride so(h, hip_stream);
+        hipStream_t st = lane(h).stream;
+        // At most 64 pairs: the pair list is checked on the host in stack arrays.
+        int32_t ids[64];
+        double hb[64], hq[3 * 64];
+        HIPCHK(hipMemcpyAsync(ids, d_problem_id, sizeof(int32_t) * n_pairs, hipMemcpyDeviceToHost,
+                              st));
+        HIPCHK(hipMemcpyAsync(hb, d_b, sizeof(double) * n_pairs, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hq, d_q, sizeof(double) * 3 * n_pairs, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        check_pairs(h, n_pairs, ids, hb, hq);
+        for (int64_t i = 1; i < n_pairs; ++i)
+            if (ids[i] != ids[0])
+                throw Error(DMRI_E_INVALID,
+                            "the no-allocation entry point runs the pairs of one problem");
+        ProblemRec& P = get_problem(h, ids[0]);
+        try {
+            run_noalloc(h, P, n_pairs, d_b, d_q, reinterpret_cast<double2*>(d_signal), stats);
+        } catch (const Error& e) {
+            if (e.code == DMRI_NOT_CONVERGED) return DMRI_NOT_CONVERGED;
+            throw;
+        }
         return DMRI_OK;
     });
 }

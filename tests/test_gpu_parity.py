@@ -443,6 +443,37 @@ def test_graph_replay_matches_eager(Sim):
     assert rel_err(eager_u, ref, ref[0]).max() < 1e-9
 
 
+def test_graph_recaptured_after_reallocation(Sim):
+    # A captured graph bakes device addresses in. Capture with the auto tile
+    # (one 64-system tile), run eagerly with 8-system tiles (the per-tile
+    # buffers grow, i.e. are reallocated), then ask for the graph again: the
+    # library must capture anew, and every result equals its eager run bit
+    # for bit.
+    prob, b, q = _cyl_case()
+    rng = np.random.default_rng(5)
+    n = 64
+    bb = np.concatenate([b, rng.uniform(0, 3000, n - len(b))])
+    qq = np.concatenate([q, rng.normal(size=(n - len(q), 3))])
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.set_options(rtol=1e-12, persistent=1, graph=0, sys_tile=0)
+        eager64, _ = sim.dmri_run([pid] * n, bb, qq)
+        sim.set_options(sys_tile=8)
+        eager8, _ = sim.dmri_run([pid] * n, bb, qq)
+        sim.set_options(sys_tile=0, graph=1)
+        g1, _ = sim.dmri_run([pid] * n, bb, qq)
+        sim.set_options(sys_tile=8, graph=0)
+        e8, _ = sim.dmri_run([pid] * n, bb, qq)
+        sim.set_options(sys_tile=0, graph=1)
+        g2, _ = sim.dmri_run([pid] * n, bb, qq)
+        g3, _ = sim.dmri_run([pid] * n, bb, qq)
+    assert np.array_equal(g1, eager64)
+    assert np.array_equal(e8, eager8)
+    assert np.array_equal(g2, eager64)
+    assert np.array_equal(g3, eager64)
+
+
 def test_autotune_matches_oracle(Sim):
     prob, b, q = _cyl_case()
     ref = _cyl_ref()
