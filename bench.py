@@ -49,20 +49,48 @@ KERNEL_NAMES = {"spmv": "k_spmv_dot", "update": "k_update", "pupdate": "k_pupdat
 
 
 def workload(name):
+    """(sequence, [(problem, systems), ...], description, golden fixtures)."""
     import dmri_inputs as di
     if name == "cylinder_57_batched":
         prob, seq, sysl = di.cylinder_57_batched()
         desc = ("cylinder r=5um in 12um periodic box, 57^3 Kuhn cubes, 2 compartments, "
                 "kappa=1e-5, 64 dirs x 16 b in [0,5000]")
-    elif name == "cylinder_36":
+        return seq, [(prob, sysl)], desc, {0: "cylinder_57_full"}
+    if name == "cylinder_36":
         prob, seq, sysl = di.cylinder_36()
         desc = "cylinder r=5um in 12um periodic box, 36^3 Kuhn cubes, 8 b in [0,3000] along x"
-    elif name == "free_diffusion_10":
+        return seq, [(prob, sysl)], desc, {0: "cylinder_36"}
+    if name == "free_diffusion_10":
         prob, seq, sysl = di.free_diffusion_10()
         desc = "free diffusion [-5,5]^3, 10^3 Kuhn cubes, b=1000 along x"
-    else:
-        raise SystemExit("unknown workload %s" % name)
-    return prob, seq, sysl, desc
+        return seq, [(prob, sysl)], desc, {}
+    if name == "seeded_cells_batch":
+        items = []
+        for seed in range(8):
+            prob, seq, sysl = di.seeded_cells(seed)
+            items.append((prob, sysl))
+        desc = ("8 seeded geometries (seeds 0-7) of 5-30 cylinders/spheres in a 30um periodic "
+                "box, 39^3-93^3 Kuhn cubes, kappa log-uniform 1e-6..1e-4, 32 (b, dir) pairs each")
+        return seq, items, desc, {2: "seeded_cells_seed2", 3: "seeded_cells_seed3"}
+    raise SystemExit("unknown workload %s" % name)
+
+
+def golden_error(fixtures, sigs):
+    """Largest relative error of the run's signals against the oracle's stored
+    signals (tests/golden/, written from the CPU oracle only), floor 1e-8 of the
+    b = 0 signal (the total initial magnetization)."""
+    import json
+    worst, n = 0.0, 0
+    for item, name in fixtures.items():
+        with open(os.path.join(ROOT, "tests", "golden", name + ".json")) as f:
+            d = json.load(f)
+        ref = np.array(d["signal_re"]) + 1j * np.array(d["signal_im"])
+        got = sigs[item][np.array(d["index"])]
+        floor = 1e-8 * np.abs(ref).max()
+        worst = max(worst, float((np.abs(got - ref) / np.maximum(np.abs(ref), floor)).max()))
+        n += len(ref)
+    return {"max_rel_err": worst, "n_signals": n, "fixtures": sorted(fixtures.values())} if n \
+        else None
 
 
 def kernel_bytes(kind, n_dof, nnz, total_iters, tile, prec_bytes, n_steps, n_sys):
@@ -211,13 +239,18 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cylinder_57_batched",
-                    choices=["free_diffusion_10", "cylinder_36", "cylinder_57_batched"])
+                    choices=["free_diffusion_10", "cylinder_36", "cylinder_57_batched",
+                             "seeded_cells_batch"])
     ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--guess", type=int, default=1)
     ap.add_argument("--time-kernel", default="spmv", choices=sorted(KERNELS))
     ap.add_argument("--sys-tile", type=int, default=0)
     ap.add_argument("--blocks-per-xcd", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=None,
+                    help="library autotuner (default: on for seeded_cells_batch)")
+    ap.add_argument("--concurrency", type=int, default=1,
+                    help="problems of a multi-mesh workload run at once (lanes)")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle processes for the CPU baseline (0 = min(16, host CPUs))")
@@ -238,35 +271,45 @@ def main():
     import torch
     from paper_1908_01719_amd import Simulator
 
-    prob, seq, sysl, desc = workload(args.workload)
+    seq, items, desc, fixtures = workload(args.workload)
+    n_pairs = sum(len(sl) for _, sl in items)
     prec = {"fp64": 0, "mixed": 1, "fp32": 2}[args.precision]
     rtol = args.rtol if args.rtol is not None else 1e-6
-    print("bench: workload %s (%s), %d systems, precision %s" % (
-        args.workload, desc, len(sysl), args.precision), file=sys.stderr, flush=True)
+    autotune = args.autotune if args.autotune is not None else int(len(items) > 1)
+    print("bench: workload %s (%s), %d systems on %d meshes, precision %s" % (
+        args.workload, desc, n_pairs, len(items), args.precision), file=sys.stderr, flush=True)
 
     # The oracle's worker processes are forked before this process touches the GPU.
+    # A multi-mesh workload is sampled on its smallest mesh.
     cpu = None
     if not args.no_cpu_baseline:
         n_proc = args.cpu_procs or min(16, os.cpu_count() or 1)
+        small = min(range(len(items)), key=lambda i: items[i][0].n_nodes)
         print("bench: timing the CPU oracle on a bounded sample (%d processes)" % n_proc,
               file=sys.stderr, flush=True)
-        cpu = cpu_baseline(prob, seq, sysl, args.cpu_steps, n_proc)
+        cpu = cpu_baseline(items[small][0], seq, items[small][1], args.cpu_steps, n_proc)
+        if len(items) > 1:
+            cpu["sample"] = "mesh %d of %d (the smallest): %s" % (small, len(items), cpu["sample"])
         print("bench: CPU oracle %.3g DOF-steps/s" % cpu["value"], file=sys.stderr, flush=True)
 
     sim = Simulator(0)
     sim.set_sequence(seq)
     t0 = time.perf_counter()
-    pid = sim.add_problem(prob)
+    pid_list = [sim.add_problem(prob) for prob, _ in items]
     t_asm = time.perf_counter() - t0
-    n_dof, nnz = sim.dmri_problem_info(pid)
-    opts = dict(precision=prec, rtol=rtol, guess=args.guess,
+    info = [sim.dmri_problem_info(p) for p in pid_list]
+    opts = dict(precision=prec, rtol=rtol, guess=args.guess, autotune=autotune,
+                concurrency=args.concurrency,
                 time_kernel=KERNELS[args.time_kernel], progress=args.progress)
     if args.sys_tile:
         opts["sys_tile"] = args.sys_tile
     if args.blocks_per_xcd:
         opts["blocks_per_xcd"] = args.blocks_per_xcd
     sim.set_options(**opts)
-    pids = np.full(len(sysl), pid, np.int32)
+    pids = np.concatenate([np.full(len(sl), p, np.int32) for p, (_, sl) in zip(pid_list, items)])
+    bs = np.concatenate([sl.b for _, sl in items])
+    qs = np.concatenate([sl.q for _, sl in items])
+    owner = np.concatenate([np.full(len(sl), i) for i, (_, sl) in enumerate(items)])
 
     if args.calibrate_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
@@ -278,41 +321,53 @@ def main():
         del a, bcopy
 
     for w in range(args.warmup):
-        sig, st = sim.dmri_run(pids, sysl.b, sysl.q)
+        sig, st = sim.dmri_run(pids, bs, qs)
         print("bench: warmup %d done (%.2fs solve)" % (w, st["t_solve_s"]), file=sys.stderr,
               flush=True)
     torch.cuda.synchronize()
     t_begin = time.perf_counter()
-    tot_iters = 0
+    iters_item = np.zeros(len(items))
     t_kernel = 0.0
     n_launch = 0
+    tot_iters = 0
     for k in range(args.steps):
-        sig, st = sim.dmri_run(pids, sysl.b, sysl.q)
+        sig, st = sim.dmri_run(pids, bs, qs)
         tot_iters += st["total_iterations"]
         t_kernel += st["t_kernel_s"]
         n_launch += st["n_kernel_launches"]
+        iters_item += np.bincount(owner, weights=st["iters_total"], minlength=len(items))
         print("bench: step %d done (%.2fs solve, %d iterations)" % (
             k, st["t_solve_s"], st["total_iterations"]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_begin
     ms_per_step = 1e3 * elapsed / args.steps
     n_steps = st["n_steps"]
-    value = n_dof * len(sysl) * n_steps * args.steps / elapsed
+    dof_sys = sum(info[i][0] * len(sl) for i, (_, sl) in enumerate(items))
+    value = dof_sys * n_steps * args.steps / elapsed
 
-    tile = args.sys_tile or (64 if len(sysl) >= 64 else 32 if len(sysl) >= 32 else
-                             16 if len(sysl) >= 16 else 8)
-    # Mixed precision on more than 64 systems runs its FP32 Krylov kernels on
-    # 128-system paired-lane tiles (the matrix is read once per such tile).
-    paired = (prec == 1 and tile == 64 and len(sysl) > 64
-              and sim.dmri_get_option("pair_lanes") == 1 and args.time_kernel != "init")
-    ktile = 128 if paired else tile
+    # Algorithmic bytes of the timed kernel, summed over the meshes.
+    pbytes = 8 if prec == 0 else 4
+    kb = 0.0
+    tiles = []
+    paired_any = False
+    for i, (_, sl) in enumerate(items):
+        ns = len(sl)
+        tile = args.sys_tile or (64 if ns >= 64 else 32 if ns >= 32 else 16 if ns >= 16 else 8)
+        if autotune and not args.sys_tile and sim.dmri_get_option("tuned_sys_tile") > 0:
+            tile = min(tile, int(sim.dmri_get_option("tuned_sys_tile")))
+        # Mixed precision on more than 64 systems runs its FP32 Krylov kernels on
+        # 128-system paired-lane tiles (the matrix is read once per such tile).
+        paired = (prec == 1 and tile == 64 and ns > 64
+                  and sim.dmri_get_option("pair_lanes") == 1 and args.time_kernel != "init")
+        paired_any |= paired
+        ktile = 128 if paired else tile
+        tiles.append(ktile)
+        kb += kernel_bytes(args.time_kernel, info[i][0], info[i][1], iters_item[i], ktile, pbytes,
+                           n_steps * args.steps, ns)
     kname = KERNEL_NAMES[args.time_kernel]
-    if paired:
+    if paired_any:
         kname = kname.replace("k_spmv_dot", "k_spmv_pair").replace("k_update", "k_update_pair") \
             .replace("k_pupdate", "k_pupdate_pair")
-    pbytes = 8 if prec == 0 else 4
-    kb = kernel_bytes(args.time_kernel, n_dof, nnz, tot_iters, ktile, pbytes,
-                      n_steps * args.steps, len(sysl))
     achieved = kb / t_kernel / 1e9 if t_kernel > 0 else None
     roofline = {
         "kernel": kname,
@@ -323,27 +378,35 @@ def main():
         "bytes_per_launch": kb / max(1, n_launch),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
     }
+    sigs = [sig[owner == i] for i in range(len(items))]
+    config = {"workload": args.workload, "description": desc,
+              "n_dof": [int(x[0]) for x in info] if len(items) > 1 else int(info[0][0]),
+              "nnz": [int(x[1]) for x in info] if len(items) > 1 else int(info[0][1]),
+              "n_systems": n_pairs, "time_steps": n_steps, "dt_us": seq.dt,
+              "rtol": rtol, "guess": args.guess,
+              "extrap_order": int(sim.dmri_get_option("extrap_order")),
+              "sys_tile": tiles if len(items) > 1 else tiles[0], "autotune": autotune,
+              "concurrency": args.concurrency,
+              "parallelism": "single GPU, systems batched per mesh"}
     out = {
         "metric": "DOF-steps/s", "value": value, "unit": "DOF-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {0: "f64", 1: "f32+f64", 2: "f32"}[prec], "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "n_dof": n_dof, "nnz": nnz,
-                   "n_systems": len(sysl), "time_steps": n_steps, "dt_us": seq.dt,
-                   "rtol": rtol, "guess": args.guess,
-                   "extrap_order": int(sim.dmri_get_option("extrap_order")), "sys_tile": tile,
-                   "parallelism": "single GPU, systems batched"},
-        "time_to_signal_s_per_pair": elapsed / args.steps / len(sysl),
-        "krylov_iterations_per_system_step": tot_iters / (len(sysl) * n_steps * args.steps),
+        "config": config,
+        "time_to_signal_s_per_pair": elapsed / args.steps / n_pairs,
+        "krylov_iterations_per_system_step": tot_iters / (n_pairs * n_steps * args.steps),
+        "accuracy_vs_oracle": golden_error(fixtures, sigs) if n_steps == seq.n_steps else None,
         "host_assembly_s": t_asm,
         "roofline": roofline,
         "plain_fp64": None,
         "cpu_baseline": None,
     }
-    if args.plain_sample > 0:
+    if args.plain_sample > 0 and len(items) == 1:
         print("bench: timing the plain FP64 solve on %d systems" % args.plain_sample,
               file=sys.stderr, flush=True)
-        pf = plain_fp64(sim, pid, sysl, rtol, args.plain_sample, sig)
+        sim.set_options(autotune=0)
+        pf = plain_fp64(sim, pid_list[0], items[0][1], rtol, args.plain_sample, sig)
         pf["speedup"] = pf["time_to_signal_s_per_pair"] / out["time_to_signal_s_per_pair"]
         out["plain_fp64"] = pf
     sim.close()

@@ -177,9 +177,10 @@ DMRI_API dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, doub
  *  "graph"      1 = when the Krylov solves run in the persistent kernel
  *               (no host decisions inside the time loop), capture the whole
  *               time loop in a HIP graph and replay it; the graph is kept in
- *               the handle and replayed while the batch, buffers and options
- *               are unchanged (default 0; not with time_kernel or sample
- *               recording)
+ *               the handle (one per kind of batch, up to 8 per lane) and
+ *               replayed while the batch, buffers and options are unchanged;
+ *               any device reallocation since the capture forces a new one
+ *               (default 0; not with time_kernel or sample recording)
  *  "n_steps"    0 = full echo (default); n > 0 stops after n steps and
  *               returns sum_i w_i u_i^n (a sampling aid, not a signal unless
  *               F(t^n) = 0)
@@ -233,9 +234,10 @@ DMRI_API dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, doub
  *               instructions per system) (default); 0 = 64-system tiles
  *  "concurrency" k > 1: a dmri_run over several problems runs up to k of
  *               them at once, each on its own stream and workspace driven by
- *               its own host thread (meshes of uneven size share the GPU);
- *               1 = one after another (default). Runs with autotune, graph
- *               or sample recording use one lane
+ *               its own host thread with its own copy of the options (meshes
+ *               of uneven size share the GPU; the autotuner tunes one batch
+ *               at a time); 1 = one after another (default). Runs with
+ *               sample recording use one lane
  * Unknown keys or out-of-range values: DMRI_E_INVALID. */
 DMRI_API dmri_status dmri_set_option(dmri_handle h, const char* key, double value);
 DMRI_API dmri_status dmri_get_option(dmri_handle h, const char* key, double* value);

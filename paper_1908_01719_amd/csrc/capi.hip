@@ -243,6 +243,7 @@ struct GraphCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void* final_u = nullptr;  // u^N after the loop
+    uint64_t last_use = 0;
     void reset() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -261,7 +262,26 @@ struct Lane {
     Workspace ws;
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> tpool;  // timing events, reused across runs
-    GraphCache graph;
+    // Captured time loops (one per kind of batch, e.g. per mesh of a
+    // multi-mesh run); the least recently used is replaced.
+    static constexpr int kGraphs = 8;
+    GraphCache graphs[kGraphs];
+    uint64_t graph_clock = 0;
+    GraphCache& graph_for(const std::vector<uint64_t>& key, bool& hit) {
+        GraphCache* victim = &graphs[0];
+        for (GraphCache& gc : graphs) {
+            if (gc.exec && gc.key == key) {
+                hit = true;
+                gc.last_use = ++graph_clock;
+                return gc;
+            }
+            if (gc.last_use < victim->last_use) victim = &gc;
+        }
+        hit = false;
+        victim->reset();
+        victim->last_use = ++graph_clock;
+        return *victim;
+    }
     void create() {
         HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -269,7 +289,7 @@ struct Lane {
     }
     ~Lane() {
         if (stream) (void)hipStreamSynchronize(stream);
-        graph.reset();
+        for (GraphCache& gc : graphs) gc.reset();
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
         for (auto& e : tpool) (void)hipEventDestroy(e);
@@ -311,6 +331,7 @@ struct dmri_ctx {
     dmri::GuessModel model;
     std::map<std::string, dmri::TuneChoice> tuned;  // autotuner cache
     dmri::TuneChoice last_tune;
+    std::mutex tuned_mu;  // the cache and last_tune (lanes tune one at a time)
     // Krylov iterations each (problem, b, q) system needed in its last run:
     // the order in which later batches tile their systems.
     std::map<std::string, int64_t> sys_cost;
@@ -330,6 +351,13 @@ namespace {
 thread_local Lane* tl_lane = nullptr;
 
 Lane& lane(dmri_ctx* h) { return tl_lane ? *tl_lane : *h->lanes[0]; }
+
+// Options of the calling thread's run: the handle's, or a private copy in the
+// lane threads of a multi-problem run, so concurrent lanes (and the
+// autotuner's trial settings inside one of them) never share one.
+thread_local Options* tl_opt = nullptr;
+Options& opts(dmri_ctx* h) { return tl_opt ? *tl_opt : h->opt; }
+const Options& opts(const dmri_ctx* h) { return tl_opt ? *tl_opt : h->opt; }
 
 std::string sys_key(int32_t pid, double b, const double* q) {
     std::string k(reinterpret_cast<const char*>(&pid), sizeof pid);
@@ -541,8 +569,8 @@ struct History {
 // History length needed by the guess options: polynomial extrapolation of
 // order p uses p + 1 past solutions; the learned guess uses two.
 int history_len(const dmri_ctx* h) {
-    if (h->opt.guess != 1) return 2;
-    return std::min(kMaxHist, std::max(2, h->opt.extrap_order + 1 + (h->opt.extrap_damp ? 1 : 0)));
+    if (opts(h).guess != 1) return 2;
+    return std::min(kMaxHist, std::max(2, opts(h).extrap_order + 1 + (opts(h).extrap_damp ? 1 : 0)));
 }
 
 // Weights of the order-p polynomial through u^{n-1}, ..., u^{n-1-p} on equal
@@ -598,11 +626,11 @@ template <typename T, typename Timer>
 int prepare_guess(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
                   const std::vector<double>& F, const std::vector<double>& f, int n,
                   int64_t n_sys, const History<typename Vec2Of<T>::type>& hs, Timer& timer) {
-    const int og = h->opt.guess;
+    const int og = opts(h).guess;
     if (og == 1) {
-        const int p = h->opt.extrap_order;
+        const int p = opts(h).extrap_order;
         ExtrapTerms<T> t{};
-        if (h->opt.extrap_damp && hs.avail >= p + 2 && p + 2 <= kMaxHist) {
+        if (opts(h).extrap_damp && hs.avail >= p + 2 && p + 2 <= kMaxHist) {
             t.m = p + 2;
             extrap_weights_damped(p, t.c);
         } else {
@@ -649,11 +677,11 @@ void record_samples(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
 
 void check_guess_setup(dmri_ctx* h, bool fp64_vectors) {
     const bool rec = h->model.rec_cap > 0;
-    if (h->opt.guess == 2 && !h->model.set)
+    if (opts(h).guess == 2 && !h->model.set)
         throw Error(DMRI_E_STATE,
                     "guess = 2 needs network parameters (dmri_guess_set_params or "
                     "dmri_load_guess_model)");
-    if ((h->opt.guess == 2 || rec) && !fp64_vectors)
+    if ((opts(h).guess == 2 || rec) && !fp64_vectors)
         throw Error(DMRI_E_UNSUPPORTED,
                     "the learned guess and sample recording need FP64 solution vectors "
                     "(precision 0 or 1)");
@@ -725,14 +753,14 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     hipStream_t st = lane(h).stream;
     Workspace& W = lane(h).ws;
     BatchSetup bs{};
-    bs.herm = (P.op.form == FORM_TRANSFORMED) ? (h->opt.krylov != 2) : false;
-    if (P.op.form == FORM_UFORM && h->opt.krylov == 1)
+    bs.herm = (P.op.form == FORM_TRANSFORMED) ? (opts(h).krylov != 2) : false;
+    if (P.op.form == FORM_UFORM && opts(h).krylov == 1)
         throw Error(DMRI_E_INVALID, "CG needs the Hermitian (periodic-box) operator; use COCG");
-    const int S = h->opt.sys_tile ? h->opt.sys_tile : auto_tile(n_sys);
+    const int S = opts(h).sys_tile ? opts(h).sys_tile : auto_tile(n_sys);
     bs.g = make_geom(static_cast<int32_t>(P.op.n_dof), static_cast<int32_t>(n_sys), S,
-                     h->opt.blocks_per_xcd, h->opt.queue, h->opt.grab, h->opt.xcd_split != 0);
-    bs.g.nt = h->opt.nt;
-    bs.g.lds = h->opt.lds;
+                     opts(h).blocks_per_xcd, opts(h).queue, opts(h).grab, opts(h).xcd_split != 0);
+    bs.g.nt = opts(h).nt;
+    bs.g.lds = opts(h).lds;
     const Geom& g = bs.g;
     const size_t ld = static_cast<size_t>(g.ld);
     int n_cu = 0;
@@ -744,10 +772,10 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     // batches on small meshes); chunked launches win once a phase has enough
     // work to hide the per-launch cost.
     const bool small = static_cast<int64_t>(g.n_rows) * g.ld <= 131072;
-    bs.persist = (h->opt.persistent == 1 || (h->opt.persistent == 2 && small)) && g.ld <= 64;
+    bs.persist = (opts(h).persistent == 1 || (opts(h).persistent == 2 && small)) && g.ld <= 64;
     // The grid barrier needs every block resident: otherwise chunked launches.
     if (bs.persist) {
-        const bool fits = h->opt.precision != 0 ? persistent_fits<float>(bs.gp, bs.herm, n_cu)
+        const bool fits = opts(h).precision != 0 ? persistent_fits<float>(bs.gp, bs.herm, n_cu)
                                                 : persistent_fits<double>(bs.gp, bs.herm, n_cu);
         if (!fits) bs.persist = false;
     }
@@ -756,8 +784,8 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
               static_cast<int64_t>(g.n_rows) * 1024 < (int64_t(1) << 31);
     bs.gi = g;
     if (bs.pair) {
-        bs.gi = make_geom(g.n_rows, static_cast<int32_t>(n_sys), 128, h->opt.blocks_per_xcd, 0, 1,
-                          h->opt.xcd_split != 0);
+        bs.gi = make_geom(g.n_rows, static_cast<int32_t>(n_sys), 128, opts(h).blocks_per_xcd, 0, 1,
+                          opts(h).xcd_split != 0);
         bs.gi.nt = g.nt;
         bs.gi.lds = 0;
     }
@@ -858,7 +886,7 @@ int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const d
             }
             // A tile that has left the loop never re-enters it, so the tiles
             // active in these (older) counts cover the ones still active.
-            if (h->opt.tile_sched)
+            if (opts(h).tile_sched)
                 gk = sched_geom(g, live.data(), static_cast<int>(live.size()));
         }
         pending = true;
@@ -884,7 +912,7 @@ Coef rhs_coef(const dmri_ctx* h, bool tr, const std::vector<double>& F,
 }
 
 void progress_line(dmri_ctx* h, int n, int N, int iters, double t0) {
-    if (h->opt.progress > 0 && (n % h->opt.progress == 0 || n == N)) {
+    if (opts(h).progress > 0 && (n % opts(h).progress == 0 || n == N)) {
         std::fprintf(stderr, "[dmri] step %d/%d: %d iterations, %.2fs\n", n, N, iters,
                      now_s() - t0);
         std::fflush(stderr);
@@ -938,21 +966,21 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     V2* q = reinterpret_cast<V2*>(vecs[hs.nh + 3].p);
     W.outer.alloc(ld, g.n_tiles);
     W.outer.reset(ld, st);
-    SolverState s = W.outer.view(static_cast<int32_t>(n_sys), h->opt.max_iter,
-                                 h->opt.rtol * h->opt.rtol);
+    SolverState s = W.outer.view(static_cast<int32_t>(n_sys), opts(h).max_iter,
+                                 opts(h).rtol * opts(h).rtol);
     const MatView<T> Av = view<T>(P, A);
     launch_set_initial<T>(st, g, P.u0.p, s.n_sys, hs.u(0));
     std::vector<double> F, f;
     step_tables(h, F, f);
     const bool tr = P.op.form == FORM_TRANSFORMED;
-    const int N = h->opt.n_steps > 0 ? std::min(h->opt.n_steps, h->n_steps) : h->n_steps;
+    const int N = opts(h).n_steps > 0 ? std::min(opts(h).n_steps, h->n_steps) : h->n_steps;
 
     constexpr bool kF64 = sizeof(T) == 8;
     check_guess_setup(h, kF64);
-    const bool learn = h->opt.guess == 2 || h->model.rec_cap > 0;
+    const bool learn = opts(h).guess == 2 || h->model.rec_cap > 0;
     const MlpDofs dofs = learn ? ensure_features(h, P) : MlpDofs{nullptr, nullptr};
 
-    KernelTimer timer(h, st, h->opt.time_kernel);
+    KernelTimer timer(h, st, opts(h).time_kernel);
     const double t0 = now_s();
     int last_iters = 8;
     auto step = [&](int n) {
@@ -963,7 +991,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
                            p, nullptr, nullptr, nullptr, s, bs.sc);
         });
         const int done = krylov_loop<T>(h, bs, Av, W.gq.p, lhs, hs.x(), r, p, q, s, timer,
-                                        last_iters - 2, h->opt.max_iter);
+                                        last_iters - 2, opts(h).max_iter);
         last_iters = done;
         if constexpr (kF64) {
             if (hs.avail >= 2)
@@ -974,8 +1002,8 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     };
     // With the persistent solver no host decision is needed inside the time
     // loop, so the whole loop can be captured once and replayed.
-    const bool use_graph = h->opt.graph && bs.persist && h->opt.time_kernel == 0 &&
-                           h->model.rec_cap == 0 && h->opt.progress == 0;
+    const bool use_graph = opts(h).graph && bs.persist && opts(h).time_kernel == 0 &&
+                           h->model.rec_cap == 0 && opts(h).progress == 0;
     V2* u_final = nullptr;
     if (use_graph) {
         std::vector<uint64_t> key;
@@ -999,17 +1027,17 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
         kp(p);
         kp(q);
         for (double v : {double(n_sys), double(N), double(sizeof(T)), double(bs.herm),
-                         double(g.S), double(bs.gp.B), h->opt.rtol, double(h->opt.max_iter),
-                         double(h->opt.guess), double(h->opt.extrap_order),
-                         double(h->opt.extrap_damp), h->dt, h->theta,
+                         double(g.S), double(bs.gp.B), opts(h).rtol, double(opts(h).max_iter),
+                         double(opts(h).guess), double(opts(h).extrap_order),
+                         double(opts(h).extrap_damp), h->dt, h->theta,
                          h->delta, h->Delta})
             kd(v);
-        GraphCache& gc = lane(h).graph;
-        if (gc.exec && gc.key == key) {
+        bool hit = false;
+        GraphCache& gc = lane(h).graph_for(key, hit);
+        if (hit) {
             HIPCHK(hipGraphLaunch(gc.exec, st));
             u_final = static_cast<V2*>(gc.final_u);
         } else {
-            gc.reset();
             HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             try {
                 for (int n = 1; n <= N; ++n) step(n);
@@ -1052,7 +1080,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                        const double* d_q, double2* d_sig, BatchResult& res) {
     hipStream_t st = lane(h).stream;
     Workspace& W = lane(h).ws;
-    const BatchSetup bs = setup_batch(h, P, n_sys, d_b, d_q, h->opt.pair_lanes != 0);
+    const BatchSetup bs = setup_batch(h, P, n_sys, d_b, d_q, opts(h).pair_lanes != 0);
     const Geom& g = bs.g;
     // Inner (FP32) solves run on bsi: the same geometry, or paired tiles.
     BatchSetup bsi = bs;
@@ -1080,15 +1108,15 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     W.inner.alloc(ldi, std::max(g.n_tiles, bs.gi.n_tiles));
     W.outer.reset(ld, st);
     W.inner.reset(ldi, st);
-    SolverState so = W.outer.view(static_cast<int32_t>(n_sys), h->opt.max_outer,
-                                  h->opt.rtol * h->opt.rtol);
-    SolverState si = W.inner.view(static_cast<int32_t>(n_sys), h->opt.max_iter,
-                                  h->opt.inner_rtol * h->opt.inner_rtol);
+    SolverState so = W.outer.view(static_cast<int32_t>(n_sys), opts(h).max_outer,
+                                  opts(h).rtol * opts(h).rtol);
+    SolverState si = W.inner.view(static_cast<int32_t>(n_sys), opts(h).max_iter,
+                                  opts(h).inner_rtol * opts(h).inner_rtol);
     // An inner solve need not reduce its residual below a quarter of the
     // outer target: ||r|| <= max(inner_rtol ||r64||, rtol ||b|| / 4).
     si.floor_bb = W.outer.bb.p;
     {
-        const double k = 0.25 * h->opt.rtol / h->opt.inner_rtol;
+        const double k = 0.25 * opts(h).rtol / opts(h).inner_rtol;
         si.floor_scale = k * k;
     }
     const MatView<double> A64 = view<double>(P, P.A64);
@@ -1097,13 +1125,13 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     std::vector<double> F, f;
     step_tables(h, F, f);
     const bool tr = P.op.form == FORM_TRANSFORMED;
-    const int N = h->opt.n_steps > 0 ? std::min(h->opt.n_steps, h->n_steps) : h->n_steps;
+    const int N = opts(h).n_steps > 0 ? std::min(opts(h).n_steps, h->n_steps) : h->n_steps;
     std::vector<int32_t> flag_or(n_sys, 0);
     check_guess_setup(h, true);
-    const bool learn = h->opt.guess == 2 || h->model.rec_cap > 0;
+    const bool learn = opts(h).guess == 2 || h->model.rec_cap > 0;
     const MlpDofs dofs = learn ? ensure_features(h, P) : MlpDofs{nullptr, nullptr};
 
-    KernelTimer timer(h, st, h->opt.time_kernel);
+    KernelTimer timer(h, st, opts(h).time_kernel);
     const double t0 = now_s();
     int last_first_pass = 8;
     for (int n = 1; n <= N; ++n) {
@@ -1114,9 +1142,9 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                                 hs.x(), r64, p64, nullptr, nullptr, b64, so, bs.sc);
         });
         int step_iters = 0;
-        for (int pass = 0; pass < h->opt.max_outer; ++pass) {
+        for (int pass = 0; pass < opts(h).max_outer; ++pass) {
             const int still = poll_active(h, g, so);
-            if (h->opt.progress > 0 && n % h->opt.progress == 0) {
+            if (opts(h).progress > 0 && n % opts(h).progress == 0) {
                 std::fprintf(stderr, "[dmri] step %d refinement pass %d: %d systems above rtol\n",
                              n, pass, still);
                 std::fflush(stderr);
@@ -1126,7 +1154,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                                p32, si, bs.sc);
             const int it = krylov_loop<float>(h, bsi, A32, W.gq.p, lhs, dx, r32, p32, q32, si,
                                               timer, pass == 0 ? last_first_pass - 2 : 2,
-                                              h->opt.max_iter);
+                                              opts(h).max_iter);
             if (pass == 0) last_first_pass = it;
             step_iters += it;
             timer.run(4, [&] {
@@ -1189,9 +1217,9 @@ void fill_stats(dmri_stats* stats, const std::vector<int64_t>& owner_idx, const 
 
 void run_batch_with(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
                     const double* d_q, double2* d_sig, BatchResult& R) {
-    if (h->opt.precision == 0) {
+    if (opts(h).precision == 0) {
         solve_batch<double>(h, P, P.A64, n_sys, d_b, d_q, d_sig, R);
-    } else if (h->opt.precision == 2) {
+    } else if (opts(h).precision == 2) {
         solve_batch<float>(h, P, P.A32, n_sys, d_b, d_q, d_sig, R);
     } else {
         solve_batch_mixed(h, P, n_sys, d_b, d_q, d_sig, R);
@@ -1203,9 +1231,9 @@ struct OptionGuard {
     dmri_ctx* h;
     Options saved;
     int64_t rec_cap;
-    explicit OptionGuard(dmri_ctx* hh) : h(hh), saved(hh->opt), rec_cap(hh->model.rec_cap) {}
+    explicit OptionGuard(dmri_ctx* hh) : h(hh), saved(opts(hh)), rec_cap(hh->model.rec_cap) {}
     ~OptionGuard() {
-        h->opt = saved;
+        opts(h) = saved;
         h->model.rec_cap = rec_cap;
     }
 };
@@ -1218,10 +1246,10 @@ TuneChoice autotune(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b
                     const double* d_q) {
     OptionGuard guard(h);
     h->model.rec_cap = 0;
-    const int total = h->opt.n_steps > 0 ? std::min(h->opt.n_steps, h->n_steps) : h->n_steps;
-    h->opt.n_steps = std::max(1, std::min(4, total));
-    h->opt.progress = 0;
-    h->opt.time_kernel = 0;
+    const int total = opts(h).n_steps > 0 ? std::min(opts(h).n_steps, h->n_steps) : h->n_steps;
+    opts(h).n_steps = std::max(1, std::min(4, total));
+    opts(h).progress = 0;
+    opts(h).time_kernel = 0;
     DevBuf<double2> sig;
     sig.alloc(static_cast<size_t>(n_sys));
     const int s0 = guard.saved.sys_tile ? guard.saved.sys_tile : auto_tile(n_sys);
@@ -1254,10 +1282,10 @@ TuneChoice autotune(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b
         }
     }
     auto apply = [&](const TuneChoice& c) {
-        h->opt.sys_tile = c.sys_tile;
-        h->opt.blocks_per_xcd = c.blocks_per_xcd;
-        h->opt.persistent = c.persistent;
-        h->opt.lds = c.lds;
+        opts(h).sys_tile = c.sys_tile;
+        opts(h).blocks_per_xcd = c.blocks_per_xcd;
+        opts(h).persistent = c.persistent;
+        opts(h).lds = c.lds;
     };
     TuneChoice best;
     best.seconds = 1e300;
@@ -1286,22 +1314,27 @@ TuneChoice autotune(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b
 
 void run_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, const double* d_q,
                double2* d_sig, BatchResult& R) {
-    if (!h->opt.autotune) {
+    if (!opts(h).autotune) {
         run_batch_with(h, P, n_sys, d_b, d_q, d_sig, R);
         return;
     }
     const std::string key = std::to_string(reinterpret_cast<uintptr_t>(&P)) + "/" +
-                            std::to_string(n_sys) + "/" + std::to_string(h->opt.precision) + "/" +
-                            std::to_string(h->opt.krylov) + "/" + std::to_string(h->opt.sys_tile);
-    auto it = h->tuned.find(key);
-    if (it == h->tuned.end()) it = h->tuned.emplace(key, autotune(h, P, n_sys, d_b, d_q)).first;
-    const TuneChoice c = it->second;
-    h->last_tune = c;
+                            std::to_string(n_sys) + "/" + std::to_string(opts(h).precision) + "/" +
+                            std::to_string(opts(h).krylov) + "/" + std::to_string(opts(h).sys_tile);
+    TuneChoice c;
+    {
+        std::lock_guard<std::mutex> lock(h->tuned_mu);
+        auto it = h->tuned.find(key);
+        if (it == h->tuned.end())
+            it = h->tuned.emplace(key, autotune(h, P, n_sys, d_b, d_q)).first;
+        c = it->second;
+        h->last_tune = c;
+    }
     OptionGuard guard(h);
-    h->opt.sys_tile = c.sys_tile;
-    h->opt.blocks_per_xcd = c.blocks_per_xcd;
-    h->opt.persistent = c.persistent;
-    h->opt.lds = c.lds;
+    opts(h).sys_tile = c.sys_tile;
+    opts(h).blocks_per_xcd = c.blocks_per_xcd;
+    opts(h).persistent = c.persistent;
+    opts(h).lds = c.lds;
     run_batch_with(h, P, n_sys, d_b, d_q, d_sig, R);
 }
 
@@ -1468,8 +1501,8 @@ dmri_status dmri_add_problem(dmri_handle h, int64_t n_nodes, const double* xyz, 
             in.hi[a] = box_hi[a];
         }
         in.periodic_mask = periodic_mask;
-        in.ordering = h->opt.ordering;
-        in.pencil = h->opt.pencil;
+        in.ordering = opts(h).ordering;
+        in.pencil = opts(h).pencil;
         auto rec = std::make_unique<ProblemRec>();
         rec->op = assemble(in);
         h->problems.push_back(std::move(rec));
@@ -1842,11 +1875,11 @@ bool run_host_pairs(dmri_ctx* h, int64_t n_pairs, const int32_t* problem_id, con
         // Tiles of systems with similar b converge together, so whole tiles
         // drop out of the Krylov loop early (results do not depend on the
         // position of a system in the batch).
-        if (h->opt.sort_systems) order_systems(h, pid, b, q, idx);
+        if (opts(h).sort_systems) order_systems(h, pid, b, q, idx);
         hipStream_t st = lane(h).stream;
         ProblemRec& P = get_problem(h, pid);
         const double ts = now_s();
-        ensure_uploaded(h, P, h->opt.precision != 0);
+        ensure_uploaded(h, P, opts(h).precision != 0);
         const int64_t ns = static_cast<int64_t>(idx.size());
         std::vector<double> hb(ns), hq(3 * ns);
         for (int64_t i = 0; i < ns; ++i) {
@@ -1876,8 +1909,8 @@ bool run_host_pairs(dmri_ctx* h, int64_t n_pairs, const int32_t* problem_id, con
     };
     // Several problems run concurrently, one lane (stream, workspace, host
     // thread) each, unless a feature shares state across batches.
-    int n_lanes = std::min<int>(h->opt.concurrency, static_cast<int>(groups.size()));
-    if (h->opt.autotune || h->model.rec_cap > 0 || h->opt.graph) n_lanes = 1;
+    int n_lanes = std::min<int>(opts(h).concurrency, static_cast<int>(groups.size()));
+    if (h->model.rec_cap > 0) n_lanes = 1;  // one sample recorder
     if (n_lanes <= 1) {
         for (const auto& gr : groups) run_group(gr.first, gr.second);
     } else {
@@ -1892,6 +1925,8 @@ bool run_host_pairs(dmri_ctx* h, int64_t n_pairs, const int32_t* problem_id, con
             pool.emplace_back([&, t] {
                 // Lane 0 keeps the stream the caller's thread set on it.
                 tl_lane = t == 0 ? &lane(h) : h->lanes[t].get();
+                Options mine = h->opt;
+                tl_opt = &mine;
                 try {
                     HIPCHK(hipSetDevice(h->device));
                     for (int gi = next++; gi < static_cast<int>(groups.size()); gi = next++)
@@ -1902,6 +1937,7 @@ bool run_host_pairs(dmri_ctx* h, int64_t n_pairs, const int32_t* problem_id, con
                     next = static_cast<int>(groups.size());
                 }
                 tl_lane = nullptr;
+                tl_opt = nullptr;
             });
         }
         for (auto& th : pool) th.join();
@@ -1980,7 +2016,7 @@ struct NoAllocBufs {
 // state is cleared with fill kernels, not memset nodes.
 void run_noalloc(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, const double* d_q,
                  double2* d_sig, dmri_stats* stats) {
-    const Options& o = h->opt;
+    const Options& o = opts(h);
     hipStream_t st = lane(h).stream;
     if (o.precision != 0)
         throw Error(DMRI_E_UNSUPPORTED, "the no-allocation entry point runs precision 0 (FP64)");
@@ -2174,12 +2210,12 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int64_t n_pairs,
         const int32_t problem_id = hp[0];
         ProblemRec& P = get_problem(h, problem_id);
         const double ts = now_s();
-        ensure_uploaded(h, P, h->opt.precision != 0);
+        ensure_uploaded(h, P, opts(h).precision != 0);
         if (stats) stats->t_setup_s = now_s() - ts;
         BatchResult R;
         std::vector<int64_t> idx(n_pairs);
         for (int64_t i = 0; i < n_pairs; ++i) idx[i] = i;
-        if (h->opt.sort_systems) order_systems(h, problem_id, hb.data(), hq.data(), idx);
+        if (opts(h).sort_systems) order_systems(h, problem_id, hb.data(), hq.data(), idx);
         bool identity = true;
         for (int64_t i = 0; i < n_pairs; ++i) identity &= idx[i] == i;
         if (identity) {
@@ -2210,7 +2246,7 @@ dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int64_t n_pairs,
             HIPCHK(hipStreamSynchronize(st));
         }
         fill_stats(stats, idx, R, n_pairs);
-        if (h->opt.sort_systems) remember_costs(h, problem_id, hb.data(), hq.data(), idx, R.iters);
+        if (opts(h).sort_systems) remember_costs(h, problem_id, hb.data(), hq.data(), idx, R.iters);
         for (int32_t fl : R.flags)
             if (fl) return DMRI_NOT_CONVERGED;
         return DMRI_OK;
@@ -2265,12 +2301,12 @@ dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which
         if (which != 0 && which != 1) throw Error(DMRI_E_INVALID, "which must be 0 or 1");
         if (n_sys <= 0 || !c || !d || !x || !y) throw Error(DMRI_E_INVALID, "bad arguments");
         ProblemRec& P = get_problem(h, problem_id);
-        const bool f32 = h->opt.precision != 0;
+        const bool f32 = opts(h).precision != 0;
         ensure_uploaded(h, P, f32);
         hipStream_t st = lane(h).stream;
-        const int S = h->opt.sys_tile ? h->opt.sys_tile : auto_tile(n_sys);
+        const int S = opts(h).sys_tile ? opts(h).sys_tile : auto_tile(n_sys);
         const Geom g = make_geom(static_cast<int32_t>(P.op.n_dof), static_cast<int32_t>(n_sys), S,
-                                 h->opt.blocks_per_xcd, h->opt.queue, h->opt.grab);
+                                 opts(h).blocks_per_xcd, opts(h).queue, opts(h).grab);
         const size_t nrow = static_cast<size_t>(g.n_rows), ld = static_cast<size_t>(g.ld);
         std::vector<double> hc(ld, 0.0), hd(3 * ld, 0.0);
         for (int64_t s = 0; s < n_sys; ++s) {

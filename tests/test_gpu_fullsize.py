@@ -5,8 +5,11 @@ properties that hold at any size, on the workloads the benchmark runs.
 * 36^3 cylinder box (51,408 DOFs), all 8 b-values, full echo: all-FP64 GPU
   within 1e-9 of the oracle; the default mixed-precision solve within 1e-4.
 * 57^3 benchmark workload (196,593 DOFs): 6 sampled systems after the first
-  2 steps within 1e-9 (FP64); the full 1024-system mixed-precision run keeps
-  the b = 0 signals at the conserved total magnetization within 1e-6.
+  2 steps within 1e-9 (FP64); the full 1024-system run with the benchmark's
+  options (mixed precision, rtol 1e-6) within 1e-4 of the oracle's full-echo
+  signals of 10 systems spread over every 128-system tile, the b = 0 signals
+  at the conserved total magnetization within 1e-6, and the all-FP64 path on
+  those 10 systems within 1e-9.
 * smallest seeded-cell geometry (63,493 DOFs): 4 sampled systems, full echo.
 """
 
@@ -79,19 +82,41 @@ def test_benchmark_workload_first_steps(Sim):
     assert err.max() < 1e-9
 
 
-def test_benchmark_workload_conservation(Sim):
-    # b = 0: no gradient, periodic box, permeable membrane, T2 = inf: the
-    # total magnetization sum_k u0_k |Omega_k| is conserved exactly by the
-    # discrete scheme (the oracle pins this); here every one of the 1024
-    # systems runs with the default solver and the 64 b = 0 signals must
-    # equal the box volume (u0 = 1) to the solver tolerance.
+def test_benchmark_workload_full_echo(Sim):
+    # The benchmark's own run: all 1024 systems of the 57^3 workload in one
+    # batch with the benchmark's options (mixed precision: FP32 inner CG on
+    # 128-system paired tiles, active-tile schedule, FP64 refinement to
+    # rtol 1e-6, damped cubic guess, systems ordered by cost). Checked
+    #  * against the oracle's full-echo signals of 10 systems, one in every
+    #    128-system tile of the batch ordered by b: within 1e-4;
+    #  * b = 0: no gradient, periodic box, permeable membrane, T2 = inf: the
+    #    total magnetization sum_k u0_k |Omega_k| is conserved exactly by the
+    #    discrete scheme (the oracle pins this), so the 64 b = 0 signals equal
+    #    the box volume to the solver tolerance;
+    # and the all-FP64 path (rtol 1e-12) on the 10 sampled systems alone
+    # within 1e-9 of the oracle.
+    d, ref = _golden("cylinder_57_full")
     prob, seq, sysl = di.cylinder_57_batched()
-    sig = _run(Sim, prob, seq, sysl.b, sysl.q)
+    idx = np.array(d["index"])
     vol = float(np.prod(np.asarray(prob.box_hi) - np.asarray(prob.box_lo)))
+    with Sim(0) as sim:
+        sim.set_sequence(seq)
+        sim.set_options(precision=1, rtol=1e-6)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * len(sysl), sysl.b, sysl.q)
+        assert st["status"] == "DMRI_OK"
+        sim.set_options(precision=0, rtol=1e-12)
+        sig64, st64 = sim.dmri_run([pid] * len(idx), sysl.b[idx], sysl.q[idx])
+        assert st64["status"] == "DMRI_OK"
+    err = _err(sig[idx], ref, vol)
+    err64 = _err(sig64, ref, vol)
     zero = sysl.b == 0
     dev = np.abs(sig[zero] - vol) / vol
-    _say("57^3 full run: b = 0 max deviation %.2e; |S| range %.3e..%.3e"
-         % (dev.max(), np.abs(sig).min(), np.abs(sig).max()))
+    _say("57^3 full run (mixed, rtol 1e-6): sampled max rel err %.2e (per system %s); "
+         "b = 0 max deviation %.2e; FP64 rtol 1e-12 on the samples: %.2e"
+         % (err.max(), np.array2string(err, precision=1), dev.max(), err64.max()))
+    assert err.max() < 1e-4
+    assert err64.max() < 1e-9
     assert dev.max() < 1e-6
     assert np.all(np.isfinite(sig)) and np.all(np.abs(sig) <= vol * (1 + 1e-9))
 
@@ -104,3 +129,71 @@ def test_seeded_cells_full_echo(Sim):
     err = np.abs(sig - ref) / np.abs(ref)
     _say("seeded cells (seed 3): max rel err %.2e" % err.max())
     assert err.max() < 1e-9
+
+
+_SEEDED = {}
+
+
+def _seeded_batch():
+    # The uneven batch: the 8 seeded-cell geometries (seeds 0-7, 50k-1M
+    # nodes), 32 (b, q) pairs each, 256 pairs in one run.
+    if "batch" not in _SEEDED:
+        items = [di.seeded_cells(seed) for seed in range(8)]
+        _SEEDED["batch"] = items
+    return _SEEDED["batch"]
+
+
+def _run_seeded(Sim, **opts):
+    items = _seeded_batch()
+    seq = items[0][1]
+    with Sim(0) as sim:
+        sim.set_sequence(seq)
+        sim.set_options(**opts)
+        pids = [sim.add_problem(prob) for prob, _, _ in items]
+        ids = np.concatenate([np.full(len(sl), p, np.int32) for p, (_, _, sl) in zip(pids, items)])
+        b = np.concatenate([sl.b for _, _, sl in items])
+        q = np.concatenate([sl.q for _, _, sl in items])
+        sig, st = sim.dmri_run(ids, b, q)
+        tuned = {k: sim.dmri_get_option(k) for k in ("tuned_sys_tile", "tuned_blocks_per_xcd",
+                                                       "tuned_persistent", "tuned_trials")}
+    assert st["status"] == "DMRI_OK"
+    return sig.reshape(8, 32), st, tuned
+
+
+def _seeded_checks(sig, tol_full, tol_first, first=None):
+    out = []
+    for seed in (2, 3):
+        d, ref = _golden("seeded_cells_seed%d" % seed)
+        got = sig[seed][np.array(d["index"])]
+        out.append(np.abs(got - ref) / np.abs(ref))
+    err_full = np.concatenate(out)
+    assert err_full.max() < tol_full, err_full
+    if first is not None:
+        d, ref = _golden("seeded_cells_first2")
+        got = np.array([first[s][i] for s, i in d["index"]])
+        err_first = np.abs(got - ref) / np.abs(ref)
+        assert err_first.max() < tol_first, err_first
+        return err_full.max(), err_first.max()
+    return err_full.max(), None
+
+
+def test_seeded_cells_batch_mixed(Sim):
+    # The whole uneven batch in one dmri_run with the autotuner, mixed
+    # precision at rtol 1e-6: the full-echo signals of the two smallest
+    # geometries within 1e-4 of the oracle; then the first two steps of every
+    # geometry in FP64 (rtol 1e-12) against the oracle's sums after 2 steps,
+    # within 1e-9.
+    sig, st, tuned = _run_seeded(Sim, precision=1, rtol=1e-6, autotune=1)
+    first, _, _ = _run_seeded(Sim, precision=0, rtol=1e-12, n_steps=2, autotune=1)
+    e_full, e_first = _seeded_checks(sig, 1e-4, 1e-9, first)
+    _say("seeded batch mixed: full-echo max rel err %.2e, first-2-steps (FP64) %.2e; %d "
+         "iterations, solve %.1fs, tuned %s" % (e_full, e_first, st["total_iterations"],
+                                                 st["t_solve_s"], tuned))
+
+
+def test_seeded_cells_batch_fp64(Sim):
+    # The same batch all-FP64 at rtol 1e-12: within 1e-9 of the oracle.
+    sig, st, tuned = _run_seeded(Sim, precision=0, rtol=1e-12, autotune=1)
+    e_full, _ = _seeded_checks(sig, 1e-9, None)
+    _say("seeded batch FP64: full-echo max rel err %.2e; %d iterations, solve %.1fs, tuned %s"
+         % (e_full, st["total_iterations"], st["t_solve_s"], tuned))
