@@ -29,6 +29,7 @@ import numpy as np
 __all__ = [
     "Problem",
     "Sequence",
+    "GeneralSequence",
     "Systems",
     "kuhn_box_mesh",
     "label_tets",
@@ -92,6 +93,23 @@ class Sequence:
     @property
     def n_steps(self) -> int:
         return int(round(self.T / self.dt))
+
+
+@dataclass
+class GeneralSequence:
+    """A named temporal profile with its parameters (us), step dt and theta.
+
+    kind: "pgse" (delta, Delta), "double_pgse" (delta, Delta, t_mix),
+    "cos_ogse" / "sin_ogse" (delta, Delta, n_periods), "trap_pgse"
+    (delta, Delta, ramp), "double_trap_pgse" (delta, Delta, ramp, t_mix).
+    Only the description: the profile itself (f, F, echo time) is evaluated
+    by whoever consumes it.
+    """
+
+    kind: str
+    params: tuple
+    dt: float
+    theta: float = 0.5
 
 
 @dataclass

@@ -11,9 +11,14 @@ each step n = 1..N solves
 U-form (Neumann walls), Appendix B, eq. matrix_form with eq. loadvec, with
 the T2 term on the mass matrix (the printed A multiplies 1/T2 by J, which
 conflicts with eq. loadvec where it multiplies the plain mass):
-  L_n = S + I_Gamma + R2 + i G f_n (q . J),
-  (M/k + theta L_n) U^n = (M/k - (1 - theta) L_n) U^{n-1},
-where f_n is the value of f on (t^{n-1}, t^n) (pulse edges lie on the grid).
+  L(f) = S + I_Gamma + R2 + i G f (q . J),
+  (M/k + theta L(f(t^n-))) U^n = (M/k - (1 - theta) L(f(t^{n-1}+))) U^{n-1},
+with the one-sided limits of f on the step interval (profile breakpoints lie
+on the grid; for PGSE both limits are the interval's constant value).
+
+Any temporal profile of oracle.sequence.Profile (PGSE, double PGSE, cos- and
+sin-OGSE, trapezoidal, double trapezoidal) enters through F(t^n) (transformed
+form) or the one-sided limits of f (U-form), and int_0^T F^2 in b -> G.
 
 Signal (Sec. 2, eq. signal): S = int U(T) = sum_i w_i u_i^N, because
 F(T) = 0 at T = Delta + delta makes u(T) = U(T).
@@ -40,6 +45,7 @@ closed form; there the oracle rests on the invariants and limits above.
 
 from __future__ import annotations
 
+import math
 from collections import OrderedDict
 from typing import Optional
 
@@ -98,6 +104,13 @@ def _krylov(A, rhs, x0, hermitian):
     return x
 
 
+def _n_steps(prof, k):
+    """N = T / k; the profile's breakpoints and T must lie on the time grid."""
+    if not prof.on_grid(k):
+        raise ValueError("profile breakpoints and the echo time must be multiples of dt")
+    return int(round(prof.T / k))
+
+
 def _unit(q):
     q = np.asarray(q, dtype=np.float64)
     nq = np.linalg.norm(q)
@@ -118,9 +131,11 @@ def solve_transformed(asm: Assembly, seq, b: float, q, n_steps: Optional[int] = 
     """
     k = float(seq.dt)
     th = float(seq.theta)
-    t = seqmod.time_grid(seq.delta, seq.Delta, seq.dt)
-    F = seqmod.pgse_F(t, seq.delta, seq.Delta)
-    G = float(seqmod.b_to_G(b, seq.delta, seq.Delta))
+    prof = seqmod.profile_of(seq)
+    N_all = _n_steps(prof, k)
+    t = np.arange(N_all + 1, dtype=np.float64) * k
+    F = np.array([prof.F(v) for v in t])
+    G = math.sqrt(b / prof.int_F2())
     qn = _unit(q)
     s0 = int(start_step)
     N = len(t) - 1 if n_steps is None else min(len(t) - 1, s0 + int(n_steps))
@@ -157,10 +172,13 @@ def solve_uform(asm: Assembly, seq, b: float, q, n_steps: Optional[int] = None,
     """Signal of one (b, q) system with the untransformed U-form (Neumann box)."""
     k = float(seq.dt)
     th = float(seq.theta)
-    fint = seqmod.interval_f(seq.delta, seq.Delta, seq.dt)
-    G = float(seqmod.b_to_G(b, seq.delta, seq.Delta))
+    prof = seqmod.profile_of(seq)
+    N_all = _n_steps(prof, k)
+    # one-sided limits f(t^{n-1}+) (right side) and f(t^n-) (left side)
+    lim = [prof.f_limits((n - 1) * k, n * k) for n in range(1, N_all + 1)]
+    G = math.sqrt(b / prof.int_F2())
     qn = _unit(q)
-    N = len(fint) if n_steps is None else int(n_steps)
+    N = N_all if n_steps is None else int(n_steps)
 
     base = (asm.S + asm.IG + asm.R2).tocsr()
     Mk = (asm.M / k).tocsr()
@@ -168,8 +186,8 @@ def solve_uform(asm: Assembly, seq, b: float, q, n_steps: Optional[int] = None,
     cache = _LUCache(cache_size)
     U = asm.u0.astype(np.complex128)
     for n in range(1, N + 1):
-        fn = float(fint[n - 1])
-        rhs = Mk @ U - (1.0 - th) * (base @ U + 1j * (G * fn) * (qJ @ U))
+        f_prev, fn = lim[n - 1]
+        rhs = Mk @ U - (1.0 - th) * (base @ U + 1j * (G * f_prev) * (qJ @ U))
         if solver == "dense":
             U = np.linalg.solve((Mk + th * (base + 1j * (G * fn) * qJ)).toarray(), rhs)
         elif solver == "krylov":
