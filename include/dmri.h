@@ -151,6 +151,53 @@ DMRI_API dmri_status dmri_export_operator(dmri_handle h, int32_t problem_id,
 DMRI_API dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_us,
                                    double dt_us, double theta);
 
+/* General temporal profiles f(t) (Sec. 3, "General diffusion-encoding
+ * sequence", which defines cos-OGSE; Sec. 4, which compares PGSE, double
+ * PGSE, cos-OGSE, sin-OGSE, trapezoidal and double trapezoidal profiles).
+ * All times in us; lobes of sign +1 then -1:
+ *   DMRI_SEQ_PGSE           {delta, Delta}: as dmri_set_sequence_pgse
+ *   DMRI_SEQ_DOUBLE_PGSE    {delta, Delta, t_mix}: a PGSE, t_mix, a PGSE;
+ *                           T = 2 (Delta + delta) + t_mix
+ *   DMRI_SEQ_COS_OGSE       {delta, Delta, n}: cos(w t) on [0, delta],
+ *                           -cos(w (t - tau)) on (tau, tau + delta],
+ *                           w = 2 n pi / delta, tau = (delta + Delta) / 2,
+ *                           n >= 1 whole periods; T = delta + Delta
+ *   DMRI_SEQ_SIN_OGSE       {delta, Delta, n}: the same with sin
+ *   DMRI_SEQ_TRAP_PGSE      {delta, Delta, ramp}: PGSE pulses of length delta
+ *                           with linear ramps of length ramp (0 < ramp <=
+ *                           delta/2) up and down; T = Delta + delta
+ *   DMRI_SEQ_DOUBLE_TRAP_PGSE {delta, Delta, ramp, t_mix}
+ * Every edge of f (pulse starts and ends, ramp corners, lobe starts) and the
+ * echo time T must be a multiple of dt (within 1e-9), 0 < delta <= Delta.
+ * F(t) = int_0^t f is evaluated in closed form at the grid points, the
+ * U-form uses the one-sided limits f(t^{n-1}+), f(t^n-) of each step, and
+ * b = G^2 int_0^T F^2 (eq. b_value) with the integral in closed form for
+ * PGSE and by Gauss-Legendre quadrature between the edges otherwise. Every
+ * profile here has F(T) = 0, so the returned S is the signal at echo time.
+ * Errors: DMRI_E_INVALID (unknown kind, wrong n_params, bad values). */
+#define DMRI_SEQ_PGSE 0
+#define DMRI_SEQ_DOUBLE_PGSE 1
+#define DMRI_SEQ_COS_OGSE 2
+#define DMRI_SEQ_SIN_OGSE 3
+#define DMRI_SEQ_TRAP_PGSE 4
+#define DMRI_SEQ_DOUBLE_TRAP_PGSE 5
+DMRI_API dmri_status dmri_set_sequence(dmri_handle h, int32_t kind, const double* params,
+                              int32_t n_params, double dt_us, double theta);
+
+/* Arbitrary profile given on the time grid t^n = n dt, n = 0..n_steps (the
+ * C analogue of giving any expression f(s), Sec. 3):
+ *   F       [n_steps + 1] F(t^n), F[0] = 0 (transformed form)
+ *   f_start [n_steps] f(t^n+), f_end [n_steps] f(t^{n+1}-) for the step
+ *           (t^n, t^{n+1}) (U-form; both NULL if only periodic problems run)
+ *   int_F2  int_0^T F^2 > 0, with T = n_steps dt (b = G^2 int_F2)
+ * The arrays are copied. The returned S is sum_i w_i u_i^N, the signal when
+ * F(T) = 0. Errors: DMRI_E_INVALID (non-finite values, F[0] != 0, one f
+ * array without the other, int_F2 <= 0); a run of a Neumann problem without
+ * f gives DMRI_E_STATE. */
+DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, double dt_us,
+                                    double theta, const double* F, const double* f_start,
+                                    const double* f_end, double int_F2);
+
 /* Solver options (all have defaults):
  *  "precision"  0 = all FP64 (default), 1 = FP32 matrices and Krylov
  *               vectors with FP64 reductions and FP64 residual refinement
@@ -182,8 +229,17 @@ DMRI_API dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, doub
  *               any device reallocation since the capture forces a new one
  *               (default 0; not with time_kernel or sample recording)
  *  "n_steps"    0 = full echo (default); n > 0 stops after n steps and
- *               returns sum_i w_i u_i^n (a sampling aid, not a signal unless
- *               F(t^n) = 0)
+ *               returns the signal at t^n (see "signal")
+ *  "signal"     what is returned when a run stops where F(t) != 0 on a
+ *               periodic problem (n_steps, or a table sequence with
+ *               F(T) != 0): 1 = the physical signal S(t) = int U(x, t) dx
+ *               with U = u exp(-i G F q . x), x from the box centre
+ *               (Appendix A's substitution; Sec. 2, eq. signal), integrated
+ *               exactly per tetrahedron for the P1 field u (default;
+ *               DMRI_E_UNSUPPORTED if G |F| times the longest edge exceeds
+ *               16 rad); 0 = sum_i w_i u_i (the transformed field's
+ *               integral). Both are the same when F = 0; for walls (U-form)
+ *               the unknown is U and sum_i w_i U_i is returned
  *  "time_kernel" 0 = off, 1 = SpMV+dot, 2 = CG update, 3 = direction
  *               update, 4 = step start, 5 = learned-guess network, 6 =
  *               extrapolation: bracket every launch of that kernel
@@ -344,7 +400,9 @@ DMRI_API dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int64_t n_
  * array holds (n_dof x padded systems x (history + 4) x 16 bytes plus
  * partials) gives DMRI_E_INVALID with the size in the message; other
  * violated limits DMRI_E_INVALID or DMRI_E_UNSUPPORTED. Systems are tiled in
- * input order (option "sort_systems" is not applied). Every call on a device
+ * input order (option "sort_systems" is not applied); a run that would need
+ * the phase-weighted signal (option "signal", F != 0 at its last step) gives
+ * DMRI_E_UNSUPPORTED. Every call on a device
  * uses that device's one array and leaves its contents there: calls that
  * overlap on one device (other threads, other handles, or work still queued
  * on another stream) race and corrupt each other; serialize them. Same

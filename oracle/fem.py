@@ -65,6 +65,7 @@ class Assembly:
     comp_volume: np.ndarray   # |Omega_k|
     interface_area: float     # |Gamma| (sum of interface face areas)
     n_torus_nodes: int
+    tet_dof: np.ndarray = None  # [n_tets, 4] DOF of each vertex (its tet's compartment)
 
 
 def torus_nodes(xyz, box_lo, box_hi, periodic_mask, rel_tol=1e-9):
@@ -204,4 +205,4 @@ def assemble(prob, centre: Optional[np.ndarray] = None) -> Assembly:
     return Assembly(n_dof=n_dof, dof_comp=dof_comp, dof_node=dof_node, M=M, S=S, MD=MD,
                     B=tuple(B), R2=R2, IG=IG, J=tuple(J), w=w, u0=u0c[dof_comp],
                     comp_volume=comp_volume, interface_area=area_total,
-                    n_torus_nodes=n_torus)
+                    n_torus_nodes=n_torus, tet_dof=dof)

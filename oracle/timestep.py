@@ -214,3 +214,46 @@ def signals(prob, seq, b, q, form: str = "auto", asm: Optional[Assembly] = None,
     q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
     return np.array([fn(asm, seq, float(b[i]), q[i], **kw) for i in range(len(b))],
                     dtype=np.complex128)
+
+
+def _simplex_rule(n):
+    """Barycentric points [P, 4] and weights [P] (summing to 1/6) of a
+    collapsed (Duffy) Gauss-Legendre rule with n points per direction on the
+    unit tetrahedron."""
+    g, w = np.polynomial.legendre.leggauss(n)
+    g = 0.5 * (g + 1.0)
+    w = 0.5 * w
+    xi, eta, zeta = np.meshgrid(g, g, g, indexing="ij")
+    wx, we, wz = np.meshgrid(w, w, w, indexing="ij")
+    l1 = xi
+    l2 = (1.0 - xi) * eta
+    l3 = (1.0 - xi) * (1.0 - eta) * zeta
+    l0 = 1.0 - l1 - l2 - l3
+    lam = np.stack([l0, l1, l2, l3], axis=-1).reshape(-1, 4)
+    wt = (wx * we * wz * (1.0 - xi) ** 2 * (1.0 - eta)).reshape(-1)
+    return lam, wt
+
+
+def physical_signal(prob, asm: Assembly, u, kvec, n_gauss: int = 8):
+    """S = int U dx with U = u exp(-i k . (x - c)) (Sec. 2, eq. signal; the
+    substitution of Appendix A with x from the box centre c): the P1 field
+    u_h of the transformed form times the plane wave, integrated over every
+    tetrahedron with a collapsed Gauss rule (n_gauss points per direction;
+    for |k| h of order 1 the rule is exact to rounding). k = G F(t) q.
+    With k = 0 this is sum_i w_i u_i."""
+    xyz = np.asarray(prob.xyz, dtype=np.float64)
+    tets = np.asarray(prob.tets, dtype=np.int64)
+    c = 0.5 * (np.asarray(prob.box_lo, dtype=np.float64) + np.asarray(prob.box_hi, dtype=np.float64))
+    X = xyz[tets] - c[None, None, :]                     # [m, 4, 3]
+    vol6 = np.abs(np.linalg.det(X[:, 1:, :] - X[:, :1, :]))   # 6 |e|
+    lam, wt = _simplex_rule(n_gauss)                     # [P, 4], [P]
+    k = np.asarray(kvec, dtype=np.float64)
+    uv = np.asarray(u)[asm.tet_dof]                      # [m, 4]
+    total = 0.0 + 0.0j
+    for s0 in range(0, X.shape[0], 4096):                # bounded memory
+        Xs = X[s0:s0 + 4096]
+        xq = np.einsum("pl,mla->mpa", lam, Xs)           # [m, P, 3]
+        wave = np.exp(-1j * (xq @ k))                    # [m, P]
+        uq = uv[s0:s0 + 4096] @ lam.T                    # [m, P]
+        total += np.sum(vol6[s0:s0 + 4096, None] * wt[None, :] * uq * wave)
+    return complex(total)

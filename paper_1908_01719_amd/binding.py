@@ -28,12 +28,16 @@ STATUS_NAMES = {
 # Symbols declared in include/dmri.h (checked by the CPU test suite).
 EXPORTED = [
     "dmri_create", "dmri_destroy", "dmri_last_error", "dmri_add_problem", "dmri_problem_info",
-    "dmri_export_operator", "dmri_set_sequence_pgse", "dmri_set_option", "dmri_get_option",
+    "dmri_export_operator", "dmri_set_sequence_pgse", "dmri_set_sequence",
+    "dmri_set_sequence_table", "dmri_set_option", "dmri_get_option",
     "dmri_run", "dmri_run_device", "dmri_run_device_noalloc", "dmri_apply_operator",
     "dmri_guess_set_params", "dmri_guess_get_params", "dmri_load_guess_model",
     "dmri_save_guess_model", "dmri_guess_record", "dmri_guess_record_count", "dmri_guess_eval",
     "dmri_guess_train",
 ]
+
+SEQ_KINDS = {"pgse": 0, "double_pgse": 1, "cos_ogse": 2, "sin_ogse": 3, "trap_pgse": 4,
+             "double_trap_pgse": 5}
 
 GUESS_N_FEATURES = 16
 GUESS_N_PARAMS = 5378
@@ -88,6 +92,8 @@ def load(path: Optional[str] = None):
     lib.dmri_problem_info.argtypes = [vp, i32, P(i64), P(i64)]
     lib.dmri_export_operator.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.dmri_set_sequence_pgse.argtypes = [vp, dbl, dbl, dbl, dbl]
+    lib.dmri_set_sequence.argtypes = [vp, i32, vp, i32, dbl, dbl]
+    lib.dmri_set_sequence_table.argtypes = [vp, i64, dbl, dbl, vp, vp, vp, dbl]
     lib.dmri_set_option.argtypes = [vp, C.c_char_p, dbl]
     lib.dmri_get_option.argtypes = [vp, C.c_char_p, P(dbl)]
     lib.dmri_guess_set_params.argtypes = [vp, vp, i64]
@@ -201,8 +207,26 @@ class Simulator:
         self._check(self.lib.dmri_set_sequence_pgse(self.h, float(delta), float(Delta),
                                                     float(dt), float(theta)))
 
+    def dmri_set_sequence(self, kind, params, dt, theta=0.5):
+        k = SEQ_KINDS[kind] if isinstance(kind, str) else int(kind)
+        p = _c(np.atleast_1d(params), np.float64)
+        self._check(self.lib.dmri_set_sequence(self.h, k, _ptr(p), p.shape[0], float(dt),
+                                               float(theta)))
+
+    def dmri_set_sequence_table(self, dt, theta, F, f_start=None, f_end=None, int_F2=None):
+        F = _c(F, np.float64)
+        fs = _c(f_start, np.float64)
+        fe = _c(f_end, np.float64)
+        self._check(self.lib.dmri_set_sequence_table(self.h, F.shape[0] - 1, float(dt),
+                                                     float(theta), _ptr(F), _ptr(fs), _ptr(fe),
+                                                     float(int_F2)))
+
     def set_sequence(self, seq):
-        self.dmri_set_sequence_pgse(seq.delta, seq.Delta, seq.dt, seq.theta)
+        """A dmri_inputs.Sequence (PGSE) or GeneralSequence (kind, params)."""
+        if hasattr(seq, "kind"):
+            self.dmri_set_sequence(seq.kind, seq.params, seq.dt, seq.theta)
+        else:
+            self.dmri_set_sequence_pgse(seq.delta, seq.Delta, seq.dt, seq.theta)
 
     def dmri_set_option(self, key: str, value: float):
         self._check(self.lib.dmri_set_option(self.h, key.encode(), float(value)))

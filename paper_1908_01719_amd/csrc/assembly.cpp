@@ -452,6 +452,26 @@ HostOperator assemble(const MeshInput& in) {
     }
     op.volume = 0.0;
     for (double v : op.comp_volume) op.volume += v;
+    // Geometry of the tetrahedra for the phase-weighted signal.
+    op.tet_dof = tdof;
+    op.tet_node.assign(in.tets, in.tets + 4 * nT);
+    op.node_xyz.resize(static_cast<size_t>(3 * in.n_nodes));
+    for (int64_t i = 0; i < in.n_nodes; ++i)
+        for (int a = 0; a < 3; ++a) op.node_xyz[3 * i + a] = in.xyz[3 * i + a] - centre[a];
+    double emax = 0.0;
+    for (int64_t e = 0; e < nT; ++e) {
+        const int32_t* tv = in.tets + 4 * e;
+        for (int a = 0; a < 4; ++a)
+            for (int b = a + 1; b < 4; ++b) {
+                double l2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double d = in.xyz[3 * tv[a] + c] - in.xyz[3 * tv[b] + c];
+                    l2 += d * d;
+                }
+                emax = std::max(emax, l2);
+            }
+    }
+    op.max_edge = std::sqrt(emax);
     return op;
 }
 

@@ -72,6 +72,13 @@ struct HostOperator {
     std::vector<float> dof_xyz;      // [n_dof][3] position relative to box centre
     std::vector<float> dof_membrane; // [n_dof] 1 if the node also belongs to another compartment
     std::vector<float> dof_D;        // [n_dof] diffusivity of the DOF's compartment
+    // Per tetrahedron (for the signal of the physical field when F(t) != 0):
+    // its four DOFs and its vertices' mesh nodes; node positions relative
+    // to the box centre.
+    std::vector<int32_t> tet_dof;    // [n_tets][4]
+    std::vector<int32_t> tet_node;   // [n_tets][4]
+    std::vector<double> node_xyz;    // [n_nodes][3]
+    double max_edge = 0.0;           // longest tetrahedron edge
 };
 
 // Validate the input and assemble. Throws dmri::Error.

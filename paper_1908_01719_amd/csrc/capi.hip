@@ -33,6 +33,7 @@
 #include "assembly.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
+#include "sequence.hpp"
 
 namespace dmri {
 namespace {
@@ -105,6 +106,10 @@ struct ProblemRec {
     DevBuf<float4> feat_geo;
     DevBuf<float2> feat_flags;
     bool feat_up = false;
+    // Tetrahedra for the phase-weighted signal (uploaded on first use).
+    DevBuf<int4> tet_dof, tet_node;
+    DevBuf<double> node_xyz;
+    bool tets_up = false;
 };
 
 void build_padded(ProblemRec& P) {
@@ -158,6 +163,7 @@ struct Options {
     int xcd_split = 0;
     int tile_sched = 1;
     int pair_lanes = 1;
+    int signal = 1;
 };
 
 // Per-system Krylov state arrays of one solver level.
@@ -325,8 +331,10 @@ struct dmri_ctx {
     std::string last_error = "no error";
     std::vector<std::unique_ptr<dmri::ProblemRec>> problems;
     bool seq_set = false;
-    double delta = 0, Delta = 0, dt = 0, theta = 0.5;
+    double dt = 0, theta = 0.5;
     int n_steps = 0;
+    dmri::SequenceTables seq;  // F, one-sided f and int F^2 on the time grid
+    uint64_t seq_gen = 0;      // bumped by every sequence change
     dmri::Options opt;
     dmri::GuessModel model;
     std::map<std::string, dmri::TuneChoice> tuned;  // autotuner cache
@@ -502,22 +510,11 @@ double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-// F(t^n) for n = 0..N (transformed form) or f on (t^{n-1}, t^n] for n = 1..N
-// (U-form, index n), from the PGSE profile of Sec. 2 eq. pgse.
+// F(t^n) for n = 0..N (transformed form) and f(t^n-) for n = 1..N (U-form
+// left side) of the current sequence.
 void step_tables(const dmri_ctx* h, std::vector<double>& F, std::vector<double>& f) {
-    const int N = h->n_steps;
-    F.assign(N + 1, 0.0);
-    f.assign(N + 1, 0.0);
-    for (int n = 0; n <= N; ++n) {
-        const double t = n * h->dt;
-        const double up = std::min(std::max(t, 0.0), h->delta);
-        const double down = std::min(std::max(t - h->Delta, 0.0), h->delta);
-        F[n] = up - down;
-        if (n >= 1) {
-            const double tm = (n - 0.5) * h->dt;
-            f[n] = (tm <= h->delta) ? 1.0 : ((tm > h->Delta && tm <= h->Delta + h->delta) ? -1.0 : 0.0);
-        }
-    }
+    F = h->seq.F;
+    f = h->seq.f_end;
 }
 
 // Learned-guess inputs of step n (n >= 2): F (or f) at the last three
@@ -812,7 +809,10 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     W.pinned(static_cast<size_t>(std::max(g.n_tiles, gi.n_tiles)));
     HIPCHK(hipMemsetAsync(W.ctr.p, 0, sizeof(int32_t) * 2 * items_max, st));
     HIPCHK(hipMemsetAsync(W.bad.p, 0, sizeof(int32_t), st));
-    const double intF2 = h->delta * h->delta * (h->Delta - h->delta / 3.0);
+    if (P.op.form == FORM_UFORM && !h->seq.has_f)
+        throw Error(DMRI_E_STATE, "the U-form (walls) needs f on the time grid: the sequence "
+                                  "table was given without f_start / f_end");
+    const double intF2 = h->seq.int_F2;
     launch_sys_params(st, static_cast<int32_t>(n_sys), static_cast<int32_t>(ld_max), d_b, d_q,
                       intF2, W.gq.p, W.bad.p);
     int32_t bad = 0;
@@ -900,6 +900,9 @@ int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const d
     return done;
 }
 
+// Coefficients of step n: the left operator at t^n, the right one at
+// t^{n-1} (transformed form: F at the grid points; U-form: the one-sided
+// limits f(t^n-) and f(t^{n-1}+) on the step interval).
 Coef lhs_coef(const dmri_ctx* h, bool tr, const std::vector<double>& F,
               const std::vector<double>& f, int n) {
     const double th = h->theta;
@@ -907,8 +910,10 @@ Coef lhs_coef(const dmri_ctx* h, bool tr, const std::vector<double>& F,
 }
 Coef rhs_coef(const dmri_ctx* h, bool tr, const std::vector<double>& F,
               const std::vector<double>& f, int n) {
+    (void)f;
     const double th = h->theta;
-    return tr ? Coef{F[n - 1], -(1.0 - th), -(1.0 - th)} : Coef{f[n], 0.0, -(1.0 - th)};
+    return tr ? Coef{F[n - 1], -(1.0 - th), -(1.0 - th)}
+              : Coef{h->seq.f_start[n], 0.0, -(1.0 - th)};
 }
 
 void progress_line(dmri_ctx* h, int n, int N, int iters, double t0) {
@@ -919,13 +924,66 @@ void progress_line(dmri_ctx* h, int n, int N, int iters, double t0) {
     }
 }
 
+TetView ensure_tets(dmri_ctx* h, ProblemRec& P) {
+    if (!P.tets_up) {
+        const HostOperator& op = P.op;
+        const size_t m = op.tet_dof.size() / 4;
+        hipStream_t st = lane(h).stream;
+        P.tet_dof.upload(reinterpret_cast<const int4*>(op.tet_dof.data()), m, st);
+        P.tet_node.upload(reinterpret_cast<const int4*>(op.tet_node.data()), m, st);
+        P.node_xyz.upload(op.node_xyz.data(), op.node_xyz.size(), st);
+        HIPCHK(hipStreamSynchronize(st));
+        P.tets_up = true;
+    }
+    return TetView{P.tet_dof.p, P.tet_node.p, P.node_xyz.p,
+                   static_cast<int32_t>(P.op.tet_dof.size() / 4)};
+}
+
+// Signal of the last step: S = sum_i w_i u_i when F(t^N) = 0 (or for the
+// U-form, whose unknown is U itself); otherwise, with option "signal" = 1,
+// the exact integral of u_h exp(-i G F q . x) over every tetrahedron (the
+// physical field of the transformed form, Appendix A, at that time).
+template <typename T>
+void launch_step_signal(dmri_ctx* h, const BatchSetup& bs, ProblemRec& P,
+                        const typename Vec2Of<T>::type* u, double2* d_sig, int64_t n_sys,
+                        double F_end) {
+    hipStream_t st = lane(h).stream;
+    const bool phase = P.op.form == FORM_TRANSFORMED && F_end != 0.0 && opts(h).signal == 1;
+    if (!phase) {
+        launch_signal<T>(st, bs.g, P.w.p, u, d_sig, static_cast<int32_t>(n_sys), bs.sc);
+        return;
+    }
+    // |k.x_l - mean| <= |k| (longest edge): the series needs it moderate.
+    std::vector<double4> gq(static_cast<size_t>(n_sys));
+    HIPCHK(hipMemcpyAsync(gq.data(), lane(h).ws.gq.p, sizeof(double4) * n_sys,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double gmax = 0.0;
+    for (const double4& v : gq) gmax = std::max(gmax, v.x);
+    if (gmax * std::fabs(F_end) * P.op.max_edge > 16.0)
+        throw Error(DMRI_E_UNSUPPORTED,
+                    "phase-weighted signal: |k| h above 16 rad (mesh too coarse for the "
+                    "gradient); use option signal = 0 for sum w u");
+    const TetView tv = ensure_tets(h, P);
+    Geom gt = make_geom(tv.n_tets, static_cast<int32_t>(n_sys), bs.g.S, opts(h).blocks_per_xcd,
+                        0, 1);
+    Workspace& W = lane(h).ws;
+    const size_t need = static_cast<size_t>(std::max(gt.n_items, 8 * gt.n_tiles)) * gt.B *
+                        gt.S * 4;
+    W.partial.alloc(need);
+    Scratch sc = bs.sc;
+    sc.partial = W.partial.p;
+    launch_signal_phase<T>(st, bs.g, gt, tv, W.gq.p, F_end, u, d_sig, static_cast<int32_t>(n_sys),
+                           sc);
+}
+
 template <typename T>
 void collect_result(dmri_ctx* h, const BatchSetup& bs, ProblemRec& P, StateBufs& sb,
                     const typename Vec2Of<T>::type* u, double2* d_sig, int64_t n_sys,
-                    BatchResult& res) {
+                    BatchResult& res, double F_end) {
     hipStream_t st = lane(h).stream;
     const double t0 = now_s();
-    launch_signal<T>(st, bs.g, P.w.p, u, d_sig, static_cast<int32_t>(n_sys), bs.sc);
+    launch_step_signal<T>(h, bs, P, u, d_sig, n_sys, F_end);
     res.iters.resize(n_sys);
     res.flags.resize(n_sys);
     res.rr.resize(n_sys);
@@ -1030,7 +1088,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
                          double(g.S), double(bs.gp.B), opts(h).rtol, double(opts(h).max_iter),
                          double(opts(h).guess), double(opts(h).extrap_order),
                          double(opts(h).extrap_damp), h->dt, h->theta,
-                         h->delta, h->Delta})
+                         double(h->seq_gen)})
             kd(v);
         bool hit = false;
         GraphCache& gc = lane(h).graph_for(key, hit);
@@ -1062,7 +1120,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     res.t_solve = now_s() - t0;
     res.steps = N;
     timer.collect(res);
-    collect_result<T>(h, bs, P, W.outer, u_final, d_sig, n_sys, res);
+    collect_result<T>(h, bs, P, W.outer, u_final, d_sig, n_sys, res, h->seq.F[N]);
     HIPCHK(hipMemcpyAsync(res.iters.data(), W.outer.iters_total.p, sizeof(int32_t) * n_sys,
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1179,7 +1237,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     res.t_solve = now_s() - t0;
     res.steps = N;
     timer.collect(res);
-    collect_result<double>(h, bs, P, W.outer, hs.u(0), d_sig, n_sys, res);
+    collect_result<double>(h, bs, P, W.outer, hs.u(0), d_sig, n_sys, res, h->seq.F[N]);
     std::vector<int32_t> inner_flags(n_sys);
     HIPCHK(hipMemcpyAsync(res.iters.data(), W.inner.iters_total.p, sizeof(int32_t) * n_sys,
                           hipMemcpyDeviceToHost, st));
@@ -1248,6 +1306,7 @@ TuneChoice autotune(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b
     h->model.rec_cap = 0;
     const int total = opts(h).n_steps > 0 ? std::min(opts(h).n_steps, h->n_steps) : h->n_steps;
     opts(h).n_steps = std::max(1, std::min(4, total));
+    opts(h).signal = 0;  // trial signals are discarded
     opts(h).progress = 0;
     opts(h).time_kernel = 0;
     DevBuf<double2> sig;
@@ -1366,7 +1425,9 @@ ProblemRec& get_problem(dmri_ctx* h, int32_t id) {
 }
 
 void need_sequence(dmri_ctx* h) {
-    if (!h->seq_set) throw Error(DMRI_E_STATE, "no sequence: call dmri_set_sequence_pgse first");
+    if (!h->seq_set)
+        throw Error(DMRI_E_STATE, "no sequence: call dmri_set_sequence_pgse, dmri_set_sequence or "
+                                  "dmri_set_sequence_table first");
 }
 
 constexpr char kModelMagic[8] = {'D', 'M', 'R', 'I', 'M', 'L', 'P', '1'};
@@ -1416,6 +1477,16 @@ namespace {
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices] = {};
+
+// Makes S the handle's sequence.
+void install_sequence(dmri_ctx* h, SequenceTables S) {
+    h->dt = S.dt;
+    h->theta = S.theta;
+    h->n_steps = S.n_steps;
+    h->seq = std::move(S);
+    h->seq_set = true;
+    ++h->seq_gen;
+}
 
 // Device address of `scratch` on `device`, which must be current. Looked up
 // on the first call for a device and kept.
@@ -1546,25 +1617,55 @@ dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_
                                    double theta) {
     if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
     return guarded(h, [&]() -> dmri_status {
-        if (!std::isfinite(delta_us) || !std::isfinite(Delta_us) || !std::isfinite(dt_us) ||
-            !std::isfinite(theta))
-            throw Error(DMRI_E_INVALID, "sequence parameters must be finite");
-        if (!(dt_us > 0) || !(delta_us > 0) || !(Delta_us >= delta_us))
-            throw Error(DMRI_E_INVALID, "need dt > 0 and 0 < delta <= Delta");
-        if (theta < 0.5 || theta > 1.0) throw Error(DMRI_E_INVALID, "theta must be in [1/2, 1]");
-        for (double v : {delta_us, Delta_us}) {
-            const double r = v / dt_us;
-            if (std::fabs(r - std::round(r)) > 1e-9 * std::max(1.0, r))
-                throw Error(DMRI_E_INVALID, "delta/dt and Delta/dt must be integers");
+        const double p[2] = {delta_us, Delta_us};
+        install_sequence(h, make_sequence(DMRI_SEQ_PGSE, p, 2, dt_us, theta));
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_set_sequence(dmri_handle h, int32_t kind, const double* params,
+                              int32_t n_params, double dt_us, double theta) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        install_sequence(h, make_sequence(kind, params, n_params, dt_us, theta));
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, double dt_us, double theta,
+                                    const double* F, const double* f_start, const double* f_end,
+                                    double int_F2) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        if (n_steps < 1 || n_steps > 10000000) throw Error(DMRI_E_INVALID, "need 1 <= n_steps <= 1e7");
+        if (!F) throw Error(DMRI_E_INVALID, "NULL F");
+        if ((f_start == nullptr) != (f_end == nullptr))
+            throw Error(DMRI_E_INVALID, "give both f_start and f_end, or neither");
+        if (!std::isfinite(dt_us) || !(dt_us > 0)) throw Error(DMRI_E_INVALID, "need dt > 0");
+        if (!std::isfinite(theta) || theta < 0.5 || theta > 1.0)
+            throw Error(DMRI_E_INVALID, "theta must be in [1/2, 1]");
+        if (!std::isfinite(int_F2) || !(int_F2 > 0)) throw Error(DMRI_E_INVALID, "need int_F2 > 0");
+        SequenceTables S;
+        S.dt = dt_us;
+        S.theta = theta;
+        S.n_steps = static_cast<int>(n_steps);
+        S.F.assign(F, F + n_steps + 1);
+        S.f_start.assign(n_steps + 1, 0.0);
+        S.f_end.assign(n_steps + 1, 0.0);
+        for (double v : S.F)
+            if (!std::isfinite(v)) throw Error(DMRI_E_INVALID, "F must be finite");
+        if (S.F[0] != 0.0) throw Error(DMRI_E_INVALID, "F(0) must be 0");
+        if (f_start) {
+            for (int64_t n = 0; n < n_steps; ++n) {
+                if (!std::isfinite(f_start[n]) || !std::isfinite(f_end[n]))
+                    throw Error(DMRI_E_INVALID, "f must be finite");
+                S.f_start[n + 1] = f_start[n];
+                S.f_end[n + 1] = f_end[n];
+            }
+            S.has_f = true;
         }
-        const double steps = std::round((Delta_us + delta_us) / dt_us);
-        if (steps > 1e7) throw Error(DMRI_E_INVALID, "too many time steps");
-        h->delta = delta_us;
-        h->Delta = Delta_us;
-        h->dt = dt_us;
-        h->theta = theta;
-        h->n_steps = static_cast<int>(steps);
-        h->seq_set = true;
+        S.int_F2 = int_F2;
+        install_sequence(h, std::move(S));
         return DMRI_OK;
     });
 }
@@ -1617,6 +1718,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "xcd_split") o.xcd_split = as_int(0, 1);
         else if (k == "tile_sched") o.tile_sched = as_int(0, 1);
         else if (k == "pair_lanes") o.pair_lanes = as_int(0, 1);
+        else if (k == "signal") o.signal = as_int(0, 1);
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -1656,6 +1758,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "xcd_split") *value = o.xcd_split;
         else if (k == "tile_sched") *value = o.tile_sched;
         else if (k == "pair_lanes") *value = o.pair_lanes;
+        else if (k == "signal") *value = o.signal;
         else if (k == "tuned_sys_tile") *value = h->last_tune.sys_tile;
         else if (k == "tuned_blocks_per_xcd") *value = h->last_tune.blocks_per_xcd;
         else if (k == "tuned_persistent") *value = h->last_tune.persistent;
@@ -2069,9 +2172,10 @@ void run_noalloc(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, c
     // The array keeps the previous call's contents: clear the state, the
     // queue counters, the invalid-input flag and the grid barrier.
     launch_zero_i32(st, B.zero_from, B.zero_to - B.zero_from);
-    const double intF2 = h->delta * h->delta * (h->Delta - h->delta / 3.0);
-    launch_sys_params(st, static_cast<int32_t>(n_sys), static_cast<int32_t>(ld), d_b, d_q, intF2,
-                      B.gq, B.bad);
+    if (P.op.form == FORM_UFORM && !h->seq.has_f)
+        throw Error(DMRI_E_STATE, "the U-form (walls) needs f on the time grid");
+    launch_sys_params(st, static_cast<int32_t>(n_sys), static_cast<int32_t>(ld), d_b, d_q,
+                      h->seq.int_F2, B.gq, B.bad);
     SolverState s{};
     s.rho = B.rho;
     s.alpha = B.alpha;
@@ -2100,6 +2204,10 @@ void run_noalloc(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, c
     step_tables(h, F, f);
     const bool tr = P.op.form == FORM_TRANSFORMED;
     const int N = o.n_steps > 0 ? std::min(o.n_steps, h->n_steps) : h->n_steps;
+    if (P.op.form == FORM_TRANSFORMED && h->seq.F[N] != 0.0 && o.signal == 1)
+        throw Error(DMRI_E_UNSUPPORTED,
+                    "the no-allocation entry point returns sum w u only: stop where F = 0 or "
+                    "set option signal = 0");
     KernelTimer timer(h, st, 0);
     const MlpDofs no_dofs{nullptr, nullptr};
     const double t0 = now_s();

@@ -1563,6 +1563,115 @@ __global__ __launch_bounds__(kBlock) void k_signal(Geom g, const double* __restr
     }
 }
 
+// Phase-weighted signal partials. For a tetrahedron with vertices x_l (from
+// the box centre) and P1 values u_l, the exact integral of u_h exp(-i k.x) is
+//   6|e| sum_j u_j E_j,  E_j = exp[z_0, z_1, z_2, z_3, z_j],  z_l = -i k.x_l,
+// the divided difference of exp with node z_j repeated (Hermite-Genocchi:
+// the barycentric integral of exp(sum lambda_l z_l) is exp[z_0..z_3], and
+// weighting by lambda_j is the derivative in z_j). With phi_l = k.x_l minus
+// their mean, E_j = exp(-i mean) sum_m (-i)^m H_m^(j) / (m + 4)!, where
+// H_m^(j) is the complete homogeneous polynomial of degree m in
+// (phi_0..phi_3, phi_j) (real), built degree by degree. Terms are added
+// until two in a row fall below 1e-18 of the sum (at most kPhaseTerms).
+constexpr int kPhaseTerms = 160;
+
+template <typename T, int S>
+__global__ __launch_bounds__(kBlock) void k_signal_phase(Geom gt, int32_t n_rows,
+                                                         TetView tv,
+                                                         const double4* __restrict__ gq, double F,
+                                                         const V2<T>* __restrict__ x,
+                                                         int32_t n_sys, Scratch sc) {
+    __shared__ double lds[kWaves * S * 2];
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int kk = xcd; kk < gt.n_items; kk += 8) {
+        const ItemRef ir = item_ref(gt, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
+        const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = static_cast<size_t>(tile) * n_rows * S + (sys - tile * S);
+        double acc[2] = {0.0, 0.0};
+        if (sys < n_sys) {
+            const double4 gg = gq[sys];
+            const double kf = gg.x * F;
+            const double kx = kf * gg.y, ky = kf * gg.z, kz = kf * gg.w;
+            sweep_static<S>(gt, part, j, [&](int first, int r1) {
+                for (int u = 0; u < kUs; ++u) {
+                    bool ok;
+                    const int e = slot_row<S>(first, u, r1, ok);
+                    if (!ok) continue;
+                    const int4 dv = tv.dof[e], nv = tv.node[e];
+                    const int nd[4] = {nv.x, nv.y, nv.z, nv.w};
+                    const int dd[4] = {dv.x, dv.y, dv.z, dv.w};
+                    double X[4][3], th[4];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) X[l][a] = tv.xyz[3 * static_cast<size_t>(nd[l]) + a];
+                        th[l] = kx * X[l][0] + ky * X[l][1] + kz * X[l][2];
+                    }
+                    double e1[3], e2[3], e3[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        e1[a] = X[1][a] - X[0][a];
+                        e2[a] = X[2][a] - X[0][a];
+                        e3[a] = X[3][a] - X[0][a];
+                    }
+                    const double det = e1[0] * (e2[1] * e3[2] - e2[2] * e3[1]) -
+                                       e1[1] * (e2[0] * e3[2] - e2[2] * e3[0]) +
+                                       e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
+                    const double w6 = fabs(det);  // 6 |e|
+                    const double tm = 0.25 * (th[0] + th[1] + th[2] + th[3]);
+                    double ph[4];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) ph[l] = th[l] - tm;
+                    double ur[4], ui[4];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const V2<T> v = x[tb + static_cast<size_t>(dd[l]) * S];
+                        ur[l] = static_cast<double>(v.x);
+                        ui[l] = static_cast<double>(v.y);
+                    }
+                    // m = 0: every H is 1, 1/4! = 1/24.
+                    double inv_f = 1.0 / 24.0;
+                    double sr = (ur[0] + ur[1] + ur[2] + ur[3]) * inv_f;
+                    double si = (ui[0] + ui[1] + ui[2] + ui[3]) * inv_f;
+                    double a0 = 1.0, a1 = 1.0, a2 = 1.0, H = 1.0;
+                    double Hj[4] = {1.0, 1.0, 1.0, 1.0};
+                    int small = 0;
+                    for (int m = 1; m <= kPhaseTerms; ++m) {
+                        a0 = ph[0] * a0;
+                        a1 = a0 + ph[1] * a1;
+                        a2 = a1 + ph[2] * a2;
+                        H = a2 + ph[3] * H;
+                        double tr = 0.0, ti = 0.0;
+#pragma unroll
+                        for (int l = 0; l < 4; ++l) {
+                            Hj[l] = H + ph[l] * Hj[l];
+                            tr += ur[l] * Hj[l];
+                            ti += ui[l] * Hj[l];
+                        }
+                        inv_f /= (m + 4);
+                        tr *= inv_f;
+                        ti *= inv_f;
+                        switch (m & 3) {  // times (-i)^m
+                            case 0: sr += tr; si += ti; break;
+                            case 1: sr += ti; si -= tr; break;
+                            case 2: sr -= tr; si -= ti; break;
+                            default: sr -= ti; si += tr; break;
+                        }
+                        const double mag = fabs(tr) + fabs(ti);
+                        small = (mag <= 1e-18 * (fabs(sr) + fabs(si)) || mag == 0.0) ? small + 1 : 0;
+                        if (small >= 2) break;
+                    }
+                    const double c = cos(tm), sn = sin(tm);  // times exp(-i tm)
+                    acc[0] += w6 * (c * sr + sn * si);
+                    acc[1] += w6 * (c * si - sn * sr);
+                }
+            });
+        }
+        reduce_store<S, 2>(gt, sc, item, j, acc, lds);
+    }
+}
+
 // Add a tile's partials in a fixed order and update the per-system scalars.
 // One block per tile; thread (grp, s) sums partials grp, grp+G, ... of
 // system s, then the groups are combined in order. Resets the tile's queue
@@ -2081,6 +2190,20 @@ void launch_signal(hipStream_t st, const Geom& g, const double* w, const V2<T>* 
 }
 
 template <typename T>
+void launch_signal_phase(hipStream_t st, const Geom& g, const Geom& gt, const TetView& tv,
+                         const double4* gq, double F, const V2<T>* x, double2* out,
+                         int32_t n_sys, Scratch sc) {
+    if (gt.S != g.S || gt.n_tiles != g.n_tiles)
+        throw std::runtime_error("signal_phase: tet geometry must share the tiles");
+    const dim3 grid = grid_of(gt), block(kBlock);
+    DMRI_DISPATCH_S(g.S, {
+        k_signal_phase<T, S><<<grid, block, 0, st>>>(gt, g.n_rows, tv, gq, F, x, n_sys, sc);
+    });
+    check_launch("signal_phase");
+    launch_fin<FIN_SIGNAL, 2>(st, gt, SolverState{}, sc, out, n_sys, nullptr);
+}
+
+template <typename T>
 void launch_apply(hipStream_t st, const Geom& g, const MatView<T>& A, int which, const double* c,
                   const double3* d, const V2<T>* x, V2<T>* y) {
     const dim3 grid = grid_of(g), block(kBlock);
@@ -2139,6 +2262,9 @@ void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
                                     int32_t, SolverState);                                     \
     template void launch_signal<T>(hipStream_t, const Geom&, const double*, const V2<T>*,      \
                                    double2*, int32_t, Scratch);                                \
+    template void launch_signal_phase<T>(hipStream_t, const Geom&, const Geom&, const TetView&,\
+                                         const double4*, double, const V2<T>*, double2*,       \
+                                         int32_t, Scratch);                                    \
     template void launch_apply<T>(hipStream_t, const Geom&, const MatView<T>&, int,            \
                                   const double*, const double3*, const V2<T>*, V2<T>*);        \
     template void launch_set_initial<T>(hipStream_t, const Geom&, const double*, int32_t,      \

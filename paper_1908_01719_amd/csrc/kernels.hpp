@@ -169,6 +169,24 @@ template <typename T>
 void launch_signal(hipStream_t st, const Geom& g, const double* w,
                    const typename Vec2Of<T>::type* x, double2* out, int32_t n_sys, Scratch sc);
 
+// Tetrahedra of a mesh on the device: DOFs and mesh nodes of the four
+// vertices, node positions relative to the box centre.
+struct TetView {
+    const int4* dof;
+    const int4* node;
+    const double* xyz;  // [n_nodes][3]
+    int32_t n_tets;
+};
+
+// Signal of the physical field U = u exp(-i k_s . x) with k_s = G_s F q_s at a
+// time where F != 0 (transformed form): S_s = sum over tetrahedra of the exact
+// integral of the P1 field u_s times the plane wave. g is the vector layout
+// (rows = DOFs), gt the same tiles with rows = tetrahedra (work items).
+template <typename T>
+void launch_signal_phase(hipStream_t st, const Geom& g, const Geom& gt, const TetView& tv,
+                         const double4* gq, double F, const typename Vec2Of<T>::type* x,
+                         double2* out, int32_t n_sys, Scratch sc);
+
 // y = (Base + c M_D + i d.V) x for explicit per-system c and d (kernel check).
 template <typename T>
 void launch_apply(hipStream_t st, const Geom& g, const MatView<T>& A, int which,

@@ -76,7 +76,7 @@ def test_benchmark_workload_first_steps(Sim):
     prob, seq, sysl = di.cylinder_57_batched()
     idx = np.array(d["index"])
     sig = _run(Sim, prob, seq, sysl.b[idx], sysl.q[idx], precision=0, rtol=1e-12,
-               n_steps=d["n_steps"])
+               n_steps=d["n_steps"], signal=0)
     err = np.abs(sig - ref) / np.abs(ref)
     _say("57^3 first %d steps: max rel err %.2e" % (d["n_steps"], err.max()))
     assert err.max() < 1e-9
@@ -184,7 +184,7 @@ def test_seeded_cells_batch_mixed(Sim):
     # geometry in FP64 (rtol 1e-12) against the oracle's sums after 2 steps,
     # within 1e-9.
     sig, st, tuned = _run_seeded(Sim, precision=1, rtol=1e-6, autotune=1)
-    first, _, _ = _run_seeded(Sim, precision=0, rtol=1e-12, n_steps=2, autotune=1)
+    first, _, _ = _run_seeded(Sim, precision=0, rtol=1e-12, n_steps=2, signal=0, autotune=1)
     e_full, e_first = _seeded_checks(sig, 1e-4, 1e-9, first)
     _say("seeded batch mixed: full-echo max rel err %.2e, first-2-steps (FP64) %.2e; %d "
          "iterations, solve %.1fs, tuned %s" % (e_full, e_first, st["total_iterations"],

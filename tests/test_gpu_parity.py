@@ -218,11 +218,12 @@ def test_two_problems_device_entry(Sim):
 
 
 def test_sampled_first_steps(Sim):
-    # n_steps limits the run; compare sum w u^n after 3 steps with the oracle.
+    # n_steps limits the run; compare sum w u^n after 3 steps with the oracle
+    # (option signal = 0: the transformed field's integral).
     prob, b, q = _cyl_case()
     with Sim(0) as sim:
         sim.set_sequence(SHORT)
-        sim.set_options(rtol=1e-13, n_steps=3)
+        sim.set_options(rtol=1e-13, n_steps=3, signal=0)
         pid = sim.add_problem(prob)
         sig, _ = sim.dmri_run([pid] * 4, b[:4], q[:4])
     ref = timestep.signals(prob, SHORT, b[:4], q[:4], solver="splu", n_steps=3)
@@ -656,3 +657,128 @@ def test_launch_options_match_oracle(Sim, opts):
     err = rel_err(sig, ref, ref[0])
     _say("%s max err %.2e" % (opts, err.max()))
     assert err.max() < 1e-9
+
+
+# ------------------------------------------------ general temporal profiles
+PROFILES = [
+    ("double_pgse", (2000.0, 4000.0, 1000.0)),
+    ("cos_ogse", (2000.0, 4000.0, 1.0)),
+    ("sin_ogse", (2000.0, 4000.0, 2.0)),
+    ("trap_pgse", (2000.0, 4000.0, 400.0)),
+    ("double_trap_pgse", (2000.0, 4000.0, 400.0, 200.0)),
+]
+
+
+@pytest.mark.parametrize("kind,params", PROFILES)
+def test_general_profiles_match_oracle(Sim, kind, params):
+    # Each profile through dmri_set_sequence, FP64 at rtol 1e-12, against the
+    # oracle's exact solves of the same theta recurrence (periodic box).
+    prob, b, q = _cyl_case()
+    sel = [1, 3, 4, 8, 12]
+    seq = di.GeneralSequence(kind, params, 200.0, 0.5)
+    with Sim(0) as sim:
+        sim.set_sequence(seq)
+        sim.set_options(rtol=1e-12)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * len(sel), b[sel], q[sel])
+        sim.set_options(precision=1, rtol=1e-9)
+        sig_m, _ = sim.dmri_run([pid] * len(sel), b[sel], q[sel])
+    ref = timestep.signals(prob, seq, b[sel], q[sel], solver="splu")
+    e = rel_err(sig, ref, ref[0])
+    em = rel_err(sig_m, ref, ref[0])
+    _say("%s: FP64 err %.2e, mixed err %.2e, %d steps" % (kind, e.max(), em.max(), st["n_steps"]))
+    assert st["status"] == "DMRI_OK"
+    assert e.max() < 1e-9
+    assert em.max() < 1e-6
+
+
+@pytest.mark.parametrize("kind,params", [("cos_ogse", (2000.0, 4000.0, 1.0)),
+                                         ("trap_pgse", (2000.0, 4000.0, 400.0))])
+def test_general_profiles_uform_match_oracle(Sim, kind, params):
+    # Walls (U-form, COCG): the one-sided limits of f on each step.
+    prob = di.slab_box(n=8, half=4.0, split=0.5, D=(3e-3, 1.5e-3), kappa=2e-3, u0=(1.0, 0.4),
+                       periodic_mask=0)
+    b = np.array([800.0, 2500.0, 4000.0])
+    q = np.array([[1.0, 0.0, 0.0], [0.6, 0.8, 0.0], [0.2, 0.3, 0.9]])
+    seq = di.GeneralSequence(kind, params, 200.0, 0.5)
+    with Sim(0) as sim:
+        sim.set_sequence(seq)
+        sim.set_options(rtol=1e-12)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * 3, b, q)
+    ref = timestep.signals(prob, seq, b, q, solver="splu")
+    e = rel_err(sig, ref, ref[0])
+    _say("U-form %s: err %.2e" % (kind, e.max()))
+    assert st["status"] == "DMRI_OK"
+    assert e.max() < 1e-9
+
+
+def test_sequence_table_entry(Sim):
+    # An arbitrary profile given as tables on the grid (here the oracle's
+    # own F, one-sided f and int F^2 of a cos-OGSE): same signals as the
+    # named profile, and the oracle's, on both forms.
+    from oracle import sequence as sq
+    kind, params, dt = "cos_ogse", (2000.0, 4000.0, 1.0), 200.0
+    prof = sq.Profile(kind, params)
+    N = int(round(prof.T / dt))
+    F = np.array([prof.F(n * dt) for n in range(N + 1)])
+    lim = np.array([prof.f_limits(n * dt, (n + 1) * dt) for n in range(N)])
+    seq = di.GeneralSequence(kind, params, dt, 0.5)
+    prob, b, q = _cyl_case()
+    sel = [2, 4, 10]
+    wall = di.slab_box(n=8, half=4.0, split=0.5, D=(3e-3, 1.5e-3), kappa=2e-3, u0=(1.0, 0.4),
+                       periodic_mask=0)
+    with Sim(0) as sim:
+        sim.set_options(rtol=1e-12)
+        pid = sim.add_problem(prob)
+        pw = sim.add_problem(wall)
+        sim.set_sequence(seq)
+        named, _ = sim.dmri_run([pid] * 3 + [pw] * 3, np.concatenate([b[sel]] * 2),
+                                np.concatenate([q[sel]] * 2))
+        sim.dmri_set_sequence_table(dt, 0.5, F, lim[:, 0], lim[:, 1], prof.int_F2())
+        table, _ = sim.dmri_run([pid] * 3 + [pw] * 3, np.concatenate([b[sel]] * 2),
+                                np.concatenate([q[sel]] * 2))
+        # without f the periodic problem still runs, the wall problem cannot
+        sim.dmri_set_sequence_table(dt, 0.5, F, None, None, prof.int_F2())
+        per, _ = sim.dmri_run([pid] * 3, b[sel], q[sel])
+        with pytest.raises(Exception, match="DMRI_E_STATE"):
+            sim.dmri_run([pw], b[:1], q[:1])
+    ref = timestep.signals(prob, seq, b[sel], q[sel], solver="splu")
+    refw = timestep.signals(wall, seq, b[sel], q[sel], solver="splu")
+    assert rel_err(table, named, named[0]).max() < 1e-12
+    assert rel_err(per, named[:3], named[0]).max() < 1e-12
+    assert rel_err(table[:3], ref, ref[0]).max() < 1e-9
+    assert rel_err(table[3:], refw, refw[0]).max() < 1e-9
+
+
+@pytest.mark.parametrize("stop", [3, 11, 17])
+def test_physical_signal_mid_sequence(Sim, stop):
+    # A run that stops where F != 0 returns the physical signal: the P1 field
+    # times the plane wave exp(-i G F q.x), integrated exactly per
+    # tetrahedron, against the oracle's Gauss-rule integral of its own u^n.
+    prob, b, q = _cyl_case()
+    sel = [0, 2, 4, 6, 10]
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-13, n_steps=stop)
+        pid = sim.add_problem(prob)
+        sig, _ = sim.dmri_run([pid] * len(sel), b[sel], q[sel])
+        sim.set_options(precision=1, rtol=1e-10)
+        sig_m, _ = sim.dmri_run([pid] * len(sel), b[sel], q[sel])
+    asm = fem.assemble(prob)
+    from oracle import sequence as sq
+    F = float(sq.pgse_F(stop * SHORT.dt, SHORT.delta, SHORT.Delta))
+    ref = []
+    for i in sel:
+        _, u = timestep.solve_transformed(asm, SHORT, b[i], q[i], n_steps=stop, solver="splu",
+                                          return_u=True)
+        G = float(sq.b_to_G(b[i], SHORT.delta, SHORT.Delta))
+        qn = np.asarray(q[i]) / np.linalg.norm(q[i])
+        ref.append(timestep.physical_signal(prob, asm, u, G * F * qn))
+    ref = np.array(ref)
+    e = np.abs(sig - ref) / np.abs(ref).max()
+    em = np.abs(sig_m - ref) / np.abs(ref).max()
+    _say("physical signal at step %d (F = %g): FP64 err %.2e, mixed %.2e" % (stop, F, e.max(),
+                                                                             em.max()))
+    assert e.max() < 1e-9
+    assert em.max() < 1e-7

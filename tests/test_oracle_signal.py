@@ -279,3 +279,68 @@ def test_forms_agree_general_profile(kind, params):
     # (the OGSE signal is small here, 0.23 of the slab's 1.8, so the
     # relative gap at n = 40 is larger than for PGSE)
     assert abs(su - st) / abs(su) < 5e-2
+
+
+# --------------------------------------- physical signal when F(t) != 0
+# S(t) = int u_h exp(-i k.(x - c)) (Sec. 2, eq. signal; Appendix A's
+# substitution). Pinned against exact box integrals of the plane wave times a
+# constant and times a linear field (both represented exactly by P1), against
+# sum w u at k = 0, and by the two forms converging to each other when the
+# run stops mid-sequence (F != 0, the U-form needs no phase).
+
+def _box_wave(L, k):
+    # int_{-L/2}^{L/2} exp(-i k x) dx and int x exp(-i k x) dx (= i d/dk of it)
+    if k == 0.0:
+        return L, 0.0
+    I = 2.0 * math.sin(0.5 * k * L) / k
+    dI = L * math.cos(0.5 * k * L) / k - 2.0 * math.sin(0.5 * k * L) / k ** 2
+    return I, 1j * dI
+
+
+@pytest.mark.parametrize("k", [(0.0, 0.0, 0.0), (0.3, -0.2, 0.5), (1.1, 0.4, -0.7)])
+def test_physical_signal_box_integrals(k):
+    p = di.free_box(n=5, half=2.5, periodic_mask=0)
+    p.xyz = p.xyz + np.array([0.7, -0.3, 0.2])           # box not centred at 0
+    p.box_lo = p.box_lo + np.array([0.7, -0.3, 0.2])
+    p.box_hi = p.box_hi + np.array([0.7, -0.3, 0.2])
+    asm = fem.assemble(p)
+    c = 0.5 * (p.box_lo + p.box_hi)
+    L = 5.0
+    Ix, Jx = _box_wave(L, k[0])
+    Iy, Jy = _box_wave(L, k[1])
+    Iz, Jz = _box_wave(L, k[2])
+    ones = np.ones(asm.n_dof)
+    s1 = timestep.physical_signal(p, asm, ones, k)
+    assert abs(s1 - Ix * Iy * Iz) < 1e-12 * L ** 3
+    xnode = p.xyz[asm.dof_node, 1] - c[1]                # linear field y - c_y
+    s2 = timestep.physical_signal(p, asm, xnode, k)
+    assert abs(s2 - Ix * Jy * Iz) < 1e-12 * L ** 4
+    if k == (0.0, 0.0, 0.0):
+        u = np.random.default_rng(1).normal(size=asm.n_dof)
+        assert timestep.physical_signal(p, asm, u, k) == pytest.approx(asm.w @ u, rel=1e-13)
+
+
+def test_physical_signal_forms_agree_mid_sequence():
+    # Stop at step n where F != 0: the U-form signal sum w U^n and the
+    # transformed form's physical signal converge to each other at second
+    # order (fixes the sign and the origin of the phase).
+    prev = None
+    for n, dt in ((10, 200.0), (20, 100.0), (40, 50.0)):
+        seq = di.Sequence(2000.0, 4000.0, dt, 0.5)
+        stop = int(round(3000.0 / dt))                   # t = 3 ms: F = delta
+        p = di.slab_box(n=n, half=5.0, split=-1.0, D=(3e-3, 1e-3), kappa=1e-3, u0=(1.0, 0.2),
+                        cross=(1.0, 1), periodic_mask=0)
+        asm = fem.assemble(p)
+        G = float(sq.b_to_G(3000.0, seq.delta, seq.Delta))
+        su = timestep.solve_uform(asm, seq, 3000.0, [1, 0, 0], n_steps=stop, solver="splu")
+        _, u = timestep.solve_transformed(asm, seq, 3000.0, [1, 0, 0], n_steps=stop,
+                                          solver="splu", return_u=True)
+        F = float(sq.pgse_F(stop * dt, seq.delta, seq.Delta))
+        st = timestep.physical_signal(p, asm, u, G * F * np.array([1.0, 0.0, 0.0]))
+        naive = asm.w @ u
+        d = abs(su - st)
+        if prev is not None:
+            assert prev / d > 3.5, (prev, d)
+        prev = d
+    assert abs(su - st) / abs(su) < 2e-2
+    assert abs(naive - su) / abs(su) > 0.1                 # the phase matters here
