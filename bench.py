@@ -257,6 +257,12 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=4,
                     help="systems timed one at a time in plain FP64 (0 = skip)")
     ap.add_argument("--progress", type=int, default=40, help="library progress line every k steps")
+    ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
+                    help="extra library option (set before the meshes are added, so DOF "
+                         "ordering options apply)")
+    ap.add_argument("--time-steps", type=int, default=0,
+                    help="stop every run after this many time steps (profiling aid; the "
+                         "value line is then not the full-echo workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
@@ -294,6 +300,8 @@ def main():
 
     sim = Simulator(0)
     sim.set_sequence(seq)
+    extra = {kv.split("=")[0]: float(kv.split("=")[1]) for kv in args.opt}
+    sim.set_options(**extra)
     t0 = time.perf_counter()
     pid_list = [sim.add_problem(prob) for prob, _ in items]
     t_asm = time.perf_counter() - t0
@@ -305,6 +313,10 @@ def main():
         opts["sys_tile"] = args.sys_tile
     if args.blocks_per_xcd:
         opts["blocks_per_xcd"] = args.blocks_per_xcd
+    if args.time_steps:
+        opts["n_steps"] = args.time_steps
+        opts["signal"] = 0
+    opts.update(extra)
     sim.set_options(**opts)
     pids = np.concatenate([np.full(len(sl), p, np.int32) for p, (_, sl) in zip(pid_list, items)])
     bs = np.concatenate([sl.b for _, sl in items])
@@ -386,7 +398,7 @@ def main():
               "rtol": rtol, "guess": args.guess,
               "extrap_order": int(sim.dmri_get_option("extrap_order")),
               "sys_tile": tiles if len(items) > 1 else tiles[0], "autotune": autotune,
-              "concurrency": args.concurrency,
+              "concurrency": args.concurrency, "extra_options": extra,
               "parallelism": "single GPU, systems batched per mesh"}
     out = {
         "metric": "DOF-steps/s", "value": value, "unit": "DOF-steps/s", "n_gpus": 1,
