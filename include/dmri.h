@@ -202,7 +202,13 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *  "precision"  0 = all FP64 (default), 1 = FP32 matrices and Krylov
  *               vectors with FP64 reductions and FP64 residual refinement
  *  "krylov"     0 = auto (CG on the Hermitian transformed operator, COCG on
- *               the complex-symmetric U-form), 1 = CG, 2 = COCG
+ *               the complex-symmetric U-form), 1 = CG, 2 = COCG, 3 = restarted
+ *               GMRES(m) with right Jacobi preconditioning (either form; a
+ *               cross-check and fallback for COCG, whose bilinear form can
+ *               break down on the U-form; precision 0 only, else
+ *               DMRI_E_UNSUPPORTED). Every system stops at the same
+ *               ||b - A x|| <= rtol ||b|| test
+ *  "gmres_m"    GMRES restart length m, 1..32 (default 30)
  *  "rtol"       per-step relative residual ||b - A x|| <= rtol ||b||
  *               (default 1e-10)
  *  "inner_rtol" FP32 inner solve reduction in mixed precision (1e-4)

@@ -164,6 +164,7 @@ struct Options {
     int tile_sched = 1;
     int pair_lanes = 1;
     int signal = 1;
+    int gmres_m = 30;
 };
 
 // Per-system Krylov state arrays of one solver level.
@@ -225,6 +226,10 @@ struct Workspace {
     DevBuf<int32_t> ctr, bad;
     DevBuf<uint32_t> barrier;  // count, generation, error flag of the persistent solver
     StateBufs outer, inner;
+    // GMRES(m): Krylov basis and per-system cycle state
+    DevBuf<double2> gm_basis, gm_H, gm_sn, gm_g, gm_y;
+    DevBuf<double> gm_partial, gm_hout, gm_cs, gm_hnorm;
+    DevBuf<int32_t> gm_cycle, gm_dim;
     int32_t* h_active[2] = {nullptr, nullptr};  // pinned
     size_t h_active_n = 0;
     ~Workspace() {
@@ -769,7 +774,10 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     // batches on small meshes); chunked launches win once a phase has enough
     // work to hide the per-launch cost.
     const bool small = static_cast<int64_t>(g.n_rows) * g.ld <= 131072;
-    bs.persist = (opts(h).persistent == 1 || (opts(h).persistent == 2 && small)) && g.ld <= 64;
+    if (opts(h).krylov == 3 && opts(h).precision != 0)
+        throw Error(DMRI_E_UNSUPPORTED, "GMRES (krylov = 3) runs in precision 0 (FP64)");
+    bs.persist = (opts(h).persistent == 1 || (opts(h).persistent == 2 && small)) && g.ld <= 64 &&
+                 opts(h).krylov != 3;
     // The grid barrier needs every block resident: otherwise chunked launches.
     if (bs.persist) {
         const bool fits = opts(h).precision != 0 ? persistent_fits<float>(bs.gp, bs.herm, n_cu)
@@ -1001,6 +1009,65 @@ void collect_result(dmri_ctx* h, const BatchSetup& bs, ProblemRec& P, StateBufs&
     res.t_signal = now_s() - t0;
 }
 
+// Restarted GMRES(m) on the systems active in s after the step start
+// (k_init has formed r = b - A x0, ||b||^2 and ||r||^2): cycles of up to m
+// Arnoldi steps with right Jacobi preconditioning, each system leaving its
+// cycle when |g_{j+1}| <= rtol ||b||; x += D^-1 V y after every cycle, the
+// true residual b - A x restarts the next. Returns the Arnoldi steps taken.
+int gmres_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<double>& Av, const double4* gq,
+               Coef lhs, double2* x, double2* r, double2* z, double2* w, const double2* b,
+               SolverState s, int64_t n_sys) {
+    hipStream_t st = lane(h).stream;
+    Workspace& W = lane(h).ws;
+    const Geom& g = bs.g;
+    const int m = std::max(1, std::min(opts(h).gmres_m, kGmMax));
+    const size_t ld = static_cast<size_t>(g.ld), nv = static_cast<size_t>(g.n_rows) * ld;
+    const Geom gg = make_geom(g.n_rows, static_cast<int32_t>(n_sys), g.S,
+                              std::min(64, opts(h).blocks_per_xcd), 0, 1);
+    W.gm_basis.alloc(static_cast<size_t>(m + 1) * nv);
+    W.gm_partial.alloc(static_cast<size_t>(std::max(gg.n_items, 8 * gg.n_tiles)) * gg.B * gg.S *
+                       kGmVals);
+    W.gm_hout.alloc(ld * kGmVals);
+    W.gm_H.alloc(ld * (kGmMax + 1) * kGmMax);
+    W.gm_cs.alloc(ld * kGmMax);
+    W.gm_sn.alloc(ld * kGmMax);
+    W.gm_g.alloc(ld * (kGmMax + 1));
+    W.gm_y.alloc(ld * kGmMax);
+    W.gm_hnorm.alloc(ld);
+    W.gm_cycle.alloc(ld);
+    W.gm_dim.alloc(ld);
+    GmresState gm{W.gm_partial.p, W.gm_hout.p, W.gm_H.p,    W.gm_cs.p,    W.gm_sn.p,
+                  W.gm_g.p,       W.gm_y.p,    W.gm_hnorm.p, W.gm_cycle.p, W.gm_dim.p};
+    const GmresBasis V{W.gm_basis.p, nv};
+    SolverState cyc = s;
+    cyc.active = gm.cycle;
+    const int32_t ns = static_cast<int32_t>(n_sys);
+    int steps = 0;
+    for (int cycle = 0;; ++cycle) {
+        gmres_cycle_start(st, g, gm, s);
+        if (poll_active(h, g, s) == 0) break;
+        if (cycle > 0) {  // true residual of the updated x
+            launch_spmv_dot<double>(st, g, Av, gq, lhs, bs.herm, x, w, cyc, bs.sc);
+            gmres_residual(st, gg, b, w, r, gm, cyc);
+        }
+        gmres_givens(st, ns, -1, m, cycle == 0, gm, s);
+        for (int col = 0; col < m; ++col) {
+            gmres_scale(st, gg, Av, gq, lhs, col == 0 ? r : w, V.base + col * nv, z, gm, cyc);
+            launch_spmv_dot<double>(st, g, Av, gq, lhs, bs.herm, z, w, cyc, bs.sc);
+            gmres_orthogonalize(st, gg, w, V, col + 1, col, ns, gm, cyc);
+            gmres_givens(st, ns, col, m, false, gm, s);
+            ++steps;
+            if ((col & 3) == 3 || col == m - 1) {
+                gmres_count(st, g, gm, s);
+                if (poll_active(h, g, s) == 0) break;
+            }
+        }
+        gmres_update(st, gg, Av, gq, lhs, x, V, ns, gm);
+        if (steps > opts(h).max_iter + m) break;
+    }
+    return steps;
+}
+
 // Solve one batch of systems on one problem in precision T throughout
 // (all-FP64, or all-FP32 for testing). b/q are device pointers ([n_sys],
 // [n_sys][3]); the signals go to d_sig ([n_sys] double2, device).
@@ -1017,11 +1084,13 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     if constexpr (sizeof(T) == 8) vecs = W.vec64; else vecs = W.vec32;
     History<V2> hs;
     hs.nh = history_len(h);
-    for (int i = 0; i < hs.nh + 4; ++i) vecs[i].alloc(2 * nv);
+    const bool gmres = opts(h).krylov == 3;
+    for (int i = 0; i < hs.nh + (gmres ? 5 : 4); ++i) vecs[i].alloc(2 * nv);
     for (int i = 0; i <= hs.nh; ++i) hs.ring.push_back(reinterpret_cast<V2*>(vecs[i].p));
     V2* r = reinterpret_cast<V2*>(vecs[hs.nh + 1].p);
     V2* p = reinterpret_cast<V2*>(vecs[hs.nh + 2].p);
     V2* q = reinterpret_cast<V2*>(vecs[hs.nh + 3].p);
+    V2* bv = gmres ? reinterpret_cast<V2*>(vecs[hs.nh + 4].p) : nullptr;  // b, for restarts
     W.outer.alloc(ld, g.n_tiles);
     W.outer.reset(ld, st);
     SolverState s = W.outer.view(static_cast<int32_t>(n_sys), opts(h).max_iter,
@@ -1046,10 +1115,16 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
         const int gm = prepare_guess<T>(h, g, dofs, tr, F, f, n, n_sys, hs, timer);
         timer.run(4, [&] {
             launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, bs.herm, gm, hs.u(0), hs.u(1), hs.x(), r,
-                           p, nullptr, nullptr, nullptr, s, bs.sc);
+                           p, nullptr, nullptr, bv, s, bs.sc);
         });
-        const int done = krylov_loop<T>(h, bs, Av, W.gq.p, lhs, hs.x(), r, p, q, s, timer,
-                                        last_iters - 2, opts(h).max_iter);
+        int done = 0;
+        if constexpr (sizeof(T) == 8) {
+            if (gmres)
+                done = gmres_loop(h, bs, Av, W.gq.p, lhs, hs.x(), r, p, q, bv, s, n_sys);
+        }
+        if (!gmres)
+            done = krylov_loop<T>(h, bs, Av, W.gq.p, lhs, hs.x(), r, p, q, s, timer,
+                                  last_iters - 2, opts(h).max_iter);
         last_iters = done;
         if constexpr (kF64) {
             if (hs.avail >= 2)
@@ -1683,7 +1758,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         };
         Options& o = h->opt;
         if (k == "precision") o.precision = as_int(0, 2);
-        else if (k == "krylov") o.krylov = as_int(0, 2);
+        else if (k == "krylov") o.krylov = as_int(0, 3);
         else if (k == "rtol") {
             if (!(v > 0 && v < 1)) throw Error(DMRI_E_INVALID, "rtol must be in (0, 1)");
             o.rtol = v;
@@ -1719,6 +1794,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "tile_sched") o.tile_sched = as_int(0, 1);
         else if (k == "pair_lanes") o.pair_lanes = as_int(0, 1);
         else if (k == "signal") o.signal = as_int(0, 1);
+        else if (k == "gmres_m") o.gmres_m = as_int(1, kGmMax);
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -1759,6 +1835,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "tile_sched") *value = o.tile_sched;
         else if (k == "pair_lanes") *value = o.pair_lanes;
         else if (k == "signal") *value = o.signal;
+        else if (k == "gmres_m") *value = o.gmres_m;
         else if (k == "tuned_sys_tile") *value = h->last_tune.sys_tile;
         else if (k == "tuned_blocks_per_xcd") *value = h->last_tune.blocks_per_xcd;
         else if (k == "tuned_persistent") *value = h->last_tune.persistent;
@@ -2125,6 +2202,8 @@ void run_noalloc(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, c
         throw Error(DMRI_E_UNSUPPORTED, "the no-allocation entry point runs precision 0 (FP64)");
     if (o.guess == 2)
         throw Error(DMRI_E_UNSUPPORTED, "the no-allocation entry point has no learned guess");
+    if (o.krylov == 3)
+        throw Error(DMRI_E_UNSUPPORTED, "the no-allocation entry point runs CG or COCG");
     if (h->model.rec_cap > 0)
         throw Error(DMRI_E_UNSUPPORTED, "sample recording allocates; not with this entry point");
     if (!P.pattern_up || !P.A64.ready || P.dt_up != h->dt || P.theta_up != h->theta)

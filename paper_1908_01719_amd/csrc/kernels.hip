@@ -1901,6 +1901,428 @@ __global__ void k_sys_params(int32_t n_sys, int32_t ld, const double* __restrict
     }
 }
 
+// ------------------------------------------------------------ GMRES(m)
+//
+// Restarted GMRES with right Jacobi preconditioning (A D^-1 y = r0,
+// x = x0 + D^-1 V y) for a batch of systems with per-system masks. The
+// Krylov basis v_0..v_m lives in `V` (batch-layout vectors); the Hessenberg
+// matrix, Givens rotations and the reduced right-hand side per system in
+// GmresState (FP64). Orthogonalization is classical Gram-Schmidt applied
+// twice (dot pass, subtract pass, again). Kernels of a cycle take a
+// SolverState whose `active` is the per-system "still in this cycle" flag.
+
+// v_j = w / hnorm, z = D^-1 v_j for the systems in the cycle.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_gm_scale(Geom g, const double* __restrict__ dK0,
+                                                     const double4* __restrict__ daux,
+                                                     const double4* __restrict__ gq, Coef lhs,
+                                                     const double2* __restrict__ w,
+                                                     double2* __restrict__ v,
+                                                     double2* __restrict__ z, GmresState gm,
+                                                     SolverState s) {
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part;
+        const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
+        const bool act = sys < s.n_sys && s.active[sys];
+        if (!act) continue;
+        const LaneCoef<double> lc(gq[sys], lhs);
+        const double inv = 1.0 / gm.hnorm[sys];
+        sweep_static<S>(g, part, j, [&](int first, int r1) {
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                bool ok;
+                const int row = slot_row<S>(first, u, r1, ok);
+                if (!ok) continue;
+                const size_t idx = tb + static_cast<size_t>(row) * S;
+                const double2 wv = w[idx];
+                const double2 vv = make_double2(wv.x * inv, wv.y * inv);
+                v[idx] = vv;
+                double dr, di;
+                diag_at(dK0, daux, row, lc, dr, di);
+                z[idx] = cdivT<double>(vv, dr, di);
+            }
+        });
+    }
+}
+
+// Block partials of v_i^H w for i = i0 .. i0+nb-1 (nb <= kGmBatch) into value
+// slots 2i, 2i+1 of gm.partial[(item * B + j) * S + lane][kGmVals].
+constexpr int kGmBatch = 8;
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_gm_dots(Geom g, const double2* __restrict__ w,
+                                                    GmresBasis V, int i0, int nb, GmresState gm,
+                                                    SolverState s) {
+    __shared__ double lds[kWaves * S];
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
+        const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
+        const bool act = sys < s.n_sys && s.active[sys];
+        if (!__syncthreads_or(act)) continue;
+        double a[2 * kGmBatch];
+#pragma unroll
+        for (int c = 0; c < 2 * kGmBatch; ++c) a[c] = 0.0;
+        if (act) {
+            sweep_static<S>(g, part, j, [&](int first, int r1) {
+                for (int u = 0; u < kUs; ++u) {
+                    bool ok;
+                    const int row = slot_row<S>(first, u, r1, ok);
+                    if (!ok) continue;
+                    const size_t idx = tb + static_cast<size_t>(row) * S;
+                    const double2 wv = w[idx];
+#pragma unroll
+                    for (int t = 0; t < kGmBatch; ++t) {
+                        if (t < nb) {
+                            const double2 vv = V.base[static_cast<size_t>(i0 + t) * V.stride + idx];
+                            a[2 * t] += vv.x * wv.x + vv.y * wv.y;
+                            a[2 * t + 1] += vv.x * wv.y - vv.y * wv.x;
+                        }
+                    }
+                }
+            });
+        }
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        double* dst = gm.partial + ((static_cast<size_t>(item) * g.B + j) * S) * kGmVals;
+#pragma unroll
+        for (int c = 0; c < 2 * kGmBatch; ++c) {
+            if (c >= 2 * nb) break;
+            double t = a[c];
+#pragma unroll
+            for (int off = S; off < 64; off <<= 1) t += __shfl_xor(t, off, 64);
+            if (lane < S) lds[wave * S + lane] = t;
+            __syncthreads();
+            if (threadIdx.x < S) {
+                double u = 0.0;
+#pragma unroll
+                for (int ww = 0; ww < kWaves; ++ww) u += lds[ww * S + threadIdx.x];
+                dst[static_cast<size_t>(threadIdx.x) * kGmVals + 2 * i0 + c] = u;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Sum one tile's partials in a fixed order: hout[sys][c] for c < nval.
+template <int S>
+__global__ __launch_bounds__(kFinBlock) void k_gm_fin(Geom g, int nval, GmresState gm,
+                                                      SolverState s) {
+    constexpr int G = kFinBlock / S;
+    __shared__ double lds[kFinBlock];
+    const int tile = static_cast<int>(blockIdx.x);
+    const int grp = threadIdx.x / S, sl = threadIdx.x % S;
+    const int sys = tile * S + sl;
+    const bool act = sys < s.n_sys && s.active[sys];
+    if (!__syncthreads_or(act)) return;
+    const int nb = g.n_parts * g.B;
+    const double* base = gm.partial + static_cast<size_t>(tile) * nb * S * kGmVals;
+    for (int c = 0; c < nval; ++c) {
+        double acc = 0.0;
+        for (int i = grp; i < nb; i += G)
+            acc += base[(static_cast<size_t>(i) * S + sl) * kGmVals + c];
+        lds[threadIdx.x] = acc;
+        __syncthreads();
+        if (threadIdx.x < S) {
+            double t = 0.0;
+            for (int gg = 0; gg < G; ++gg) t += lds[gg * S + sl];
+            if (act) gm.hout[static_cast<size_t>(sys) * kGmVals + c] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// w -= sum_{i<nv} c_i v_i with c_i from hout (the last dot pass); block
+// partials of ||w||^2 in value slot 0.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_gm_orth(Geom g, double2* __restrict__ w, GmresBasis V,
+                                                    int nv, GmresState gm, SolverState s) {
+    __shared__ double lds[kWaves * S];
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
+        const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
+        const bool act = sys < s.n_sys && s.active[sys];
+        if (!__syncthreads_or(act)) continue;
+        double a = 0.0;
+        if (act) {
+            const double* hs = gm.hout + static_cast<size_t>(sys) * kGmVals;
+            sweep_static<S>(g, part, j, [&](int first, int r1) {
+                for (int u = 0; u < kUs; ++u) {
+                    bool ok;
+                    const int row = slot_row<S>(first, u, r1, ok);
+                    if (!ok) continue;
+                    const size_t idx = tb + static_cast<size_t>(row) * S;
+                    double2 wv = w[idx];
+                    for (int i = 0; i < nv; ++i) {
+                        const double cr = hs[2 * i], ci = hs[2 * i + 1];
+                        const double2 vv = V.base[static_cast<size_t>(i) * V.stride + idx];
+                        wv.x -= cr * vv.x - ci * vv.y;
+                        wv.y -= cr * vv.y + ci * vv.x;
+                    }
+                    w[idx] = wv;
+                    a += wv.x * wv.x + wv.y * wv.y;
+                }
+            });
+        }
+#pragma unroll
+        for (int off = S; off < 64; off <<= 1) a += __shfl_xor(a, off, 64);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (lane < S) lds[wave * S + lane] = a;
+        __syncthreads();
+        if (threadIdx.x < S) {
+            double t = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < kWaves; ++ww) t += lds[ww * S + threadIdx.x];
+            gm.partial[((static_cast<size_t>(item) * g.B + j) * S + threadIdx.x) * kGmVals] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Per system in the cycle: column `col` of H gets the dot pass's
+// coefficients (pass 0 sets them, pass 1 adds the re-orthogonalization's).
+__global__ void k_gm_addcol(int32_t n_sys, int nv, int col, int pass, GmresState gm) {
+    const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sys >= n_sys || !gm.cycle[sys]) return;
+    const double* hs = gm.hout + static_cast<size_t>(sys) * kGmVals;
+    double2* H = gm.H + static_cast<size_t>(sys) * (kGmMax + 1) * kGmMax;
+    for (int i = 0; i < nv; ++i) {
+        double2& h = H[i * kGmMax + col];
+        const double2 c = make_double2(hs[2 * i], hs[2 * i + 1]);
+        h = pass == 0 ? c : make_double2(h.x + c.x, h.y + c.y);
+    }
+}
+
+// Per system in the cycle, with ||w||^2 in hout slot 0:
+//  col < 0 (cycle start, w = r): beta = ||r||, g = (beta, 0, ...); a system
+//    already within rtol leaves (active and cycle cleared);
+//  col >= 0: h_{col+1,col} = ||w||, earlier rotations applied to column col,
+//    new rotation, g updated; |g_{col+1}| is the residual norm. Convergence,
+//    a non-finite value or max_iter ends the system's solve; the last column
+//    (col + 1 = m) or a breakdown (||w|| = 0) ends only the cycle.
+__global__ void k_gm_givens(int32_t n_sys, int col, int m, int use_rr, GmresState gm,
+                            SolverState s) {
+    const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sys >= n_sys || !gm.cycle[sys]) return;
+    const double nrm2 = use_rr ? s.rr[sys] : gm.hout[static_cast<size_t>(sys) * kGmVals];
+    const double nrm = sqrt(fmax(nrm2, 0.0));
+    double2* g = gm.g + static_cast<size_t>(sys) * (kGmMax + 1);
+    gm.hnorm[sys] = nrm;
+    if (col < 0) {
+        g[0] = make_double2(nrm, 0.0);
+        gm.dim[sys] = 0;
+        s.rr[sys] = nrm2;
+        if (!isfinite(nrm2)) {
+            s.flags[sys] |= 2;
+            s.active[sys] = 0;
+            gm.cycle[sys] = 0;
+        } else if (nrm2 <= s.rtol2 * s.bb[sys]) {
+            s.active[sys] = 0;
+            gm.cycle[sys] = 0;
+        }
+        return;
+    }
+    double2* H = gm.H + static_cast<size_t>(sys) * (kGmMax + 1) * kGmMax;
+    double* cs = gm.cs + static_cast<size_t>(sys) * kGmMax;
+    double2* sn = gm.sn + static_cast<size_t>(sys) * kGmMax;
+    for (int i = 0; i < col; ++i) {
+        const double2 a = H[i * kGmMax + col], b = H[(i + 1) * kGmMax + col];
+        const double c = cs[i];
+        const double2 sv = sn[i];
+        // [a; b] -> [c a + s b; -conj(s) a + c b]
+        H[i * kGmMax + col] = make_double2(c * a.x + sv.x * b.x - sv.y * b.y,
+                                           c * a.y + sv.x * b.y + sv.y * b.x);
+        H[(i + 1) * kGmMax + col] = make_double2(-(sv.x * a.x + sv.y * a.y) + c * b.x,
+                                                 -(sv.x * a.y - sv.y * a.x) + c * b.y);
+    }
+    const double2 a = H[col * kGmMax + col];
+    const double an = sqrt(a.x * a.x + a.y * a.y);
+    const double nu = sqrt(an * an + nrm2);
+    double c;
+    double2 sv, r;
+    if (an == 0.0) {
+        c = 0.0;
+        sv = make_double2(1.0, 0.0);
+        r = make_double2(nrm, 0.0);
+    } else {
+        // b = nrm (real): s = (a/|a|) b / nu, r = (a/|a|) nu
+        c = an / nu;
+        const double2 ph = make_double2(a.x / an, a.y / an);
+        sv = make_double2(ph.x * nrm / nu, ph.y * nrm / nu);
+        r = make_double2(ph.x * nu, ph.y * nu);
+    }
+    cs[col] = c;
+    sn[col] = sv;
+    H[col * kGmMax + col] = r;
+    const double2 gj = g[col];
+    g[col] = make_double2(c * gj.x, c * gj.y);
+    g[col + 1] = make_double2(-(sv.x * gj.x + sv.y * gj.y), -(sv.x * gj.y - sv.y * gj.x));
+    gm.dim[sys] = col + 1;
+    const double2 gn = g[col + 1];
+    const double res2 = gn.x * gn.x + gn.y * gn.y;
+    s.rr[sys] = res2;
+    s.iters[sys] += 1;
+    s.iters_total[sys] += 1;
+    bool stop = false;
+    if (!isfinite(res2) || !isfinite(nrm)) {
+        s.flags[sys] |= 2;
+        stop = true;
+    } else if (res2 <= s.rtol2 * s.bb[sys]) {
+        stop = true;
+    } else if (s.iters[sys] >= s.max_iter) {
+        s.flags[sys] |= 1;
+        stop = true;
+    }
+    if (stop) s.active[sys] = 0;
+    if (stop || col + 1 >= m || nrm == 0.0) gm.cycle[sys] = 0;
+}
+
+// Per system whose last cycle has columns (dim > 0): y = R^-1 g.
+__global__ void k_gm_solve(int32_t n_sys, GmresState gm) {
+    const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sys >= n_sys) return;
+    const int k = gm.dim[sys];
+    const double2* H = gm.H + static_cast<size_t>(sys) * (kGmMax + 1) * kGmMax;
+    const double2* g = gm.g + static_cast<size_t>(sys) * (kGmMax + 1);
+    double2* y = gm.y + static_cast<size_t>(sys) * kGmMax;
+    for (int i = k - 1; i >= 0; --i) {
+        double2 t = g[i];
+        for (int l = i + 1; l < k; ++l) {
+            const double2 h = H[i * kGmMax + l];
+            t.x -= h.x * y[l].x - h.y * y[l].y;
+            t.y -= h.x * y[l].y + h.y * y[l].x;
+        }
+        y[i] = cdiv(t, H[i * kGmMax + i]);
+    }
+}
+
+// x += D^-1 sum_{i<dim} y_i v_i; dim is then cleared.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_gm_update(Geom g, const double* __restrict__ dK0,
+                                                      const double4* __restrict__ daux,
+                                                      const double4* __restrict__ gq, Coef lhs,
+                                                      double2* __restrict__ x, GmresBasis V,
+                                                      GmresState gm, int32_t n_sys) {
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part;
+        const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
+        if (sys >= n_sys) continue;
+        const int k = gm.dim[sys];
+        if (k <= 0) continue;
+        const LaneCoef<double> lc(gq[sys], lhs);
+        const double2* y = gm.y + static_cast<size_t>(sys) * kGmMax;
+        sweep_static<S>(g, part, j, [&](int first, int r1) {
+            for (int u = 0; u < kUs; ++u) {
+                bool ok;
+                const int row = slot_row<S>(first, u, r1, ok);
+                if (!ok) continue;
+                const size_t idx = tb + static_cast<size_t>(row) * S;
+                double2 t = make_double2(0.0, 0.0);
+                for (int i = 0; i < k; ++i) {
+                    const double2 vv = V.base[static_cast<size_t>(i) * V.stride + idx];
+                    t.x += y[i].x * vv.x - y[i].y * vv.y;
+                    t.y += y[i].x * vv.y + y[i].y * vv.x;
+                }
+                double dr, di;
+                diag_at(dK0, daux, row, lc, dr, di);
+                const double2 zt = cdivT<double>(t, dr, di);
+                const double2 xo = x[idx];
+                x[idx] = make_double2(xo.x + zt.x, xo.y + zt.y);
+            }
+        });
+    }
+}
+
+// r = b - q (q = A x) for the systems in the cycle; ||r||^2 partials in
+// value slot 0.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_gm_resid(Geom g, const double2* __restrict__ b,
+                                                     const double2* __restrict__ q,
+                                                     double2* __restrict__ r, GmresState gm,
+                                                     SolverState s) {
+    __shared__ double lds[kWaves * S];
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
+        const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
+        const bool act = sys < s.n_sys && s.active[sys];
+        if (!__syncthreads_or(act)) continue;
+        double a = 0.0;
+        if (act) {
+            sweep_static<S>(g, part, j, [&](int first, int r1) {
+#pragma unroll
+                for (int u = 0; u < kUs; ++u) {
+                    bool ok;
+                    const int row = slot_row<S>(first, u, r1, ok);
+                    if (!ok) continue;
+                    const size_t idx = tb + static_cast<size_t>(row) * S;
+                    const double2 bv = b[idx], qv = q[idx];
+                    const double2 rv = make_double2(bv.x - qv.x, bv.y - qv.y);
+                    r[idx] = rv;
+                    a += rv.x * rv.x + rv.y * rv.y;
+                }
+            });
+        }
+#pragma unroll
+        for (int off = S; off < 64; off <<= 1) a += __shfl_xor(a, off, 64);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (lane < S) lds[wave * S + lane] = a;
+        __syncthreads();
+        if (threadIdx.x < S) {
+            double t = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < kWaves; ++ww) t += lds[ww * S + threadIdx.x];
+            gm.partial[((static_cast<size_t>(item) * g.B + j) * S + threadIdx.x) * kGmVals] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// cycle = active (start of a cycle), dim = 0; n_active[tile] = systems in it.
+__global__ void k_gm_cycle_start(Geom g, GmresState gm, SolverState s) {
+    const int tile = blockIdx.x;
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int l = threadIdx.x; l < g.S; l += blockDim.x) {
+        const int sys = tile * g.S + l;
+        const int a = (sys < s.n_sys && s.active[sys]) ? 1 : 0;
+        if (sys < g.ld) {
+            gm.cycle[sys] = a;
+            gm.dim[sys] = 0;
+        }
+        if (a) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s.n_active[tile] = cnt;
+}
+
+// n_active[tile] = systems still in the cycle (polled by the host).
+__global__ void k_gm_count(Geom g, GmresState gm, SolverState s) {
+    const int tile = blockIdx.x;
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int l = threadIdx.x; l < g.S; l += blockDim.x) {
+        const int sys = tile * g.S + l;
+        if (sys < s.n_sys && gm.cycle[sys]) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s.n_active[tile] = cnt;
+}
+
 inline void check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -2238,6 +2660,83 @@ void launch_combine(hipStream_t st, const Geom& g, const ExtrapTerms<T>& t, V2<T
 template void launch_combine<double>(hipStream_t, const Geom&, const ExtrapTerms<double>&,
                                      double2*);
 template void launch_combine<float>(hipStream_t, const Geom&, const ExtrapTerms<float>&, float2*);
+
+// ------------------------------------------------------ GMRES launchers
+
+namespace {
+inline unsigned sys_blocks(int32_t n) { return static_cast<unsigned>((n + 255) / 256); }
+
+void gm_fin(hipStream_t st, const Geom& g, int nval, const GmresState& gm, const SolverState& s) {
+    const dim3 grid(static_cast<unsigned>(g.n_tiles)), block(kFinBlock);
+    DMRI_DISPATCH_S(g.S, { k_gm_fin<S><<<grid, block, 0, st>>>(g, nval, gm, s); });
+    check_launch("gm_fin");
+}
+}  // namespace
+
+void gmres_cycle_start(hipStream_t st, const Geom& g, const GmresState& gm, const SolverState& s) {
+    k_gm_cycle_start<<<dim3(static_cast<unsigned>(g.n_tiles)), dim3(256), 0, st>>>(g, gm, s);
+    check_launch("gm_cycle_start");
+}
+
+void gmres_count(hipStream_t st, const Geom& g, const GmresState& gm, const SolverState& s) {
+    k_gm_count<<<dim3(static_cast<unsigned>(g.n_tiles)), dim3(256), 0, st>>>(g, gm, s);
+    check_launch("gm_count");
+}
+
+void gmres_scale(hipStream_t st, const Geom& g, const MatView<double>& A, const double4* gq,
+                 Coef lhs, const double2* w, double2* v, double2* z, const GmresState& gm,
+                 const SolverState& cyc) {
+    const dim3 grid = grid_of(g), block(kBlock);
+    DMRI_DISPATCH_S(g.S, {
+        k_gm_scale<S><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, w, v, z, gm, cyc);
+    });
+    check_launch("gm_scale");
+}
+
+void gmres_orthogonalize(hipStream_t st, const Geom& g, double2* w, GmresBasis V, int nv, int col,
+                         int32_t n_sys, const GmresState& gm, const SolverState& cyc) {
+    const dim3 grid = grid_of(g), block(kBlock);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i0 = 0; i0 < nv; i0 += kGmBatch) {
+            const int nb = std::min(kGmBatch, nv - i0);
+            DMRI_DISPATCH_S(g.S, {
+                k_gm_dots<S><<<grid, block, 0, st>>>(g, w, V, i0, nb, gm, cyc);
+            });
+            check_launch("gm_dots");
+        }
+        gm_fin(st, g, 2 * nv, gm, cyc);
+        k_gm_addcol<<<sys_blocks(n_sys), 256, 0, st>>>(n_sys, nv, col, pass, gm);
+        check_launch("gm_addcol");
+        DMRI_DISPATCH_S(g.S, { k_gm_orth<S><<<grid, block, 0, st>>>(g, w, V, nv, gm, cyc); });
+        check_launch("gm_orth");
+    }
+    gm_fin(st, g, 1, gm, cyc);  // ||w||^2 after the second pass
+}
+
+void gmres_givens(hipStream_t st, int32_t n_sys, int col, int m, bool use_rr,
+                  const GmresState& gm, const SolverState& s) {
+    k_gm_givens<<<sys_blocks(n_sys), 256, 0, st>>>(n_sys, col, m, use_rr ? 1 : 0, gm, s);
+    check_launch("gm_givens");
+}
+
+void gmres_update(hipStream_t st, const Geom& g, const MatView<double>& A, const double4* gq,
+                  Coef lhs, double2* x, GmresBasis V, int32_t n_sys, const GmresState& gm) {
+    k_gm_solve<<<sys_blocks(n_sys), 256, 0, st>>>(n_sys, gm);
+    check_launch("gm_solve");
+    const dim3 grid = grid_of(g), block(kBlock);
+    DMRI_DISPATCH_S(g.S, {
+        k_gm_update<S><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, x, V, gm, n_sys);
+    });
+    check_launch("gm_update");
+}
+
+void gmres_residual(hipStream_t st, const Geom& g, const double2* b, const double2* q, double2* r,
+                    const GmresState& gm, const SolverState& cyc) {
+    const dim3 grid = grid_of(g), block(kBlock);
+    DMRI_DISPATCH_S(g.S, { k_gm_resid<S><<<grid, block, 0, st>>>(g, b, q, r, gm, cyc); });
+    check_launch("gm_resid");
+    gm_fin(st, g, 1, gm, cyc);
+}
 
 void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
     if (n <= 0) return;

@@ -229,6 +229,42 @@ void launch_krylov_persistent(hipStream_t st, const Geom& g, const MatView<T>& A
 template <typename T>
 bool persistent_fits(const Geom& g, bool herm, int n_cu);
 
+// ---- restarted GMRES(m) with right Jacobi preconditioning (FP64) ----
+constexpr int kGmMax = 32;                      // longest cycle (restart length)
+constexpr int kGmVals = 2 * (kGmMax + 1) + 2;   // reduction values per system
+// Krylov basis: v_i = base + i * stride (batch-layout FP64 vectors).
+struct GmresBasis {
+    double2* base;
+    size_t stride;
+};
+// Per-system state of the cycles (FP64), indexed by system < ld.
+struct GmresState {
+    double* partial;   // [items][B][S][kGmVals] block partials
+    double* hout;      // [ld][kGmVals] reduced values
+    double2* H;        // [ld][(kGmMax + 1) * kGmMax] Hessenberg, row-major
+    double* cs;        // [ld][kGmMax] Givens cosines
+    double2* sn;       // [ld][kGmMax] Givens sines
+    double2* g;        // [ld][kGmMax + 1] rotated right-hand side
+    double2* y;        // [ld][kGmMax] small solution
+    double* hnorm;     // [ld] last norm (beta, then h_{j+1,j})
+    int32_t* cycle;    // [ld] 1 while the system iterates in the current cycle
+    int32_t* dim;      // [ld] columns of the current cycle
+};
+// A cycle's kernels take a SolverState whose `active` points at gm.cycle.
+void gmres_cycle_start(hipStream_t st, const Geom& g, const GmresState& gm, const SolverState& s);
+void gmres_count(hipStream_t st, const Geom& g, const GmresState& gm, const SolverState& s);
+void gmres_scale(hipStream_t st, const Geom& g, const MatView<double>& A, const double4* gq,
+                 Coef lhs, const double2* w, double2* v, double2* z, const GmresState& gm,
+                 const SolverState& cyc);
+void gmres_orthogonalize(hipStream_t st, const Geom& g, double2* w, GmresBasis V, int nv, int col,
+                         int32_t n_sys, const GmresState& gm, const SolverState& cyc);
+void gmres_givens(hipStream_t st, int32_t n_sys, int col, int m, bool use_rr,
+                  const GmresState& gm, const SolverState& s);
+void gmres_update(hipStream_t st, const Geom& g, const MatView<double>& A, const double4* gq,
+                  Coef lhs, double2* x, GmresBasis V, int32_t n_sys, const GmresState& gm);
+void gmres_residual(hipStream_t st, const Geom& g, const double2* b, const double2* q, double2* r,
+                    const GmresState& gm, const SolverState& cyc);
+
 // Zero n int32 values (a kernel, so it may be captured in a graph).
 void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n);
 

@@ -782,3 +782,49 @@ def test_physical_signal_mid_sequence(Sim, stop):
                                                                              em.max()))
     assert e.max() < 1e-9
     assert em.max() < 1e-7
+
+
+# ---------------------------------------------------------------- GMRES(m)
+@pytest.mark.parametrize("m", [4, 30])
+def test_gmres_uform_matches_oracle(Sim, m):
+    # Restarted GMRES (krylov = 3) on the complex-symmetric U-form (walls),
+    # FP64 at rtol 1e-12: within 1e-9 of the oracle's exact solves, and of
+    # COCG; m = 4 forces many restarts.
+    prob = di.cylinder_box(n=9, half=6.0, r=4.0, kappa=2e-2, D_in=1.5e-3, periodic_mask=0,
+                           u0=(1.0, 0.6))
+    b = np.array([0.0, 700.0, 2200.0, 4000.0, 1500.0])
+    q = di.fibonacci_directions(5)
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12, krylov=3, gmres_m=m)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+        sim.set_options(krylov=0)
+        cocg, st_c = sim.dmri_run([pid] * len(b), b, q)
+        sim.set_options(krylov=3, precision=1)
+        with pytest.raises(Exception, match="DMRI_E_UNSUPPORTED"):
+            sim.dmri_run([pid], b[:1], q[:1])
+    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    e = rel_err(sig, ref, ref[0])
+    _say("GMRES(%d) U-form: err %.2e (COCG %.2e), iterations %d vs COCG %d"
+         % (m, e.max(), rel_err(cocg, ref, ref[0]).max(), st["total_iterations"],
+            st_c["total_iterations"]))
+    assert st["status"] == "DMRI_OK" and np.all(st["converged"] == 1)
+    assert e.max() < 1e-9
+    assert np.all(st["final_rel_res"] <= 1e-12 * 1.0001)
+
+
+def test_gmres_transformed_matches_oracle(Sim):
+    # GMRES on the Hermitian transformed operator, a ragged 13-system batch
+    # over 8-system tiles (systems leave their cycles at different times).
+    prob, b, q = _cyl_case()
+    ref = _cyl_ref()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12, krylov=3, gmres_m=12, sys_tile=8)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+    e = rel_err(sig, ref, ref[0])
+    _say("GMRES(12) transformed: err %.2e, %d iterations" % (e.max(), st["total_iterations"]))
+    assert st["status"] == "DMRI_OK"
+    assert e.max() < 1e-9
