@@ -40,6 +40,8 @@ __all__ = [
     "seeded_cells",
     "seeded_cells_78",
     "cylinder_box",
+    "conforming_cylinder_box",
+    "tensor",
     "slab_box",
     "free_box",
 ]
@@ -57,7 +59,7 @@ class Problem:
     tets: np.ndarray                # [n_tets, 4] int32, 0-based node ids
     tet_label: np.ndarray           # [n_tets] int32 in [0, n_comp)
     n_comp: int
-    D: np.ndarray                   # [n_comp] um^2/us
+    D: np.ndarray                   # [n_comp] um^2/us, or [n_comp, 3, 3] tensors
     T2: Optional[np.ndarray]        # [n_comp] us, None = infinite
     u0: Optional[np.ndarray]        # [n_comp], None = 1 everywhere
     kappa: float                    # um/us on every interface
@@ -263,6 +265,62 @@ def cylinder_box(n=36, half=6.0, r=5.0, D_in=D_FREE, D_out=D_FREE, kappa=1e-5,
                    None if u0 is None else np.asarray(u0, dtype=np.float64),
                    float(kappa), np.array([-half] * 3), np.array([half] * 3), periodic_mask,
                    n_cells=n, meta={"name": "cylinder_box", "n": n, "r": r, "mode": mode})
+
+
+def tensor(eig, angles=(0.0, 0.0, 0.0)):
+    """Symmetric positive definite 3x3 tensor with eigenvalues eig, rotated by
+    Euler angles (z, y, z) in radians."""
+    a, b, c = angles
+
+    def rz(t):
+        return np.array([[math.cos(t), -math.sin(t), 0.0], [math.sin(t), math.cos(t), 0.0],
+                         [0.0, 0.0, 1.0]])
+
+    def ry(t):
+        return np.array([[math.cos(t), 0.0, math.sin(t)], [0.0, 1.0, 0.0],
+                         [-math.sin(t), 0.0, math.cos(t)]])
+
+    R = rz(a) @ ry(b) @ rz(c)
+    return R @ np.diag(np.asarray(eig, dtype=np.float64)) @ R.T
+
+
+def conforming_cylinder_box(n=12, half=6.0, r=4.0, D_in=D_FREE, D_out=D_FREE, kappa=1e-3,
+                            jitter=0.15, seed=0, T2=None, u0=None, periodic_mask=7):
+    """A z-cylinder in a box on an unstructured, interface-conforming mesh.
+
+    Kuhn mesh of n^3 cubes; nodes within 0.4 h of the cylinder surface are
+    moved radially onto it (the membrane becomes a faceted cylinder made of
+    mesh faces, not a voxel staircase), then every other node strictly inside
+    the box is moved by a seeded uniform displacement of up to jitter * h per
+    coordinate (the mesh is no longer structured; box faces stay planar and
+    periodic faces still match). Labels by tet centroid (1 inside). D_in /
+    D_out: scalars or 3x3 tensors (then D has shape [2, 3, 3]).
+    """
+    xyz, tets, _ = kuhn_box_mesh([-half] * 3, [half] * 3, n)
+    h = 2.0 * half / n
+    rho = np.hypot(xyz[:, 0], xyz[:, 1])
+    on_face = np.any(np.isclose(np.abs(xyz), half, rtol=0, atol=1e-12), axis=1)
+    snap = (np.abs(rho - r) < 0.4 * h) & ~on_face & (rho > 0)
+    xyz = xyz.copy()
+    xyz[snap, 0] *= r / rho[snap]
+    xyz[snap, 1] *= r / rho[snap]
+    rng = np.random.default_rng(seed)
+    move = ~on_face & ~snap
+    xyz[move] += rng.uniform(-jitter * h, jitter * h, size=(int(move.sum()), 3))
+    v = xyz[tets]
+    vol = np.einsum("mi,mi->m", v[:, 1] - v[:, 0], np.cross(v[:, 2] - v[:, 0], v[:, 3] - v[:, 0]))
+    if np.any(vol <= 1e-6 * h ** 3):
+        raise ValueError("mesh perturbation inverted a tetrahedron")
+    shapes = [{"kind": "cylz", "c": (0.0, 0.0), "r": r}]
+    lab = label_tets(xyz, tets, shapes, mode="centroid")
+    Din, Dout = np.asarray(D_in, dtype=np.float64), np.asarray(D_out, dtype=np.float64)
+    D = np.stack([Dout, Din]) if Din.ndim == 2 else np.array([float(Dout), float(Din)])
+    return Problem(xyz, tets, lab, 2, D,
+                   None if T2 is None else np.asarray(T2, dtype=np.float64),
+                   None if u0 is None else np.asarray(u0, dtype=np.float64),
+                   float(kappa), np.array([-half] * 3), np.array([half] * 3), periodic_mask,
+                   n_cells=n, meta={"name": "conforming_cylinder_box", "n": n, "r": r,
+                                    "jitter": jitter, "seed": seed, "snapped": int(snap.sum())})
 
 
 def slab_box(n=16, half=5.0, split=0.0, D=(D_FREE, D_FREE), kappa=0.0, u0=None,

@@ -121,6 +121,28 @@ DMRI_API dmri_status dmri_add_problem(dmri_handle h,
                              uint32_t periodic_mask,
                              int32_t* problem_id);
 
+/* Same as dmri_add_problem with an intrinsic diffusion tensor per
+ * compartment (Sec. 2: D(x) symmetric positive definite; Sec. 3, "Diffusion
+ * coefficients and tensors": cell-based, piecewise constant per partition
+ * marker, i.e. per compartment here):
+ *   D_tensor [n_comp][6] = D_xx, D_yy, D_zz, D_xy, D_xz, D_yz (um^2/us)
+ * The stiffness takes grad phi_i . D_k grad phi_j, the transformed form's
+ * first-order term (D_k q) . grad and its mass term (gamma F)^2 q . D_k q
+ * (Appendix A, eq. trBlo); the U-form is unchanged apart from the
+ * stiffness. Validation as dmri_add_problem, plus DMRI_E_INVALID for a
+ * tensor that is not positive definite (leading principal minors). The
+ * exported M_D (dmri_export_operator) holds trace(D_k)/3 times the mass;
+ * dmri_apply_operator's c then multiplies the plain mass matrix. */
+DMRI_API dmri_status dmri_add_problem_tensor(dmri_handle h,
+                             int64_t n_nodes, const double* xyz,
+                             int64_t n_tets, const int32_t* tets,
+                             const int32_t* tet_label, int32_t n_comp,
+                             const double* D_tensor, const double* T2, const double* u0,
+                             double kappa,
+                             const double box_lo[3], const double box_hi[3],
+                             uint32_t periodic_mask,
+                             int32_t* problem_id);
+
 /* Number of DOFs (one per compartment touching a node, after periodic
  * identification) and stored nonzeros of problem `problem_id`. */
 DMRI_API dmri_status dmri_problem_info(dmri_handle h, int32_t problem_id,

@@ -55,7 +55,7 @@ class Assembly:
     dof_node: np.ndarray      # [n_dof] torus node of each DOF
     M: sp.csr_matrix          # mass
     S: sp.csr_matrix          # sum_k D_k stiffness
-    MD: sp.csr_matrix         # sum_k D_k mass
+    MD: sp.csr_matrix         # sum_k D_k mass (trace(D)/3 for tensors)
     B: tuple                  # (Bx, By, Bz) real skew
     R2: sp.csr_matrix         # sum_k (1/T2_k) mass
     IG: sp.csr_matrix         # kappa * interface jump face mass
@@ -66,6 +66,7 @@ class Assembly:
     interface_area: float     # |Gamma| (sum of interface face areas)
     n_torus_nodes: int
     tet_dof: np.ndarray = None  # [n_tets, 4] DOF of each vertex (its tet's compartment)
+    MDab: tuple = None        # int D_ab phi_i phi_j for ab = xx, yy, zz, xy, xz, yz
 
 
 def torus_nodes(xyz, box_lo, box_hi, periodic_mask, rel_tol=1e-9):
@@ -113,7 +114,14 @@ def assemble(prob, centre: Optional[np.ndarray] = None) -> Assembly:
     tets = np.asarray(prob.tets, dtype=np.int64)
     lab = np.asarray(prob.tet_label, dtype=np.int64)
     K = int(prob.n_comp)
+    # D: a scalar per compartment, or a symmetric 3x3 tensor per compartment
+    # (Sec. 2: D(x) symmetric positive definite; Sec. 3, "Diffusion
+    # coefficients and tensors": piecewise constant per partition marker).
     D = np.asarray(prob.D, dtype=np.float64)
+    if D.ndim == 1:
+        Dt = D[:, None, None] * np.eye(3)[None]
+    else:
+        Dt = D.reshape(K, 3, 3)
     invT2 = np.zeros(K) if prob.T2 is None else 1.0 / np.asarray(prob.T2, dtype=np.float64)
     u0c = np.ones(K) if prob.u0 is None else np.asarray(prob.u0, dtype=np.float64)
     if centre is None:
@@ -136,18 +144,25 @@ def assemble(prob, centre: Optional[np.ndarray] = None) -> Assembly:
     C = np.repeat(dof[:, None, :], 4, axis=1)       # col = trial index j
 
     Me = vol[:, None, None] * (1.0 + eye)[None] / 20.0
-    Se = vol[:, None, None] * np.einsum("mia,mja->mij", grads, grads)
-    Dk = D[lab]
+    De = Dt[lab]                                       # [m, 3, 3] tensor of each tet
+    # stiffness: int grad phi_i . D grad phi_j = |e| grad lambda_i^T D grad lambda_j
+    Se = vol[:, None, None] * np.einsum("mia,mab,mjb->mij", grads, De, grads)
     M = _coo(R, C, Me, n_dof)
-    S = _coo(R, C, Dk[:, None, None] * Se, n_dof)
-    MD = _coo(R, C, Dk[:, None, None] * Me, n_dof)
+    S = _coo(R, C, Se, n_dof)
+    # (gamma F)^2 g.Dg mass term: g.Dg = G^2 sum_ab q_a q_b D_ab, so six arrays
+    # int D_ab phi_i phi_j; for a scalar D they are D delta_ab times the mass.
+    pairs_ab = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+    MDab = tuple(_coo(R, C, De[:, a, b][:, None, None] * Me, n_dof) for a, b in pairs_ab)
+    MD = _coo(R, C, (np.trace(De, axis1=1, axis2=2) / 3.0)[:, None, None] * Me, n_dof)
     R2 = _coo(R, C, invT2[lab][:, None, None] * Me, n_dof)
     B = []
     J = []
     xs = xyz[tets] - np.asarray(centre)[None, None, :]   # [m, 4, 3]
     for a in range(3):
-        ga = grads[:, :, a]                           # d_a lambda_i  [m, 4]
-        Be = Dk[:, None, None] * vol[:, None, None] * (ga[:, None, :] - ga[:, :, None]) / 4.0
+        # first-order term (D g).grad with g = G q: int (phi_i d_b phi_j - phi_j
+        # d_b phi_i) (D q)_b = sum_a q_a [sum_b D_ba int (phi_i d_b phi_j - ...)]
+        gDa = np.einsum("mib,mb->mi", grads, De[:, :, a])   # sum_b D_ba d_b lambda_i
+        Be = vol[:, None, None] * (gDa[:, None, :] - gDa[:, :, None]) / 4.0
         B.append(_coo(R, C, Be, n_dof))
         xa = xs[:, :, a]
         ssum = xa.sum(axis=1)
@@ -203,6 +218,6 @@ def assemble(prob, centre: Optional[np.ndarray] = None) -> Assembly:
         IG = sp.csr_matrix((n_dof, n_dof))
 
     return Assembly(n_dof=n_dof, dof_comp=dof_comp, dof_node=dof_node, M=M, S=S, MD=MD,
-                    B=tuple(B), R2=R2, IG=IG, J=tuple(J), w=w, u0=u0c[dof_comp],
+                    B=tuple(B), R2=R2, MDab=MDab, IG=IG, J=tuple(J), w=w, u0=u0c[dof_comp],
                     comp_volume=comp_volume, interface_area=area_total,
                     n_torus_nodes=n_torus, tet_dof=dof)

@@ -143,12 +143,16 @@ def solve_transformed(asm: Assembly, seq, b: float, q, n_steps: Optional[int] = 
     base = (asm.S + asm.IG + asm.R2).tocsr()
     Mk = (asm.M / k).tocsr()
     qB = _qB(asm, qn).tocsr()
+    # g.Dg mass term for the direction q: sum_ab q_a q_b int D_ab phi_i phi_j
+    qq = (qn[0] ** 2, qn[1] ** 2, qn[2] ** 2, 2 * qn[0] * qn[1], 2 * qn[0] * qn[2],
+          2 * qn[1] * qn[2])
+    Mq = sum(c * m for c, m in zip(qq, asm.MDab)).tocsr()
 
     def L(Fv):
-        return base + (G * Fv) ** 2 * asm.MD + 1j * (G * Fv) * qB
+        return base + (G * Fv) ** 2 * Mq + 1j * (G * Fv) * qB
 
     def L_apply(Fv, v):
-        return base @ v + (G * Fv) ** 2 * (asm.MD @ v) + 1j * (G * Fv) * (qB @ v)
+        return base @ v + (G * Fv) ** 2 * (Mq @ v) + 1j * (G * Fv) * (qB @ v)
 
     cache = _LUCache(cache_size)
     u = asm.u0.astype(np.complex128)

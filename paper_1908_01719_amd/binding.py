@@ -27,7 +27,8 @@ STATUS_NAMES = {
 
 # Symbols declared in include/dmri.h (checked by the CPU test suite).
 EXPORTED = [
-    "dmri_create", "dmri_destroy", "dmri_last_error", "dmri_add_problem", "dmri_problem_info",
+    "dmri_create", "dmri_destroy", "dmri_last_error", "dmri_add_problem",
+    "dmri_add_problem_tensor", "dmri_problem_info",
     "dmri_export_operator", "dmri_set_sequence_pgse", "dmri_set_sequence",
     "dmri_set_sequence_table", "dmri_set_option", "dmri_get_option",
     "dmri_run", "dmri_run_device", "dmri_run_device_noalloc", "dmri_apply_operator",
@@ -89,6 +90,8 @@ def load(path: Optional[str] = None):
     lib.dmri_last_error.restype = C.c_char_p
     lib.dmri_add_problem.argtypes = [vp, i64, vp, i64, vp, vp, i32, vp, vp, vp, dbl, vp, vp,
                                      C.c_uint32, P(i32)]
+    lib.dmri_add_problem_tensor.argtypes = [vp, i64, vp, i64, vp, vp, i32, vp, vp, vp, dbl, vp,
+                                            vp, C.c_uint32, P(i32)]
     lib.dmri_problem_info.argtypes = [vp, i32, P(i64), P(i64)]
     lib.dmri_export_operator.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.dmri_set_sequence_pgse.argtypes = [vp, dbl, dbl, dbl, dbl]
@@ -178,8 +181,36 @@ class Simulator:
             int(periodic_mask), C.byref(pid)))
         return pid.value
 
+    def dmri_add_problem_tensor(self, xyz, tets, tet_label, n_comp, D_tensor, T2=None, u0=None,
+                                kappa=0.0, box_lo=(0, 0, 0), box_hi=(1, 1, 1),
+                                periodic_mask=7) -> int:
+        """D_tensor: [n_comp][6] (xx, yy, zz, xy, xz, yz) or [n_comp][3][3]."""
+        Dt = np.asarray(D_tensor, dtype=np.float64)
+        if Dt.ndim == 3:
+            Dt = np.stack([Dt[:, 0, 0], Dt[:, 1, 1], Dt[:, 2, 2], Dt[:, 0, 1], Dt[:, 0, 2],
+                           Dt[:, 1, 2]], axis=1)
+        Dt = _c(Dt.reshape(-1, 6), np.float64)
+        xyz = _c(xyz, np.float64).reshape(-1, 3)
+        tets = _c(tets, np.int32).reshape(-1, 4)
+        lab = _c(tet_label, np.int32).reshape(-1)
+        T2 = _c(T2, np.float64)
+        u0 = _c(u0, np.float64)
+        lo = _c(box_lo, np.float64)
+        hi = _c(box_hi, np.float64)
+        pid = C.c_int32(-1)
+        self._check(self.lib.dmri_add_problem_tensor(
+            self.h, xyz.shape[0], _ptr(xyz), tets.shape[0], _ptr(tets), _ptr(lab), int(n_comp),
+            _ptr(Dt), _ptr(T2), _ptr(u0), float(kappa), _ptr(lo), _ptr(hi),
+            int(periodic_mask), C.byref(pid)))
+        return pid.value
+
     def add_problem(self, prob) -> int:
-        """Add a dmri_inputs.Problem-like object (fields as in include/dmri.h)."""
+        """Add a dmri_inputs.Problem-like object (fields as in include/dmri.h);
+        a D of shape [n_comp, 3, 3] adds it with diffusion tensors."""
+        if np.asarray(prob.D).ndim == 3:
+            return self.dmri_add_problem_tensor(prob.xyz, prob.tets, prob.tet_label, prob.n_comp,
+                                                prob.D, prob.T2, prob.u0, prob.kappa,
+                                                prob.box_lo, prob.box_hi, prob.periodic_mask)
         return self.dmri_add_problem(prob.xyz, prob.tets, prob.tet_label, prob.n_comp, prob.D,
                                      prob.T2, prob.u0, prob.kappa, prob.box_lo, prob.box_hi,
                                      prob.periodic_mask)

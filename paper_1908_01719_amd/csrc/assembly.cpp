@@ -60,7 +60,7 @@ HostOperator assemble(const MeshInput& in) {
     // ---------------------------------------------------------------- checks
     if (in.n_nodes < 4 || in.n_tets < 1 || in.n_comp < 1)
         fail(DMRI_E_INVALID, "need n_nodes >= 4, n_tets >= 1, n_comp >= 1");
-    if (!in.xyz || !in.tets || !in.label || !in.D)
+    if (!in.xyz || !in.tets || !in.label || (!in.D && !in.Dt))
         fail(DMRI_E_INVALID, "xyz, tets, tet_label and D must not be NULL");
     if (in.n_nodes > (int64_t(1) << 31) - 1 || in.n_tets > (int64_t(1) << 31) / 4)
         fail(DMRI_E_INVALID, "mesh too large for 32-bit indices");
@@ -71,7 +71,19 @@ HostOperator assemble(const MeshInput& in) {
         if (!finite(in.lo[a]) || !finite(in.hi[a]) || !(in.lo[a] < in.hi[a]))
             fail(DMRI_E_INVALID, "box_lo < box_hi must hold on every axis");
     for (int32_t k = 0; k < in.n_comp; ++k) {
-        if (!finite(in.D[k]) || in.D[k] <= 0) fail(DMRI_E_INVALID, "D must be finite and > 0");
+        if (in.Dt) {
+            const double* t = in.Dt + 6 * k;
+            for (int c = 0; c < 6; ++c)
+                if (!finite(t[c])) fail(DMRI_E_INVALID, "diffusion tensors must be finite");
+            // positive definite: leading principal minors (Sylvester)
+            const double m1 = t[0], m2 = t[0] * t[1] - t[3] * t[3];
+            const double m3 = t[0] * (t[1] * t[2] - t[5] * t[5]) - t[3] * (t[3] * t[2] - t[5] * t[4]) +
+                              t[4] * (t[3] * t[5] - t[1] * t[4]);
+            if (!(m1 > 0) || !(m2 > 0) || !(m3 > 0))
+                fail(DMRI_E_INVALID, "diffusion tensors must be positive definite");
+        } else if (!finite(in.D[k]) || in.D[k] <= 0) {
+            fail(DMRI_E_INVALID, "D must be finite and > 0");
+        }
         if (in.T2 && (!finite(in.T2[k]) || in.T2[k] <= 0))
             fail(DMRI_E_INVALID, "T2 must be finite and > 0");
         if (in.u0 && !finite(in.u0[k])) fail(DMRI_E_INVALID, "u0 must be finite");
@@ -400,7 +412,24 @@ HostOperator assemble(const MeshInput& in) {
         g[0] = {-(g[1].x + g[2].x + g[3].x), -(g[1].y + g[2].y + g[3].y),
                 -(g[1].z + g[2].z + g[3].z)};
         const int32_t k = in.label[e];
-        const double Dk = in.D[k];
+        // D as a 3x3 matrix (a scalar times the identity without tensors)
+        double Dm[3][3];
+        if (in.Dt) {
+            const double* t = in.Dt + 6 * k;
+            Dm[0][0] = t[0]; Dm[1][1] = t[1]; Dm[2][2] = t[2];
+            Dm[0][1] = Dm[1][0] = t[3];
+            Dm[0][2] = Dm[2][0] = t[4];
+            Dm[1][2] = Dm[2][1] = t[5];
+        } else {
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) Dm[a][b] = a == b ? in.D[k] : 0.0;
+        }
+        const double Dk = in.Dt ? (Dm[0][0] + Dm[1][1] + Dm[2][2]) / 3.0 : in.D[k];  // trace/3
+        Vec3 Dg[4];  // D grad lambda_i
+        for (int i = 0; i < 4; ++i)
+            Dg[i] = {Dm[0][0] * g[i].x + Dm[0][1] * g[i].y + Dm[0][2] * g[i].z,
+                     Dm[1][0] * g[i].x + Dm[1][1] * g[i].y + Dm[1][2] * g[i].z,
+                     Dm[2][0] * g[i].x + Dm[2][1] * g[i].y + Dm[2][2] * g[i].z};
         const double r2 = in.T2 ? 1.0 / in.T2[k] : 0.0;
         op.comp_volume[k] += vol;
         double xs[4][3];
@@ -419,10 +448,14 @@ HostOperator assemble(const MeshInput& in) {
                 const double mass = vol * (i == j ? 2.0 : 1.0) / 20.0;
                 op.M[p] += mass;
                 op.MD[p] += Dk * mass;
-                op.R[p] += Dk * vol * dot(g[i], g[j]) + r2 * mass;
+                // grad phi_i . D grad phi_j
+                op.R[p] += vol * dot(g[i], Dg[j]) + r2 * mass;
+                const double Dgi[3] = {Dg[i].x, Dg[i].y, Dg[i].z};
+                const double Dgj[3] = {Dg[j].x, Dg[j].y, Dg[j].z};
                 for (int c = 0; c < 3; ++c) {
+                    // (phi_i (D q).grad phi_j - phi_j (D q).grad phi_i) per q_c
                     if (op.form == FORM_TRANSFORMED)
-                        op.V[c][p] += Dk * vol * (gj[c] - gi[c]) * 0.25;
+                        op.V[c][p] += vol * (Dgj[c] - Dgi[c]) * 0.25;
                     else
                         op.V[c][p] += vol * (i == j ? 2.0 : 1.0) / 120.0 *
                                       (xsum[c] + xs[i][c] + xs[j][c]);
@@ -447,8 +480,17 @@ HostOperator assemble(const MeshInput& in) {
     op.u0.resize(nD);
     op.dof_D.resize(nD);
     for (int64_t dd = 0; dd < nD; ++dd) {
-        op.u0[dd] = in.u0 ? in.u0[op.dof_comp[dd]] : 1.0;
-        op.dof_D[dd] = static_cast<float>(in.D[op.dof_comp[dd]]);
+        const int32_t k = op.dof_comp[dd];
+        op.u0[dd] = in.u0 ? in.u0[k] : 1.0;
+        op.dof_D[dd] = static_cast<float>(
+            in.Dt ? (in.Dt[6 * k] + in.Dt[6 * k + 1] + in.Dt[6 * k + 2]) / 3.0 : in.D[k]);
+    }
+    op.aniso = in.Dt != nullptr;
+    if (op.aniso) {
+        op.MT = op.M;
+        op.comp_tensor.assign(in.Dt, in.Dt + 6 * in.n_comp);
+    } else {
+        op.MT = op.MD;
     }
     op.volume = 0.0;
     for (double v : op.comp_volume) op.volume += v;

@@ -39,6 +39,9 @@ struct MeshInput {
     const int32_t* label = nullptr;
     int32_t n_comp = 0;
     const double* D = nullptr;
+    // Optional diffusion tensors per compartment, [n_comp][6] = xx, yy, zz,
+    // xy, xz, yz (symmetric positive definite); D is then ignored.
+    const double* Dt = nullptr;
     const double* T2 = nullptr;   // may be null
     const double* u0 = nullptr;   // may be null
     double kappa = 0.0;
@@ -61,6 +64,12 @@ struct HostOperator {
     int32_t n_comp = 0;
     std::vector<int32_t> row_ptr, col, diag_pos;
     std::vector<double> M, R, MD, V[3];
+    // Array of the (gamma F)^2 g.Dg mass term on the device: M_D for scalar
+    // diffusivities; for tensors the plain mass M, scaled per row by the
+    // row's compartment factor q.D_k q (mass entries never join compartments).
+    std::vector<double> MT;
+    bool aniso = false;
+    std::vector<double> comp_tensor;  // [n_comp][6] when aniso
     std::vector<double> w, u0;
     std::vector<int32_t> dof_comp, dof_node;
     std::vector<double> comp_volume;

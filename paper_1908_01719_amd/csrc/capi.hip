@@ -106,6 +106,9 @@ struct ProblemRec {
     DevBuf<float4> feat_geo;
     DevBuf<float2> feat_flags;
     bool feat_up = false;
+    // Anisotropic problems: compartment of each row, tensors [n_comp][6].
+    DevBuf<int32_t> row_comp;
+    DevBuf<double> comp_tensor;
     // Tetrahedra for the phase-weighted signal (uploaded on first use).
     DevBuf<int4> tet_dof, tet_node;
     DevBuf<double> node_xyz;
@@ -229,6 +232,7 @@ struct Workspace {
     // GMRES(m): Krylov basis and per-system cycle state
     DevBuf<double2> gm_basis, gm_H, gm_sn, gm_g, gm_y;
     DevBuf<double> gm_partial, gm_hout, gm_cs, gm_hnorm;
+    DevBuf<double> acomp;  // [n_comp][ld] q.D_k q per system (anisotropic problems)
     DevBuf<int32_t> gm_cycle, gm_dim;
     int32_t* h_active[2] = {nullptr, nullptr};  // pinned
     size_t h_active_n = 0;
@@ -444,7 +448,7 @@ void upload_matrix(const ProblemRec& P, double dt, double th, DevMatrix<T>& A, h
         if (k >= 0) {
             K0[d] = static_cast<T>(op.M[k] / dt + th * op.R[k]);
             Kr[d] = static_cast<T>(op.M[k] / dt - (1.0 - th) * op.R[k]);
-            a.x = static_cast<T>(op.MD[k]);
+            a.x = static_cast<T>(op.MT[k]);
             a.y = static_cast<T>(op.V[0][k]);
             a.z = static_cast<T>(op.V[1][k]);
             a.w = static_cast<T>(op.V[2][k]);
@@ -454,7 +458,7 @@ void upload_matrix(const ProblemRec& P, double dt, double th, DevMatrix<T>& A, h
     for (size_t i = 0; i < n; ++i) {
         const int64_t k = op.diag_pos[i];
         dK0[i] = static_cast<T>(op.M[k] / dt + th * op.R[k]);
-        daux[i].x = static_cast<T>(op.MD[k]);
+        daux[i].x = static_cast<T>(op.MT[k]);
         daux[i].y = static_cast<T>(op.V[0][k]);
         daux[i].z = static_cast<T>(op.V[1][k]);
         daux[i].w = static_cast<T>(op.V[2][k]);
@@ -476,6 +480,10 @@ void ensure_uploaded(dmri_ctx* h, ProblemRec& P, bool need32) {
         P.col.upload(P.pad_col.data(), P.pad_col.size(), st);
         P.w.upload(P.op.w.data(), P.op.w.size(), st);
         P.u0.upload(P.op.u0.data(), P.op.u0.size(), st);
+        if (P.op.aniso) {
+            P.row_comp.upload(P.op.dof_comp.data(), P.op.dof_comp.size(), st);
+            P.comp_tensor.upload(P.op.comp_tensor.data(), P.op.comp_tensor.size(), st);
+        }
         HIPCHK(hipStreamSynchronize(st));
         P.pattern_up = true;
     }
@@ -748,6 +756,7 @@ struct BatchSetup {
     bool herm;
     Scratch sc;
     GridBarrier bar;
+    int32_t ld_aniso = 0;  // row stride of the q.D_k q table (anisotropic problems)
 };
 
 BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
@@ -823,6 +832,20 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     const double intF2 = h->seq.int_F2;
     launch_sys_params(st, static_cast<int32_t>(n_sys), static_cast<int32_t>(ld_max), d_b, d_q,
                       intF2, W.gq.p, W.bad.p);
+    if (P.op.aniso) {
+        // q.D_k q per (compartment, system); layout [k][ld] of the vector layout
+        // in use (the paired inner tiles have ld_max >= ld columns: one table of
+        // ld_max per compartment serves both, systems index it directly).
+        W.acomp.alloc(static_cast<size_t>(P.op.n_comp) * ld_max);
+        launch_aniso_params(st, P.op.n_comp, static_cast<int32_t>(ld_max), W.gq.p,
+                            P.comp_tensor.p, W.acomp.p);
+        for (Geom* gg : {&bs.g, &bs.gi, &bs.gp}) {
+            gg->comp = P.row_comp.p;
+            gg->acomp = W.acomp.p;
+            gg->acomp_ld = static_cast<int32_t>(ld_max);
+        }
+        bs.ld_aniso = static_cast<int32_t>(ld_max);
+    }
     int32_t bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, W.bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1022,8 +1045,11 @@ int gmres_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<double>& Av, con
     const Geom& g = bs.g;
     const int m = std::max(1, std::min(opts(h).gmres_m, kGmMax));
     const size_t ld = static_cast<size_t>(g.ld), nv = static_cast<size_t>(g.n_rows) * ld;
-    const Geom gg = make_geom(g.n_rows, static_cast<int32_t>(n_sys), g.S,
-                              std::min(64, opts(h).blocks_per_xcd), 0, 1);
+    Geom gg = make_geom(g.n_rows, static_cast<int32_t>(n_sys), g.S,
+                        std::min(64, opts(h).blocks_per_xcd), 0, 1);
+    gg.comp = g.comp;
+    gg.acomp = g.acomp;
+    gg.acomp_ld = g.acomp_ld;
     W.gm_basis.alloc(static_cast<size_t>(m + 1) * nv);
     W.gm_partial.alloc(static_cast<size_t>(std::max(gg.n_items, 8 * gg.n_tiles)) * gg.B * gg.S *
                        kGmVals);
@@ -1623,10 +1649,15 @@ const char* dmri_last_error(dmri_handle h) {
     return h ? h->last_error.c_str() : g_create_error.c_str();
 }
 
-dmri_status dmri_add_problem(dmri_handle h, int64_t n_nodes, const double* xyz, int64_t n_tets,
+}  // extern "C"
+
+namespace dmri {
+namespace {
+
+dmri_status add_problem_impl(dmri_handle h, int64_t n_nodes, const double* xyz, int64_t n_tets,
                              const int32_t* tets, const int32_t* tet_label, int32_t n_comp,
-                             const double* D, const double* T2, const double* u0, double kappa,
-                             const double box_lo[3], const double box_hi[3],
+                             const double* D, const double* Dt, const double* T2, const double* u0,
+                             double kappa, const double box_lo[3], const double box_hi[3],
                              uint32_t periodic_mask, int32_t* problem_id) {
     if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
     return guarded(h, [&]() -> dmri_status {
@@ -1639,6 +1670,7 @@ dmri_status dmri_add_problem(dmri_handle h, int64_t n_nodes, const double* xyz, 
         in.label = tet_label;
         in.n_comp = n_comp;
         in.D = D;
+        in.Dt = Dt;
         in.T2 = T2;
         in.u0 = u0;
         in.kappa = kappa;
@@ -1655,6 +1687,32 @@ dmri_status dmri_add_problem(dmri_handle h, int64_t n_nodes, const double* xyz, 
         *problem_id = static_cast<int32_t>(h->problems.size() - 1);
         return DMRI_OK;
     });
+}
+
+}  // namespace
+}  // namespace dmri
+
+extern "C" {
+
+dmri_status dmri_add_problem(dmri_handle h, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                             const int32_t* tets, const int32_t* tet_label, int32_t n_comp,
+                             const double* D, const double* T2, const double* u0, double kappa,
+                             const double box_lo[3], const double box_hi[3],
+                             uint32_t periodic_mask, int32_t* problem_id) {
+    if (!D) return set_err(h, DMRI_E_INVALID, "D must not be NULL");
+    return add_problem_impl(h, n_nodes, xyz, n_tets, tets, tet_label, n_comp, D, nullptr, T2, u0,
+                            kappa, box_lo, box_hi, periodic_mask, problem_id);
+}
+
+dmri_status dmri_add_problem_tensor(dmri_handle h, int64_t n_nodes, const double* xyz,
+                                    int64_t n_tets, const int32_t* tets, const int32_t* tet_label,
+                                    int32_t n_comp, const double* D_tensor, const double* T2,
+                                    const double* u0, double kappa, const double box_lo[3],
+                                    const double box_hi[3], uint32_t periodic_mask,
+                                    int32_t* problem_id) {
+    if (!D_tensor) return set_err(h, DMRI_E_INVALID, "D_tensor must not be NULL");
+    return add_problem_impl(h, n_nodes, xyz, n_tets, tets, tet_label, n_comp, nullptr, D_tensor,
+                            T2, u0, kappa, box_lo, box_hi, periodic_mask, problem_id);
 }
 
 dmri_status dmri_problem_info(dmri_handle h, int32_t problem_id, int64_t* n_dof, int64_t* nnz) {
@@ -2165,10 +2223,12 @@ struct NoAllocBufs {
     // zero-filled at the start of a run: [zero_from, zero_to) in int32 words
     int32_t* zero_from;
     int32_t* zero_to;
+    double* acomp;  // q.D_k q per (compartment, system), anisotropic problems
     void carve(Arena& a, int n_vec, size_t nv, size_t ld, size_t n_tiles, size_t part_n,
-               size_t items_max) {
+               size_t items_max, size_t n_acomp) {
         for (int i = 0; i < n_vec; ++i) vec[i] = a.take<double2>(nv);
         gq = a.take<double4>(ld);
+        acomp = n_acomp ? a.take<double>(n_acomp) : nullptr;
         partial = a.take<double>(part_n);
         // The state below is contiguous so one fill clears it.
         rho = a.take<double2>(ld);
@@ -2238,8 +2298,9 @@ void run_noalloc(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, c
     const int n_vec = hs.nh + 4;
     Arena probe{nullptr, 0};
     NoAllocBufs B{};
+    const size_t n_acomp = P.op.aniso ? static_cast<size_t>(P.op.n_comp) * ld : 0;
     B.carve(probe, n_vec, nv, ld, static_cast<size_t>(g.n_tiles), part_n,
-            static_cast<size_t>(items_max));
+            static_cast<size_t>(items_max), n_acomp);
     if (probe.used > kNoAllocScratchBytes)
         throw Error(DMRI_E_INVALID,
                     "the run needs " + std::to_string(probe.used) + " bytes of scratch; the "
@@ -2247,7 +2308,7 @@ void run_noalloc(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, c
                     " (fewer systems or a smaller mesh)");
     Arena arena{static_cast<char*>(h->scratch_dev), kNoAllocScratchBytes};
     B.carve(arena, n_vec, nv, ld, static_cast<size_t>(g.n_tiles), part_n,
-            static_cast<size_t>(items_max));
+            static_cast<size_t>(items_max), n_acomp);
     // The array keeps the previous call's contents: clear the state, the
     // queue counters, the invalid-input flag and the grid barrier.
     launch_zero_i32(st, B.zero_from, B.zero_to - B.zero_from);
@@ -2255,6 +2316,15 @@ void run_noalloc(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, c
         throw Error(DMRI_E_STATE, "the U-form (walls) needs f on the time grid");
     launch_sys_params(st, static_cast<int32_t>(n_sys), static_cast<int32_t>(ld), d_b, d_q,
                       h->seq.int_F2, B.gq, B.bad);
+    if (P.op.aniso) {
+        launch_aniso_params(st, P.op.n_comp, static_cast<int32_t>(ld), B.gq, P.comp_tensor.p,
+                            B.acomp);
+        for (Geom* gg : {&g, &gp}) {
+            gg->comp = P.row_comp.p;
+            gg->acomp = B.acomp;
+            gg->acomp_ld = static_cast<int32_t>(ld);
+        }
+    }
     SolverState s{};
     s.rho = B.rho;
     s.alpha = B.alpha;

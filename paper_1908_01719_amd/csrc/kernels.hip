@@ -48,16 +48,28 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 }
 
 // Per-lane coefficients of one operator: c on M_D, (d0, d1, d2) on V.
+// For anisotropic problems the mass coefficient of a row is c times the
+// lane system's q.D_k q of the row's compartment k (cr(row)).
 template <typename T>
 struct LaneCoef {
     T c, d0, d1, d2;
-    __device__ __forceinline__ LaneCoef(const double4 gg, const Coef k) {
+    const int32_t* comp;
+    const double* acs;  // acomp + sys (stride ld)
+    int32_t ld;
+    __device__ __forceinline__ LaneCoef(const double4 gg, const Coef k, const Geom& g, int sys) {
         const double gf = gg.x * k.F;
         c = static_cast<T>(k.cm * gf * gf);
         const double s = k.cd * gf;
         d0 = static_cast<T>(s * gg.y);
         d1 = static_cast<T>(s * gg.z);
         d2 = static_cast<T>(s * gg.w);
+        comp = g.comp;
+        acs = g.acomp ? g.acomp + sys : nullptr;
+        ld = g.acomp_ld;
+    }
+    __device__ __forceinline__ T cr(int row) const {
+        return comp ? static_cast<T>(static_cast<double>(c) * acs[static_cast<size_t>(comp[row]) * ld])
+                    : c;
     }
 };
 
@@ -110,7 +122,7 @@ template <typename T>
 __device__ __forceinline__ void diag_at(const T* __restrict__ dK0, const V4<T>* __restrict__ daux,
                                         int row, const LaneCoef<T>& lc, T& dr, T& di) {
     const V4<T> a = daux[row];
-    dr = dK0[row] + lc.c * a.x;
+    dr = dK0[row] + lc.cr(row) * a.x;
     di = lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w;
 }
 
@@ -255,6 +267,7 @@ __device__ __forceinline__ void spmv_item(const Geom& g, int part, int j, int32_
     sweep_gather<S>(g, part, j, ctr, [&](int row) {
         if (!act) return;
         const int kb = row_ptr[row], ke = row_ptr[row + 1];
+        const T cm = lc.cr(row);
         T yr = 0, yi = 0;
         for (int k0 = kb; k0 < ke; k0 += kRowPad) {
             int jj[kRowPad];
@@ -266,7 +279,7 @@ __device__ __forceinline__ void spmv_item(const Geom& g, int part, int j, int32_
 #pragma unroll
             for (int u = 0; u < kRowPad; ++u) {
                 const V4<T> a = aux[k0 + u];
-                const T ar = K0[k0 + u] + lc.c * a.x;
+                const T ar = K0[k0 + u] + cm * a.x;
                 const T ai = lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w;
                 yr += ar * xv[u].x - ai * xv[u].y;
                 yi += ar * xv[u].y + ai * xv[u].x;
@@ -348,8 +361,8 @@ __device__ __forceinline__ void spmv16_rows(const int32_t* __restrict__ col,
                                             const T* __restrict__ K0,
                                             const V4<T>* __restrict__ aux,
                                             __amdgpu_buffer_rsrc_t pt, uint32_t lane_bytes,
-                                            const int (&kb)[G], const LaneCoef<T>& lc,
-                                            T (&yr)[G], T (&yi)[G]) {
+                                            const int (&kb)[G], const T (&cm)[G],
+                                            const LaneCoef<T>& lc, T (&yr)[G], T (&yi)[G]) {
     V2<T> xv[G][16];
 #pragma unroll
     for (int gi = 0; gi < G; ++gi) {
@@ -365,7 +378,7 @@ __device__ __forceinline__ void spmv16_rows(const int32_t* __restrict__ col,
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const V4<T> a = aux[kb[gi] + u];
-            const T ar = fma(lc.c, a.x, K0[kb[gi] + u]);
+            const T ar = fma(cm[gi], a.x, K0[kb[gi] + u]);
             const T ai = fma(lc.d2, a.w, fma(lc.d1, a.z, lc.d0 * a.y));
             cmac<T>(r, i, ar, ai, xv[gi][u]);
         }
@@ -380,7 +393,8 @@ __device__ __forceinline__ void spmv8_row(const int32_t* __restrict__ col,
                                           const T* __restrict__ K0,
                                           const V4<T>* __restrict__ aux,
                                           __amdgpu_buffer_rsrc_t pt, uint32_t lane_bytes,
-                                          int kb, int ke, const LaneCoef<T>& lc, T& yr, T& yi) {
+                                          int kb, int ke, T cm, const LaneCoef<T>& lc, T& yr,
+                                          T& yi) {
     yr = 0;
     yi = 0;
     for (int k0 = kb; k0 < ke; k0 += kRowPad) {
@@ -393,7 +407,7 @@ __device__ __forceinline__ void spmv8_row(const int32_t* __restrict__ col,
 #pragma unroll
         for (int u = 0; u < kRowPad; ++u) {
             const V4<T> a = aux[k0 + u];
-            const T ar = fma(lc.c, a.x, K0[k0 + u]);
+            const T ar = fma(cm, a.x, K0[k0 + u]);
             const T ai = fma(lc.d2, a.w, fma(lc.d1, a.z, lc.d0 * a.y));
             cmac<T>(yr, yi, ar, ai, xv[u]);
         }
@@ -439,13 +453,16 @@ __device__ __forceinline__ void spmv_item64(const Geom& g, int part, int j, int 
                 all16 &= (ke[gi] - kb[gi] == 16);
             }
             if (!any) break;
-            T yr[G], yi[G];
+            T yr[G], yi[G], cm[G];
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) cm[gi] = lc.cr(row[gi]);
             if (all16) {
-                spmv16_rows<T, G>(col, K0, aux, rs, lane_bytes, kb, lc, yr, yi);
+                spmv16_rows<T, G>(col, K0, aux, rs, lane_bytes, kb, cm, lc, yr, yi);
             } else {
 #pragma unroll
                 for (int gi = 0; gi < G; ++gi)
-                    spmv8_row<T>(col, K0, aux, rs, lane_bytes, kb[gi], ke[gi], lc, yr[gi], yi[gi]);
+                    spmv8_row<T>(col, K0, aux, rs, lane_bytes, kb[gi], ke[gi], cm[gi], lc, yr[gi],
+                                 yi[gi]);
             }
 #pragma unroll
             for (int gi = 0; gi < G; ++gi) {
@@ -475,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && s.active[sys];
         if (!__syncthreads_or(act)) continue;
-        const LaneCoef<T> lc(gq[sys], lhs);
+        const LaneCoef<T> lc(gq[sys], lhs, g, sys);
         double acc[2] = {0.0, 0.0};
         if constexpr (S == 64) {
             if (!g.queue && g.tile_bytes_ok) {
@@ -523,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lds(
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && s.active[sys];
         if (!__syncthreads_or(act)) continue;
-        const LaneCoef<T> lc(gq[sys], lhs);
+        const LaneCoef<T> lc(gq[sys], lhs, g, sys);
         double acc[2] = {0.0, 0.0};
         const int r0 = part * g.part_rows;
         const int r1 = min(g.n_rows, r0 + g.part_rows);
@@ -579,10 +596,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lds(
                         for (int gg = 0; gg < G; ++gg) {
                             const int base = kb[gg] + kRowPad * min(b, nb[gg] - 1);
                             const T mk = b < nb[gg] ? T(1) : T(0);
+                            const T cm = lc.cr(rw[gg]);
 #pragma unroll
                             for (int u = 0; u < kRowPad; ++u) {
                                 const V4<T> a = s_aux[base + u];
-                                const T ar = mk * (s_k0[base + u] + lc.c * a.x);
+                                const T ar = mk * (s_k0[base + u] + cm * a.x);
                                 const T ai = mk * (lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w);
                                 yr[gg] += ar * xv[gg][u].x - ai * xv[gg][u].y;
                                 yi[gg] += ar * xv[gg][u].y + ai * xv[gg][u].x;
@@ -603,9 +621,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lds(
                     const int row = c0 + lane_off + u * kWaves * R;
                     if (row >= c1) continue;
                     T yr = 0, yi = 0;
+                    const T cm = lc.cr(row);
                     for (int k = row_ptr[row]; k < row_ptr[row + 1]; ++k) {
                         const V4<T> a = aux[k];
-                        const T ar = K0[k] + lc.c * a.x;
+                        const T ar = K0[k] + cm * a.x;
                         const T ai = lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w;
                         const V2<T> xv = p[tb + static_cast<size_t>(col[k]) * S];
                         yr += ar * xv.x - ai * xv.y;
@@ -683,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && s.active[sys];
         if (!__syncthreads_or(act)) continue;
-        const LaneCoef<T> lc(gq[sys], lhs);
+        const LaneCoef<T> lc(gq[sys], lhs, g, sys);
         const double2 al = act ? s.alpha[sys] : make_double2(0.0, 0.0);
         double acc[3] = {0.0, 0.0, 0.0};
         if (act)
@@ -752,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(Geom g, const T* __restrict_
         const bool do_p = real && s.active[sys];
         const bool do_x = real && s.iters[sys] == k_iter;
         if (!(do_p || do_x)) continue;
-        const LaneCoef<T> lc(gq[sys], lhs);
+        const LaneCoef<T> lc(gq[sys], lhs, g, sys);
         const double2 be = do_p ? s.beta[sys] : make_double2(0.0, 0.0);
         const double2 al = s.alpha[sys];
         pupdate_item<T, S>(g, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y), do_p,
@@ -809,7 +828,8 @@ __device__ __forceinline__ void pair_block(const int32_t* __restrict__ col,
                                            const float4* __restrict__ aux,
                                            __amdgpu_buffer_rsrc_t rs, uint32_t lane_bytes, int k0,
                                            const LaneCoef<float>& c0, const LaneCoef<float>& c1,
-                                           float& yr0, float& yi0, float& yr1, float& yi1) {
+                                           float cm0, float cm1, float& yr0, float& yi0,
+                                           float& yr1, float& yi1) {
     float4 xv[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
@@ -820,8 +840,8 @@ __device__ __forceinline__ void pair_block(const int32_t* __restrict__ col,
     for (int u = 0; u < NB; ++u) {
         const float4 a = aux[k0 + u];
         const float k = K0[k0 + u];
-        const float ar0 = fma(c0.c, a.x, k), ai0 = fma(c0.d2, a.w, fma(c0.d1, a.z, c0.d0 * a.y));
-        const float ar1 = fma(c1.c, a.x, k), ai1 = fma(c1.d2, a.w, fma(c1.d1, a.z, c1.d0 * a.y));
+        const float ar0 = fma(cm0, a.x, k), ai0 = fma(c0.d2, a.w, fma(c0.d1, a.z, c0.d0 * a.y));
+        const float ar1 = fma(cm1, a.x, k), ai1 = fma(c1.d2, a.w, fma(c1.d1, a.z, c1.d0 * a.y));
         cmac<float>(yr0, yi0, ar0, ai0, lo2(xv[u]));
         cmac<float>(yr1, yi1, ar1, ai1, hi2(xv[u]));
     }
@@ -846,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(
         const bool a1 = s0 + 1 < s.n_sys && s.active[s0 + 1];
         const bool la = a0 || a1;
         if (!__syncthreads_or(la)) continue;
-        const LaneCoef<float> c0(gq[s0], lhs), c1(gq[s0 + 1], lhs);
+        const LaneCoef<float> c0(gq[s0], lhs, g, s0), c1(gq[s0 + 1], lhs, g, s0 + 1);
         double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
         const float4* pt = p + pair_tile(g, tile);
         float4* qt = q + pair_tile(g, tile);
@@ -866,13 +886,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(
                 // lines of its converged systems are not fetched.
                 if (!la) continue;
                 const int kb = row_ptr[row], ke = row_ptr[row + 1];
+                const float cm0 = c0.cr(row), cm1 = c1.cr(row);
                 float yr0 = 0.f, yi0 = 0.f, yr1 = 0.f, yi1 = 0.f;
                 if (ke - kb == 16) {
-                    pair_block<16>(col, K0, aux, rs, lane_bytes, kb, c0, c1, yr0, yi0, yr1, yi1);
+                    pair_block<16>(col, K0, aux, rs, lane_bytes, kb, c0, c1, cm0, cm1, yr0, yi0,
+                                   yr1, yi1);
                 } else {
                     for (int k0 = kb; k0 < ke; k0 += kRowPad)
-                        pair_block<kRowPad>(col, K0, aux, rs, lane_bytes, k0, c0, c1, yr0, yi0,
-                                            yr1, yi1);
+                        pair_block<kRowPad>(col, K0, aux, rs, lane_bytes, k0, c0, c1, cm0, cm1,
+                                            yr0, yi0, yr1, yi1);
                 }
                 const size_t o = static_cast<size_t>(row) * 64 + lane;
                 const float4 y = make_float4(yr0, yi0, yr1, yi1);
@@ -905,7 +927,7 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(
         const bool a0 = s0 < s.n_sys && s.active[s0];
         const bool a1 = s0 + 1 < s.n_sys && s.active[s0 + 1];
         if (!__syncthreads_or(a0 || a1)) continue;
-        const LaneCoef<float> c0(gq[s0], lhs), c1(gq[s0 + 1], lhs);
+        const LaneCoef<float> c0(gq[s0], lhs, g, s0), c1(gq[s0 + 1], lhs, g, s0 + 1);
         const double2 al0 = a0 ? s.alpha[s0] : make_double2(0.0, 0.0);
         const double2 al1 = a1 ? s.alpha[s0 + 1] : make_double2(0.0, 0.0);
         const float ar0 = static_cast<float>(al0.x), ai0 = static_cast<float>(al0.y);
@@ -970,7 +992,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_pair(
         const bool dx0 = re0 && s.iters[s0] == k_iter, dx1 = re1 && s.iters[s0 + 1] == k_iter;
         const bool do_p = dp0 || dp1, do_x = dx0 || dx1;
         if (!(do_p || do_x)) continue;
-        const LaneCoef<float> c0(gq[s0], lhs), c1(gq[s0 + 1], lhs);
+        const LaneCoef<float> c0(gq[s0], lhs, g, s0), c1(gq[s0 + 1], lhs, g, s0 + 1);
         const double2 b0 = dp0 ? s.beta[s0] : make_double2(0.0, 0.0);
         const double2 b1 = dp1 ? s.beta[s0 + 1] : make_double2(0.0, 0.0);
         const double2 al0 = dx0 ? s.alpha[s0] : make_double2(0.0, 0.0);
@@ -1050,7 +1072,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_start_pair(
         const int s0 = tile * kPairS + 2 * lane;
         const bool a0 = s0 < s.n_sys && outer_active[s0];
         const bool a1 = s0 + 1 < s.n_sys && outer_active[s0 + 1];
-        const LaneCoef<float> c0(gq[s0], lhs), c1(gq[s0 + 1], lhs);
+        const LaneCoef<float> c0(gq[s0], lhs, g, s0), c1(gq[s0 + 1], lhs, g, s0 + 1);
         // both systems of the lane sit next to each other in the 64-wide tile
         const size_t b64 = static_cast<size_t>(s0 / 64) * g.n_rows * 64 + (s0 % 64);
         double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
@@ -1239,7 +1261,7 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
             const size_t tb = vbase(g, tile, S, sys);
             const bool act = sh_act[sys] != 0;
             if (!__syncthreads_or(act)) continue;
-            const LaneCoef<T> lc(gq[sys], lhs);
+            const LaneCoef<T> lc(gq[sys], lhs, g, sys);
             double acc[2] = {0.0, 0.0};
             spmv_item<T, S, HERM>(g, part, j, nullptr, act, tb, lc, row_ptr, col, K0, aux, p, q,
                                   acc);
@@ -1261,7 +1283,7 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
             const size_t tb = vbase(g, tile, S, sys);
             const bool act = sh_act[sys] != 0;
             if (!__syncthreads_or(act)) continue;
-            const LaneCoef<T> lc(gq[sys], lhs);
+            const LaneCoef<T> lc(gq[sys], lhs, g, sys);
             const double2 al = sh_alpha[sys];
             double acc[3] = {0.0, 0.0, 0.0};
             if (act)
@@ -1309,7 +1331,7 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
             const int sys = tile * S + (threadIdx.x & 63) % S;
             const size_t tb = vbase(g, tile, S, sys);
             if (!sh_act[sys]) continue;
-            const LaneCoef<T> lc(gq[sys], lhs);
+            const LaneCoef<T> lc(gq[sys], lhs, g, sys);
             const double2 be = sh_beta[sys];
             pupdate_item<T, S>(g, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y),
                                true, T(0), T(0), false, dK0, daux, r, p, x);
@@ -1354,7 +1376,7 @@ __global__ __launch_bounds__(kBlock) void k_init(
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys;
         const double4 gg = gq[sys];
-        const LaneCoef<T> ll(gg, lhs), lr(gg, rhs);
+        const LaneCoef<T> ll(gg, lhs, g, sys), lr(gg, rhs, g, sys);
         // dx of the refinement passes may be stored in the paired layout.
         const size_t tbx = g.dx_pair ? static_cast<size_t>(sys / kPairS) * g.n_rows * kPairS +
                                            static_cast<size_t>(sys % kPairS)
@@ -1386,6 +1408,7 @@ __global__ __launch_bounds__(kBlock) void k_init(
         sweep_gather<S>(g, part, j, sc.ctr_init + item, [&](int row) {
             if (!act) return;
             const int kb = row_ptr[row], ke = row_ptr[row + 1];
+            const T cml = ll.cr(row), cmr = lr.cr(row);
             T br = 0, bi = 0, axr = 0, axi = 0;
             V2<T> x0_own = mk2<T>(0, 0);
             constexpr int kB = S == 64 ? kRowPad : kRowPad / 2;
@@ -1435,11 +1458,11 @@ __global__ __launch_bounds__(kBlock) void k_init(
                     if (GM == 1) xj[u] = mk2<T>(T(2) * uj[u].x - xj[u].x, T(2) * uj[u].y - xj[u].y);
                     const V4<T> a = aux[k];
                     const T vl = ll.d0 * a.y + ll.d1 * a.z + ll.d2 * a.w;
-                    const T al = K0[k] + ll.c * a.x;
+                    const T al = K0[k] + cml * a.x;
                     if (jj[u] == row) x0_own = xj[u];
                     if (kRhs) {
                         const T vr = lr.d0 * a.y + lr.d1 * a.z + lr.d2 * a.w;
-                        const T arr = Kr[k] + lr.c * a.x;
+                        const T arr = Kr[k] + cmr * a.x;
                         br += arr * uj[u].x - vr * uj[u].y;
                         bi += arr * uj[u].y + vr * uj[u].x;
                     }
@@ -1500,7 +1523,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_start(
         const int sys = tile * S + (threadIdx.x & 63) % S;
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && outer_active[sys];
-        const LaneCoef<float> lc(gq[sys], lhs);
+        const LaneCoef<float> lc(gq[sys], lhs, g, sys);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         sweep_static<S>(g, part, j, [&](int first, int r1) {
             int row[kUs];
@@ -1870,6 +1893,19 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, ExtrapTerms<T> t,
     }
 }
 
+__global__ void k_aniso_params(int32_t n_comp, int32_t ld, const double4* __restrict__ gq,
+                               const double* __restrict__ t, double* __restrict__ acomp) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ld) return;
+    const double4 g = gq[s];
+    const double x = g.y, y = g.z, z = g.w;
+    for (int k = 0; k < n_comp; ++k) {
+        const double* d = t + 6 * k;
+        acomp[static_cast<size_t>(k) * ld + s] = d[0] * x * x + d[1] * y * y + d[2] * z * z +
+                                                 2.0 * (d[3] * x * y + d[4] * x * z + d[5] * y * z);
+    }
+}
+
 __global__ void k_zero_i32(int32_t* __restrict__ p, int64_t n) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -1928,7 +1964,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_scale(Geom g, const double* __res
         const size_t tb = vbase(g, tile, S, sys);
         const bool act = sys < s.n_sys && s.active[sys];
         if (!act) continue;
-        const LaneCoef<double> lc(gq[sys], lhs);
+        const LaneCoef<double> lc(gq[sys], lhs, g, sys);
         const double inv = 1.0 / gm.hnorm[sys];
         sweep_static<S>(g, part, j, [&](int first, int r1) {
 #pragma unroll
@@ -2219,7 +2255,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_update(Geom g, const double* __re
         if (sys >= n_sys) continue;
         const int k = gm.dim[sys];
         if (k <= 0) continue;
-        const LaneCoef<double> lc(gq[sys], lhs);
+        const LaneCoef<double> lc(gq[sys], lhs, g, sys);
         const double2* y = gm.y + static_cast<size_t>(sys) * kGmMax;
         sweep_static<S>(g, part, j, [&](int first, int r1) {
             for (int u = 0; u < kUs; ++u) {
@@ -2736,6 +2772,13 @@ void gmres_residual(hipStream_t st, const Geom& g, const double2* b, const doubl
     DMRI_DISPATCH_S(g.S, { k_gm_resid<S><<<grid, block, 0, st>>>(g, b, q, r, gm, cyc); });
     check_launch("gm_resid");
     gm_fin(st, g, 1, gm, cyc);
+}
+
+void launch_aniso_params(hipStream_t st, int32_t n_comp, int32_t ld, const double4* gq,
+                         const double* tensors, double* acomp) {
+    k_aniso_params<<<dim3(static_cast<unsigned>((ld + 255) / 256)), dim3(256), 0, st>>>(
+        n_comp, ld, gq, tensors, acomp);
+    check_launch("aniso_params");
 }
 
 void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {

@@ -110,6 +110,13 @@ struct Geom {
     int32_t bpx;         // blocks per XCD asked for (B = min(bpx, chunks of a part))
     int32_t n_sched;     // 0: items cover tiles 0..n_tiles-1; else tiles sched[0..n_sched)
     int32_t sched[kMaxSched];
+    // Anisotropic problems (a diffusion tensor per compartment): the mass
+    // term's coefficient of a row is scaled by q.D_k q of the row's
+    // compartment k: comp[row] = k, acomp[k * ld + sys] = q_sys . D_k q_sys.
+    // Both null for scalar diffusivities (the factor is then in M_D itself).
+    const int32_t* comp;
+    const double* acomp;
+    int32_t acomp_ld;    // row stride of acomp (>= ld)
 };
 
 struct Scratch {
@@ -192,6 +199,12 @@ template <typename T>
 void launch_apply(hipStream_t st, const Geom& g, const MatView<T>& A, int which,
                   const double* c, const double3* d, const typename Vec2Of<T>::type* x,
                   typename Vec2Of<T>::type* y);
+
+// acomp[k * ld + s] = q_s . D_k q_s for every compartment k < n_comp and
+// system s < ld (q from gq; padding systems have q = x). tensors [n_comp][6]
+// = xx, yy, zz, xy, xz, yz.
+void launch_aniso_params(hipStream_t st, int32_t n_comp, int32_t ld, const double4* gq,
+                         const double* tensors, double* acomp);
 
 // Fill: x = u0 per DOF for every system < n_sys, 0 for padding.
 template <typename T>

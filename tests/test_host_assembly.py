@@ -63,6 +63,14 @@ CASES = {
     "slab_neumann": lambda: di.slab_box(n=6, half=3.0, split=0.4, D=(3e-3, 1e-3), kappa=1e-2,
                                         periodic_mask=0),
     "seeded_cells": lambda: di.seeded_cells(3, n_fixed=10)[0],
+    # unstructured interface-conforming mesh with a diffusion tensor per
+    # compartment (through dmri_add_problem_tensor), both forms
+    "conforming_tensor": lambda: di.conforming_cylinder_box(
+        n=7, half=6.0, r=4.0, D_in=di.tensor([3e-3, 1e-3, 2e-3], (0.3, 0.5, 0.2)),
+        D_out=di.tensor([2e-3, 2.5e-3, 1.5e-3], (1.0, -0.4, 0.7)), kappa=5e-3),
+    "conforming_tensor_neumann": lambda: di.conforming_cylinder_box(
+        n=7, half=6.0, r=4.0, D_in=di.tensor([3e-3, 1e-3, 2e-3], (0.3, 0.5, 0.2)),
+        D_out=di.tensor([2e-3, 2e-3, 2e-3]), periodic_mask=0, kappa=5e-3),
 }
 
 

@@ -312,9 +312,15 @@ def test_physical_signal_box_integrals(k):
     ones = np.ones(asm.n_dof)
     s1 = timestep.physical_signal(p, asm, ones, k)
     assert abs(s1 - Ix * Iy * Iz) < 1e-12 * L ** 3
-    xnode = p.xyz[asm.dof_node, 1] - c[1]                # linear field y - c_y
-    s2 = timestep.physical_signal(p, asm, xnode, k)
+    tn, nt = fem.torus_nodes(p.xyz, p.box_lo, p.box_hi, p.periodic_mask)
+    node_xyz = np.zeros((nt, 3))
+    node_xyz[tn] = p.xyz                                  # dof_node numbers these
+    ynode = node_xyz[asm.dof_node, 1] - c[1]              # linear field y - c_y
+    s2 = timestep.physical_signal(p, asm, ynode, k)
     assert abs(s2 - Ix * Jy * Iz) < 1e-12 * L ** 4
+    xnode = node_xyz[asm.dof_node, 0] - c[0]              # and x - c_x
+    s3 = timestep.physical_signal(p, asm, xnode, k)
+    assert abs(s3 - Jx * Iy * Iz) < 1e-12 * L ** 4
     if k == (0.0, 0.0, 0.0):
         u = np.random.default_rng(1).normal(size=asm.n_dof)
         assert timestep.physical_signal(p, asm, u, k) == pytest.approx(asm.w @ u, rel=1e-13)
@@ -344,3 +350,42 @@ def test_physical_signal_forms_agree_mid_sequence():
         prev = d
     assert abs(su - st) / abs(su) < 2e-2
     assert abs(naive - su) / abs(su) > 0.1                 # the phase matters here
+
+
+def test_free_diffusion_tensor_closed_form():
+    # one compartment with a tensor on the torus: u stays uniform, so the
+    # scalar recurrence holds with a = (q.D q) (G F)^2, and the signal tends
+    # to exp(-b q.D q) at second order
+    Dt = di.tensor([3e-3, 1e-3, 2e-3], (0.4, 0.9, -0.3))
+    q = np.array([0.6, 0.0, 0.8])
+    b = 1200.0
+    errs = []
+    for dt in (100.0, 50.0, 25.0):
+        prob = di.free_box(n=4, half=5.0)
+        prob.D = Dt[None]
+        seq = di.Sequence(10600.0, 13400.0, dt, 0.5)
+        asm = fem.assemble(prob)
+        s = timestep.signals(prob, seq, [b], [q], asm=asm, solver="splu")[0]
+        c = recurrence(float(q @ Dt @ q), b, seq)
+        assert s.real / 1000.0 == pytest.approx(c, rel=1e-11)
+        assert abs(s.imag) < 1e-11 * 1000.0
+        errs.append(c / math.exp(-b * q @ Dt @ q) - 1.0)
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.9 < r1 < 4.1 and 3.9 < r2 < 4.1
+
+
+def test_uform_slab_with_tensor_equals_scalar_Dxx():
+    # a slab invariant in y and z, gradient along x: only D_xx acts (the
+    # off-diagonal couplings integrate to zero over the periodic cross
+    # section), so the full-tensor U-form signal equals the scalar one
+    Dt = di.tensor([3e-3, 1e-3, 2e-3], (0.5, 0.7, 0.1))
+    seq = di.Sequence(2000.0, 4000.0, 200.0, 0.5)
+    ps = di.slab_box(n=12, half=4.0, split=10.0, D=(float(Dt[0, 0]),), cross=(1.0, 1),
+                     periodic_mask=0b110)
+    pt = di.slab_box(n=12, half=4.0, split=10.0, D=(float(Dt[0, 0]),), cross=(1.0, 1),
+                     periodic_mask=0b110)
+    pt.D = Dt[None]
+    for mask in (0b110,):
+        ss = timestep.signals(ps, seq, [2500.0], [[1, 0, 0]], form="uform", solver="splu")[0]
+        st = timestep.signals(pt, seq, [2500.0], [[1, 0, 0]], form="uform", solver="splu")[0]
+        assert abs(st - ss) < 1e-12 * abs(ss)

@@ -87,6 +87,22 @@ def test_noalloc_matches_device_entry_twice():
         with pytest.raises(Exception, match="DMRI_E_INVALID"):
             sim.dmri_run_device_noalloc(mixed, dev(b[:2], torch.float64), dev(q[:2], torch.float64),
                                         torch.zeros((2, 2), dtype=torch.float64, device="cuda"))
+        # a problem with diffusion tensors (per-compartment factor table in
+        # the array too)
+        pt = di.conforming_cylinder_box(
+            n=6, D_in=di.tensor([3e-3, 1e-3, 2e-3], (0.3, 0.5, 0.2)),
+            D_out=di.tensor([2e-3, 2e-3, 1e-3]), kappa=5e-3)
+        it = sim.add_problem(pt)
+        sel = np.array([1, 3, 4])
+        idt = dev(np.full(3, it, np.int32), torch.int32)
+        db, dq = dev(b[sel], torch.float64), dev(q[sel], torch.float64)
+        s_dev = torch.zeros((3, 2), dtype=torch.float64, device="cuda")
+        s_na = torch.zeros((3, 2), dtype=torch.float64, device="cuda")
+        sim.dmri_run_device(idt, db, dq, s_dev)
+        sim.dmri_run_device_noalloc(idt, db, dq, s_na)
+        torch.cuda.synchronize()
+        a, c = s_dev.cpu().numpy(), s_na.cpu().numpy()
+        assert _rel(c[:, 0] + 1j * c[:, 1], a[:, 0] + 1j * a[:, 1]).max() < 1e-12
         sim.set_options(precision=1)
         with pytest.raises(Exception, match="DMRI_E_UNSUPPORTED"):
             sim.dmri_run_device_noalloc(ids[:2], dev(b[:2], torch.float64),
