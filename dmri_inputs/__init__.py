@@ -44,6 +44,7 @@ __all__ = [
     "tensor",
     "slab_box",
     "free_box",
+    "nonmatching_faces",
 ]
 
 # Ordered vertex paths of the 6 Kuhn tetrahedra in a unit cube: start at the
@@ -321,6 +322,38 @@ def conforming_cylinder_box(n=12, half=6.0, r=4.0, D_in=D_FREE, D_out=D_FREE, ka
                    float(kappa), np.array([-half] * 3), np.array([half] * 3), periodic_mask,
                    n_cells=n, meta={"name": "conforming_cylinder_box", "n": n, "r": r,
                                     "jitter": jitter, "seed": seed, "snapped": int(snap.sum())})
+
+
+def nonmatching_faces(prob: Problem, axes=(0, 1, 2), amount=0.25, seed=0) -> Problem:
+    """Copy of prob whose faces x_a = hi_a (a in axes) no longer match the
+    opposite faces node for node: every node inside such a face (not on its
+    border) moves within the face plane by a seeded uniform displacement of
+    up to amount * h per tangential coordinate (h = the mean edge length of
+    the structured grid, box length / n_cells). For weak pseudo-periodic
+    faces (non-matching meshes); the strong identification rejects it."""
+    xyz = np.asarray(prob.xyz, dtype=np.float64).copy()
+    lo, hi = np.asarray(prob.box_lo, dtype=np.float64), np.asarray(prob.box_hi, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    for a in axes:
+        h = (hi[a] - lo[a]) / max(1, int(prob.n_cells))
+        others = [b for b in range(3) if b != a]
+        on = np.isclose(xyz[:, a], hi[a], rtol=0, atol=1e-12 * (hi[a] - lo[a]))
+        for b in others:
+            on &= ~np.isclose(xyz[:, b], lo[b], rtol=0, atol=1e-12) & \
+                ~np.isclose(xyz[:, b], hi[b], rtol=0, atol=1e-12)
+        for b in others:
+            xyz[on, b] += rng.uniform(-amount * h, amount * h, size=int(on.sum()))
+    v = xyz[np.asarray(prob.tets)]
+    vol = np.einsum("mi,mi->m", v[:, 1] - v[:, 0], np.cross(v[:, 2] - v[:, 0], v[:, 3] - v[:, 0]))
+    v0 = np.asarray(prob.xyz)[np.asarray(prob.tets)]
+    vol0 = np.einsum("mi,mi->m", v0[:, 1] - v0[:, 0],
+                     np.cross(v0[:, 2] - v0[:, 0], v0[:, 3] - v0[:, 0]))
+    if np.any(vol * vol0 <= 0) or np.any(np.abs(vol) < 1e-6 * np.abs(vol0)):
+        raise ValueError("face perturbation inverted a tetrahedron")
+    meta = dict(prob.meta)
+    meta.update({"nonmatching_axes": tuple(axes), "face_amount": amount, "face_seed": seed})
+    return Problem(xyz, prob.tets, prob.tet_label, prob.n_comp, prob.D, prob.T2, prob.u0,
+                   prob.kappa, lo, hi, prob.periodic_mask, n_cells=prob.n_cells, meta=meta)
 
 
 def slab_box(n=16, half=5.0, split=0.0, D=(D_FREE, D_FREE), kappa=0.0, u0=None,

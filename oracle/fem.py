@@ -14,6 +14,10 @@ Follows:
   face term kappa <[[u]], [[v]]>_Gamma (also in eq. loadvec).
 * Appendix B, eq. loadvec / eq. matrix_form: the untransformed U-form with
   the (g.x)-weighted mass matrix J, used for boxes with Neumann walls.
+* Appendix B, eq. bjump1/bjump2/weak_periodic, forms a* and L*: with bit 3
+  of periodic_mask set, the axes in bits 0-2 get weak pseudo-periodic faces
+  (artificial permeability, oracle/weakbc.py) on the U-form; their faces
+  are not identified.
 
 Reading of the first-order term. Substituting U = u exp(-i phi) and the
 test function exp(+i phi) v (phi = gamma F g.x) into the bilinear U weak
@@ -67,6 +71,11 @@ class Assembly:
     n_torus_nodes: int
     tet_dof: np.ndarray = None  # [n_tets, 4] DOF of each vertex (its tet's compartment)
     MDab: tuple = None        # int D_ab phi_i phi_j for ab = xx, yy, zz, xy, xz, yz
+    # weak pseudo-periodic faces (Appendix B): kappa_e face mass on the faces
+    # of the weak axes, and per axis (C_ms, C_sm, L_a) partner couplings
+    KB: sp.csr_matrix = None
+    weak: tuple = ()
+    kappa_e: float = 0.0      # max{D / h} before the weak_kappa scale
 
 
 def torus_nodes(xyz, box_lo, box_hi, periodic_mask, rel_tol=1e-9):
@@ -74,8 +83,11 @@ def torus_nodes(xyz, box_lo, box_hi, periodic_mask, rel_tol=1e-9):
 
     Returns (node -> torus id, number of torus nodes). Coordinates are
     rounded to a grid of rel_tol * box size; a node on the upper face of a
-    periodic axis is moved to the lower face before matching.
+    periodic axis is moved to the lower face before matching. Weak
+    pseudo-periodic faces (bit 3 of the mask) are never identified.
     """
+    if periodic_mask & 8:
+        periodic_mask = 0
     lo = np.asarray(box_lo, dtype=np.float64)
     hi = np.asarray(box_hi, dtype=np.float64)
     L = hi - lo
@@ -108,7 +120,7 @@ def _coo(rows, cols, vals, n):
     return sp.coo_matrix((vals.ravel(), (rows.ravel(), cols.ravel())), shape=(n, n)).tocsr()
 
 
-def assemble(prob, centre: Optional[np.ndarray] = None) -> Assembly:
+def assemble(prob, centre: Optional[np.ndarray] = None, weak_kappa: float = 1.0) -> Assembly:
     """Assemble every real operator of the method on the PUFEM DOF set."""
     xyz = np.asarray(prob.xyz, dtype=np.float64)
     tets = np.asarray(prob.tets, dtype=np.int64)
@@ -127,7 +139,10 @@ def assemble(prob, centre: Optional[np.ndarray] = None) -> Assembly:
     if centre is None:
         centre = 0.5 * (np.asarray(prob.box_lo) + np.asarray(prob.box_hi))
 
-    tnode, n_torus = torus_nodes(xyz, prob.box_lo, prob.box_hi, prob.periodic_mask)
+    pmask = int(prob.periodic_mask)
+    weak_axes = [a for a in range(3) if pmask & 8 and pmask >> a & 1]
+    # weakly periodic axes are not identified (the U-form on the open box)
+    tnode, n_torus = torus_nodes(xyz, prob.box_lo, prob.box_hi, pmask)
     tt = tnode[tets]                                # [m, 4] torus nodes
     # PUFEM DOF (k, torus node) exists iff the node touches a tet of label k.
     key = lab[:, None] * n_torus + tt               # [m, 4]
@@ -217,7 +232,25 @@ def assemble(prob, centre: Optional[np.ndarray] = None) -> Assembly:
     else:
         IG = sp.csr_matrix((n_dof, n_dof))
 
+    KB = None
+    weak = ()
+    ke0 = 0.0
+    if weak_axes:
+        from . import weakbc
+        Dmax = np.array([np.linalg.eigvalsh(Dt[k])[-1] for k in range(K)])
+        ke0 = weakbc.kappa_e(prob, Dmax[lab], weak_axes)
+        ke = weak_kappa * ke0
+        KB = sp.csr_matrix((n_dof, n_dof))
+        wl = []
+        for a in weak_axes:
+            La = float(prob.box_hi[a] - prob.box_lo[a])
+            Cms, Csm, Kf = weakbc.coupling(prob, dof, a, ke, La)
+            KB = KB + Kf
+            wl.append((a, Cms, Csm, La))
+        weak = tuple(wl)
+
     return Assembly(n_dof=n_dof, dof_comp=dof_comp, dof_node=dof_node, M=M, S=S, MD=MD,
                     B=tuple(B), R2=R2, MDab=MDab, IG=IG, J=tuple(J), w=w, u0=u0c[dof_comp],
                     comp_volume=comp_volume, interface_area=area_total,
-                    n_torus_nodes=n_torus, tet_dof=dof)
+                    n_torus_nodes=n_torus, tet_dof=dof, KB=KB, weak=weak,
+                    kappa_e=ke0)

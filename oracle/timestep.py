@@ -187,11 +187,23 @@ def solve_uform(asm: Assembly, seq, b: float, q, n_steps: Optional[int] = None,
     base = (asm.S + asm.IG + asm.R2).tocsr()
     Mk = (asm.M / k).tocsr()
     qJ = _qJ(asm, qn).tocsr()
+    # weak pseudo-periodic faces (Appendix B, a* and L*): theta kappa_e face
+    # mass on the left, the lagged partner with the phase of t^n on the right
+    weak = asm.weak if asm.weak else ()
+    if weak:
+        if abs(th - 0.5) > 1e-12:
+            raise ValueError("the weak pseudo-periodic scheme is the Crank-Nicolson one")
+        Mk = (Mk + th * asm.KB).tocsr()
+        Fg = [prof.F(v * k) for v in range(N_all + 1)]
     cache = _LUCache(cache_size)
     U = asm.u0.astype(np.complex128)
     for n in range(1, N + 1):
         f_prev, fn = lim[n - 1]
-        rhs = Mk @ U - (1.0 - th) * (base @ U + 1j * (G * f_prev) * (qJ @ U))
+        rhs = (Mk @ U - (th * asm.KB @ U if weak else 0.0)
+               - (1.0 - th) * (base @ U + 1j * (G * f_prev) * (qJ @ U)))
+        for a, Cms, Csm, La in weak:
+            ph = G * Fg[n] * qn[a] * La          # theta_ms = gamma g.(x_s - x_m) F(t^n)
+            rhs = rhs + (1.0 - th) * (np.exp(1j * ph) * (Cms @ U) + np.exp(-1j * ph) * (Csm @ U))
         if solver == "dense":
             U = np.linalg.solve((Mk + th * (base + 1j * (G * fn) * qJ)).toarray(), rhs)
         elif solver == "krylov":
@@ -212,7 +224,8 @@ def signals(prob, seq, b, q, form: str = "auto", asm: Optional[Assembly] = None,
     if asm is None:
         asm = assemble(prob)
     if form == "auto":
-        form = "uform" if int(prob.periodic_mask) == 0 else "transformed"
+        pm = int(prob.periodic_mask)
+        form = "uform" if (pm & 7) == 0 or (pm & 8) else "transformed"
     fn = solve_transformed if form == "transformed" else solve_uform
     b = np.atleast_1d(np.asarray(b, dtype=np.float64))
     q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
