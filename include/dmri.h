@@ -103,13 +103,23 @@ DMRI_API const char* dmri_last_error(dmri_handle h);
  *   periodic_mask  7 = periodic along x, y and z: pseudo-periodic
  *              conditions imposed strongly (Appendix A); opposite faces must
  *              match node for node. 0 = homogeneous Neumann walls (U-form,
- *              Appendix B). Other values: DMRI_E_UNSUPPORTED.
+ *              Appendix B). 8 + axes (9..15, bit a = axis a): pseudo-periodic
+ *              conditions imposed weakly on those axes by an artificial
+ *              permeability (Appendix B, eq. bjump1, eq. bjump2,
+ *              eq. weak_periodic, forms a* and L*), U-form, other axes
+ *              Neumann walls. Opposite faces need not match: the coupling
+ *              integrals are exact over the overlaps of face triangles.
+ *              kappa_e = max{D / h}, the largest lambda_max(D_k) / h_e over
+ *              the tetrahedra with a face on a weak face (h_e the longest
+ *              edge), times option "weak_kappa"; runs need theta = 1/2.
+ *              Other values: DMRI_E_UNSUPPORTED.
  * Interior interfaces are found from the labels: a face shared by two
  * tetrahedra with different labels carries the kappa jump term.
  * Validation (DMRI_E_INVALID): non-finite values, D <= 0, T2 <= 0,
  * kappa < 0, a label or node index out of range, a degenerate tetrahedron
  * (|volume| < 1e-12 h^3 with h the mean edge length), a periodic face that
- * does not match its opposite face.
+ * does not match its opposite face, a weakly periodic box face not fully
+ * covered by mesh faces.
  * On success *problem_id receives the new id (0, 1, ...). */
 DMRI_API dmri_status dmri_add_problem(dmri_handle h,
                              int64_t n_nodes, const double* xyz,
@@ -164,6 +174,27 @@ DMRI_API dmri_status dmri_export_operator(dmri_handle h, int32_t problem_id,
                                  int32_t* row_ptr, int32_t* col, double* vals,
                                  double* w, double* u0,
                                  int32_t* dof_comp, int32_t* dof_node);
+
+/* Weak pseudo-periodic faces of a problem (periodic_mask 9..15; host
+ * data). *n_slots receives the number of DOFs on a weak face, *n_entries
+ * the number of coupling entries, *kappa_e the artificial permeability
+ * (before the "weak_kappa" scale); both are 0 for other problems. Arrays
+ * (each may be NULL):
+ *   rows [n_slots]       DOF of each slot, ascending
+ *   ptr  [n_slots + 1]   entries of slot s: ptr[s] .. ptr[s+1]
+ *   col, code, val [n_entries]: partner DOF, code and
+ *        kappa_e int_{face} phi_row(x) phi_col(x +- L_a e_a) dx;
+ *        code a in 0..2: the row lies on the face x_a = lo_a and the
+ *        partner term carries e^{+i G F q_a L_a}; code 3 + a: the row lies
+ *        on x_a = hi_a, phase e^{-i G F q_a L_a} (Appendix B, theta_ms =
+ *        -theta_sm = gamma g.(x_s - x_m) F)
+ *   face_mass [nnz]      kappa_e <phi_i, phi_j> over the weak faces on the
+ *        CSR pattern of dmri_export_operator (added with theta to the
+ *        left operator only). */
+DMRI_API dmri_status dmri_export_weak(dmri_handle h, int32_t problem_id, int64_t* n_slots,
+                             int64_t* n_entries, double* kappa_e, int32_t* rows,
+                             int32_t* ptr, int32_t* col, int32_t* code, double* val,
+                             double* face_mass);
 
 /* PGSE sequence (Sec. 2, eq. pgse) with pulse length delta and pulse
  * spacing Delta (us), fixed time step dt (us) and theta in [1/2, 1]
@@ -231,6 +262,10 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *               DMRI_E_UNSUPPORTED). Every system stops at the same
  *               ||b - A x|| <= rtol ||b|| test
  *  "gmres_m"    GMRES restart length m, 1..32 (default 30)
+ *  "weak_kappa" scale of kappa_e on weak pseudo-periodic faces, (0, 1e6]
+ *               (default 1: the paper's max{D / h}). Larger values couple
+ *               the faces more tightly and need a smaller dt (the partner
+ *               term is lagged by one step).
  *  "rtol"       per-step relative residual ||b - A x|| <= rtol ||b||
  *               (default 1e-10)
  *  "inner_rtol" FP32 inner solve reduction in mixed precision (1e-4)
@@ -422,7 +457,8 @@ DMRI_API dmri_status dmri_run_device(dmri_handle h, void* hip_stream, int64_t n_
  * fill kernels. The caller still passes the inputs and the output.
  * Limits: 1..64 pairs, all on one problem; precision 0 (FP64) with the
  * persistent Krylov kernel (one launch per step); guess 0 or 1; no sample
- * recording. The problem's operators must already be on the device for the
+ * recording; no weak pseudo-periodic faces (DMRI_E_UNSUPPORTED). The
+ * problem's operators must already be on the device for the
  * current sequence (any earlier dmri_run / dmri_run_device of the problem
  * uploads them), else DMRI_E_STATE. A run that needs more scratch than the
  * array holds (n_dof x padded systems x (history + 4) x 16 bytes plus
@@ -445,7 +481,9 @@ DMRI_API dmri_status dmri_run_device_noalloc(dmri_handle h, void* hip_stream, in
  * theta R when which = 0 (left side) or M/dt - (1-theta) R when which = 1
  * (right side, without the sign flip of the time-dependent parts: the
  * coefficients are taken as given). x, y: [n_dof][n_sys][2] doubles;
- * c [n_sys], d [n_sys][3]. Uses the precision of option "precision". */
+ * c [n_sys], d [n_sys][3]. Uses the precision of option "precision". With
+ * weak pseudo-periodic faces the left Base also holds theta times the
+ * scaled face mass (dmri_export_weak); the partner term is not applied. */
 DMRI_API dmri_status dmri_apply_operator(dmri_handle h, int32_t problem_id, int32_t which,
                                 int64_t n_sys, const double* c, const double* d,
                                 const double* x, double* y);

@@ -29,7 +29,7 @@ STATUS_NAMES = {
 EXPORTED = [
     "dmri_create", "dmri_destroy", "dmri_last_error", "dmri_add_problem",
     "dmri_add_problem_tensor", "dmri_problem_info",
-    "dmri_export_operator", "dmri_set_sequence_pgse", "dmri_set_sequence",
+    "dmri_export_operator", "dmri_export_weak", "dmri_set_sequence_pgse", "dmri_set_sequence",
     "dmri_set_sequence_table", "dmri_set_option", "dmri_get_option",
     "dmri_run", "dmri_run_device", "dmri_run_device_noalloc", "dmri_apply_operator",
     "dmri_guess_set_params", "dmri_guess_get_params", "dmri_load_guess_model",
@@ -94,6 +94,7 @@ def load(path: Optional[str] = None):
                                             vp, C.c_uint32, P(i32)]
     lib.dmri_problem_info.argtypes = [vp, i32, P(i64), P(i64)]
     lib.dmri_export_operator.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.dmri_export_weak.argtypes = [vp, i32, P(i64), P(i64), P(dbl), vp, vp, vp, vp, vp, vp]
     lib.dmri_set_sequence_pgse.argtypes = [vp, dbl, dbl, dbl, dbl]
     lib.dmri_set_sequence.argtypes = [vp, i32, vp, i32, dbl, dbl]
     lib.dmri_set_sequence_table.argtypes = [vp, i64, dbl, dbl, vp, vp, vp, dbl]
@@ -231,6 +232,23 @@ class Simulator:
         self._check(self.lib.dmri_export_operator(
             self.h, int(pid), _ptr(out["row_ptr"]), _ptr(out["col"]), _ptr(out["vals"]),
             _ptr(out["w"]), _ptr(out["u0"]), _ptr(out["dof_comp"]), _ptr(out["dof_node"])))
+        return out
+
+    def dmri_export_weak(self, pid: int) -> dict:
+        ns, ne, ke = C.c_int64(), C.c_int64(), C.c_double()
+        self._check(self.lib.dmri_export_weak(self.h, int(pid), C.byref(ns), C.byref(ne),
+                                              C.byref(ke), None, None, None, None, None, None))
+        _, nnz = self.dmri_problem_info(pid)
+        out = {"kappa_e": ke.value, "rows": np.empty(ns.value, np.int32),
+               "ptr": np.empty(ns.value + 1, np.int32), "col": np.empty(ne.value, np.int32),
+               "code": np.empty(ne.value, np.int32), "val": np.empty(ne.value, np.float64),
+               "face_mass": np.zeros(nnz, np.float64)}
+        if ns.value == 0:
+            return out
+        self._check(self.lib.dmri_export_weak(
+            self.h, int(pid), C.byref(ns), C.byref(ne), C.byref(ke), _ptr(out["rows"]),
+            _ptr(out["ptr"]), _ptr(out["col"]), _ptr(out["code"]), _ptr(out["val"]),
+            _ptr(out["face_mass"])))
         return out
 
     # -- sequence and options -----------------------------------------------

@@ -18,7 +18,7 @@ BUILD = os.path.join(os.path.dirname(PKG), "_build")
 LIB = os.path.join(PKG, "libdmri.so")
 ARCH = "gfx950"
 
-SOURCES = ["assembly.cpp", "sequence.cpp", "kernels.hip", "mlp.hip", "capi.hip"]
+SOURCES = ["assembly.cpp", "weakbc.cpp", "sequence.cpp", "kernels.hip", "mlp.hip", "capi.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

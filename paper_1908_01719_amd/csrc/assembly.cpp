@@ -64,8 +64,12 @@ HostOperator assemble(const MeshInput& in) {
         fail(DMRI_E_INVALID, "xyz, tets, tet_label and D must not be NULL");
     if (in.n_nodes > (int64_t(1) << 31) - 1 || in.n_tets > (int64_t(1) << 31) / 4)
         fail(DMRI_E_INVALID, "mesh too large for 32-bit indices");
-    if (in.periodic_mask != 0 && in.periodic_mask != 7)
-        fail(DMRI_E_UNSUPPORTED, "periodic_mask must be 0 (Neumann walls) or 7 (periodic box)");
+    const bool weak = (in.periodic_mask & 8u) != 0;
+    if (weak ? (in.periodic_mask > 15u || (in.periodic_mask & 7u) == 0)
+             : (in.periodic_mask != 0 && in.periodic_mask != 7))
+        fail(DMRI_E_UNSUPPORTED,
+             "periodic_mask must be 0 (Neumann walls), 7 (periodic box) or 8 plus the "
+             "weakly periodic axes (bits 0-2)");
     if (!finite(in.kappa) || in.kappa < 0) fail(DMRI_E_INVALID, "kappa must be finite and >= 0");
     for (int a = 0; a < 3; ++a)
         if (!finite(in.lo[a]) || !finite(in.hi[a]) || !(in.lo[a] < in.hi[a]))
@@ -102,6 +106,8 @@ HostOperator assemble(const MeshInput& in) {
 
     HostOperator op;
     op.form = in.periodic_mask == 7 ? FORM_TRANSFORMED : FORM_UFORM;
+    // strong identification of opposite faces (weak faces stay apart)
+    const uint32_t ident = weak ? 0u : in.periodic_mask;
     op.n_comp = in.n_comp;
     const double L[3] = {in.hi[0] - in.lo[0], in.hi[1] - in.lo[1], in.hi[2] - in.lo[2]};
     const double centre[3] = {0.5 * (in.lo[0] + in.hi[0]), 0.5 * (in.lo[1] + in.hi[1]),
@@ -118,7 +124,7 @@ HostOperator assemble(const MeshInput& in) {
         }
     }
     for (int a = 0; a < 3; ++a) {
-        if (!(in.periodic_mask >> a & 1)) continue;
+        if (!(ident >> a & 1)) continue;
         const int b = (a + 1) % 3, c = (a + 2) % 3;
         std::vector<std::pair<int64_t, int64_t>> lo_face, hi_face;
         for (int64_t n = 0; n < nN; ++n) {
@@ -135,8 +141,8 @@ HostOperator assemble(const MeshInput& in) {
         // Edge/corner nodes wrap along other axes too; compare wrapped keys.
         auto wrap = [&](std::vector<std::pair<int64_t, int64_t>>& v) {
             for (auto& p : v) {
-                if ((in.periodic_mask >> b & 1) && p.first == kQuantI) p.first = 0;
-                if ((in.periodic_mask >> c & 1) && p.second == kQuantI) p.second = 0;
+                if ((ident >> b & 1) && p.first == kQuantI) p.first = 0;
+                if ((ident >> c & 1) && p.second == kQuantI) p.second = 0;
             }
             std::sort(v.begin(), v.end());
             v.erase(std::unique(v.begin(), v.end()), v.end());
@@ -148,7 +154,7 @@ HostOperator assemble(const MeshInput& in) {
     }
     for (int64_t n = 0; n < nN; ++n)
         for (int a = 0; a < 3; ++a)
-            if ((in.periodic_mask >> a & 1) && qk[n][a] == kQuantI) qk[n][a] = 0;
+            if ((ident >> a & 1) && qk[n][a] == kQuantI) qk[n][a] = 0;
 
     std::unordered_map<Key3, int64_t, Key3Hash> tmap;
     tmap.reserve(static_cast<size_t>(nN * 1.3) + 16);
@@ -514,6 +520,7 @@ HostOperator assemble(const MeshInput& in) {
             }
     }
     op.max_edge = std::sqrt(emax);
+    if (weak) add_weak_faces(in, tdof, op);
     return op;
 }
 

@@ -47,6 +47,8 @@ struct MeshInput {
     double kappa = 0.0;
     double lo[3] = {0, 0, 0};
     double hi[3] = {0, 0, 0};
+    // 0 = Neumann walls, 7 = periodic box (strong), 8 | axes = weak
+    // pseudo-periodic faces on those axes (U-form, Appendix B)
     uint32_t periodic_mask = 0;
     // DOF ordering: 0 = Morton (Z-order) of node positions; 1 = pencils:
     // columns of pencil x pencil cells in (x, y), each swept z-, y-, x-major,
@@ -88,7 +90,23 @@ struct HostOperator {
     std::vector<int32_t> tet_node;   // [n_tets][4]
     std::vector<double> node_xyz;    // [n_nodes][3]
     double max_edge = 0.0;           // longest tetrahedron edge
+    // Weak pseudo-periodic faces (Appendix B; periodic_mask bit 3 with the
+    // axes in bits 0-2, U-form, no identification): KB [nnz] the face mass
+    // kappa_e <phi_i, phi_j> on the weak faces (empty otherwise); the
+    // partner couplings in rows wk_rows (ascending), entries
+    // wk_ptr[r]..wk_ptr[r+1] with column wk_col, value wk_val (kappa_e
+    // folded in) and wk_code = a (row on the face x_a = lo, phase
+    // e^{+i G F q_a L_a}) or 3 + a (row on x_a = hi, phase e^{-i ...}).
+    std::vector<double> KB;
+    double kappa_e = 0.0;
+    std::vector<int32_t> wk_rows, wk_ptr, wk_col, wk_code;
+    std::vector<double> wk_val;
+    double box_len[3] = {0.0, 0.0, 0.0};
 };
+
+// Fill the weak-face arrays of op (called by assemble once the pattern
+// exists); tdof [n_tets][4] holds the DOF of every tetrahedron vertex.
+void add_weak_faces(const MeshInput& in, const std::vector<int32_t>& tdof, HostOperator& op);
 
 // Validate the input and assemble. Throws dmri::Error.
 HostOperator assemble(const MeshInput& in);

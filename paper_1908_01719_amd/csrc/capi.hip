@@ -113,6 +113,11 @@ struct ProblemRec {
     DevBuf<int4> tet_dof, tet_node;
     DevBuf<double> node_xyz;
     bool tets_up = false;
+    // Weak pseudo-periodic faces: partner couplings (rows = slots) and the
+    // row -> slot map; the kappa_e scale the device K0 was built with.
+    DevBuf<int32_t> wk_ptr, wk_col, wk_code, wk_map;
+    DevBuf<double> wk_val;
+    double wk_scale_up = -1;
 };
 
 void build_padded(ProblemRec& P) {
@@ -168,6 +173,7 @@ struct Options {
     int pair_lanes = 1;
     int signal = 1;
     int gmres_m = 30;
+    double weak_kappa = 1.0;  // scale of kappa_e on weak pseudo-periodic faces
 };
 
 // Per-system Krylov state arrays of one solver level.
@@ -233,6 +239,7 @@ struct Workspace {
     DevBuf<double2> gm_basis, gm_H, gm_sn, gm_g, gm_y;
     DevBuf<double> gm_partial, gm_hout, gm_cs, gm_hnorm;
     DevBuf<double> acomp;  // [n_comp][ld] q.D_k q per system (anisotropic problems)
+    DevBuf<double> wb;     // [slots][ld] complex partner terms of weak faces
     DevBuf<int32_t> gm_cycle, gm_dim;
     int32_t* h_active[2] = {nullptr, nullptr};  // pinned
     size_t h_active_n = 0;
@@ -433,9 +440,12 @@ void need_device(dmri_ctx* h) {
 }
 
 // Build K0 = M/dt + theta R, Kr = M/dt - (1-theta) R, aux = {M_D, V} and the
-// diagonal, in precision T, and upload them.
+// diagonal, in precision T, and upload them. Weak pseudo-periodic faces add
+// kb K_B to K0 only (kb = theta times the kappa_e scale; the form a*), the
+// right side keeps no face mass (L*).
 template <typename T>
-void upload_matrix(const ProblemRec& P, double dt, double th, DevMatrix<T>& A, hipStream_t st) {
+void upload_matrix(const ProblemRec& P, double dt, double th, double kb, DevMatrix<T>& A,
+                   hipStream_t st) {
     using T4 = typename Vec4Of<T>::type;
     const HostOperator& op = P.op;
     const size_t total = P.pad_col.size(), n = static_cast<size_t>(op.n_dof);
@@ -446,7 +456,7 @@ void upload_matrix(const ProblemRec& P, double dt, double th, DevMatrix<T>& A, h
         T4 a;
         a.x = a.y = a.z = a.w = T(0);
         if (k >= 0) {
-            K0[d] = static_cast<T>(op.M[k] / dt + th * op.R[k]);
+            K0[d] = static_cast<T>(op.M[k] / dt + th * op.R[k] + (op.KB.empty() ? 0.0 : kb * op.KB[k]));
             Kr[d] = static_cast<T>(op.M[k] / dt - (1.0 - th) * op.R[k]);
             a.x = static_cast<T>(op.MT[k]);
             a.y = static_cast<T>(op.V[0][k]);
@@ -457,7 +467,7 @@ void upload_matrix(const ProblemRec& P, double dt, double th, DevMatrix<T>& A, h
     }
     for (size_t i = 0; i < n; ++i) {
         const int64_t k = op.diag_pos[i];
-        dK0[i] = static_cast<T>(op.M[k] / dt + th * op.R[k]);
+        dK0[i] = static_cast<T>(op.M[k] / dt + th * op.R[k] + (op.KB.empty() ? 0.0 : kb * op.KB[k]));
         daux[i].x = static_cast<T>(op.MT[k]);
         daux[i].y = static_cast<T>(op.V[0][k]);
         daux[i].z = static_cast<T>(op.V[1][k]);
@@ -484,17 +494,32 @@ void ensure_uploaded(dmri_ctx* h, ProblemRec& P, bool need32) {
             P.row_comp.upload(P.op.dof_comp.data(), P.op.dof_comp.size(), st);
             P.comp_tensor.upload(P.op.comp_tensor.data(), P.op.comp_tensor.size(), st);
         }
+        std::vector<int32_t> wmap;
+        if (!P.op.wk_rows.empty()) {
+            const HostOperator& op = P.op;
+            wmap.assign(static_cast<size_t>(op.n_dof), -1);
+            for (size_t sl = 0; sl < op.wk_rows.size(); ++sl)
+                wmap[op.wk_rows[sl]] = static_cast<int32_t>(sl);
+            P.wk_ptr.upload(op.wk_ptr.data(), op.wk_ptr.size(), st);
+            P.wk_col.upload(op.wk_col.data(), op.wk_col.size(), st);
+            P.wk_code.upload(op.wk_code.data(), op.wk_code.size(), st);
+            P.wk_val.upload(op.wk_val.data(), op.wk_val.size(), st);
+            P.wk_map.upload(wmap.data(), wmap.size(), st);
+        }
         HIPCHK(hipStreamSynchronize(st));
         P.pattern_up = true;
     }
-    if (P.dt_up != h->dt || P.theta_up != h->theta) {
+    const double wks = P.op.KB.empty() ? 1.0 : opts(h).weak_kappa;
+    if (P.dt_up != h->dt || P.theta_up != h->theta || P.wk_scale_up != wks) {
         P.A64.ready = false;
         P.A32.ready = false;
         P.dt_up = h->dt;
         P.theta_up = h->theta;
+        P.wk_scale_up = wks;
     }
-    if (!P.A64.ready) upload_matrix<double>(P, h->dt, h->theta, P.A64, st);
-    if (need32 && !P.A32.ready) upload_matrix<float>(P, h->dt, h->theta, P.A32, st);
+    const double kb = h->theta * wks;
+    if (!P.A64.ready) upload_matrix<double>(P, h->dt, h->theta, kb, P.A64, st);
+    if (need32 && !P.A32.ready) upload_matrix<float>(P, h->dt, h->theta, kb, P.A32, st);
 }
 
 template <typename T>
@@ -509,6 +534,26 @@ MatView<T> view(ProblemRec& P, DevMatrix<T>& A) {
     v.daux = A.daux.p;
     v.n_rows = static_cast<int32_t>(P.op.n_dof);
     return v;
+}
+
+// Device view of a problem's weak pseudo-periodic faces (n_slots = 0 when
+// it has none). The scheme of Appendix B keeps a constant field constant
+// only with theta = 1/2 (implicit face mass theta, lagged partner 1 -
+// theta), so other theta values are refused.
+WeakView weak_view(const dmri_ctx* h, const ProblemRec& P) {
+    WeakView w{};
+    if (P.op.wk_rows.empty()) return w;
+    if (std::fabs(h->theta - 0.5) > 1e-12)
+        throw Error(DMRI_E_UNSUPPORTED,
+                    "weak pseudo-periodic faces need the Crank-Nicolson scheme (theta = 1/2)");
+    w.ptr = P.wk_ptr.p;
+    w.col = P.wk_col.p;
+    w.code = P.wk_code.p;
+    w.val = P.wk_val.p;
+    w.map = P.wk_map.p;
+    w.n_slots = static_cast<int32_t>(P.op.wk_rows.size());
+    for (int a = 0; a < 3; ++a) w.L[a] = P.op.box_len[a];
+    return w;
 }
 
 int auto_tile(int64_t n_sys) {
@@ -1122,6 +1167,13 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     SolverState s = W.outer.view(static_cast<int32_t>(n_sys), opts(h).max_iter,
                                  opts(h).rtol * opts(h).rtol);
     const MatView<T> Av = view<T>(P, A);
+    const WeakView wv = weak_view(h, P);
+    V2* wb = nullptr;
+    if (wv.n_slots > 0) {
+        W.wb.alloc(2 * static_cast<size_t>(wv.n_slots) * ld);
+        wb = reinterpret_cast<V2*>(W.wb.p);
+    }
+    const double wc = (1.0 - h->theta) * opts(h).weak_kappa;
     launch_set_initial<T>(st, g, P.u0.p, s.n_sys, hs.u(0));
     std::vector<double> F, f;
     step_tables(h, F, f);
@@ -1140,8 +1192,9 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
         const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
         const int gm = prepare_guess<T>(h, g, dofs, tr, F, f, n, n_sys, hs, timer);
         timer.run(4, [&] {
+            if (wb) launch_weak_rhs<T>(st, g, wv, W.gq.p, s.n_sys, F[n], wc, hs.u(0), wb);
             launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, bs.herm, gm, hs.u(0), hs.u(1), hs.x(), r,
-                           p, nullptr, nullptr, bv, s, bs.sc);
+                           p, nullptr, nullptr, bv, s, bs.sc, wb ? wv.map : nullptr, wb);
         });
         int done = 0;
         if constexpr (sizeof(T) == 8) {
@@ -1185,6 +1238,8 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
         kp(r);
         kp(p);
         kp(q);
+        kp(wb);
+        kd(wc);
         for (double v : {double(n_sys), double(N), double(sizeof(T)), double(bs.herm),
                          double(g.S), double(bs.gp.B), opts(h).rtol, double(opts(h).max_iter),
                          double(opts(h).guess), double(opts(h).extrap_order),
@@ -1280,6 +1335,13 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     }
     const MatView<double> A64 = view<double>(P, P.A64);
     const MatView<float> A32 = view<float>(P, P.A32);
+    const WeakView wv = weak_view(h, P);
+    double2* wb = nullptr;
+    if (wv.n_slots > 0) {
+        W.wb.alloc(2 * static_cast<size_t>(wv.n_slots) * ld);
+        wb = reinterpret_cast<double2*>(W.wb.p);
+    }
+    const double wc = (1.0 - h->theta) * opts(h).weak_kappa;
     launch_set_initial<double>(st, g, P.u0.p, so.n_sys, hs.u(0));
     std::vector<double> F, f;
     step_tables(h, F, f);
@@ -1297,8 +1359,10 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
         const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
         const int gm = prepare_guess<double>(h, g, dofs, tr, F, f, n, n_sys, hs, timer);
         timer.run(4, [&] {
+            if (wb) launch_weak_rhs<double>(st, g, wv, W.gq.p, so.n_sys, F[n], wc, hs.u(0), wb);
             launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, gm, hs.u(0), hs.u(1),
-                                hs.x(), r64, p64, nullptr, nullptr, b64, so, bs.sc);
+                                hs.x(), r64, p64, nullptr, nullptr, b64, so, bs.sc,
+                                wb ? wv.map : nullptr, wb);
         });
         int step_iters = 0;
         for (int pass = 0; pass < opts(h).max_outer; ++pass) {
@@ -1746,6 +1810,27 @@ dmri_status dmri_export_operator(dmri_handle h, int32_t problem_id, int32_t* row
     });
 }
 
+dmri_status dmri_export_weak(dmri_handle h, int32_t problem_id, int64_t* n_slots,
+                             int64_t* n_entries, double* kappa_e, int32_t* rows, int32_t* ptr,
+                             int32_t* col, int32_t* code, double* val, double* face_mass) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        const HostOperator& op = get_problem(h, problem_id).op;
+        const size_t ns = op.wk_rows.size(), ne = op.wk_col.size();
+        if (n_slots) *n_slots = static_cast<int64_t>(ns);
+        if (n_entries) *n_entries = static_cast<int64_t>(ne);
+        if (kappa_e) *kappa_e = op.kappa_e;
+        if (ns == 0) return DMRI_OK;
+        if (rows) std::memcpy(rows, op.wk_rows.data(), ns * sizeof(int32_t));
+        if (ptr) std::memcpy(ptr, op.wk_ptr.data(), (ns + 1) * sizeof(int32_t));
+        if (col) std::memcpy(col, op.wk_col.data(), ne * sizeof(int32_t));
+        if (code) std::memcpy(code, op.wk_code.data(), ne * sizeof(int32_t));
+        if (val) std::memcpy(val, op.wk_val.data(), ne * sizeof(double));
+        if (face_mass) std::memcpy(face_mass, op.KB.data(), op.KB.size() * sizeof(double));
+        return DMRI_OK;
+    });
+}
+
 dmri_status dmri_set_sequence_pgse(dmri_handle h, double delta_us, double Delta_us, double dt_us,
                                    double theta) {
     if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
@@ -1853,7 +1938,10 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "pair_lanes") o.pair_lanes = as_int(0, 1);
         else if (k == "signal") o.signal = as_int(0, 1);
         else if (k == "gmres_m") o.gmres_m = as_int(1, kGmMax);
-        else throw Error(DMRI_E_INVALID, "unknown option " + k);
+        else if (k == "weak_kappa") {
+            if (!(v > 0 && v <= 1e6)) throw Error(DMRI_E_INVALID, "weak_kappa must be in (0, 1e6]");
+            o.weak_kappa = v;
+        } else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
 }
@@ -1894,6 +1982,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "pair_lanes") *value = o.pair_lanes;
         else if (k == "signal") *value = o.signal;
         else if (k == "gmres_m") *value = o.gmres_m;
+        else if (k == "weak_kappa") *value = o.weak_kappa;
         else if (k == "tuned_sys_tile") *value = h->last_tune.sys_tile;
         else if (k == "tuned_blocks_per_xcd") *value = h->last_tune.blocks_per_xcd;
         else if (k == "tuned_persistent") *value = h->last_tune.persistent;
@@ -2266,6 +2355,9 @@ void run_noalloc(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, c
         throw Error(DMRI_E_UNSUPPORTED, "the no-allocation entry point runs CG or COCG");
     if (h->model.rec_cap > 0)
         throw Error(DMRI_E_UNSUPPORTED, "sample recording allocates; not with this entry point");
+    if (!P.op.wk_rows.empty())
+        throw Error(DMRI_E_UNSUPPORTED,
+                    "the no-allocation entry point has no weak pseudo-periodic faces");
     if (!P.pattern_up || !P.A64.ready || P.dt_up != h->dt || P.theta_up != h->theta)
         throw Error(DMRI_E_STATE,
                     "the problem's operators are not on the device for this sequence: run it "

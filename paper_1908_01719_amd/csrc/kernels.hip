@@ -1365,7 +1365,7 @@ __global__ __launch_bounds__(kBlock) void k_init(
     Coef lhs, Coef rhs, const V2<T>* __restrict__ u_prev, const V2<T>* __restrict__ u_prev2,
     V2<T>* __restrict__ x, V2<T>* __restrict__ r, V2<T>* __restrict__ p,
     const float2* __restrict__ dx, V2<T>* __restrict__ x_out, V2<T>* __restrict__ bvec,
-    SolverState s, Scratch sc) {
+    SolverState s, Scratch sc, const int32_t* __restrict__ wmap, const V2<T>* __restrict__ wb) {
     constexpr bool kRhs = GM < 3;  // b formed from u_prev in this launch
     __shared__ double lds[kWaves * S * 4];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
@@ -1471,6 +1471,15 @@ __global__ __launch_bounds__(kBlock) void k_init(
                 }
             }
             const size_t idx = tb + static_cast<size_t>(row) * S;
+            if (kRhs && wmap) {
+                // weak pseudo-periodic faces: the lagged partner term
+                const int32_t sl = wmap[row];
+                if (sl >= 0) {
+                    const V2<T> e = wb[static_cast<size_t>(sl) * g.ld + sys];
+                    br += e.x;
+                    bi += e.y;
+                }
+            }
             if (!kRhs) {
                 const V2<T> bv = bvec[idx];
                 br = bv.x;
@@ -1854,6 +1863,45 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, MatView<T> A, int whic
             }
         });
     }
+}
+
+// Partner term of the weak pseudo-periodic faces (see launch_weak_rhs):
+// one thread per (slot, system), consecutive threads on consecutive systems
+// so the u_prev reads of a column are contiguous. FP64 phases and sums.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_weak_rhs(WeakView w, int32_t n_rows, int32_t S,
+                                                     int32_t ld, int32_t n_sys,
+                                                     const double4* __restrict__ gq, double F,
+                                                     double c, const V2<T>* __restrict__ u,
+                                                     V2<T>* __restrict__ wb) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= static_cast<int64_t>(w.n_slots) * ld) return;
+    const int32_t slot = static_cast<int32_t>(i / ld);
+    const int32_t sys = static_cast<int32_t>(i - static_cast<int64_t>(slot) * ld);
+    if (sys >= n_sys) {
+        wb[i] = mk2<T>(T(0), T(0));
+        return;
+    }
+    const double4 g = gq[sys];
+    const double GF = g.x * F;
+    double cs[3], sn[3];
+    sincos(GF * g.y * w.L[0], &sn[0], &cs[0]);
+    sincos(GF * g.z * w.L[1], &sn[1], &cs[1]);
+    sincos(GF * g.w * w.L[2], &sn[2], &cs[2]);
+    const int32_t tile = sys / S;
+    const size_t base = static_cast<size_t>(tile) * n_rows * S + (sys - tile * S);
+    double re = 0.0, im = 0.0;
+    for (int32_t k = w.ptr[slot]; k < w.ptr[slot + 1]; ++k) {
+        const int32_t cd = w.code[k];
+        const int32_t a = cd < 3 ? cd : cd - 3;
+        const double er = cs[a], ei = cd < 3 ? sn[a] : -sn[a];
+        const V2<T> v = u[base + static_cast<size_t>(w.col[k]) * S];
+        const double vr = static_cast<double>(v.x), vi = static_cast<double>(v.y);
+        const double val = w.val[k];
+        re += val * (er * vr - ei * vi);
+        im += val * (er * vi + ei * vr);
+    }
+    wb[i] = mk2<T>(static_cast<T>(c * re), static_cast<T>(c * im));
 }
 
 template <typename T>
@@ -2444,13 +2492,14 @@ template <typename T>
 void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq, Coef lhs,
                  Coef rhs, bool herm, int guess_mode, const V2<T>* u_prev, const V2<T>* u_prev2,
                  V2<T>* x, V2<T>* r, V2<T>* p, const float2* dx, V2<T>* x_out, V2<T>* bvec,
-                 SolverState s, Scratch sc) {
+                 SolverState s, Scratch sc, const int32_t* wmap, const V2<T>* wb) {
     if (guess_mode >= 3 && !bvec) throw std::runtime_error("init: refinement needs the stored b");
+    if ((wmap == nullptr) != (wb == nullptr)) throw std::runtime_error("init: wmap and wb go together");
     const dim3 grid = grid_of(g), block(kBlock);
 #define DMRI_INIT(H, GMV)                                                                     \
     k_init<T, S, H, GMV><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.Kr, A.aux, A.dK0, \
                                                  A.daux, gq, lhs, rhs, u_prev, u_prev2, x, r, p, \
-                                                 dx, x_out, bvec, s, sc)
+                                                 dx, x_out, bvec, s, sc, wmap, wb)
 #define DMRI_INIT_GM(H)                      \
     switch (guess_mode) {                    \
         case 0: DMRI_INIT(H, 0); break;      \
@@ -2678,6 +2727,20 @@ void launch_set_initial(hipStream_t st, const Geom& g, const double* u0, int32_t
     check_launch("set_initial");
 }
 
+template <typename T>
+void launch_weak_rhs(hipStream_t st, const Geom& g, const WeakView& w, const double4* gq,
+                     int32_t n_sys, double F, double c, const V2<T>* u_prev, V2<T>* wb) {
+    const int64_t n = static_cast<int64_t>(w.n_slots) * g.ld;
+    if (n <= 0) return;
+    const unsigned blocks = static_cast<unsigned>((n + kBlock - 1) / kBlock);
+    k_weak_rhs<T><<<blocks, kBlock, 0, st>>>(w, g.n_rows, g.S, g.ld, n_sys, gq, F, c, u_prev, wb);
+    check_launch("weak_rhs");
+}
+template void launch_weak_rhs<double>(hipStream_t, const Geom&, const WeakView&, const double4*,
+                                      int32_t, double, double, const double2*, double2*);
+template void launch_weak_rhs<float>(hipStream_t, const Geom&, const WeakView&, const double4*,
+                                     int32_t, double, double, const float2*, float2*);
+
 void launch_sys_params(hipStream_t st, int32_t n_sys, int32_t ld, const double* b, const double* q,
                        double int_F2, double4* gq, int32_t* bad) {
     const unsigned blocks = static_cast<unsigned>((ld + 255) / 256);
@@ -2792,7 +2855,7 @@ void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
     template void launch_init<T>(hipStream_t, const Geom&, const MatView<T>&, const double4*,  \
                                  Coef, Coef, bool, int, const V2<T>*, const V2<T>*, V2<T>*,    \
                                  V2<T>*, V2<T>*, const float2*, V2<T>*, V2<T>*, SolverState, \
-                                 Scratch);                                                     \
+                                 Scratch, const int32_t*, const V2<T>*);                       \
     template void launch_spmv_dot<T>(hipStream_t, const Geom&, const MatView<T>&,              \
                                      const double4*, Coef, bool, const V2<T>*, V2<T>*,         \
                                      SolverState, Scratch);                                    \

@@ -144,7 +144,29 @@ void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const doubl
                  const typename Vec2Of<T>::type* u_prev, const typename Vec2Of<T>::type* u_prev2,
                  typename Vec2Of<T>::type* x, typename Vec2Of<T>::type* r,
                  typename Vec2Of<T>::type* p, const float2* dx, typename Vec2Of<T>::type* x_out,
-                 typename Vec2Of<T>::type* bvec, SolverState s, Scratch sc);
+                 typename Vec2Of<T>::type* bvec, SolverState s, Scratch sc,
+                 const int32_t* wmap = nullptr, const typename Vec2Of<T>::type* wb = nullptr);
+
+// Weak pseudo-periodic faces (Appendix B, the partner term of L*): for every
+// DOF on a weak face (slot), wb[slot * ld + sys] =
+//   c sum_k val_k e^{i s_k phi_a} u_prev[col_k][sys],  phi_a = G F q_a L_a,
+// a = code_k % 3, s_k = +1 for code_k < 3 (row on the face x_a = lo), -1
+// otherwise; G, q from gq, F = F(t^n), c = (1 - theta) times the kappa_e
+// scale. k_init adds wb to the right-hand side of the rows wmap maps to a
+// slot (wmap[row] = slot or -1).
+struct WeakView {
+    const int32_t* ptr;   // [n_slots + 1]
+    const int32_t* col;
+    const int32_t* code;
+    const double* val;
+    const int32_t* map;   // [n_rows]
+    int32_t n_slots;
+    double L[3];
+};
+template <typename T>
+void launch_weak_rhs(hipStream_t st, const Geom& g, const WeakView& w, const double4* gq,
+                     int32_t n_sys, double F, double c, const typename Vec2Of<T>::type* u_prev,
+                     typename Vec2Of<T>::type* wb);
 
 // Start of an FP32 inner solve on the FP64 residual r64 of the systems still
 // active in `outer`: r = (float) r64, dx = 0, p = D^-1 r (FP32 operator).

@@ -904,3 +904,69 @@ def test_isotropic_tensor_equals_scalar(Sim):
             out[prec] = rel_err(s2, s1, s1[0]).max()
     _say("isotropic tensor vs scalar: FP64 %.2e, mixed %.2e" % (out[0], out[1]))
     assert out[0] < 1e-11 and out[1] < 1e-8
+
+
+# ------------------------------------------- weak pseudo-periodic faces
+def _weak_case():
+    # Two compartments on an unstructured conforming mesh whose opposite box
+    # faces do not match node for node; weak faces on x, y and z.
+    return di.nonmatching_faces(
+        di.conforming_cylinder_box(n=7, half=6.0, r=4.0, kappa=1e-2, D_in=1e-3,
+                                   periodic_mask=15, seed=1, u0=(1.0, 0.7)),
+        amount=0.25, seed=7)
+
+
+@pytest.mark.parametrize("scale", [1.0, 8.0])
+def test_weak_faces_match_oracle(Sim, scale):
+    # Artificial-permeability faces (face mass in the left operator, lagged
+    # phase-shifted partner in the right side): FP64 COCG and GMRES within
+    # 1e-9 of the oracle, mixed precision within 1e-9 at rtol 1e-12, the
+    # FP32 path within 1e-4, a graph replay equal to the eager run.
+    prob = _weak_case()
+    b = np.array([0.0, 800.0, 2500.0, 4000.0, 1500.0, 3200.0])
+    q = di.fibonacci_directions(6)
+    asm = fem.assemble(prob, weak_kappa=scale)
+    ref = timestep.signals(prob, SHORT, b, q, asm=asm, solver="splu")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-12, weak_kappa=scale)
+        pid = sim.add_problem(prob)
+        _say("weak faces scale %g: FP64" % scale)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+        sim.set_options(krylov=3)
+        sig_g, _ = sim.dmri_run([pid] * len(b), b, q)
+        sim.set_options(krylov=0, precision=1)
+        sig_m, _ = sim.dmri_run([pid] * len(b), b, q)
+        sim.set_options(precision=2, rtol=1e-6)
+        sig_32, _ = sim.dmri_run([pid] * len(b), b, q)
+        sim.set_options(precision=0, rtol=1e-12, persistent=1, graph=1)
+        _say("weak faces scale %g: graph" % scale)
+        sig_gr = [sim.dmri_run([pid] * len(b), b, q)[0] for _ in range(2)]
+        sim.set_options(graph=0)
+        eager, _ = sim.dmri_run([pid] * len(b), b, q)
+    e = [rel_err(x, ref, ref[0]).max() for x in (sig, sig_g, sig_m, sig_32)]
+    _say("weak faces scale %g: FP64 %.2e GMRES %.2e mixed %.2e FP32 %.2e" % (scale, *e))
+    assert st["status"] == "DMRI_OK"
+    assert e[0] < 1e-9 and e[1] < 1e-9 and e[2] < 1e-9 and e[3] < 1e-4
+    for g in sig_gr:
+        assert np.array_equal(g, eager)
+    assert abs(ref[2].imag) > 1e-6 * abs(ref[0])  # non-matching faces: a complex signal
+
+
+def test_weak_faces_refusals(Sim):
+    import torch
+    prob = _weak_case()
+    with Sim(0) as sim:
+        sim.set_sequence(di.Sequence(2000.0, 4000.0, 200.0, 0.75))
+        pid = sim.add_problem(prob)
+        with pytest.raises(Exception, match="DMRI_E_UNSUPPORTED"):
+            sim.dmri_run([pid], [1000.0], [[1.0, 0.0, 0.0]])
+        sim.set_sequence(SHORT)
+        sim.dmri_run([pid], [1000.0], [[1.0, 0.0, 0.0]])
+        dev = torch.device("cuda:0")
+        b = torch.tensor([1000.0], dtype=torch.float64, device=dev)
+        q = torch.tensor([[1.0, 0.0, 0.0]], dtype=torch.float64, device=dev)
+        out = torch.zeros(2, dtype=torch.float64, device=dev)
+        pids = torch.full((1,), pid, dtype=torch.int32, device=dev)
+        with pytest.raises(Exception, match="DMRI_E_UNSUPPORTED"):
+            sim.dmri_run_device_noalloc(pids, b, q, out)

@@ -68,6 +68,11 @@ CASES = {
     "conforming_tensor": lambda: di.conforming_cylinder_box(
         n=7, half=6.0, r=4.0, D_in=di.tensor([3e-3, 1e-3, 2e-3], (0.3, 0.5, 0.2)),
         D_out=di.tensor([2e-3, 2.5e-3, 1.5e-3], (1.0, -0.4, 0.7)), kappa=5e-3),
+    # weak pseudo-periodic faces (the arrays of the faces are compared in
+    # test_weak_faces_match_oracle)
+    "weak_nonmatching": lambda: di.nonmatching_faces(
+        di.conforming_cylinder_box(n=6, half=6.0, r=4.0, kappa=1e-2, D_in=1e-3,
+                                   periodic_mask=13, seed=1), axes=(0, 2), amount=0.25, seed=7),
     "conforming_tensor_neumann": lambda: di.conforming_cylinder_box(
         n=7, half=6.0, r=4.0, D_in=di.tensor([3e-3, 1e-3, 2e-3], (0.3, 0.5, 0.2)),
         D_out=di.tensor([2e-3, 2e-3, 2e-3]), periodic_mask=0, kappa=5e-3),
@@ -88,7 +93,7 @@ def test_operators_match_oracle(name):
     nnz = exp["col"].shape[0]
     rows = np.repeat(np.arange(n), np.diff(exp["row_ptr"]))
     P = sp.csr_matrix((np.ones(n), (np.arange(n), perm)), shape=(n, n))
-    V = asm.B if prob.periodic_mask else asm.J
+    V = asm.B if prob.periodic_mask == 7 else asm.J
     refs = [asm.M, asm.S + asm.IG + asm.R2, asm.MD, V[0], V[1], V[2]]
     names = ["M", "R", "MD", "Vx", "Vy", "Vz"]
     for a in range(6):
@@ -103,6 +108,70 @@ def test_operators_match_oracle(name):
     pat = sp.csr_matrix((np.ones(nnz), (rows, exp["col"])), shape=(n, n))
     assert (pat != pat.T).nnz == 0
     assert np.all(pat.diagonal() == 1)
+
+
+WEAK_CASES = {
+    "free_matching": lambda: di.free_box(n=4, half=2.0, periodic_mask=15),
+    "slab_x": lambda: di.slab_box(n=12, half=5.0, split=10.0, cross=(0.5, 1), periodic_mask=9),
+    "nonmatching_cylinder": lambda: di.nonmatching_faces(
+        di.conforming_cylinder_box(n=6, half=6.0, r=4.0, kappa=1e-2, D_in=1e-3,
+                                   periodic_mask=13, seed=1), axes=(0, 2), amount=0.25, seed=7),
+    "nonmatching_tensor": lambda: di.nonmatching_faces(
+        di.conforming_cylinder_box(
+            n=6, half=6.0, r=4.0, D_in=di.tensor([3e-3, 1e-3, 2e-3], (0.3, 0.5, 0.2)),
+            D_out=di.tensor([2e-3, 2.5e-3, 4e-3], (1.0, -0.4, 0.7)), kappa=5e-3,
+            periodic_mask=15, seed=3), amount=0.2, seed=2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WEAK_CASES))
+def test_weak_faces_match_oracle(name):
+    # kappa_e, the face mass and the partner couplings of weak
+    # pseudo-periodic faces (exact overlap integrals on non-matching faces)
+    # equal the oracle's entry by entry after matching DOFs.
+    prob = WEAK_CASES[name]()
+    with Simulator(-1) as s:
+        pid = s.add_problem(prob)
+        exp = s.dmri_export_operator(pid)
+        wk = s.dmri_export_weak(pid)
+    asm = fem.assemble(prob)
+    n = asm.n_dof
+    perm = _lib_to_oracle_perm(prob, exp, asm)
+    P = sp.csr_matrix((np.ones(n), (np.arange(n), perm)), shape=(n, n))
+    assert wk["kappa_e"] == pytest.approx(asm.kappa_e, rel=1e-13)
+    rows = np.repeat(np.arange(n), np.diff(exp["row_ptr"]))
+    KB = sp.csr_matrix((wk["face_mass"], (rows, exp["col"])), shape=(n, n))
+    ref = (P @ asm.KB @ P.T).tocsr()
+    assert abs(KB - ref).max() <= 1e-12 * abs(ref).max()
+    slot_rows = np.repeat(wk["rows"], np.diff(wk["ptr"]))
+    assert np.all(np.diff(wk["rows"]) > 0)
+    axes = {a: (Cms, Csm) for a, Cms, Csm, _ in asm.weak}
+    assert sorted(set(wk["code"] % 3)) == sorted(axes)
+    for code in range(6):
+        sel = wk["code"] == code
+        mine = sp.csr_matrix((wk["val"][sel], (slot_rows[sel], wk["col"][sel])), shape=(n, n))
+        a = code % 3
+        if a not in axes:
+            assert sel.sum() == 0
+            continue
+        ref = (P @ axes[a][0 if code < 3 else 1] @ P.T).tocsr()
+        assert abs(mine - ref).max() <= 1e-12 * abs(ref).max(), code
+
+
+def test_weak_face_validation():
+    prob = di.free_box(n=4, half=2.0, periodic_mask=9)
+    args = _prob_args(prob)
+    with Simulator(-1) as s:
+        for mask in (8, 16, 24):
+            a = dict(args, periodic_mask=mask)
+            with pytest.raises(DmriError, match="DMRI_E_UNSUPPORTED"):
+                s.dmri_add_problem(**a)
+        # a box face not fully meshed: drop the tets touching part of x = hi
+        c = prob.xyz[prob.tets].mean(axis=1)
+        keep = ~((c[:, 0] > 1.0) & (c[:, 1] > 1.0) & (c[:, 2] > 1.0))
+        a = dict(args, tets=prob.tets[keep].copy(), tet_label=prob.tet_label[keep].copy())
+        with pytest.raises(DmriError, match="not fully covered"):
+            s.dmri_add_problem(**a)
 
 
 def _prob_args(prob):
