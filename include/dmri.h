@@ -389,6 +389,18 @@ DMRI_API dmri_status dmri_guess_get_params(dmri_handle h, float* params, int64_t
 DMRI_API dmri_status dmri_load_guess_model(dmri_handle h, const char* path);
 DMRI_API dmri_status dmri_save_guess_model(dmri_handle h, const char* path);
 
+/* Autotuner cache (option "autotune"; Sec. 5 "Parallelization": many runs of
+ * the same meshes): the launch configuration chosen for each (device
+ * architecture and CU count, mesh structure hash, number of systems,
+ * precision, krylov, sys_tile) is kept in the handle; these calls write it
+ * to a text file and merge a file into the handle, so later processes skip
+ * the trial runs. A loaded entry reports option "tuned_trials" 0. Malformed
+ * files (header "dmri-tuning-v1", then "key sys_tile blocks_per_xcd
+ * persistent lds seconds" per line, values in their option ranges) give
+ * DMRI_E_INVALID and change nothing. Host-only handles may load and save. */
+DMRI_API dmri_status dmri_save_tuning(dmri_handle h, const char* path);
+DMRI_API dmri_status dmri_load_tuning(dmri_handle h, const char* path);
+
 /* Record training samples during later dmri_run / dmri_run_device calls:
  * at every step n >= 2, every stride-th element of the batch (a different
  * offset each step) appends its features to d_features ([capacity][16]

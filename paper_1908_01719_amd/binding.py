@@ -34,7 +34,7 @@ EXPORTED = [
     "dmri_run", "dmri_run_device", "dmri_run_device_noalloc", "dmri_apply_operator",
     "dmri_guess_set_params", "dmri_guess_get_params", "dmri_load_guess_model",
     "dmri_save_guess_model", "dmri_guess_record", "dmri_guess_record_count", "dmri_guess_eval",
-    "dmri_guess_train",
+    "dmri_guess_train", "dmri_save_tuning", "dmri_load_tuning",
 ]
 
 SEQ_KINDS = {"pgse": 0, "double_pgse": 1, "cos_ogse": 2, "sin_ogse": 3, "trap_pgse": 4,
@@ -104,6 +104,8 @@ def load(path: Optional[str] = None):
     lib.dmri_guess_get_params.argtypes = [vp, vp, i64]
     lib.dmri_load_guess_model.argtypes = [vp, C.c_char_p]
     lib.dmri_save_guess_model.argtypes = [vp, C.c_char_p]
+    lib.dmri_save_tuning.argtypes = [vp, C.c_char_p]
+    lib.dmri_load_tuning.argtypes = [vp, C.c_char_p]
     lib.dmri_guess_record.argtypes = [vp, vp, vp, i64, i64]
     lib.dmri_guess_record_count.argtypes = [vp, P(i64)]
     lib.dmri_guess_eval.argtypes = [vp, i64, vp, vp, vp, vp, P(dbl)]
@@ -301,6 +303,12 @@ class Simulator:
 
     def dmri_load_guess_model(self, path: str):
         self._check(self.lib.dmri_load_guess_model(self.h, os.fsencode(path)))
+
+    def dmri_save_tuning(self, path: str):
+        self._check(self.lib.dmri_save_tuning(self.h, os.fsencode(path)))
+
+    def dmri_load_tuning(self, path: str):
+        self._check(self.lib.dmri_load_tuning(self.h, os.fsencode(path)))
 
     def dmri_save_guess_model(self, path: str):
         self._check(self.lib.dmri_save_guess_model(self.h, os.fsencode(path)))

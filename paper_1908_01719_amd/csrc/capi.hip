@@ -118,7 +118,28 @@ struct ProblemRec {
     DevBuf<int32_t> wk_ptr, wk_col, wk_code, wk_map;
     DevBuf<double> wk_val;
     double wk_scale_up = -1;
+    // Hash of the sparsity structure (form, DOF count, CSR pattern): the
+    // problem's part of the autotuner cache key, stable across processes.
+    uint64_t fingerprint = 0;
 };
+
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+    const unsigned char* p = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 0x100000001B3ULL;
+    }
+    return h;
+}
+
+uint64_t structure_fingerprint(const HostOperator& op) {
+    uint64_t h = 0xCBF29CE484222325ULL;
+    h = fnv1a(h, &op.form, sizeof op.form);
+    h = fnv1a(h, &op.n_dof, sizeof op.n_dof);
+    h = fnv1a(h, op.row_ptr.data(), op.row_ptr.size() * sizeof(int32_t));
+    h = fnv1a(h, op.col.data(), op.col.size() * sizeof(int32_t));
+    return h;
+}
 
 void build_padded(ProblemRec& P) {
     const HostOperator& op = P.op;
@@ -354,6 +375,7 @@ struct dmri_ctx {
     dmri::Options opt;
     dmri::GuessModel model;
     std::map<std::string, dmri::TuneChoice> tuned;  // autotuner cache
+    std::string device_tag = "host";  // architecture and CU count, in cache keys
     dmri::TuneChoice last_tune;
     std::mutex tuned_mu;  // the cache and last_tune (lanes tune one at a time)
     // Krylov iterations each (problem, b, q) system needed in its last run:
@@ -1542,8 +1564,12 @@ void run_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, con
         run_batch_with(h, P, n_sys, d_b, d_q, d_sig, R);
         return;
     }
-    const std::string key = std::to_string(reinterpret_cast<uintptr_t>(&P)) + "/" +
-                            std::to_string(n_sys) + "/" + std::to_string(opts(h).precision) + "/" +
+    // Content-based key (device, mesh structure, batch shape, solver), so a
+    // cache saved by dmri_save_tuning serves later processes.
+    char fp[17];
+    std::snprintf(fp, sizeof fp, "%016llx", static_cast<unsigned long long>(P.fingerprint));
+    const std::string key = h->device_tag + "/" + fp + "/" + std::to_string(n_sys) + "/" +
+                            std::to_string(opts(h).precision) + "/" +
                             std::to_string(opts(h).krylov) + "/" + std::to_string(opts(h).sys_tile);
     TuneChoice c;
     {
@@ -1688,6 +1714,12 @@ dmri_status dmri_create(int device_ordinal, dmri_handle* out) {
             h->device = device_ordinal;
             h->host_only = false;
             h->scratch_dev = scratch_address(device_ordinal);
+            hipDeviceProp_t prop;
+            HIPCHK(hipGetDeviceProperties(&prop, device_ordinal));
+            std::string arch(prop.gcnArchName);
+            for (char& c : arch)
+                if (c == ' ' || c == '/') c = '_';
+            h->device_tag = arch + "_cu" + std::to_string(prop.multiProcessorCount);
             h->lanes.push_back(std::make_unique<Lane>());
             h->lanes.back()->create();
         } else if (device_ordinal != -1) {
@@ -1747,6 +1779,7 @@ dmri_status add_problem_impl(dmri_handle h, int64_t n_nodes, const double* xyz, 
         in.pencil = opts(h).pencil;
         auto rec = std::make_unique<ProblemRec>();
         rec->op = assemble(in);
+        rec->fingerprint = structure_fingerprint(rec->op);
         h->problems.push_back(std::move(rec));
         *problem_id = static_cast<int32_t>(h->problems.size() - 1);
         return DMRI_OK;
@@ -2036,6 +2069,74 @@ dmri_status dmri_load_guess_model(dmri_handle h, const char* path) {
             dims[1] != kMlpHid || dims[2] != kMlpOut)
             throw Error(DMRI_E_INVALID, std::string("not a guess-network file: ") + path);
         set_guess_params(h, theta.data());
+        return DMRI_OK;
+    });
+}
+
+// Autotuner cache file: a header line, then one line per entry
+//   key sys_tile blocks_per_xcd persistent lds seconds
+constexpr const char* kTuneHeader = "dmri-tuning-v1";
+
+dmri_status dmri_save_tuning(dmri_handle h, const char* path) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        if (!path) throw Error(DMRI_E_INVALID, "NULL path");
+        std::lock_guard<std::mutex> lock(h->tuned_mu);
+        std::FILE* fp = std::fopen(path, "w");
+        if (!fp) throw Error(DMRI_E_INVALID, std::string("cannot create ") + path);
+        bool ok = std::fprintf(fp, "%s\n", kTuneHeader) > 0;
+        for (const auto& kv : h->tuned) {
+            const TuneChoice& c = kv.second;
+            ok = ok && std::fprintf(fp, "%s %d %d %d %d %.9g\n", kv.first.c_str(), c.sys_tile,
+                                    c.blocks_per_xcd, c.persistent, c.lds, c.seconds) > 0;
+        }
+        const bool closed = std::fclose(fp) == 0;
+        if (!ok || !closed) throw Error(DMRI_E_INVALID, std::string("write failed: ") + path);
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_load_tuning(dmri_handle h, const char* path) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        if (!path) throw Error(DMRI_E_INVALID, "NULL path");
+        std::FILE* fp = std::fopen(path, "r");
+        if (!fp) throw Error(DMRI_E_INVALID, std::string("cannot open ") + path);
+        std::map<std::string, TuneChoice> got;
+        char line[1024];
+        bool header = false, bad = false;
+        while (std::fgets(line, sizeof line, fp)) {
+            std::string ln(line);
+            while (!ln.empty() && (ln.back() == '\n' || ln.back() == '\r')) ln.pop_back();
+            if (ln.empty()) continue;
+            if (!header) {
+                header = ln == kTuneHeader;
+                if (!header) {
+                    bad = true;
+                    break;
+                }
+                continue;
+            }
+            char key[512];
+            TuneChoice c;
+            int used = 0;
+            if (ln.size() >= sizeof key ||
+                std::sscanf(ln.c_str(), "%511s %d %d %d %d %lf%n", key, &c.sys_tile,
+                            &c.blocks_per_xcd, &c.persistent, &c.lds, &c.seconds, &used) != 6 ||
+                used != static_cast<int>(ln.size()) ||
+                !(c.sys_tile == 8 || c.sys_tile == 16 || c.sys_tile == 32 || c.sys_tile == 64) ||
+                c.blocks_per_xcd < 1 || c.blocks_per_xcd > 4096 || c.persistent < 0 ||
+                c.persistent > 2 || c.lds < 0 || c.lds > 1 || !std::isfinite(c.seconds)) {
+                bad = true;
+                break;
+            }
+            c.trials = 0;  // served from the file: no trial run in this process
+            got[key] = c;
+        }
+        std::fclose(fp);
+        if (bad || !header) throw Error(DMRI_E_INVALID, std::string("not a tuning file: ") + path);
+        std::lock_guard<std::mutex> lock(h->tuned_mu);
+        for (auto& kv : got) h->tuned[kv.first] = kv.second;
         return DMRI_OK;
     });
 }

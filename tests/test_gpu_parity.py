@@ -497,6 +497,33 @@ def test_autotune_matches_oracle(Sim):
         assert rel_err(s_, ref, ref[0]).max() < 1e-9
 
 
+def test_autotune_cache_persists_across_handles(Sim, tmp_path):
+    # The tuned choice saved by one handle serves a fresh handle (another
+    # process would read the same file): no trial runs there, the same
+    # launch configuration, bit-identical signals.
+    prob, b, q = _cyl_case()
+    path = str(tmp_path / "tuning.txt")
+    keys = ("tuned_sys_tile", "tuned_blocks_per_xcd", "tuned_persistent", "tuned_lds")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.set_options(rtol=1e-12, autotune=1)
+        sig, _ = sim.dmri_run([pid] * len(b), b, q)
+        assert sim.dmri_get_option("tuned_trials") >= 2
+        choice = [sim.dmri_get_option(k) for k in keys]
+        sim.dmri_save_tuning(path)
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.dmri_load_tuning(path)
+        sim.set_options(rtol=1e-12, autotune=1)
+        sig2, _ = sim.dmri_run([pid] * len(b), b, q)
+        assert sim.dmri_get_option("tuned_trials") == 0
+        assert [sim.dmri_get_option(k) for k in keys] == choice
+    _say("tuning cache: %s" % open(path).read().strip().replace("\n", " | "))
+    assert np.array_equal(sig, sig2)
+
+
 def test_concurrent_problems_match_sequential(Sim):
     # Meshes of uneven size in one run: with concurrency each problem runs on
     # its own lane (stream, workspace, host thread); the signals are the same

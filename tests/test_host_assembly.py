@@ -234,3 +234,30 @@ def test_sequence_and_option_validation():
         with pytest.raises(DmriError) as ei:
             s.dmri_run([0], [1000.0], [[1, 0, 0]])
         assert "DMRI_E_STATE" in str(ei.value)
+
+
+def test_tuning_file_round_trip(tmp_path):
+    # The autotuner cache file: entries merge into a handle and are written
+    # back unchanged; malformed files are refused without changing anything.
+    good = tmp_path / "t.txt"
+    good.write_text("dmri-tuning-v1\n"
+                    "gfx950_cu256/00ab12cd34ef5678/1024/1/0/0 64 512 0 0 0.125\n"
+                    "gfx950_cu256/1111222233334444/32/0/0/0 32 256 1 0 0.0625\n")
+    out = tmp_path / "o.txt"
+    with Simulator(-1) as s:
+        s.dmri_load_tuning(str(good))
+        s.dmri_save_tuning(str(out))
+        lines = out.read_text().splitlines()
+        assert lines[0] == "dmri-tuning-v1"
+        assert sorted(lines[1:]) == sorted(good.read_text().splitlines()[1:])
+        for text in ["nope\n", "dmri-tuning-v1\nkey 12 512 0 0 0.1\n",
+                     "dmri-tuning-v1\nkey 64 512 0 0\n", "dmri-tuning-v1\nkey 64 0 0 0 0.1\n",
+                     "dmri-tuning-v1\nkey 64 512 0 0 0.1 extra\n"]:
+            bad = tmp_path / "bad.txt"
+            bad.write_text(text)
+            with pytest.raises(DmriError, match="DMRI_E_INVALID"):
+                s.dmri_load_tuning(str(bad))
+        with pytest.raises(DmriError, match="DMRI_E_INVALID"):
+            s.dmri_load_tuning(str(tmp_path / "missing.txt"))
+        s.dmri_save_tuning(str(out))
+        assert sorted(out.read_text().splitlines()[1:]) == sorted(lines[1:])
