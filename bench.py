@@ -265,7 +265,8 @@ def main():
                          "value line is then not the full-echo workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+                    help="also run a plain 1 GiB device copy and a 1 GiB gather of 1 KiB rows "
+                         "in random order (for HBM counter scaling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -331,6 +332,19 @@ def main():
             torch.mul(a, 2.0, out=bcopy)  # one elementwise kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         del a, bcopy
+        # Gather leg: 1 KiB rows in a seeded random order (the SpMV's access
+        # shape: whole rows of a tile, in an order set by the mesh), each
+        # source row read once: 1 GiB gathered, 1 GiB written.
+        src = torch.empty((1 << 20, 256), dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        gen = torch.Generator(device="cpu")
+        gen.manual_seed(0)
+        perm = torch.randperm(1 << 20, generator=gen).to("cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.index_select(src, 0, perm, out=dst)
+        torch.cuda.synchronize()
+        del src, dst, perm
 
     for w in range(args.warmup):
         sig, st = sim.dmri_run(pids, bs, qs)

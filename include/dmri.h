@@ -362,19 +362,23 @@ DMRI_API dmri_status dmri_set_option(dmri_handle h, const char* key, double valu
 DMRI_API dmri_status dmri_get_option(dmri_handle h, const char* key, double* value);
 
 /* ---- Learned initial guess (option "guess" = 2) ----------------------
- * A per-element network corrects the linear extrapolation of the next time
- * step's solution (the theta-scheme of Appendix A marches u^{n-1} -> u^n;
- * the network only moves the Krylov starting point, the solve and its
- * stopping test are unchanged). For element (DOF i, system s) the inputs are
- * 16 features: relative first difference (u^{n-1} - u^{n-2}) / |u^{n-1}| and
- * phase u^{n-1} / |u^{n-1}| (Re, Im), the changes of G F(t) over the last two
- * steps (x10), G F(t^n), dt D (G F)^2 at t^n and t^{n-1}, (q . x) / 10 with x
- * from the box centre in um, compartment index, membrane flag, zeros. The
- * network 16 -> 64 -> 64 -> 2 (ReLU) predicts 100 (u^n - (2u^{n-1} - u^{n-2}))
- * / |u^{n-1}| (Re, Im; recorded targets clipped to [-100, 100]). Layers run as BF16 matrix-core products with FP32
- * accumulation; the parameters are FP32, packed W1[16][64], b1[64],
- * W2[64][64], b2[64], W3[64][2], b3[2] (row-major, x W + b). Non-finite
- * predictions fall back to u^{n-1} element by element. */
+ * A per-element network corrects the damped cubic extrapolation of the next
+ * time step's solution (the theta-scheme of Appendix A marches u^{n-1} ->
+ * u^n; the network only moves the Krylov starting point, the solve and its
+ * stopping test are unchanged). With u_k = u^{n-1-k} (k = 0..4), the base is
+ * x_dc = (49 u_0 - 36 u_1 - 26 u_2 + 44 u_3 - 15 u_4) / 16 (option guess = 1's
+ * default) and the scale is s = |u_0 - u_1|. For element (DOF i, system s)
+ * the 16 features are: (u_k - u_{k+1}) / s for k = 0..3 (Re, Im), the phase
+ * u_0 / |u_0| (Re, Im), the changes of G F(t) over the last two steps (x10),
+ * G F(t^n), dt D (G F(t^n))^2, (q . x) / 10 with x from the box centre in um,
+ * the membrane flag; all zero where s or |u_0| is 0. The network 16 -> 64 ->
+ * 64 -> 2 (ReLU) predicts 100 (u^n - x_dc) / s (Re, Im; recorded targets
+ * clipped to [-100, 100]); the guess is x_dc + s y / 100, so an element
+ * whose history did not change gets no correction. Layers run as BF16
+ * matrix-core products with FP32 accumulation; the parameters are FP32,
+ * packed W1[16][64], b1[64], W2[64][64], b2[64], W3[64][2], b3[2]
+ * (row-major, x W + b). Non-finite predictions fall back to x_dc element by
+ * element; the first four steps use the extrapolation of guess = 1. */
 #define DMRI_GUESS_N_FEATURES 16
 #define DMRI_GUESS_N_PARAMS 5378
 
@@ -402,7 +406,7 @@ DMRI_API dmri_status dmri_save_tuning(dmri_handle h, const char* path);
 DMRI_API dmri_status dmri_load_tuning(dmri_handle h, const char* path);
 
 /* Record training samples during later dmri_run / dmri_run_device calls:
- * at every step n >= 2, every stride-th element of the batch (a different
+ * at every step n >= 5, every stride-th element of the batch (a different
  * offset each step) appends its features to d_features ([capacity][16]
  * float32, device) and its target to d_targets ([capacity][2] float32,
  * device) until capacity samples are held; capacity = 0 stops recording.

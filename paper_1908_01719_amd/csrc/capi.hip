@@ -644,8 +644,10 @@ struct History {
 };
 
 // History length needed by the guess options: polynomial extrapolation of
-// order p uses p + 1 past solutions; the learned guess uses two.
+// order p uses p + 1 past solutions (p + 2 damped); the learned guess
+// corrects the damped cubic and uses five.
 int history_len(const dmri_ctx* h) {
+    if (opts(h).guess == 2) return kMlpHist;
     if (opts(h).guess != 1) return 2;
     return std::min(kMaxHist, std::max(2, opts(h).extrap_order + 1 + (opts(h).extrap_damp ? 1 : 0)));
 }
@@ -704,10 +706,25 @@ int prepare_guess(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
                   const std::vector<double>& F, const std::vector<double>& f, int n,
                   int64_t n_sys, const History<typename Vec2Of<T>::type>& hs, Timer& timer) {
     const int og = opts(h).guess;
-    if (og == 1) {
-        const int p = opts(h).extrap_order;
+    if (og == 2 && hs.avail >= kMlpHist) {
+        if constexpr (sizeof(T) == 8) {
+            MlpHist mh{};
+            extrap_weights_damped(3, mh.c);
+            for (int k = 0; k < kMlpHist; ++k) mh.u[k] = hs.u(k);
+            timer.run(5, [&] {
+                launch_mlp_guess(lane(h).stream, g, h->model.theta.p, dofs, lane(h).ws.gq.p,
+                                 mlp_step(h, tr, F, f, n), static_cast<int32_t>(n_sys), mh,
+                                 hs.x());
+            });
+            return 2;
+        }
+    }
+    // The first steps of the learned guess (history shorter than five) use
+    // the same extrapolation as guess = 1 with the default cubic order.
+    if (og == 1 || og == 2) {
+        const int p = og == 1 ? opts(h).extrap_order : 3;
         ExtrapTerms<T> t{};
-        if (opts(h).extrap_damp && hs.avail >= p + 2 && p + 2 <= kMaxHist) {
+        if ((og == 2 || opts(h).extrap_damp) && hs.avail >= p + 2 && p + 2 <= kMaxHist) {
             t.m = p + 2;
             extrap_weights_damped(p, t.c);
         } else {
@@ -721,33 +738,26 @@ int prepare_guess(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
         timer.run(6, [&] { launch_combine<T>(lane(h).stream, g, t, hs.x()); });
         return 2;
     }
-    if (og == 2 && hs.avail >= 2) {
-        if constexpr (sizeof(T) == 8) {
-            timer.run(5, [&] {
-                launch_mlp_guess(lane(h).stream, g, h->model.theta.p, dofs, lane(h).ws.gq.p,
-                                 mlp_step(h, tr, F, f, n), static_cast<int32_t>(n_sys), hs.u(0),
-                                 hs.u(1), hs.x());
-            });
-            return 2;
-        }
-    }
     return 0;
 }
 
-// Append training samples of step n (u1 = u^{n-1}, u2 = u^{n-2}, un = u^n)
-// while the registered recorder has room.
+// Append training samples of step n (history u^{n-1} .. u^{n-5}, solved
+// un = u^n) while the registered recorder has room.
 void record_samples(dmri_ctx* h, const Geom& g, const MlpDofs& dofs, bool tr,
                     const std::vector<double>& F, const std::vector<double>& f, int n,
-                    int64_t n_sys, const double2* u1, const double2* u2, const double2* un) {
+                    int64_t n_sys, const History<double2>& hs, const double2* un) {
     GuessModel& M = h->model;
-    if (n < 2 || M.rec_cap <= 0 || M.rec_count >= M.rec_cap) return;
+    if (n < 2 || hs.avail < kMlpHist || M.rec_cap <= 0 || M.rec_count >= M.rec_cap) return;
+    MlpHist mh{};
+    extrap_weights_damped(3, mh.c);
+    for (int k = 0; k < kMlpHist; ++k) mh.u[k] = hs.u(k);
     const int64_t nv = static_cast<int64_t>(g.n_rows) * g.ld;
     const int64_t offset = static_cast<int64_t>((static_cast<uint64_t>(n) * 2654435761u) %
                                                 static_cast<uint64_t>(M.rec_stride));
     if (offset >= nv) return;
     const int64_t cnt = (nv - offset + M.rec_stride - 1) / M.rec_stride;
     launch_mlp_record(lane(h).stream, g, dofs, lane(h).ws.gq.p, mlp_step(h, tr, F, f, n),
-                      static_cast<int32_t>(n_sys), u1, u2, un, M.rec_stride, offset, M.rec_count,
+                      static_cast<int32_t>(n_sys), mh, un, M.rec_stride, offset, M.rec_count,
                       M.rec_cap, M.rec_X, M.rec_T);
     M.rec_count = std::min(M.rec_cap, M.rec_count + cnt);
 }
@@ -1228,8 +1238,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
                                   last_iters - 2, opts(h).max_iter);
         last_iters = done;
         if constexpr (kF64) {
-            if (hs.avail >= 2)
-                record_samples(h, g, dofs, tr, F, f, n, n_sys, hs.u(0), hs.u(1), hs.x());
+            record_samples(h, g, dofs, tr, F, f, n, n_sys, hs, hs.x());
         }
         progress_line(h, n, N, done, t0);
         hs.advance();
@@ -1416,7 +1425,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
             for (int64_t i = 0; i < n_sys; ++i)
                 if (act[i]) flag_or[i] |= 1;
         }
-        if (hs.avail >= 2) record_samples(h, g, dofs, tr, F, f, n, n_sys, hs.u(0), hs.u(1), hs.x());
+        record_samples(h, g, dofs, tr, F, f, n, n_sys, hs, hs.x());
         progress_line(h, n, N, step_iters, t0);
         hs.advance();
     }

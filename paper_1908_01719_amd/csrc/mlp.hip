@@ -2,9 +2,9 @@
 //
 // Every wavefront owns 64 samples at a time. The three layers are matrix
 // products of a [64 samples x K] activation tile in LDS with a weight tile in
-// LDS, done with v_mfma_f32_32x32x8_bf16 (32x32 output blocks, K in steps of
-// 8, FP32 accumulation). Lane l of an MFMA holds A[l % 32][4 (l / 32) + t]
-// and B[4 (l / 32) + t][l % 32] (t = 0..3), and accumulator element v of
+// LDS, done with gfx950's v_mfma_f32_32x32x16_bf16 (32x32 output blocks, K in
+// steps of 16, FP32 accumulation). Lane l of an MFMA holds A[l % 32][8 (l / 32)
+// + t] and B[8 (l / 32) + t][l % 32] (t = 0..7), and accumulator element v of
 // lane l is C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]. Biases and ReLU are
 // applied when the accumulators are written back to LDS as BF16.
 //
@@ -21,7 +21,7 @@
 namespace dmri {
 namespace {
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 using bf16 = unsigned short;
 
@@ -91,27 +91,30 @@ __device__ inline int acc_col(int bn) { return bn * 32 + (lane_id() & 31); }
 
 // acc[bm][bn] += A[bm block rows][K] * B[K][bn block cols]; A(i, k) at
 // A[i * a_si + k * a_sk], B(k, j) at B[k * b_sk + j * b_sj] (LDS, BF16).
+// K is a multiple of 16.
 template <int MB, int NB>
 __device__ inline void wave_gemm(const bf16* A, int a_si, int a_sk, const bf16* B, int b_sk,
                                  int b_sj, int K, f32x16_t (&acc)[MB][NB]) {
     const int i = lane_id() & 31, kg = lane_id() >> 5;
-    for (int k0 = 0; k0 < K; k0 += 8) {
-        bf16x4_t a[MB], b[NB];
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x8_t a[MB], b[NB];
 #pragma unroll
         for (int bm = 0; bm < MB; ++bm)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                a[bm][t] = static_cast<short>(A[(bm * 32 + i) * a_si + (k0 + 4 * kg + t) * a_sk]);
+            for (int t = 0; t < 8; ++t)
+                a[bm][t] = __builtin_bit_cast(
+                    __bf16, A[(bm * 32 + i) * a_si + (k0 + 8 * kg + t) * a_sk]);
 #pragma unroll
         for (int bn = 0; bn < NB; ++bn)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                b[bn][t] = static_cast<short>(B[(k0 + 4 * kg + t) * b_sk + (bn * 32 + i) * b_sj]);
+            for (int t = 0; t < 8; ++t)
+                b[bn][t] = __builtin_bit_cast(
+                    __bf16, B[(k0 + 8 * kg + t) * b_sk + (bn * 32 + i) * b_sj]);
 #pragma unroll
         for (int bm = 0; bm < MB; ++bm)
 #pragma unroll
             for (int bn = 0; bn < NB; ++bn)
-                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[bm], b[bn], acc[bm][bn],
+                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[bm], b[bn], acc[bm][bn],
                                                                       0, 0, 0);
     }
 }
@@ -176,31 +179,43 @@ __device__ inline void clear_pad(WaveLds& s) {
     for (int c = 0; c < 32; ++c) s.dY[l * 32 + c] = 0;
 }
 
-// Features of one element (see mlp.hpp): relative first difference and
-// phase of u^{n-1}, gradient-coefficient changes around the step, decay per
-// step, position along the gradient, compartment and membrane flags.
-// Returns |u^{n-1}| (0 when the element carries no magnetization).
-__device__ inline double features(float (&f)[kMlpIn], double2 a, double2 b, double4 gg,
-                                  const MlpStep& ms, float4 geo, float2 fl) {
-    const double m = sqrt(a.x * a.x + a.y * a.y);
+// Features of one element (see mlp.hpp and include/dmri.h): the last four
+// changes of the history relative to the newest one, d_k / s with d_k =
+// u^{n-1-k} - u^{n-2-k} and s = |d_0| (Re, Im; the first has modulus 1), the
+// phase of u^{n-1}, the changes of G F over the last two steps, G F(t^n),
+// dt D (G F)^2 at t^n, the position along the gradient, the membrane flag.
+// Writes the damped cubic x_dc; returns s (0: no correction, features 0).
+__device__ inline double features(float (&f)[kMlpIn], const double2 (&v)[kMlpHist],
+                                  const double (&c)[kMlpHist], double4 gg, const MlpStep& ms,
+                                  float4 geo, float2 fl, double2& xdc) {
+    xdc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < kMlpHist; ++k) {
+        xdc.x += c[k] * v[k].x;
+        xdc.y += c[k] * v[k].y;
+    }
 #pragma unroll
     for (int k = 0; k < kMlpIn; ++k) f[k] = 0.0f;
-    if (!(m > 1e-200) || !isfinite(m)) return 0.0;
+    const double sx = v[0].x - v[1].x, sy = v[0].y - v[1].y;
+    const double sc = sqrt(sx * sx + sy * sy);
+    const double m = sqrt(v[0].x * v[0].x + v[0].y * v[0].y);
+    if (!(sc > 1e-200) || !isfinite(sc) || !(m > 0.0) || !isfinite(m)) return 0.0;
+#pragma unroll
+    for (int k = 0; k < kMlpHist - 1; ++k) {
+        f[2 * k] = static_cast<float>((v[k].x - v[k + 1].x) / sc);
+        f[2 * k + 1] = static_cast<float>((v[k].y - v[k + 1].y) / sc);
+    }
     const double G = gg.x;
     const double g0 = G * ms.F0, g1 = G * ms.F1, g2 = G * ms.F2;
-    f[0] = static_cast<float>((a.x - b.x) / m);
-    f[1] = static_cast<float>((a.y - b.y) / m);
-    f[2] = static_cast<float>(a.x / m);
-    f[3] = static_cast<float>(a.y / m);
-    f[4] = static_cast<float>(10.0 * (g0 - g1));
-    f[5] = static_cast<float>(10.0 * (g1 - g2));
-    f[6] = static_cast<float>(g0);
-    f[7] = static_cast<float>(ms.dt * geo.w * g0 * g0);
-    f[8] = static_cast<float>(0.1 * (gg.y * geo.x + gg.z * geo.y + gg.w * geo.z));
-    f[9] = fl.x;
-    f[10] = fl.y;
-    f[11] = static_cast<float>(ms.dt * geo.w * g1 * g1);
-    return m;
+    f[8] = static_cast<float>(v[0].x / m);
+    f[9] = static_cast<float>(v[0].y / m);
+    f[10] = static_cast<float>(10.0 * (g0 - g1));
+    f[11] = static_cast<float>(10.0 * (g1 - g2));
+    f[12] = static_cast<float>(g0);
+    f[13] = static_cast<float>(ms.dt * geo.w * g0 * g0);
+    f[14] = static_cast<float>(0.1 * (gg.y * geo.x + gg.z * geo.y + gg.w * geo.z));
+    f[15] = fl.y;
+    return sc;
 }
 
 // Element e of a tile-major vector: (tile, row, lane-in-tile).
@@ -213,9 +228,7 @@ __device__ inline void decode(const Geom& g, int64_t e, int& row, int& sys) {
 
 __global__ __launch_bounds__(kBlk) void k_mlp_guess(Geom g, const float* __restrict__ theta,
                                                      MlpDofs dofs, const double4* __restrict__ gq,
-                                                     MlpStep ms, int32_t n_sys,
-                                                     const double2* __restrict__ u1,
-                                                     const double2* __restrict__ u2,
+                                                     MlpStep ms, int32_t n_sys, MlpHist hist,
                                                      double2* __restrict__ x) {
     __shared__ WeightLds w;
     __shared__ WaveLds ws[kWavesPerBlock];
@@ -228,30 +241,31 @@ __global__ __launch_bounds__(kBlk) void k_mlp_guess(Geom g, const float* __restr
     const int l = lane_id();
     for (int64_t base = wave0 * 64; base < n; base += nwaves * 64) {
         const int64_t e = base + l;
-        double2 a = make_double2(0.0, 0.0), b = a;
-        double m = 0.0;
+        double2 xdc = make_double2(0.0, 0.0);
+        double sc = 0.0;
         float f[kMlpIn];
-        int row = 0, sys = 0;
-        if (e < n) {
-            decode(g, e, row, sys);
-            a = u1[e];
-            b = u2[e];
-            m = features(f, sys < n_sys ? a : make_double2(0.0, 0.0), b, gq[sys], ms,
-                         dofs.geo[row], dofs.flags[row]);
-        } else {
 #pragma unroll
-            for (int k = 0; k < kMlpIn; ++k) f[k] = 0.0f;
+        for (int k = 0; k < kMlpIn; ++k) f[k] = 0.0f;
+        if (e < n) {
+            int row = 0, sys = 0;
+            decode(g, e, row, sys);
+            double2 v[kMlpHist];
+#pragma unroll
+            for (int k = 0; k < kMlpHist; ++k) v[k] = hist.u[k][e];
+            sc = features(f, v, hist.c, gq[sys], ms, dofs.geo[row], dofs.flags[row], xdc);
+            if (sys >= n_sys) sc = 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < kMlpIn; ++k) s.X[l * 32 + k] = to_bf16(f[k]);
+        for (int k = 0; k < kMlpIn; ++k) s.X[l * 32 + k] = to_bf16(sc > 0.0 ? f[k] : 0.0f);
         forward_wave(w, s);
         if (e < n) {
-            double2 out;
-            const double ex = 2.0 * a.x - b.x, ey = 2.0 * a.y - b.y;
-            const double cs = m / kMlpTargetScale;
-            out.x = ex + cs * s.Y[l * 2 + 0];
-            out.y = ey + cs * s.Y[l * 2 + 1];
-            if (!(isfinite(out.x) && isfinite(out.y))) out = a;
+            double2 out = xdc;
+            if (sc > 0.0) {
+                const double cs = sc / kMlpTargetScale;
+                out.x += cs * s.Y[l * 2 + 0];
+                out.y += cs * s.Y[l * 2 + 1];
+                if (!(isfinite(out.x) && isfinite(out.y))) out = xdc;
+            }
             x[e] = out;
         }
     }
@@ -259,8 +273,7 @@ __global__ __launch_bounds__(kBlk) void k_mlp_guess(Geom g, const float* __restr
 
 __global__ __launch_bounds__(kBlk) void k_mlp_record(Geom g, MlpDofs dofs,
                                                       const double4* __restrict__ gq, MlpStep ms,
-                                                      int32_t n_sys, const double2* __restrict__ u1,
-                                                      const double2* __restrict__ u2,
+                                                      int32_t n_sys, MlpHist hist,
                                                       const double2* __restrict__ un,
                                                       int64_t stride, int64_t offset, int64_t base,
                                                       int64_t capacity, float* __restrict__ X,
@@ -275,17 +288,20 @@ __global__ __launch_bounds__(kBlk) void k_mlp_record(Geom g, MlpDofs dofs,
         int row, sys;
         decode(g, e, row, sys);
         float f[kMlpIn];
-        const double2 a = u1[e], b = u2[e], c = un[e];
-        const double m = features(f, sys < n_sys ? a : make_double2(0.0, 0.0), b, gq[sys], ms,
-                                  dofs.geo[row], dofs.flags[row]);
+        double2 v[kMlpHist], xdc;
 #pragma unroll
-        for (int k = 0; k < kMlpIn; ++k) X[pos * kMlpIn + k] = f[k];
+        for (int k = 0; k < kMlpHist; ++k) v[k] = hist.u[k][e];
+        double sc = features(f, v, hist.c, gq[sys], ms, dofs.geo[row], dofs.flags[row], xdc);
+        if (sys >= n_sys) sc = 0.0;
+        const double2 c = un[e];
         float t0 = 0.0f, t1 = 0.0f;
-        if (m > 0.0) {
-            t0 = static_cast<float>(kMlpTargetScale * (c.x - (2.0 * a.x - b.x)) / m);
-            t1 = static_cast<float>(kMlpTargetScale * (c.y - (2.0 * a.y - b.y)) / m);
+        if (sc > 0.0) {
+            t0 = static_cast<float>(kMlpTargetScale * (c.x - xdc.x) / sc);
+            t1 = static_cast<float>(kMlpTargetScale * (c.y - xdc.y) / sc);
         }
-        // Relative corrections beyond 1 (|u^{n-1}| near zero) are clipped so a
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k) X[pos * kMlpIn + k] = sc > 0.0 ? f[k] : 0.0f;
+        // Corrections larger than the history's last change are clipped, so a
         // few such samples cannot dominate the squared error.
         T[pos * 2 + 0] = fminf(fmaxf(t0, -kMlpTargetScale), kMlpTargetScale);
         T[pos * 2 + 1] = fminf(fmaxf(t1, -kMlpTargetScale), kMlpTargetScale);
@@ -490,24 +506,24 @@ inline void check(const char* what) {
 }  // namespace
 
 void launch_mlp_guess(hipStream_t st, const Geom& g, const float* theta, MlpDofs dofs,
-                      const double4* gq, MlpStep ms, int32_t n_sys, const double2* u1,
-                      const double2* u2, double2* x) {
+                      const double4* gq, MlpStep ms, int32_t n_sys, const MlpHist& hist,
+                      double2* x) {
     const int64_t n = static_cast<int64_t>(g.n_rows) * g.ld;
     const int64_t waves = (n + 63) / 64;
     const unsigned blocks = static_cast<unsigned>(
         std::min<int64_t>(2048, (waves + kWavesPerBlock - 1) / kWavesPerBlock));
-    k_mlp_guess<<<blocks, kBlk, 0, st>>>(g, theta, dofs, gq, ms, n_sys, u1, u2, x);
+    k_mlp_guess<<<blocks, kBlk, 0, st>>>(g, theta, dofs, gq, ms, n_sys, hist, x);
     check("mlp_guess");
 }
 
 void launch_mlp_record(hipStream_t st, const Geom& g, MlpDofs dofs, const double4* gq,
-                       MlpStep ms, int32_t n_sys, const double2* u1, const double2* u2,
-                       const double2* un, int64_t stride, int64_t offset, int64_t base,
-                       int64_t capacity, float* X, float* T) {
+                       MlpStep ms, int32_t n_sys, const MlpHist& hist, const double2* un,
+                       int64_t stride, int64_t offset, int64_t base, int64_t capacity, float* X,
+                       float* T) {
     const int64_t n = static_cast<int64_t>(g.n_rows) * g.ld;
     const int64_t cnt = (n - offset + stride - 1) / stride;
     const unsigned blocks = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(4096, (cnt + 255) / 256)));
-    k_mlp_record<<<blocks, 256, 0, st>>>(g, dofs, gq, ms, n_sys, u1, u2, un, stride, offset, base,
+    k_mlp_record<<<blocks, 256, 0, st>>>(g, dofs, gq, ms, n_sys, hist, un, stride, offset, base,
                                          capacity, X, T);
     check("mlp_record");
 }

@@ -38,7 +38,7 @@ def init_params(seed: int = 0, out_scale: float = 0.1) -> np.ndarray:
 
 
 def zero_params() -> np.ndarray:
-    """All-zero network: its guess is the plain linear extrapolation."""
+    """All-zero network: its guess is the damped cubic extrapolation itself."""
     return np.zeros(GUESS_N_PARAMS, np.float32)
 
 

@@ -5,11 +5,14 @@
   multiply in BF16 and accumulate in FP32; tolerances follow from BF16's
   2^-9 relative rounding of the hidden activations);
 * recorded features and targets against the definitions in include/dmri.h,
-  computed from the oracle's solutions u^0, u^1, u^2;
+  computed from the oracle's solutions u^0 .. u^5;
 * the learned guess never changes the accepted answer: signals stay within
   1e-9 of the oracle for any network, and a network with non-finite weights
-  falls back to the previous step exactly;
-* training by the library's own backward and Adam kernels lowers the loss.
+  falls back to the damped cubic extrapolation;
+* training by the library's own backward and Adam kernels lowers the loss;
+* trained on the solver's trajectories of some geometries and run on a
+  held-out one, the network's effect on the Krylov iterations against the
+  damped cubic it corrects is measured and asserted.
 """
 
 import numpy as np
@@ -130,8 +133,8 @@ def _perm(prob, exp, asm):
 
 
 def test_recorded_samples_match_definition(env):
-    """Every element of a 3-system batch after step 2, against the features
-    and targets recomputed from the oracle's u^0, u^1, u^2."""
+    """Every element of a 3-system batch at step 5, against the features and
+    targets recomputed from the oracle's u^0 .. u^5."""
     torch, Sim, lg = env
     prob = di.cylinder_box(n=8, half=6.0, r=4.3, kappa=5e-3, D_in=1.5e-3, T2=(6e4, 4e4),
                            u0=(1.0, 0.7))
@@ -140,12 +143,14 @@ def test_recorded_samples_match_definition(env):
     asm = fem.assemble(prob)
     U = []
     for s in range(3):
-        u1 = timestep.solve_transformed(asm, SHORT, b[s], q[s], n_steps=1, return_u=True)[1]
-        u2 = timestep.solve_transformed(asm, SHORT, b[s], q[s], n_steps=2, return_u=True)[1]
-        U.append((asm.u0.astype(np.complex128), u1, u2))
+        hist = [asm.u0.astype(np.complex128)]
+        for k in range(1, 6):
+            hist.append(timestep.solve_transformed(asm, SHORT, b[s], q[s], n_steps=k,
+                                                   return_u=True)[1])
+        U.append(hist)
     with Sim(0) as sim:
         sim.set_sequence(SHORT)
-        sim.set_options(rtol=1e-13, n_steps=2, sys_tile=8)
+        sim.set_options(rtol=1e-13, n_steps=5, sys_tile=8)
         pid = sim.add_problem(prob)
         exp = sim.dmri_export_operator(pid)
         n_dof = exp["w"].shape[0]
@@ -154,7 +159,7 @@ def test_recorded_samples_match_definition(env):
         T = torch.zeros((cap, 2), dtype=torch.float32, device="cuda")
         sim.dmri_guess_record(X, T, cap, 1)
         sim.dmri_run([pid] * 3, b, q)
-        assert sim.dmri_guess_record_count() == cap
+        assert sim.dmri_guess_record_count() == cap  # step 5 only: one tile's elements
         X, T = X.cpu().numpy().astype(np.float64), T.cpu().numpy().astype(np.float64)
     perm = _perm(prob, exp, asm)
     # element e of the tile-major batch: row e // 8, system e % 8 (one tile)
@@ -172,30 +177,39 @@ def test_recorded_samples_match_definition(env):
     for c, nd in zip(asm.dof_comp, asm.dof_node):
         n_comp_of_node[int(nd)] = n_comp_of_node.get(int(nd), 0) + 1
     memb = np.array([1.0 if n_comp_of_node[int(tn[nd])] > 1 else 0.0 for nd in exp["dof_node"]])
+    cw = np.array([49.0, -36.0, -26.0, 44.0, -15.0]) / 16.0
     for s in range(3):
-        u0, u1, u2 = (v[perm] for v in U[s])
-        m = np.abs(u1)
+        u = [v[perm] for v in U[s]]          # u[k] = u^k, k = 0..5
+        hist = [u[4 - k] for k in range(5)]  # u_k = u^{n-1-k} at n = 5
+        sc = np.abs(hist[0] - hist[1])
         G = float(oseq.b_to_G(b[s], SHORT.delta, SHORT.Delta))
-        g0, g1, g2 = G * F[2], G * F[1], G * F[0]
+        g0, g1, g2 = G * F[5], G * F[4], G * F[3]
         f = np.zeros((n_dof, 16))
-        f[:, 0], f[:, 1] = ((u1 - u0) / m).real, ((u1 - u0) / m).imag
-        f[:, 2], f[:, 3] = (u1 / m).real, (u1 / m).imag
-        f[:, 4] = 10 * (g0 - g1)
-        f[:, 5] = 10 * (g1 - g2)
-        f[:, 6] = g0
-        f[:, 7] = SHORT.dt * D * g0 ** 2
-        f[:, 8] = 0.1 * xyz @ (q[s] / np.linalg.norm(q[s]))
-        f[:, 9] = exp["dof_comp"]
-        f[:, 10] = memb
-        f[:, 11] = SHORT.dt * D * g1 ** 2
-        cols = [c for c in range(16) if c != 8]
-        np.testing.assert_allclose(Xr[:, s, cols], f[:, cols], rtol=2e-6, atol=1e-6)
-        np.testing.assert_allclose(Xr[inner, s, 8], f[inner, 8], rtol=2e-6, atol=1e-6)
-        tgt = 100.0 * (u2 - (2 * u1 - u0)) / m
+        for k in range(4):
+            d = (hist[k] - hist[k + 1]) / sc
+            f[:, 2 * k], f[:, 2 * k + 1] = d.real, d.imag
+        ph = hist[0] / np.abs(hist[0])
+        f[:, 8], f[:, 9] = ph.real, ph.imag
+        f[:, 10] = 10 * (g0 - g1)
+        f[:, 11] = 10 * (g1 - g2)
+        f[:, 12] = g0
+        f[:, 13] = SHORT.dt * D * g0 ** 2
+        f[:, 14] = 0.1 * xyz @ (q[s] / np.linalg.norm(q[s]))
+        f[:, 15] = memb
+        assert np.all(sc > 0)
+        # the relative differences lose digits where s is small against |u|
+        cols = [c for c in range(16) if c != 14]
+        tol = 2e-6 + 1e-12 * (np.abs(hist[0]) / sc)[:, None]
+        err = np.abs(Xr[:, s, cols] - f[:, cols])
+        assert np.all(err <= tol + 2e-6 * np.abs(f[:, cols])), err.max()
+        np.testing.assert_allclose(Xr[inner, s, 14], f[inner, 14], rtol=2e-6, atol=1e-6)
+        xdc = sum(cw[k] * hist[k] for k in range(5))
+        tgt = 100.0 * (u[5] - xdc) / sc
         tgt = np.stack([tgt.real, tgt.imag], axis=1).clip(-100, 100)
-        err = np.max(np.abs(Tr[:, s] - tgt))
-        _say("  system %d: max target error %.2e (target rms %.2e)" % (s, err, np.sqrt(np.mean(tgt ** 2))))
-        assert err < 1e-4 + 1e-5 * np.max(np.abs(tgt))
+        terr = np.abs(Tr[:, s] - tgt)
+        _say("  system %d: max target error %.2e (target rms %.2e)"
+             % (s, terr.max(), np.sqrt(np.mean(tgt ** 2))))
+        assert np.all(terr <= 1e-4 + 1e-5 * np.abs(tgt) + 1e-9 * (np.abs(u[5]) / sc)[:, None])
 
 
 def _cyl_case():
@@ -215,7 +229,7 @@ def test_learned_guess_keeps_answer(env, precision):
         sim.set_sequence(SHORT)
         sim.set_options(rtol=1e-12, precision=precision)
         pid = sim.add_problem(prob)
-        sim.set_options(guess=0)
+        sim.set_options(guess=1)
         sig0, st0 = sim.dmri_run([pid] * len(b), b, q)
         sim.set_options(guess=2)
         sim.dmri_guess_set_params(lg.init_params(3, out_scale=1.0))
@@ -228,10 +242,11 @@ def test_learned_guess_keeps_answer(env, precision):
         assert st["status"] == "DMRI_OK"
         err = np.abs(sig - ref) / np.maximum(np.abs(ref), 1e-8 * abs(ref[0]))
         assert err.max() < 1e-9, err.max()
-    _say("  iterations guess0 %d, random network %d, NaN network %d"
+    _say("  iterations damped cubic %d, random network %d, NaN network %d"
          % (st0["total_iterations"], st2["total_iterations"], stn["total_iterations"]))
-    # non-finite network => every element falls back to u^{n-1} (= guess 0)
-    assert stn["total_iterations"] == st0["total_iterations"]
+    # non-finite network => every element falls back to the damped cubic
+    # (guess 1), formed by other code: the same iterations up to rounding
+    assert abs(stn["total_iterations"] - st0["total_iterations"]) <= 0.01 * st0["total_iterations"]
     assert np.array_equal(sign, sig0)
 
 
@@ -263,42 +278,50 @@ def test_guess_api_errors(env, tmp_path):
             sim.dmri_run([pid], b[:1], q[:1])
 
 
-def test_trained_network_gain_on_held_out_geometry(env):
-    """Train on trajectories of one cylinder geometry, evaluate on another
-    (different radius, permeability and b-values): the trained network's
-    correction of the linear extrapolation has a lower mean squared error on
-    the held-out samples than the zero network (the plain extrapolation), and
-    the learned guess keeps the signals. The Krylov iterations of the three
-    guesses are reported (the per-element error gain does not by itself
-    lower them: the network's error varies from element to element)."""
+def test_trained_network_on_held_out_geometry(env):
+    """Train on trajectories of two seeded-cell geometries and a cylinder box
+    (PGSE of the benchmark, dt = 100 us), evaluate on a held-out seeded-cell
+    geometry (seed 100): the held-out loss against the zero network (the
+    damped cubic itself) and the Krylov iterations of the benchmark's solver
+    settings (mixed precision, rtol 1e-6) with the damped cubic and with the
+    trained correction. Signals stay within 1e-4 of each other."""
     torch, Sim, lg = env
-    train = di.cylinder_box(n=12, half=6.0, r=4.0, kappa=5e-3, D_in=2e-3, T2=(6e4, 4e4))
-    held = di.cylinder_box(n=12, half=6.0, r=3.2, kappa=1e-3, D_in=1.2e-3, T2=(5e4, 5e4))
-    seq = di.Sequence(2000.0, 4000.0, 100.0, 0.5)
+    seq = di.PGSE_SHORT
+    trains = [di.seeded_cells(0, n_fixed=20), di.seeded_cells(1, n_fixed=20)]
+    cyl = di.cylinder_box(n=16, half=6.0, r=4.0, kappa=5e-3, D_in=2e-3)
+    held, _, sl = di.seeded_cells(100, n_fixed=24)
     bt = np.linspace(500.0, 5000.0, 16)
     qt = di.fibonacci_directions(16)
-    bh = np.linspace(700.0, 4500.0, 8)
-    qh = di.fibonacci_directions(8)[::-1].copy()
-    ref = timestep.signals(held, seq, bh, qh, solver="splu")
     with Sim(0) as sim:
         sim.set_sequence(seq)
-        sim.set_options(rtol=1e-10)
-        pt, ph = sim.add_problem(train), sim.add_problem(held)
-        X, T = lg.record(sim, [(pt, bt, qt)], capacity=400_000, stride=7)
-        Xv, Tv = lg.record(sim, [(ph, bh, qh)], capacity=200_000, stride=11)
+        sim.set_options(rtol=1e-10, guess=1)
+        pids = [sim.add_problem(p) for p, _, _ in trains] + [sim.add_problem(cyl)]
+        ph = sim.add_problem(held)
+        X, T = lg.record(sim, [(p, bt, qt) for p in pids], capacity=600_000, stride=13)
+        Xv, Tv = lg.record(sim, [(ph, sl.b, sl.q)], capacity=200_000, stride=17)
         sim.dmri_guess_set_params(lg.zero_params())
         l_zero = sim.dmri_guess_eval(Xv, Tv)
         sim.dmri_guess_set_params(lg.init_params(0))
-        hist = lg.train(sim, X, T, iters=1500, lr=2e-3)
+        hist = lg.train(sim, X, T, iters=2000, lr=2e-3)
         l_held = sim.dmri_guess_eval(Xv, Tv)
-        its = {}
-        for g in (0, 1, 2):
-            sim.set_options(guess=g, extrap_order=1)
-            sig, st = sim.dmri_run([ph] * len(bh), bh, qh)
-            its[g] = st["total_iterations"]
-            err = np.abs(sig - ref) / np.maximum(np.abs(ref), 1e-8 * abs(ref[0]))
-            assert err.max() < 1e-8, (g, err.max())
+        sim.set_options(precision=1, rtol=1e-6)
+        out = {}
+        for g in (1, 2):
+            sim.set_options(guess=g)
+            sig, st = sim.dmri_run([ph] * len(sl.b), sl.b, sl.q)
+            assert st["status"] == "DMRI_OK"
+            out[g] = (sig, st["total_iterations"], st["t_solve_s"])
     _say("  %d training samples, train loss %.3e -> %.3e; held-out loss: zero network %.3e, "
-         "trained %.3e; iterations prev/extrap/learned %s"
-         % (X.shape[0], hist[0], hist[-1], l_zero, l_held, its))
-    assert l_held < 0.8 * l_zero
+         "trained %.3e; iterations damped cubic %d (%.2fs), learned %d (%.2fs)"
+         % (X.shape[0], hist[0], hist[-1], l_zero, l_held, out[1][1], out[1][2], out[2][1],
+            out[2][2]))
+    dev = np.abs(out[2][0] - out[1][0]) / np.abs(out[1][0])
+    assert dev.max() < 1e-4
+    # What was measured on one MI355X (deterministic training): the network
+    # learns its target (held-out loss 1.35e2 -> 1.43e1) yet the Krylov
+    # iterations double (13,959 -> 29,612): its correction carries element-
+    # to-element noise that the operator's large eigenvalues amplify in the
+    # initial residual, which a smooth extrapolation error does not. The
+    # damped cubic stays the default guess.
+    assert l_held < 0.2 * l_zero
+    assert out[2][1] > 1.5 * out[1][1]
