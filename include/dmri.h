@@ -262,6 +262,9 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *               DMRI_E_UNSUPPORTED). Every system stops at the same
  *               ||b - A x|| <= rtol ||b|| test
  *  "gmres_m"    GMRES restart length m, 1..32 (default 30)
+ *  "markers"    1: roctx ranges ("dmri batch <systems>", "dmri step <n>")
+ *               around each batch and time step, for profiler timelines
+ *               (rocprofv3 --marker-trace); 0 (default): none
  *  "weak_kappa" scale of kappa_e on weak pseudo-periodic faces, (0, 1e6]
  *               (default 1: the paper's max{D / h}). Larger values couple
  *               the faces more tightly and need a smaller dt (the partner

@@ -60,7 +60,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             if o.strip():
                 print(o)
     tmp = LIB + ".tmp"
-    _run([hipcc, *COMMON, "-shared", "-o", tmp, *objs])
+    _run([hipcc, *COMMON, "-shared", "-o", tmp, *objs, "-L/opt/rocm/lib",
+          "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -13,6 +13,7 @@
 // chunk, and checks the previous chunk's counts while the next one runs.
 // Converged systems drop out inside the kernels (per-system masks).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -195,6 +196,7 @@ struct Options {
     int signal = 1;
     int gmres_m = 30;
     double weak_kappa = 1.0;  // scale of kappa_e on weak pseudo-periodic faces
+    int markers = 0;          // 1: roctx ranges around runs, batches and time steps
 };
 
 // Per-system Krylov state arrays of one solver level.
@@ -1024,6 +1026,23 @@ Coef rhs_coef(const dmri_ctx* h, bool tr, const std::vector<double>& F,
               : Coef{h->seq.f_start[n], 0.0, -(1.0 - th)};
 }
 
+// roctx range for profiler timelines (option "markers"), popped on scope exit.
+struct Marker {
+    bool on;
+    Marker(const dmri_ctx* h, const char* what, int64_t k = -1) : on(opts(h).markers != 0) {
+        if (!on) return;
+        char buf[64];
+        if (k >= 0) std::snprintf(buf, sizeof buf, "dmri %s %lld", what, static_cast<long long>(k));
+        else std::snprintf(buf, sizeof buf, "dmri %s", what);
+        roctxRangePush(buf);
+    }
+    ~Marker() {
+        if (on) roctxRangePop();
+    }
+    Marker(const Marker&) = delete;
+    Marker& operator=(const Marker&) = delete;
+};
+
 void progress_line(dmri_ctx* h, int n, int N, int iters, double t0) {
     if (opts(h).progress > 0 && (n % opts(h).progress == 0 || n == N)) {
         std::fprintf(stderr, "[dmri] step %d/%d: %d iterations, %.2fs\n", n, N, iters,
@@ -1221,6 +1240,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     const double t0 = now_s();
     int last_iters = 8;
     auto step = [&](int n) {
+        const Marker mk(h, "step", n);
         const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
         const int gm = prepare_guess<T>(h, g, dofs, tr, F, f, n, n_sys, hs, timer);
         timer.run(4, [&] {
@@ -1387,6 +1407,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     const double t0 = now_s();
     int last_first_pass = 8;
     for (int n = 1; n <= N; ++n) {
+        const Marker mk(h, "step", n);
         const Coef lhs = lhs_coef(h, tr, F, f, n), rhs = rhs_coef(h, tr, F, f, n);
         const int gm = prepare_guess<double>(h, g, dofs, tr, F, f, n, n_sys, hs, timer);
         timer.run(4, [&] {
@@ -1569,6 +1590,7 @@ TuneChoice autotune(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b
 
 void run_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, const double* d_q,
                double2* d_sig, BatchResult& R) {
+    const Marker mk(h, "batch", n_sys);
     if (!opts(h).autotune) {
         run_batch_with(h, P, n_sys, d_b, d_q, d_sig, R);
         return;
@@ -1983,7 +2005,8 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "weak_kappa") {
             if (!(v > 0 && v <= 1e6)) throw Error(DMRI_E_INVALID, "weak_kappa must be in (0, 1e6]");
             o.weak_kappa = v;
-        } else throw Error(DMRI_E_INVALID, "unknown option " + k);
+        } else if (k == "markers") o.markers = as_int(0, 1);
+        else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
 }
@@ -2025,6 +2048,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "signal") *value = o.signal;
         else if (k == "gmres_m") *value = o.gmres_m;
         else if (k == "weak_kappa") *value = o.weak_kappa;
+        else if (k == "markers") *value = o.markers;
         else if (k == "tuned_sys_tile") *value = h->last_tune.sys_tile;
         else if (k == "tuned_blocks_per_xcd") *value = h->last_tune.blocks_per_xcd;
         else if (k == "tuned_persistent") *value = h->last_tune.persistent;

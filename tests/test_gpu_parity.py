@@ -997,3 +997,31 @@ def test_weak_faces_refusals(Sim):
         pids = torch.full((1,), pid, dtype=torch.int32, device=dev)
         with pytest.raises(Exception, match="DMRI_E_UNSUPPORTED"):
             sim.dmri_run_device_noalloc(pids, b, q, out)
+
+
+# ------------------------- membrane limits and spheres in mixed precision
+@pytest.mark.parametrize("case", ["kappa0", "kappa_large", "spheres"])
+def test_mixed_precision_membrane_limits_and_spheres(Sim, case):
+    # Mixed precision (FP32 inner solves, FP64 refinement) at rtol 1e-12
+    # within 1e-9 of the oracle: decoupled compartments (kappa = 0), a
+    # nearly impermeable-to-free jump (kappa = 5 um/us, the membrane term
+    # dominating its rows), and a seeded geometry with spheres and cylinders.
+    if case == "kappa0":
+        prob = di.cylinder_box(n=10, half=6.0, r=4.0, kappa=0.0, D_in=1.5e-3, u0=(1.0, 0.6))
+    elif case == "kappa_large":
+        prob = di.cylinder_box(n=10, half=6.0, r=4.0, kappa=5.0, D_in=1.5e-3, u0=(1.0, 0.6))
+    else:
+        prob = di.seeded_cells(7, n_fixed=12)[0]
+        assert sum(s["kind"] == "sphere" for s in prob.meta["shapes"]) > 0
+    b = np.array([0.0, 900.0, 2600.0, 4100.0, 1700.0])
+    q = di.fibonacci_directions(5)
+    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(precision=1, rtol=1e-12)
+        pid = sim.add_problem(prob)
+        sig, st = sim.dmri_run([pid] * len(b), b, q)
+    err = rel_err(sig, ref, ref[0])
+    _say("mixed %s: max err %.2e, %d iterations" % (case, err.max(), st["total_iterations"]))
+    assert st["status"] == "DMRI_OK"
+    assert err.max() < 1e-9

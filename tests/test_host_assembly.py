@@ -261,3 +261,14 @@ def test_tuning_file_round_trip(tmp_path):
             s.dmri_load_tuning(str(tmp_path / "missing.txt"))
         s.dmri_save_tuning(str(out))
         assert sorted(out.read_text().splitlines()[1:]) == sorted(lines[1:])
+
+
+def test_marker_and_weak_options():
+    with Simulator(-1) as s:
+        for k, good, bad in (("markers", (0, 1), (2, -1, 0.5)), ("weak_kappa", (0.5, 1e6), (0.0, 2e6))):
+            for v in good:
+                s.dmri_set_option(k, v)
+                assert s.dmri_get_option(k) == v
+            for v in bad:
+                with pytest.raises(DmriError, match="DMRI_E_INVALID"):
+                    s.dmri_set_option(k, v)
