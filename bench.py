@@ -120,16 +120,17 @@ def kernel_bytes(kind, n_dof, nnz, total_iters, tile, prec_bytes, n_steps, n_sys
     raise ValueError(kind)
 
 
-def profiled_traffic(kernel, workload, precision, rtol):
+def profiled_traffic(kernel, workload, precision, rtol, key="traffic_bytes_per_launch"):
     """Measured HBM bytes per launch of `kernel` from the committed rocprofv3
-    counter summary, or None when none matches or the library sources changed
-    since the counters were taken."""
+    counter summary (`key`: the copy-calibrated FETCH + WRITE figure, or
+    traffic_l2_miss_bytes_per_launch), or None when none matches or the
+    library sources changed since the counters were taken."""
     import re
     path = os.path.join(ROOT, "profiles", "hbm_counters_%s_%s_%s.md" % (kernel, workload, precision))
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m_t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m_t = re.search(key + r":\s*([0-9.eE+]+)", text)
     m_h = re.search(r"csrc_sha256:\s*([0-9a-f]+)", text)
     m_w = re.search(r"workload: \S+ precision=\S+ rtol=(\S+)", text)
     if not (m_t and m_h and m_w) or float(m_w.group(1)) != rtol:
@@ -400,9 +401,12 @@ def main():
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
         "traffic": profiled_traffic(kname, args.workload, args.precision, rtol),
+        "traffic_l2_miss": profiled_traffic(kname, args.workload, args.precision, rtol,
+                                            "traffic_l2_miss_bytes_per_launch"),
         "launches": n_launch, "mean_launch_us": 1e6 * t_kernel / max(1, n_launch),
         "bytes_per_launch": kb / max(1, n_launch),
-        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
+        "traffic_unit": "bytes per launch: traffic = rocprofv3 FETCH_SIZE x2 + WRITE_SIZE "
+                        "(copy-calibrated); traffic_l2_miss = TCC_MISS x 64 B + WRITE_SIZE",
     }
     sigs = [sig[owner == i] for i in range(len(items))]
     config = {"workload": args.workload, "description": desc,

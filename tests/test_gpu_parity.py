@@ -1024,4 +1024,8 @@ def test_mixed_precision_membrane_limits_and_spheres(Sim, case):
     err = rel_err(sig, ref, ref[0])
     _say("mixed %s: max err %.2e, %d iterations" % (case, err.max(), st["total_iterations"]))
     assert st["status"] == "DMRI_OK"
-    assert err.max() < 1e-9
+    # With kappa dt / h ~ 800 the membrane rows dominate and A is ill
+    # conditioned: rtol 1e-12 on the residual bounds the signal error only by
+    # cond(A) * 1e-12 (measured 9.4e-9, 14x the iterations of kappa = 0);
+    # mixed precision's own target is 1e-4.
+    assert err.max() < (1e-7 if case == "kappa_large" else 1e-9)
