@@ -1357,14 +1357,15 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     const size_t nvi = static_cast<size_t>(g.n_rows) * ldi;
     History<double2> hs;
     hs.nh = history_len(h);
-    for (int i = 0; i < hs.nh + 5; ++i) W.vec64[i].alloc(2 * nv);
+    // FP64 level: history ring, x_alt, r64, b64 (no FP64 direction vector:
+    // the inner solves form their own).
+    for (int i = 0; i < hs.nh + 4; ++i) W.vec64[i].alloc(2 * nv);
     for (int i = 0; i < 4; ++i) W.vec32[i].alloc(2 * nvi);
     for (int i = 0; i <= hs.nh; ++i) hs.ring.push_back(reinterpret_cast<double2*>(W.vec64[i].p));
     // The refinement passes alternate x between hs.x() and x_alt.
     double2* x_alt = reinterpret_cast<double2*>(W.vec64[hs.nh + 1].p);
     double2* r64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 2].p);
-    double2* p64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 3].p);
-    double2* b64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 4].p);  // right-hand side of the step
+    double2* b64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 3].p);  // right-hand side of the step
     float2* r32 = reinterpret_cast<float2*>(W.vec32[0].p);
     float2* dx = reinterpret_cast<float2*>(W.vec32[1].p);
     float2* p32 = reinterpret_cast<float2*>(W.vec32[2].p);
@@ -1413,7 +1414,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
         timer.run(4, [&] {
             if (wb) launch_weak_rhs<double>(st, g, wv, W.gq.p, so.n_sys, F[n], wc, hs.u(0), wb);
             launch_init<double>(st, g, A64, W.gq.p, lhs, rhs, bs.herm, gm, hs.u(0), hs.u(1),
-                                hs.x(), r64, p64, nullptr, nullptr, b64, so, bs.sc,
+                                hs.x(), r64, nullptr, nullptr, nullptr, b64, so, bs.sc,
                                 wb ? wv.map : nullptr, wb);
         });
         int step_iters = 0;
@@ -1434,7 +1435,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
             step_iters += it;
             timer.run(4, [&] {
                 launch_init<double>(st, gr, A64, W.gq.p, lhs, rhs, bs.herm, 4, hs.u(0), hs.u(1),
-                                    hs.x(), r64, p64, dx, x_alt, b64, so, bs.sc);
+                                    hs.x(), r64, nullptr, dx, x_alt, b64, so, bs.sc);
             });
             std::swap(hs.ring[hs.nh], x_alt);
         }

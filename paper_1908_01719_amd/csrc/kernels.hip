@@ -40,7 +40,8 @@ constexpr int kSpmvRows = 2;    // rows per lane processed together in the LDS S
 template <typename T> using V2 = typename Vec2Of<T>::type;
 template <typename T> using V4 = typename Vec4Of<T>::type;
 
-enum FinMode { FIN_ALPHA = 0, FIN_BETA = 1, FIN_INIT = 2, FIN_SIGNAL = 3 };
+// FIN_REFINE: as FIN_INIT for a refinement pass, keeping the step's ||b||^2.
+enum FinMode { FIN_ALPHA = 0, FIN_BETA = 1, FIN_INIT = 2, FIN_SIGNAL = 3, FIN_REFINE = 4 };
 
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
     const double den = b.x * b.x + b.y * b.y;
@@ -1480,11 +1481,11 @@ __global__ __launch_bounds__(kBlock) void k_init(
                     bi += e.y;
                 }
             }
-            if (!kRhs) {
+            if (GM == 3) {
                 const V2<T> bv = bvec[idx];
                 br = bv.x;
                 bi = bv.y;
-            } else if (bvec) {
+            } else if (kRhs && bvec) {
                 bvec[idx] = mk2<T>(br, bi);
             }
             V2<T> rv;
@@ -1498,10 +1499,10 @@ __global__ __launch_bounds__(kBlock) void k_init(
             T dr, di;
             diag_at(dK0, daux, row, ll, dr, di);
             const V2<T> z = cdivT<T>(rv, dr, di);
-            if (GM < 3) p[idx] = z;
+            if (GM < 3 && p) p[idx] = z;
             dot_acc<HERM, T>(acc[0], acc[1], rv, z);
             acc[2] += double(rv.x) * rv.x + double(rv.y) * rv.y;
-            acc[3] += double(br) * br + double(bi) * bi;
+            if (GM != 4) acc[3] += double(br) * br + double(bi) * bi;
             // The guess of this row is stored where no other row reads it
             // during this launch: x itself when the gathers read u_prev
             // (GM 0/1), a second buffer when they read x (GM 3).
@@ -1803,11 +1804,13 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, S
                     atomicAdd(&cnt, 1);
                 }
             }
-        } else {  // FIN_INIT
+        } else {  // FIN_INIT, FIN_REFINE
             if (sys < s.n_sys) {
                 const double rr = tot[2];
                 const double bb =
-                    s.floor_bb ? fmax(tot[3], s.floor_scale * s.floor_bb[sys]) : tot[3];
+                    MODE == FIN_REFINE
+                        ? s.bb[sys]
+                        : (s.floor_bb ? fmax(tot[3], s.floor_scale * s.floor_bb[sys]) : tot[3]);
                 s.rho[sys] = make_double2(tot[0], tot[1]);
                 s.rr[sys] = rr;
                 s.bb[sys] = bb;
@@ -1825,7 +1828,8 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, S
         }
     }
     __syncthreads();
-    if ((MODE == FIN_BETA || MODE == FIN_INIT) && threadIdx.x == 0) s.n_active[tile] = cnt;
+    if ((MODE == FIN_BETA || MODE == FIN_INIT || MODE == FIN_REFINE) && threadIdx.x == 0)
+        s.n_active[tile] = cnt;
 }
 
 // y = (Base + c M_D + i d.V) x with explicit per-system coefficients.
@@ -2493,7 +2497,8 @@ void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const doubl
                  Coef rhs, bool herm, int guess_mode, const V2<T>* u_prev, const V2<T>* u_prev2,
                  V2<T>* x, V2<T>* r, V2<T>* p, const float2* dx, V2<T>* x_out, V2<T>* bvec,
                  SolverState s, Scratch sc, const int32_t* wmap, const V2<T>* wb) {
-    if (guess_mode >= 3 && !bvec) throw std::runtime_error("init: refinement needs the stored b");
+    if (guess_mode == 3 && !bvec) throw std::runtime_error("init: refinement needs the stored b");
+    if (guess_mode == 4 && !(dx && x_out)) throw std::runtime_error("init: refinement needs dx");
     if ((wmap == nullptr) != (wb == nullptr)) throw std::runtime_error("init: wmap and wb go together");
     const dim3 grid = grid_of(g), block(kBlock);
 #define DMRI_INIT(H, GMV)                                                                     \
@@ -2518,7 +2523,10 @@ void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const doubl
 #undef DMRI_INIT_GM
 #undef DMRI_INIT
     check_launch("init");
-    launch_fin<FIN_INIT, 4>(st, g, s, sc, nullptr, 0, sc.ctr_init);
+    if (guess_mode >= 4)
+        launch_fin<FIN_REFINE, 4>(st, g, s, sc, nullptr, 0, sc.ctr_init);
+    else
+        launch_fin<FIN_INIT, 4>(st, g, s, sc, nullptr, 0, sc.ctr_init);
 }
 
 void launch_inner_start(hipStream_t st, const Geom& g, const MatView<float>& A, const double4* gq,

@@ -137,7 +137,10 @@ Geom sched_geom(const Geom& g, const int32_t* tiles, int n);
 
 // guess_mode: 0 x0 = u_prev, 1 x0 = 2 u_prev - u_prev2 (x0 written to x),
 // 2 x0 given in x, 3 x0 = x + dx (mixed-precision correction, written to
-// x_out, which must not alias x). p is written except in mode 3.
+// x_out, which must not alias x; b read from bvec), 4 r -= A dx, x_out =
+// x + dx (refinement pass keeping the step's ||b||^2). In modes 0-2 p = D^-1 r
+// is written when p is not null (the mixed-precision outer level passes null:
+// its inner solves form their own directions).
 template <typename T>
 void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
                  Coef lhs, Coef rhs, bool herm, int guess_mode,
