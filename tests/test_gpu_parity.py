@@ -1029,3 +1029,17 @@ def test_mixed_precision_membrane_limits_and_spheres(Sim, case):
     # cond(A) * 1e-12 (measured 9.4e-9, 14x the iterations of kappa = 0);
     # mixed precision's own target is 1e-4.
     assert err.max() < (1e-7 if case == "kappa_large" else 1e-9)
+
+
+def test_markers_change_nothing(Sim):
+    # roctx ranges around batches and steps are host-side only.
+    prob, b, q = _cyl_case()
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        pid = sim.add_problem(prob)
+        sim.set_options(rtol=1e-12)
+        plain, _ = sim.dmri_run([pid] * len(b), b, q)
+        sim.set_options(markers=1)
+        marked, st = sim.dmri_run([pid] * len(b), b, q)
+    assert st["status"] == "DMRI_OK"
+    assert np.array_equal(plain, marked)
