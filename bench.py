@@ -93,27 +93,30 @@ def golden_error(fixtures, sigs):
         else None
 
 
-def kernel_bytes(kind, n_dof, nnz, total_iters, tile, prec_bytes, n_steps, n_sys):
+def kernel_bytes(kind, n_dof, nnz, total_iters, tile, prec_bytes, n_steps, n_sys, cp=None):
     """Algorithmic HBM bytes of one kernel summed over a run.
 
-    Vector traffic per DOF and system (complex of c = 2*prec_bytes bytes) plus
-    matrix traffic per active system tile, since every tile of S systems
-    re-reads the matrix: the SpMV reads p once and writes q (2c) and reads per
-    stored entry a column index (4 B) and five values (K0, M_D, V_x, V_y, V_z),
-    plus the row pointers; the CG update reads r, q and writes r (3c); the
-    direction update reads r, p, x and writes p, x (5c); both read the five
-    diagonal values per row and tile.
+    Vector traffic per DOF and system (complex of c = 2*prec_bytes bytes; the
+    search direction p may be stored narrower, cp bytes per complex: BF16
+    directions of the paired inner solves, 4 B) plus matrix traffic per active
+    system tile, since every tile of S systems re-reads the matrix: the SpMV
+    reads p once and writes q (cp + c) and reads per stored entry a column
+    index (4 B) and five values (K0, M_D, V_x, V_y, V_z), plus the row
+    pointers; the CG update reads r, q and writes r (3c); the direction update
+    reads r, p, x and writes p, x (3c + 2cp); both read the five diagonal
+    values per row and tile.
     """
     c = 2 * prec_bytes
+    cp = c if cp is None else cp
     mat = nnz * (4 + 5 * prec_bytes) + 4 * n_dof       # col + K0 + {MD, Vx, Vy, Vz} + row_ptr
     diag = n_dof * 5 * prec_bytes
     tile_iters = total_iters / tile
     if kind == "spmv":
-        return 2 * c * n_dof * total_iters + mat * tile_iters
+        return (cp + c) * n_dof * total_iters + mat * tile_iters
     if kind == "update":  # r, q read, r written
         return 3 * c * n_dof * total_iters + diag * tile_iters
     if kind == "pupdate":  # r, p, x read, p, x written
-        return 5 * c * n_dof * total_iters + diag * tile_iters
+        return (3 * c + 2 * cp) * n_dof * total_iters + diag * tile_iters
     if kind == "init":
         # gathers u_prev (and u_prev2), writes x, r, p, reads both base arrays
         return (5 * c * n_dof * n_sys + (mat + nnz * prec_bytes) * n_sys / tile) * n_steps
@@ -389,8 +392,10 @@ def main():
         paired_any |= paired
         ktile = 128 if paired else tile
         tiles.append(ktile)
+        # paired inner solves keep their search directions in BF16 (option dir_bf16)
+        cp = 4 if (paired and sim.dmri_get_option("dir_bf16") == 1) else None
         kb += kernel_bytes(args.time_kernel, info[i][0], info[i][1], iters_item[i], ktile, pbytes,
-                           n_steps * args.steps, ns)
+                           n_steps * args.steps, ns, cp)
     kname = KERNEL_NAMES[args.time_kernel]
     if paired_any:
         kname = kname.replace("k_spmv_dot", "k_spmv_pair").replace("k_update", "k_update_pair") \

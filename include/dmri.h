@@ -262,6 +262,12 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *               DMRI_E_UNSUPPORTED). Every system stops at the same
  *               ||b - A x|| <= rtol ||b|| test
  *  "gmres_m"    GMRES restart length m, 1..32 (default 30)
+ *  "dir_bf16"   1 (default): the FP32 inner solves on 128-system paired
+ *               tiles (precision 1, batches above 64 systems) store their
+ *               search directions in BF16, halving the SpMV's gathered bytes;
+ *               every recurrence uses the stored direction, so the residual
+ *               stays consistent and the FP64 refinement sets the accuracy.
+ *               0: FP32 directions
  *  "markers"    1: roctx ranges ("dmri batch <systems>", "dmri step <n>")
  *               around each batch and time step, for profiler timelines
  *               (rocprofv3 --marker-trace); 0 (default): none

@@ -197,6 +197,7 @@ struct Options {
     int gmres_m = 30;
     double weak_kappa = 1.0;  // scale of kappa_e on weak pseudo-periodic faces
     int markers = 0;          // 1: roctx ranges around runs, batches and time steps
+    int dir_bf16 = 1;         // paired FP32 inner solves keep their directions in BF16
 };
 
 // Per-system Krylov state arrays of one solver level.
@@ -881,6 +882,7 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                           opts(h).xcd_split != 0);
         bs.gi.nt = g.nt;
         bs.gi.lds = 0;
+        bs.gi.dir16 = opts(h).dir_bf16;
     }
     const Geom& gi = bs.gi;
     const size_t ld_max = std::max<size_t>(ld, static_cast<size_t>(gi.ld));
@@ -2007,6 +2009,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
             if (!(v > 0 && v <= 1e6)) throw Error(DMRI_E_INVALID, "weak_kappa must be in (0, 1e6]");
             o.weak_kappa = v;
         } else if (k == "markers") o.markers = as_int(0, 1);
+        else if (k == "dir_bf16") o.dir_bf16 = as_int(0, 1);
         else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
@@ -2050,6 +2053,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "gmres_m") *value = o.gmres_m;
         else if (k == "weak_kappa") *value = o.weak_kappa;
         else if (k == "markers") *value = o.markers;
+        else if (k == "dir_bf16") *value = o.dir_bf16;
         else if (k == "tuned_sys_tile") *value = h->last_tune.sys_tile;
         else if (k == "tuned_blocks_per_xcd") *value = h->last_tune.blocks_per_xcd;
         else if (k == "tuned_persistent") *value = h->last_tune.persistent;

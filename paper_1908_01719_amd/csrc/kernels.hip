@@ -792,7 +792,33 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(Geom g, const T* __restrict_
 // (complex units); the matrix stays wavefront-uniform.
 
 __device__ __forceinline__ size_t pair_tile(const Geom& g, int tile) {
-    return static_cast<size_t>(tile) * g.n_rows * 64;  // float4 units
+    return static_cast<size_t>(tile) * g.n_rows * 64;  // lane-element units (float4 or uint2)
+}
+
+// Search directions of the paired layout may be stored in BF16 (Geom::dir16):
+// a lane's four values (two systems' complex numbers) in 8 bytes, rounded to
+// nearest even. The Krylov recurrences use the stored (rounded) direction
+// everywhere -- the SpMV's q = A p, x += alpha p, the next p = z + beta p --
+// so the residual recurrence stays consistent; only the directions' mutual
+// conjugacy is perturbed (BF16 keeps FP32's exponent range: no scaling).
+template <bool B16> struct DirOf;
+template <> struct DirOf<false> { using type = float4; };
+template <> struct DirOf<true> { using type = uint2; };
+
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float4 dir_load(const float4* p, size_t o) { return p[o]; }
+__device__ __forceinline__ float4 dir_load(const uint2* p, size_t o) {
+    const uint2 w = p[o];
+    return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                       __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
+}
+__device__ __forceinline__ void dir_store(float4* p, size_t o, float4 v) { p[o] = v; }
+__device__ __forceinline__ void dir_store(uint2* p, size_t o, float4 v) {
+    p[o] = make_uint2(bf16_bits(v.x) | (bf16_bits(v.y) << 16),
+                      bf16_bits(v.z) | (bf16_bits(v.w) << 16));
 }
 
 template <int K>
@@ -823,7 +849,7 @@ __device__ __forceinline__ float2 hi2(float4 v) { return make_float2(v.z, v.w); 
 __device__ __forceinline__ float4 cat4(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
 
 // NB entries of a row from k0 for both systems of the lane.
-template <int NB>
+template <int NB, bool B16>
 __device__ __forceinline__ void pair_block(const int32_t* __restrict__ col,
                                            const float* __restrict__ K0,
                                            const float4* __restrict__ aux,
@@ -832,10 +858,23 @@ __device__ __forceinline__ void pair_block(const int32_t* __restrict__ col,
                                            float cm0, float cm1, float& yr0, float& yi0,
                                            float& yr1, float& yi1) {
     float4 xv[NB];
+    if constexpr (B16) {
+        uint2 w[NB];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        const uint32_t off = static_cast<uint32_t>(col[k0 + u]) * (kPairS * 8u);
-        xv[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, lane_bytes, off, 0));
+        for (int u = 0; u < NB; ++u) {
+            const uint32_t off = static_cast<uint32_t>(col[k0 + u]) * (kPairS * 4u);
+            w[u] = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, lane_bytes, off, 0));
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+            xv[u] = make_float4(__uint_as_float(w[u].x << 16), __uint_as_float(w[u].x & 0xFFFF0000u),
+                                __uint_as_float(w[u].y << 16), __uint_as_float(w[u].y & 0xFFFF0000u));
+    } else {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const uint32_t off = static_cast<uint32_t>(col[k0 + u]) * (kPairS * 8u);
+            xv[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, lane_bytes, off, 0));
+        }
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
@@ -849,15 +888,17 @@ __device__ __forceinline__ void pair_block(const int32_t* __restrict__ col,
 }
 
 // q = A p and sigma = p^H q (or p^T q) for the paired layout.
-template <bool HERM>
+template <bool HERM, bool B16>
 __global__ __launch_bounds__(kBlock) void k_spmv_pair(
     Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const float* __restrict__ K0, const float4* __restrict__ aux, const double4* __restrict__ gq,
-    Coef lhs, const float4* __restrict__ p, float4* __restrict__ q, SolverState s, Scratch sc) {
+    Coef lhs, const typename DirOf<B16>::type* __restrict__ p, float4* __restrict__ q, SolverState s,
+    Scratch sc) {
+    using DT = typename DirOf<B16>::type;
     __shared__ double lds[kWaves * kPairS * 2];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const int lane = threadIdx.x & 63;
-    const uint32_t lane_bytes = static_cast<uint32_t>(lane) * 16u;
+    const uint32_t lane_bytes = static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(DT));
     const int off = wave_id_uniform();
     for (int kk = xcd; kk < g.n_items; kk += 8) {
         const ItemRef ir = item_ref(g, kk);
@@ -869,11 +910,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(
         if (!__syncthreads_or(la)) continue;
         const LaneCoef<float> c0(gq[s0], lhs, g, s0), c1(gq[s0 + 1], lhs, g, s0 + 1);
         double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-        const float4* pt = p + pair_tile(g, tile);
+        const DT* pt = p + pair_tile(g, tile);
         float4* qt = q + pair_tile(g, tile);
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float4*>(pt), 0, static_cast<int>(static_cast<uint32_t>(g.n_rows) * 1024u),
-            kBufWord3);
+            const_cast<DT*>(pt), 0,
+            static_cast<int>(static_cast<uint32_t>(g.n_rows) * (64u * sizeof(DT))), kBufWord3);
         const int r0 = part * g.part_rows;
         const int r1 = min(g.n_rows, r0 + g.part_rows);
         const int step = g.B * g.chunk_rows;
@@ -890,18 +931,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(
                 const float cm0 = c0.cr(row), cm1 = c1.cr(row);
                 float yr0 = 0.f, yi0 = 0.f, yr1 = 0.f, yi1 = 0.f;
                 if (ke - kb == 16) {
-                    pair_block<16>(col, K0, aux, rs, lane_bytes, kb, c0, c1, cm0, cm1, yr0, yi0,
-                                   yr1, yi1);
+                    pair_block<16, B16>(col, K0, aux, rs, lane_bytes, kb, c0, c1, cm0, cm1, yr0,
+                                        yi0, yr1, yi1);
                 } else {
                     for (int k0 = kb; k0 < ke; k0 += kRowPad)
-                        pair_block<kRowPad>(col, K0, aux, rs, lane_bytes, k0, c0, c1, cm0, cm1,
-                                            yr0, yi0, yr1, yi1);
+                        pair_block<kRowPad, B16>(col, K0, aux, rs, lane_bytes, k0, c0, c1, cm0,
+                                                 cm1, yr0, yi0, yr1, yi1);
                 }
                 const size_t o = static_cast<size_t>(row) * 64 + lane;
                 const float4 y = make_float4(yr0, yi0, yr1, yi1);
                 if (g.nt) store_nt(qt + o, y);
                 else qt[o] = y;
-                const float4 pv = pt[o];
+                const float4 pv = dir_load(pt, o);
                 dot_acc<HERM, float>(acc[0][0], acc[0][1], lo2(pv), lo2(y));
                 dot_acc<HERM, float>(acc[1][0], acc[1][1], hi2(pv), hi2(y));
             }
@@ -977,10 +1018,13 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(
 
 // End of Krylov iteration k_iter in the paired layout: x += alpha p for the
 // systems that took part in it, p = D^-1 r + beta p for those still active.
+template <bool B16>
 __global__ __launch_bounds__(kBlock) void k_pupdate_pair(
     Geom g, const float* __restrict__ dK0, const float4* __restrict__ daux,
     const double4* __restrict__ gq, Coef lhs, const float4* __restrict__ r,
-    float4* __restrict__ p, float4* __restrict__ x, int32_t k_iter, SolverState s) {
+    typename DirOf<B16>::type* __restrict__ p, float4* __restrict__ x, int32_t k_iter,
+    SolverState s) {
+    using DT = typename DirOf<B16>::type;
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const int lane = threadIdx.x & 63;
     const int off = wave_id_uniform();
@@ -1003,7 +1047,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_pair(
         const float xr0 = static_cast<float>(al0.x), xi0 = static_cast<float>(al0.y);
         const float xr1 = static_cast<float>(al1.x), xi1 = static_cast<float>(al1.y);
         const float4* rt = r + pair_tile(g, tile);
-        float4* pt = p + pair_tile(g, tile);
+        DT* pt = p + pair_tile(g, tile);
         float4* xt = x + pair_tile(g, tile);
         const int r0 = part * g.part_rows;
         const int r1 = min(g.n_rows, r0 + g.part_rows);
@@ -1018,7 +1062,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_pair(
                 ok[u] = rr < r1;
                 row[u] = ok[u] ? rr : r1 - 1;
                 const size_t o = static_cast<size_t>(row[u]) * 64 + lane;
-                pv[u] = pt[o];
+                pv[u] = dir_load(pt, o);
                 if (do_p) rv[u] = rt[o];
                 if (do_x) xv[u] = xt[o];
             }
@@ -1047,7 +1091,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_pair(
                         const float2 z = cdivT<float>(hi2(rv[u]), dr, di);
                         n1 = make_float2(z.x + br1 * p1.x - bi1 * p1.y, z.y + br1 * p1.y + bi1 * p1.x);
                     }
-                    pt[o] = cat4(n0, n1);
+                    dir_store(pt, o, cat4(n0, n1));
                 }
             }
         }
@@ -1057,12 +1101,13 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_pair(
 // Start of an FP32 inner solve in the paired layout: r = (float) r64 for
 // outer-active systems (0 otherwise), dx = 0, p = z = D^-1 r; partials rho,
 // ||r||^2, ||r64||^2. r64 is in the 64-wide FP64 layout (n64 rows per tile).
-template <bool HERM>
+template <bool HERM, bool B16>
 __global__ __launch_bounds__(kBlock) void k_inner_start_pair(
     Geom g, const float* __restrict__ dK0, const float4* __restrict__ daux,
     const double4* __restrict__ gq, Coef lhs, const double2* __restrict__ r64,
     const int32_t* __restrict__ outer_active, float4* __restrict__ r, float4* __restrict__ dx,
-    float4* __restrict__ p, SolverState s, Scratch sc) {
+    typename DirOf<B16>::type* __restrict__ p, SolverState s, Scratch sc) {
+    using DT = typename DirOf<B16>::type;
     __shared__ double lds[kWaves * kPairS * 4];
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const int lane = threadIdx.x & 63;
@@ -1079,7 +1124,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_start_pair(
         double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
         float4* rt = r + pair_tile(g, tile);
         float4* xt = dx + pair_tile(g, tile);
-        float4* pt = p + pair_tile(g, tile);
+        DT* pt = p + pair_tile(g, tile);
         const int r0 = part * g.part_rows;
         const int r1 = min(g.n_rows, r0 + g.part_rows);
         const int step = g.B * g.chunk_rows;
@@ -1108,7 +1153,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_start_pair(
                 diag_at(dK0, daux, row[u], c1, dr, di);
                 const float2 z1 = cdivT<float>(x1, dr, di);
                 rt[o] = cat4(x0, x1);
-                pt[o] = cat4(z0, z1);
+                dir_store(pt, o, cat4(z0, z1));
                 xt[o] = make_float4(0.f, 0.f, 0.f, 0.f);
                 dot_acc<HERM, float>(acc[0][0], acc[0][1], x0, z0);
                 dot_acc<HERM, float>(acc[1][0], acc[1][1], x1, z1);
@@ -2536,13 +2581,16 @@ void launch_inner_start(hipStream_t st, const Geom& g, const MatView<float>& A, 
     if (g.S == kPairS) {
         auto* r4 = reinterpret_cast<float4*>(r);
         auto* x4 = reinterpret_cast<float4*>(dx);
-        auto* p4 = reinterpret_cast<float4*>(p);
-        if (herm)
-            k_inner_start_pair<true><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r64,
-                                                             outer_active, r4, x4, p4, s, sc);
-        else
-            k_inner_start_pair<false><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs, r64,
-                                                              outer_active, r4, x4, p4, s, sc);
+#define DMRI_ISP(H, B)                                                                        \
+    k_inner_start_pair<H, B><<<grid, block, 0, st>>>(                                          \
+        g, A.dK0, A.daux, gq, lhs, r64, outer_active, r4, x4,                                 \
+        reinterpret_cast<typename DirOf<B>::type*>(p), s, sc)
+        if (herm) {
+            if (g.dir16) DMRI_ISP(true, true); else DMRI_ISP(true, false);
+        } else {
+            if (g.dir16) DMRI_ISP(false, true); else DMRI_ISP(false, false);
+        }
+#undef DMRI_ISP
         check_launch("inner_start");
         launch_fin<FIN_INIT, 4>(st, g, s, sc, nullptr, 0, nullptr);
         return;
@@ -2565,14 +2613,17 @@ void launch_spmv_dot(hipStream_t st, const Geom& g, const MatView<T>& A, const d
     const dim3 grid = grid_of(g), block(kBlock);
     if (g.S == kPairS) {
         if constexpr (sizeof(T) == 4) {
-            const auto* p4 = reinterpret_cast<const float4*>(p);
             auto* q4 = reinterpret_cast<float4*>(q);
-            if (herm)
-                k_spmv_pair<true><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.aux, gq,
-                                                          lhs, p4, q4, s, sc);
-            else
-                k_spmv_pair<false><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.aux, gq,
-                                                           lhs, p4, q4, s, sc);
+#define DMRI_SPP(H, B)                                                                        \
+    k_spmv_pair<H, B><<<grid, block, 0, st>>>(                                                 \
+        g, A.row_ptr, A.col, A.K0, A.aux, gq, lhs,                                            \
+        reinterpret_cast<const typename DirOf<B>::type*>(p), q4, s, sc)
+            if (herm) {
+                if (g.dir16) DMRI_SPP(true, true); else DMRI_SPP(true, false);
+            } else {
+                if (g.dir16) DMRI_SPP(false, true); else DMRI_SPP(false, false);
+            }
+#undef DMRI_SPP
             check_launch("spmv_pair");
             launch_fin<FIN_ALPHA, 2>(st, g, s, sc, nullptr, 0, sc.ctr_spmv);
             return;
@@ -2679,10 +2730,17 @@ void launch_pupdate(hipStream_t st, const Geom& g, const MatView<T>& A, const do
     const dim3 grid = grid_of(g), block(kBlock);
     if (g.S == kPairS) {
         if constexpr (sizeof(T) == 4) {
-            k_pupdate_pair<<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs,
-                                                   reinterpret_cast<const float4*>(r),
-                                                   reinterpret_cast<float4*>(p),
-                                                   reinterpret_cast<float4*>(x), k_iter, s);
+            if (g.dir16)
+                k_pupdate_pair<true><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs,
+                                                             reinterpret_cast<const float4*>(r),
+                                                             reinterpret_cast<uint2*>(p),
+                                                             reinterpret_cast<float4*>(x), k_iter, s);
+            else
+                k_pupdate_pair<false><<<grid, block, 0, st>>>(g, A.dK0, A.daux, gq, lhs,
+                                                              reinterpret_cast<const float4*>(r),
+                                                              reinterpret_cast<float4*>(p),
+                                                              reinterpret_cast<float4*>(x), k_iter,
+                                                              s);
             check_launch("pupdate_pair");
             return;
         } else {
