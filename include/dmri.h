@@ -281,8 +281,8 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *  "max_iter"   Krylov iterations per step and system (default 2000)
  *  "guess"      0 = previous step, 1 = polynomial extrapolation of the
  *               past solutions (default), 2 = learned correction of the
- *               linear extrapolation (needs network parameters; precision
- *               0 or 1)
+ *               damped cubic extrapolation (needs network parameters;
+ *               precision 0 or 1)
  *  "extrap_order" order p of the extrapolation (1..4, default 3): the
  *               polynomial through u^{n-1}, ..., u^{n-1-p} at t^n, i.e.
  *               x0 = sum_k (-1)^k C(p+1, k+1) u^{n-1-k}; early steps use the
@@ -314,8 +314,28 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *               the unknown is U and sum_i w_i U_i is returned
  *  "time_kernel" 0 = off, 1 = SpMV+dot, 2 = CG update, 3 = direction
  *               update, 4 = step start, 5 = learned-guess network, 6 =
- *               extrapolation: bracket every launch of that kernel
+ *               extrapolation, 7 = polynomial preconditioner (its terms and
+ *               direction update): bracket every launch of that kernel
  *               with HIP events and report the summed time in dmri_stats
+ *  "precond"    preconditioner of the Krylov solves (the paper leaves the
+ *               solver open, Sec. 3): 0 = Jacobi (default); 1 = Chebyshev
+ *               polynomial in D^-1 A (D = diag A) on the spectral interval
+ *               [a, b] that the preconditioner network predicts for each
+ *               system and step (dmri_precond_set_params); 2 = the same on
+ *               the fixed interval [cheb_a, cheb_b]. 1 and 2 run flexible CG
+ *               (FCG(1): each direction is the preconditioned residual made
+ *               A-orthogonal to the previous one) to the same ||b - A x|| <=
+ *               rtol ||b|| test; a step in which a system ends with a new
+ *               flag (max_iter, non-finite) is solved again by Jacobi CG
+ *               from the flexible solve's x. CG on the transformed form in
+ *               precision 0 only, static sweeps (queue 0); otherwise
+ *               DMRI_E_UNSUPPORTED
+ *  "cheb_terms" m, terms of the polynomial (1..16, default 4): m - 1
+ *               products with A per application; m = 1 is Jacobi
+ *  "cheb_a", "cheb_b" fixed interval of precond = 2 (defaults 0.5, 1.5;
+ *               0 < a, 1.001 a < b <= 1e6)
+ *  "pc_fallback_steps" read-only: steps re-solved by Jacobi CG since the
+ *               handle was created
  *  "blocks_per_xcd" workgroups per XCD sweeping the rows (default 512)
  *  "max_outer"  FP64 refinement passes per step in mixed precision (8)
  *  "queue"      1 = gather kernels take rows from a per-XCD queue,
@@ -440,6 +460,41 @@ DMRI_API dmri_status dmri_guess_eval(dmri_handle h, int64_t n, const float* d_fe
 DMRI_API dmri_status dmri_guess_train(dmri_handle h, int64_t n, const float* d_features,
                              const float* d_targets, int32_t n_iters, double lr,
                              double* loss_first, double* loss_last);
+
+/* Preconditioner network (option "precond" = 1; the learned preconditioner
+ * that goes with the learned guess). Same shape and parameter layout as the
+ * guess network (16 -> 64 -> 64 -> 2, BF16 matrix-core layers, FP32
+ * parameters), one sample per system and time step. Inputs: log(theta dt
+ * D/h^2), log(1 + theta dt D (G F)^2), log(1 + theta dt D |G F| / h),
+ * log(1 + theta dt kappa / h), |q_x|, |q_y|, |q_z|, then nine zeros (D the
+ * largest compartment diffusivity, h the longest edge, F = F(t^n)). Outputs
+ * y give the interval [0.5 e^y0, 1.5 e^y1] (y clipped to [-20, 20]; the
+ * reference interval [0.5, 1.5] where that is not finite or not an interval,
+ * so a zero network gives the reference). */
+#define DMRI_PRECOND_N_FEATURES 16
+#define DMRI_PRECOND_N_PARAMS 5378
+DMRI_API dmri_status dmri_precond_set_params(dmri_handle h, const float* params,
+                                             int64_t n_params);
+DMRI_API dmri_status dmri_precond_get_params(dmri_handle h, float* params, int64_t n_params);
+/* Record training samples during later runs with precond = 0 (Jacobi CG,
+ * precision 0, transformed form, static sweeps): after every time step,
+ * each system that took 2..64 iterations without a flag appends its 16
+ * features to d_features ([capacity][16] float32, device) and the targets
+ * {log(r_min / 0.5), log(1.1 r_max / 1.5)} to d_targets ([capacity][2]),
+ * where r_min, r_max are the extreme Ritz values of the step's CG run (the
+ * eigenvalues of the Lanczos tridiagonal its alpha_k and beta_k define:
+ * estimates of the ends of the spectrum of D^-1 A that the residual
+ * explored; 1.1 is the margin over the largest). Samples go in system order
+ * until capacity are held; capacity = 0 stops recording. Resets the count.
+ * The buffers are the caller's and must stay valid while recording is on. */
+DMRI_API dmri_status dmri_precond_record(dmri_handle h, float* d_features, float* d_targets,
+                                         int64_t capacity);
+DMRI_API dmri_status dmri_precond_record_count(dmri_handle h, int64_t* count);
+/* n_iters full-batch Adam steps on the mean squared error of the
+ * preconditioner network over n device samples (as dmri_guess_train). */
+DMRI_API dmri_status dmri_precond_train(dmri_handle h, int64_t n, const float* d_features,
+                                        const float* d_targets, int32_t n_iters, double lr,
+                                        double* loss_first, double* loss_last);
 
 /* Simulate n_pairs (problem, b, direction) systems and write their signals.
  *   problem_id [n_pairs] ids from dmri_add_problem

@@ -34,7 +34,9 @@ EXPORTED = [
     "dmri_run", "dmri_run_device", "dmri_run_device_noalloc", "dmri_apply_operator",
     "dmri_guess_set_params", "dmri_guess_get_params", "dmri_load_guess_model",
     "dmri_save_guess_model", "dmri_guess_record", "dmri_guess_record_count", "dmri_guess_eval",
-    "dmri_guess_train", "dmri_save_tuning", "dmri_load_tuning",
+    "dmri_guess_train", "dmri_save_tuning", "dmri_load_tuning", "dmri_precond_set_params",
+    "dmri_precond_get_params", "dmri_precond_record", "dmri_precond_record_count",
+    "dmri_precond_train",
 ]
 
 SEQ_KINDS = {"pgse": 0, "double_pgse": 1, "cos_ogse": 2, "sin_ogse": 3, "trap_pgse": 4,
@@ -110,6 +112,11 @@ def load(path: Optional[str] = None):
     lib.dmri_guess_record_count.argtypes = [vp, P(i64)]
     lib.dmri_guess_eval.argtypes = [vp, i64, vp, vp, vp, vp, P(dbl)]
     lib.dmri_guess_train.argtypes = [vp, i64, vp, vp, i32, dbl, P(dbl), P(dbl)]
+    lib.dmri_precond_set_params.argtypes = [vp, vp, i64]
+    lib.dmri_precond_get_params.argtypes = [vp, vp, i64]
+    lib.dmri_precond_record.argtypes = [vp, vp, vp, i64]
+    lib.dmri_precond_record_count.argtypes = [vp, P(i64)]
+    lib.dmri_precond_train.argtypes = [vp, i64, vp, vp, i32, dbl, P(dbl), P(dbl)]
     lib.dmri_run.argtypes = [vp, i64, vp, vp, vp, vp, P(Stats)]
     lib.dmri_run_device.argtypes = [vp, vp, i64, vp, vp, vp, vp, P(Stats)]
     lib.dmri_run_device_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, P(Stats)]
@@ -357,6 +364,45 @@ class Simulator:
         _sync(features_dev)
         self._check(self.lib.dmri_guess_train(self.h, n, _dptr(features_dev), _dptr(targets_dev),
                                               int(n_iters), float(lr), C.byref(l0), C.byref(l1)))
+        return l0.value, l1.value
+
+    # -- preconditioner network -------------------------------------------
+    def dmri_precond_set_params(self, params):
+        p = _c(params, np.float32).reshape(-1)
+        self._check(self.lib.dmri_precond_set_params(self.h, _ptr(p), p.shape[0]))
+
+    def dmri_precond_get_params(self) -> np.ndarray:
+        p = np.empty(GUESS_N_PARAMS, np.float32)
+        self._check(self.lib.dmri_precond_get_params(self.h, _ptr(p), p.shape[0]))
+        return p
+
+    def dmri_precond_record(self, features_dev, targets_dev, capacity: int):
+        """Record (system, step) samples of Jacobi-CG runs into torch float32
+        CUDA tensors [capacity, 16] and [capacity, 2] (capacity 0 stops)."""
+        if capacity > 0:
+            _dev_f32(features_dev, (capacity, GUESS_N_FEATURES))
+            _dev_f32(targets_dev, (capacity, 2))
+        self._check(self.lib.dmri_precond_record(
+            self.h, _dptr(features_dev) if capacity > 0 else None,
+            _dptr(targets_dev) if capacity > 0 else None, int(capacity)))
+
+    def dmri_precond_record_count(self) -> int:
+        n = C.c_int64()
+        self._check(self.lib.dmri_precond_record_count(self.h, C.byref(n)))
+        return n.value
+
+    def dmri_precond_train(self, features_dev, targets_dev, n_iters: int, lr: float, n=None):
+        """Full-batch Adam steps; returns (loss before the first, before the last step)."""
+        n = int(features_dev.shape[0]) if n is None else int(n)
+        _dev_f32(features_dev, None)
+        _dev_f32(targets_dev, None)
+        if n > features_dev.shape[0] or n > targets_dev.shape[0]:
+            raise ValueError("n exceeds the sample buffers")
+        l0, l1 = C.c_double(), C.c_double()
+        _sync(features_dev)
+        self._check(self.lib.dmri_precond_train(self.h, n, _dptr(features_dev),
+                                                _dptr(targets_dev), int(n_iters), float(lr),
+                                                C.byref(l0), C.byref(l1)))
         return l0.value, l1.value
 
     # -- runs ---------------------------------------------------------------

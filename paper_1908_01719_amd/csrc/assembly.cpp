@@ -520,6 +520,16 @@ HostOperator assemble(const MeshInput& in) {
             }
     }
     op.max_edge = std::sqrt(emax);
+    op.kappa = in.kappa;
+    for (int32_t k = 0; k < in.n_comp; ++k) {
+        double dk = in.Dt ? 0.0 : in.D[k];
+        if (in.Dt) {
+            const double* t = in.Dt + 6 * k;
+            double A[3][3] = {{t[0], t[3], t[4]}, {t[3], t[1], t[5]}, {t[4], t[5], t[2]}};
+            dk = lambda_max(A);
+        }
+        op.d_max = std::max(op.d_max, dk);
+    }
     if (weak) add_weak_faces(in, tdof, op);
     return op;
 }

@@ -102,7 +102,16 @@ struct HostOperator {
     std::vector<int32_t> wk_rows, wk_ptr, wk_col, wk_code;
     std::vector<double> wk_val;
     double box_len[3] = {0.0, 0.0, 0.0};
+    // Scales of the operator's terms (inputs of the preconditioner's
+    // interval network): the largest compartment diffusivity (largest
+    // eigenvalue for tensors) and the membrane permeability.
+    double d_max = 0.0;
+    double kappa = 0.0;
 };
+
+// Largest eigenvalue of a symmetric 3x3 matrix (cyclic Jacobi rotations;
+// A is overwritten).
+double lambda_max(double A[3][3]);
 
 // Fill the weak-face arrays of op (called by assemble once the pattern
 // exists); tdof [n_tets][4] holds the DOF of every tetrahedron vertex.

@@ -198,6 +198,13 @@ struct Options {
     double weak_kappa = 1.0;  // scale of kappa_e on weak pseudo-periodic faces
     int markers = 0;          // 1: roctx ranges around runs, batches and time steps
     int dir_bf16 = 1;         // paired FP32 inner solves keep their directions in BF16
+    // Krylov preconditioner of the FP64 Hermitian solves: 0 Jacobi (CG), 1
+    // Chebyshev polynomial in D^-1 A on the interval the preconditioner
+    // network predicts, 2 the same on the fixed interval [cheb_a, cheb_b];
+    // 1 and 2 run flexible CG with Jacobi CG as the fallback.
+    int precond = 0;
+    int cheb_terms = 4;
+    double cheb_a = kPcARef, cheb_b = kPcBRef;
 };
 
 // Per-system Krylov state arrays of one solver level.
@@ -264,6 +271,12 @@ struct Workspace {
     DevBuf<double> gm_partial, gm_hout, gm_cs, gm_hnorm;
     DevBuf<double> acomp;  // [n_comp][ld] q.D_k q per system (anisotropic problems)
     DevBuf<double> wb;     // [slots][ld] complex partner terms of weak faces
+    // Polynomial preconditioner: two term vectors y, the update d, the
+    // per-system interval, the network's inputs and outputs, and the CG
+    // coefficients of the recorder.
+    DevBuf<double> pc_y[2], pc_d;
+    DevBuf<double2> pc_ab, pc_hist;
+    DevBuf<float> pc_X, pc_Y;
     DevBuf<int32_t> gm_cycle, gm_dim;
     int32_t* h_active[2] = {nullptr, nullptr};  // pinned
     size_t h_active_n = 0;
@@ -360,6 +373,7 @@ struct GuessModel {
     float* rec_T = nullptr;
     int64_t rec_cap = 0, rec_count = 0;
     int64_t rec_stride = 1;
+    DevBuf<int64_t> rec_count_dev;  // sample count kept on the device (preconditioner)
 };
 
 }  // namespace
@@ -377,6 +391,10 @@ struct dmri_ctx {
     uint64_t seq_gen = 0;      // bumped by every sequence change
     dmri::Options opt;
     dmri::GuessModel model;
+    // Network of the preconditioner's interval (same shape as the guess
+    // network) and its recorder of Ritz-value samples.
+    dmri::GuessModel pcmodel;
+    std::atomic<int64_t> pc_fallbacks{0};  // steps re-solved by Jacobi CG
     std::map<std::string, dmri::TuneChoice> tuned;  // autotuner cache
     std::string device_tag = "host";  // architecture and CU count, in cache keys
     dmri::TuneChoice last_tune;
@@ -866,7 +884,7 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     if (opts(h).krylov == 3 && opts(h).precision != 0)
         throw Error(DMRI_E_UNSUPPORTED, "GMRES (krylov = 3) runs in precision 0 (FP64)");
     bs.persist = (opts(h).persistent == 1 || (opts(h).persistent == 2 && small)) && g.ld <= 64 &&
-                 opts(h).krylov != 3;
+                 opts(h).krylov != 3 && opts(h).precond == 0 && h->pcmodel.rec_cap == 0;
     // The grid barrier needs every block resident: otherwise chunked launches.
     if (bs.persist) {
         const bool fits = opts(h).precision != 0 ? persistent_fits<float>(bs.gp, bs.herm, n_cu)
@@ -1004,6 +1022,78 @@ int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const d
         pending = true;
         slot ^= 1;
         chunk = 2;
+        if (done > max_iter + 4) {
+            HIPCHK(hipStreamSynchronize(st));
+            break;
+        }
+    }
+    return done;
+}
+
+// Buffers of the polynomial preconditioner.
+struct PcBufs {
+    double2* y[2];
+    double2* d;
+    double2* ab;
+};
+
+// Flexible CG (Notay's FCG(1)) with the Chebyshev polynomial preconditioner
+// on the systems active in s after the step start (k_init has formed r and
+// p = D^-1 r): z0 = P(r0), p0 = z0, then per iteration q = A p, alpha =
+// rho / (p^H q), x += alpha p, r -= alpha q, z = P(r), beta = -(q^H z) /
+// (p^H q), rho = r^H z, p = z + beta p. Chunks and polling as krylov_loop.
+// Returns the iterations enqueued.
+int fcg_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<double>& Av, const double4* gq,
+             Coef lhs, double2* x, double2* r, double2* p, double2* q, const PcBufs& pb,
+             SolverState s, KernelTimer& timer, int max_iter) {
+    hipStream_t st = lane(h).stream;
+    const Geom& g = bs.g;
+    const int m = opts(h).cheb_terms;
+    timer.run(7, [&] {
+        // (no q yet: the start's q^H z is not used, r stands in for q)
+        const double2* z = launch_cheb(st, g, Av, gq, lhs, pb.ab, m, true, r, r, pb.y, pb.d, s,
+                                       bs.sc);
+        launch_pupdate_z(st, g, z, p, x, -1, s);
+    });
+    int done = 0, slot = 0;
+    bool pending = false;
+    Geom gk = g;
+    std::vector<int32_t> live;
+    for (;;) {
+        for (int i = 0; i < 2; ++i) {
+            const int32_t k_iter = done + i + 1;
+            timer.run(1, [&] { launch_spmv_dot<double>(st, gk, Av, gq, lhs, true, p, q, s, bs.sc); });
+            timer.run(2, [&] {
+                launch_update<double>(st, gk, Av, gq, lhs, true, x, r, p, q, s, bs.sc, true);
+            });
+            timer.run(7, [&] {
+                const double2* z = launch_cheb(st, gk, Av, gq, lhs, pb.ab, m, false, r, q, pb.y,
+                                               pb.d, s, bs.sc);
+                launch_pupdate_z(st, gk, z, p, x, k_iter, s);
+            });
+        }
+        done += 2;
+        HIPCHK(hipMemcpyAsync(lane(h).ws.h_active[slot], s.n_active, sizeof(int32_t) * g.n_tiles,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(lane(h).ev[slot], st));
+        if (pending) {
+            HIPCHK(hipEventSynchronize(lane(h).ev[slot ^ 1]));
+            int tot = 0;
+            live.clear();
+            for (int t = 0; t < g.n_tiles; ++t) {
+                const int32_t a = lane(h).ws.h_active[slot ^ 1][t];
+                tot += a;
+                if (a > 0) live.push_back(t);
+            }
+            if (tot == 0) {
+                done -= 2;
+                break;
+            }
+            if (opts(h).tile_sched)
+                gk = sched_geom(g, live.data(), static_cast<int>(live.size()));
+        }
+        pending = true;
+        slot ^= 1;
         if (done > max_iter + 4) {
             HIPCHK(hipStreamSynchronize(st));
             break;
@@ -1238,6 +1328,43 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     const bool learn = opts(h).guess == 2 || h->model.rec_cap > 0;
     const MlpDofs dofs = learn ? ensure_features(h, P) : MlpDofs{nullptr, nullptr};
 
+    // Polynomial preconditioner (flexible CG) and its sample recorder.
+    const bool pc = opts(h).precond != 0;
+    GuessModel& PM = h->pcmodel;
+    const bool pc_rec = PM.rec_cap > 0;
+    PcBufs pb{};
+    PcScalars ps{h->dt, h->theta, P.op.d_max, P.op.max_edge, P.op.kappa, 0.0};
+    if (pc || pc_rec) {
+        if (!kF64 || gmres || !bs.herm || g.queue)
+            throw Error(DMRI_E_UNSUPPORTED,
+                        "the polynomial preconditioner and its recorder run with CG on the "
+                        "Hermitian (transformed) form in precision 0, without row queues");
+        if (pc && pc_rec)
+            throw Error(DMRI_E_UNSUPPORTED,
+                        "preconditioner samples come from Jacobi CG runs (precond = 0)");
+        if (opts(h).precond == 1 && !PM.set)
+            throw Error(DMRI_E_STATE, "precond = 1 needs network parameters "
+                                      "(dmri_precond_set_params)");
+    }
+    std::vector<int32_t> pc_prev, pc_cur;
+    if (pc) {
+        for (auto& v : W.pc_y) v.alloc(2 * nv);
+        W.pc_d.alloc(2 * nv);
+        W.pc_ab.alloc(ld);
+        W.pc_X.alloc(ld * 16);
+        W.pc_Y.alloc(ld * 2);
+        pb.y[0] = reinterpret_cast<double2*>(W.pc_y[0].p);
+        pb.y[1] = reinterpret_cast<double2*>(W.pc_y[1].p);
+        pb.d = reinterpret_cast<double2*>(W.pc_d.p);
+        pb.ab = W.pc_ab.p;
+        pc_prev.assign(static_cast<size_t>(n_sys), 0);
+        pc_cur.resize(static_cast<size_t>(n_sys));
+    }
+    if (pc_rec) {
+        W.pc_hist.alloc(ld * kRitzMax);
+        s.ab_hist = W.pc_hist.p;
+    }
+
     KernelTimer timer(h, st, opts(h).time_kernel);
     const double t0 = now_s();
     int last_iters = 8;
@@ -1255,9 +1382,43 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
             if (gmres)
                 done = gmres_loop(h, bs, Av, W.gq.p, lhs, hs.x(), r, p, q, bv, s, n_sys);
         }
-        if (!gmres)
+        if (!gmres && !pc)
             done = krylov_loop<T>(h, bs, Av, W.gq.p, lhs, hs.x(), r, p, q, s, timer,
                                   last_iters - 2, opts(h).max_iter);
+        if constexpr (kF64) {
+            if (pc) {
+                ps.F = lhs.F;
+                launch_pc_interval(st, static_cast<int32_t>(n_sys), static_cast<int32_t>(ld),
+                                   W.gq.p, ps, opts(h).precond == 1 ? PM.theta.p : nullptr,
+                                   opts(h).cheb_a, opts(h).cheb_b, W.pc_X.p, W.pc_Y.p, pb.ab);
+                done = fcg_loop(h, bs, Av, W.gq.p, lhs, hs.x(), r, p, q, pb, s, timer,
+                                opts(h).max_iter);
+                // Jacobi CG re-solves the step from the flexible solve's x
+                // when a system ended with a flag it did not have before.
+                HIPCHK(hipMemcpyAsync(pc_cur.data(), s.flags, sizeof(int32_t) * n_sys,
+                                      hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                if (pc_cur != pc_prev) {
+                    HIPCHK(hipMemcpyAsync(s.flags, pc_prev.data(), sizeof(int32_t) * n_sys,
+                                          hipMemcpyHostToDevice, st));
+                    launch_init<T>(st, g, Av, W.gq.p, lhs, rhs, bs.herm, 2, hs.u(0), hs.u(1),
+                                   hs.x(), r, p, nullptr, nullptr, bv, s, bs.sc,
+                                   wb ? wv.map : nullptr, wb);
+                    done += krylov_loop<T>(h, bs, Av, W.gq.p, lhs, hs.x(), r, p, q, s, timer,
+                                           8, opts(h).max_iter);
+                    HIPCHK(hipMemcpyAsync(pc_cur.data(), s.flags, sizeof(int32_t) * n_sys,
+                                          hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    h->pc_fallbacks.fetch_add(1);
+                }
+                pc_prev.swap(pc_cur);
+            }
+            if (pc_rec) {
+                ps.F = lhs.F;
+                launch_pc_record(st, static_cast<int32_t>(n_sys), W.gq.p, ps, s, PM.rec_X,
+                                 PM.rec_T, PM.rec_count_dev.p, PM.rec_cap);
+            }
+        }
         last_iters = done;
         if constexpr (kF64) {
             record_samples(h, g, dofs, tr, F, f, n, n_sys, hs, hs.x());
@@ -1495,6 +1656,9 @@ void fill_stats(dmri_stats* stats, const std::vector<int64_t>& owner_idx, const 
 
 void run_batch_with(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
                     const double* d_q, double2* d_sig, BatchResult& R) {
+    if ((opts(h).precond != 0 || h->pcmodel.rec_cap > 0) && opts(h).precision != 0)
+        throw Error(DMRI_E_UNSUPPORTED,
+                    "the polynomial preconditioner and its recorder run in precision 0");
     if (opts(h).precision == 0) {
         solve_batch<double>(h, P, P.A64, n_sys, d_b, d_q, d_sig, R);
     } else if (opts(h).precision == 2) {
@@ -1508,11 +1672,13 @@ void run_batch_with(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b
 struct OptionGuard {
     dmri_ctx* h;
     Options saved;
-    int64_t rec_cap;
-    explicit OptionGuard(dmri_ctx* hh) : h(hh), saved(opts(hh)), rec_cap(hh->model.rec_cap) {}
+    int64_t rec_cap, pc_rec_cap;
+    explicit OptionGuard(dmri_ctx* hh)
+        : h(hh), saved(opts(hh)), rec_cap(hh->model.rec_cap), pc_rec_cap(hh->pcmodel.rec_cap) {}
     ~OptionGuard() {
         opts(h) = saved;
         h->model.rec_cap = rec_cap;
+        h->pcmodel.rec_cap = pc_rec_cap;
     }
 };
 
@@ -1524,6 +1690,7 @@ TuneChoice autotune(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b
                     const double* d_q) {
     OptionGuard guard(h);
     h->model.rec_cap = 0;
+    h->pcmodel.rec_cap = 0;
     const int total = opts(h).n_steps > 0 ? std::min(opts(h).n_steps, h->n_steps) : h->n_steps;
     opts(h).n_steps = std::max(1, std::min(4, total));
     opts(h).signal = 0;  // trial signals are discarded
@@ -1658,8 +1825,7 @@ void need_sequence(dmri_ctx* h) {
 constexpr char kModelMagic[8] = {'D', 'M', 'R', 'I', 'M', 'L', 'P', '1'};
 
 // New parameters; the Adam moments restart from zero.
-void set_guess_params(dmri_ctx* h, const float* host_theta) {
-    GuessModel& M = h->model;
+void set_model_params(dmri_ctx* h, GuessModel& M, const float* host_theta) {
     hipStream_t st = lane(h).stream;
     M.theta.alloc(kMlpParams);
     M.adam_m.alloc(kMlpParams);
@@ -1675,13 +1841,40 @@ void set_guess_params(dmri_ctx* h, const float* host_theta) {
 }
 
 // Gradient and loss of the current parameters over n samples into M.grad.
-void grad_pass(dmri_ctx* h, int64_t n, const float* X, const float* T) {
-    GuessModel& M = h->model;
+void grad_pass(dmri_ctx* h, GuessModel& M, int64_t n, const float* X, const float* T) {
     int n_cu = 0;
     HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
     const int waves = std::max(4, 4 * n_cu);  // one block of four waves per CU
     M.partial.alloc(static_cast<size_t>(waves) * (kMlpParams + 1));
     launch_mlp_grad(lane(h).stream, n, X, T, M.theta.p, M.partial.p, waves, M.grad.p);
+}
+
+
+// n_iters full-batch Adam steps of network M on n device samples.
+void train_model(dmri_ctx* h, GuessModel& M, int64_t n, const float* X, const float* T,
+                 int32_t n_iters, double lr, double* loss_first, double* loss_last) {
+    if (n < 1 || !X || !T || n_iters < 1)
+        throw Error(DMRI_E_INVALID, "need n >= 1, n_iters >= 1 and sample buffers");
+    if (!(lr > 0.0) || !std::isfinite(lr)) throw Error(DMRI_E_INVALID, "lr must be > 0");
+    hipStream_t st = lane(h).stream;
+    M.loss_hist.alloc(2);
+    for (int32_t it = 0; it < n_iters; ++it) {
+        grad_pass(h, M, n, X, T);
+        if (it == 0)
+            HIPCHK(hipMemcpyAsync(M.loss_hist.p, M.grad.p + kMlpParams, sizeof(float),
+                                  hipMemcpyDeviceToDevice, st));
+        if (it == n_iters - 1)
+            HIPCHK(hipMemcpyAsync(M.loss_hist.p + 1, M.grad.p + kMlpParams, sizeof(float),
+                                  hipMemcpyDeviceToDevice, st));
+        ++M.adam_t;
+        launch_adam(st, M.theta.p, M.adam_m.p, M.adam_v.p, M.grad.p, static_cast<float>(lr), 0.9f,
+                    0.999f, 1e-8f, M.adam_t);
+    }
+    float lh[2] = {0.0f, 0.0f};
+    HIPCHK(hipMemcpyAsync(lh, M.loss_hist.p, sizeof(lh), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (loss_first) *loss_first = lh[0];
+    if (loss_last) *loss_last = lh[1];
 }
 
 }  // namespace
@@ -1994,7 +2187,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         else if (k == "nt") o.nt = as_int(0, 1);
         else if (k == "lds") o.lds = as_int(0, 1);
         else if (k == "persistent") o.persistent = as_int(0, 2);
-        else if (k == "time_kernel") o.time_kernel = as_int(0, 6);
+        else if (k == "time_kernel") o.time_kernel = as_int(0, 7);
         else if (k == "progress") o.progress = as_int(0, 1000000);
         else if (k == "ordering") o.ordering = as_int(0, 1);
         else if (k == "pencil") o.pencil = as_int(1, 4096);
@@ -2010,7 +2203,15 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
             o.weak_kappa = v;
         } else if (k == "markers") o.markers = as_int(0, 1);
         else if (k == "dir_bf16") o.dir_bf16 = as_int(0, 1);
-        else throw Error(DMRI_E_INVALID, "unknown option " + k);
+        else if (k == "precond") o.precond = as_int(0, 2);
+        else if (k == "cheb_terms") o.cheb_terms = as_int(1, 16);
+        else if (k == "cheb_a" || k == "cheb_b") {
+            const double a = k == "cheb_a" ? v : o.cheb_a, b = k == "cheb_b" ? v : o.cheb_b;
+            if (!(a > 0.0 && b <= 1e6 && a * 1.001 < b))
+                throw Error(DMRI_E_INVALID, "need 0 < cheb_a, cheb_a * 1.001 < cheb_b <= 1e6");
+            o.cheb_a = a;
+            o.cheb_b = b;
+        } else throw Error(DMRI_E_INVALID, "unknown option " + k);
         return DMRI_OK;
     });
 }
@@ -2054,6 +2255,11 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "weak_kappa") *value = o.weak_kappa;
         else if (k == "markers") *value = o.markers;
         else if (k == "dir_bf16") *value = o.dir_bf16;
+        else if (k == "precond") *value = o.precond;
+        else if (k == "cheb_terms") *value = o.cheb_terms;
+        else if (k == "cheb_a") *value = o.cheb_a;
+        else if (k == "cheb_b") *value = o.cheb_b;
+        else if (k == "pc_fallback_steps") *value = static_cast<double>(h->pc_fallbacks.load());
         else if (k == "tuned_sys_tile") *value = h->last_tune.sys_tile;
         else if (k == "tuned_blocks_per_xcd") *value = h->last_tune.blocks_per_xcd;
         else if (k == "tuned_persistent") *value = h->last_tune.persistent;
@@ -2070,7 +2276,7 @@ dmri_status dmri_guess_set_params(dmri_handle h, const float* params, int64_t n_
         need_device(h);
         if (!params || n_params != kMlpParams)
             throw Error(DMRI_E_INVALID, "params must hold DMRI_GUESS_N_PARAMS floats");
-        set_guess_params(h, params);
+        set_model_params(h, h->model, params);
         return DMRI_OK;
     });
 }
@@ -2106,7 +2312,7 @@ dmri_status dmri_load_guess_model(dmri_handle h, const char* path) {
         if (!ok || std::memcmp(magic, kModelMagic, 8) != 0 || dims[0] != kMlpIn ||
             dims[1] != kMlpHid || dims[2] != kMlpOut)
             throw Error(DMRI_E_INVALID, std::string("not a guess-network file: ") + path);
-        set_guess_params(h, theta.data());
+        set_model_params(h, h->model, theta.data());
         return DMRI_OK;
     });
 }
@@ -2241,7 +2447,7 @@ dmri_status dmri_guess_eval(dmri_handle h, int64_t n, const float* d_features,
         GuessModel& M = h->model;
         if (d_out) launch_mlp_forward(st, n, d_features, M.theta.p, d_out);
         if (d_grad || loss) {
-            grad_pass(h, n, d_features, d_targets);
+            grad_pass(h, h->model, n, d_features, d_targets);
             if (d_grad)
                 HIPCHK(hipMemcpyAsync(d_grad, M.grad.p, sizeof(float) * kMlpParams,
                                       hipMemcpyDeviceToDevice, st));
@@ -2265,29 +2471,81 @@ dmri_status dmri_guess_train(dmri_handle h, int64_t n, const float* d_features,
     return guarded(h, [&]() -> dmri_status {
         need_device(h);
         if (!h->model.set) throw Error(DMRI_E_STATE, "no guess network parameters set");
-        if (n < 1 || !d_features || !d_targets || n_iters < 1)
-            throw Error(DMRI_E_INVALID, "need n >= 1, n_iters >= 1 and sample buffers");
-        if (!(lr > 0.0) || !std::isfinite(lr)) throw Error(DMRI_E_INVALID, "lr must be > 0");
-        hipStream_t st = lane(h).stream;
-        GuessModel& M = h->model;
-        M.loss_hist.alloc(2);
-        for (int32_t it = 0; it < n_iters; ++it) {
-            grad_pass(h, n, d_features, d_targets);
-            if (it == 0)
-                HIPCHK(hipMemcpyAsync(M.loss_hist.p, M.grad.p + kMlpParams, sizeof(float),
-                                      hipMemcpyDeviceToDevice, st));
-            if (it == n_iters - 1)
-                HIPCHK(hipMemcpyAsync(M.loss_hist.p + 1, M.grad.p + kMlpParams, sizeof(float),
-                                      hipMemcpyDeviceToDevice, st));
-            ++M.adam_t;
-            launch_adam(st, M.theta.p, M.adam_m.p, M.adam_v.p, M.grad.p, static_cast<float>(lr),
-                        0.9f, 0.999f, 1e-8f, M.adam_t);
+        train_model(h, h->model, n, d_features, d_targets, n_iters, lr, loss_first, loss_last);
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_precond_set_params(dmri_handle h, const float* params, int64_t n_params) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        if (!params || n_params != kMlpParams)
+            throw Error(DMRI_E_INVALID, "params must hold DMRI_PRECOND_N_PARAMS floats");
+        set_model_params(h, h->pcmodel, params);
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_precond_get_params(dmri_handle h, float* params, int64_t n_params) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        if (!params || n_params != kMlpParams)
+            throw Error(DMRI_E_INVALID, "params must hold DMRI_PRECOND_N_PARAMS floats");
+        if (!h->pcmodel.set) throw Error(DMRI_E_STATE, "no preconditioner network parameters set");
+        HIPCHK(hipMemcpyAsync(params, h->pcmodel.theta.p, sizeof(float) * kMlpParams,
+                              hipMemcpyDeviceToHost, lane(h).stream));
+        HIPCHK(hipStreamSynchronize(lane(h).stream));
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_precond_record(dmri_handle h, float* d_features, float* d_targets,
+                                int64_t capacity) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        if (capacity < 0) throw Error(DMRI_E_INVALID, "need capacity >= 0");
+        if (capacity > 0 && (!d_features || !d_targets))
+            throw Error(DMRI_E_INVALID, "NULL sample buffer");
+        GuessModel& M = h->pcmodel;
+        M.rec_X = capacity > 0 ? d_features : nullptr;
+        M.rec_T = capacity > 0 ? d_targets : nullptr;
+        M.rec_cap = capacity;
+        M.rec_count_dev.alloc(1);
+        const int64_t zero = 0;
+        HIPCHK(hipMemcpyAsync(M.rec_count_dev.p, &zero, sizeof zero, hipMemcpyHostToDevice,
+                              lane(h).stream));
+        HIPCHK(hipStreamSynchronize(lane(h).stream));
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_precond_record_count(dmri_handle h, int64_t* count) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        if (!count) throw Error(DMRI_E_INVALID, "NULL argument");
+        *count = 0;
+        GuessModel& M = h->pcmodel;
+        if (M.rec_count_dev.p) {
+            need_device(h);
+            HIPCHK(hipMemcpyAsync(count, M.rec_count_dev.p, sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, lane(h).stream));
+            HIPCHK(hipStreamSynchronize(lane(h).stream));
         }
-        float lh[2] = {0.0f, 0.0f};
-        HIPCHK(hipMemcpyAsync(lh, M.loss_hist.p, sizeof(lh), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (loss_first) *loss_first = lh[0];
-        if (loss_last) *loss_last = lh[1];
+        return DMRI_OK;
+    });
+}
+
+dmri_status dmri_precond_train(dmri_handle h, int64_t n, const float* d_features,
+                               const float* d_targets, int32_t n_iters, double lr,
+                               double* loss_first, double* loss_last) {
+    if (!h) return set_err(nullptr, DMRI_E_INVALID, "NULL handle");
+    return guarded(h, [&]() -> dmri_status {
+        need_device(h);
+        if (!h->pcmodel.set) throw Error(DMRI_E_STATE, "no preconditioner network parameters set");
+        train_model(h, h->pcmodel, n, d_features, d_targets, n_iters, lr, loss_first, loss_last);
         return DMRI_OK;
     });
 }
@@ -2376,7 +2634,7 @@ bool run_host_pairs(dmri_ctx* h, int64_t n_pairs, const int32_t* problem_id, con
     // Several problems run concurrently, one lane (stream, workspace, host
     // thread) each, unless a feature shares state across batches.
     int n_lanes = std::min<int>(opts(h).concurrency, static_cast<int>(groups.size()));
-    if (h->model.rec_cap > 0) n_lanes = 1;  // one sample recorder
+    if (h->model.rec_cap > 0 || h->pcmodel.rec_cap > 0) n_lanes = 1;  // one sample recorder
     if (n_lanes <= 1) {
         for (const auto& gr : groups) run_group(gr.first, gr.second);
     } else {
@@ -2492,8 +2750,11 @@ void run_noalloc(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b, c
         throw Error(DMRI_E_UNSUPPORTED, "the no-allocation entry point has no learned guess");
     if (o.krylov == 3)
         throw Error(DMRI_E_UNSUPPORTED, "the no-allocation entry point runs CG or COCG");
-    if (h->model.rec_cap > 0)
+    if (h->model.rec_cap > 0 || h->pcmodel.rec_cap > 0)
         throw Error(DMRI_E_UNSUPPORTED, "sample recording allocates; not with this entry point");
+    if (o.precond != 0)
+        throw Error(DMRI_E_UNSUPPORTED,
+                    "the no-allocation entry point runs Jacobi CG or COCG (precond = 0)");
     if (!P.op.wk_rows.empty())
         throw Error(DMRI_E_UNSUPPORTED,
                     "the no-allocation entry point has no weak pseudo-periodic faces");

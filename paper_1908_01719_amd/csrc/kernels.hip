@@ -16,6 +16,7 @@
 // block stores one partial per system and item, and a finalize kernel adds
 // them in a fixed order. The hot kernels contain no fences.
 #include "kernels.hpp"
+#include "mlp.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -41,11 +42,28 @@ template <typename T> using V2 = typename Vec2Of<T>::type;
 template <typename T> using V4 = typename Vec4Of<T>::type;
 
 // FIN_REFINE: as FIN_INIT for a refinement pass, keeping the step's ||b||^2.
-enum FinMode { FIN_ALPHA = 0, FIN_BETA = 1, FIN_INIT = 2, FIN_SIGNAL = 3, FIN_REFINE = 4 };
+// Flexible CG with a polynomial preconditioner: FIN_CHECK takes the
+// convergence decision of FIN_BETA from ||r||^2 alone; FIN_FLEX0 / FIN_FLEX
+// read rho' = r^H z and q^H z of the preconditioned residual z and set
+// beta = 0 (first direction) or beta = -(q^H z) / (p^H q).
+enum FinMode {
+    FIN_ALPHA = 0,
+    FIN_BETA = 1,
+    FIN_INIT = 2,
+    FIN_SIGNAL = 3,
+    FIN_REFINE = 4,
+    FIN_CHECK = 5,
+    FIN_FLEX0 = 6,
+    FIN_FLEX = 7
+};
 
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
     const double den = b.x * b.x + b.y * b.y;
     return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
 // Per-lane coefficients of one operator: c on M_D, (d0, d1, d2) on V.
@@ -778,6 +796,292 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(Geom g, const T* __restrict_
         pupdate_item<T, S>(g, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y), do_p,
                            static_cast<T>(al.x), static_cast<T>(al.y), do_x, dK0, daux, r, p, x);
     }
+}
+
+// ------------------------------ polynomial preconditioner in flexible CG
+//
+// Chebyshev acceleration of Jacobi on the interval [a, b] of D^-1 A (Saad,
+// Iterative Methods for Sparse Linear Systems, Sec. 12.3), m terms from
+// y = 0, one launch per term:
+//   theta = (b + a)/2, delta = (b - a)/2, sigma = theta/delta, rho_0 = 1/sigma
+//   term 0:  d = D^-1 r / theta,  y = d
+//   term j:  rho_j = 1 / (2 sigma - rho_{j-1}),
+//            d = rho_j rho_{j-1} d + (2 rho_j / delta) D^-1 (r - A y),  y += d
+// Neighbouring rows gather y, so a term reads y from one buffer and writes
+// y + d to the other; d is updated in place. The last term also forms the
+// flexible-CG dot products r^H z and q^H z (z = the new y).
+
+__device__ __forceinline__ void cheb_coef(double2 ab, int j, double& c1, double& c2) {
+    const double th = 0.5 * (ab.y + ab.x), de = 0.5 * (ab.y - ab.x);
+    if (j == 0) {
+        c1 = 0.0;
+        c2 = 1.0 / th;
+        return;
+    }
+    const double sg = th / de;
+    double rho = 1.0 / sg, prev = rho;
+    for (int i = 1; i <= j; ++i) {
+        prev = rho;
+        rho = 1.0 / (2.0 * sg - prev);
+    }
+    c1 = rho * prev;
+    c2 = 2.0 * rho / de;
+}
+
+template <int S, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_cheb(
+    Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const double* __restrict__ K0, const double4* __restrict__ aux,
+    const double* __restrict__ dK0, const double4* __restrict__ daux,
+    const double4* __restrict__ gq, Coef lhs, const double2* __restrict__ ab, int32_t term,
+    const double2* __restrict__ r, const double2* __restrict__ q,
+    const double2* __restrict__ y_in, double2* __restrict__ y_out, double2* __restrict__ d,
+    SolverState s, Scratch sc) {
+    __shared__ double lds[kWaves * S * 4];
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part, item = ir.item;
+        const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
+        const bool act = sys < s.n_sys && s.active[sys];
+        if (!__syncthreads_or(act)) continue;
+        const LaneCoef<double> lc(gq[sys], lhs, g, sys);
+        double c1 = 0.0, c2 = 0.0;
+        if (act) cheb_coef(ab[sys], term, c1, c2);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        sweep_gather<S>(g, part, j, nullptr, [&](int row) {
+            if (!act) return;
+            double yr = 0.0, yi = 0.0;
+            if (!FIRST) {  // (A y)_row
+                const int kb = row_ptr[row], ke = row_ptr[row + 1];
+                const double cm = lc.cr(row);
+                for (int k0 = kb; k0 < ke; k0 += kRowPad) {
+                    int jj[kRowPad];
+                    double2 xv[kRowPad];
+#pragma unroll
+                    for (int u = 0; u < kRowPad; ++u) jj[u] = col[k0 + u];
+#pragma unroll
+                    for (int u = 0; u < kRowPad; ++u)
+                        xv[u] = y_in[tb + static_cast<size_t>(jj[u]) * S];
+#pragma unroll
+                    for (int u = 0; u < kRowPad; ++u) {
+                        const double4 a = aux[k0 + u];
+                        const double ar = K0[k0 + u] + cm * a.x;
+                        const double ai = lc.d0 * a.y + lc.d1 * a.z + lc.d2 * a.w;
+                        yr += ar * xv[u].x - ai * xv[u].y;
+                        yi += ar * xv[u].y + ai * xv[u].x;
+                    }
+                }
+            }
+            const size_t idx = tb + static_cast<size_t>(row) * S;
+            const double2 rv = r[idx];
+            double dr, di;
+            diag_at(dK0, daux, row, lc, dr, di);
+            const double2 w = cdivT<double>(make_double2(rv.x - yr, rv.y - yi), dr, di);
+            double2 dn = make_double2(c2 * w.x, c2 * w.y);
+            double2 yn = dn;
+            if (!FIRST) {
+                const double2 dv = d[idx], yv = y_in[idx];
+                dn.x = fma(c1, dv.x, dn.x);
+                dn.y = fma(c1, dv.y, dn.y);
+                yn = make_double2(yv.x + dn.x, yv.y + dn.y);
+            }
+            if (!LAST) d[idx] = dn;
+            y_out[idx] = yn;
+            if (LAST) {
+                dot_acc<true, double>(acc[0], acc[1], rv, yn);
+                dot_acc<true, double>(acc[2], acc[3], q[idx], yn);
+            }
+        });
+        if (LAST) reduce_store<S, 4>(g, sc, item, j, acc, lds);
+    }
+}
+
+// x += alpha p (systems that took part in iteration k_iter), p = z + beta p
+// (systems still active), z read from a vector.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_pupdate_z(Geom g, const double2* __restrict__ z,
+                                                      double2* __restrict__ p,
+                                                      double2* __restrict__ x, int32_t k_iter,
+                                                      SolverState s) {
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    for (int kk = xcd; kk < g.n_items; kk += 8) {
+        const ItemRef ir = item_ref(g, kk);
+        const int tile = ir.tile, part = ir.part;
+        const int sys = tile * S + (threadIdx.x & 63) % S;
+        const size_t tb = vbase(g, tile, S, sys);
+        const bool real = sys < s.n_sys;
+        const bool do_p = real && s.active[sys];
+        const bool do_x = real && k_iter >= 0 && s.iters[sys] == k_iter;
+        if (!(do_p || do_x)) continue;
+        const double2 be = do_p ? s.beta[sys] : make_double2(0.0, 0.0);
+        const double2 al = do_x ? s.alpha[sys] : make_double2(0.0, 0.0);
+        sweep_static<S>(g, part, j, [&](int first, int r1) {
+#pragma unroll
+            for (int u = 0; u < kUs; ++u) {
+                bool ok;
+                const int row = slot_row<S>(first, u, r1, ok);
+                if (!ok) continue;
+                const size_t idx = tb + static_cast<size_t>(row) * S;
+                const double2 pv = p[idx];
+                if (do_x) {
+                    const double2 xv = x[idx];
+                    x[idx] = make_double2(xv.x + al.x * pv.x - al.y * pv.y,
+                                          xv.y + al.x * pv.y + al.y * pv.x);
+                }
+                if (do_p) {
+                    const double2 zv = z[idx];
+                    p[idx] = make_double2(zv.x + be.x * pv.x - be.y * pv.y,
+                                          zv.y + be.x * pv.y + be.y * pv.x);
+                }
+            }
+        });
+    }
+}
+
+// Inputs of the interval network for system sys at one step (zero past 7).
+__device__ __forceinline__ void pc_features(const double4 gg, const PcScalars ps, float* x) {
+    const double gf = fabs(gg.x * ps.F);
+    const double k = ps.theta * ps.dt;
+    const double qn = sqrt(gg.y * gg.y + gg.z * gg.z + gg.w * gg.w);
+    const double iq = qn > 0.0 ? 1.0 / qn : 0.0;
+    x[0] = static_cast<float>(log(k * ps.d_max / (ps.h * ps.h)));
+    x[1] = static_cast<float>(log1p(k * ps.d_max * gf * gf));
+    x[2] = static_cast<float>(log1p(k * ps.d_max * gf / ps.h));
+    x[3] = static_cast<float>(log1p(k * ps.kappa / ps.h));
+    x[4] = static_cast<float>(fabs(gg.y) * iq);
+    x[5] = static_cast<float>(fabs(gg.z) * iq);
+    x[6] = static_cast<float>(fabs(gg.w) * iq);
+#pragma unroll
+    for (int i = 7; i < 16; ++i) x[i] = 0.0f;
+}
+
+__global__ void k_pc_features(int32_t ld, const double4* __restrict__ gq, PcScalars ps,
+                              float* __restrict__ X) {
+    const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sys >= ld) return;
+    float f[16];
+    pc_features(gq[sys], ps, f);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) X[static_cast<size_t>(sys) * 16 + i] = f[i];
+}
+
+__global__ void k_pc_interval(int32_t n_sys, int32_t ld, const float* __restrict__ Y, double a,
+                              double b, double2* __restrict__ ab) {
+    const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sys >= ld) return;
+    double lo = a, hi = b;
+    if (Y && sys < n_sys) {
+        const double y0 = Y[2 * sys], y1 = Y[2 * sys + 1];
+        lo = kPcARef;
+        hi = kPcBRef;
+        if (isfinite(y0) && isfinite(y1)) {
+            const double ta = kPcARef * exp(fmin(20.0, fmax(-20.0, y0)));
+            const double tb = kPcBRef * exp(fmin(20.0, fmax(-20.0, y1)));
+            if (ta * 1.001 < tb) {
+                lo = ta;
+                hi = tb;
+            }
+        }
+    }
+    ab[sys] = make_double2(lo, hi);
+}
+
+// Eigenvalues of the Lanczos tridiagonal of a PCG run below x (Sturm count):
+// diagonal 1/alpha_0, 1/alpha_k + beta_{k-1}/alpha_{k-1}; squared
+// off-diagonal beta_{k-1}/alpha_{k-1}^2.
+__device__ int sturm_below(const double2* __restrict__ h, int n, double x) {
+    int cnt = 0;
+    double qv = 1.0;
+    for (int k = 0; k < n; ++k) {
+        const double al = h[k].x;
+        double dk = 1.0 / al;
+        double e2 = 0.0;
+        if (k > 0) {
+            const double ap = h[k - 1].x, bp = h[k - 1].y;
+            dk += bp / ap;
+            e2 = bp / (ap * ap);
+        }
+        qv = dk - x - (k > 0 ? e2 / qv : 0.0);
+        if (qv == 0.0) qv = -1e-300;
+        if (qv < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// One block: systems in order, a block-wide scan of the valid ones gives
+// each sample its slot; *count advances by the number written.
+__global__ __launch_bounds__(1024) void k_pc_record(int32_t n_sys, const double4* __restrict__ gq,
+                                                    PcScalars ps, SolverState s,
+                                                    float* __restrict__ X, float* __restrict__ T,
+                                                    int64_t* __restrict__ count, int64_t cap) {
+    __shared__ int scan[1024];
+    __shared__ int64_t base;
+    if (threadIdx.x == 0) base = *count;
+    __syncthreads();
+    for (int c0 = 0; c0 < n_sys; c0 += 1024) {
+        const int sys = c0 + static_cast<int>(threadIdx.x);
+        bool ok = false;
+        double lo = 0.0, hi = 0.0;
+        if (sys < n_sys) {
+            const int n = s.iters[sys];
+            const double2* h = s.ab_hist + static_cast<size_t>(sys) * kRitzMax;
+            ok = s.flags[sys] == 0 && n >= 2 && n <= kRitzMax;
+            double glo = 1e300, ghi = -1e300;
+            for (int k = 0; ok && k < n; ++k) {
+                const double al = h[k].x;
+                const double bp = k > 0 ? h[k - 1].y : 0.0;
+                ok = isfinite(al) && al > 0.0 && isfinite(bp) && bp >= 0.0;
+                if (!ok) break;
+                // Gershgorin bracket of the tridiagonal
+                const double ap = k > 0 ? h[k - 1].x : 1.0;
+                const double dk = 1.0 / al + (k > 0 ? bp / ap : 0.0);
+                const double el = k > 0 ? sqrt(bp) / ap : 0.0;
+                const double er = k + 1 < n ? sqrt(fmax(0.0, h[k].y)) / al : 0.0;
+                glo = fmin(glo, dk - el - er);
+                ghi = fmax(ghi, dk + el + er);
+            }
+            if (ok) {
+                // smallest: the x with one eigenvalue below; largest: n - 1 below
+                double a0 = glo, b0 = ghi;
+                for (int it = 0; it < 100; ++it) {
+                    const double m = 0.5 * (a0 + b0);
+                    if (sturm_below(h, n, m) >= 1) b0 = m; else a0 = m;
+                }
+                lo = 0.5 * (a0 + b0);
+                a0 = glo;
+                b0 = ghi;
+                for (int it = 0; it < 100; ++it) {
+                    const double m = 0.5 * (a0 + b0);
+                    if (sturm_below(h, n, m) >= n) b0 = m; else a0 = m;
+                }
+                hi = 0.5 * (a0 + b0);
+                ok = lo > 0.0 && hi >= lo && isfinite(hi);
+            }
+        }
+        scan[threadIdx.x] = ok ? 1 : 0;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int v = threadIdx.x >= static_cast<unsigned>(off) ? scan[threadIdx.x - off] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        const int64_t pos = base + scan[threadIdx.x] - 1;
+        if (ok && pos < cap) {
+            float f[16];
+            pc_features(gq[sys], ps, f);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) X[pos * 16 + i] = f[i];
+            T[pos * 2] = static_cast<float>(log(lo / kPcARef));
+            T[pos * 2 + 1] = static_cast<float>(log(kPcMargin * hi / kPcBRef));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) base = base + scan[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base < cap ? base : cap;
 }
 
 // ------------------------------------------- paired lanes (FP32, 128 systems)
@@ -1775,7 +2079,9 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, S
     const int grp = threadIdx.x / S, sl = threadIdx.x % S;
     const int sys = tile * S + sl;
     if (zero_ctr && threadIdx.x < g.n_parts) zero_ctr[tile * g.n_parts + threadIdx.x] = 0;
-    if (MODE == FIN_ALPHA || MODE == FIN_BETA) {
+    constexpr bool kActiveOnly = MODE == FIN_ALPHA || MODE == FIN_BETA || MODE == FIN_CHECK ||
+                                 MODE == FIN_FLEX0 || MODE == FIN_FLEX;
+    if (kActiveOnly) {
         const bool act = sys < s.n_sys && s.active[sys];
         if (!__syncthreads_or(act)) return;
     }
@@ -1821,9 +2127,34 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, S
         if (MODE == FIN_SIGNAL) {
             if (sys < n_sig) out[sys] = make_double2(tot[0], tot[1]);
         } else if (MODE == FIN_ALPHA) {
-            if (sys < s.n_sys && s.active[sys])
-                s.alpha[sys] = cdiv(s.rho[sys], make_double2(tot[0], tot[1]));
-        } else if (MODE == FIN_BETA) {
+            if (sys < s.n_sys && s.active[sys]) {
+                const double2 al = cdiv(s.rho[sys], make_double2(tot[0], tot[1]));
+                s.alpha[sys] = al;
+                if (s.ab_hist) {
+                    const int it = s.iters[sys];
+                    if (it < kRitzMax) s.ab_hist[static_cast<size_t>(sys) * kRitzMax + it].x = al.x;
+                }
+            }
+        } else if (MODE == FIN_FLEX0 || MODE == FIN_FLEX) {
+            if (sys < s.n_sys && s.active[sys]) {
+                const double2 rho_new = make_double2(tot[0], tot[1]);
+                const double2 qz = make_double2(tot[2], tot[3]);
+                if (!isfinite(rho_new.x) || !isfinite(rho_new.y) || !isfinite(qz.x) ||
+                    !isfinite(qz.y)) {
+                    s.flags[sys] |= 2;
+                    s.active[sys] = 0;
+                } else {
+                    double2 be = make_double2(0.0, 0.0);
+                    if (MODE == FIN_FLEX) {  // -(q^H z) / sigma with sigma = rho / alpha
+                        const double2 t = cdiv(cmul(qz, s.alpha[sys]), s.rho[sys]);
+                        be = make_double2(-t.x, -t.y);
+                    }
+                    s.beta[sys] = be;
+                    s.rho[sys] = rho_new;
+                    atomicAdd(&cnt, 1);
+                }
+            }
+        } else if (MODE == FIN_BETA || MODE == FIN_CHECK) {
             if (sys < s.n_sys && s.active[sys]) {
                 const double2 rho_new = make_double2(tot[0], tot[1]);
                 const double rr = tot[2];
@@ -1843,9 +2174,14 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, S
                 }
                 if (stop) {
                     s.active[sys] = 0;
+                } else if (MODE == FIN_CHECK) {
+                    atomicAdd(&cnt, 1);
                 } else {
-                    s.beta[sys] = cdiv(rho_new, s.rho[sys]);
+                    const double2 be = cdiv(rho_new, s.rho[sys]);
+                    s.beta[sys] = be;
                     s.rho[sys] = rho_new;
+                    if (s.ab_hist && it_now - 1 < kRitzMax)
+                        s.ab_hist[static_cast<size_t>(sys) * kRitzMax + it_now - 1].y = be.x;
                     atomicAdd(&cnt, 1);
                 }
             }
@@ -1873,7 +2209,9 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, S
         }
     }
     __syncthreads();
-    if ((MODE == FIN_BETA || MODE == FIN_INIT || MODE == FIN_REFINE) && threadIdx.x == 0)
+    if ((MODE == FIN_BETA || MODE == FIN_INIT || MODE == FIN_REFINE || MODE == FIN_CHECK ||
+         MODE == FIN_FLEX0 || MODE == FIN_FLEX) &&
+        threadIdx.x == 0)
         s.n_active[tile] = cnt;
 }
 
@@ -2660,7 +2998,7 @@ void launch_spmv_dot(hipStream_t st, const Geom& g, const MatView<T>& A, const d
 template <typename T>
 void launch_update(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
                    Coef lhs, bool herm, V2<T>* x, V2<T>* r, const V2<T>* p, const V2<T>* q,
-                   SolverState s, Scratch sc) {
+                   SolverState s, Scratch sc, bool check_only) {
     const dim3 grid = grid_of(g), block(kBlock);
     if (g.S == kPairS) {
         if constexpr (sizeof(T) == 4) {
@@ -2687,7 +3025,65 @@ void launch_update(hipStream_t st, const Geom& g, const MatView<T>& A, const dou
                                                           s, sc);
     });
     check_launch("update");
-    launch_fin<FIN_BETA, 3>(st, g, s, sc, nullptr, 0, nullptr);
+    if (check_only) launch_fin<FIN_CHECK, 3>(st, g, s, sc, nullptr, 0, nullptr);
+    else launch_fin<FIN_BETA, 3>(st, g, s, sc, nullptr, 0, nullptr);
+}
+
+const double2* launch_cheb(hipStream_t st, const Geom& g, const MatView<double>& A,
+                           const double4* gq, Coef lhs, const double2* ab, int m, bool start,
+                           const double2* r, const double2* q, double2* const y[2], double2* d,
+                           SolverState s, Scratch sc) {
+    if (g.queue || g.S == kPairS)
+        throw std::runtime_error("polynomial preconditioner: needs static sweeps, 8-64 systems a tile");
+    if (m < 1) throw std::runtime_error("polynomial preconditioner: at least one term");
+    const dim3 grid = grid_of(g), block(kBlock);
+    for (int t = 0; t < m; ++t) {
+        const double2* yin = t > 0 ? y[(t - 1) & 1] : nullptr;
+        double2* yout = y[t & 1];
+        const bool first = t == 0, last = t == m - 1;
+#define DMRI_CHEB(F, L)                                                                        \
+    k_cheb<S, F, L><<<grid, block, 0, st>>>(g, A.row_ptr, A.col, A.K0, A.aux, A.dK0, A.daux,  \
+                                            gq, lhs, ab, t, r, q, yin, yout, d, s, sc)
+        DMRI_DISPATCH_S(g.S, {
+            if (first && last) DMRI_CHEB(true, true);
+            else if (first) DMRI_CHEB(true, false);
+            else if (last) DMRI_CHEB(false, true);
+            else DMRI_CHEB(false, false);
+        });
+#undef DMRI_CHEB
+        check_launch("cheb");
+    }
+    if (start) launch_fin<FIN_FLEX0, 4>(st, g, s, sc, nullptr, 0, nullptr);
+    else launch_fin<FIN_FLEX, 4>(st, g, s, sc, nullptr, 0, nullptr);
+    return y[(m - 1) & 1];
+}
+
+void launch_pupdate_z(hipStream_t st, const Geom& g, const double2* z, double2* p, double2* x,
+                      int32_t k_iter, SolverState s) {
+    if (g.S == kPairS) throw std::runtime_error("pupdate_z: 8-64 systems a tile");
+    const dim3 grid = grid_of(g), block(kBlock);
+    DMRI_DISPATCH_S(g.S, { k_pupdate_z<S><<<grid, block, 0, st>>>(g, z, p, x, k_iter, s); });
+    check_launch("pupdate_z");
+}
+
+void launch_pc_interval(hipStream_t st, int32_t n_sys, int32_t ld, const double4* gq,
+                        PcScalars ps, const float* theta, double a, double b, float* X, float* Y,
+                        double2* ab) {
+    const dim3 grid(static_cast<unsigned>((ld + 255) / 256)), block(256);
+    if (theta) {
+        k_pc_features<<<grid, block, 0, st>>>(ld, gq, ps, X);
+        check_launch("pc_features");
+        launch_mlp_forward(st, n_sys, X, theta, Y);
+    }
+    k_pc_interval<<<grid, block, 0, st>>>(n_sys, ld, theta ? Y : nullptr, a, b, ab);
+    check_launch("pc_interval");
+}
+
+void launch_pc_record(hipStream_t st, int32_t n_sys, const double4* gq, PcScalars ps,
+                      SolverState s, float* X, float* T, int64_t* count, int64_t cap) {
+    if (!s.ab_hist) throw std::runtime_error("pc_record: no coefficient history");
+    k_pc_record<<<1, 1024, 0, st>>>(n_sys, gq, ps, s, X, T, count, cap);
+    check_launch("pc_record");
 }
 
 template <typename T>
@@ -2927,7 +3323,7 @@ void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
                                      SolverState, Scratch);                                    \
     template void launch_update<T>(hipStream_t, const Geom&, const MatView<T>&,                \
                                    const double4*, Coef, bool, V2<T>*, V2<T>*, const V2<T>*,   \
-                                   const V2<T>*, SolverState, Scratch);                        \
+                                   const V2<T>*, SolverState, Scratch, bool);                  \
     template void launch_pupdate<T>(hipStream_t, const Geom&, const MatView<T>&,               \
                                     const double4*, Coef, const V2<T>*, V2<T>*, V2<T>*,        \
                                     int32_t, SolverState);                                     \

@@ -88,7 +88,13 @@ struct SolverState {
     // of mixed precision stop once they reach the outer tolerance).
     const double* floor_bb;
     double floor_scale;
+    // Optional record of the CG coefficients of the current step for the
+    // Ritz values that train the preconditioner's interval network:
+    // ab_hist[sys * kRitzMax + k] = {Re alpha_k, Re beta_k}.
+    double2* ab_hist;
 };
+
+constexpr int kRitzMax = 64;  // CG coefficients kept per system and step
 
 // Launch geometry shared by every kernel of a problem.
 struct Geom {
@@ -184,11 +190,51 @@ void launch_spmv_dot(hipStream_t st, const Geom& g, const MatView<T>& A, const d
                      Coef lhs, bool herm, const typename Vec2Of<T>::type* p,
                      typename Vec2Of<T>::type* q, SolverState s, Scratch sc);
 
+// r -= alpha q with the convergence decision on ||r||^2; check_only keeps
+// beta and rho (flexible CG forms them from the preconditioned residual).
 template <typename T>
 void launch_update(hipStream_t st, const Geom& g, const MatView<T>& A, const double4* gq,
                    Coef lhs, bool herm, typename Vec2Of<T>::type* x,
                    typename Vec2Of<T>::type* r, const typename Vec2Of<T>::type* p,
-                   const typename Vec2Of<T>::type* q, SolverState s, Scratch sc);
+                   const typename Vec2Of<T>::type* q, SolverState s, Scratch sc,
+                   bool check_only = false);
+
+// ---- polynomial preconditioner inside flexible CG (FP64, Hermitian) ----
+// z = p(D^-1 A) D^-1 r by m terms of the Chebyshev recurrence on each
+// system's interval ab[sys] = {a, b} (0 < a < b), for the systems active in
+// s: term 0 writes y[0] (and d), term j reads y[(j-1) & 1] and writes
+// y[j & 1]; returns z = y[(m-1) & 1]. The last term also forms r^H z and
+// q^H z, and a finalize sets rho = r^H z and beta = -(q^H z) / (p^H q) (or
+// beta = 0 when start is set). Needs static sweeps (g.queue == 0).
+const double2* launch_cheb(hipStream_t st, const Geom& g, const MatView<double>& A,
+                           const double4* gq, Coef lhs, const double2* ab, int m, bool start,
+                           const double2* r, const double2* q, double2* const y[2], double2* d,
+                           SolverState s, Scratch sc);
+
+// End of flexible-CG iteration k_iter: x += alpha p for the systems that took
+// part in it (none when k_iter < 0), p = z + beta p for the systems active.
+void launch_pupdate_z(hipStream_t st, const Geom& g, const double2* z, double2* p, double2* x,
+                      int32_t k_iter, SolverState s);
+
+// Scalars of one step for the interval network's features.
+struct PcScalars {
+    double dt, theta, d_max, h, kappa;
+    double F;  // F(t^n)
+};
+// Interval per system: features X[ld][16] -> network (theta, the packed
+// 16-64-64-2 parameters) -> Y[ld][2] -> ab[sys] = {A_ref e^Y0, B_ref e^Y1}
+// (clipped exponents; the reference interval where that is not finite or
+// not an interval). theta = NULL gives every system the interval {a, b}.
+constexpr double kPcARef = 0.5, kPcBRef = 1.5, kPcMargin = 1.1;
+void launch_pc_interval(hipStream_t st, int32_t n_sys, int32_t ld, const double4* gq,
+                        PcScalars ps, const float* theta, double a, double b, float* X, float* Y,
+                        double2* ab);
+// Training samples of a Jacobi-CG step (coefficients in s.ab_hist): every
+// system that took 2 to kRitzMax iterations and ended without a flag appends
+// its features and targets {log(ritz_min / A_ref), log(margin ritz_max /
+// B_ref)}, in system order, at *count while *count < cap.
+void launch_pc_record(hipStream_t st, int32_t n_sys, const double4* gq, PcScalars ps,
+                      SolverState s, float* X, float* T, int64_t* count, int64_t cap);
 
 template <typename T>
 // End of Krylov iteration k_iter (1-based within the solve): x += alpha p

@@ -73,7 +73,18 @@ void clip(std::vector<P2>& poly, const FaceTri& t, double eps) {
     }
 }
 
-// Largest eigenvalue of a symmetric 3x3 matrix (cyclic Jacobi rotations).
+struct Coo {
+    int32_t row, code, col;
+    double val;
+    bool operator<(const Coo& o) const {
+        if (row != o.row) return row < o.row;
+        if (code != o.code) return code < o.code;
+        return col < o.col;
+    }
+};
+
+}  // namespace
+
 double lambda_max(double A[3][3]) {
     for (int sweep = 0; sweep < 32; ++sweep) {
         double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
@@ -99,18 +110,6 @@ double lambda_max(double A[3][3]) {
     }
     return std::max(A[0][0], std::max(A[1][1], A[2][2]));
 }
-
-struct Coo {
-    int32_t row, code, col;
-    double val;
-    bool operator<(const Coo& o) const {
-        if (row != o.row) return row < o.row;
-        if (code != o.code) return code < o.code;
-        return col < o.col;
-    }
-};
-
-}  // namespace
 
 void add_weak_faces(const MeshInput& in, const std::vector<int32_t>& tdof, HostOperator& op) {
     static const int kFace[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
