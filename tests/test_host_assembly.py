@@ -273,3 +273,27 @@ def test_marker_and_weak_options():
             for v in bad:
                 with pytest.raises(DmriError, match="DMRI_E_INVALID"):
                     s.dmri_set_option(k, v)
+
+
+def test_preconditioner_options():
+    # precond, cheb_terms ranges; the fixed interval keeps 0 < a, 1.001 a < b
+    with Simulator(-1) as s:
+        for k, good, bad in (("precond", (0, 1, 2), (3, -1, 0.5)),
+                             ("cheb_terms", (1, 4, 16), (0, 17, 2.5))):
+            for v in good:
+                s.dmri_set_option(k, v)
+                assert s.dmri_get_option(k) == v
+            for v in bad:
+                with pytest.raises(DmriError, match="DMRI_E_INVALID"):
+                    s.dmri_set_option(k, v)
+        assert (s.dmri_get_option("cheb_a"), s.dmri_get_option("cheb_b")) == (0.5, 1.5)
+        s.dmri_set_option("cheb_b", 3.0)
+        s.dmri_set_option("cheb_a", 0.1)
+        assert (s.dmri_get_option("cheb_a"), s.dmri_get_option("cheb_b")) == (0.1, 3.0)
+        for k, v in (("cheb_a", 3.0), ("cheb_a", 0.0), ("cheb_a", -1.0), ("cheb_b", 0.1),
+                     ("cheb_b", 2e6)):
+            with pytest.raises(DmriError, match="DMRI_E_INVALID"):
+                s.dmri_set_option(k, v)
+        assert (s.dmri_get_option("cheb_a"), s.dmri_get_option("cheb_b")) == (0.1, 3.0)
+        assert s.dmri_get_option("pc_fallback_steps") == 0
+        assert s.dmri_precond_record_count() == 0
