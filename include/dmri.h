@@ -268,6 +268,10 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *               every recurrence uses the stored direction, so the residual
  *               stays consistent and the FP64 refinement sets the accuracy.
  *               0: FP32 directions
+ *  "spmv_rows"  2 (default): a wavefront of the paired BF16 SpMV takes its
+ *               rows two at a time, both rows' gathers in flight together (the
+ *               kernel is bound by the latency of each row's dependent loads);
+ *               1: one row at a time
  *  "markers"    1: roctx ranges ("dmri batch <systems>", "dmri step <n>")
  *               around each batch and time step, for profiler timelines
  *               (rocprofv3 --marker-trace); 0 (default): none

@@ -198,6 +198,7 @@ struct Options {
     double weak_kappa = 1.0;  // scale of kappa_e on weak pseudo-periodic faces
     int markers = 0;          // 1: roctx ranges around runs, batches and time steps
     int dir_bf16 = 1;         // paired FP32 inner solves keep their directions in BF16
+    int spmv_rows = 2;        // rows a wavefront of the paired BF16 SpMV takes at once (1, 2)
     // Krylov preconditioner of the FP64 Hermitian solves: 0 Jacobi (CG), 1
     // Chebyshev polynomial in D^-1 A on the interval the preconditioner
     // network predicts, 2 the same on the fixed interval [cheb_a, cheb_b];
@@ -901,6 +902,7 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
         bs.gi.nt = g.nt;
         bs.gi.lds = 0;
         bs.gi.dir16 = opts(h).dir_bf16;
+        bs.gi.rows2 = opts(h).spmv_rows;
     }
     const Geom& gi = bs.gi;
     const size_t ld_max = std::max<size_t>(ld, static_cast<size_t>(gi.ld));
@@ -2203,6 +2205,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
             o.weak_kappa = v;
         } else if (k == "markers") o.markers = as_int(0, 1);
         else if (k == "dir_bf16") o.dir_bf16 = as_int(0, 1);
+        else if (k == "spmv_rows") o.spmv_rows = as_int(1, 2);
         else if (k == "precond") o.precond = as_int(0, 2);
         else if (k == "cheb_terms") o.cheb_terms = as_int(1, 16);
         else if (k == "cheb_a" || k == "cheb_b") {
@@ -2255,6 +2258,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "weak_kappa") *value = o.weak_kappa;
         else if (k == "markers") *value = o.markers;
         else if (k == "dir_bf16") *value = o.dir_bf16;
+        else if (k == "spmv_rows") *value = o.spmv_rows;
         else if (k == "precond") *value = o.precond;
         else if (k == "cheb_terms") *value = o.cheb_terms;
         else if (k == "cheb_a") *value = o.cheb_a;

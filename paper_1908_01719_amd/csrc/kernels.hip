@@ -1191,8 +1191,40 @@ __device__ __forceinline__ void pair_block(const int32_t* __restrict__ col,
     }
 }
 
-// q = A p and sigma = p^H q (or p^T q) for the paired layout.
-template <bool HERM, bool B16>
+// The 16 BF16 direction gathers of a 16-entry row, and the row's products
+// from them (split so that two rows' gathers can be in flight together).
+__device__ __forceinline__ void gather16_b16(const int32_t* __restrict__ col,
+                                             __amdgpu_buffer_rsrc_t rs, uint32_t lane_bytes,
+                                             int k0, uint2 (&w)[16]) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const uint32_t off = static_cast<uint32_t>(col[k0 + u]) * (kPairS * 4u);
+        w[u] = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, lane_bytes, off, 0));
+    }
+}
+__device__ __forceinline__ void fma16_b16(const float* __restrict__ K0,
+                                          const float4* __restrict__ aux, int k0,
+                                          const LaneCoef<float>& c0, const LaneCoef<float>& c1,
+                                          float cm0, float cm1, const uint2 (&w)[16], float& yr0,
+                                          float& yi0, float& yr1, float& yi1) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const float4 a = aux[k0 + u];
+        const float k = K0[k0 + u];
+        const float2 x0 = make_float2(__uint_as_float(w[u].x << 16), __uint_as_float(w[u].x & 0xFFFF0000u));
+        const float2 x1 = make_float2(__uint_as_float(w[u].y << 16), __uint_as_float(w[u].y & 0xFFFF0000u));
+        const float ar0 = fma(cm0, a.x, k), ai0 = fma(c0.d2, a.w, fma(c0.d1, a.z, c0.d0 * a.y));
+        const float ar1 = fma(cm1, a.x, k), ai1 = fma(c1.d2, a.w, fma(c1.d1, a.z, c1.d0 * a.y));
+        cmac<float>(yr0, yi0, ar0, ai0, x0);
+        cmac<float>(yr1, yi1, ar1, ai1, x1);
+    }
+}
+
+// q = A p and sigma = p^H q (or p^T q) for the paired layout. With R2 = 2 (BF16
+// directions) a wavefront takes its rows two at a time: when both have 16
+// entries their 32 gathers are issued before either row's products, so two
+// rows' dependent chains (row pointer, column indices, gathers) overlap.
+template <bool HERM, bool B16, int R2 = 0>
 __global__ __launch_bounds__(kBlock) void k_spmv_pair(
     Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const float* __restrict__ K0, const float4* __restrict__ aux, const double4* __restrict__ gq,
@@ -1222,33 +1254,67 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(
         const int r0 = part * g.part_rows;
         const int r1 = min(g.n_rows, r0 + g.part_rows);
         const int step = g.B * g.chunk_rows;
+        // q row out, and its sigma terms from the lane's own direction row
+        auto finish = [&](int row, float yr0, float yi0, float yr1, float yi1) {
+            const size_t o = static_cast<size_t>(row) * 64 + lane;
+            const float4 y = make_float4(yr0, yi0, yr1, yi1);
+            if (g.nt) store_nt(qt + o, y);
+            else qt[o] = y;
+            const float4 pv = dir_load(pt, o);
+            dot_acc<HERM, float>(acc[0][0], acc[0][1], lo2(pv), lo2(y));
+            dot_acc<HERM, float>(acc[1][0], acc[1][1], hi2(pv), hi2(y));
+        };
+        auto one_row = [&](int row, int kb, int ke) {
+            const float cm0 = c0.cr(row), cm1 = c1.cr(row);
+            float yr0 = 0.f, yi0 = 0.f, yr1 = 0.f, yi1 = 0.f;
+            if (ke - kb == 16) {
+                pair_block<16, B16>(col, K0, aux, rs, lane_bytes, kb, c0, c1, cm0, cm1, yr0,
+                                    yi0, yr1, yi1);
+            } else {
+                for (int k0 = kb; k0 < ke; k0 += kRowPad)
+                    pair_block<kRowPad, B16>(col, K0, aux, rs, lane_bytes, k0, c0, c1, cm0, cm1,
+                                             yr0, yi0, yr1, yi1);
+            }
+            finish(row, yr0, yi0, yr1, yi1);
+        };
         for (int c0r = r0 + j * g.chunk_rows; c0r < r1; c0r += step) {
+            if constexpr (B16 && R2 == 2) {
+                static_assert(kUs % 2 == 0, "rows are taken in pairs");
 #pragma unroll
-            for (int u = 0; u < kUs; ++u) {
-                const int row = c0r + off + u * kWaves;
-                if (row >= r1) break;
-                // Lanes whose two systems have both converged neither gather
-                // nor store: in a tile that is only partly active, the cache
-                // lines of its converged systems are not fetched.
-                if (!la) continue;
-                const int kb = row_ptr[row], ke = row_ptr[row + 1];
-                const float cm0 = c0.cr(row), cm1 = c1.cr(row);
-                float yr0 = 0.f, yi0 = 0.f, yr1 = 0.f, yi1 = 0.f;
-                if (ke - kb == 16) {
-                    pair_block<16, B16>(col, K0, aux, rs, lane_bytes, kb, c0, c1, cm0, cm1, yr0,
-                                        yi0, yr1, yi1);
-                } else {
-                    for (int k0 = kb; k0 < ke; k0 += kRowPad)
-                        pair_block<kRowPad, B16>(col, K0, aux, rs, lane_bytes, k0, c0, c1, cm0,
-                                                 cm1, yr0, yi0, yr1, yi1);
+                for (int u = 0; u < kUs; u += 2) {
+                    const int ra = c0r + off + u * kWaves, rb = ra + kWaves;
+                    if (ra >= r1) break;
+                    if (!la) continue;
+                    const bool hb = rb < r1;
+                    const int kba = row_ptr[ra], kea = row_ptr[ra + 1];
+                    const int kbb = hb ? row_ptr[rb] : 0, keb = hb ? row_ptr[rb + 1] : 0;
+                    if (hb && kea - kba == 16 && keb - kbb == 16) {
+                        uint2 wa[16], wb[16];
+                        gather16_b16(col, rs, lane_bytes, kba, wa);
+                        gather16_b16(col, rs, lane_bytes, kbb, wb);
+                        float ya[4] = {0.f, 0.f, 0.f, 0.f}, yb[4] = {0.f, 0.f, 0.f, 0.f};
+                        fma16_b16(K0, aux, kba, c0, c1, c0.cr(ra), c1.cr(ra), wa, ya[0], ya[1],
+                                  ya[2], ya[3]);
+                        fma16_b16(K0, aux, kbb, c0, c1, c0.cr(rb), c1.cr(rb), wb, yb[0], yb[1],
+                                  yb[2], yb[3]);
+                        finish(ra, ya[0], ya[1], ya[2], ya[3]);
+                        finish(rb, yb[0], yb[1], yb[2], yb[3]);
+                    } else {
+                        one_row(ra, kba, kea);
+                        if (hb) one_row(rb, kbb, keb);
+                    }
                 }
-                const size_t o = static_cast<size_t>(row) * 64 + lane;
-                const float4 y = make_float4(yr0, yi0, yr1, yi1);
-                if (g.nt) store_nt(qt + o, y);
-                else qt[o] = y;
-                const float4 pv = dir_load(pt, o);
-                dot_acc<HERM, float>(acc[0][0], acc[0][1], lo2(pv), lo2(y));
-                dot_acc<HERM, float>(acc[1][0], acc[1][1], hi2(pv), hi2(y));
+            } else {
+#pragma unroll
+                for (int u = 0; u < kUs; ++u) {
+                    const int row = c0r + off + u * kWaves;
+                    if (row >= r1) break;
+                    // Lanes whose two systems have both converged neither
+                    // gather nor store: in a tile that is only partly active,
+                    // the cache lines of its converged systems are not fetched.
+                    if (!la) continue;
+                    one_row(row, row_ptr[row], row_ptr[row + 1]);
+                }
             }
         }
         reduce_store_pair<2>(g, sc, item, j, acc, lds);
@@ -2952,14 +3018,18 @@ void launch_spmv_dot(hipStream_t st, const Geom& g, const MatView<T>& A, const d
     if (g.S == kPairS) {
         if constexpr (sizeof(T) == 4) {
             auto* q4 = reinterpret_cast<float4*>(q);
-#define DMRI_SPP(H, B)                                                                        \
-    k_spmv_pair<H, B><<<grid, block, 0, st>>>(                                                 \
+#define DMRI_SPP(H, B, R)                                                                     \
+    k_spmv_pair<H, B, R><<<grid, block, 0, st>>>(                                              \
         g, A.row_ptr, A.col, A.K0, A.aux, gq, lhs,                                            \
         reinterpret_cast<const typename DirOf<B>::type*>(p), q4, s, sc)
             if (herm) {
-                if (g.dir16) DMRI_SPP(true, true); else DMRI_SPP(true, false);
+                if (g.dir16 && g.rows2 == 2) DMRI_SPP(true, true, 2);
+                else if (g.dir16) DMRI_SPP(true, true, 0);
+                else DMRI_SPP(true, false, 0);
             } else {
-                if (g.dir16) DMRI_SPP(false, true); else DMRI_SPP(false, false);
+                if (g.dir16 && g.rows2 == 2) DMRI_SPP(false, true, 2);
+                else if (g.dir16) DMRI_SPP(false, true, 0);
+                else DMRI_SPP(false, false, 0);
             }
 #undef DMRI_SPP
             check_launch("spmv_pair");

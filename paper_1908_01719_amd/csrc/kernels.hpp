@@ -114,6 +114,7 @@ struct Geom {
     int32_t nt;          // 1 = SpMV output stored non-temporally
     int32_t lds;         // 1 = LDS-staged SpMV for tiles of 32 or 64 systems
     int32_t dir16;       // paired layout: search directions p stored as BF16 (8 B per lane)
+    int32_t rows2;       // paired SpMV with BF16 directions: 2 = a wavefront takes two rows at once
     int32_t bpx;         // blocks per XCD asked for (B = min(bpx, chunks of a part))
     int32_t n_sched;     // 0: items cover tiles 0..n_tiles-1; else tiles sched[0..n_sched)
     int32_t sched[kMaxSched];

@@ -576,22 +576,24 @@ def test_sorted_batches_give_identical_signals(Sim, precision):
     assert np.array_equal(out[0], out[1])
 
 
-@pytest.mark.parametrize("pair,dir16", [(0, 0), (1, 0), (1, 1)])
-def test_paired_lanes_match_oracle(Sim, pair, dir16):
+@pytest.mark.parametrize("pair,dir16,rows", [(0, 0, 1), (1, 0, 1), (1, 1, 1), (1, 1, 2)])
+def test_paired_lanes_match_oracle(Sim, pair, dir16, rows):
     # Mixed precision on 67 systems: the FP32 inner solves in one ragged
     # 128-system tile with two systems per lane (pair = 1) or in 64-system
     # tiles (pair = 0), with FP32 or BF16 search directions in the paired
-    # tiles; all refine to the oracle.
+    # tiles, the BF16 SpMV taking one or two rows per wavefront at a time;
+    # all refine to the oracle.
     prob, b, q, ref = _wide_case()
     with Sim(0) as sim:
         sim.set_sequence(SHORT)
-        sim.set_options(rtol=1e-12, precision=1, persistent=0, pair_lanes=pair, dir_bf16=dir16)
+        sim.set_options(rtol=1e-12, precision=1, persistent=0, pair_lanes=pair, dir_bf16=dir16,
+                        spmv_rows=rows)
         pid = sim.add_problem(prob)
         sig, st = sim.dmri_run([pid] * len(b), b, q)
     assert st["status"] == "DMRI_OK"
     err = rel_err(sig, ref, ref[0])
-    _say("paired lanes %d, BF16 directions %d: max err %.2e, %d inner iterations"
-         % (pair, dir16, err.max(), st["total_iterations"]))
+    _say("paired lanes %d, BF16 directions %d, rows %d: max err %.2e, %d inner iterations"
+         % (pair, dir16, rows, err.max(), st["total_iterations"]))
     assert err.max() < 1e-9
 
 

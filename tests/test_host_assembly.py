@@ -266,6 +266,7 @@ def test_tuning_file_round_trip(tmp_path):
 def test_marker_and_weak_options():
     with Simulator(-1) as s:
         for k, good, bad in (("markers", (0, 1), (2, -1, 0.5)), ("dir_bf16", (0, 1), (2, 0.5)),
+                             ("spmv_rows", (1, 2), (0, 3, 1.5)),
                              ("weak_kappa", (0.5, 1e6), (0.0, 2e6))):
             for v in good:
                 s.dmri_set_option(k, v)
