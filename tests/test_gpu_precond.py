@@ -17,6 +17,8 @@ recorder and training, through the C ABI.
 * trained on recorded samples of some systems, the learned interval keeps
   the answer and its effect on the iterations is measured, on other systems
   of the same mesh and on a held-out geometry;
+* diffusion tensors on a conforming mesh and the autotuner's launch shapes
+  keep the answer;
 * unsupported combinations are refused.
 """
 
@@ -338,3 +340,25 @@ def test_learned_interval_on_held_out_geometry(env):
              n, l_first, l_last, err.max(), st0["total_iterations"], st["total_iterations"], fb))
     assert err.max() < 1e-9
     assert st["total_iterations"] < st0["total_iterations"]
+
+
+def test_tensor_mesh_and_autotuner(env):
+    # Flexible CG with a fixed interval on a conforming mesh with a diffusion
+    # tensor per compartment (the per-row mass coefficient inside the
+    # Chebyshev terms), and with the autotuner choosing the launch shape:
+    # both within 1e-9 of the oracle.
+    torch, Sim = env
+    prob = di.conforming_cylinder_box(
+        n=7, half=6.0, r=4.0, D_in=di.tensor([3e-3, 1e-3, 2e-3], (0.3, 0.5, 0.2)),
+        D_out=di.tensor([2e-3, 2.5e-3, 1.5e-3], (1.0, -0.4, 0.7)), kappa=5e-3)
+    rng = np.random.default_rng(2)
+    b = rng.uniform(0.0, 5000.0, 10)
+    q = di.fibonacci_directions(10)
+    ref = timestep.signals(prob, SHORT, b, q, solver="splu")
+    for opts in (dict(sys_tile=8), dict(autotune=1)):
+        sig, st, fb = _run(Sim, prob, b, q, rtol=1e-12, precond=2, cheb_terms=4, **opts)
+        err = rel_err(sig, ref, ref[0])
+        _say("tensor mesh %s: max err %.2e, iterations %d" % (opts, err.max(),
+                                                              st["total_iterations"]))
+        assert err.max() < 1e-9
+        assert fb == 0
