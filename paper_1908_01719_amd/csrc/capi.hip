@@ -967,38 +967,23 @@ int poll_active(dmri_ctx* h, const Geom& g, const SolverState& s) {
     return tot;
 }
 
-// Krylov iterations on the systems active in s until none is left.
-// Chunks of iterations are enqueued back to back; behind each chunk the
-// per-tile active counts are copied to pinned memory, and the host checks
-// chunk k's counts while chunk k+1 runs. Returns the iterations enqueued.
-template <typename T>
-int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const double4* gq,
-                Coef lhs, typename Vec2Of<T>::type* x, typename Vec2Of<T>::type* r,
-                typename Vec2Of<T>::type* p, typename Vec2Of<T>::type* q, SolverState s,
-                KernelTimer& timer, int first_chunk, int max_iter) {
+// Host driver of a chunked Krylov loop: enqueues `iterate(gk, k)` for
+// iterations k = done + 1, ... in chunks (the first of first_chunk, then 2),
+// each followed by a copy of the per-tile active counts to pinned memory;
+// the host reads chunk k's counts while chunk k + 1 runs, restricts later
+// chunks to the tiles still active (option tile_sched) and stops when none
+// is. Returns the iterations enqueued.
+template <typename Iterate>
+int chunked_loop(dmri_ctx* h, const Geom& g, const SolverState& s, int first_chunk,
+                 int max_iter, Iterate&& iterate) {
     hipStream_t st = lane(h).stream;
-    const Geom& g = bs.g;
-    if (bs.persist) {
-        timer.run(1, [&] {
-            launch_krylov_persistent<T>(st, bs.gp, Av, gq, lhs, bs.herm, x, r, p, q, s, bs.sc,
-                                        bs.bar);
-        });
-        return 0;
-    }
     int done = 0, slot = 0;
     bool pending = false;
     int chunk = std::max(1, first_chunk);
     Geom gk = g;  // geometry of the next chunk: every tile, or the tiles still active
     std::vector<int32_t> live;
     for (;;) {
-        for (int i = 0; i < chunk; ++i) {
-            const int32_t k_iter = done + i + 1;
-            timer.run(1, [&] { launch_spmv_dot<T>(st, gk, Av, gq, lhs, bs.herm, p, q, s, bs.sc); });
-            timer.run(2, [&] {
-                launch_update<T>(st, gk, Av, gq, lhs, bs.herm, x, r, p, q, s, bs.sc);
-            });
-            timer.run(3, [&] { launch_pupdate<T>(st, gk, Av, gq, lhs, r, p, x, k_iter, s); });
-        }
+        for (int i = 0; i < chunk; ++i) iterate(gk, done + i + 1);
         done += chunk;
         HIPCHK(hipMemcpyAsync(lane(h).ws.h_active[slot], s.n_active, sizeof(int32_t) * g.n_tiles,
                               hipMemcpyDeviceToHost, st));
@@ -1032,6 +1017,30 @@ int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const d
     return done;
 }
 
+// Krylov iterations on the systems active in s until none is left.
+// Chunks of iterations are enqueued back to back; behind each chunk the
+// per-tile active counts are copied to pinned memory, and the host checks
+// chunk k's counts while chunk k+1 runs. Returns the iterations enqueued.
+template <typename T>
+int krylov_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<T>& Av, const double4* gq,
+                Coef lhs, typename Vec2Of<T>::type* x, typename Vec2Of<T>::type* r,
+                typename Vec2Of<T>::type* p, typename Vec2Of<T>::type* q, SolverState s,
+                KernelTimer& timer, int first_chunk, int max_iter) {
+    hipStream_t st = lane(h).stream;
+    if (bs.persist) {
+        timer.run(1, [&] {
+            launch_krylov_persistent<T>(st, bs.gp, Av, gq, lhs, bs.herm, x, r, p, q, s, bs.sc,
+                                        bs.bar);
+        });
+        return 0;
+    }
+    return chunked_loop(h, bs.g, s, first_chunk, max_iter, [&](const Geom& gk, int32_t k_iter) {
+        timer.run(1, [&] { launch_spmv_dot<T>(st, gk, Av, gq, lhs, bs.herm, p, q, s, bs.sc); });
+        timer.run(2, [&] { launch_update<T>(st, gk, Av, gq, lhs, bs.herm, x, r, p, q, s, bs.sc); });
+        timer.run(3, [&] { launch_pupdate<T>(st, gk, Av, gq, lhs, r, p, x, k_iter, s); });
+    });
+}
+
 // Buffers of the polynomial preconditioner.
 struct PcBufs {
     double2* y[2];
@@ -1049,59 +1058,24 @@ int fcg_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<double>& Av, const
              Coef lhs, double2* x, double2* r, double2* p, double2* q, const PcBufs& pb,
              SolverState s, KernelTimer& timer, int max_iter) {
     hipStream_t st = lane(h).stream;
-    const Geom& g = bs.g;
     const int m = opts(h).cheb_terms;
     timer.run(7, [&] {
         // (no q yet: the start's q^H z is not used, r stands in for q)
-        const double2* z = launch_cheb(st, g, Av, gq, lhs, pb.ab, m, true, r, r, pb.y, pb.d, s,
+        const double2* z = launch_cheb(st, bs.g, Av, gq, lhs, pb.ab, m, true, r, r, pb.y, pb.d, s,
                                        bs.sc);
-        launch_pupdate_z(st, g, z, p, x, -1, s);
+        launch_pupdate_z(st, bs.g, z, p, x, -1, s);
     });
-    int done = 0, slot = 0;
-    bool pending = false;
-    Geom gk = g;
-    std::vector<int32_t> live;
-    for (;;) {
-        for (int i = 0; i < 2; ++i) {
-            const int32_t k_iter = done + i + 1;
-            timer.run(1, [&] { launch_spmv_dot<double>(st, gk, Av, gq, lhs, true, p, q, s, bs.sc); });
-            timer.run(2, [&] {
-                launch_update<double>(st, gk, Av, gq, lhs, true, x, r, p, q, s, bs.sc, true);
-            });
-            timer.run(7, [&] {
-                const double2* z = launch_cheb(st, gk, Av, gq, lhs, pb.ab, m, false, r, q, pb.y,
-                                               pb.d, s, bs.sc);
-                launch_pupdate_z(st, gk, z, p, x, k_iter, s);
-            });
-        }
-        done += 2;
-        HIPCHK(hipMemcpyAsync(lane(h).ws.h_active[slot], s.n_active, sizeof(int32_t) * g.n_tiles,
-                              hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(lane(h).ev[slot], st));
-        if (pending) {
-            HIPCHK(hipEventSynchronize(lane(h).ev[slot ^ 1]));
-            int tot = 0;
-            live.clear();
-            for (int t = 0; t < g.n_tiles; ++t) {
-                const int32_t a = lane(h).ws.h_active[slot ^ 1][t];
-                tot += a;
-                if (a > 0) live.push_back(t);
-            }
-            if (tot == 0) {
-                done -= 2;
-                break;
-            }
-            if (opts(h).tile_sched)
-                gk = sched_geom(g, live.data(), static_cast<int>(live.size()));
-        }
-        pending = true;
-        slot ^= 1;
-        if (done > max_iter + 4) {
-            HIPCHK(hipStreamSynchronize(st));
-            break;
-        }
-    }
-    return done;
+    return chunked_loop(h, bs.g, s, 2, max_iter, [&](const Geom& gk, int32_t k_iter) {
+        timer.run(1, [&] { launch_spmv_dot<double>(st, gk, Av, gq, lhs, true, p, q, s, bs.sc); });
+        timer.run(2, [&] {
+            launch_update<double>(st, gk, Av, gq, lhs, true, x, r, p, q, s, bs.sc, true);
+        });
+        timer.run(7, [&] {
+            const double2* z =
+                launch_cheb(st, gk, Av, gq, lhs, pb.ab, m, false, r, q, pb.y, pb.d, s, bs.sc);
+            launch_pupdate_z(st, gk, z, p, x, k_iter, s);
+        });
+    });
 }
 
 // Coefficients of step n: the left operator at t^n, the right one at
