@@ -282,6 +282,11 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *  "rtol"       per-step relative residual ||b - A x|| <= rtol ||b||
  *               (default 1e-10)
  *  "inner_rtol" FP32 inner solve reduction in mixed precision (1e-4)
+ *  "inner_floor" fraction f in (0, 1] of the outer target below which an
+ *               FP32 inner solve does not go: it stops once ||r|| <=
+ *               max(inner_rtol ||r64||, f rtol ||b||) (default 0.25). A
+ *               larger f saves inner iterations; the FP64 refinement still
+ *               ends every step at ||b - A x|| <= rtol ||b||
  *  "max_iter"   Krylov iterations per step and system (default 2000)
  *  "guess"      0 = previous step, 1 = polynomial extrapolation of the
  *               past solutions (default), 2 = learned correction of the

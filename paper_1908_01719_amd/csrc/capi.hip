@@ -169,6 +169,7 @@ struct Options {
     int krylov = 0;
     double rtol = 1e-10;
     double inner_rtol = 1e-4;
+    double inner_floor = 0.25;  // inner FP32 solves stop at inner_floor * rtol ||b|| at the latest
     int max_iter = 2000;
     int guess = 1;
     int extrap_order = 3;
@@ -1517,11 +1518,11 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                                   opts(h).rtol * opts(h).rtol);
     SolverState si = W.inner.view(static_cast<int32_t>(n_sys), opts(h).max_iter,
                                   opts(h).inner_rtol * opts(h).inner_rtol);
-    // An inner solve need not reduce its residual below a quarter of the
-    // outer target: ||r|| <= max(inner_rtol ||r64||, rtol ||b|| / 4).
+    // An inner solve need not reduce its residual below a fraction f of the
+    // outer target: ||r|| <= max(inner_rtol ||r64||, f rtol ||b||).
     si.floor_bb = W.outer.bb.p;
     {
-        const double k = 0.25 * opts(h).rtol / opts(h).inner_rtol;
+        const double k = opts(h).inner_floor * opts(h).rtol / opts(h).inner_rtol;
         si.floor_scale = k * k;
     }
     const MatView<double> A64 = view<double>(P, P.A64);
@@ -2144,6 +2145,9 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         } else if (k == "inner_rtol") {
             if (!(v > 0 && v < 1)) throw Error(DMRI_E_INVALID, "inner_rtol must be in (0, 1)");
             o.inner_rtol = v;
+        } else if (k == "inner_floor") {
+            if (!(v > 0 && v <= 1)) throw Error(DMRI_E_INVALID, "inner_floor must be in (0, 1]");
+            o.inner_floor = v;
         } else if (k == "max_iter") o.max_iter = as_int(1, 1000000);
         else if (k == "guess") o.guess = as_int(0, 2);
         else if (k == "extrap_order") o.extrap_order = as_int(1, kMaxHist - 1);
@@ -2203,6 +2207,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "krylov") *value = o.krylov;
         else if (k == "rtol") *value = o.rtol;
         else if (k == "inner_rtol") *value = o.inner_rtol;
+        else if (k == "inner_floor") *value = o.inner_floor;
         else if (k == "max_iter") *value = o.max_iter;
         else if (k == "guess") *value = o.guess;
         else if (k == "extrap_order") *value = o.extrap_order;

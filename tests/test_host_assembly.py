@@ -227,8 +227,11 @@ def test_sequence_and_option_validation():
                 s.dmri_set_sequence_pgse(*bad)
         s.dmri_set_option("rtol", 1e-8)
         assert s.dmri_get_option("rtol") == 1e-8
+        assert s.dmri_get_option("inner_floor") == 0.25
+        s.dmri_set_option("inner_floor", 1.0)
+        assert s.dmri_get_option("inner_floor") == 1.0
         for k, v in [("rtol", 0.0), ("precision", 5), ("sys_tile", 12), ("nope", 1),
-                     ("max_iter", 0)]:
+                     ("max_iter", 0), ("inner_floor", 0.0), ("inner_floor", 1.5)]:
             with pytest.raises(DmriError):
                 s.dmri_set_option(k, v)
         with pytest.raises(DmriError) as ei:
