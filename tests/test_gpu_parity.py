@@ -597,6 +597,29 @@ def test_paired_lanes_match_oracle(Sim, pair, dir16, rows):
     assert err.max() < 1e-9
 
 
+def test_inner_floor_matches_oracle(Sim):
+    # Mixed precision on the 67-system paired case at rtol 1e-8: an inner
+    # FP32 solve may stop at inner_floor * rtol ||b|| (here up to the outer
+    # target itself); the FP64 refinement still ends every step at rtol, so
+    # the signals stay within 1e-6 of the oracle with fewer inner iterations.
+    prob, b, q, ref = _wide_case()
+    out, iters = {}, {}
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(rtol=1e-8, precision=1, persistent=0)
+        pid = sim.add_problem(prob)
+        for f in (0.25, 1.0):
+            sim.set_options(inner_floor=f)
+            out[f], st = sim.dmri_run([pid] * len(b), b, q)
+            assert st["status"] == "DMRI_OK"
+            iters[f] = st["total_iterations"]
+    for f in (0.25, 1.0):
+        err = rel_err(out[f], ref, ref[0])
+        _say("inner_floor %.2f: max err %.2e, %d inner iterations" % (f, err.max(), iters[f]))
+        assert err.max() < 1e-6
+    assert iters[1.0] <= iters[0.25]
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_tile_schedule_matches_oracle(Sim, precision):
     # Two 8-system tiles sorted by b: the low-b tile leaves the Krylov loop
