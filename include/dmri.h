@@ -282,6 +282,16 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *  "rtol"       per-step relative residual ||b - A x|| <= rtol ||b||
  *               (default 1e-10)
  *  "inner_rtol" FP32 inner solve reduction in mixed precision (1e-4)
+ *  "mesh_merge" 1: a dmri_run over pairs of several problems solves them as
+ *               one batch: the problems' operators concatenated block-
+ *               diagonally, each problem's pairs (ordered by cost) padded
+ *               with b = 0 systems to whole tiles, so each tile holds one
+ *               mesh's systems; every kernel launch then covers the tiles of
+ *               all meshes, each over its own mesh's rows. Precision 0 or 1,
+ *               CG/COCG, guess 0/1, signal at echo (or option signal = 0);
+ *               one form for all problems, no tensors or weak faces; other
+ *               combinations end in DMRI_E_UNSUPPORTED. 0 (default): one
+ *               batch per problem (option concurrency). dmri_run only.
  *  "inner_floor" fraction f in (0, 1] of the outer target below which an
  *               FP32 inner solve does not go: it stops once ||r|| <=
  *               max(inner_rtol ||r64||, f rtol ||b||) (default 0.25). A

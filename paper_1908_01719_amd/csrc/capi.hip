@@ -200,6 +200,7 @@ struct Options {
     int markers = 0;          // 1: roctx ranges around runs, batches and time steps
     int dir_bf16 = 1;         // paired FP32 inner solves keep their directions in BF16
     int spmv_rows = 2;        // rows a wavefront of the paired BF16 SpMV takes at once (1, 2)
+    int mesh_merge = 0;       // runs over several meshes: 1 = one batch, each launch over all meshes
     // Krylov preconditioner of the FP64 Hermitian solves: 0 Jacobi (CG), 1
     // Chebyshev polynomial in D^-1 A on the interval the preconditioner
     // network predicts, 2 the same on the fixed interval [cheb_a, cheb_b];
@@ -280,6 +281,7 @@ struct Workspace {
     DevBuf<double2> pc_ab, pc_hist;
     DevBuf<float> pc_X, pc_Y;
     DevBuf<int32_t> gm_cycle, gm_dim;
+    DevBuf<int64_t> mtab;  // per tile {first row, end row, element base} of a several-mesh batch
     int32_t* h_active[2] = {nullptr, nullptr};  // pinned
     size_t h_active_n = 0;
     ~Workspace() {
@@ -318,9 +320,19 @@ struct GraphCache {
 
 // One execution lane: a stream with its own workspace, polling events,
 // timing-event pool and captured graph.
+// Row layout of a batch over several meshes (their rows concatenated): per
+// tile {first row, end row, element base} (also uploaded to Workspace::mtab),
+// the elements of one vector, and the largest mesh's row count.
+struct MeshLayout {
+    std::vector<int64_t> tab;
+    int64_t vlen = 0;
+    int64_t max_rows = 0;
+};
+
 struct Lane {
     hipStream_t stream = nullptr;
     Workspace ws;
+    const MeshLayout* layout = nullptr;  // set while a several-mesh batch runs
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> tpool;  // timing events, reused across runs
     // Captured time loops (one per kind of batch, e.g. per mesh of a
@@ -408,6 +420,9 @@ struct dmri_ctx {
     // Execution lanes: lane 0 serves the calling thread; runs over several
     // problems may use more lanes, one host thread each.
     std::vector<std::unique_ptr<dmri::Lane>> lanes;
+    // Problems formed by concatenating several problems' operators (block
+    // diagonal), keyed by the member ids: the operator of a several-mesh batch.
+    std::map<std::vector<int32_t>, std::unique_ptr<dmri::ProblemRec>> merged;
     // Device address of this device's copy of the file-scope scratch array
     // (the buffers of dmri_run_device_noalloc), looked up at creation.
     void* scratch_dev = nullptr;
@@ -797,6 +812,25 @@ void check_guess_setup(dmri_ctx* h, bool fp64_vectors) {
                     "(precision 0 or 1)");
 }
 
+// u^0 = u0 per DOF for every system (0 for padding systems): over the whole
+// vector for one mesh, tile by tile (each over its own mesh's rows) for a
+// several-mesh batch.
+template <typename T>
+void fill_initial(dmri_ctx* h, const Geom& g, const ProblemRec& P, int32_t n_sys,
+                  typename Vec2Of<T>::type* x) {
+    hipStream_t st = lane(h).stream;
+    const MeshLayout* ml = lane(h).layout;
+    if (!ml || !g.mtab) {
+        launch_set_initial<T>(st, g, P.u0.p, n_sys, x);
+        return;
+    }
+    for (int32_t t = 0; t < g.n_tiles; ++t) {
+        const int64_t lo = ml->tab[3 * t], hi = ml->tab[3 * t + 1], base = ml->tab[3 * t + 2];
+        const int32_t live = std::max(0, std::min(g.S, n_sys - t * g.S));
+        launch_set_initial_block<T>(st, hi - lo, g.S, live, P.u0.p + lo, x + (base + lo * g.S));
+    }
+}
+
 struct BatchResult {
     std::vector<double> sig;       // [n_sys][2]
     std::vector<int32_t> iters, flags;
@@ -872,6 +906,28 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                      opts(h).blocks_per_xcd, opts(h).queue, opts(h).grab, opts(h).xcd_split != 0);
     bs.g.nt = opts(h).nt;
     bs.g.lds = opts(h).lds;
+    if (const MeshLayout* ml = lane(h).layout) {
+        // Several meshes: every tile is split into 8 parts of its own mesh's
+        // rows (parts sized for the largest mesh; the rest run short or
+        // empty), vectors hold only each tile's rows, and the kernels' paths
+        // that assume one row range per launch stay off.
+        Geom& gm = bs.g;
+        if (static_cast<int64_t>(gm.n_tiles) * 3 != static_cast<int64_t>(ml->tab.size()))
+            throw Error(DMRI_E_STATE, "several-mesh layout does not match the batch");
+        if (gm.lds || opts(h).persistent == 1 || want_pair)
+            throw Error(DMRI_E_UNSUPPORTED, "several-mesh batches: no LDS SpMV, persistent "
+                                            "solver or paired tiles");
+        gm.mtab = lane(h).ws.mtab.p;
+        gm.vlen = ml->vlen;
+        gm.tile_bytes_ok = 0;
+        gm.n_parts = 8;
+        gm.n_items = gm.n_tiles * gm.n_parts;
+        int64_t pr = (ml->max_rows + gm.n_parts - 1) / gm.n_parts;
+        pr = (pr + gm.chunk_rows - 1) / gm.chunk_rows * gm.chunk_rows;
+        gm.part_rows = static_cast<int32_t>(std::max<int64_t>(pr, gm.chunk_rows));
+        const int32_t chunks = (gm.part_rows + gm.chunk_rows - 1) / gm.chunk_rows;
+        gm.B = std::max(1, std::min(gm.bpx, chunks));
+    }
     const Geom& g = bs.g;
     const size_t ld = static_cast<size_t>(g.ld);
     int n_cu = 0;
@@ -886,7 +942,8 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     if (opts(h).krylov == 3 && opts(h).precision != 0)
         throw Error(DMRI_E_UNSUPPORTED, "GMRES (krylov = 3) runs in precision 0 (FP64)");
     bs.persist = (opts(h).persistent == 1 || (opts(h).persistent == 2 && small)) && g.ld <= 64 &&
-                 opts(h).krylov != 3 && opts(h).precond == 0 && h->pcmodel.rec_cap == 0;
+                 opts(h).krylov != 3 && opts(h).precond == 0 && h->pcmodel.rec_cap == 0 &&
+                 !g.mtab;
     // The grid barrier needs every block resident: otherwise chunked launches.
     if (bs.persist) {
         const bool fits = opts(h).precision != 0 ? persistent_fits<float>(bs.gp, bs.herm, n_cu)
@@ -1270,7 +1327,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     Workspace& W = lane(h).ws;
     const BatchSetup bs = setup_batch(h, P, n_sys, d_b, d_q);
     const Geom& g = bs.g;
-    const size_t nv = static_cast<size_t>(g.n_rows) * g.ld, ld = static_cast<size_t>(g.ld);
+    const size_t nv = static_cast<size_t>(vec_elems(g)), ld = static_cast<size_t>(g.ld);
     DevBuf<T>* vecs;
     if constexpr (sizeof(T) == 8) vecs = W.vec64; else vecs = W.vec32;
     History<V2> hs;
@@ -1294,7 +1351,7 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
         wb = reinterpret_cast<V2*>(W.wb.p);
     }
     const double wc = (1.0 - h->theta) * opts(h).weak_kappa;
-    launch_set_initial<T>(st, g, P.u0.p, s.n_sys, hs.u(0));
+    fill_initial<T>(h, g, P, s.n_sys, hs.u(0));
     std::vector<double> F, f;
     step_tables(h, F, f);
     const bool tr = P.op.form == FORM_TRANSFORMED;
@@ -1492,9 +1549,9 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     bsi.g = bs.gi;
     Geom gr = g;  // refinement residual: dx in the inner layout
     gr.dx_pair = bs.pair ? 1 : 0;
-    const size_t nv = static_cast<size_t>(g.n_rows) * g.ld, ld = static_cast<size_t>(g.ld);
+    const size_t nv = static_cast<size_t>(vec_elems(g)), ld = static_cast<size_t>(g.ld);
     const size_t ldi = std::max(ld, static_cast<size_t>(bs.gi.ld));
-    const size_t nvi = static_cast<size_t>(g.n_rows) * ldi;
+    const size_t nvi = bs.pair ? static_cast<size_t>(g.n_rows) * ldi : nv;
     History<double2> hs;
     hs.nh = history_len(h);
     // FP64 level: history ring, x_alt, r64, b64 (no FP64 direction vector:
@@ -1534,7 +1591,7 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
         wb = reinterpret_cast<double2*>(W.wb.p);
     }
     const double wc = (1.0 - h->theta) * opts(h).weak_kappa;
-    launch_set_initial<double>(st, g, P.u0.p, so.n_sys, hs.u(0));
+    fill_initial<double>(h, g, P, so.n_sys, hs.u(0));
     std::vector<double> F, f;
     step_tables(h, F, f);
     const bool tr = P.op.form == FORM_TRANSFORMED;
@@ -2184,6 +2241,7 @@ dmri_status dmri_set_option(dmri_handle h, const char* key, double v) {
         } else if (k == "markers") o.markers = as_int(0, 1);
         else if (k == "dir_bf16") o.dir_bf16 = as_int(0, 1);
         else if (k == "spmv_rows") o.spmv_rows = as_int(1, 2);
+        else if (k == "mesh_merge") o.mesh_merge = as_int(0, 1);
         else if (k == "precond") o.precond = as_int(0, 2);
         else if (k == "cheb_terms") o.cheb_terms = as_int(1, 16);
         else if (k == "cheb_a" || k == "cheb_b") {
@@ -2238,6 +2296,7 @@ dmri_status dmri_get_option(dmri_handle h, const char* key, double* value) {
         else if (k == "markers") *value = o.markers;
         else if (k == "dir_bf16") *value = o.dir_bf16;
         else if (k == "spmv_rows") *value = o.spmv_rows;
+        else if (k == "mesh_merge") *value = o.mesh_merge;
         else if (k == "precond") *value = o.precond;
         else if (k == "cheb_terms") *value = o.cheb_terms;
         else if (k == "cheb_a") *value = o.cheb_a;
@@ -2563,6 +2622,164 @@ void check_pairs(dmri_ctx* h, int64_t n_pairs, const int32_t* problem_id, const 
     }
 }
 
+// The block-diagonal concatenation of the listed problems (rows and
+// columns of problem k shifted by the DOFs of problems 0..k-1), built once
+// per list and kept in the handle: the operator of a several-mesh batch.
+// Its members must share the form; diffusion tensors and weak faces are not
+// supported here.
+ProblemRec& merged_problem(dmri_ctx* h, const std::vector<int32_t>& pids) {
+    auto it = h->merged.find(pids);
+    if (it != h->merged.end()) return *it->second;
+    auto M = std::make_unique<ProblemRec>();
+    HostOperator& op = M->op;
+    const HostOperator& first = get_problem(h, pids.front()).op;
+    op.form = first.form;
+    uint64_t fp = 0xCBF29CE484222325ULL;
+    int64_t rows = 0, nnz = 0;
+    for (int32_t pid : pids) {
+        const ProblemRec& P = get_problem(h, pid);
+        const HostOperator& m = P.op;
+        if (m.form != op.form)
+            throw Error(DMRI_E_UNSUPPORTED, "several-mesh batches need one form (all periodic "
+                                            "boxes, or all walls)");
+        if (m.aniso || !m.wk_rows.empty())
+            throw Error(DMRI_E_UNSUPPORTED, "several-mesh batches: no diffusion tensors or weak "
+                                            "pseudo-periodic faces");
+        const int64_t mnz = static_cast<int64_t>(m.col.size());
+        if (rows + m.n_dof > (int64_t(1) << 31) - 1 || nnz + mnz > (int64_t(1) << 31) - 1)
+            throw Error(DMRI_E_UNSUPPORTED, "several-mesh batch too large for 32-bit indices");
+        for (int64_t i = 0; i < m.n_dof; ++i) {
+            op.row_ptr.push_back(static_cast<int32_t>(m.row_ptr[i] + nnz));
+            op.diag_pos.push_back(static_cast<int32_t>(m.diag_pos[i] + nnz));
+        }
+        for (int32_t c : m.col) op.col.push_back(static_cast<int32_t>(c + rows));
+        op.M.insert(op.M.end(), m.M.begin(), m.M.end());
+        op.R.insert(op.R.end(), m.R.begin(), m.R.end());
+        op.MT.insert(op.MT.end(), m.MT.begin(), m.MT.end());
+        for (int a = 0; a < 3; ++a) op.V[a].insert(op.V[a].end(), m.V[a].begin(), m.V[a].end());
+        op.w.insert(op.w.end(), m.w.begin(), m.w.end());
+        op.u0.insert(op.u0.end(), m.u0.begin(), m.u0.end());
+        fp = fnv1a(fp, &P.fingerprint, sizeof P.fingerprint);
+        rows += m.n_dof;
+        nnz += mnz;
+    }
+    op.row_ptr.push_back(static_cast<int32_t>(nnz));
+    op.n_dof = rows;
+    op.nnz = nnz;
+    M->fingerprint = fp;
+    ProblemRec& ref = *M;
+    h->merged.emplace(pids, std::move(M));
+    return ref;
+}
+
+// Several problems as one batch (option mesh_merge): the problems' operators
+// concatenated block-diagonally, each problem's pairs ordered by cost and
+// padded with b = 0 systems to whole tiles, so every tile belongs to one
+// mesh. Each kernel launch then covers the tiles of all meshes, every tile
+// over its own mesh's rows only (vectors hold just those rows). FP64 and
+// mixed precision with CG/COCG and the polynomial-extrapolation guesses.
+bool run_merged(dmri_ctx* h, const std::vector<std::pair<int32_t, std::vector<int64_t>>>& groups,
+                int64_t n_pairs, const double* b, const double* q, double* signal_out,
+                dmri_stats* stats) {
+    const Options& o = opts(h);
+    if (o.precision == 2 || o.krylov == 3 || o.precond != 0 || o.guess == 2 || o.graph ||
+        o.lds || h->model.rec_cap > 0 || h->pcmodel.rec_cap > 0)
+        throw Error(DMRI_E_UNSUPPORTED,
+                    "several-mesh batches run precision 0 or 1 with CG/COCG, guess 0/1, no "
+                    "graph, LDS SpMV, preconditioner or sample recording");
+    std::vector<int32_t> pids;
+    size_t max_ns = 0;
+    for (const auto& gr : groups) {
+        pids.push_back(gr.first);
+        max_ns = std::max(max_ns, gr.second.size());
+    }
+    const int S = o.sys_tile ? o.sys_tile : auto_tile(static_cast<int64_t>(max_ns));
+    hipStream_t st = lane(h).stream;
+    const double ts = now_s();
+    ProblemRec& M = merged_problem(h, pids);
+    ensure_uploaded(h, M, o.precision != 0);
+    if (M.op.form == FORM_TRANSFORMED && o.signal == 1) {
+        const int N = o.n_steps > 0 ? std::min(o.n_steps, h->n_steps) : h->n_steps;
+        if (h->seq.F[N] != 0.0)
+            throw Error(DMRI_E_UNSUPPORTED, "several-mesh batches return sum w u (F(t) != 0 at "
+                                            "the last step needs option signal = 0)");
+    }
+    // Slots: per problem its pairs (cost order) then b = 0 padding to whole tiles.
+    MeshLayout ml;
+    std::vector<int64_t> owner;
+    std::vector<double> hb, hq;
+    std::vector<std::vector<int64_t>> order(groups.size());
+    int64_t row0 = 0, elems = 0;
+    for (size_t k = 0; k < groups.size(); ++k) {
+        const int32_t pid = groups[k].first;
+        std::vector<int64_t> idx = groups[k].second;
+        if (o.sort_systems) order_systems(h, pid, b, q, idx);
+        const int64_t rows = get_problem(h, pid).op.n_dof;
+        const int64_t nt = (static_cast<int64_t>(idx.size()) + S - 1) / S;
+        for (int64_t t = 0; t < nt; ++t) {
+            ml.tab.push_back(row0);
+            ml.tab.push_back(row0 + rows);
+            ml.tab.push_back(elems - row0 * S);
+            elems += rows * S;
+        }
+        for (int64_t i = 0; i < nt * S; ++i) {
+            const bool real = i < static_cast<int64_t>(idx.size());
+            owner.push_back(real ? idx[i] : -1);
+            hb.push_back(real ? b[idx[i]] : 0.0);
+            for (int a = 0; a < 3; ++a) hq.push_back(real ? q[3 * idx[i] + a] : (a == 0 ? 1.0 : 0.0));
+        }
+        ml.max_rows = std::max(ml.max_rows, rows);
+        row0 += rows;
+        order[k] = std::move(idx);
+    }
+    ml.vlen = elems;
+    const int64_t ns = static_cast<int64_t>(owner.size());
+    if (ns / S > 4096) throw Error(DMRI_E_UNSUPPORTED, "several-mesh batch: over 4096 tiles");
+    Workspace& W = lane(h).ws;
+    W.mtab.upload(ml.tab.data(), ml.tab.size(), st);
+    W.b_in.upload(hb.data(), ns, st);
+    W.q_in.upload(hq.data(), 3 * ns, st);
+    W.sig.alloc(ns);
+    HIPCHK(hipStreamSynchronize(st));  // host staging vectors go out of scope
+    const double t_up = now_s() - ts;
+    BatchResult R;
+    {
+        OptionGuard guard(h);
+        opts(h).sys_tile = S;
+        opts(h).persistent = 0;
+        opts(h).pair_lanes = 0;
+        struct LayoutScope {
+            Lane& l;
+            LayoutScope(Lane& ln, const MeshLayout* m) : l(ln) { l.layout = m; }
+            ~LayoutScope() { l.layout = nullptr; }
+        } scope(lane(h), &ml);
+        const Marker mk(h, "batch", ns);
+        run_batch_with(h, M, ns, W.b_in.p, W.q_in.p, W.sig.p, R);
+    }
+    std::vector<double> sig(2 * ns);
+    HIPCHK(hipMemcpyAsync(sig.data(), W.sig.p, sizeof(double2) * ns, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool any_nc = false;
+    for (int64_t i = 0; i < ns; ++i) {
+        if (owner[i] < 0) continue;
+        signal_out[2 * owner[i]] = sig[2 * i];
+        signal_out[2 * owner[i] + 1] = sig[2 * i + 1];
+        if (R.flags[i]) any_nc = true;
+    }
+    if (stats) stats->t_setup_s += t_up;
+    fill_stats(stats, owner, R, n_pairs);
+    // Costs per problem, in the order its pairs took in the slots.
+    int64_t slot = 0;
+    for (size_t k = 0; k < groups.size(); ++k) {
+        const std::vector<int64_t>& idx = order[k];
+        std::vector<int32_t> it(idx.size());
+        for (size_t i = 0; i < idx.size(); ++i) it[i] = R.iters[slot + static_cast<int64_t>(i)];
+        remember_costs(h, groups[k].first, b, q, idx, it);
+        slot += (static_cast<int64_t>(idx.size()) + S - 1) / S * S;
+    }
+    return any_nc;
+}
+
 // Runs host pairs grouped by problem: one batch per problem, in sequence or
 // (option "concurrency") on several lanes at once. Signals go to host memory
 // in input order. Returns true when some system did not converge.
@@ -2576,6 +2793,8 @@ bool run_host_pairs(dmri_ctx* h, int64_t n_pairs, const int32_t* problem_id, con
             if (problem_id[i] == pid) idx.push_back(i);
         if (!idx.empty()) groups.emplace_back(pid, std::move(idx));
     }
+    if (opts(h).mesh_merge && groups.size() > 1)
+        return run_merged(h, groups, n_pairs, b, q, signal_out, stats);
     std::atomic<bool> any_nc{false};
     std::mutex mu;
     auto run_group = [&](int32_t pid, std::vector<int64_t> idx) {

@@ -149,7 +149,23 @@ __device__ __forceinline__ void diag_at(const T* __restrict__ dK0, const V4<T>* 
 // one tile are contiguous (S complex values per row) and spread evenly over
 // the L2 channels. Element (row, sys) of the tile is at vbase + row * S.
 __device__ __forceinline__ size_t vbase(const Geom& g, int tile, int S, int sys) {
+    // Several meshes: tile t holds only its mesh's rows, from element
+    // mtab[3t + 2] + lo * S on (the base may be below zero; the sum is not).
+    if (g.mtab)
+        return static_cast<size_t>(g.mtab[3 * tile + 2]) + static_cast<size_t>(sys - tile * S);
     return static_cast<size_t>(tile) * g.n_rows * S + (sys - tile * S);
+}
+
+// Rows [r0, r1) of row part `part` of a tile: a slice of the tile's mesh
+// (all rows when the batch has one mesh).
+__device__ __forceinline__ void part_range(const Geom& g, int tile, int part, int& r0, int& r1) {
+    int lo = 0, hi = g.n_rows;
+    if (g.mtab) {
+        lo = static_cast<int>(g.mtab[3 * tile]);
+        hi = static_cast<int>(g.mtab[3 * tile + 1]);
+    }
+    r0 = lo + part * g.part_rows;
+    r1 = min(hi, r0 + g.part_rows);
 }
 
 // Work item kk of a launch: its tile (through the schedule list when the
@@ -178,10 +194,10 @@ __device__ __forceinline__ int wave_id_uniform() {
 // Static sweep of a streaming kernel: block j takes chunks j, j+B, ...;
 // body(first_slot_row, r1) handles the kUs row slots first + u*kWaves*R.
 template <int S, typename Body>
-__device__ __forceinline__ void sweep_static(const Geom& g, int part, int j, Body body) {
+__device__ __forceinline__ void sweep_static(const Geom& g, int tile, int part, int j, Body body) {
     constexpr int R = 64 / S;
-    const int r0 = part * g.part_rows;
-    const int r1 = min(g.n_rows, r0 + g.part_rows);
+    int r0, r1;
+    part_range(g, tile, part, r0, r1);
     const int off = wave_id_uniform() * R + (threadIdx.x & 63) / S;
     const int step = g.B * g.chunk_rows;
     for (int c0 = r0 + j * g.chunk_rows; c0 < r1; c0 += step) body(c0 + off, r1);
@@ -207,11 +223,11 @@ __device__ __forceinline__ int grab(int32_t* ctr) {
 // wavefront takes grab*kUg*R consecutive rows at a time from the item's
 // queue (one atomic per grab). Static mode: block j takes chunks j, j+B, ...
 template <int S, typename Body>
-__device__ __forceinline__ void sweep_gather(const Geom& g, int part, int j, int32_t* ctr,
+__device__ __forceinline__ void sweep_gather(const Geom& g, int tile, int part, int j, int32_t* ctr,
                                              Body body) {
     constexpr int R = 64 / S;
-    const int r0 = part * g.part_rows;
-    const int r1 = min(g.n_rows, r0 + g.part_rows);
+    int r0, r1;
+    part_range(g, tile, part, r0, r1);
     if (r1 <= r0) return;
     const int rs = (threadIdx.x & 63) / S;
     if (g.queue) {
@@ -276,14 +292,14 @@ __device__ __forceinline__ void reduce_store(const Geom& g, Scratch sc, int item
 
 // One item of q = A p with sigma partial sums (p^H q or p^T q) per lane.
 template <typename T, int S, bool HERM>
-__device__ __forceinline__ void spmv_item(const Geom& g, int part, int j, int32_t* ctr, bool act,
+__device__ __forceinline__ void spmv_item(const Geom& g, int tile, int part, int j, int32_t* ctr, bool act,
                                           size_t tb, const LaneCoef<T>& lc,
                                           const int32_t* __restrict__ row_ptr,
                                           const int32_t* __restrict__ col,
                                           const T* __restrict__ K0, const V4<T>* __restrict__ aux,
                                           const V2<T>* __restrict__ p, V2<T>* __restrict__ q,
                                           double (&acc)[2]) {
-    sweep_gather<S>(g, part, j, ctr, [&](int row) {
+    sweep_gather<S>(g, tile, part, j, ctr, [&](int row) {
         if (!act) return;
         const int kb = row_ptr[row], ke = row_ptr[row + 1];
         const T cm = lc.cr(row);
@@ -514,15 +530,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(
         const LaneCoef<T> lc(gq[sys], lhs, g, sys);
         double acc[2] = {0.0, 0.0};
         if constexpr (S == 64) {
-            if (!g.queue && g.tile_bytes_ok) {
+            if (!g.queue && g.tile_bytes_ok && !g.mtab) {
                 if (act)
                     spmv_item64<T, HERM>(g, part, j, tile, lc, row_ptr, col, K0, aux, p, q, acc);
             } else {
-                spmv_item<T, S, HERM>(g, part, j, sc.ctr_spmv + item, act, tb, lc, row_ptr, col,
+                spmv_item<T, S, HERM>(g, tile, part, j, sc.ctr_spmv + item, act, tb, lc, row_ptr, col,
                                       K0, aux, p, q, acc);
             }
         } else {
-            spmv_item<T, S, HERM>(g, part, j, sc.ctr_spmv + item, act, tb, lc, row_ptr, col, K0,
+            spmv_item<T, S, HERM>(g, tile, part, j, sc.ctr_spmv + item, act, tb, lc, row_ptr, col, K0,
                                   aux, p, q, acc);
         }
         reduce_store<S, 2>(g, sc, item, j, acc, lds);
@@ -663,13 +679,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lds(
 // One item of x += alpha p (WITH_X), r -= alpha q, z = D^-1 r with partial
 // sums rho' = r^H z (or r^T z) and ||r||^2.
 template <typename T, int S, bool HERM, bool WITH_X = true>
-__device__ __forceinline__ void update_item(const Geom& g, int part, int j, size_t tb,
+__device__ __forceinline__ void update_item(const Geom& g, int tile, int part, int j, size_t tb,
                                             const LaneCoef<T>& lc, T ar, T ai,
                                             const T* __restrict__ dK0,
                                             const V4<T>* __restrict__ daux, V2<T>* __restrict__ x,
                                             V2<T>* __restrict__ r, const V2<T>* __restrict__ p,
                                             const V2<T>* __restrict__ q, double (&acc)[3]) {
-    sweep_static<S>(g, part, j, [&](int first, int r1) {
+    sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
         int row[kUs];
         bool ok[kUs];
         V2<T> pv[kUs], qv[kUs], xv[kUs], rv[kUs];
@@ -725,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
         const double2 al = act ? s.alpha[sys] : make_double2(0.0, 0.0);
         double acc[3] = {0.0, 0.0, 0.0};
         if (act)
-            update_item<T, S, HERM, false>(g, part, j, tb, lc, static_cast<T>(al.x),
+            update_item<T, S, HERM, false>(g, tile, part, j, tb, lc, static_cast<T>(al.x),
                                            static_cast<T>(al.y), dK0, daux, x, r, p, q, acc);
         reduce_store<S, 3>(g, sc, item, j, acc, lds);
     }
@@ -733,14 +749,14 @@ __global__ __launch_bounds__(kBlock) void k_update(
 
 // One item of x += alpha p (do_x) and p = D^-1 r + beta p (do_p), per lane.
 template <typename T, int S>
-__device__ __forceinline__ void pupdate_item(const Geom& g, int part, int j, size_t tb,
+__device__ __forceinline__ void pupdate_item(const Geom& g, int tile, int part, int j, size_t tb,
                                              const LaneCoef<T>& lc, T br, T bi, bool do_p,
                                              T ar, T ai, bool do_x,
                                              const T* __restrict__ dK0,
                                              const V4<T>* __restrict__ daux,
                                              const V2<T>* __restrict__ r, V2<T>* __restrict__ p,
                                              V2<T>* __restrict__ x) {
-    sweep_static<S>(g, part, j, [&](int first, int r1) {
+    sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
         int row[kUs];
         bool ok[kUs];
         V2<T> rv[kUs], pv[kUs], xv[kUs];
@@ -793,7 +809,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(Geom g, const T* __restrict_
         const LaneCoef<T> lc(gq[sys], lhs, g, sys);
         const double2 be = do_p ? s.beta[sys] : make_double2(0.0, 0.0);
         const double2 al = s.alpha[sys];
-        pupdate_item<T, S>(g, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y), do_p,
+        pupdate_item<T, S>(g, tile, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y), do_p,
                            static_cast<T>(al.x), static_cast<T>(al.y), do_x, dK0, daux, r, p, x);
     }
 }
@@ -850,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb(
         double c1 = 0.0, c2 = 0.0;
         if (act) cheb_coef(ab[sys], term, c1, c2);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        sweep_gather<S>(g, part, j, nullptr, [&](int row) {
+        sweep_gather<S>(g, tile, part, j, nullptr, [&](int row) {
             if (!act) return;
             double yr = 0.0, yi = 0.0;
             if (!FIRST) {  // (A y)_row
@@ -917,7 +933,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_z(Geom g, const double2* __r
         if (!(do_p || do_x)) continue;
         const double2 be = do_p ? s.beta[sys] : make_double2(0.0, 0.0);
         const double2 al = do_x ? s.alpha[sys] : make_double2(0.0, 0.0);
-        sweep_static<S>(g, part, j, [&](int first, int r1) {
+        sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
 #pragma unroll
             for (int u = 0; u < kUs; ++u) {
                 bool ok;
@@ -1679,7 +1695,7 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
             if (!__syncthreads_or(act)) continue;
             const LaneCoef<T> lc(gq[sys], lhs, g, sys);
             double acc[2] = {0.0, 0.0};
-            spmv_item<T, S, HERM>(g, part, j, nullptr, act, tb, lc, row_ptr, col, K0, aux, p, q,
+            spmv_item<T, S, HERM>(g, tile, part, j, nullptr, act, tb, lc, row_ptr, col, K0, aux, p, q,
                                   acc);
             reduce_store<S, 2>(g, scA, item, j, acc, lds);
         }
@@ -1703,7 +1719,7 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
             const double2 al = sh_alpha[sys];
             double acc[3] = {0.0, 0.0, 0.0};
             if (act)
-                update_item<T, S, HERM>(g, part, j, tb, lc, static_cast<T>(al.x),
+                update_item<T, S, HERM>(g, tile, part, j, tb, lc, static_cast<T>(al.x),
                                         static_cast<T>(al.y), dK0, daux, x, r, p, q, acc);
             reduce_store<S, 3>(g, scB, item, j, acc, lds);
         }
@@ -1749,7 +1765,7 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
             if (!sh_act[sys]) continue;
             const LaneCoef<T> lc(gq[sys], lhs, g, sys);
             const double2 be = sh_beta[sys];
-            pupdate_item<T, S>(g, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y),
+            pupdate_item<T, S>(g, tile, part, j, tb, lc, static_cast<T>(be.x), static_cast<T>(be.y),
                                true, T(0), T(0), false, dK0, daux, r, p, x);
         }
         if (!grid_sync(bar)) break;
@@ -1800,7 +1816,7 @@ __global__ __launch_bounds__(kBlock) void k_init(
         const size_t sx = g.dx_pair ? kPairS : S;
         // 64-system tiles with static chunks: every row is wavefront-uniform,
         // so the gathers go through buffer resources with uniform row offsets.
-        const bool fast = S == 64 && !g.queue && g.tile_bytes_ok;
+        const bool fast = S == 64 && !g.queue && g.tile_bytes_ok && !g.mtab;
         TileRows tu{}, tu2{}, tx{}, tdx{};
         if constexpr (S == 64) {
             if (fast) {
@@ -1821,7 +1837,7 @@ __global__ __launch_bounds__(kBlock) void k_init(
             }
         }
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        sweep_gather<S>(g, part, j, sc.ctr_init + item, [&](int row) {
+        sweep_gather<S>(g, tile, part, j, sc.ctr_init + item, [&](int row) {
             if (!act) return;
             const int kb = row_ptr[row], ke = row_ptr[row + 1];
             const T cml = ll.cr(row), cmr = lr.cr(row);
@@ -1950,7 +1966,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_start(
         const bool act = sys < s.n_sys && outer_active[sys];
         const LaneCoef<float> lc(gq[sys], lhs, g, sys);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        sweep_static<S>(g, part, j, [&](int first, int r1) {
+        sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
             int row[kUs];
             bool ok[kUs];
             double2 rv64[kUs];
@@ -1995,7 +2011,7 @@ __global__ __launch_bounds__(kBlock) void k_signal(Geom g, const double* __restr
         const size_t tb = vbase(g, tile, S, sys);
         double acc[2] = {0.0, 0.0};
         if (sys < n_sys) {
-            sweep_static<S>(g, part, j, [&](int first, int r1) {
+            sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
 #pragma unroll
                 for (int u = 0; u < kUs; ++u) {
                     bool ok;
@@ -2041,7 +2057,7 @@ __global__ __launch_bounds__(kBlock) void k_signal_phase(Geom gt, int32_t n_rows
             const double4 gg = gq[sys];
             const double kf = gg.x * F;
             const double kx = kf * gg.y, ky = kf * gg.z, kz = kf * gg.w;
-            sweep_static<S>(gt, part, j, [&](int first, int r1) {
+            sweep_static<S>(gt, tile, part, j, [&](int first, int r1) {
                 for (int u = 0; u < kUs; ++u) {
                     bool ok;
                     const int e = slot_row<S>(first, u, r1, ok);
@@ -2298,7 +2314,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, MatView<T> A, int whic
         const T c = static_cast<T>(cc[sys]);
         const double3 d3 = dd[sys];
         const T d0 = static_cast<T>(d3.x), d1 = static_cast<T>(d3.y), d2 = static_cast<T>(d3.z);
-        sweep_static<S>(g, part, j, [&](int first, int r1) {
+        sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
             for (int u = 0; u < kUs; ++u) {
                 bool ok;
                 const int row = slot_row<S>(first, u, r1, ok);
@@ -2467,7 +2483,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_scale(Geom g, const double* __res
         if (!act) continue;
         const LaneCoef<double> lc(gq[sys], lhs, g, sys);
         const double inv = 1.0 / gm.hnorm[sys];
-        sweep_static<S>(g, part, j, [&](int first, int r1) {
+        sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
 #pragma unroll
             for (int u = 0; u < kUs; ++u) {
                 bool ok;
@@ -2506,7 +2522,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_dots(Geom g, const double2* __res
 #pragma unroll
         for (int c = 0; c < 2 * kGmBatch; ++c) a[c] = 0.0;
         if (act) {
-            sweep_static<S>(g, part, j, [&](int first, int r1) {
+            sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
                 for (int u = 0; u < kUs; ++u) {
                     bool ok;
                     const int row = slot_row<S>(first, u, r1, ok);
@@ -2590,7 +2606,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_orth(Geom g, double2* __restrict_
         double a = 0.0;
         if (act) {
             const double* hs = gm.hout + static_cast<size_t>(sys) * kGmVals;
-            sweep_static<S>(g, part, j, [&](int first, int r1) {
+            sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
                 for (int u = 0; u < kUs; ++u) {
                     bool ok;
                     const int row = slot_row<S>(first, u, r1, ok);
@@ -2758,7 +2774,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_update(Geom g, const double* __re
         if (k <= 0) continue;
         const LaneCoef<double> lc(gq[sys], lhs, g, sys);
         const double2* y = gm.y + static_cast<size_t>(sys) * kGmMax;
-        sweep_static<S>(g, part, j, [&](int first, int r1) {
+        sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
             for (int u = 0; u < kUs; ++u) {
                 bool ok;
                 const int row = slot_row<S>(first, u, r1, ok);
@@ -2798,7 +2814,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_resid(Geom g, const double2* __re
         if (!__syncthreads_or(act)) continue;
         double a = 0.0;
         if (act) {
-            sweep_static<S>(g, part, j, [&](int first, int r1) {
+            sweep_static<S>(g, tile, part, j, [&](int first, int r1) {
 #pragma unroll
                 for (int u = 0; u < kUs; ++u) {
                     bool ok;
@@ -2915,7 +2931,7 @@ Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
 }
 
 Geom sched_geom(const Geom& g, const int32_t* tiles, int n) {
-    if (n <= 0 || n >= g.n_tiles || n > kMaxSched || g.queue) return g;
+    if (n <= 0 || n >= g.n_tiles || n > kMaxSched || g.queue || g.mtab) return g;
     Geom s = g;
     s.n_sched = n;
     for (int i = 0; i < n; ++i) {
@@ -3253,10 +3269,22 @@ void launch_apply(hipStream_t st, const Geom& g, const MatView<T>& A, int which,
 template <typename T>
 void launch_set_initial(hipStream_t st, const Geom& g, const double* u0, int32_t n_sys,
                         V2<T>* x) {
+    if (g.mtab) throw std::runtime_error("set_initial: several-mesh batches fill per tile");
     const int64_t n = static_cast<int64_t>(g.n_rows) * g.ld;
     const unsigned blocks = static_cast<unsigned>((n + kBlock - 1) / kBlock);
     k_set_initial<T><<<blocks, kBlock, 0, st>>>(n, g.n_rows, g.S, n_sys, u0, x);
     check_launch("set_initial");
+}
+
+template <typename T>
+void launch_set_initial_block(hipStream_t st, int64_t rows, int32_t S, int32_t n_live,
+                              const double* u0, V2<T>* x) {
+    const int64_t n = rows * S;
+    if (n <= 0) return;
+    if (rows > INT32_MAX) throw std::runtime_error("set_initial: block too large");
+    const unsigned blocks = static_cast<unsigned>((n + kBlock - 1) / kBlock);
+    k_set_initial<T><<<blocks, kBlock, 0, st>>>(n, static_cast<int32_t>(rows), S, n_live, u0, x);
+    check_launch("set_initial_block");
 }
 
 template <typename T>
@@ -3283,7 +3311,7 @@ void launch_sys_params(hipStream_t st, int32_t n_sys, int32_t ld, const double* 
 template <typename T>
 void launch_combine(hipStream_t st, const Geom& g, const ExtrapTerms<T>& t, V2<T>* x) {
     if (t.m < 1 || t.m > kMaxHist) throw std::runtime_error("combine: 1..kMaxHist terms");
-    const int64_t n = static_cast<int64_t>(g.n_rows) * g.ld;
+    const int64_t n = vec_elems(g);
     const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(8192, (n + kBlock - 1) / kBlock));
     k_combine<T><<<blocks, kBlock, 0, st>>>(n, t, x);
     check_launch("combine");
@@ -3406,6 +3434,8 @@ void launch_zero_i32(hipStream_t st, int32_t* p, int64_t n) {
                                   const double*, const double3*, const V2<T>*, V2<T>*);        \
     template void launch_set_initial<T>(hipStream_t, const Geom&, const double*, int32_t,      \
                                         V2<T>*);                                               \
+    template void launch_set_initial_block<T>(hipStream_t, int64_t, int32_t, int32_t,          \
+                                              const double*, V2<T>*);                          \
     template void launch_krylov_persistent<T>(hipStream_t, const Geom&, const MatView<T>&,     \
                                               const double4*, Coef, bool, V2<T>*, V2<T>*,      \
                                               V2<T>*, V2<T>*, SolverState, Scratch,            \

@@ -125,7 +125,19 @@ struct Geom {
     const int32_t* comp;
     const double* acomp;
     int32_t acomp_ld;    // row stride of acomp (>= ld)
+    // Batches over several meshes (the meshes' rows concatenated, each tile
+    // holding systems of one mesh): per tile {first row, end row, element
+    // base} in device memory, where element (row, system) of tile t sits at
+    // base + row * S + (system - t S) for the tile's rows only; vlen is the
+    // elements of one vector (the sum over tiles of rows * S). Null and 0
+    // for one mesh (element base tile * n_rows * S, vlen n_rows * ld).
+    const int64_t* mtab;
+    int64_t vlen;
 };
+
+inline int64_t vec_elems(const Geom& g) {
+    return g.vlen ? g.vlen : static_cast<int64_t>(g.n_rows) * g.ld;
+}
 
 struct Scratch {
     double* partial;     // [n_tiles * n_parts][B][S][4], item = tile * n_parts + part
@@ -138,7 +150,8 @@ Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd,
 // Geometry of g restricted to the n tiles listed (the tiles that may still
 // be active): each is split into enough row parts that every XCD gets the
 // same number of items. Returns g itself when the list is empty, covers
-// every tile, is longer than kMaxSched or g uses row queues. Partials and
+// every tile, is longer than kMaxSched, or g uses row queues or spans
+// several meshes (whose tiles keep their own row parts). Partials and
 // queue counters of the restricted launches stay addressed by
 // (tile * n_parts + part), so buffers sized for n_tiles * 8 parts serve both.
 Geom sched_geom(const Geom& g, const int32_t* tiles, int n);
@@ -283,6 +296,11 @@ void launch_aniso_params(hipStream_t st, int32_t n_comp, int32_t ld, const doubl
 template <typename T>
 void launch_set_initial(hipStream_t st, const Geom& g, const double* u0, int32_t n_sys,
                         typename Vec2Of<T>::type* x);
+// The same for one tile block of a several-mesh batch: rows * S elements
+// from x, row r of lane l set to u0[r] for lanes l < n_live, 0 otherwise.
+template <typename T>
+void launch_set_initial_block(hipStream_t st, int64_t rows, int32_t S, int32_t n_live,
+                              const double* u0, typename Vec2Of<T>::type* x);
 
 // Per-system parameters from b and q on the device: G = sqrt(b / intF2),
 // q normalised; padding systems get G = 0.
