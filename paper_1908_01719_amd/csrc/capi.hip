@@ -281,7 +281,7 @@ struct Workspace {
     DevBuf<double2> pc_ab, pc_hist;
     DevBuf<float> pc_X, pc_Y;
     DevBuf<int32_t> gm_cycle, gm_dim;
-    DevBuf<int64_t> mtab;  // per tile {first row, end row, element base} of a several-mesh batch
+    DevBuf<int64_t> mtab;  // per tile {first row, end row, element base, part rows}, several meshes
     int32_t* h_active[2] = {nullptr, nullptr};  // pinned
     size_t h_active_n = 0;
     ~Workspace() {
@@ -321,8 +321,9 @@ struct GraphCache {
 // One execution lane: a stream with its own workspace, polling events,
 // timing-event pool and captured graph.
 // Row layout of a batch over several meshes (their rows concatenated): per
-// tile {first row, end row, element base} (also uploaded to Workspace::mtab),
-// the elements of one vector, and the largest mesh's row count.
+// tile {first row, end row, element base, rows per part} (also uploaded to
+// Workspace::mtab), the elements of one vector, and the largest mesh's row
+// count.
 struct MeshLayout {
     std::vector<int64_t> tab;
     int64_t vlen = 0;
@@ -825,7 +826,7 @@ void fill_initial(dmri_ctx* h, const Geom& g, const ProblemRec& P, int32_t n_sys
         return;
     }
     for (int32_t t = 0; t < g.n_tiles; ++t) {
-        const int64_t lo = ml->tab[3 * t], hi = ml->tab[3 * t + 1], base = ml->tab[3 * t + 2];
+        const int64_t lo = ml->tab[4 * t], hi = ml->tab[4 * t + 1], base = ml->tab[4 * t + 2];
         const int32_t live = std::max(0, std::min(g.S, n_sys - t * g.S));
         launch_set_initial_block<T>(st, hi - lo, g.S, live, P.u0.p + lo, x + (base + lo * g.S));
     }
@@ -881,6 +882,16 @@ struct KernelTimer {
 };
 
 // Common set-up of a batch: geometry, per-system parameters, scratch.
+// Row parts of a several-mesh batch: each tile's mesh in kMeshParts parts of
+// whole chunks (chunk_rows rows, the streaming kernels' block chunk).
+constexpr int kMeshParts = 8;
+int64_t mesh_part_rows(int64_t rows, int64_t chunk_rows) {
+    int64_t pr = (rows + kMeshParts - 1) / kMeshParts;
+    pr = (pr + chunk_rows - 1) / chunk_rows * chunk_rows;
+    return std::max<int64_t>(pr, chunk_rows);
+}
+int64_t mesh_chunk_rows(int S) { return make_geom(1, S, S, 1, 0, 1).chunk_rows; }
+
 struct BatchSetup {
     Geom g;
     Geom gi;        // geometry of the FP32 inner solves (g, or 128-system paired tiles)
@@ -908,11 +919,11 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     bs.g.lds = opts(h).lds;
     if (const MeshLayout* ml = lane(h).layout) {
         // Several meshes: every tile is split into 8 parts of its own mesh's
-        // rows (parts sized for the largest mesh; the rest run short or
-        // empty), vectors hold only each tile's rows, and the kernels' paths
-        // that assume one row range per launch stay off.
+        // rows (so every XCD takes an eighth of every mesh), vectors hold
+        // only each tile's rows, and the kernels' paths that assume one row
+        // range per launch stay off. part_rows and B follow the largest mesh.
         Geom& gm = bs.g;
-        if (static_cast<int64_t>(gm.n_tiles) * 3 != static_cast<int64_t>(ml->tab.size()))
+        if (static_cast<int64_t>(gm.n_tiles) * 4 != static_cast<int64_t>(ml->tab.size()))
             throw Error(DMRI_E_STATE, "several-mesh layout does not match the batch");
         if (gm.lds || opts(h).persistent == 1 || want_pair)
             throw Error(DMRI_E_UNSUPPORTED, "several-mesh batches: no LDS SpMV, persistent "
@@ -920,11 +931,9 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
         gm.mtab = lane(h).ws.mtab.p;
         gm.vlen = ml->vlen;
         gm.tile_bytes_ok = 0;
-        gm.n_parts = 8;
+        gm.n_parts = kMeshParts;
         gm.n_items = gm.n_tiles * gm.n_parts;
-        int64_t pr = (ml->max_rows + gm.n_parts - 1) / gm.n_parts;
-        pr = (pr + gm.chunk_rows - 1) / gm.chunk_rows * gm.chunk_rows;
-        gm.part_rows = static_cast<int32_t>(std::max<int64_t>(pr, gm.chunk_rows));
+        gm.part_rows = static_cast<int32_t>(mesh_part_rows(ml->max_rows, gm.chunk_rows));
         const int32_t chunks = (gm.part_rows + gm.chunk_rows - 1) / gm.chunk_rows;
         gm.B = std::max(1, std::min(gm.bpx, chunks));
     }
@@ -2716,10 +2725,12 @@ bool run_merged(dmri_ctx* h, const std::vector<std::pair<int32_t, std::vector<in
         if (o.sort_systems) order_systems(h, pid, b, q, idx);
         const int64_t rows = get_problem(h, pid).op.n_dof;
         const int64_t nt = (static_cast<int64_t>(idx.size()) + S - 1) / S;
+        const int64_t chunk_rows = mesh_chunk_rows(S);
         for (int64_t t = 0; t < nt; ++t) {
             ml.tab.push_back(row0);
             ml.tab.push_back(row0 + rows);
             ml.tab.push_back(elems - row0 * S);
+            ml.tab.push_back(mesh_part_rows(rows, chunk_rows));
             elems += rows * S;
         }
         for (int64_t i = 0; i < nt * S; ++i) {

@@ -150,22 +150,23 @@ __device__ __forceinline__ void diag_at(const T* __restrict__ dK0, const V4<T>* 
 // the L2 channels. Element (row, sys) of the tile is at vbase + row * S.
 __device__ __forceinline__ size_t vbase(const Geom& g, int tile, int S, int sys) {
     // Several meshes: tile t holds only its mesh's rows, from element
-    // mtab[3t + 2] + lo * S on (the base may be below zero; the sum is not).
+    // mtab[4t + 2] + lo * S on (the base may be below zero; the sum is not).
     if (g.mtab)
-        return static_cast<size_t>(g.mtab[3 * tile + 2]) + static_cast<size_t>(sys - tile * S);
+        return static_cast<size_t>(g.mtab[4 * tile + 2]) + static_cast<size_t>(sys - tile * S);
     return static_cast<size_t>(tile) * g.n_rows * S + (sys - tile * S);
 }
 
-// Rows [r0, r1) of row part `part` of a tile: a slice of the tile's mesh
-// (all rows when the batch has one mesh).
+// Rows [r0, r1) of row part `part` of a tile: a slice of the tile's mesh,
+// whose parts have their own length (all rows when the batch has one mesh).
 __device__ __forceinline__ void part_range(const Geom& g, int tile, int part, int& r0, int& r1) {
-    int lo = 0, hi = g.n_rows;
+    int lo = 0, hi = g.n_rows, pr = g.part_rows;
     if (g.mtab) {
-        lo = static_cast<int>(g.mtab[3 * tile]);
-        hi = static_cast<int>(g.mtab[3 * tile + 1]);
+        lo = static_cast<int>(g.mtab[4 * tile]);
+        hi = static_cast<int>(g.mtab[4 * tile + 1]);
+        pr = static_cast<int>(g.mtab[4 * tile + 3]);
     }
-    r0 = lo + part * g.part_rows;
-    r1 = min(hi, r0 + g.part_rows);
+    r0 = lo + part * pr;
+    r1 = min(hi, r0 + pr);
 }
 
 // Work item kk of a launch: its tile (through the schedule list when the

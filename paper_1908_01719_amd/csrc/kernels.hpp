@@ -127,10 +127,12 @@ struct Geom {
     int32_t acomp_ld;    // row stride of acomp (>= ld)
     // Batches over several meshes (the meshes' rows concatenated, each tile
     // holding systems of one mesh): per tile {first row, end row, element
-    // base} in device memory, where element (row, system) of tile t sits at
-    // base + row * S + (system - t S) for the tile's rows only; vlen is the
-    // elements of one vector (the sum over tiles of rows * S). Null and 0
-    // for one mesh (element base tile * n_rows * S, vlen n_rows * ld).
+    // base, rows per part} in device memory, where element (row, system) of
+    // tile t sits at base + row * S + (system - t S) for the tile's rows
+    // only and each tile's n_parts parts split its own rows; part_rows is
+    // then the longest part. vlen is the elements of one vector (the sum
+    // over tiles of rows * S). Null and 0 for one mesh (element base
+    // tile * n_rows * S, vlen n_rows * ld).
     const int64_t* mtab;
     int64_t vlen;
 };

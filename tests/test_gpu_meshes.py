@@ -121,3 +121,54 @@ def test_one_batch_refusals(Sim):
     for opts in (dict(precision=2), dict(krylov=3), dict(graph=1), dict(lds=1)):
         with pytest.raises(DmriError):
             _run(Sim, items, rtol=1e-10, mesh_merge=1, **opts)
+
+
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           name + ".json")) as f:
+        d = json.load(f)
+    return d, np.array(d["signal_re"]) + 1j * np.array(d["signal_im"])
+
+
+def test_seeded_cells_one_batch(Sim):
+    # The uneven workload as one batch: the 8 seeded-cell geometries (seeds
+    # 0-7, 63k-878k DOFs), 32 (b, q) pairs each, every launch over all 8
+    # meshes. Mixed precision at rtol 1e-6 over the full echo: the oracle's
+    # full-echo signals of seeds 2 and 3 within 1e-4. All-FP64 at rtol 1e-12
+    # for the first two steps: the oracle's sums after two steps on seeds 0,
+    # 1 and 4 within 1e-9.
+    items = [di.seeded_cells(seed) for seed in range(8)]
+    seq = items[0][1]
+    out = {}
+    with Sim(0) as sim:
+        sim.set_sequence(seq)
+        pids = [sim.add_problem(prob) for prob, _, _ in items]
+        ids = np.concatenate([np.full(len(sl), p, np.int32) for p, (_, _, sl) in zip(pids, items)])
+        b = np.concatenate([sl.b for _, _, sl in items])
+        q = np.concatenate([sl.q for _, _, sl in items])
+        for key, opts in (("mixed", dict(precision=1, rtol=1e-6)),
+                          ("first2", dict(precision=0, rtol=1e-12, n_steps=2, signal=0))):
+            o = dict(mesh_merge=1, n_steps=0, signal=1)
+            o.update(opts)
+            sim.set_options(**o)
+            sig, st = sim.dmri_run(ids, b, q)
+            assert st["status"] == "DMRI_OK"
+            out[key] = (sig.reshape(8, 32), st)
+    sig, st = out["mixed"]
+    errs = []
+    for seed in (2, 3):
+        d, ref = _golden("seeded_cells_seed%d" % seed)
+        errs.append(np.abs(sig[seed][np.array(d["index"])] - ref) / np.abs(ref))
+    e_full = np.concatenate(errs).max()
+    d, ref = _golden("seeded_cells_first2")
+    first = out["first2"][0]
+    got = np.array([first[s][i] for s, i in d["index"]])
+    e_first = (np.abs(got - ref) / np.abs(ref)).max()
+    _say("seeded cells, 8 meshes in one batch: mixed full echo max err %.2e (solve %.1f s, %d "
+         "inner iterations); FP64 first two steps max err %.2e"
+         % (e_full, st["t_solve_s"], st["total_iterations"], e_first))
+    assert e_full < 1e-4
+    assert e_first < 1e-9
+    assert np.all(np.isfinite(sig))
