@@ -251,8 +251,12 @@ def main():
     ap.add_argument("--time-kernel", default="spmv", choices=sorted(KERNELS))
     ap.add_argument("--sys-tile", type=int, default=0)
     ap.add_argument("--blocks-per-xcd", type=int, default=0)
+    ap.add_argument("--mesh-merge", type=int, default=None,
+                    help="several meshes as one batch, every launch over all of them "
+                         "(library option mesh_merge; default: on for seeded_cells_batch)")
     ap.add_argument("--autotune", type=int, default=None,
-                    help="library autotuner (default: on for seeded_cells_batch)")
+                    help="library autotuner (default: on for a several-mesh workload run mesh "
+                         "by mesh)")
     ap.add_argument("--concurrency", type=int, default=1,
                     help="problems of a multi-mesh workload run at once (lanes)")
     ap.add_argument("--cpu-steps", type=int, default=6)
@@ -286,7 +290,8 @@ def main():
     n_pairs = sum(len(sl) for _, sl in items)
     prec = {"fp64": 0, "mixed": 1, "fp32": 2}[args.precision]
     rtol = args.rtol if args.rtol is not None else 1e-6
-    autotune = args.autotune if args.autotune is not None else int(len(items) > 1)
+    merge = args.mesh_merge if args.mesh_merge is not None else int(len(items) > 1)
+    autotune = args.autotune if args.autotune is not None else int(len(items) > 1 and not merge)
     print("bench: workload %s (%s), %d systems on %d meshes, precision %s" % (
         args.workload, desc, n_pairs, len(items), args.precision), file=sys.stderr, flush=True)
 
@@ -312,7 +317,7 @@ def main():
     t_asm = time.perf_counter() - t0
     info = [sim.dmri_problem_info(p) for p in pid_list]
     opts = dict(precision=prec, rtol=rtol, guess=args.guess, autotune=autotune,
-                concurrency=args.concurrency,
+                concurrency=args.concurrency, mesh_merge=merge,
                 time_kernel=KERNELS[args.time_kernel], progress=args.progress)
     if args.sys_tile:
         opts["sys_tile"] = args.sys_tile
@@ -421,8 +426,9 @@ def main():
               "rtol": rtol, "guess": args.guess,
               "extrap_order": int(sim.dmri_get_option("extrap_order")),
               "sys_tile": tiles if len(items) > 1 else tiles[0], "autotune": autotune,
-              "concurrency": args.concurrency, "extra_options": extra,
-              "parallelism": "single GPU, systems batched per mesh"}
+              "concurrency": args.concurrency, "mesh_merge": merge, "extra_options": extra,
+              "parallelism": ("single GPU, all meshes in one batch" if merge and len(items) > 1
+                              else "single GPU, systems batched per mesh")}
     out = {
         "metric": "DOF-steps/s", "value": value, "unit": "DOF-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
