@@ -291,7 +291,8 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *               CG/COCG, guess 0/1, signal at echo (or option signal = 0);
  *               one form for all problems, no tensors or weak faces; other
  *               combinations end in DMRI_E_UNSUPPORTED. 0 (default): one
- *               batch per problem (option concurrency). dmri_run only.
+ *               batch per problem (option concurrency). Applies to dmri_run
+ *               and to dmri_run_device over several problems.
  *  "inner_floor" fraction f in (0, 1] of the outer target below which an
  *               FP32 inner solve does not go: it stops once ||r|| <=
  *               max(inner_rtol ||r64||, f rtol ||b||) (default 0.25). A

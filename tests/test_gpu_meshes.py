@@ -89,16 +89,20 @@ def _run(Sim, items, **opts):
     return sig, st
 
 
-@pytest.mark.parametrize("precision,tile", [(0, 0), (0, 16), (1, 0), (1, 8)])
-def test_periodic_meshes_one_batch_match_oracle(Sim, precision, tile):
+@pytest.mark.parametrize("precision,tile,queue", [(0, 0, 0), (0, 16, 0), (0, 64, 0), (0, 8, 1),
+                                                  (1, 0, 0), (1, 8, 0), (1, 16, 1)])
+def test_periodic_meshes_one_batch_match_oracle(Sim, precision, tile, queue):
+    # Tiles of 8-64 systems (64: one ragged tile per mesh), static row
+    # chunks or per-item row queues in the gather kernels.
     items = _periodic_case()
     ref = np.concatenate([it[3] for it in items])
-    merged, st = _run(Sim, items, rtol=1e-12, precision=precision, sys_tile=tile, mesh_merge=1)
-    seq, _ = _run(Sim, items, rtol=1e-12, precision=precision, sys_tile=tile, mesh_merge=0)
+    opts = dict(rtol=1e-12, precision=precision, sys_tile=tile, queue=queue)
+    merged, st = _run(Sim, items, mesh_merge=1, **opts)
+    seq, _ = _run(Sim, items, mesh_merge=0, **opts)
     err = _err(merged, ref)
     diff = np.abs(merged - seq).max() / np.abs(ref).max()
-    _say("3 meshes in one batch, precision %d, tile %d: max err %.2e, vs mesh by mesh %.2e, "
-         "%d iterations" % (precision, tile, err.max(), diff, st["total_iterations"]))
+    _say("3 meshes in one batch, precision %d, tile %d, queue %d: max err %.2e, vs mesh by mesh "
+         "%.2e, %d iterations" % (precision, tile, queue, err.max(), diff, st["total_iterations"]))
     assert err.max() < 1e-9
     assert diff < 1e-10
 
