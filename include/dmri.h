@@ -290,7 +290,9 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *               all meshes, each over its own mesh's rows. Precision 0 or 1,
  *               CG/COCG, guess 0/1, signal at echo (or option signal = 0);
  *               one form for all problems, no tensors or weak faces; other
- *               combinations end in DMRI_E_UNSUPPORTED. 0 (default): one
+ *               combinations end in DMRI_E_UNSUPPORTED. The concatenated
+ *               operator is built once per list of problems and kept (host
+ *               and device copies) until dmri_destroy. 0 (default): one
  *               batch per problem (option concurrency). Applies to dmri_run
  *               and to dmri_run_device over several problems.
  *  "inner_floor" fraction f in (0, 1] of the outer target below which an

@@ -2777,6 +2777,16 @@ bool run_merged(dmri_ctx* h, const std::vector<std::pair<int32_t, std::vector<in
         signal_out[2 * owner[i] + 1] = sig[2 * i + 1];
         if (R.flags[i]) any_nc = true;
     }
+    // Totals over the caller's pairs only (not the b = 0 padding), each
+    // system's products over its own mesh's rows.
+    R.total_iters = 0;
+    R.spmv_rows = 0;
+    for (int64_t i = 0; i < ns; ++i) {
+        if (owner[i] < 0) continue;
+        const int64_t t = i / S;
+        R.total_iters += R.iters[i];
+        R.spmv_rows += static_cast<int64_t>(R.iters[i]) * (ml.tab[4 * t + 1] - ml.tab[4 * t]);
+    }
     if (stats) stats->t_setup_s += t_up;
     fill_stats(stats, owner, R, n_pairs);
     // Costs per problem, in the order its pairs took in the slots.

@@ -85,6 +85,7 @@ def _run(Sim, items, **opts):
         b = np.concatenate([it[1] for it in items])
         q = np.concatenate([it[2] for it in items])
         sig, st = sim.dmri_run(ids, b, q)
+        st["n_dof"] = [sim.dmri_problem_info(p)[0] for p in pids]
     assert st["status"] == "DMRI_OK"
     return sig, st
 
@@ -105,6 +106,11 @@ def test_periodic_meshes_one_batch_match_oracle(Sim, precision, tile, queue):
          "%.2e, %d iterations" % (precision, tile, queue, err.max(), diff, st["total_iterations"]))
     assert err.max() < 1e-9
     assert diff < 1e-10
+    # Work counters cover the caller's pairs only, each over its own mesh.
+    rows = np.concatenate([np.full(len(it[1]), n) for it, n in zip(items, st["n_dof"])])
+    iters = np.asarray(st["iters_total"], np.int64)
+    assert st["total_iterations"] == iters.sum()
+    assert st["spmv_rows"] == int((iters * rows).sum())
 
 
 @pytest.mark.parametrize("guess", [0, 1])
