@@ -287,7 +287,10 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *               diagonally, each problem's pairs (ordered by cost) padded
  *               with b = 0 systems to whole tiles, so each tile holds one
  *               mesh's systems; every kernel launch then covers the tiles of
- *               all meshes, each over its own mesh's rows. Precision 0 or 1,
+ *               all meshes, each over its own mesh's rows; a batch of at most
+ *               64 systems can run the persistent Krylov kernel (options
+ *               persistent, graph: one launch per solve over all meshes, the
+ *               time loop captured in a HIP graph). Precision 0 or 1,
  *               CG/COCG, guess 0/1, signal at echo (or option signal = 0);
  *               one form for all problems, no tensors or weak faces; other
  *               combinations end in DMRI_E_UNSUPPORTED. The concatenated

@@ -925,9 +925,8 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
         Geom& gm = bs.g;
         if (static_cast<int64_t>(gm.n_tiles) * 4 != static_cast<int64_t>(ml->tab.size()))
             throw Error(DMRI_E_STATE, "several-mesh layout does not match the batch");
-        if (gm.lds || opts(h).persistent == 1 || want_pair)
-            throw Error(DMRI_E_UNSUPPORTED, "several-mesh batches: no LDS SpMV, persistent "
-                                            "solver or paired tiles");
+        if (gm.lds || want_pair)
+            throw Error(DMRI_E_UNSUPPORTED, "several-mesh batches: no LDS SpMV or paired tiles");
         gm.mtab = lane(h).ws.mtab.p;
         gm.vlen = ml->vlen;
         gm.tile_bytes_ok = 0;
@@ -944,15 +943,25 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     bs.gp = make_geom(g.n_rows, static_cast<int32_t>(n_sys), S, std::max(1, n_cu / 8), 0, 1);
     bs.gp.nt = g.nt;
     bs.gp.lds = 0;
+    if (g.mtab) {  // the persistent solver's items follow the several-mesh layout too
+        Geom& gq = bs.gp;
+        gq.mtab = g.mtab;
+        gq.vlen = g.vlen;
+        gq.tile_bytes_ok = 0;
+        gq.n_parts = g.n_parts;
+        gq.n_items = gq.n_tiles * gq.n_parts;
+        gq.part_rows = g.part_rows;
+        const int32_t chunks = (gq.part_rows + gq.chunk_rows - 1) / gq.chunk_rows;
+        gq.B = std::max(1, std::min(gq.bpx, chunks));
+    }
     // Auto: the persistent solver wins where launch latency dominates (small
     // batches on small meshes); chunked launches win once a phase has enough
     // work to hide the per-launch cost.
-    const bool small = static_cast<int64_t>(g.n_rows) * g.ld <= 131072;
+    const bool small = vec_elems(g) <= 131072;
     if (opts(h).krylov == 3 && opts(h).precision != 0)
         throw Error(DMRI_E_UNSUPPORTED, "GMRES (krylov = 3) runs in precision 0 (FP64)");
     bs.persist = (opts(h).persistent == 1 || (opts(h).persistent == 2 && small)) && g.ld <= 64 &&
-                 opts(h).krylov != 3 && opts(h).precond == 0 && h->pcmodel.rec_cap == 0 &&
-                 !g.mtab;
+                 opts(h).krylov != 3 && opts(h).precond == 0 && h->pcmodel.rec_cap == 0;
     // The grid barrier needs every block resident: otherwise chunked launches.
     if (bs.persist) {
         const bool fits = opts(h).precision != 0 ? persistent_fits<float>(bs.gp, bs.herm, n_cu)
@@ -1503,6 +1512,8 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
                          double(opts(h).extrap_damp), h->dt, h->theta,
                          double(h->seq_gen)})
             kd(v);
+        if (const MeshLayout* ml = lane(h).layout)  // the tiles' meshes and rows
+            for (int64_t v : ml->tab) key.push_back(static_cast<uint64_t>(v));
         bool hit = false;
         GraphCache& gc = lane(h).graph_for(key, hit);
         if (hit) {
@@ -2691,11 +2702,11 @@ bool run_merged(dmri_ctx* h, const std::vector<std::pair<int32_t, std::vector<in
                 int64_t n_pairs, const double* b, const double* q, double* signal_out,
                 dmri_stats* stats) {
     const Options& o = opts(h);
-    if (o.precision == 2 || o.krylov == 3 || o.precond != 0 || o.guess == 2 || o.graph ||
-        o.lds || h->model.rec_cap > 0 || h->pcmodel.rec_cap > 0)
+    if (o.precision == 2 || o.krylov == 3 || o.precond != 0 || o.guess == 2 || o.lds ||
+        h->model.rec_cap > 0 || h->pcmodel.rec_cap > 0)
         throw Error(DMRI_E_UNSUPPORTED,
                     "several-mesh batches run precision 0 or 1 with CG/COCG, guess 0/1, no "
-                    "graph, LDS SpMV, preconditioner or sample recording");
+                    "LDS SpMV, preconditioner or sample recording");
     std::vector<int32_t> pids;
     size_t max_ns = 0;
     for (const auto& gr : groups) {
@@ -2757,7 +2768,6 @@ bool run_merged(dmri_ctx* h, const std::vector<std::pair<int32_t, std::vector<in
     {
         OptionGuard guard(h);
         opts(h).sys_tile = S;
-        opts(h).persistent = 0;
         opts(h).pair_lanes = 0;
         struct LayoutScope {
             Lane& l;

@@ -113,6 +113,45 @@ def test_periodic_meshes_one_batch_match_oracle(Sim, precision, tile, queue):
     assert st["spmv_rows"] == int((iters * rows).sum())
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_periodic_meshes_persistent_and_graph(Sim, precision):
+    # The three meshes' 21 pairs in 32 slots (tiles of 8) solved by the
+    # persistent Krylov kernel: one launch per solve spans every mesh. In
+    # FP64 the whole time loop is also captured in a HIP graph, then
+    # replayed by a second run; both runs match the oracle within 1e-9 and
+    # each other exactly, and the chunked launches within 1e-10.
+    items = _periodic_case()
+    ref = np.concatenate([it[3] for it in items])
+    base = dict(rtol=1e-12, precision=precision, mesh_merge=1)
+    chunked, stc = _run(Sim, items, persistent=0, time_kernel=1, **base)
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        sim.set_options(persistent=1, graph=1 if precision == 0 else 0, **base)
+        pids = [sim.add_problem(prob) for prob, _, _, _ in items]
+        ids = np.concatenate([np.full(len(b), p, np.int32)
+                              for p, (_, b, _, _) in zip(pids, items)])
+        b = np.concatenate([it[1] for it in items])
+        q = np.concatenate([it[2] for it in items])
+        first, st1 = sim.dmri_run(ids, b, q)
+        second, st2 = sim.dmri_run(ids, b, q)
+        # Krylov launches counted (no graph): one per solve in the persistent kernel.
+        sim.set_options(graph=0, time_kernel=1)
+        _, st3 = sim.dmri_run(ids, b, q)
+    assert st1["status"] == "DMRI_OK" and st2["status"] == "DMRI_OK"
+    err = _err(first, ref)
+    diff = np.abs(first - chunked).max() / np.abs(ref).max()
+    _say("3 meshes, persistent kernel (precision %d): max err %.2e, vs chunked %.2e"
+         % (precision, err.max(), diff))
+    assert err.max() < 1e-9
+    assert diff < 1e-10
+    assert np.array_equal(first, second)
+    _say("Krylov launches: persistent %d, chunked %d" % (st3["n_kernel_launches"],
+                                                         stc["n_kernel_launches"]))
+    if precision == 0:
+        assert st3["n_kernel_launches"] == st3["n_steps"]
+    assert st3["n_kernel_launches"] * 4 < stc["n_kernel_launches"]
+
+
 @pytest.mark.parametrize("guess", [0, 1])
 def test_walled_meshes_one_batch_match_oracle(Sim, guess):
     items = _walls_case()
@@ -128,7 +167,7 @@ def test_one_batch_refusals(Sim):
     # error, not run another way.
     from paper_1908_01719_amd.binding import DmriError
     items = _periodic_case()[:2]
-    for opts in (dict(precision=2), dict(krylov=3), dict(graph=1), dict(lds=1)):
+    for opts in (dict(precision=2), dict(krylov=3), dict(lds=1), dict(guess=2)):
         with pytest.raises(DmriError):
             _run(Sim, items, rtol=1e-10, mesh_merge=1, **opts)
 
