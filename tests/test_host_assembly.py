@@ -230,8 +230,12 @@ def test_sequence_and_option_validation():
         assert s.dmri_get_option("inner_floor") == 0.25
         s.dmri_set_option("inner_floor", 1.0)
         assert s.dmri_get_option("inner_floor") == 1.0
+        assert s.dmri_get_option("mesh_merge") == 0
+        s.dmri_set_option("mesh_merge", 1)
+        assert s.dmri_get_option("mesh_merge") == 1
         for k, v in [("rtol", 0.0), ("precision", 5), ("sys_tile", 12), ("nope", 1),
-                     ("max_iter", 0), ("inner_floor", 0.0), ("inner_floor", 1.5)]:
+                     ("max_iter", 0), ("inner_floor", 0.0), ("inner_floor", 1.5),
+                     ("mesh_merge", 2)]:
             with pytest.raises(DmriError):
                 s.dmri_set_option(k, v)
         with pytest.raises(DmriError) as ei:
