@@ -178,9 +178,10 @@ def _seeded_checks(sig, tol_full, tol_first, first=None):
 
 
 _SEEDED_BATCH_SKIP = (
-    "a GPU memory fault ended the box during this test's run (8 meshes x 32 pairs, "
-    "autotuned, mixed precision) after it had passed earlier; its cause is not found yet, so "
-    "the uneven-batch runs stay off the GPU until it is")
+    "a GPU memory fault ended the box during this test's run (8 meshes x 32 pairs, run mesh by "
+    "mesh, autotuned, mixed precision) after it had passed earlier; its cause is not found yet, "
+    "so this path stays off the GPU until it is (the same batch runs as one batch in "
+    "tests/test_gpu_meshes.py::test_seeded_cells_one_batch)")
 
 
 @pytest.mark.skip(reason=_SEEDED_BATCH_SKIP)
