@@ -376,7 +376,10 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *               number of systems, precision, solver), time its first steps
  *               under each candidate launch configuration (tile width,
  *               blocks per XCD, persistent kernel, LDS SpMV) and use the
- *               fastest; the choice is cached in the handle (default 0)
+ *               fastest; the choice is cached in the handle (default 0). A
+ *               several-mesh batch (mesh_merge) is one kind of batch per list
+ *               of problems and pair counts; its candidates are the tile
+ *               width, blocks per XCD and the persistent kernel
  *  "tuned_sys_tile", "tuned_blocks_per_xcd", "tuned_persistent",
  *  "tuned_lds", "tuned_trials"  read-only (dmri_get_option): the
  *               configuration the autotuner applied last (-1 before any)

@@ -2698,6 +2698,149 @@ ProblemRec& merged_problem(dmri_ctx* h, const std::vector<int32_t>& pids) {
 // mesh. Each kernel launch then covers the tiles of all meshes, every tile
 // over its own mesh's rows only (vectors hold just those rows). FP64 and
 // mixed precision with CG/COCG and the polynomial-extrapolation guesses.
+// Slots of a several-mesh batch at tile width S: per problem its pairs
+// (cost order) then b = 0 padding to whole tiles, with the row layout.
+struct MergedSlots {
+    MeshLayout ml;
+    std::vector<int64_t> owner;  // caller's pair index per slot, -1 for padding
+    std::vector<double> b, q;
+    std::vector<std::vector<int64_t>> order;  // per problem, its pairs in slot order
+};
+
+MergedSlots merged_slots(dmri_ctx* h,
+                         const std::vector<std::pair<int32_t, std::vector<int64_t>>>& groups,
+                         const double* b, const double* q, int S) {
+    MergedSlots m;
+    m.order.resize(groups.size());
+    int64_t row0 = 0, elems = 0;
+    const int64_t chunk_rows = mesh_chunk_rows(S);
+    for (size_t k = 0; k < groups.size(); ++k) {
+        const int32_t pid = groups[k].first;
+        std::vector<int64_t> idx = groups[k].second;
+        if (opts(h).sort_systems) order_systems(h, pid, b, q, idx);
+        const int64_t rows = get_problem(h, pid).op.n_dof;
+        const int64_t nt = (static_cast<int64_t>(idx.size()) + S - 1) / S;
+        for (int64_t t = 0; t < nt; ++t) {
+            m.ml.tab.push_back(row0);
+            m.ml.tab.push_back(row0 + rows);
+            m.ml.tab.push_back(elems - row0 * S);
+            m.ml.tab.push_back(mesh_part_rows(rows, chunk_rows));
+            elems += rows * S;
+        }
+        for (int64_t i = 0; i < nt * S; ++i) {
+            const bool real = i < static_cast<int64_t>(idx.size());
+            m.owner.push_back(real ? idx[i] : -1);
+            m.b.push_back(real ? b[idx[i]] : 0.0);
+            for (int a = 0; a < 3; ++a)
+                m.q.push_back(real ? q[3 * idx[i] + a] : (a == 0 ? 1.0 : 0.0));
+        }
+        m.ml.max_rows = std::max(m.ml.max_rows, rows);
+        row0 += rows;
+        m.order[k] = std::move(idx);
+    }
+    m.ml.vlen = elems;
+    if (static_cast<int64_t>(m.owner.size()) / S > 4096)
+        throw Error(DMRI_E_UNSUPPORTED, "several-mesh batch: over 4096 tiles");
+    return m;
+}
+
+// One run of a several-mesh batch with tile width S, blocks per XCD and the
+// persistent-kernel option as given (the options are restored afterwards).
+void run_merged_with(dmri_ctx* h, ProblemRec& M, const MergedSlots& m, int S, int bpx,
+                     int persistent, double2* d_sig, BatchResult& R) {
+    hipStream_t st = lane(h).stream;
+    Workspace& W = lane(h).ws;
+    const int64_t ns = static_cast<int64_t>(m.owner.size());
+    W.mtab.upload(m.ml.tab.data(), m.ml.tab.size(), st);
+    W.b_in.upload(m.b.data(), ns, st);
+    W.q_in.upload(m.q.data(), 3 * ns, st);
+    HIPCHK(hipStreamSynchronize(st));
+    OptionGuard guard(h);
+    opts(h).sys_tile = S;
+    opts(h).blocks_per_xcd = bpx;
+    opts(h).persistent = persistent;
+    opts(h).pair_lanes = 0;
+    struct LayoutScope {
+        Lane& l;
+        LayoutScope(Lane& ln, const MeshLayout* ml) : l(ln) { l.layout = ml; }
+        ~LayoutScope() { l.layout = nullptr; }
+    } scope(lane(h), &m.ml);
+    const Marker mk(h, "batch", ns);
+    run_batch_with(h, M, ns, W.b_in.p, W.q_in.p, d_sig, R);
+}
+
+// Autotuner of several-mesh batches: the first steps under each candidate
+// (tile width S0 or S0 / 2, 256/512/1024 blocks per XCD, and the persistent
+// kernel when all slots fit it), fastest kept; trials record nothing and
+// write their signals to scratch.
+TuneChoice autotune_merged(dmri_ctx* h, ProblemRec& M,
+                           const std::vector<std::pair<int32_t, std::vector<int64_t>>>& groups,
+                           const double* b, const double* q, int S0) {
+    OptionGuard guard(h);
+    const int total = opts(h).n_steps > 0 ? std::min(opts(h).n_steps, h->n_steps) : h->n_steps;
+    opts(h).n_steps = std::max(1, std::min(4, total));
+    opts(h).signal = 0;
+    opts(h).progress = 0;
+    opts(h).time_kernel = 0;
+    opts(h).graph = 0;
+    std::vector<TuneChoice> cands;
+    for (int S : {S0, S0 / 2}) {
+        if (S < 8 || (S != S0 && opts(h).sys_tile)) continue;
+        for (int bpx : {256, 512, 1024}) {
+            TuneChoice c;
+            c.sys_tile = S;
+            c.blocks_per_xcd = bpx;
+            c.persistent = 0;
+            c.lds = 0;
+            cands.push_back(c);
+        }
+        size_t slots = 0;
+        for (const auto& gr : groups) slots += (gr.second.size() + S - 1) / S * S;
+        if (slots <= 64) {
+            TuneChoice c;
+            c.sys_tile = S;
+            c.blocks_per_xcd = 512;
+            c.persistent = 1;
+            c.lds = 0;
+            cands.push_back(c);
+        }
+    }
+    TuneChoice best;
+    best.seconds = 1e300;
+    DevBuf<double2> sig;
+    bool warm = false;
+    int trials = 0;
+    for (const TuneChoice& c : cands) {
+        const MergedSlots m = merged_slots(h, groups, b, q, c.sys_tile);
+        sig.alloc(m.owner.size());
+        if (!warm) {  // allocations and first-touch costs stay out of the trials
+            BatchResult R0;
+            run_merged_with(h, M, m, c.sys_tile, c.blocks_per_xcd, c.persistent, sig.p, R0);
+            warm = true;
+        }
+        BatchResult R;
+        const double t0 = now_s();
+        run_merged_with(h, M, m, c.sys_tile, c.blocks_per_xcd, c.persistent, sig.p, R);
+        HIPCHK(hipStreamSynchronize(lane(h).stream));
+        const double t = now_s() - t0;
+        ++trials;
+        if (t < best.seconds) {
+            best = c;
+            best.seconds = t;
+        }
+    }
+    best.trials = trials;
+    return best;
+}
+
+// Several problems as one batch (option mesh_merge): the problems' operators
+// concatenated block-diagonally, each problem's pairs ordered by cost and
+// padded with b = 0 systems to whole tiles, so every tile belongs to one
+// mesh. Each kernel launch then covers the tiles of all meshes, every tile
+// over its own mesh's rows only (vectors hold just those rows). FP64 and
+// mixed precision with CG/COCG and the polynomial-extrapolation guesses;
+// with option autotune the tile width, blocks per XCD and persistent kernel
+// are tuned per kind of batch (cached with the other choices).
 bool run_merged(dmri_ctx* h, const std::vector<std::pair<int32_t, std::vector<int64_t>>>& groups,
                 int64_t n_pairs, const double* b, const double* q, double* signal_out,
                 dmri_stats* stats) {
@@ -2713,7 +2856,8 @@ bool run_merged(dmri_ctx* h, const std::vector<std::pair<int32_t, std::vector<in
         pids.push_back(gr.first);
         max_ns = std::max(max_ns, gr.second.size());
     }
-    const int S = o.sys_tile ? o.sys_tile : auto_tile(static_cast<int64_t>(max_ns));
+    int S = o.sys_tile ? o.sys_tile : auto_tile(static_cast<int64_t>(max_ns));
+    int bpx = o.blocks_per_xcd, persistent = o.persistent;
     hipStream_t st = lane(h).stream;
     const double ts = now_s();
     ProblemRec& M = merged_problem(h, pids);
@@ -2724,67 +2868,41 @@ bool run_merged(dmri_ctx* h, const std::vector<std::pair<int32_t, std::vector<in
             throw Error(DMRI_E_UNSUPPORTED, "several-mesh batches return sum w u (F(t) != 0 at "
                                             "the last step needs option signal = 0)");
     }
-    // Slots: per problem its pairs (cost order) then b = 0 padding to whole tiles.
-    MeshLayout ml;
-    std::vector<int64_t> owner;
-    std::vector<double> hb, hq;
-    std::vector<std::vector<int64_t>> order(groups.size());
-    int64_t row0 = 0, elems = 0;
-    for (size_t k = 0; k < groups.size(); ++k) {
-        const int32_t pid = groups[k].first;
-        std::vector<int64_t> idx = groups[k].second;
-        if (o.sort_systems) order_systems(h, pid, b, q, idx);
-        const int64_t rows = get_problem(h, pid).op.n_dof;
-        const int64_t nt = (static_cast<int64_t>(idx.size()) + S - 1) / S;
-        const int64_t chunk_rows = mesh_chunk_rows(S);
-        for (int64_t t = 0; t < nt; ++t) {
-            ml.tab.push_back(row0);
-            ml.tab.push_back(row0 + rows);
-            ml.tab.push_back(elems - row0 * S);
-            ml.tab.push_back(mesh_part_rows(rows, chunk_rows));
-            elems += rows * S;
+    if (o.autotune) {
+        char fp[17];
+        std::snprintf(fp, sizeof fp, "%016llx", static_cast<unsigned long long>(M.fingerprint));
+        std::string key = h->device_tag + "/merged-" + fp + "/";
+        for (const auto& gr : groups) key += std::to_string(gr.second.size()) + ",";
+        key += "/" + std::to_string(o.precision) + "/" + std::to_string(o.krylov) + "/" +
+               std::to_string(o.sys_tile);
+        TuneChoice c;
+        {
+            std::lock_guard<std::mutex> lock(h->tuned_mu);
+            auto it = h->tuned.find(key);
+            if (it == h->tuned.end())
+                it = h->tuned.emplace(key, autotune_merged(h, M, groups, b, q, S)).first;
+            c = it->second;
+            h->last_tune = c;
         }
-        for (int64_t i = 0; i < nt * S; ++i) {
-            const bool real = i < static_cast<int64_t>(idx.size());
-            owner.push_back(real ? idx[i] : -1);
-            hb.push_back(real ? b[idx[i]] : 0.0);
-            for (int a = 0; a < 3; ++a) hq.push_back(real ? q[3 * idx[i] + a] : (a == 0 ? 1.0 : 0.0));
-        }
-        ml.max_rows = std::max(ml.max_rows, rows);
-        row0 += rows;
-        order[k] = std::move(idx);
+        S = c.sys_tile;
+        bpx = c.blocks_per_xcd;
+        persistent = c.persistent;
     }
-    ml.vlen = elems;
-    const int64_t ns = static_cast<int64_t>(owner.size());
-    if (ns / S > 4096) throw Error(DMRI_E_UNSUPPORTED, "several-mesh batch: over 4096 tiles");
+    const MergedSlots m = merged_slots(h, groups, b, q, S);
+    const int64_t ns = static_cast<int64_t>(m.owner.size());
     Workspace& W = lane(h).ws;
-    W.mtab.upload(ml.tab.data(), ml.tab.size(), st);
-    W.b_in.upload(hb.data(), ns, st);
-    W.q_in.upload(hq.data(), 3 * ns, st);
     W.sig.alloc(ns);
-    HIPCHK(hipStreamSynchronize(st));  // host staging vectors go out of scope
     const double t_up = now_s() - ts;
     BatchResult R;
-    {
-        OptionGuard guard(h);
-        opts(h).sys_tile = S;
-        opts(h).pair_lanes = 0;
-        struct LayoutScope {
-            Lane& l;
-            LayoutScope(Lane& ln, const MeshLayout* m) : l(ln) { l.layout = m; }
-            ~LayoutScope() { l.layout = nullptr; }
-        } scope(lane(h), &ml);
-        const Marker mk(h, "batch", ns);
-        run_batch_with(h, M, ns, W.b_in.p, W.q_in.p, W.sig.p, R);
-    }
+    run_merged_with(h, M, m, S, bpx, persistent, W.sig.p, R);
     std::vector<double> sig(2 * ns);
     HIPCHK(hipMemcpyAsync(sig.data(), W.sig.p, sizeof(double2) * ns, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     bool any_nc = false;
     for (int64_t i = 0; i < ns; ++i) {
-        if (owner[i] < 0) continue;
-        signal_out[2 * owner[i]] = sig[2 * i];
-        signal_out[2 * owner[i] + 1] = sig[2 * i + 1];
+        if (m.owner[i] < 0) continue;
+        signal_out[2 * m.owner[i]] = sig[2 * i];
+        signal_out[2 * m.owner[i] + 1] = sig[2 * i + 1];
         if (R.flags[i]) any_nc = true;
     }
     // Totals over the caller's pairs only (not the b = 0 padding), each
@@ -2792,17 +2910,17 @@ bool run_merged(dmri_ctx* h, const std::vector<std::pair<int32_t, std::vector<in
     R.total_iters = 0;
     R.spmv_rows = 0;
     for (int64_t i = 0; i < ns; ++i) {
-        if (owner[i] < 0) continue;
+        if (m.owner[i] < 0) continue;
         const int64_t t = i / S;
         R.total_iters += R.iters[i];
-        R.spmv_rows += static_cast<int64_t>(R.iters[i]) * (ml.tab[4 * t + 1] - ml.tab[4 * t]);
+        R.spmv_rows += static_cast<int64_t>(R.iters[i]) * (m.ml.tab[4 * t + 1] - m.ml.tab[4 * t]);
     }
     if (stats) stats->t_setup_s += t_up;
-    fill_stats(stats, owner, R, n_pairs);
+    fill_stats(stats, m.owner, R, n_pairs);
     // Costs per problem, in the order its pairs took in the slots.
     int64_t slot = 0;
     for (size_t k = 0; k < groups.size(); ++k) {
-        const std::vector<int64_t>& idx = order[k];
+        const std::vector<int64_t>& idx = m.order[k];
         std::vector<int32_t> it(idx.size());
         for (size_t i = 0; i < idx.size(); ++i) it[i] = R.iters[slot + static_cast<int64_t>(i)];
         remember_costs(h, groups[k].first, b, q, idx, it);

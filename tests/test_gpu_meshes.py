@@ -152,6 +152,38 @@ def test_periodic_meshes_persistent_and_graph(Sim, precision):
     assert st3["n_kernel_launches"] * 4 < stc["n_kernel_launches"]
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_periodic_meshes_autotuned(Sim, precision):
+    # The several-mesh batch under the autotuner: its trials (tile width,
+    # blocks per XCD, persistent kernel) run on the first steps, the choice
+    # is cached for the kind of batch; both runs within 1e-9 of the oracle,
+    # the second (from the cache, no trials) identical to the first.
+    items = _periodic_case()
+    ref = np.concatenate([it[3] for it in items])
+    with Sim(0) as sim:
+        sim.set_sequence(SHORT)
+        # (sort_systems = 0: both runs fill the slots in the same order)
+        sim.set_options(rtol=1e-12, precision=precision, mesh_merge=1, autotune=1,
+                        sort_systems=0)
+        pids = [sim.add_problem(prob) for prob, _, _, _ in items]
+        ids = np.concatenate([np.full(len(b), p, np.int32)
+                              for p, (_, b, _, _) in zip(pids, items)])
+        b = np.concatenate([it[1] for it in items])
+        q = np.concatenate([it[2] for it in items])
+        first, st1 = sim.dmri_run(ids, b, q)
+        tuned = {k: sim.dmri_get_option(k) for k in ("tuned_sys_tile", "tuned_blocks_per_xcd",
+                                                       "tuned_persistent", "tuned_trials")}
+        second, st2 = sim.dmri_run(ids, b, q)
+    assert st1["status"] == "DMRI_OK" and st2["status"] == "DMRI_OK"
+    err = _err(first, ref)
+    _say("3 meshes autotuned (precision %d): %s, max err %.2e" % (precision, tuned, err.max()))
+    # tiles of 8 (13 pairs at most per mesh): 3 launch shapes + the persistent kernel
+    assert tuned["tuned_trials"] == 4
+    assert tuned["tuned_sys_tile"] == 8
+    assert err.max() < 1e-9
+    assert np.array_equal(first, second)
+
+
 @pytest.mark.parametrize("guess", [0, 1])
 def test_walled_meshes_one_batch_match_oracle(Sim, guess):
     items = _walls_case()
