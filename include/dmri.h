@@ -534,7 +534,8 @@ DMRI_API dmri_status dmri_precond_train(dmri_handle h, int64_t n, const float* d
  * The pairs of each problem are solved as one batch on the device (all
  * systems of a mesh share every matrix read); batches of different
  * problems run one after another, or several at once on their own streams
- * with option "concurrency" > 1. Results do not depend on either.
+ * with option "concurrency" > 1, or all problems form one batch with option
+ * "mesh_merge" = 1. Results agree to rounding across these choices.
  * n_pairs = 0 is an empty run: DMRI_OK, stats zeroed, nothing read or written.
  * Returns DMRI_NOT_CONVERGED (results still written) when any system hit
  * max_iter in some step. */
