@@ -290,10 +290,11 @@ DMRI_API dmri_status dmri_set_sequence_table(dmri_handle h, int64_t n_steps, dou
  *               all meshes, each over its own mesh's rows; a batch of at most
  *               64 systems can run the persistent Krylov kernel (options
  *               persistent, graph: one launch per solve over all meshes, the
- *               time loop captured in a HIP graph). Precision 0 or 1,
- *               CG/COCG, guess 0/1, signal at echo (or option signal = 0);
- *               one form for all problems, no tensors or weak faces; other
- *               combinations end in DMRI_E_UNSUPPORTED. The concatenated
+ *               time loop captured in a HIP graph). Any precision and
+ *               Krylov method, guess 0/1, signal at echo (or option
+ *               signal = 0); one form for all problems, no tensors, weak
+ *               faces, LDS SpMV, polynomial preconditioner or sample
+ *               recording; other combinations end in DMRI_E_UNSUPPORTED. The concatenated
  *               operator is built once per list of problems and kept (host
  *               and device copies) until dmri_destroy. 0 (default): one
  *               batch per problem (option concurrency). Applies to dmri_run

@@ -892,6 +892,21 @@ int64_t mesh_part_rows(int64_t rows, int64_t chunk_rows) {
 }
 int64_t mesh_chunk_rows(int S) { return make_geom(1, S, S, 1, 0, 1).chunk_rows; }
 
+// A second geometry of a several-mesh batch (the persistent solver's, or
+// GMRES's with fewer blocks per XCD) takes the batch's row layout: the same
+// tile table and row parts, its own blocks per XCD.
+void follow_mesh_layout(Geom& d, const Geom& g) {
+    if (!g.mtab) return;
+    d.mtab = g.mtab;
+    d.vlen = g.vlen;
+    d.tile_bytes_ok = 0;
+    d.n_parts = g.n_parts;
+    d.n_items = d.n_tiles * d.n_parts;
+    d.part_rows = g.part_rows;
+    const int32_t chunks = (d.part_rows + d.chunk_rows - 1) / d.chunk_rows;
+    d.B = std::max(1, std::min(d.bpx, chunks));
+}
+
 struct BatchSetup {
     Geom g;
     Geom gi;        // geometry of the FP32 inner solves (g, or 128-system paired tiles)
@@ -943,17 +958,7 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     bs.gp = make_geom(g.n_rows, static_cast<int32_t>(n_sys), S, std::max(1, n_cu / 8), 0, 1);
     bs.gp.nt = g.nt;
     bs.gp.lds = 0;
-    if (g.mtab) {  // the persistent solver's items follow the several-mesh layout too
-        Geom& gq = bs.gp;
-        gq.mtab = g.mtab;
-        gq.vlen = g.vlen;
-        gq.tile_bytes_ok = 0;
-        gq.n_parts = g.n_parts;
-        gq.n_items = gq.n_tiles * gq.n_parts;
-        gq.part_rows = g.part_rows;
-        const int32_t chunks = (gq.part_rows + gq.chunk_rows - 1) / gq.chunk_rows;
-        gq.B = std::max(1, std::min(gq.bpx, chunks));
-    }
+    follow_mesh_layout(bs.gp, g);  // the persistent solver's items follow a several-mesh layout
     // Auto: the persistent solver wins where launch latency dominates (small
     // batches on small meshes); chunked launches win once a phase has enough
     // work to hide the per-launch cost.
@@ -1284,9 +1289,10 @@ int gmres_loop(dmri_ctx* h, const BatchSetup& bs, const MatView<double>& Av, con
     Workspace& W = lane(h).ws;
     const Geom& g = bs.g;
     const int m = std::max(1, std::min(opts(h).gmres_m, kGmMax));
-    const size_t ld = static_cast<size_t>(g.ld), nv = static_cast<size_t>(g.n_rows) * ld;
+    const size_t ld = static_cast<size_t>(g.ld), nv = static_cast<size_t>(vec_elems(g));
     Geom gg = make_geom(g.n_rows, static_cast<int32_t>(n_sys), g.S,
                         std::min(64, opts(h).blocks_per_xcd), 0, 1);
+    follow_mesh_layout(gg, g);
     gg.comp = g.comp;
     gg.acomp = g.acomp;
     gg.acomp_ld = g.acomp_ld;
@@ -2845,11 +2851,11 @@ bool run_merged(dmri_ctx* h, const std::vector<std::pair<int32_t, std::vector<in
                 int64_t n_pairs, const double* b, const double* q, double* signal_out,
                 dmri_stats* stats) {
     const Options& o = opts(h);
-    if (o.precision == 2 || o.krylov == 3 || o.precond != 0 || o.guess == 2 || o.lds ||
-        h->model.rec_cap > 0 || h->pcmodel.rec_cap > 0)
+    if (o.precond != 0 || o.guess == 2 || o.lds || h->model.rec_cap > 0 ||
+        h->pcmodel.rec_cap > 0)
         throw Error(DMRI_E_UNSUPPORTED,
-                    "several-mesh batches run precision 0 or 1 with CG/COCG, guess 0/1, no "
-                    "LDS SpMV, preconditioner or sample recording");
+                    "several-mesh batches run without the LDS SpMV, the learned guess or "
+                    "preconditioner, and sample recording");
     std::vector<int32_t> pids;
     size_t max_ns = 0;
     for (const auto& gr : groups) {

@@ -184,6 +184,30 @@ def test_periodic_meshes_autotuned(Sim, precision):
     assert np.array_equal(first, second)
 
 
+def test_periodic_meshes_fp32(Sim):
+    # FP32 throughout (precision 2) over the three meshes in one batch:
+    # within 1e-4 of the oracle, as for one mesh.
+    items = _periodic_case()
+    ref = np.concatenate([it[3] for it in items])
+    sig, _ = _run(Sim, items, rtol=1e-6, precision=2, mesh_merge=1)
+    err = _err(sig, ref)
+    _say("3 meshes in one batch, FP32: max err %.2e" % err.max())
+    assert err.max() < 1e-4
+
+
+@pytest.mark.parametrize("case", ["walls", "periodic"])
+def test_meshes_one_batch_gmres(Sim, case):
+    # Restarted GMRES(12) over several meshes in one batch (the U-form's
+    # cross-check, and on the transformed form): within 1e-9 of the oracle.
+    items = _walls_case() if case == "walls" else _periodic_case()
+    ref = np.concatenate([it[3] for it in items])
+    sig, st = _run(Sim, items, rtol=1e-12, krylov=3, gmres_m=12, mesh_merge=1)
+    err = _err(sig, ref)
+    _say("%s meshes in one batch, GMRES(12): max err %.2e, %d Arnoldi steps"
+         % (case, err.max(), st["total_iterations"]))
+    assert err.max() < 1e-9
+
+
 @pytest.mark.parametrize("guess", [0, 1])
 def test_walled_meshes_one_batch_match_oracle(Sim, guess):
     items = _walls_case()
@@ -199,7 +223,7 @@ def test_one_batch_refusals(Sim):
     # error, not run another way.
     from paper_1908_01719_amd.binding import DmriError
     items = _periodic_case()[:2]
-    for opts in (dict(precision=2), dict(krylov=3), dict(lds=1), dict(guess=2)):
+    for opts in (dict(precond=2), dict(lds=1), dict(guess=2)):
         with pytest.raises(DmriError):
             _run(Sim, items, rtol=1e-10, mesh_merge=1, **opts)
 
