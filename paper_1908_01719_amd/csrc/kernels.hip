@@ -23,6 +23,7 @@
 #include <numeric>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 
 namespace dmri {
 namespace {
@@ -1844,10 +1845,13 @@ __global__ __launch_bounds__(kBlock) void k_init(
             const T cml = ll.cr(row), cmr = lr.cr(row);
             T br = 0, bi = 0, axr = 0, axi = 0;
             V2<T> x0_own = mk2<T>(0, 0);
-            constexpr int kB = S == 64 ? kRowPad : kRowPad / 2;
-            for (int k0 = kb; k0 < ke; k0 += kB) {
+            // NB entries from k0: their column indices, then all their gathers,
+            // then the products.
+            auto block = [&](auto nb, int k0) {
+                constexpr int kB = decltype(nb)::value;
                 int jj[kB];
                 V2<T> uj[kB], xj[kB];
+                float2 dj[kB];  // GM 4: the FP32 correction, widened where it is used
 #pragma unroll
                 for (int u = 0; u < kB; ++u) jj[u] = col[k0 + u];
 #pragma unroll
@@ -1863,8 +1867,7 @@ __global__ __launch_bounds__(kBlock) void k_init(
                             const float2 d = load_row<float2>(tdx, jj[u]);
                             xj[u] = mk2<T>(xo.x + static_cast<T>(d.x), xo.y + static_cast<T>(d.y));
                         } else if (GM == 4) {
-                            const float2 d = load_row<float2>(tdx, jj[u]);
-                            xj[u] = mk2<T>(static_cast<T>(d.x), static_cast<T>(d.y));
+                            dj[u] = load_row<float2>(tdx, jj[u]);
                         }
                         continue;
                     }
@@ -1880,14 +1883,14 @@ __global__ __launch_bounds__(kBlock) void k_init(
                         const float2 d = dx[tbx + static_cast<size_t>(jj[u]) * sx];
                         xj[u] = mk2<T>(xo.x + static_cast<T>(d.x), xo.y + static_cast<T>(d.y));
                     } else if (GM == 4) {
-                        const float2 d = dx[tbx + static_cast<size_t>(jj[u]) * sx];
-                        xj[u] = mk2<T>(static_cast<T>(d.x), static_cast<T>(d.y));
+                        dj[u] = dx[tbx + static_cast<size_t>(jj[u]) * sx];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < kB; ++u) {
                     const int k = k0 + u;
                     if (GM == 0) xj[u] = uj[u];
+                    if (GM == 4) xj[u] = mk2<T>(static_cast<T>(dj[u].x), static_cast<T>(dj[u].y));
                     if (GM == 1) xj[u] = mk2<T>(T(2) * uj[u].x - xj[u].x, T(2) * uj[u].y - xj[u].y);
                     const V4<T> a = aux[k];
                     const T vl = ll.d0 * a.y + ll.d1 * a.z + ll.d2 * a.w;
@@ -1902,7 +1905,19 @@ __global__ __launch_bounds__(kBlock) void k_init(
                     axr += al * xj[u].x - vl * xj[u].y;
                     axi += al * xj[u].y + vl * xj[u].x;
                 }
+            };
+            constexpr int kB = S == 64 ? kRowPad : kRowPad / 2;
+            bool whole = false;
+            if constexpr (GM == 4 && S == 64) {
+                // The cheap refinement pass gathers only the FP32 correction,
+                // so a 16-entry row's 16 gathers fit in flight together.
+                if (fast && ke - kb == 2 * kRowPad) {
+                    block(std::integral_constant<int, 2 * kRowPad>{}, kb);
+                    whole = true;
+                }
             }
+            if (!whole)
+                for (int k0 = kb; k0 < ke; k0 += kB) block(std::integral_constant<int, kB>{}, k0);
             const size_t idx = tb + static_cast<size_t>(row) * S;
             if (kRhs && wmap) {
                 // weak pseudo-periodic faces: the lagged partner term
