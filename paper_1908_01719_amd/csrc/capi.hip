@@ -1564,6 +1564,24 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
 // repeated until ||r64|| <= rtol ||b|| (iterative refinement). The inner
 // solves reduce the residual by inner_rtol and use FP32 matrices and vectors
 // with FP64 dot products.
+// Geometries of one refinement pass from the outer per-tile active counts
+// `cnt`: the FP64 tiles with a system above rtol (g_ref) and the inner tiles
+// that hold their systems (g_in; the inner tiles may be wider).
+void refine_sched(const int32_t* cnt, const Geom& g, const Geom& gi, int64_t n_sys, Geom& g_ref,
+                  Geom& g_in) {
+    std::vector<int32_t> live, live_in;
+    for (int t = 0; t < g.n_tiles; ++t) {
+        if (cnt[t] <= 0) continue;
+        live.push_back(t);
+        const int64_t s0 = static_cast<int64_t>(t) * g.S;
+        const int64_t s1 = std::min(n_sys, s0 + g.S) - 1;
+        for (int64_t ti = s0 / gi.S; ti <= s1 / gi.S; ++ti)
+            if (live_in.empty() || live_in.back() < ti) live_in.push_back(static_cast<int32_t>(ti));
+    }
+    g_ref = sched_geom(g, live.data(), static_cast<int>(live.size()));
+    g_in = sched_geom(gi, live_in.data(), static_cast<int>(live_in.size()));
+}
+
 void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
                        const double* d_q, double2* d_sig, BatchResult& res) {
     hipStream_t st = lane(h).stream;
@@ -1580,15 +1598,13 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     const size_t nvi = bs.pair ? static_cast<size_t>(g.n_rows) * ldi : nv;
     History<double2> hs;
     hs.nh = history_len(h);
-    // FP64 level: history ring, x_alt, r64, b64 (no FP64 direction vector:
-    // the inner solves form their own).
-    for (int i = 0; i < hs.nh + 4; ++i) W.vec64[i].alloc(2 * nv);
+    // FP64 level: history ring, r64, b64 (no FP64 direction vector: the
+    // inner solves form their own). The refinement passes update x in place.
+    for (int i = 0; i < hs.nh + 3; ++i) W.vec64[i].alloc(2 * nv);
     for (int i = 0; i < 4; ++i) W.vec32[i].alloc(2 * nvi);
     for (int i = 0; i <= hs.nh; ++i) hs.ring.push_back(reinterpret_cast<double2*>(W.vec64[i].p));
-    // The refinement passes alternate x between hs.x() and x_alt.
-    double2* x_alt = reinterpret_cast<double2*>(W.vec64[hs.nh + 1].p);
-    double2* r64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 2].p);
-    double2* b64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 3].p);  // right-hand side of the step
+    double2* r64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 1].p);
+    double2* b64 = reinterpret_cast<double2*>(W.vec64[hs.nh + 2].p);  // right-hand side of the step
     float2* r32 = reinterpret_cast<float2*>(W.vec32[0].p);
     float2* dx = reinterpret_cast<float2*>(W.vec32[1].p);
     float2* p32 = reinterpret_cast<float2*>(W.vec32[2].p);
@@ -1649,7 +1665,13 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                 std::fflush(stderr);
             }
             if (still == 0) break;
-            launch_inner_start(st, bsi.g, A32, W.gq.p, lhs, bs.herm, r64, W.outer.active.p, r32, dx,
+            // Only the tiles that hold a system above rtol take part in the
+            // pass (later passes typically have a handful of such systems):
+            // the others keep x and r64, and their inner tiles stay idle.
+            Geom g_ref = gr, g_in = bsi.g;
+            if (opts(h).tile_sched)
+                refine_sched(lane(h).ws.h_active[0], gr, bsi.g, so.n_sys, g_ref, g_in);
+            launch_inner_start(st, g_in, A32, W.gq.p, lhs, bs.herm, r64, W.outer.active.p, r32, dx,
                                p32, si, bs.sc);
             const int it = krylov_loop<float>(h, bsi, A32, W.gq.p, lhs, dx, r32, p32, q32, si,
                                               timer, pass == 0 ? last_first_pass - 2 : 2,
@@ -1657,10 +1679,9 @@ void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
             if (pass == 0) last_first_pass = it;
             step_iters += it;
             timer.run(4, [&] {
-                launch_init<double>(st, gr, A64, W.gq.p, lhs, rhs, bs.herm, 4, hs.u(0), hs.u(1),
-                                    hs.x(), r64, nullptr, dx, x_alt, b64, so, bs.sc);
+                launch_init<double>(st, g_ref, A64, W.gq.p, lhs, rhs, bs.herm, 4, hs.u(0), hs.u(1),
+                                    hs.x(), r64, nullptr, dx, hs.x(), b64, so, bs.sc);
             });
-            std::swap(hs.ring[hs.nh], x_alt);
         }
         if (poll_active(h, g, so) != 0) {
             // Outer refinement did not reach rtol within max_outer passes.

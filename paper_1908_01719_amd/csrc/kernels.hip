@@ -1790,15 +1790,16 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
 // At a step start (GM 0/1/2) b is also stored to bvec when it is given; a
 // refinement pass (GM 3) reads b from bvec instead of recomputing it. GM 4
 // is the cheaper refinement pass: r -= A dx (FP64 operator, only the FP32
-// correction dx is gathered) and x_out = x + dx.
+// correction dx is gathered) and x_out = x + dx; x_out may be x itself,
+// since this mode reads x only at the row it writes.
 template <typename T, int S, bool HERM, int GM>
 __global__ __launch_bounds__(kBlock) void k_init(
     Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const T* __restrict__ K0, const T* __restrict__ Kr, const V4<T>* __restrict__ aux,
     const T* __restrict__ dK0, const V4<T>* __restrict__ daux, const double4* __restrict__ gq,
     Coef lhs, Coef rhs, const V2<T>* __restrict__ u_prev, const V2<T>* __restrict__ u_prev2,
-    V2<T>* __restrict__ x, V2<T>* __restrict__ r, V2<T>* __restrict__ p,
-    const float2* __restrict__ dx, V2<T>* __restrict__ x_out, V2<T>* __restrict__ bvec,
+    V2<T>* x, V2<T>* __restrict__ r, V2<T>* __restrict__ p,
+    const float2* __restrict__ dx, V2<T>* x_out, V2<T>* __restrict__ bvec,
     SolverState s, Scratch sc, const int32_t* __restrict__ wmap, const V2<T>* __restrict__ wb) {
     constexpr bool kRhs = GM < 3;  // b formed from u_prev in this launch
     __shared__ double lds[kWaves * S * 4];
@@ -2980,6 +2981,7 @@ void launch_init(hipStream_t st, const Geom& g, const MatView<T>& A, const doubl
                  SolverState s, Scratch sc, const int32_t* wmap, const V2<T>* wb) {
     if (guess_mode == 3 && !bvec) throw std::runtime_error("init: refinement needs the stored b");
     if (guess_mode == 4 && !(dx && x_out)) throw std::runtime_error("init: refinement needs dx");
+    if (guess_mode == 3 && x_out == x) throw std::runtime_error("init: mode 3 gathers x, x_out must differ");
     if ((wmap == nullptr) != (wb == nullptr)) throw std::runtime_error("init: wmap and wb go together");
     const dim3 grid = grid_of(g), block(kBlock);
 #define DMRI_INIT(H, GMV)                                                                     \
