@@ -266,6 +266,7 @@ struct Workspace {
     DevBuf<double4> gq;
     DevBuf<double2> sig;
     DevBuf<double> partial, b_in, q_in;
+    DevBuf<double> fin_stage;  // group sums of the two-stage finalize
     DevBuf<int32_t> ctr, bad;
     DevBuf<uint32_t> barrier;  // count, generation, error flag of the persistent solver
     StateBufs outer, inner;
@@ -998,6 +999,12 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
                              gi.S * 4),
         2 * static_cast<size_t>(bs.gp.n_items) * bs.gp.B * S * 4);
     W.partial.alloc(part_n);
+    {
+        size_t cols = 0;  // tiles x tile width of the widest geometry
+        for (const Geom* gg : {&g, &gi, static_cast<const Geom*>(&bs.gp)})
+            cols = std::max(cols, static_cast<size_t>(gg->n_tiles) * gg->S);
+        W.fin_stage.alloc(cols * kFinGroups * 4);
+    }
     W.barrier.alloc(32 * 11);
     HIPCHK(hipMemsetAsync(W.barrier.p, 0, sizeof(uint32_t) * 32 * 11, st));
     bs.bar.count = W.barrier.p;
@@ -1035,6 +1042,7 @@ BatchSetup setup_batch(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* 
     bs.sc.partial = W.partial.p;
     bs.sc.ctr_spmv = W.ctr.p;
     bs.sc.ctr_init = W.ctr.p + items_max;
+    bs.sc.stage = W.fin_stage.p;
     return bs;
 }
 

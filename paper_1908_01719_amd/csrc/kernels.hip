@@ -2161,6 +2161,47 @@ __global__ __launch_bounds__(kBlock) void k_signal_phase(Geom gt, int32_t n_rows
 // partials, then the groups are combined in a fixed order.
 constexpr int kFinBlock = 1024;
 
+// First stage of a finalize: block (tile, group) adds group `group` of the
+// tile's nb partials (contiguous, in order) and stores the sum at
+// stage[tile][group]. Fixed order, so the result is deterministic. Group 0
+// also clears the tile's chunk counters (zero_ctr) for the next launch.
+constexpr int kStageBlock = 256;
+template <int S>
+__global__ __launch_bounds__(kStageBlock) void k_fin_stage(Geom g, Scratch sc, int32_t nb,
+                                                           int32_t* zero_ctr) {
+    int tile = static_cast<int>(blockIdx.x) / kFinGroups;
+    const int grp = static_cast<int>(blockIdx.x) % kFinGroups;
+    if (g.n_sched) {
+        const int t = tile;
+#pragma unroll
+        for (int i = 0; i < kMaxSched; ++i)
+            if (i == t) tile = g.sched[i];
+    }
+    if (zero_ctr && grp == 0 && static_cast<int>(threadIdx.x) < g.n_parts)
+        zero_ctr[tile * g.n_parts + threadIdx.x] = 0;
+    const int per = (nb + kFinGroups - 1) / kFinGroups;
+    const int i0 = grp * per, i1 = min(nb, i0 + per);
+    constexpr int W = S * 4;  // doubles per partial
+    const double* base = sc.partial + static_cast<size_t>(tile) * nb * W;
+    double* dst = sc.stage + (static_cast<size_t>(tile) * kFinGroups + grp) * W;
+    for (int v = threadIdx.x; v < W; v += kStageBlock) {
+        double acc = 0.0;
+        int i = i0;
+        for (; i + 3 < i1; i += 4) {
+            const double a0 = base[static_cast<size_t>(i) * W + v];
+            const double a1 = base[static_cast<size_t>(i + 1) * W + v];
+            const double a2 = base[static_cast<size_t>(i + 2) * W + v];
+            const double a3 = base[static_cast<size_t>(i + 3) * W + v];
+            acc += a0;
+            acc += a1;
+            acc += a2;
+            acc += a3;
+        }
+        for (; i < i1; ++i) acc += base[static_cast<size_t>(i) * W + v];
+        dst[v] = acc;
+    }
+}
+
 template <int S, int K, int MODE>
 __global__ __launch_bounds__(kFinBlock) void k_finalize(Geom g, SolverState s, Scratch sc,
                                                         double2* __restrict__ out, int32_t n_sig,
@@ -2903,8 +2944,30 @@ inline void check_launch(const char* what) {
 inline dim3 grid_of(const Geom& g) { return dim3(8u * static_cast<unsigned>(g.B)); }
 
 template <int MODE, int K>
-void launch_fin(hipStream_t st, const Geom& g, SolverState s, Scratch sc, double2* out,
+void launch_fin(hipStream_t st, const Geom& g0, SolverState s, Scratch sc, double2* out,
                 int32_t n_sig, int32_t* zero_ctr) {
+    // With many partials per tile (blocks x row parts) one block per tile
+    // would read them all; a first stage spread over kFinGroups blocks per
+    // tile adds them in groups, and the finalize adds the group sums.
+    Geom g = g0;
+    const int32_t nb = g0.n_parts * g0.B;
+    if (sc.stage && nb > 2 * kFinGroups) {
+        const unsigned nt = static_cast<unsigned>(g0.n_sched ? g0.n_sched : g0.n_tiles);
+        const dim3 sgrid(nt * kFinGroups), sblock(kStageBlock);
+        switch (g0.S) {
+            case 8: k_fin_stage<8><<<sgrid, sblock, 0, st>>>(g0, sc, nb, zero_ctr); break;
+            case 16: k_fin_stage<16><<<sgrid, sblock, 0, st>>>(g0, sc, nb, zero_ctr); break;
+            case 32: k_fin_stage<32><<<sgrid, sblock, 0, st>>>(g0, sc, nb, zero_ctr); break;
+            case 64: k_fin_stage<64><<<sgrid, sblock, 0, st>>>(g0, sc, nb, zero_ctr); break;
+            case kPairS: k_fin_stage<kPairS><<<sgrid, sblock, 0, st>>>(g0, sc, nb, zero_ctr); break;
+            default: throw std::runtime_error("unsupported tile width");
+        }
+        check_launch("finalize stage");
+        g.n_parts = 1;
+        g.B = kFinGroups;
+        sc.partial = sc.stage;
+        zero_ctr = nullptr;
+    }
     const dim3 grid(static_cast<unsigned>(g.n_sched ? g.n_sched : g.n_tiles)), block(kFinBlock);
     switch (g.S) {
         case 8: k_finalize<8, K, MODE><<<grid, block, 0, st>>>(g, s, sc, out, n_sig, zero_ctr); break;

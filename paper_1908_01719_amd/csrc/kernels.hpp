@@ -145,7 +145,13 @@ struct Scratch {
     double* partial;     // [n_tiles * n_parts][B][S][4], item = tile * n_parts + part
     int32_t* ctr_spmv;   // [n_tiles * n_parts] chunk queues of the gather kernels,
     int32_t* ctr_init;   // [n_tiles * n_parts] zero between launches
+    // [n_tiles][kFinGroups][S][4] group sums of a two-stage finalize, or null
+    // (the finalize then adds every partial itself)
+    double* stage = nullptr;
 };
+
+// Groups of the first stage of a finalize over many partials per tile.
+constexpr int kFinGroups = 64;
 
 Geom make_geom(int32_t n_rows, int32_t n_sys, int32_t S, int32_t blocks_per_xcd, int32_t queue,
                int32_t grab, bool xcd_split = false);
