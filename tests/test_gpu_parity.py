@@ -669,26 +669,33 @@ def test_tile_schedule_odd_tile_counts(Sim):
 
 def test_refinement_schedule_paired_mixed(Sim):
     # Mixed precision on 203 systems: four 64-system FP64 tiles (the last one
-    # ragged) and two 128-system paired inner tiles. At rtol 1e-10 a step
-    # takes several refinement passes, and the low-b tiles drop out of the
-    # later ones, which then run the refinement residual and the inner start
-    # over the remaining tiles only (tile_sched = 1). The signals match the
+    # ragged) and two 128-system paired inner tiles. The first FP64 tile holds
+    # only b = 0 systems, which converge at every step start, so each
+    # refinement pass runs the refinement residual over the other three tiles
+    # only (tile_sched = 1), and the inner start over both inner tiles (the
+    # first of which is half idle). At rtol 1e-10 a step takes several
+    # passes, and low-b tiles drop out of the later ones. The signals match the
     # runs over every tile (tile_sched = 0) to rounding, and the summed inner
     # iterations agree to within rounding-level differences in when a system
     # stops.
     prob, _, _ = _cyl_case()
-    b = np.linspace(0.0, 5000.0, 203)
+    b = np.concatenate([np.zeros(64), np.linspace(200.0, 5000.0, 139)])
     q = di.fibonacci_directions(203)
     out, iters = {}, {}
     with Sim(0) as sim:
         sim.set_sequence(SHORT)
         pid = sim.add_problem(prob)
-        sim.set_options(rtol=1e-10, precision=1, pair_lanes=1, persistent=0)
+        # Input order for every run (no reordering by the previous run's costs).
+        sim.set_options(rtol=1e-10, precision=1, pair_lanes=1, persistent=0, sort_systems=0)
         for ts in (0, 1):
             sim.set_options(tile_sched=ts)
             out[ts], st = sim.dmri_run([pid] * len(b), b, q)
             assert st["status"] == "DMRI_OK"
             iters[ts] = st["total_iterations"]
+        # Partials are added in a fixed order (in groups first when a tile has
+        # many of them), so a second run is bitwise identical.
+        again, _ = sim.dmri_run([pid] * len(b), b, q)
+    assert np.array_equal(again, out[1])
     err = rel_err(out[1], out[0], out[0][0])
     _say("refinement schedule, 203 systems mixed: max difference %.2e, iterations %d / %d"
          % (err.max(), iters[0], iters[1]))
