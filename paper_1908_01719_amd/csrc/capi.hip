@@ -1566,12 +1566,6 @@ void solve_batch(dmri_ctx* h, ProblemRec& P, DevMatrix<T>& A, int64_t n_sys, con
     res.spmv_rows = res.total_iters * g.n_rows;
 }
 
-// Mixed precision: FP64 time stepping (right-hand side, residual, solution,
-// signal) around FP32 Krylov solves of the correction equation
-//   A dx = r64,  x64 += dx,  r64 = b - A x64  (FP64 operator)
-// repeated until ||r64|| <= rtol ||b|| (iterative refinement). The inner
-// solves reduce the residual by inner_rtol and use FP32 matrices and vectors
-// with FP64 dot products.
 // Geometries of one refinement pass from the outer per-tile active counts
 // `cnt`: the FP64 tiles with a system above rtol (g_ref) and the inner tiles
 // that hold their systems (g_in; the inner tiles may be wider).
@@ -1590,6 +1584,12 @@ void refine_sched(const int32_t* cnt, const Geom& g, const Geom& gi, int64_t n_s
     g_in = sched_geom(gi, live_in.data(), static_cast<int>(live_in.size()));
 }
 
+// Mixed precision: FP64 time stepping (right-hand side, residual, solution,
+// signal) around FP32 Krylov solves of the correction equation
+//   A dx = r64,  x64 += dx,  r64 = b - A x64  (FP64 operator)
+// repeated until ||r64|| <= rtol ||b|| (iterative refinement). The inner
+// solves reduce the residual by inner_rtol and use FP32 matrices and vectors
+// with FP64 dot products.
 void solve_batch_mixed(dmri_ctx* h, ProblemRec& P, int64_t n_sys, const double* d_b,
                        const double* d_q, double2* d_sig, BatchResult& res) {
     hipStream_t st = lane(h).stream;
