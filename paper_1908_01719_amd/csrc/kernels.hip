@@ -1793,7 +1793,8 @@ __global__ __launch_bounds__(kBlock) void k_krylov_persistent(
 // correction dx is gathered) and x_out = x + dx; x_out may be x itself,
 // since this mode reads x only at the row it writes.
 template <typename T, int S, bool HERM, int GM>
-__global__ __launch_bounds__(kBlock) void k_init(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(GM == 4 ? 5 : 1))) void k_init(
     Geom g, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const T* __restrict__ K0, const T* __restrict__ Kr, const V4<T>* __restrict__ aux,
     const T* __restrict__ dK0, const V4<T>* __restrict__ daux, const double4* __restrict__ gq,
